@@ -1,0 +1,431 @@
+"""Oracle for the exposure / white-balance correction of a ring of cameras.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring): plain, slow and exact.
+
+The method is the one of section 3.1 of the paper ("White balance and exposure
+correction"):
+
+* narrow bands on both sides of every seam are assumed to share one colour
+  spectrum (the local constancy prior);
+* a shared spectrum is estimated per seam by averaging the two facing bands;
+* each camera side gets one affine map f_c(x) = a_c x + b_c per colour
+  channel that sends its band onto the shared spectrum; a map depends only on
+  the two adjacent streams;
+* the map is blended convexly from the identity at the image centre to f_c at
+  the border, over half of each image;
+* the stream is split vertically into blocks of equal size, one map per block;
+* optional exponential smoothing E = (1 - alpha) E_prev + alpha E_new with
+  alpha = 0.05 (the blending equation of section 3.1).
+
+Where the paper is silent the readings are fixed here (and listed with their
+reasons in the design notes of the repository):
+
+R-ring    camera at ring position p meets position p+1 (closed ring by
+          default, the last meeting the first; open chain optional, where the
+          two outer sides get the identity map).
+R-block   block j covers rows [floor(j H / NB), floor((j+1) H / NB)).
+R-band    band width B' = min(B, floor(W / 2)); left band = columns [0, B'),
+          right band = columns [W - B', W).
+R-bins    uint8 sample v -> bin v; uint16 sample v of bit depth d ->
+          bin min(v >> (d - 8), 255).
+R-mid     shared spectrum = the "midway" distribution: mean of the two means
+          and mean of the two standard deviations.
+R-fit     a = sigma* / sigma_own (a = 1 when the own variance is 0), clamped to
+          [a_min, a_max]; b = mu* - a mu_own, computed after the clamp.  No
+          estimate when either band is empty: keep the previous map (identity
+          if there is none).
+R-ema     smoothing blends (a, b) pointwise, as two products and one sum;
+          the first estimate is taken as is.
+R-q16     A = round_half_even(a * 65536), Bq = round_half_even(b * 65536);
+          f(x) = clamp((A x + Bq + 32768) >> 16) with >> a floor shift.
+R-weight  h = floor(W / 2); left column col < h has Q8 weight
+          round_half_up(256 (h - col) / h); right column col >= W - h has
+          round_half_up(256 (col - (W - h) + 1) / h); the centre column of an
+          odd width has weight 0.
+R-apply   y = ((256 - w) x + w f(x) + 128) >> 8, i.e. the exact convex
+          combination rounded half up.
+
+Every floating-point step is one IEEE binary64 operation on Python floats
+(no fused multiply-add), so the result is reproducible to the last bit.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+NBINS = 256
+CSLOTS = 3          # channel slots of every per-camera statistics array
+LEFT, RIGHT = 0, 1  # camera sides
+
+
+@dataclass(frozen=True)
+class Camera:
+    """Geometry of one camera.  bit_depth 8 means uint8 samples, 9..16 uint16."""
+    width: int
+    height: int
+    channels: int = 3
+    bit_depth: int = 8
+    ring: int = 0
+    pos: int = 0
+
+
+@dataclass(frozen=True)
+class Options:
+    n_blocks: int = 16          # vertical blocks (section 3.1: 16 and 64 tested)
+    band_width: int = 32        # B, clamped to floor(W / 2)
+    closed_ring: bool = True
+    smoothing: bool = False     # exponential smoothing of section 3.1
+    ema_alpha: float = 0.05     # alpha of the blending equation of section 3.1
+    a_min: float = 0.125
+    a_max: float = 8.0
+
+
+# --------------------------------------------------------------------------
+# Regions (section 3.1: bands along the seam, vertical blocks, half images)
+# --------------------------------------------------------------------------
+
+def block_bounds(height: int, n_blocks: int) -> list[tuple[int, int]]:
+    """Rows [r0, r1) of every vertical block (reading R-block)."""
+    return [(j * height // n_blocks, (j + 1) * height // n_blocks) for j in range(n_blocks)]
+
+
+def block_of_row(row: int, height: int, n_blocks: int) -> int:
+    """Index of the block that holds `row` (closed form of R-block)."""
+    return ((row + 1) * n_blocks - 1) // height
+
+
+def band_columns(width: int, band_width: int) -> tuple[tuple[int, int], tuple[int, int]]:
+    """Column ranges of the left and right bands (reading R-band)."""
+    b = min(band_width, width // 2)
+    return (0, b), (width - b, width)
+
+
+def ring_order(cams: list[Camera], ring: int) -> list[int]:
+    """Camera indices of one ring sorted by ring position."""
+    return [i for _, i in sorted((c.pos, i) for i, c in enumerate(cams) if c.ring == ring)]
+
+
+def facing(cams: list[Camera], opts: Options, k: int, side: int):
+    """(camera, side) whose band faces `side` of camera k across a seam, or None.
+
+    Right side of position p meets the left side of position p + 1 (reading
+    R-ring).  A one-camera closed ring faces itself.
+    """
+    order = ring_order(cams, cams[k].ring)
+    m, p = len(order), order.index(k)
+    if side == RIGHT:
+        q = p + 1
+        if q == m:
+            if not opts.closed_ring:
+                return None
+            q = 0
+        return order[q], LEFT
+    q = p - 1
+    if q < 0:
+        if not opts.closed_ring:
+            return None
+        q = m - 1
+    return order[q], RIGHT
+
+
+# --------------------------------------------------------------------------
+# Statistics (section 3.1: intensity distributions of the narrow bands)
+# --------------------------------------------------------------------------
+
+def sample_bins(values: np.ndarray, bit_depth: int) -> np.ndarray:
+    """Histogram bin of every sample (reading R-bins)."""
+    v = values.astype(np.int64)
+    if bit_depth == 8:
+        return v
+    return np.minimum(v >> (bit_depth - 8), NBINS - 1)
+
+
+def region_stats(pix: np.ndarray, bit_depth: int) -> tuple[np.ndarray, np.ndarray]:
+    """256-bin histogram and exact (n, S1, S2) of each channel of a region.
+
+    pix has shape (rows, cols, C).  Returns hist int64 [CSLOTS][256] and sums
+    int64 [CSLOTS][3] = (count, sum of samples, sum of squared samples);
+    channel slots >= C stay zero.
+    """
+    hist = np.zeros((CSLOTS, NBINS), np.int64)
+    sums = np.zeros((CSLOTS, 3), np.int64)
+    for c in range(pix.shape[2]):
+        v = pix[:, :, c].astype(np.int64).ravel()
+        hist[c] = np.bincount(sample_bins(v, bit_depth), minlength=NBINS)
+        sums[c, 0] = v.size
+        sums[c, 1] = int(v.sum())
+        sums[c, 2] = int((v * v).sum())
+    return hist, sums
+
+
+def band_stats(frame: np.ndarray, cam: Camera, opts: Options) -> tuple[np.ndarray, np.ndarray]:
+    """Statistics of every (side, block) band of one camera.
+
+    Returns hist [2][NB][CSLOTS][256] and sums [2][NB][CSLOTS][3].
+    """
+    nb = opts.n_blocks
+    hist = np.zeros((2, nb, CSLOTS, NBINS), np.int64)
+    sums = np.zeros((2, nb, CSLOTS, 3), np.int64)
+    cols = band_columns(cam.width, opts.band_width)
+    for j, (r0, r1) in enumerate(block_bounds(cam.height, nb)):
+        for s in (LEFT, RIGHT):
+            c0, c1 = cols[s]
+            hist[s, j], sums[s, j] = region_stats(frame[r0:r1, c0:c1, :], cam.bit_depth)
+    return hist, sums
+
+
+def whole_stats(frame: np.ndarray, cam: Camera) -> tuple[np.ndarray, np.ndarray]:
+    """Statistics of the whole frame: hist [CSLOTS][256], sums [CSLOTS][3]."""
+    return region_stats(frame, cam.bit_depth)
+
+
+# --------------------------------------------------------------------------
+# Estimate (section 3.1: shared spectrum and per-channel affine fit)
+# --------------------------------------------------------------------------
+
+def moments(n: int, s1: int, s2: int) -> tuple[float, float, float]:
+    """Mean, variance and standard deviation from exact sums (binary64)."""
+    nf = float(n)
+    mu = float(s1) / nf
+    ex2 = float(s2) / nf
+    mu2 = mu * mu
+    var = ex2 - mu2
+    if var < 0.0:
+        var = 0.0
+    return mu, var, math.sqrt(var)
+
+
+def fit_side(own: tuple[int, int, int], fac: tuple[int, int, int],
+             a_min: float, a_max: float):
+    """Affine map (a, b) that sends the own band onto the shared spectrum.
+
+    own, fac are (n, S1, S2) of one channel of the own and the facing band.
+    Returns None when either band is empty (reading R-fit).
+    """
+    if own[0] == 0 or fac[0] == 0:
+        return None
+    mu_o, var_o, sd_o = moments(*own)
+    mu_f, _, sd_f = moments(*fac)
+    mu_s = (mu_o + mu_f) / 2.0            # shared spectrum (reading R-mid)
+    sd_s = (sd_o + sd_f) / 2.0
+    a = 1.0 if var_o == 0.0 else sd_s / sd_o
+    a = min(max(a, a_min), a_max)
+    am = a * mu_o
+    b = mu_s - am
+    return a, b
+
+
+def ema(prev: float, new: float, alpha: float) -> float:
+    """One step of the exponential smoothing of section 3.1 (reading R-ema)."""
+    keep = 1.0 - alpha
+    t_prev = keep * prev
+    t_new = alpha * new
+    return t_prev + t_new
+
+
+def estimate(cams: list[Camera], opts: Options, band_sums: np.ndarray,
+             prev_params: np.ndarray | None = None, prev_valid: np.ndarray | None = None):
+    """Per (camera, side, block, channel) affine maps for one frame-set.
+
+    band_sums: [K][2][NB][CSLOTS][3].  prev_params f64 [K][2][NB][CSLOTS][2],
+    prev_valid u8 [K][2][NB][CSLOTS] (1 = the unit holds an estimate).
+    Returns (params, valid) of the same shapes.
+    """
+    K, nb = len(cams), opts.n_blocks
+    if prev_params is None:
+        prev_params = np.zeros((K, 2, nb, CSLOTS, 2), np.float64)
+        prev_params[..., 0] = 1.0
+    if prev_valid is None:
+        prev_valid = np.zeros((K, 2, nb, CSLOTS), np.uint8)
+    params = np.zeros((K, 2, nb, CSLOTS, 2), np.float64)
+    valid = np.zeros((K, 2, nb, CSLOTS), np.uint8)
+    for k, cam in enumerate(cams):
+        for s in (LEFT, RIGHT):
+            fc = facing(cams, opts, k, s)
+            for j in range(nb):
+                for c in range(CSLOTS):
+                    if c >= cam.channels:
+                        params[k, s, j, c] = (1.0, 0.0)
+                        continue
+                    if fc is None:
+                        params[k, s, j, c] = (1.0, 0.0)
+                        valid[k, s, j, c] = 1
+                        continue
+                    own = tuple(int(v) for v in band_sums[k, s, j, c])
+                    fac = tuple(int(v) for v in band_sums[fc[0], fc[1], j, c])
+                    new = fit_side(own, fac, opts.a_min, opts.a_max)
+                    had = bool(prev_valid[k, s, j, c])
+                    if new is None:
+                        if had:
+                            params[k, s, j, c] = prev_params[k, s, j, c]
+                            valid[k, s, j, c] = 1
+                        else:
+                            params[k, s, j, c] = (1.0, 0.0)
+                        continue
+                    a, b = new
+                    if opts.smoothing and had:
+                        a = ema(float(prev_params[k, s, j, c, 0]), a, opts.ema_alpha)
+                        b = ema(float(prev_params[k, s, j, c, 1]), b, opts.ema_alpha)
+                    params[k, s, j, c] = (a, b)
+                    valid[k, s, j, c] = 1
+    return params, valid
+
+
+# --------------------------------------------------------------------------
+# LUTs and column weights (section 3.1: the map and its convex blend)
+# --------------------------------------------------------------------------
+
+def q16(value: float) -> int:
+    """round_half_even(value * 65536) as an exact integer (reading R-q16)."""
+    return int(round(value * 65536.0))
+
+
+def affine_fixed(A: int, Bq: int, x: int, max_value: int) -> int:
+    """f(x) = clamp((A x + Bq + 32768) >> 16, 0, max_value) in exact integers."""
+    y = (A * x + Bq + 32768) >> 16
+    return min(max(y, 0), max_value)
+
+
+def lut_u8(a: float, b: float) -> np.ndarray:
+    """256-entry uint8 table of the affine map (a, b)."""
+    A, Bq = q16(a), q16(b)
+    return np.array([affine_fixed(A, Bq, x, 255) for x in range(NBINS)], np.uint8)
+
+
+def build_luts(cams: list[Camera], opts: Options, params: np.ndarray):
+    """lut8 u8 [K][2][NB][CSLOTS][256] (uint8 cameras only) and q16 i64 [K][2][NB][CSLOTS][2]."""
+    K, nb = len(cams), opts.n_blocks
+    lut8 = np.zeros((K, 2, nb, CSLOTS, NBINS), np.uint8)
+    qq = np.zeros((K, 2, nb, CSLOTS, 2), np.int64)
+    for k, cam in enumerate(cams):
+        for s in (LEFT, RIGHT):
+            for j in range(nb):
+                for c in range(CSLOTS):
+                    a, b = float(params[k, s, j, c, 0]), float(params[k, s, j, c, 1])
+                    qq[k, s, j, c] = (q16(a), q16(b))
+                    if cam.bit_depth == 8:
+                        lut8[k, s, j, c] = lut_u8(a, b)
+    return lut8, qq
+
+
+def column_weights(width: int) -> tuple[np.ndarray, np.ndarray]:
+    """Q8 weight and side (0 left, 1 right, -1 centre) of every column (reading R-weight)."""
+    h = width // 2
+    w = np.zeros(width, np.int64)
+    side = np.full(width, -1, np.int64)
+    for col in range(width):
+        if col < h:
+            side[col] = LEFT
+            w[col] = ((h - col) * 256 + h // 2) // h
+        elif col >= width - h:
+            side[col] = RIGHT
+            w[col] = ((col - width + h + 1) * 256 + h // 2) // h
+    return w, side
+
+
+def weights_table(cams: list[Camera]) -> np.ndarray:
+    """u16 [K][W_max] column weights, zero beyond each camera's width."""
+    wmax = max(c.width for c in cams)
+    t = np.zeros((len(cams), wmax), np.uint16)
+    for k, cam in enumerate(cams):
+        t[k, :cam.width] = column_weights(cam.width)[0]
+    return t
+
+
+# --------------------------------------------------------------------------
+# Apply (section 3.1: identity at the centre, f_c at the border)
+# --------------------------------------------------------------------------
+
+def blend(x: np.ndarray, fx: np.ndarray, w: np.ndarray) -> np.ndarray:
+    """y = ((256 - w) x + w f(x) + 128) >> 8 in exact integers (reading R-apply)."""
+    return ((256 - w) * x + w * fx + 128) >> 8
+
+
+def apply_camera(frame: np.ndarray, cam: Camera, opts: Options,
+                 lut8_cam: np.ndarray, q16_cam: np.ndarray) -> np.ndarray:
+    """Corrected copy of one frame.  lut8_cam [2][NB][CSLOTS][256], q16_cam [2][NB][CSLOTS][2]."""
+    out = frame.copy()
+    w, side = column_weights(cam.width)
+    maxv = (1 << cam.bit_depth) - 1
+    for j, (r0, r1) in enumerate(block_bounds(cam.height, opts.n_blocks)):
+        for s in (LEFT, RIGHT):
+            cols = np.nonzero(side == s)[0]
+            if cols.size == 0 or r1 == r0:
+                continue
+            ws = w[cols][None, :]
+            for c in range(cam.channels):
+                x = frame[r0:r1][:, cols, c].astype(np.int64)
+                if cam.bit_depth == 8:
+                    fx = lut8_cam[s, j, c].astype(np.int64)[x]
+                else:
+                    A, Bq = int(q16_cam[s, j, c, 0]), int(q16_cam[s, j, c, 1])
+                    fx = np.clip((A * x + Bq + 32768) >> 16, 0, maxv)
+                out[r0:r1, cols[0]:cols[-1] + 1, c] = blend(x, fx, ws).astype(frame.dtype)
+    return out
+
+
+# --------------------------------------------------------------------------
+# One frame-set end to end
+# --------------------------------------------------------------------------
+
+def frameset(cams: list[Camera], opts: Options, frames: list[np.ndarray],
+             prev_params: np.ndarray | None = None, prev_valid: np.ndarray | None = None) -> dict:
+    """Statistics -> estimate -> LUTs -> apply for one synchronized frame-set.
+
+    Whole-frame statistics are of the input frames.
+    """
+    K, nb = len(cams), opts.n_blocks
+    bh = np.zeros((K, 2, nb, CSLOTS, NBINS), np.int64)
+    bs = np.zeros((K, 2, nb, CSLOTS, 3), np.int64)
+    wh = np.zeros((K, CSLOTS, NBINS), np.int64)
+    ws = np.zeros((K, CSLOTS, 3), np.int64)
+    for k, (cam, f) in enumerate(zip(cams, frames)):
+        bh[k], bs[k] = band_stats(f, cam, opts)
+        wh[k], ws[k] = whole_stats(f, cam)
+    params, valid = estimate(cams, opts, bs, prev_params, prev_valid)
+    lut8, qq = build_luts(cams, opts, params)
+    outs = [apply_camera(f, cam, opts, lut8[k], qq[k]) for k, (cam, f) in enumerate(zip(cams, frames))]
+    return dict(band_hist=bh, band_sums=bs, whole_hist=wh, whole_sums=ws, params=params,
+                valid=valid, lut8=lut8, q16=qq, weights=weights_table(cams), out=outs)
+
+
+# --------------------------------------------------------------------------
+# Seam gradient cost (section 4.2, the gradient-cost equation)
+# --------------------------------------------------------------------------
+
+def box_downsample(img: np.ndarray, factor: int, from_right: bool) -> np.ndarray:
+    """Mean of non-overlapping factor x factor boxes (binary64).
+
+    Rows are taken from the top; columns from the right edge when from_right
+    (so that the last box column touches the seam), else from the left edge.
+    """
+    h = img.shape[0] // factor * factor
+    wc = img.shape[1] // factor * factor
+    sub = img[:h, img.shape[1] - wc:] if from_right else img[:h, :wc]
+    sub = sub.astype(np.float64)
+    r, cc = h // factor, wc // factor
+    return sub.reshape(r, factor, cc, factor, img.shape[2]).mean(axis=(1, 3))
+
+
+def seam_cost(left: np.ndarray, right: np.ndarray, factor: int = 8) -> float:
+    """Mean over rows of (d+ + d-)/2 for the seam between `left` and `right`.
+
+    d+ = |(I+_1 - I+_0) - (I+_0 - I-_0)|, d- = |(I-_-1 - I-_0) - (I-_0 - I+_0)|,
+    with |.| the Euclidean norm over the colour channels, after box
+    downsampling by `factor` in both directions.
+    """
+    lft = box_downsample(left[:, left.shape[1] - 2 * factor:], factor, True)
+    rgt = box_downsample(right[:, :2 * factor], factor, False)
+    im1, im0 = lft[:, 0, :], lft[:, 1, :]
+    ip0, ip1 = rgt[:, 0, :], rgt[:, 1, :]
+    d_plus = np.sqrt((((ip1 - ip0) - (ip0 - im0)) ** 2).sum(axis=1))
+    d_minus = np.sqrt((((im1 - im0) - (im0 - ip0)) ** 2).sum(axis=1))
+    return float(((d_plus + d_minus) / 2.0).mean())
+
+
+def interior_cost(img: np.ndarray, factor: int = 8) -> float:
+    """The same cost at a virtual seam in the middle of one image (section 4.2)."""
+    m = img.shape[1] // 2
+    return seam_cost(img[:, :m], img[:, m:], factor)
