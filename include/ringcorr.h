@@ -1,0 +1,195 @@
+/*
+ * ringcorr.h -- C-ABI of the MI355X (gfx950) seam-matched exposure and
+ * white-balance correction for a ring of non-overlapping cameras.
+ *
+ * Method: paper section 3.1 ("White balance and exposure correction").  Narrow
+ * bands on both sides of every seam are matched to a shared colour spectrum by
+ * one affine map f_c(x) = a_c x + b_c per colour channel, per camera side and
+ * per vertical block; each map is blended from the identity at the image
+ * centre to f_c at the border over half of the image.  Optional exponential
+ * smoothing E = (1 - alpha) E_prev + alpha E_new (alpha = 0.05) of section 3.1.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * K        number of cameras of the context (1 .. RT_MAX_CAMS).
+ * NB       number of vertical blocks; block j of a camera of height H covers
+ *          rows [floor(j H / NB), floor((j + 1) H / NB)).
+ * side     0 = left border band (columns [0, B')), 1 = right border band
+ *          (columns [W - B', W)), B' = min(band_width, floor(W / 2)).
+ * channel  slot c in 0..2; slots >= the camera's channel count are unused
+ *          (statistics 0, parameters identity, valid 0).
+ * Rings    cameras with equal `ring` form one ring ordered by `pos`
+ *          (0 .. m-1, each once): the right side of position p faces the left
+ *          side of position p + 1, and in a closed ring the last position
+ *          faces position 0.  A one-camera closed ring faces itself.
+ *
+ * All buffer pointers inside the rt_*_buf structs and all frame pointers are
+ * DEVICE pointers owned by the caller; the library never allocates or frees
+ * caller-visible memory (a context owns only its own small device tables).
+ * Arrays are dense C-order with the shapes given below.  Frames are row-major
+ * interleaved: sample (r, col, c) of camera k lives at byte
+ *   frame[k] + r * pitch_bytes + (col * channels + c) * bytes_per_sample,
+ * bytes_per_sample = 1 for bit_depth 8 and 2 (little-endian uint16) for
+ * bit_depth 9..16.  Frame base pointers and pitch_bytes must be multiples of
+ * 16; bytes of a row beyond width * channels * bytes_per_sample are neither
+ * read nor written.
+ *
+ * Every compute entry point is asynchronous: it validates its arguments on the
+ * host, enqueues kernels on `stream` (a hipStream_t passed as void*, NULL = the
+ * default stream) and returns.  Validation failures return a negative status,
+ * set rt_last_error() and enqueue nothing.  A HIP launch failure returns
+ * RT_EDEVICE.  Nothing aborts and no C++ exception crosses this boundary.  A
+ * context is not internally locked: use one context per host thread.
+ */
+#ifndef RINGCORR_H
+#define RINGCORR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RT_MAX_CAMS 64
+#define RT_CSLOTS 3
+#define RT_NBINS 256
+#define RT_MAX_BLOCKS 1024
+
+typedef int32_t rt_status;
+enum {
+  RT_OK = 0,
+  RT_EINVAL = -1,        /* invalid argument: nothing was enqueued */
+  RT_ENOMEM = -2,        /* the context could not allocate its device tables */
+  RT_EDEVICE = -3,       /* a HIP call failed (launch, copy, graph) */
+  RT_EUNSUPPORTED = -4,  /* valid but unsupported combination */
+  RT_ESTATE = -5         /* call made on a context in the wrong state */
+};
+
+enum { RT_MODE_STANDARD = 0, RT_MODE_SMOOTHING = 1 };
+
+/* Geometry of one camera.  channels is 3 (RGB) or 1; bit_depth 8 (uint8
+ * samples) or 9..16 (uint16 samples, channels must be 1).  Every camera of one
+ * ring must have the same channels and bit_depth. */
+typedef struct {
+  int32_t width, height, channels, bit_depth;
+  int32_t ring, pos;
+  int64_t pitch_bytes;
+} rt_camera_desc;
+
+/* Method options.  n_blocks >= 1 (paper: 16 or 64), band_width >= 1 (clamped to
+ * floor(W/2) per camera), closed_ring 0/1, mode RT_MODE_*, ema_alpha in (0, 1]
+ * (paper: 0.05), 0 < a_min <= a_max (clamp of the gain a). */
+typedef struct {
+  int32_t n_blocks, band_width, closed_ring, mode;
+  double ema_alpha, a_min, a_max;
+} rt_opts;
+
+/* Element counts of every caller-owned buffer of a context. */
+typedef struct {
+  int32_t n_cams, n_blocks, w_max, reserved;
+  int64_t band_hist;   /* uint32 [K][2][NB][3][256] */
+  int64_t band_sums;   /* uint64 [K][2][NB][3][3] = (n, S1, S2) */
+  int64_t whole_hist;  /* uint32 [K][3][256] */
+  int64_t whole_sums;  /* uint64 [K][3][3] = (n, S1, S2) */
+  int64_t params;      /* double [K][2][NB][3][2] = (a, b) in sample units */
+  int64_t valid;       /* uint8  [K][2][NB][3] */
+  int64_t lut8;        /* uint8  [K][2][NB][3][256] */
+  int64_t q16;         /* int64  [K][2][NB][3][2] = (A, Bq) */
+  int64_t weights;     /* uint16 [K][w_max] */
+} rt_sizes;
+
+/* Statistics (section 3.1: intensity distributions of the narrow bands along
+ * the seams; whole-frame distributions of each camera).  Histogram bin of a
+ * sample v: v for 8-bit samples, min(v >> (bit_depth - 8), 255) otherwise.
+ * n, S1 = sum v, S2 = sum v^2 are exact. */
+typedef struct {
+  uint32_t* band_hist;
+  uint64_t* band_sums;
+  uint32_t* whole_hist;  /* may be NULL where documented */
+  uint64_t* whole_sums;  /* may be NULL where documented */
+} rt_stats_buf;
+
+/* Per (camera, side, block, channel) affine maps and their history flag
+ * (1 = the unit holds an estimate).  This is the device-resident state that
+ * exponential smoothing reads and updates. */
+typedef struct {
+  double* params;
+  uint8_t* valid;
+} rt_params_buf;
+
+/* Fixed-point maps: q16 (A, Bq) = round_half_even((a, b) * 65536) for every
+ * unit; lut8 L[x] = clamp((A x + Bq + 32768) >> 16, 0, 255) for units of 8-bit
+ * cameras (entries of 16-bit cameras are not written); weights = Q8 blend
+ * weight per column (zero beyond a camera's width). */
+typedef struct {
+  uint8_t* lut8;
+  int64_t* q16;
+  uint16_t* weights;
+} rt_lut_buf;
+
+typedef struct rt_ctx rt_ctx;
+
+/* Create a context for n_cams cameras.  Validates the rig (dimensions,
+ * channels/bit depth, ring positions, pitch) and uploads small device tables
+ * to the current HIP device.  *out receives the context; on failure *out is
+ * NULL and a negative status is returned. */
+rt_status rt_ctx_create(const rt_camera_desc* cams, int32_t n_cams, const rt_opts* opts, rt_ctx** out);
+
+/* Destroy a context (NULL is accepted).  Synchronizes the device first. */
+rt_status rt_ctx_destroy(rt_ctx* ctx);
+
+/* Element counts of every buffer this context expects. */
+rt_status rt_ctx_sizes(const rt_ctx* ctx, rt_sizes* out);
+
+/* Section 3.1, band statistics: per (camera, side, block, channel) histogram
+ * and (n, S1, S2) of the border bands; and, when out->whole_hist and
+ * out->whole_sums are both non-NULL, the same over each whole frame.
+ * frames: host array of K device pointers.  Outputs are overwritten. */
+rt_status rt_stats(rt_ctx* ctx, const void* const* frames, const rt_stats_buf* out, void* stream);
+
+/* Section 3.1, shared spectrum and affine fit, then exponential smoothing.
+ * For every (camera, side, block, channel): mu, sigma of the own band and of
+ * the facing band (binary64, from n, S1, S2); shared mu_s = (mu_own + mu_fac)/2,
+ * sigma_s = (sigma_own + sigma_fac)/2; a = sigma_s/sigma_own (1 if the own
+ * variance is 0) clamped to [a_min, a_max]; b = mu_s - a mu_own.  No estimate
+ * when either band is empty: the unit keeps its state (identity if invalid).
+ * Sides without a facing band (open chain) get the identity.  In smoothing
+ * mode a valid unit becomes (1 - alpha) prev + alpha new, element-wise.
+ * state is read and overwritten in place (params and valid). */
+rt_status rt_estimate(rt_ctx* ctx, const rt_stats_buf* stats, const rt_params_buf* state, void* stream);
+
+/* Section 3.1, the affine maps as fixed-point tables plus the convex-blend
+ * column weights.  weights: h = floor(W/2); column col < h has
+ * round_half_up(256 (h - col) / h), col >= W - h has
+ * round_half_up(256 (col - W + h + 1) / h), the centre column of an odd width
+ * has 0.  All three arrays of `out` are written. */
+rt_status rt_build_lut(rt_ctx* ctx, const rt_params_buf* params, const rt_lut_buf* out, void* stream);
+
+/* Section 3.1, the convex blend of the identity and the map over each half
+ * image: for every sample x at column col of block j,
+ *   y = ((256 - w[col]) x + w[col] f_{side,j,c}(x) + 128) >> 8,
+ * with f the 8-bit table (8-bit cameras) or the q16 map clamped to
+ * [0, 2^bit_depth - 1] (16-bit cameras); centre columns are copied.
+ * out_frames may equal frames (in place).  When whole_out is non-NULL its
+ * whole_hist / whole_sums receive the statistics of the INPUT frames, fused
+ * into the same pass (its band fields are ignored). */
+rt_status rt_apply(rt_ctx* ctx, const void* const* frames, void* const* out_frames, const rt_lut_buf* lut,
+                   const rt_stats_buf* whole_out, void* stream);
+
+/* One whole frame-set: band statistics of frame t -> estimate (updating
+ * `state`) -> tables -> apply to frame t with fused whole-frame statistics.
+ * Equivalent to rt_stats (bands only), rt_estimate, rt_build_lut and rt_apply
+ * with whole statistics, in that order; all buffers must be distinct. */
+rt_status rt_frameset(rt_ctx* ctx, const void* const* frames, void* const* out_frames, const rt_stats_buf* stats,
+                      const rt_params_buf* state, const rt_lut_buf* lut, void* stream);
+
+/* Static description of a status code. */
+const char* rt_status_str(rt_status s);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char* rt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RINGCORR_H */

@@ -1,0 +1,360 @@
+// Host side of the C-ABI: rig validation, context tables, argument checks and
+// the launch sequences of every entry point.  No exception leaves this file.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "rt_internal.h"
+
+using namespace rc;
+
+struct rt_ctx {
+  int device = 0;
+  int n_cams = 0;
+  rt_opts opts{};
+  std::vector<rt_camera_desc> cams;
+  std::vector<DevCam> hcams;
+  std::vector<Tile> htiles;
+  int w_max = 0;
+  int tile_rows = 0;
+  DevCam* dcams = nullptr;
+  Tile* dtiles = nullptr;
+  Geo geo{};
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+rt_status fail(rt_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+rt_status fail(rt_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return s;
+}
+
+rt_status hip_fail(hipError_t e, const char* what) {
+  return fail(RT_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+constexpr int kMaxDim = 32768;
+constexpr int kDefaultTileRows = 8;
+
+bool aligned(const void* p, uintptr_t a) { return ((uintptr_t)p % a) == 0; }
+
+rt_status check_frames(const rt_ctx* ctx, const void* const* frames, const char* name) {
+  if (!frames) return fail(RT_EINVAL, "%s is NULL", name);
+  for (int k = 0; k < ctx->n_cams; ++k) {
+    if (!frames[k]) return fail(RT_EINVAL, "%s[%d] is NULL", name, k);
+    if (!aligned(frames[k], 16)) return fail(RT_EINVAL, "%s[%d] is not 16-byte aligned", name, k);
+  }
+  return RT_OK;
+}
+
+rt_status check_ptr(const void* p, uintptr_t align, const char* name) {
+  if (!p) return fail(RT_EINVAL, "%s is NULL", name);
+  if (!aligned(p, align)) return fail(RT_EINVAL, "%s is not %u-byte aligned", name, (unsigned)align);
+  return RT_OK;
+}
+
+FramePtrs make_ptrs(const rt_ctx* ctx, const void* const* in, void* const* out) {
+  FramePtrs fp;
+  memset(&fp, 0, sizeof fp);
+  for (int k = 0; k < ctx->n_cams; ++k) {
+    fp.in[k] = (const uint8_t*)in[k];
+    fp.out[k] = out ? (uint8_t*)out[k] : nullptr;
+  }
+  return fp;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rt_status_str(rt_status s) {
+  switch (s) {
+    case RT_OK: return "ok";
+    case RT_EINVAL: return "invalid argument";
+    case RT_ENOMEM: return "out of device memory";
+    case RT_EDEVICE: return "HIP device error";
+    case RT_EUNSUPPORTED: return "unsupported";
+    case RT_ESTATE: return "invalid state";
+    default: return "unknown status";
+  }
+}
+
+const char* rt_last_error(void) { return g_last_error.c_str(); }
+
+rt_status rt_ctx_create(const rt_camera_desc* cams, int32_t n_cams, const rt_opts* opts, rt_ctx** out) {
+  if (!out) return fail(RT_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!cams || !opts) return fail(RT_EINVAL, "cams or opts is NULL");
+  if (n_cams < 1 || n_cams > RT_MAX_CAMS) return fail(RT_EINVAL, "n_cams %d outside 1..%d", n_cams, RT_MAX_CAMS);
+  const rt_opts& o = *opts;
+  if (o.n_blocks < 1 || o.n_blocks > RT_MAX_BLOCKS) return fail(RT_EINVAL, "n_blocks %d outside 1..%d", o.n_blocks, RT_MAX_BLOCKS);
+  if (o.band_width < 1) return fail(RT_EINVAL, "band_width %d < 1", o.band_width);
+  if (o.closed_ring != 0 && o.closed_ring != 1) return fail(RT_EINVAL, "closed_ring must be 0 or 1");
+  if (o.mode != RT_MODE_STANDARD && o.mode != RT_MODE_SMOOTHING) return fail(RT_EINVAL, "mode %d unknown", o.mode);
+  if (!(o.ema_alpha > 0.0 && o.ema_alpha <= 1.0)) return fail(RT_EINVAL, "ema_alpha must lie in (0, 1]");
+  if (!(o.a_min > 0.0 && o.a_min <= o.a_max && isfinite(o.a_max)))
+    return fail(RT_EINVAL, "need 0 < a_min <= a_max < inf");
+
+  for (int k = 0; k < n_cams; ++k) {
+    const rt_camera_desc& c = cams[k];
+    if (c.width < 1 || c.height < 1 || c.width > kMaxDim || c.height > kMaxDim)
+      return fail(RT_EINVAL, "camera %d: size %dx%d outside 1..%d", k, c.width, c.height, kMaxDim);
+    if (c.channels != 1 && c.channels != 3) return fail(RT_EINVAL, "camera %d: channels %d not 1 or 3", k, c.channels);
+    if (c.bit_depth < 8 || c.bit_depth > 16) return fail(RT_EINVAL, "camera %d: bit_depth %d outside 8..16", k, c.bit_depth);
+    if (c.bit_depth > 8 && c.channels != 1)
+      return fail(RT_EINVAL, "camera %d: 16-bit samples need channels == 1", k);
+    const int64_t row_bytes = (int64_t)c.width * c.channels * (c.bit_depth > 8 ? 2 : 1);
+    if (c.pitch_bytes < row_bytes || c.pitch_bytes % 16 != 0)
+      return fail(RT_EINVAL, "camera %d: pitch %lld must be >= %lld and a multiple of 16", k,
+                  (long long)c.pitch_bytes, (long long)row_bytes);
+    if ((int64_t)(c.height - 1) * c.pitch_bytes + row_bytes >= (int64_t)1 << 31)
+      return fail(RT_EUNSUPPORTED, "camera %d: frame larger than 2 GiB", k);
+  }
+  // Rings: positions 0..m-1 each once; equal channels and bit depth.
+  for (int k = 0; k < n_cams; ++k) {
+    int m = 0;
+    std::vector<int> seen;
+    for (int i = 0; i < n_cams; ++i) {
+      if (cams[i].ring != cams[k].ring) continue;
+      ++m;
+      seen.push_back(cams[i].pos);
+      if (cams[i].channels != cams[k].channels || cams[i].bit_depth != cams[k].bit_depth)
+        return fail(RT_EINVAL, "ring %d mixes channel counts or bit depths", cams[k].ring);
+    }
+    std::sort(seen.begin(), seen.end());
+    for (int p = 0; p < m; ++p)
+      if (seen[p] != p) return fail(RT_EINVAL, "ring %d: positions must be 0..%d, each once", cams[k].ring, m - 1);
+  }
+
+  rt_ctx* ctx = new (std::nothrow) rt_ctx();
+  if (!ctx) return fail(RT_ENOMEM, "host allocation failed");
+  (void)hipGetDevice(&ctx->device);
+  ctx->n_cams = n_cams;
+  ctx->opts = o;
+  ctx->cams.assign(cams, cams + n_cams);
+  ctx->tile_rows = kDefaultTileRows;
+  ctx->hcams.resize(n_cams);
+  for (int k = 0; k < n_cams; ++k) {
+    const rt_camera_desc& c = cams[k];
+    DevCam& d = ctx->hcams[k];
+    memset(&d, 0, sizeof d);
+    d.width = c.width;
+    d.height = c.height;
+    d.channels = c.channels;
+    d.bit_depth = c.bit_depth;
+    d.bps = c.bit_depth > 8 ? 2 : 1;
+    d.half = c.width / 2;
+    d.band = std::min(o.band_width, d.half);
+    d.row_bytes = c.width * c.channels * d.bps;
+    d.pitch = c.pitch_bytes;
+    // Ring neighbours: right side of position p meets the left side of p + 1.
+    int m = 0;
+    for (int i = 0; i < n_cams; ++i) m += cams[i].ring == c.ring;
+    for (int s = 0; s < 2; ++s) {
+      int q = c.pos + (s == 1 ? 1 : -1);
+      d.face_cam[s] = -1;
+      d.face_side[s] = 1 - s;
+      if (q < 0 || q >= m) {
+        if (!o.closed_ring) continue;
+        q = (q + m) % m;
+      }
+      for (int i = 0; i < n_cams; ++i)
+        if (cams[i].ring == c.ring && cams[i].pos == q) d.face_cam[s] = i;
+    }
+    ctx->w_max = std::max(ctx->w_max, c.width);
+  }
+  // Tiles: every block split into runs of at most tile_rows rows.
+  for (int k = 0; k < n_cams; ++k) {
+    const int H = cams[k].height;
+    for (int j = 0; j < o.n_blocks; ++j) {
+      const int r0 = (int)((int64_t)j * H / o.n_blocks), r1 = (int)((int64_t)(j + 1) * H / o.n_blocks);
+      for (int r = r0; r < r1; r += ctx->tile_rows)
+        ctx->htiles.push_back(Tile{k, j, r, std::min(r1, r + ctx->tile_rows)});
+    }
+  }
+  hipError_t e = hipMalloc((void**)&ctx->dcams, sizeof(DevCam) * n_cams);
+  if (e == hipSuccess) e = hipMalloc((void**)&ctx->dtiles, sizeof(Tile) * ctx->htiles.size());
+  if (e != hipSuccess) {
+    rt_ctx_destroy(ctx);
+    return fail(RT_ENOMEM, "device tables: %s", hipGetErrorString(e));
+  }
+  e = hipMemcpy(ctx->dcams, ctx->hcams.data(), sizeof(DevCam) * n_cams, hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(ctx->dtiles, ctx->htiles.data(), sizeof(Tile) * ctx->htiles.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    rt_ctx_destroy(ctx);
+    return hip_fail(e, "uploading context tables");
+  }
+  Geo& g = ctx->geo;
+  g.cams = ctx->dcams;
+  g.tiles = ctx->dtiles;
+  g.n_cams = n_cams;
+  g.n_blocks = o.n_blocks;
+  g.w_max = ctx->w_max;
+  g.n_tiles = (int32_t)ctx->htiles.size();
+  g.mode = o.mode;
+  g.alpha = o.ema_alpha;
+  g.a_min = o.a_min;
+  g.a_max = o.a_max;
+  *out = ctx;
+  return RT_OK;
+}
+
+rt_status rt_ctx_destroy(rt_ctx* ctx) {
+  if (!ctx) return RT_OK;
+  (void)hipDeviceSynchronize();
+  if (ctx->dcams) (void)hipFree(ctx->dcams);
+  if (ctx->dtiles) (void)hipFree(ctx->dtiles);
+  delete ctx;
+  return RT_OK;
+}
+
+rt_status rt_ctx_sizes(const rt_ctx* ctx, rt_sizes* out) {
+  if (!ctx || !out) return fail(RT_EINVAL, "ctx or out is NULL");
+  const int64_t K = ctx->n_cams, NB = ctx->opts.n_blocks;
+  out->n_cams = ctx->n_cams;
+  out->n_blocks = ctx->opts.n_blocks;
+  out->w_max = ctx->w_max;
+  out->reserved = 0;
+  out->band_hist = K * 2 * NB * kCS * kNB;
+  out->band_sums = K * 2 * NB * kCS * 3;
+  out->whole_hist = K * kCS * kNB;
+  out->whole_sums = K * kCS * 3;
+  out->params = K * 2 * NB * kCS * 2;
+  out->valid = K * 2 * NB * kCS;
+  out->lut8 = K * 2 * NB * kCS * kNB;
+  out->q16 = K * 2 * NB * kCS * 2;
+  out->weights = K * ctx->w_max;
+  return RT_OK;
+}
+
+static rt_status check_stats(const rt_stats_buf* s, bool bands, bool whole) {
+  if (!s) return fail(RT_EINVAL, "stats buffer struct is NULL");
+  rt_status r = RT_OK;
+  if (bands && (r = check_ptr(s->band_hist, 4, "band_hist")) != RT_OK) return r;
+  if (bands && (r = check_ptr(s->band_sums, 8, "band_sums")) != RT_OK) return r;
+  if (whole && (r = check_ptr(s->whole_hist, 4, "whole_hist")) != RT_OK) return r;
+  if (whole && (r = check_ptr(s->whole_sums, 8, "whole_sums")) != RT_OK) return r;
+  return RT_OK;
+}
+
+static rt_status check_params(const rt_params_buf* p) {
+  if (!p) return fail(RT_EINVAL, "params buffer struct is NULL");
+  rt_status r = check_ptr(p->params, 8, "params");
+  if (r == RT_OK) r = check_ptr(p->valid, 1, "valid");
+  return r;
+}
+
+static rt_status check_lut(const rt_lut_buf* l) {
+  if (!l) return fail(RT_EINVAL, "lut buffer struct is NULL");
+  rt_status r = check_ptr(l->lut8, 4, "lut8");
+  if (r == RT_OK) r = check_ptr(l->q16, 8, "q16");
+  if (r == RT_OK) r = check_ptr(l->weights, 2, "weights");
+  return r;
+}
+
+static Bufs make_bufs(const rt_stats_buf* s, const rt_params_buf* p, const rt_lut_buf* l) {
+  Bufs b;
+  memset(&b, 0, sizeof b);
+  if (s) { b.band_hist = s->band_hist; b.band_sums = s->band_sums; b.whole_hist = s->whole_hist; b.whole_sums = s->whole_sums; }
+  if (p) { b.params = p->params; b.valid = p->valid; }
+  if (l) { b.lut8 = l->lut8; b.q16 = l->q16; b.weights = l->weights; }
+  return b;
+}
+
+static rt_status whole_pass(rt_ctx* ctx, const FramePtrs& fp, const Bufs& b, bool write, hipStream_t st) {
+  const int64_t K = ctx->n_cams;
+  hipError_t e = launch_fill_zero(b.whole_hist, K * kCS * kNB * 4, st);
+  if (e == hipSuccess) e = launch_fill_zero(b.whole_sums, K * kCS * 3 * 8, st);
+  if (e != hipSuccess) return hip_fail(e, "zero fill");
+  e = write ? launch_apply(ctx->geo, fp, b, true, st) : launch_whole_stats(ctx->geo, fp, b, st);
+  if (e != hipSuccess) return hip_fail(e, write ? "apply" : "whole-frame statistics");
+  e = launch_whole_finalize(ctx->geo, b, st);
+  if (e != hipSuccess) return hip_fail(e, "whole-frame finalize");
+  return RT_OK;
+}
+
+rt_status rt_stats(rt_ctx* ctx, const void* const* frames, const rt_stats_buf* out, void* stream) {
+  if (!ctx) return fail(RT_EINVAL, "ctx is NULL");
+  rt_status r = check_frames(ctx, frames, "frames");
+  if (r != RT_OK) return r;
+  if (!out) return fail(RT_EINVAL, "out is NULL");
+  const bool whole = out->whole_hist && out->whole_sums;
+  if ((r = check_stats(out, true, whole)) != RT_OK) return r;
+  hipStream_t st = (hipStream_t)stream;
+  const FramePtrs fp = make_ptrs(ctx, frames, nullptr);
+  const Bufs b = make_bufs(out, nullptr, nullptr);
+  hipError_t e = launch_band_stats(ctx->geo, fp, b, st);
+  if (e != hipSuccess) return hip_fail(e, "band statistics");
+  if (whole) return whole_pass(ctx, fp, b, false, st);
+  return RT_OK;
+}
+
+rt_status rt_estimate(rt_ctx* ctx, const rt_stats_buf* stats, const rt_params_buf* state, void* stream) {
+  if (!ctx) return fail(RT_EINVAL, "ctx is NULL");
+  rt_status r = check_stats(stats, true, false);
+  if (r == RT_OK) r = check_params(state);
+  if (r != RT_OK) return r;
+  hipError_t e = launch_estimate(ctx->geo, make_bufs(stats, state, nullptr), (hipStream_t)stream);
+  return e == hipSuccess ? RT_OK : hip_fail(e, "estimate");
+}
+
+rt_status rt_build_lut(rt_ctx* ctx, const rt_params_buf* params, const rt_lut_buf* out, void* stream) {
+  if (!ctx) return fail(RT_EINVAL, "ctx is NULL");
+  rt_status r = check_params(params);
+  if (r == RT_OK) r = check_lut(out);
+  if (r != RT_OK) return r;
+  hipError_t e = launch_build_lut(ctx->geo, make_bufs(nullptr, params, out), (hipStream_t)stream);
+  return e == hipSuccess ? RT_OK : hip_fail(e, "build_lut");
+}
+
+rt_status rt_apply(rt_ctx* ctx, const void* const* frames, void* const* out_frames, const rt_lut_buf* lut,
+                   const rt_stats_buf* whole_out, void* stream) {
+  if (!ctx) return fail(RT_EINVAL, "ctx is NULL");
+  rt_status r = check_frames(ctx, frames, "frames");
+  if (r == RT_OK) r = check_frames(ctx, (const void* const*)out_frames, "out_frames");
+  if (r == RT_OK) r = check_lut(lut);
+  if (r == RT_OK && whole_out) r = check_stats(whole_out, false, true);
+  if (r != RT_OK) return r;
+  hipStream_t st = (hipStream_t)stream;
+  const FramePtrs fp = make_ptrs(ctx, frames, out_frames);
+  const Bufs b = make_bufs(whole_out, nullptr, lut);
+  if (whole_out) return whole_pass(ctx, fp, b, true, st);
+  hipError_t e = launch_apply(ctx->geo, fp, b, false, st);
+  return e == hipSuccess ? RT_OK : hip_fail(e, "apply");
+}
+
+rt_status rt_frameset(rt_ctx* ctx, const void* const* frames, void* const* out_frames, const rt_stats_buf* stats,
+                      const rt_params_buf* state, const rt_lut_buf* lut, void* stream) {
+  if (!ctx) return fail(RT_EINVAL, "ctx is NULL");
+  rt_status r = check_frames(ctx, frames, "frames");
+  if (r == RT_OK) r = check_frames(ctx, (const void* const*)out_frames, "out_frames");
+  if (r == RT_OK) r = check_stats(stats, true, true);
+  if (r == RT_OK) r = check_params(state);
+  if (r == RT_OK) r = check_lut(lut);
+  if (r != RT_OK) return r;
+  hipStream_t st = (hipStream_t)stream;
+  const FramePtrs fp = make_ptrs(ctx, frames, out_frames);
+  const Bufs b = make_bufs(stats, state, lut);
+  hipError_t e = launch_band_stats(ctx->geo, fp, b, st);
+  if (e == hipSuccess) e = launch_estimate(ctx->geo, b, st);
+  if (e == hipSuccess) e = launch_build_lut(ctx->geo, b, st);
+  if (e != hipSuccess) return hip_fail(e, "frameset estimate stage");
+  return whole_pass(ctx, fp, b, true, st);
+}
+
+}  // extern "C"

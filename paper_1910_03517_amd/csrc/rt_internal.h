@@ -1,0 +1,82 @@
+// Internal declarations of the ringcorr HIP library (not part of the C-ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/ringcorr.h"
+
+namespace rc {
+
+constexpr int kCS = RT_CSLOTS;   // channel slots
+constexpr int kNB = RT_NBINS;    // histogram bins
+
+// Per-camera geometry as the kernels see it (uploaded once per context).
+struct DevCam {
+  int32_t width, height, channels, bit_depth;
+  int32_t bps;           // bytes per sample: 1 or 2
+  int32_t band;          // band width clamped to floor(W/2)
+  int32_t half;          // floor(W/2)
+  int32_t row_bytes;     // width * channels * bps
+  int32_t face_cam[2];   // camera facing side s, -1 if none (open chain end)
+  int32_t face_side[2];
+  int64_t pitch;         // bytes between rows
+};
+
+// One unit of the apply pass: rows [r0, r1) of block `block` of camera `cam`.
+struct Tile {
+  int32_t cam, block, r0, r1;
+};
+
+// Frame pointers of one launch, passed by value as a kernel argument.
+struct FramePtrs {
+  const uint8_t* in[RT_MAX_CAMS];
+  uint8_t* out[RT_MAX_CAMS];
+};
+
+// Caller buffers (device pointers) of one launch.
+struct Bufs {
+  uint32_t* band_hist;
+  uint64_t* band_sums;
+  uint32_t* whole_hist;
+  uint64_t* whole_sums;
+  double* params;
+  uint8_t* valid;
+  uint8_t* lut8;
+  int64_t* q16;
+  uint16_t* weights;
+};
+
+// Context-wide constants passed to every kernel.
+struct Geo {
+  const DevCam* cams;    // device array [K]
+  const Tile* tiles;     // device array [n_tiles]
+  int32_t n_cams, n_blocks, w_max, n_tiles;
+  int32_t mode;
+  double alpha, a_min, a_max;
+};
+
+// Buffer resource over one frame: loads beyond the last sample of the frame
+// return zero and stores there are dropped by the hardware range check.
+constexpr int kRsrcWord3 = 0x00020000;   // raw dword access on gfx9-family parts
+
+__device__ inline __amdgpu_buffer_rsrc_t frame_rsrc(const void* p, const DevCam& cam) {
+  const int64_t bytes = (int64_t)(cam.height - 1) * cam.pitch + cam.row_bytes;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, kRsrcWord3);
+}
+
+// Index helpers for the caller layouts.
+__host__ __device__ inline int64_t unit_index(int k, int s, int j, int c, int nb) {
+  return (((int64_t)k * 2 + s) * nb + j) * kCS + c;
+}
+
+// Launchers (each defined next to its kernels).  All return hipError_t of the launch.
+hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t st);
+hipError_t launch_band_stats(const Geo& g, const FramePtrs& fp, const Bufs& b, hipStream_t st);
+hipError_t launch_whole_stats(const Geo& g, const FramePtrs& fp, const Bufs& b, hipStream_t st);
+hipError_t launch_whole_finalize(const Geo& g, const Bufs& b, hipStream_t st);
+hipError_t launch_estimate(const Geo& g, const Bufs& b, hipStream_t st);
+hipError_t launch_build_lut(const Geo& g, const Bufs& b, hipStream_t st);
+hipError_t launch_apply(const Geo& g, const FramePtrs& fp, const Bufs& b, bool with_stats, hipStream_t st);
+
+}  // namespace rc

@@ -1,0 +1,323 @@
+"""ctypes binding of libringcorr.so (argument marshalling only).
+
+The functions below carry the names of the C-ABI in include/ringcorr.h and do
+nothing but convert Python / torch arguments into the C structs and pointers;
+every step of the correction runs in the library's HIP kernels.  torch is
+used for device memory and streams only.
+
+The library must have been built (python -m paper_1910_03517_amd.build);
+loading fails loudly otherwise - there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libringcorr.so")
+
+RT_OK, RT_EINVAL, RT_ENOMEM, RT_EDEVICE, RT_EUNSUPPORTED, RT_ESTATE = 0, -1, -2, -3, -4, -5
+RT_MODE_STANDARD, RT_MODE_SMOOTHING = 0, 1
+RT_MAX_CAMS = 64
+CSLOTS, NBINS = 3, 256
+
+EXPORTED = ["rt_ctx_create", "rt_ctx_destroy", "rt_ctx_sizes", "rt_stats", "rt_estimate",
+            "rt_build_lut", "rt_apply", "rt_frameset", "rt_status_str", "rt_last_error"]
+
+
+class rt_camera_desc(ct.Structure):
+    _fields_ = [("width", ct.c_int32), ("height", ct.c_int32), ("channels", ct.c_int32),
+                ("bit_depth", ct.c_int32), ("ring", ct.c_int32), ("pos", ct.c_int32),
+                ("pitch_bytes", ct.c_int64)]
+
+
+class rt_opts(ct.Structure):
+    _fields_ = [("n_blocks", ct.c_int32), ("band_width", ct.c_int32), ("closed_ring", ct.c_int32),
+                ("mode", ct.c_int32), ("ema_alpha", ct.c_double), ("a_min", ct.c_double),
+                ("a_max", ct.c_double)]
+
+
+class rt_sizes(ct.Structure):
+    _fields_ = [("n_cams", ct.c_int32), ("n_blocks", ct.c_int32), ("w_max", ct.c_int32),
+                ("reserved", ct.c_int32), ("band_hist", ct.c_int64), ("band_sums", ct.c_int64),
+                ("whole_hist", ct.c_int64), ("whole_sums", ct.c_int64), ("params", ct.c_int64),
+                ("valid", ct.c_int64), ("lut8", ct.c_int64), ("q16", ct.c_int64), ("weights", ct.c_int64)]
+
+
+class rt_stats_buf(ct.Structure):
+    _fields_ = [("band_hist", ct.c_void_p), ("band_sums", ct.c_void_p),
+                ("whole_hist", ct.c_void_p), ("whole_sums", ct.c_void_p)]
+
+
+class rt_params_buf(ct.Structure):
+    _fields_ = [("params", ct.c_void_p), ("valid", ct.c_void_p)]
+
+
+class rt_lut_buf(ct.Structure):
+    _fields_ = [("lut8", ct.c_void_p), ("q16", ct.c_void_p), ("weights", ct.c_void_p)]
+
+
+class RtError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"ringcorr status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ct.CDLL:
+    """Load the library once; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_1910_03517_amd.build`")
+    lib = ct.CDLL(path)
+    P = ct.c_void_p
+    lib.rt_ctx_create.argtypes = [ct.POINTER(rt_camera_desc), ct.c_int32, ct.POINTER(rt_opts), ct.POINTER(P)]
+    lib.rt_ctx_destroy.argtypes = [P]
+    lib.rt_ctx_sizes.argtypes = [P, ct.POINTER(rt_sizes)]
+    lib.rt_stats.argtypes = [P, ct.POINTER(P), ct.POINTER(rt_stats_buf), P]
+    lib.rt_estimate.argtypes = [P, ct.POINTER(rt_stats_buf), ct.POINTER(rt_params_buf), P]
+    lib.rt_build_lut.argtypes = [P, ct.POINTER(rt_params_buf), ct.POINTER(rt_lut_buf), P]
+    lib.rt_apply.argtypes = [P, ct.POINTER(P), ct.POINTER(P), ct.POINTER(rt_lut_buf), ct.POINTER(rt_stats_buf), P]
+    lib.rt_frameset.argtypes = [P, ct.POINTER(P), ct.POINTER(P), ct.POINTER(rt_stats_buf),
+                                ct.POINTER(rt_params_buf), ct.POINTER(rt_lut_buf), P]
+    for name in EXPORTED:
+        getattr(lib, name).restype = ct.c_int32
+    lib.rt_status_str.argtypes = [ct.c_int32]
+    lib.rt_status_str.restype = ct.c_char_p
+    lib.rt_last_error.argtypes = []
+    lib.rt_last_error.restype = ct.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(status: int) -> None:
+    if status != RT_OK:
+        raise RtError(status, load().rt_last_error().decode())
+
+
+def _stream_handle(stream) -> ct.c_void_p:
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return ct.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _ptr_array(tensors) -> ct.Array:
+    arr = (ct.c_void_p * len(tensors))()
+    for i, t in enumerate(tensors):
+        arr[i] = t.data_ptr() if hasattr(t, "data_ptr") else int(t)
+    return arr
+
+
+def _p(t):
+    return None if t is None else ct.c_void_p(t.data_ptr())
+
+
+# ----------------------------------------------------------------------------- C-ABI calls
+
+def rt_ctx_create(cams, opts: "Options") -> ct.c_void_p:
+    lib = load()
+    arr = (rt_camera_desc * len(cams))()
+    for i, c in enumerate(cams):
+        arr[i] = rt_camera_desc(c.width, c.height, c.channels, c.bit_depth, c.ring, c.pos, c.pitch_bytes)
+    o = opts.to_c()
+    ctx = ct.c_void_p()
+    _check(lib.rt_ctx_create(arr, len(cams), ct.byref(o), ct.byref(ctx)))
+    return ctx
+
+
+def rt_ctx_destroy(ctx) -> None:
+    _check(load().rt_ctx_destroy(ctx))
+
+
+def rt_ctx_sizes(ctx) -> rt_sizes:
+    s = rt_sizes()
+    _check(load().rt_ctx_sizes(ctx, ct.byref(s)))
+    return s
+
+
+def rt_stats(ctx, frames, band_hist, band_sums, whole_hist=None, whole_sums=None, stream=None) -> None:
+    sb = rt_stats_buf(_p(band_hist), _p(band_sums), _p(whole_hist), _p(whole_sums))
+    _check(load().rt_stats(ctx, _ptr_array(frames), ct.byref(sb), _stream_handle(stream)))
+
+
+def rt_estimate(ctx, band_hist, band_sums, params, valid, stream=None) -> None:
+    sb = rt_stats_buf(_p(band_hist), _p(band_sums), None, None)
+    pb = rt_params_buf(_p(params), _p(valid))
+    _check(load().rt_estimate(ctx, ct.byref(sb), ct.byref(pb), _stream_handle(stream)))
+
+
+def rt_build_lut(ctx, params, valid, lut8, q16, weights, stream=None) -> None:
+    pb = rt_params_buf(_p(params), _p(valid))
+    lb = rt_lut_buf(_p(lut8), _p(q16), _p(weights))
+    _check(load().rt_build_lut(ctx, ct.byref(pb), ct.byref(lb), _stream_handle(stream)))
+
+
+def rt_apply(ctx, frames, out_frames, lut8, q16, weights, whole_hist=None, whole_sums=None, stream=None) -> None:
+    lb = rt_lut_buf(_p(lut8), _p(q16), _p(weights))
+    wb = None
+    if whole_hist is not None or whole_sums is not None:
+        wb = ct.byref(rt_stats_buf(None, None, _p(whole_hist), _p(whole_sums)))
+    _check(load().rt_apply(ctx, _ptr_array(frames), _ptr_array(out_frames), ct.byref(lb), wb,
+                           _stream_handle(stream)))
+
+
+def rt_frameset(ctx, frames, out_frames, bufs: "Buffers", stream=None) -> None:
+    sb = rt_stats_buf(_p(bufs.band_hist), _p(bufs.band_sums), _p(bufs.whole_hist), _p(bufs.whole_sums))
+    pb = rt_params_buf(_p(bufs.params), _p(bufs.valid))
+    lb = rt_lut_buf(_p(bufs.lut8), _p(bufs.q16), _p(bufs.weights))
+    _check(load().rt_frameset(ctx, _ptr_array(frames), _ptr_array(out_frames), ct.byref(sb), ct.byref(pb),
+                              ct.byref(lb), _stream_handle(stream)))
+
+
+# ----------------------------------------------------------------------------- convenience
+
+@dataclass(frozen=True)
+class Camera:
+    width: int
+    height: int
+    channels: int = 3
+    bit_depth: int = 8
+    ring: int = 0
+    pos: int = 0
+    pitch_bytes: int = 0
+
+    @property
+    def bps(self) -> int:
+        return 1 if self.bit_depth == 8 else 2
+
+    @property
+    def row_bytes(self) -> int:
+        return self.width * self.channels * self.bps
+
+    def with_pitch(self, pitch: int | None = None) -> "Camera":
+        p = pitch if pitch is not None else (self.row_bytes + 15) // 16 * 16
+        return Camera(self.width, self.height, self.channels, self.bit_depth, self.ring, self.pos, p)
+
+
+@dataclass(frozen=True)
+class Options:
+    n_blocks: int = 16
+    band_width: int = 32
+    closed_ring: bool = True
+    smoothing: bool = False
+    ema_alpha: float = 0.05
+    a_min: float = 0.125
+    a_max: float = 8.0
+
+    def to_c(self) -> rt_opts:
+        return rt_opts(self.n_blocks, self.band_width, int(self.closed_ring),
+                       RT_MODE_SMOOTHING if self.smoothing else RT_MODE_STANDARD,
+                       self.ema_alpha, self.a_min, self.a_max)
+
+
+class Buffers:
+    """Caller-owned device buffers of one context, shaped as the C-ABI documents."""
+
+    def __init__(self, sizes: rt_sizes, device="cuda"):
+        import torch
+        K, NB, WM = sizes.n_cams, sizes.n_blocks, sizes.w_max
+        e = dict(device=device)
+        self.band_hist = torch.zeros((K, 2, NB, CSLOTS, NBINS), dtype=torch.int32, **e)
+        self.band_sums = torch.zeros((K, 2, NB, CSLOTS, 3), dtype=torch.int64, **e)
+        self.whole_hist = torch.zeros((K, CSLOTS, NBINS), dtype=torch.int32, **e)
+        self.whole_sums = torch.zeros((K, CSLOTS, 3), dtype=torch.int64, **e)
+        self.params = torch.zeros((K, 2, NB, CSLOTS, 2), dtype=torch.float64, **e)
+        self.params[..., 0] = 1.0
+        self.valid = torch.zeros((K, 2, NB, CSLOTS), dtype=torch.uint8, **e)
+        self.lut8 = torch.zeros((K, 2, NB, CSLOTS, NBINS), dtype=torch.uint8, **e)
+        self.q16 = torch.zeros((K, 2, NB, CSLOTS, 2), dtype=torch.int64, **e)
+        self.weights = torch.zeros((K, max(WM, 1)), dtype=torch.int16, **e)
+        for name, t in self.__dict__.items():
+            assert t.numel() == getattr(sizes, name), name
+
+    def host(self) -> dict:
+        """Copies of every buffer as numpy arrays (unsigned views where the ABI is unsigned)."""
+        out = {}
+        for name, t in self.__dict__.items():
+            a = t.cpu().numpy()
+            if name in ("band_hist", "whole_hist"):
+                a = a.view(np.uint32)
+            elif name in ("band_sums", "whole_sums"):
+                a = a.view(np.uint64)
+            elif name == "weights":
+                a = a.view(np.uint16)
+            out[name] = a
+        return out
+
+
+class Rig:
+    """A context plus its buffers; frames are torch tensors laid out per camera."""
+
+    def __init__(self, cams, opts: Options = Options(), device="cuda"):
+        self.cams = [c if c.pitch_bytes else c.with_pitch() for c in cams]
+        self.opts = opts
+        self.ctx = rt_ctx_create(self.cams, opts)
+        self.sizes = rt_ctx_sizes(self.ctx)
+        self.bufs = Buffers(self.sizes, device)
+        self.device = device
+
+    def close(self) -> None:
+        if self.ctx is not None:
+            rt_ctx_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # frame helpers ----------------------------------------------------------
+    def alloc_frames(self) -> list:
+        """Zeroed device frames with each camera's pitch (tensors of shape (H, pitch) bytes)."""
+        import torch
+        return [torch.zeros((c.height, c.pitch_bytes), dtype=torch.uint8, device=self.device) for c in self.cams]
+
+    def upload(self, frames_np) -> list:
+        out = self.alloc_frames()
+        self.upload_into(out, frames_np)
+        return out
+
+    def upload_into(self, dev, frames_np) -> None:
+        import torch
+        for d, c, f in zip(dev, self.cams, frames_np):
+            raw = np.ascontiguousarray(f).view(np.uint8).reshape(c.height, c.row_bytes)
+            d[:, :c.row_bytes].copy_(torch.from_numpy(raw))
+
+    def download(self, frames_dev) -> list:
+        out = []
+        for d, c in zip(frames_dev, self.cams):
+            raw = d[:, :c.row_bytes].cpu().numpy()
+            dt = np.uint8 if c.bps == 1 else np.uint16
+            out.append(np.ascontiguousarray(raw).view(dt).reshape(c.height, c.width, c.channels))
+        return out
+
+    # the C-ABI steps ----------------------------------------------------------
+    def stats(self, frames, whole=True, stream=None) -> None:
+        b = self.bufs
+        rt_stats(self.ctx, frames, b.band_hist, b.band_sums,
+                 b.whole_hist if whole else None, b.whole_sums if whole else None, stream)
+
+    def estimate(self, stream=None) -> None:
+        b = self.bufs
+        rt_estimate(self.ctx, b.band_hist, b.band_sums, b.params, b.valid, stream)
+
+    def build_lut(self, stream=None) -> None:
+        b = self.bufs
+        rt_build_lut(self.ctx, b.params, b.valid, b.lut8, b.q16, b.weights, stream)
+
+    def apply(self, frames, out_frames, whole=False, stream=None) -> None:
+        b = self.bufs
+        rt_apply(self.ctx, frames, out_frames, b.lut8, b.q16, b.weights,
+                 b.whole_hist if whole else None, b.whole_sums if whole else None, stream)
+
+    def frameset(self, frames, out_frames, stream=None) -> None:
+        rt_frameset(self.ctx, frames, out_frames, self.bufs, stream)

@@ -1,0 +1,105 @@
+"""Helpers of the GPU parity tests: run the HIP path through the C-ABI, run the
+oracle on the same seeded inputs, and compare at the stated bar:
+bit-exact statistics, tables and pixels; parameters within 1e-4 relative."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+
+from oracle import ringcorr as rc
+from paper_1910_03517_amd import rt
+
+PARAM_RTOL = 1e-4
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def oracle_cams(cams):
+    return [rc.Camera(c.width, c.height, c.channels, c.bit_depth, c.ring, c.pos) for c in cams]
+
+
+def oracle_opts(o: rt.Options) -> rc.Options:
+    return rc.Options(n_blocks=o.n_blocks, band_width=o.band_width, closed_ring=o.closed_ring,
+                      smoothing=o.smoothing, ema_alpha=o.ema_alpha, a_min=o.a_min, a_max=o.a_max)
+
+
+def rt_cams(spec_cams, pad: int = 0):
+    out = []
+    for c in spec_cams:
+        cam = rt.Camera(c.width, c.height, c.channels, c.bit_depth, c.ring, c.pos)
+        out.append(cam.with_pitch((cam.row_bytes + 15) // 16 * 16 + 16 * pad))
+    return out
+
+
+def assert_ints_equal(gpu, ref, name):
+    g = np.asarray(gpu).astype(np.int64)
+    r = np.asarray(ref).astype(np.int64)
+    assert g.shape == r.shape, (name, g.shape, r.shape)
+    bad = np.argwhere(g != r)
+    assert bad.size == 0, f"{name}: {len(bad)} mismatches, first at {bad[0].tolist()}: gpu {g[tuple(bad[0])]} ref {r[tuple(bad[0])]}"
+
+
+def assert_params_close(gpu, ref, name="params"):
+    a_g, b_g = gpu[..., 0], gpu[..., 1]
+    a_r, b_r = ref[..., 0], ref[..., 1]
+    assert np.all(np.isfinite(gpu)), name
+    da = np.abs(a_g - a_r) <= PARAM_RTOL * np.abs(a_r)
+    db = np.abs(b_g - b_r) <= PARAM_RTOL * np.maximum(np.abs(b_r), 1.0)
+    assert da.all() and db.all(), f"{name}: {np.count_nonzero(~da)} a and {np.count_nonzero(~db)} b outside 1e-4"
+
+
+def gpu_chain_separate(rig: rt.Rig, frames_dev, out_dev, whole_in_stats=True, whole_in_apply=True):
+    """rt_stats -> rt_estimate -> rt_build_lut -> rt_apply, then copies of every buffer."""
+    import torch
+    rig.stats(frames_dev, whole=whole_in_stats)
+    torch.cuda.synchronize()
+    st = rig.bufs.host()
+    rig.estimate()
+    rig.build_lut()
+    rig.apply(frames_dev, out_dev, whole=whole_in_apply)
+    torch.cuda.synchronize()
+    h = rig.bufs.host()
+    h["stats_band_hist"] = st["band_hist"]
+    h["stats_band_sums"] = st["band_sums"]
+    h["stats_whole_hist"] = st["whole_hist"]
+    h["stats_whole_sums"] = st["whole_sums"]
+    h["out"] = rig.download(out_dev)
+    return h
+
+
+def compare_step(cams_o, opts_o, frames_np, gpu: dict, prev_params=None, prev_valid=None,
+                 whole_checked=True) -> dict:
+    """Check one frame-set of GPU results against the oracle at the bar.
+
+    Statistics are compared bit for bit.  Parameters are compared within the
+    tolerance and are expected to be bitwise equal; the tables are then checked
+    bit for bit against the oracle's tables *built from the GPU's parameters*,
+    and the pixels against the oracle's apply *with the GPU's tables*, so that
+    an integer step is never excused by a floating-point one.
+    """
+    ref = rc.frameset(cams_o, opts_o, frames_np, prev_params, prev_valid)
+    assert_ints_equal(gpu["band_hist"], ref["band_hist"], "band_hist")
+    assert_ints_equal(gpu["band_sums"], ref["band_sums"], "band_sums")
+    if whole_checked:
+        assert_ints_equal(gpu["whole_hist"], ref["whole_hist"], "whole_hist")
+        assert_ints_equal(gpu["whole_sums"], ref["whole_sums"], "whole_sums")
+    assert_ints_equal(gpu["valid"], ref["valid"], "valid")
+    assert_params_close(gpu["params"], ref["params"])
+    bitwise = np.array_equal(gpu["params"].view(np.uint64), ref["params"].view(np.uint64))
+    lut8_o, q16_o = rc.build_luts(cams_o, opts_o, gpu["params"])
+    assert_ints_equal(gpu["q16"], q16_o, "q16")
+    for k, c in enumerate(cams_o):
+        if c.bit_depth == 8:
+            assert_ints_equal(gpu["lut8"][k], lut8_o[k], f"lut8[{k}]")
+    assert_ints_equal(gpu["weights"], rc.weights_table(cams_o), "weights")
+    for k, c in enumerate(cams_o):
+        exp = rc.apply_camera(frames_np[k], c, opts_o, lut8_o[k], q16_o[k])
+        assert_ints_equal(gpu["out"][k], exp, f"out[{k}]")
+    if bitwise:
+        for k in range(len(cams_o)):
+            assert_ints_equal(gpu["out"][k], ref["out"][k], f"out end-to-end [{k}]")
+    return dict(ref=ref, bitwise=bitwise)

@@ -1,0 +1,171 @@
+"""GPU parity: the HIP path through the C-ABI against the CPU oracle.
+
+Bit-exact statistics, tables and pixels; parameters within 1e-4 relative (and
+bitwise equal where the binary64 arithmetic is the same, which is expected).
+Sizes run from 1x1 frames to the full 14x1920x1080 and uneven rigs, in the
+launch configuration the benchmark times."""
+import numpy as np
+import pytest
+
+from tests.gpu_helpers import (compare_step, gpu_chain_separate, oracle_cams, oracle_opts, rt_cams, say,
+                               assert_ints_equal)
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_1910_03517_amd import rt, synth  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    rt.load()   # fails loudly if the library is missing
+
+
+def run_separate(spec_cams, opts, frames_np, pad=0, whole_in_apply=True):
+    cams = rt_cams(spec_cams, pad)
+    rig = rt.Rig(cams, opts)
+    dev = rig.upload(frames_np)
+    out = rig.alloc_frames()
+    g = gpu_chain_separate(rig, dev, out, whole_in_apply=whole_in_apply)
+    for name in ("band_hist", "band_sums", "whole_hist", "whole_sums"):
+        assert_ints_equal(g["stats_" + name], g[name], "stats-vs-fused " + name)
+    res = compare_step(oracle_cams(cams), oracle_opts(opts), frames_np, g)
+    rig.close()
+    return res
+
+
+def test_vga_single_camera_separate_calls():
+    say("case: 1x640x480 rgb8, separate calls")
+    rig = synth.single_vga()
+    frames = synth.rig_frames(rig, 0)
+    res = run_separate(rig.cams, rt.Options(), frames)
+    assert res["bitwise"], "params not bitwise equal to the binary64 oracle"
+
+
+SMALL_CASES = [
+    # (W, H, C, bit_depth, K, closed, NB, B, pad)
+    (1, 1, 3, 8, 1, True, 1, 32, 0),
+    (1, 5, 3, 8, 2, True, 4, 32, 1),
+    (2, 3, 1, 8, 3, True, 2, 1, 0),
+    (3, 7, 3, 8, 2, True, 16, 32, 0),          # H < NB: empty blocks
+    (5, 9, 3, 8, 3, False, 4, 2, 2),           # open chain
+    (17, 13, 3, 8, 2, True, 3, 32, 1),         # W < 2B: band clamp, ragged groups
+    (33, 31, 3, 8, 4, True, 7, 5, 0),
+    (64, 48, 1, 8, 2, True, 4, 8, 1),          # gray8
+    (61, 40, 1, 10, 2, True, 5, 6, 0),         # 10-bit
+    (50, 21, 1, 12, 3, False, 3, 7, 2),        # 12-bit open
+    (77, 66, 1, 16, 2, True, 16, 32, 1),       # 16-bit
+    (130, 70, 3, 8, 3, True, 16, 32, 0),
+    (1031, 67, 3, 8, 2, True, 64, 32, 3),      # several 256-thread passes + tail
+]
+
+
+@pytest.mark.parametrize("case", SMALL_CASES, ids=[f"{c[0]}x{c[1]}x{c[2]}b{c[3]}k{c[4]}" for c in SMALL_CASES])
+def test_small_geometries(case):
+    W, H, C, bd, K, closed, NB, B, pad = case
+    say("case:", case)
+    rng = np.random.default_rng(abs(hash(case)) % (2 ** 32))
+    spec = [synth.CamSpec(W, H, C, bd, 0, p) for p in range(K)]
+    frames = [synth.tiny_frame(H, W, C, bd, rng) for _ in range(K)]
+    opts = rt.Options(n_blocks=NB, band_width=B, closed_ring=closed)
+    run_separate(spec, opts, frames, pad)
+
+
+def test_flat_and_saturated_bands():
+    """sigma = 0 bands (a = 1 path) and fully saturated cameras."""
+    say("case: flat/saturated 3x 96x64")
+    rng = np.random.default_rng(7)
+    f0 = np.full((64, 96, 3), 255, np.uint8)
+    f1 = rng.integers(0, 256, (64, 96, 3)).astype(np.uint8)
+    f1[:, :40] = 17
+    f2 = np.zeros((64, 96, 3), np.uint8)
+    spec = [synth.CamSpec(96, 64, 3, 8, 0, p) for p in range(3)]
+    run_separate(spec, rt.Options(n_blocks=4, band_width=16), [f0, f1, f2])
+
+
+def test_two_rings_mixed_dtypes():
+    say("case: two rings rgb8 + u16")
+    rng = np.random.default_rng(3)
+    spec = ([synth.CamSpec(200, 90, 3, 8, 0, p) for p in (1, 0, 2)]
+            + [synth.CamSpec(120, 64, 1, 16, 7, p) for p in (1, 0)])
+    frames = [synth.tiny_frame(c.height, c.width, c.channels, c.bit_depth, rng) for c in spec]
+    run_separate(spec, rt.Options(n_blocks=8, band_width=12), frames)
+
+
+def test_inplace_apply():
+    say("case: in-place apply 2x 256x40")
+    rng = np.random.default_rng(4)
+    spec = [synth.CamSpec(256, 40, 3, 8, 0, p) for p in range(2)]
+    frames = [synth.tiny_frame(40, 256, 3, 8, rng) for _ in range(2)]
+    cams = rt_cams(spec)
+    rig = rt.Rig(cams, rt.Options(n_blocks=4))
+    dev = rig.upload(frames)
+    out = rig.alloc_frames()
+    g = gpu_chain_separate(rig, dev, out)
+    rig.apply(dev, dev)
+    torch.cuda.synchronize()
+    for a, b in zip(rig.download(dev), g["out"]):
+        assert np.array_equal(a, b)
+    rig.close()
+
+
+def frameset_sequence(rig_spec, opts, n_frames, drift=True, seed=0):
+    cams = rt_cams(rig_spec.cams)
+    rig = rt.Rig(cams, opts)
+    co, oo = oracle_cams(cams), oracle_opts(opts)
+    out = rig.alloc_frames()
+    prev_p = prev_v = None
+    dev = None
+    for t in range(n_frames):
+        say(f"case: {rig_spec.name} frame {t} smoothing={opts.smoothing}")
+        frames = synth.rig_frames(rig_spec, t, drift=drift, seed=seed)
+        if dev is None:
+            dev = rig.upload(frames)
+        else:
+            rig.upload_into(dev, frames)
+        rig.frameset(dev, out)
+        torch.cuda.synchronize()
+        g = rig.bufs.host()
+        g["out"] = rig.download(out)
+        res = compare_step(co, oo, frames, g, prev_p, prev_v)
+        assert res["bitwise"], f"frame {t}: params not bitwise equal"
+        prev_p, prev_v = res["ref"]["params"], res["ref"]["valid"]
+    rig.close()
+
+
+def test_rig14_frameset_standard():
+    frameset_sequence(synth.rig14_1080p(), rt.Options(), 2)
+
+
+def test_rig14_frameset_smoothing():
+    frameset_sequence(synth.rig14_1080p(), rt.Options(smoothing=True), 3)
+
+
+def test_uneven_rig_frameset():
+    frameset_sequence(synth.uneven_rig(), rt.Options(), 1)
+
+
+def test_determinism_repeated_runs():
+    """Integer atomics are order independent: 20 runs must agree bit for bit."""
+    say("case: determinism 14x1920x1080 x20")
+    spec = synth.rig14_1080p()
+    cams = rt_cams(spec.cams)
+    rig = rt.Rig(cams, rt.Options())
+    frames = synth.rig_frames(spec, 0)
+    dev = rig.upload(frames)
+    out = rig.alloc_frames()
+    first = None
+    for i in range(20):
+        rig.bufs.valid.zero_()
+        rig.frameset(dev, out)
+        torch.cuda.synchronize()
+        h = rig.bufs.host()
+        cur = (h["band_hist"].tobytes(), h["whole_hist"].tobytes(), h["whole_sums"].tobytes(),
+               h["params"].tobytes(), b"".join(o[:, :cams[0].row_bytes].cpu().numpy().tobytes() for o in out))
+        if first is None:
+            first = cur
+        else:
+            assert cur == first, f"run {i} differs"
+    rig.close()
