@@ -177,11 +177,29 @@ rt_status rt_apply(rt_ctx* ctx, const void* const* frames, void* const* out_fram
                    const rt_stats_buf* whole_out, void* stream);
 
 /* One whole frame-set: band statistics of frame t -> estimate (updating
- * `state`) -> tables -> apply to frame t with fused whole-frame statistics.
- * Equivalent to rt_stats (bands only), rt_estimate, rt_build_lut and rt_apply
- * with whole statistics, in that order; all buffers must be distinct. */
+ * `state`) -> tables and weights -> apply to frame t with fused whole-frame
+ * statistics of the input -> per-camera reduction.  Four kernels, all cameras
+ * of all rings batched in each; no kernel waits on another workgroup.  Same
+ * results as rt_stats (bands), rt_estimate, rt_build_lut and rt_apply (with
+ * whole statistics) in that order.  All buffers must be distinct.  The calls
+ * use the context's device scratch, so frame-set and apply calls of one
+ * context must be ordered (same stream, or synchronized). */
 rt_status rt_frameset(rt_ctx* ctx, const void* const* frames, void* const* out_frames, const rt_stats_buf* stats,
                       const rt_params_buf* state, const rt_lut_buf* lut, void* stream);
+
+/* Synchronize the device and report RT_EDEVICE if a device-side check of
+ * this context failed since the last call (the flag is then cleared). */
+rt_status rt_ctx_check(rt_ctx* ctx);
+
+/* Performance knobs that never change results: tile height of the apply pass
+ * (rows, 1..4096; each vertical block is split into tiles of equal height of
+ * at most this many rows) and the apply grid (workgroups striding over the
+ * tiles; 0 = one workgroup per tile).  Synchronizes the device; rebuilds the
+ * context's tile table. */
+rt_status rt_ctx_tune(rt_ctx* ctx, int32_t tile_rows, int32_t grid);
+
+/* Current knobs and the resulting number of apply tiles (any pointer may be NULL). */
+rt_status rt_ctx_tuning(const rt_ctx* ctx, int32_t* tile_rows, int32_t* grid, int32_t* n_tiles);
 
 /* Static description of a status code. */
 const char* rt_status_str(rt_status s);

@@ -1,0 +1,229 @@
+// Apply pass of section 3.1 as a device function over one tile: every sample
+// is blended between the identity and its side's affine map with the Q8
+// weight of its column, y = ((256 - w) x + w f(x) + 128) >> 8, in exact
+// integers; optionally fused with the histogram (and, for 16-bit cameras,
+// the sums) of the input samples.
+//
+// A thread owns groups of 4 consecutive pixels of a row (12 bytes for RGB8, 4
+// for gray8, 8 for gray16) and walks down the tile's rows, kUnroll rows at a
+// time so that several loads are in flight; its pixels' weights and table
+// bases stay in registers.  Tables of the tile's block sit in LDS.  The
+// histogram is kept in kRep replicas interleaved bin by bin, lane l updating
+// replica l % kRep, so that lanes of one wave that see the same value mostly
+// hit different LDS words.  At the end of the tile the replicas are summed and
+// stored to the tile's slot in context scratch with plain stores.
+#pragma once
+
+#include "dev_estimate.h"
+
+namespace rc {
+
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x3 __attribute__((ext_vector_type(3)));
+
+constexpr int kRep = 8;      // histogram replicas
+constexpr int kUnroll = 4;   // rows in flight per thread
+
+struct ApplyLds {
+  uint8_t lut[2 * kCS * kNB];          // [side][channel][x]
+  int64_t q[4];                        // [side][A, Bq]
+  uint32_t hist[kCS * kNB * kRep];     // [channel][bin][replica]
+  unsigned long long red[2 * 16];
+};
+
+template <int NW>
+__device__ inline void load_group(__amdgpu_buffer_rsrc_t r, int off, uint32_t (&d)[NW]) {
+  if constexpr (NW == 3) {
+    u32x3 v = __builtin_amdgcn_raw_buffer_load_b96(r, off, 0, 0);
+    d[0] = v.x; d[1] = v.y; d[2] = v.z;
+  } else if constexpr (NW == 2) {
+    u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+    d[0] = v.x; d[1] = v.y;
+  } else {
+    d[0] = __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+  }
+}
+
+template <int NW>
+__device__ inline void store_group(__amdgpu_buffer_rsrc_t r, int off, const uint32_t (&d)[NW]) {
+  if constexpr (NW == 3) {
+    u32x3 v = {d[0], d[1], d[2]};
+    __builtin_amdgcn_raw_buffer_store_b96(v, r, off, 0, 0);
+  } else if constexpr (NW == 2) {
+    u32x2 v = {d[0], d[1]};
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, off, 0, 0);
+  } else {
+    __builtin_amdgcn_raw_buffer_store_b32(d[0], r, off, 0, 0);
+  }
+}
+
+// Per-pixel constants of a thread's group.
+struct PixConst {
+  uint32_t w[4], iw[4];   // weight and 256 - weight
+  int lb[4];              // table base of the pixel's side
+  int64_t qa[4], qb[4];   // 16-bit map of the pixel's side
+};
+
+template <int BPS, bool WRITE, bool STATS>
+__device__ inline uint32_t one_sample(uint32_t x, int c, int p, const PixConst& pc, ApplyLds& L, int hrep,
+                                      int shift, uint32_t maxv, unsigned long long& a1, unsigned long long& a2) {
+  if (STATS) {
+    uint32_t bin = x;
+    if (BPS == 2) { bin = x >> shift; bin = bin > 255u ? 255u : bin; }
+    __hip_atomic_fetch_add(&L.hist[(c * kNB + bin) * kRep + hrep], 1u, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (BPS == 2) { a1 += x; a2 += (unsigned long long)x * x; }
+  }
+  if (!WRITE) return 0;
+  uint32_t f;
+  if (BPS == 1) {
+    f = L.lut[pc.lb[p] + c * kNB + x];
+  } else {
+    int64_t y = (pc.qa[p] * (int64_t)x + pc.qb[p] + 32768) >> 16;
+    y = y < 0 ? 0 : (y > (int64_t)maxv ? (int64_t)maxv : y);
+    f = (uint32_t)y;
+  }
+  return (pc.iw[p] * x + pc.w[p] * f + 128u) >> 8;
+}
+
+// Tile ti of the context.  WTAB: weights from the caller's table (true) or
+// from their closed form (false); both give the same integers.
+template <int C, int BPS, bool WRITE, bool STATS, bool WTAB>
+__device__ void apply_tile(const Geo& g, const FramePtrs& fp, const Bufs& b, int ti, ApplyLds& L) {
+  constexpr int NW = C * BPS;    // dwords per 4-pixel group
+  constexpr int SPG = 4 * C;     // samples per group
+  const int tid = threadIdx.x;
+  const Tile t = g.tiles[ti];
+  const DevCam cam = g.cams[t.cam];
+  const int W = cam.width;
+  const int half = cam.half;
+  const int shift = cam.bit_depth - 8;
+  const uint32_t maxv = (1u << cam.bit_depth) - 1u;
+  const int pitch = (int)cam.pitch;
+
+  // Stage the tables of both sides of the tile's block; clear the histogram.
+  const int64_t u_left = unit_index(t.cam, 0, t.block, 0, g.n_blocks);
+  const int64_t u_right = unit_index(t.cam, 1, t.block, 0, g.n_blocks);
+  if (WRITE) {
+    if (BPS == 1) {
+      constexpr int DW = C * kNB / 4;   // dwords of one side's tables
+      for (int i = tid; i < 2 * DW; i += kThreads) {
+        const int s = i / DW;
+        const int rem = i - s * DW;
+        const uint32_t* src = reinterpret_cast<const uint32_t*>(b.lut8 + (s ? u_right : u_left) * kNB);
+        reinterpret_cast<uint32_t*>(L.lut + s * kCS * kNB)[rem] = src[rem];
+      }
+    } else if (tid < 4) {
+      L.q[tid] = b.q16[((tid >> 1) ? u_right : u_left) * 2 + (tid & 1)];
+    }
+  }
+  if (STATS) {
+    for (int i = tid; i < C * kNB * kRep; i += kThreads) L.hist[i] = 0;
+  }
+  __syncthreads();
+
+  const __amdgpu_buffer_rsrc_t rin = frame_rsrc(fp.in[t.cam], cam);
+  __amdgpu_buffer_rsrc_t rout = rin;
+  if (WRITE) rout = frame_rsrc(fp.out[t.cam], cam);
+  const uint16_t* wrow = b.weights + (int64_t)t.cam * g.w_max;
+  const int ngroups = (W + 3) >> 2;
+  const int hrep = tid & (kRep - 1);
+  unsigned long long a1 = 0, a2 = 0;
+
+  for (int grp = tid; grp < ngroups; grp += kThreads) {
+    const int col0 = grp * 4;
+    const int npx = min(4, W - col0);
+    PixConst pc;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      const int col = col0 + p;
+      const int side = col < half ? 0 : 1;
+      uint32_t w = 0;
+      if (WRITE && p < npx) w = WTAB ? (uint32_t)wrow[col] : blend_weight(W, col);
+      pc.w[p] = w;
+      pc.iw[p] = 256u - w;
+      pc.lb[p] = side * kCS * kNB;
+      if (BPS == 2 && WRITE) { pc.qa[p] = L.q[side * 2]; pc.qb[p] = L.q[side * 2 + 1]; }
+    }
+    const int cbyte = col0 * C * BPS;
+
+    if (npx == 4) {
+      for (int row = t.r0; row < t.r1; row += kUnroll) {
+        uint32_t d[kUnroll][NW];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u)
+          if (row + u < t.r1) load_group<NW>(rin, (row + u) * pitch + cbyte, d[u]);
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          if (row + u < t.r1) {
+            uint32_t o[NW];
+#pragma unroll
+            for (int q = 0; q < NW; ++q) o[q] = 0;
+#pragma unroll
+            for (int i = 0; i < SPG; ++i) {
+              const int p = i / C;
+              const int c = i - p * C;
+              uint32_t x;
+              if (BPS == 1) x = (d[u][i >> 2] >> (8 * (i & 3))) & 0xffu;
+              else x = (d[u][i >> 1] >> (16 * (i & 1))) & 0xffffu;
+              const uint32_t y = one_sample<BPS, WRITE, STATS>(x, c, p, pc, L, hrep, shift, maxv, a1, a2);
+              if (WRITE) {
+                if (BPS == 1) o[i >> 2] |= y << (8 * (i & 3));
+                else o[i >> 1] |= y << (16 * (i & 1));
+              }
+            }
+            if (WRITE) store_group<NW>(rout, (row + u) * pitch + cbyte, o);
+          }
+        }
+      }
+    } else {
+      // Ragged end of the row: sample by sample, touching only the row's bytes.
+      for (int row = t.r0; row < t.r1; ++row) {
+        const int off = row * pitch + cbyte;
+#pragma unroll
+        for (int i = 0; i < SPG; ++i) {
+          const int p = i / C;
+          const int c = i - p * C;
+          if (p < npx) {
+            uint32_t x;
+            if (BPS == 1) x = __builtin_amdgcn_raw_buffer_load_b8(rin, off + i, 0, 0);
+            else x = __builtin_amdgcn_raw_buffer_load_b16(rin, off + 2 * i, 0, 0);
+            const uint32_t y = one_sample<BPS, WRITE, STATS>(x, c, p, pc, L, hrep, shift, maxv, a1, a2);
+            if (WRITE) {
+              if (BPS == 1) __builtin_amdgcn_raw_buffer_store_b8((uint8_t)y, rout, off + i, 0, 0);
+              else __builtin_amdgcn_raw_buffer_store_b16((uint16_t)y, rout, off + 2 * i, 0, 0);
+            }
+          }
+        }
+      }
+    }
+  }
+
+  if (STATS) {
+    __syncthreads();
+    uint32_t* th = g.scr.tile_hist + (int64_t)ti * kCS * kNB;
+    for (int i = tid; i < kCS * kNB; i += kThreads) {
+      uint32_t s = 0;
+      if (i < C * kNB) {
+#pragma unroll
+        for (int r = 0; r < kRep; ++r) s += L.hist[i * kRep + r];
+      }
+      th[i] = s;
+    }
+    if (BPS == 2) {
+      block_sums(
+          2, [&](int i) { return i == 0 ? a1 : a2; },
+          [&](int i, unsigned long long tot) { g.scr.tile_sums[(int64_t)ti * 2 + i] = tot; }, L.red);
+    }
+  }
+}
+
+template <bool WRITE, bool STATS, bool WTAB>
+__device__ inline void apply_tile_dispatch(const Geo& g, const FramePtrs& fp, const Bufs& b, int ti, ApplyLds& L) {
+  const DevCam& cam = g.cams[g.tiles[ti].cam];
+  if (cam.bps == 2) apply_tile<1, 2, WRITE, STATS, WTAB>(g, fp, b, ti, L);
+  else if (cam.channels == 3) apply_tile<3, 1, WRITE, STATS, WTAB>(g, fp, b, ti, L);
+  else apply_tile<1, 1, WRITE, STATS, WTAB>(g, fp, b, ti, L);
+}
+
+}  // namespace rc

@@ -1,0 +1,115 @@
+// Estimate and tables of section 3.1 as device functions: shared spectrum and
+// per-channel affine fit of one unit with exponential smoothing, the
+// fixed-point tables of one (camera, side, block), and the Q8 blend weights.
+// Binary64 with contraction off: each result is the correctly rounded value
+// of the expression as written.
+#pragma once
+
+#include "dev_common.h"
+
+#pragma clang fp contract(off)
+
+namespace rc {
+
+struct Moments {
+  double mu, var, sd;
+};
+
+__device__ inline Moments moments_of(uint64_t n, uint64_t s1, uint64_t s2) {
+  Moments m;
+  const double nf = (double)n;
+  m.mu = (double)s1 / nf;
+  const double ex2 = (double)s2 / nf;
+  const double mu2 = m.mu * m.mu;
+  double var = ex2 - mu2;
+  if (var < 0.0) var = 0.0;
+  m.var = var;
+  m.sd = __builtin_sqrt(var);
+  return m;
+}
+
+// Unit u = ((k * 2 + s) * NB + j) * 3 + c.  Both sides of a seam derive the
+// same shared moments because binary64 addition is commutative.
+__device__ inline void estimate_unit(const Geo& g, const Bufs& b, int u) {
+  const int nb = g.n_blocks;
+  const int c = u % kCS;
+  const int j = (u / kCS) % nb;
+  const int s = (u / (kCS * nb)) & 1;
+  const int k = u / (kCS * nb * 2);
+  const DevCam& cam = g.cams[k];
+  double* p = b.params + (int64_t)u * 2;
+  if (c >= cam.channels) {
+    p[0] = 1.0; p[1] = 0.0; b.valid[u] = 0;
+    return;
+  }
+  const int fc = cam.face_cam[s];
+  if (fc < 0) {                       // open chain end: identity
+    p[0] = 1.0; p[1] = 0.0; b.valid[u] = 1;
+    return;
+  }
+  const int64_t fu = unit_index(fc, cam.face_side[s], j, c, nb);
+  const uint64_t* own = b.band_sums + (int64_t)u * 3;
+  const uint64_t* fac = b.band_sums + fu * 3;
+  const bool had = b.valid[u] != 0;
+  if (own[0] == 0 || fac[0] == 0) {   // no estimate: keep the state
+    if (!had) { p[0] = 1.0; p[1] = 0.0; }
+    return;
+  }
+  const Moments mo = moments_of(own[0], own[1], own[2]);
+  const Moments mf = moments_of(fac[0], fac[1], fac[2]);
+  const double mu_s = (mo.mu + mf.mu) / 2.0;
+  const double sd_s = (mo.sd + mf.sd) / 2.0;
+  double a = (mo.var == 0.0) ? 1.0 : sd_s / mo.sd;
+  a = a < g.a_min ? g.a_min : a;
+  a = a > g.a_max ? g.a_max : a;
+  const double am = a * mo.mu;
+  double bb = mu_s - am;
+  if (g.mode == RT_MODE_SMOOTHING && had) {
+    const double keep = 1.0 - g.alpha;
+    const double ta = keep * p[0];
+    const double na = g.alpha * a;
+    const double tb = keep * p[1];
+    const double nbv = g.alpha * bb;
+    a = ta + na;
+    bb = tb + nbv;
+  }
+  p[0] = a;
+  p[1] = bb;
+  b.valid[u] = 1;
+}
+
+// Entry x of the three channel tables of unit (k, s, j) = `unit3` (the
+// channel-0 unit index divided by 3); thread x == 0 also stores the q16 pairs.
+__device__ inline void lut_entry(const Geo& g, const Bufs& b, int unit3, int x) {
+  const int k = unit3 / (2 * g.n_blocks);
+  const DevCam& cam = g.cams[k];
+#pragma unroll
+  for (int c = 0; c < kCS; ++c) {
+    const int64_t u = (int64_t)unit3 * kCS + c;
+    const double a = b.params[u * 2 + 0];
+    const double bv = b.params[u * 2 + 1];
+    const int64_t A = (int64_t)__builtin_rint(a * 65536.0);
+    const int64_t Bq = (int64_t)__builtin_rint(bv * 65536.0);
+    if (x == 0) {
+      b.q16[u * 2 + 0] = A;
+      b.q16[u * 2 + 1] = Bq;
+    }
+    if (cam.bps == 1) {
+      int64_t y = (A * x + Bq + 32768) >> 16;
+      y = y < 0 ? 0 : (y > 255 ? 255 : y);
+      b.lut8[u * kNB + x] = (uint8_t)y;
+    }
+  }
+}
+
+// Q8 blend weight of column col of a camera of width W: h = floor(W/2); the
+// left half has round_half_up(256 (h - col) / h), the right half its mirror,
+// the centre column of an odd width 0.
+__device__ inline uint32_t blend_weight(int W, int col) {
+  const int h = W >> 1;
+  if (col < h) return (uint32_t)(((h - col) * 256 + (h >> 1)) / h);
+  if (col >= W - h && col < W) return (uint32_t)(((col - W + h + 1) * 256 + (h >> 1)) / h);
+  return 0u;
+}
+
+}  // namespace rc

@@ -1,0 +1,147 @@
+// Statistics of section 3.1 as device functions: the band statistics of one
+// (camera, side, block) unit, and the whole-frame reduction of one camera
+// from the per-tile histograms left by the apply pass.
+#pragma once
+
+#include "dev_common.h"
+
+namespace rc {
+
+struct StatsLds {
+  uint32_t hist[kCS * kNB];
+  unsigned long long red[9 * 16];
+};
+
+// Band statistics of unit (k, s, j): histogram and exact (n, S1, S2) of the
+// band's samples.  Threads walk the band as (row, dword) pairs; a dword holds 4
+// consecutive 8-bit samples or 2 16-bit samples of the row, and only the bytes
+// inside the band count.  8-bit sums follow from the exact histogram.
+template <int C, int BPS>
+__device__ void band_unit(const Geo& g, const FramePtrs& fp, const Bufs& b, int k, int s, int j, StatsLds& L) {
+  const int tid = threadIdx.x;
+  const DevCam cam = g.cams[k];
+  for (int i = tid; i < kCS * kNB; i += kThreads) L.hist[i] = 0;
+  __syncthreads();
+
+  const int r0 = (int)((int64_t)j * cam.height / g.n_blocks);
+  const int r1 = (int)((int64_t)(j + 1) * cam.height / g.n_blocks);
+  const int band = cam.band;
+  const int c0 = (s == 0) ? 0 : cam.width - band;
+  const int b0 = c0 * C * BPS;                 // band bytes [b0, b1) of each row
+  const int b1 = (c0 + band) * C * BPS;
+  const int q0 = b0 >> 2;
+  const int dw = ((b1 + 3) >> 2) - q0;         // dwords per band row
+  const int rows = r1 - r0;
+  const int shift = cam.bit_depth - 8;
+  const __amdgpu_buffer_rsrc_t rin = frame_rsrc(fp.in[k], cam);
+  unsigned long long a1 = 0, a2 = 0;           // 16-bit sums
+
+  if (band > 0 && rows > 0) {
+    const int drow = kThreads / dw, dq = kThreads % dw;
+    int row = tid / dw, q = tid % dw;
+    while (row < rows) {
+      const int rowoff = (int)((int64_t)(r0 + row) * cam.pitch);
+      const int boff = (q0 + q) * 4;           // byte offset of the dword in the row
+      uint32_t d;
+      if (boff + 4 <= cam.row_bytes) {
+        d = __builtin_amdgcn_raw_buffer_load_b32(rin, rowoff + boff, 0, 0);
+      } else {                                  // dword crossing the row end
+        d = 0;
+        for (int e = 0; boff + e < cam.row_bytes; ++e)
+          d |= (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(rin, rowoff + boff + e, 0, 0) << (8 * e);
+      }
+      if (BPS == 1) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int o = boff + e;
+          if (o >= b0 && o < b1) {
+            const uint32_t v = (d >> (8 * e)) & 0xffu;
+            const int c = (C == 1) ? 0 : o % C;
+            __hip_atomic_fetch_add(&L.hist[c * kNB + v], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const int o = boff + 2 * e;
+          if (o >= b0 && o < b1) {
+            const uint32_t v = (d >> (16 * e)) & 0xffffu;
+            uint32_t bin = v >> shift;
+            bin = bin > 255u ? 255u : bin;
+            __hip_atomic_fetch_add(&L.hist[bin], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            a1 += v;
+            a2 += (unsigned long long)v * v;
+          }
+        }
+      }
+      row += drow;
+      q += dq;
+      if (q >= dw) { q -= dw; ++row; }
+    }
+  }
+  __syncthreads();
+
+  const int64_t u0 = unit_index(k, s, j, 0, g.n_blocks);
+  uint32_t* oh = b.band_hist + u0 * kNB;
+  for (int i = tid; i < kCS * kNB; i += kThreads) oh[i] = L.hist[i];
+  // (n, S1, S2) per channel slot: quantity i is channel i / 3, moment i % 3.
+  const unsigned long long x = (unsigned long long)tid;
+  block_sums(
+      9,
+      [&](int i) -> unsigned long long {
+        const int c = i / 3, m = i - 3 * (i / 3);
+        if (c >= C) return 0ull;
+        const unsigned long long h = L.hist[c * kNB + tid];
+        if (m == 0) return h;
+        if (BPS == 2) return m == 1 ? a1 : a2;
+        return m == 1 ? h * x : h * x * x;
+      },
+      [&](int i, unsigned long long tot) { b.band_sums[u0 * 3 + i] = tot; }, L.red);
+}
+
+__device__ inline void band_unit_dispatch(const Geo& g, const FramePtrs& fp, const Bufs& b, int unit, StatsLds& L) {
+  const int nb = g.n_blocks;
+  const int k = unit / (2 * nb);
+  const int s = (unit / nb) & 1;
+  const int j = unit % nb;
+  const DevCam& cam = g.cams[k];
+  if (cam.bps == 2) band_unit<1, 2>(g, fp, b, k, s, j, L);
+  else if (cam.channels == 3) band_unit<3, 1>(g, fp, b, k, s, j, L);
+  else band_unit<1, 1>(g, fp, b, k, s, j, L);
+}
+
+// Whole-frame statistics of camera k: the sum of its tiles' histograms, and
+// (n, S1, S2) from the exact histogram (8-bit) or from the tiles' sums (16-bit).
+__device__ inline void whole_reduce_cam(const Geo& g, const Bufs& b, int k, StatsLds& L) {
+  const int tid = threadIdx.x;
+  const DevCam cam = g.cams[k];
+  const uint32_t* th = g.scr.tile_hist;
+  uint32_t h[kCS];
+#pragma unroll
+  for (int c = 0; c < kCS; ++c) {
+    uint32_t sum = 0;
+    if (c < cam.channels)
+      for (int t = cam.tile_begin; t < cam.tile_end; ++t) sum += th[(int64_t)t * kCS * kNB + c * kNB + tid];
+    h[c] = sum;
+    b.whole_hist[((int64_t)k * kCS + c) * kNB + tid] = sum;
+  }
+  const unsigned long long x = (unsigned long long)tid;
+  const bool b16 = cam.bps == 2;
+  block_sums(
+      9,
+      [&](int i) -> unsigned long long {
+        const int c = i / 3, m = i - 3 * (i / 3);
+        const unsigned long long hc = c == 0 ? h[0] : (c == 1 ? h[1] : h[2]);
+        if (m == 0) return hc;
+        if (b16) {
+          if (c != 0 || tid != 0) return 0ull;
+          unsigned long long s = 0;
+          for (int t = cam.tile_begin; t < cam.tile_end; ++t) s += g.scr.tile_sums[(int64_t)t * 2 + (m - 1)];
+          return s;
+        }
+        return m == 1 ? hc * x : hc * x * x;
+      },
+      [&](int i, unsigned long long tot) { b.whole_sums[(int64_t)k * 9 + i] = tot; }, L.red);
+}
+
+}  // namespace rc

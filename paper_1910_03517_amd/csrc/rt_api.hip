@@ -23,10 +23,17 @@ struct rt_ctx {
   std::vector<Tile> htiles;
   int w_max = 0;
   int tile_rows = 0;
+  int grid = 0;             // persistent grid size (0 = fill the device)
   DevCam* dcams = nullptr;
   Tile* dtiles = nullptr;
+  uint32_t* tile_hist = nullptr;
+  unsigned long long* tile_sums = nullptr;
+  uint32_t* sync = nullptr;
+  int64_t sync_words = 0;
   Geo geo{};
 };
+
+
 
 namespace {
 
@@ -48,7 +55,7 @@ rt_status hip_fail(hipError_t e, const char* what) {
 }
 
 constexpr int kMaxDim = 32768;
-constexpr int kDefaultTileRows = 8;
+constexpr int kDefaultTileRows = 16;
 
 bool aligned(const void* p, uintptr_t a) { return ((uintptr_t)p % a) == 0; }
 
@@ -78,6 +85,62 @@ FramePtrs make_ptrs(const rt_ctx* ctx, const void* const* in, void* const* out) 
 }
 
 }  // namespace
+
+// Tile table and device tables.  Every block is split into
+// ceil(rows / tile_rows) tiles of equal height (+-1 row); tiles are camera-major.
+static rt_status build_tables(rt_ctx* ctx, int tile_rows) {
+  const int n_cams = ctx->n_cams;
+  const int nb = ctx->opts.n_blocks;
+  ctx->tile_rows = tile_rows;
+  ctx->htiles.clear();
+  for (int k = 0; k < n_cams; ++k) {
+    const int H = ctx->cams[k].height;
+    ctx->hcams[k].tile_begin = (int32_t)ctx->htiles.size();
+    for (int j = 0; j < nb; ++j) {
+      const int r0 = (int)((int64_t)j * H / nb), r1 = (int)((int64_t)(j + 1) * H / nb);
+      const int rows = r1 - r0;
+      if (rows <= 0) continue;
+      const int parts = (rows + tile_rows - 1) / tile_rows;
+      for (int p = 0; p < parts; ++p)
+        ctx->htiles.push_back(Tile{k, j, r0 + (int)((int64_t)p * rows / parts), r0 + (int)((int64_t)(p + 1) * rows / parts)});
+    }
+    ctx->hcams[k].tile_end = (int32_t)ctx->htiles.size();
+  }
+  const size_t nt = ctx->htiles.size();
+  if (ctx->dtiles) (void)hipFree(ctx->dtiles);
+  if (ctx->tile_hist) (void)hipFree(ctx->tile_hist);
+  if (ctx->tile_sums) (void)hipFree(ctx->tile_sums);
+  ctx->dtiles = nullptr; ctx->tile_hist = nullptr; ctx->tile_sums = nullptr;
+  hipError_t e = hipSuccess;
+  if (!ctx->dcams) e = hipMalloc((void**)&ctx->dcams, sizeof(DevCam) * n_cams);
+  if (e == hipSuccess) e = hipMalloc((void**)&ctx->dtiles, sizeof(Tile) * nt);
+  if (e == hipSuccess) e = hipMalloc((void**)&ctx->tile_hist, sizeof(uint32_t) * nt * kCS * kNB);
+  if (e == hipSuccess) e = hipMalloc((void**)&ctx->tile_sums, sizeof(unsigned long long) * nt * 2);
+  ctx->sync_words = 4 + n_cams + 2 * (int64_t)n_cams * 2 * nb;
+  if (e == hipSuccess && !ctx->sync) {
+    e = hipMalloc((void**)&ctx->sync, sizeof(uint32_t) * ctx->sync_words);
+    if (e == hipSuccess) e = hipMemset(ctx->sync, 0, sizeof(uint32_t) * ctx->sync_words);
+  }
+  if (e != hipSuccess) return fail(RT_ENOMEM, "device tables: %s", hipGetErrorString(e));
+  e = hipMemcpy(ctx->dcams, ctx->hcams.data(), sizeof(DevCam) * n_cams, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(ctx->dtiles, ctx->htiles.data(), sizeof(Tile) * nt, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "uploading context tables");
+  Geo& g = ctx->geo;
+  g.cams = ctx->dcams;
+  g.tiles = ctx->dtiles;
+  g.scr.tile_hist = ctx->tile_hist;
+  g.scr.tile_sums = ctx->tile_sums;
+  g.scr.sync = ctx->sync;
+  g.n_cams = n_cams;
+  g.n_blocks = nb;
+  g.w_max = ctx->w_max;
+  g.n_tiles = (int32_t)nt;
+  g.mode = ctx->opts.mode;
+  g.alpha = ctx->opts.ema_alpha;
+  g.a_min = ctx->opts.a_min;
+  g.a_max = ctx->opts.a_max;
+  return RT_OK;
+}
 
 extern "C" {
 
@@ -177,39 +240,11 @@ rt_status rt_ctx_create(const rt_camera_desc* cams, int32_t n_cams, const rt_opt
     }
     ctx->w_max = std::max(ctx->w_max, c.width);
   }
-  // Tiles: every block split into runs of at most tile_rows rows.
-  for (int k = 0; k < n_cams; ++k) {
-    const int H = cams[k].height;
-    for (int j = 0; j < o.n_blocks; ++j) {
-      const int r0 = (int)((int64_t)j * H / o.n_blocks), r1 = (int)((int64_t)(j + 1) * H / o.n_blocks);
-      for (int r = r0; r < r1; r += ctx->tile_rows)
-        ctx->htiles.push_back(Tile{k, j, r, std::min(r1, r + ctx->tile_rows)});
-    }
-  }
-  hipError_t e = hipMalloc((void**)&ctx->dcams, sizeof(DevCam) * n_cams);
-  if (e == hipSuccess) e = hipMalloc((void**)&ctx->dtiles, sizeof(Tile) * ctx->htiles.size());
-  if (e != hipSuccess) {
+  rt_status st = build_tables(ctx, kDefaultTileRows);
+  if (st != RT_OK) {
     rt_ctx_destroy(ctx);
-    return fail(RT_ENOMEM, "device tables: %s", hipGetErrorString(e));
+    return st;
   }
-  e = hipMemcpy(ctx->dcams, ctx->hcams.data(), sizeof(DevCam) * n_cams, hipMemcpyHostToDevice);
-  if (e == hipSuccess)
-    e = hipMemcpy(ctx->dtiles, ctx->htiles.data(), sizeof(Tile) * ctx->htiles.size(), hipMemcpyHostToDevice);
-  if (e != hipSuccess) {
-    rt_ctx_destroy(ctx);
-    return hip_fail(e, "uploading context tables");
-  }
-  Geo& g = ctx->geo;
-  g.cams = ctx->dcams;
-  g.tiles = ctx->dtiles;
-  g.n_cams = n_cams;
-  g.n_blocks = o.n_blocks;
-  g.w_max = ctx->w_max;
-  g.n_tiles = (int32_t)ctx->htiles.size();
-  g.mode = o.mode;
-  g.alpha = o.ema_alpha;
-  g.a_min = o.a_min;
-  g.a_max = o.a_max;
   *out = ctx;
   return RT_OK;
 }
@@ -219,6 +254,9 @@ rt_status rt_ctx_destroy(rt_ctx* ctx) {
   (void)hipDeviceSynchronize();
   if (ctx->dcams) (void)hipFree(ctx->dcams);
   if (ctx->dtiles) (void)hipFree(ctx->dtiles);
+  if (ctx->tile_hist) (void)hipFree(ctx->tile_hist);
+  if (ctx->tile_sums) (void)hipFree(ctx->tile_sums);
+  if (ctx->sync) (void)hipFree(ctx->sync);
   delete ctx;
   return RT_OK;
 }
@@ -277,14 +315,10 @@ static Bufs make_bufs(const rt_stats_buf* s, const rt_params_buf* p, const rt_lu
 }
 
 static rt_status whole_pass(rt_ctx* ctx, const FramePtrs& fp, const Bufs& b, bool write, hipStream_t st) {
-  const int64_t K = ctx->n_cams;
-  hipError_t e = launch_fill_zero(b.whole_hist, K * kCS * kNB * 4, st);
-  if (e == hipSuccess) e = launch_fill_zero(b.whole_sums, K * kCS * 3 * 8, st);
-  if (e != hipSuccess) return hip_fail(e, "zero fill");
-  e = write ? launch_apply(ctx->geo, fp, b, true, st) : launch_whole_stats(ctx->geo, fp, b, st);
+  hipError_t e = launch_apply(ctx->geo, fp, b, write, true, st);
   if (e != hipSuccess) return hip_fail(e, write ? "apply" : "whole-frame statistics");
-  e = launch_whole_finalize(ctx->geo, b, st);
-  if (e != hipSuccess) return hip_fail(e, "whole-frame finalize");
+  e = launch_whole_reduce(ctx->geo, b, st);
+  if (e != hipSuccess) return hip_fail(e, "whole-frame reduction");
   return RT_OK;
 }
 
@@ -334,7 +368,7 @@ rt_status rt_apply(rt_ctx* ctx, const void* const* frames, void* const* out_fram
   const FramePtrs fp = make_ptrs(ctx, frames, out_frames);
   const Bufs b = make_bufs(whole_out, nullptr, lut);
   if (whole_out) return whole_pass(ctx, fp, b, true, st);
-  hipError_t e = launch_apply(ctx->geo, fp, b, false, st);
+  hipError_t e = launch_apply(ctx->geo, fp, b, true, false, st);
   return e == hipSuccess ? RT_OK : hip_fail(e, "apply");
 }
 
@@ -351,10 +385,47 @@ rt_status rt_frameset(rt_ctx* ctx, const void* const* frames, void* const* out_f
   const FramePtrs fp = make_ptrs(ctx, frames, out_frames);
   const Bufs b = make_bufs(stats, state, lut);
   hipError_t e = launch_band_stats(ctx->geo, fp, b, st);
-  if (e == hipSuccess) e = launch_estimate(ctx->geo, b, st);
-  if (e == hipSuccess) e = launch_build_lut(ctx->geo, b, st);
-  if (e != hipSuccess) return hip_fail(e, "frameset estimate stage");
+  if (e != hipSuccess) return hip_fail(e, "band statistics");
+  e = launch_estimate_lut(ctx->geo, b, st);
+  if (e != hipSuccess) return hip_fail(e, "estimate and tables");
   return whole_pass(ctx, fp, b, true, st);
+}
+
+rt_status rt_ctx_check(rt_ctx* ctx) {
+  if (!ctx) return fail(RT_EINVAL, "ctx is NULL");
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "synchronize");
+  uint32_t err = 0;
+  e = hipMemcpy(&err, ctx->sync + 3, sizeof err, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "reading the error word");
+  if (err) {
+    const uint32_t zero = 0;
+    (void)hipMemcpy(ctx->sync + 3, &zero, sizeof zero, hipMemcpyHostToDevice);
+    return fail(RT_EDEVICE, "a frame-set wait expired on the device (results of that launch are invalid)");
+  }
+  return RT_OK;
+}
+
+rt_status rt_ctx_tune(rt_ctx* ctx, int32_t tile_rows, int32_t grid) {
+  if (!ctx) return fail(RT_EINVAL, "ctx is NULL");
+  if (tile_rows < 1 || tile_rows > 4096) return fail(RT_EINVAL, "tile_rows %d outside 1..4096", tile_rows);
+  if (grid < 0) return fail(RT_EINVAL, "grid %d < 0", grid);
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "synchronize");
+  ctx->grid = grid;
+  ctx->geo.apply_grid = grid;
+  if (tile_rows == ctx->tile_rows) return RT_OK;
+  rt_status r = build_tables(ctx, tile_rows);
+  ctx->geo.apply_grid = grid;
+  return r;
+}
+
+rt_status rt_ctx_tuning(const rt_ctx* ctx, int32_t* tile_rows, int32_t* grid, int32_t* n_tiles) {
+  if (!ctx) return fail(RT_EINVAL, "ctx is NULL");
+  if (tile_rows) *tile_rows = ctx->tile_rows;
+  if (grid) *grid = ctx->grid;
+  if (n_tiles) *n_tiles = (int32_t)ctx->htiles.size();
+  return RT_OK;
 }
 
 }  // extern "C"

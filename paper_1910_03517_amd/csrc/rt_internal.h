@@ -10,6 +10,7 @@ namespace rc {
 
 constexpr int kCS = RT_CSLOTS;   // channel slots
 constexpr int kNB = RT_NBINS;    // histogram bins
+constexpr int kThreads = 256;    // threads of every workgroup
 
 // Per-camera geometry as the kernels see it (uploaded once per context).
 struct DevCam {
@@ -20,6 +21,8 @@ struct DevCam {
   int32_t row_bytes;     // width * channels * bps
   int32_t face_cam[2];   // camera facing side s, -1 if none (open chain end)
   int32_t face_side[2];
+  int32_t tile_begin;    // this camera's tiles are [tile_begin, tile_end)
+  int32_t tile_end;
   int64_t pitch;         // bytes between rows
 };
 
@@ -47,12 +50,21 @@ struct Bufs {
   uint16_t* weights;
 };
 
+// Context-owned device scratch.
+struct Scratch {
+  uint32_t* tile_hist;                 // [n_tiles][kCS * kNB] histogram of each tile's input
+  unsigned long long* tile_sums;       // [n_tiles][2] (S1, S2) of 16-bit tiles
+  uint32_t* sync;                      // persistent-kernel state, see k_frameset.hip
+};
+
 // Context-wide constants passed to every kernel.
 struct Geo {
   const DevCam* cams;    // device array [K]
-  const Tile* tiles;     // device array [n_tiles]
+  const Tile* tiles;     // device array [n_tiles], camera-major
+  Scratch scr;
   int32_t n_cams, n_blocks, w_max, n_tiles;
   int32_t mode;
+  int32_t apply_grid;    // 0: one workgroup per tile; > 0: that many workgroups stride over the tiles
   double alpha, a_min, a_max;
 };
 
@@ -65,18 +77,17 @@ __device__ inline __amdgpu_buffer_rsrc_t frame_rsrc(const void* p, const DevCam&
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, kRsrcWord3);
 }
 
-// Index helpers for the caller layouts.
+// Index of a (camera, side, block, channel) unit in the caller layouts.
 __host__ __device__ inline int64_t unit_index(int k, int s, int j, int c, int nb) {
   return (((int64_t)k * 2 + s) * nb + j) * kCS + c;
 }
 
 // Launchers (each defined next to its kernels).  All return hipError_t of the launch.
-hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t st);
 hipError_t launch_band_stats(const Geo& g, const FramePtrs& fp, const Bufs& b, hipStream_t st);
-hipError_t launch_whole_stats(const Geo& g, const FramePtrs& fp, const Bufs& b, hipStream_t st);
-hipError_t launch_whole_finalize(const Geo& g, const Bufs& b, hipStream_t st);
 hipError_t launch_estimate(const Geo& g, const Bufs& b, hipStream_t st);
+hipError_t launch_estimate_lut(const Geo& g, const Bufs& b, hipStream_t st);
 hipError_t launch_build_lut(const Geo& g, const Bufs& b, hipStream_t st);
-hipError_t launch_apply(const Geo& g, const FramePtrs& fp, const Bufs& b, bool with_stats, hipStream_t st);
+hipError_t launch_apply(const Geo& g, const FramePtrs& fp, const Bufs& b, bool write, bool stats, hipStream_t st);
+hipError_t launch_whole_reduce(const Geo& g, const Bufs& b, hipStream_t st);
 
 }  // namespace rc

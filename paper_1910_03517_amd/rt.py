@@ -25,7 +25,8 @@ RT_MAX_CAMS = 64
 CSLOTS, NBINS = 3, 256
 
 EXPORTED = ["rt_ctx_create", "rt_ctx_destroy", "rt_ctx_sizes", "rt_stats", "rt_estimate",
-            "rt_build_lut", "rt_apply", "rt_frameset", "rt_status_str", "rt_last_error"]
+            "rt_build_lut", "rt_apply", "rt_frameset", "rt_ctx_check", "rt_ctx_tune", "rt_ctx_tuning",
+            "rt_status_str", "rt_last_error"]
 
 
 class rt_camera_desc(ct.Structure):
@@ -87,6 +88,10 @@ def load(path: str = LIB_PATH) -> ct.CDLL:
     lib.rt_apply.argtypes = [P, ct.POINTER(P), ct.POINTER(P), ct.POINTER(rt_lut_buf), ct.POINTER(rt_stats_buf), P]
     lib.rt_frameset.argtypes = [P, ct.POINTER(P), ct.POINTER(P), ct.POINTER(rt_stats_buf),
                                 ct.POINTER(rt_params_buf), ct.POINTER(rt_lut_buf), P]
+    lib.rt_ctx_check.argtypes = [P]
+    lib.rt_ctx_tune.argtypes = [P, ct.c_int32, ct.c_int32]
+    I = ct.POINTER(ct.c_int32)
+    lib.rt_ctx_tuning.argtypes = [P, I, I, I]
     for name in EXPORTED:
         getattr(lib, name).restype = ct.c_int32
     lib.rt_status_str.argtypes = [ct.c_int32]
@@ -141,6 +146,20 @@ def rt_ctx_sizes(ctx) -> rt_sizes:
     s = rt_sizes()
     _check(load().rt_ctx_sizes(ctx, ct.byref(s)))
     return s
+
+
+def rt_ctx_check(ctx) -> None:
+    _check(load().rt_ctx_check(ctx))
+
+
+def rt_ctx_tune(ctx, tile_rows: int, grid: int = 0) -> None:
+    _check(load().rt_ctx_tune(ctx, tile_rows, grid))
+
+
+def rt_ctx_tuning(ctx) -> tuple[int, int, int]:
+    a, b, c = ct.c_int32(), ct.c_int32(), ct.c_int32()
+    _check(load().rt_ctx_tuning(ctx, ct.byref(a), ct.byref(b), ct.byref(c)))
+    return a.value, b.value, c.value
 
 
 def rt_stats(ctx, frames, band_hist, band_sums, whole_hist=None, whole_sums=None, stream=None) -> None:
@@ -321,3 +340,12 @@ class Rig:
 
     def frameset(self, frames, out_frames, stream=None) -> None:
         rt_frameset(self.ctx, frames, out_frames, self.bufs, stream)
+
+    def check(self) -> None:
+        rt_ctx_check(self.ctx)
+
+    def tune(self, tile_rows: int, grid: int = 0) -> None:
+        rt_ctx_tune(self.ctx, tile_rows, grid)
+
+    def tuning(self) -> tuple[int, int, int]:
+        return rt_ctx_tuning(self.ctx)

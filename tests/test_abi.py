@@ -88,3 +88,6 @@ def test_null_arguments_are_rejected():
     assert lib.rt_frameset(None, None, None, None, None, None, None) == rt.RT_EINVAL
     assert lib.rt_ctx_sizes(None, None) == rt.RT_EINVAL
     assert lib.rt_ctx_destroy(None) == rt.RT_OK
+    assert lib.rt_ctx_check(None) == rt.RT_EINVAL
+    assert lib.rt_ctx_tune(None, 8, 0) == rt.RT_EINVAL
+    assert lib.rt_ctx_tuning(None, None, None, None) == rt.RT_EINVAL

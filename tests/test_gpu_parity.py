@@ -169,3 +169,36 @@ def test_determinism_repeated_runs():
         else:
             assert cur == first, f"run {i} differs"
     rig.close()
+
+
+@pytest.mark.parametrize("tile_rows,grid", [(1, 0), (3, 1), (16, 7), (64, 0), (4096, 2)])
+def test_frameset_tuning_knobs_do_not_change_results(tile_rows, grid):
+    """Tile height and apply grid (down to one workgroup striding over every
+    tile) are performance knobs only."""
+    say(f"case: knobs tile_rows={tile_rows} grid={grid}")
+    rng = np.random.default_rng(tile_rows * 31 + grid)
+    spec = ([synth.CamSpec(300, 77, 3, 8, 0, p) for p in range(3)]
+            + [synth.CamSpec(96, 40, 1, 12, 1, p) for p in range(2)])
+    frames = [synth.tiny_frame(c.height, c.width, c.channels, c.bit_depth, rng) for c in spec]
+    cams = rt_cams(spec)
+    opts = rt.Options(n_blocks=5, band_width=9, smoothing=True)
+    rig = rt.Rig(cams, opts)
+    rig.tune(tile_rows, grid)
+    dev = rig.upload(frames)
+    out = rig.alloc_frames()
+    prev_p = prev_v = None
+    for t in range(2):
+        rig.frameset(dev, out)
+        rig.check()
+        g = rig.bufs.host()
+        g["out"] = rig.download(out)
+        res = compare_step(oracle_cams(cams), oracle_opts(opts), frames, g, prev_p, prev_v)
+        prev_p, prev_v = res["ref"]["params"], res["ref"]["valid"]
+    rig.close()
+
+
+@pytest.mark.skip(reason="the single-launch persistent frame-set kernel (in-kernel dependency waits) did not "
+                         "complete on its first two device runs; it is switched off (not built) until its cause "
+                         "is shown, and rt_frameset uses the four-kernel sequence")
+def test_persistent_single_launch_frameset():
+    frameset_sequence(synth.rig14_1080p(), rt.Options(), 1)
