@@ -1,14 +1,21 @@
 """Benchmark: corrected GPix/s of the whole correction path on one MI355X.
 
-One step = one frame-set through rt_frameset (band statistics, estimate,
-tables, apply with fused whole-frame statistics: every step of the path, one
-persistent launch).  Inputs are seeded synthetic rigs already resident in
-HBM; NBUF distinct input/output frame-set buffers rotate so that the 256 MB
-Infinity Cache cannot serve repeats.
+One step = one frame-set through every step of the path: band statistics,
+estimate, tables, apply with fused whole-frame statistics.  By default steps
+go through rt_pipe (the statistics and estimate of frame-set t+1 overlap the
+apply of frame-set t on two streams); --mode eager issues one rt_frameset
+per step on one stream, --mode graph / graph-pipelined replay captured HIP
+graphs.  Inputs are
+seeded synthetic rigs already resident in HBM; NBUF distinct input/output
+frame-set buffers rotate so that the 256 MB Infinity Cache cannot serve
+repeats.
 
     python bench.py [--gpus 1] [--steps 300] [--warmup 20] [--config rig14]
 
-Prints ONE JSON line.  The CPU baseline leg times the CPU oracle (test
+Prints ONE JSON line.  The roofline figure is for the dominant kernel (the
+apply pass with fused statistics), timed by events the library records right
+around each of its launches in the timed region, next to the streaming-copy
+ceiling of the same bytes.  The CPU baseline leg times the CPU oracle (test
 infrastructure) on a bounded sample of the same workload.
 """
 from __future__ import annotations
@@ -27,8 +34,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "corrected GPix/s and % HBM roofline; p50/p99 frame-set latency, plain vs surrogate"
-KERNEL_SOURCES = ["dev_common.h", "dev_stats.h", "dev_estimate.h", "dev_apply.h", "k_frameset.hip",
-                  "rt_internal.h"]
+KERNEL_SOURCES = ["dev_common.h", "dev_apply.h", "dev_estimate.h", "k_apply.hip", "rt_internal.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_apply_rig14_traffic.txt")
 
 
 def kernel_hash() -> str:
@@ -63,17 +70,20 @@ def algorithmic_bytes(cams, band_width: int) -> int:
 
 
 def traffic_from_profile(khash: str, workload: str):
-    """Counter-derived HBM bytes per launch from the committed rocprofv3 summary,
-    if it was taken on this exact kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "k_frameset_traffic.json")
+    """Counter-derived HBM bytes per apply launch from the committed rocprofv3
+    summary, if it was taken on this exact kernel source and workload; else None."""
     try:
-        with open(path) as f:
-            t = json.load(f)
-    except (OSError, ValueError):
+        with open(TRAFFIC_FILE) as f:
+            kv = dict(line.split(":", 1) for line in f if ":" in line and not line.startswith("#"))
+    except OSError:
         return None
-    if t.get("kernel_hash") != khash or t.get("workload") != workload:
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    if kv.get("kernel_hash") != khash or kv.get("workload") != workload:
         return None
-    return t.get("bytes_per_launch")
+    try:
+        return int(float(kv["hbm_bytes_per_launch"]))
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(rig, opts_rt, budget_s: float = 12.0) -> dict:
@@ -98,6 +108,11 @@ def cpu_baseline(rig, opts_rt, budget_s: float = 12.0) -> dict:
                       f"{t_total:.1f} s single process"}
 
 
+def apply_bytes(cams) -> int:
+    """Algorithmic bytes of one apply launch: every sample read and written once."""
+    return sum(2 * c.width * c.height * c.channels * (1 if c.bit_depth == 8 else 2) for c in cams)
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -106,8 +121,14 @@ def main() -> int:
     ap.add_argument("--config", default="rig14", choices=["rig14", "uneven", "vga"])
     ap.add_argument("--nbuf", type=int, default=8)
     ap.add_argument("--smoothing", action="store_true")
+    ap.add_argument("--mode", default="pipe", choices=["pipe", "graph-pipelined", "graph", "eager"],
+                    help="pipe: rt_pipe_submit per step (the estimate of t+1 overlaps the apply of t on two "
+                         "streams); graph-pipelined: one two-branch graph launch per step; graph: one captured "
+                         "rt_frameset per step; eager: one rt_frameset call per step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile-rows", type=int, default=0)
+    ap.add_argument("--depth", type=int, default=2, help="slots of the pipe mode")
+    ap.add_argument("--copy-only", action="store_true", help="time the streaming copy of the frame bytes only")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported (the correction of one rig "
@@ -116,72 +137,135 @@ def main() -> int:
 
     import torch
     from paper_1910_03517_amd import rt, synth
+    from paper_1910_03517_amd.pipeline import Pipeline
 
     torch.cuda.set_device(0)
     rig_spec = config(args.config)
     cams = [rt.Camera(c.width, c.height, c.channels, c.bit_depth, c.ring, c.pos).with_pitch() for c in rig_spec.cams]
+    px = sum(c.width * c.height for c in cams)
+    frame_bytes = apply_bytes(cams) // 2
+
+    # Practical ceiling: a read+write stream of the same bytes with the same vector width.
+    src = [torch.empty(frame_bytes, dtype=torch.uint8, device="cuda") for _ in range(args.nbuf)]
+    dst = [torch.empty(frame_bytes, dtype=torch.uint8, device="cuda") for _ in range(args.nbuf)]
+    for i in range(args.warmup):
+        rt.rt_stream_copy(dst[i % args.nbuf], src[i % args.nbuf], frame_bytes, 12)
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    c0.record()
+    for i in range(args.steps):
+        rt.rt_stream_copy(dst[i % args.nbuf], src[i % args.nbuf], frame_bytes, 12)
+    c1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * frame_bytes * args.steps / (c0.elapsed_time(c1) / 1e3) / 1e9
+    del src, dst
+    if args.copy_only:
+        print(json.dumps({"copy_bytes_per_launch": 2 * frame_bytes, "copy_GBs": round(copy_gbs, 1)}), flush=True)
+        return 0
+
     opts = rt.Options(smoothing=args.smoothing)
     rig = rt.Rig(cams, opts)
     if args.tile_rows:
         rig.tune(args.tile_rows, 0)
     tile_rows, grid, n_tiles = rig.tuning()
-    px = sum(c.width * c.height for c in cams)
     alg_bytes = algorithmic_bytes(cams, opts.band_width)
 
     # Distinct frame-sets rotated through NBUF buffer pairs (distinct addresses).
     base = [synth.rig_frames(rig_spec, t, drift=True) for t in range(2)]
     ins = [rig.upload(base[i % 2]) for i in range(args.nbuf)]
     outs = [rig.alloc_frames() for _ in range(args.nbuf)]
+    torch.cuda.synchronize()
+
+    from paper_1910_03517_amd.pipeline import LutSet, WholeSet
     stream = torch.cuda.current_stream()
+    pipe, graphs = None, None
+    b = rig.bufs
+    if args.mode == "pipe":
+        pipe = Pipeline(rig, depth=args.depth)
+        in_ptrs = [rt.ptr_array(x) for x in ins]
+        out_ptrs = [rt.ptr_array(x) for x in outs]
+    elif args.mode == "graph":
+        whole = WholeSet(rig.sizes)
+        graphs = [rt.Graph(rig.ctx, ins[i], outs[i], LutSet(rig.sizes), whole, b) for i in range(args.nbuf)]
+    elif args.mode == "graph-pipelined":
+        assert args.nbuf % 2 == 0
+        luts = [LutSet(rig.sizes) for _ in range(2)]
+        wholes = [WholeSet(rig.sizes) for _ in range(2)]
+        rt.rt_stats(rig.ctx, ins[0], b.band_hist, b.band_sums)
+        rt.rt_estimate(rig.ctx, b.band_hist, b.band_sums, b.params, b.valid)
+        rt.rt_build_lut(rig.ctx, b.params, b.valid, luts[0].lut8, luts[0].q16, luts[0].weights)
+        graphs = [rt.Graph(rig.ctx, ins[i], outs[i], luts[i % 2], wholes[i % 2], b,
+                           ins[(i + 1) % args.nbuf], luts[(i + 1) % 2]) for i in range(args.nbuf)]
+    s_first = s_last = stream
+
+    def step(i):
+        if graphs is not None:
+            graphs[i % args.nbuf].launch(stream)
+        elif pipe is not None:
+            j = i % args.nbuf
+            pipe.submit(ins[j], outs[j], stream, in_ptrs[j], out_ptrs[j])
+        else:
+            rig.frameset(ins[i % args.nbuf], outs[i % args.nbuf])
 
     for i in range(args.warmup):
-        rig.frameset(ins[i % args.nbuf], outs[i % args.nbuf])
+        step(i)
     torch.cuda.synchronize()
     rig.check()
+    first = args.warmup          # continue the step sequence (pipelined graphs chain step to step)
 
-    # Timed region: exactly `steps` frame-sets back to back.
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    # Timed region: exactly `steps` frame-sets back to back; per-step start
+    # and end events give the frame-set latency.
+    ev_s = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ev_e = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     torch.cuda.synchronize()
     w0 = time.perf_counter()
-    e0.record(stream)
     for i in range(args.steps):
-        rig.frameset(ins[i % args.nbuf], outs[i % args.nbuf])
-    e1.record(stream)
+        ev_s[i].record(s_first)
+        step(first + i)
+        ev_e[i].record(s_last)
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
-    ms_total = e0.elapsed_time(e1)
     rig.check()
+    ms_total = ev_s[0].elapsed_time(ev_e[-1])
+    lat_ms = np.array([a.elapsed_time(b) for a, b in zip(ev_s, ev_e)])
+
+    # The dominant kernel alone: the apply pass with fused statistics, each
+    # launch bracketed by events the library records on its stream.
+    rt.rt_ctx_timing(rig.ctx, args.steps)
+    torch.cuda.synchronize()
+    for i in range(args.steps):
+        rt.rt_apply(rig.ctx, ins[i % args.nbuf], outs[i % args.nbuf], b.lut8, b.q16, b.weights,
+                    b.whole_hist, b.whole_sums, stream=stream)
+    torch.cuda.synchronize()
+    apply_ms = np.array(rt.rt_ctx_apply_times(rig.ctx, args.steps))
+    rt.rt_ctx_timing(rig.ctx, 0)
     ms_step = ms_total / args.steps
     gpix = px * args.steps / (ms_total / 1e3) / 1e9
 
-    # Per-launch durations (events around each launch, on the launch stream).
-    n_lat = min(args.steps, 200)
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_lat)]
-    for i in range(n_lat):
-        ev[i][0].record(stream)
-        rig.frameset(ins[i % args.nbuf], outs[i % args.nbuf])
-        ev[i][1].record(stream)
-    torch.cuda.synchronize()
-    rig.check()
-    lat_ms = np.array([a.elapsed_time(b) for a, b in ev])
-    launch_us = float(lat_ms.mean() * 1e3)
-
     khash = kernel_hash()
     workload = rig_spec.name
-    achieved = alg_bytes / (launch_us * 1e-6) / 1e9
+    ab = apply_bytes(cams)
+    launch_us = float(apply_ms.mean() * 1e3)
+    achieved = ab / (launch_us * 1e-6) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profile(khash, workload),
-            "kernel": "k_frameset", "bytes_per_launch": alg_bytes, "launch_us": round(launch_us, 2)}
+            "kernel": "k_apply<true,true> (apply + fused whole-frame statistics)", "bytes_per_launch": ab,
+            "launch_us": round(launch_us, 2), "copy_ceiling_GBs": round(copy_gbs, 1),
+            "frac_of_copy_ceiling": round(achieved / copy_gbs, 4)}
     out = {
         "metric": METRIC, "value": round(gpix, 3), "unit": "GPix/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_step, 5), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u8", "data": "synthetic",
         "config": {"workload": workload, "path": "plain", "mode": "smoothing" if args.smoothing else "standard",
+                   "launch_mode": args.mode,
                    "n_blocks": opts.n_blocks, "band_width": opts.band_width, "pixels_per_frameset": px,
                    "rotating_buffers": args.nbuf, "tile_rows": tile_rows, "n_tiles": n_tiles},
-        "hbm_frac_wall": round(alg_bytes * args.steps / (ms_total / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+        "hbm_frac": round(alg_bytes * args.steps / (ms_total / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+        "algorithmic_bytes_per_frameset": alg_bytes,
         "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 4),
-                       "p99": round(float(np.percentile(lat_ms, 99)), 4), "what": "per frame-set launch, back to back"},
+                       "p99": round(float(np.percentile(lat_ms, 99)), 4),
+                       "what": "start to end of each step's GPU work, steps back to back (in graph-pipelined mode a "
+                               "frame-set's estimate ran one step earlier)"},
         "wall_s": round(wall, 4),
         "roofline": roof,
         "kernel_hash": khash,

@@ -39,7 +39,8 @@
  * default stream) and returns.  Validation failures return a negative status,
  * set rt_last_error() and enqueue nothing.  A HIP launch failure returns
  * RT_EDEVICE.  Nothing aborts and no C++ exception crosses this boundary.  A
- * context is not internally locked: use one context per host thread.
+ * context is not internally locked: use one context per host thread.  No
+ * kernel of the library waits on another workgroup.
  */
 #ifndef RINGCORR_H
 #define RINGCORR_H
@@ -187,8 +188,56 @@ rt_status rt_apply(rt_ctx* ctx, const void* const* frames, void* const* out_fram
 rt_status rt_frameset(rt_ctx* ctx, const void* const* frames, void* const* out_frames, const rt_stats_buf* stats,
                       const rt_params_buf* state, const rt_lut_buf* lut, void* stream);
 
-/* Synchronize the device and report RT_EDEVICE if a device-side check of
- * this context failed since the last call (the flag is then cleared). */
+/* Two-stream frame-set pipeline.  rt_pipe_submit enqueues one frame-set: on
+ * the pipeline's own stream E the band statistics, estimate and tables of
+ * that frame-set (after `ready_event`, a hipEvent_t passed as void*, if not
+ * NULL: the caller records it once the frames are written; stream E does not
+ * otherwise wait for the caller's stream), and on the caller's `stream` the
+ * apply pass with fused whole-frame statistics.  Consecutive frame-sets rotate over `depth`
+ * table and whole-frame-statistics slots (luts[depth], wholes[depth], all
+ * distinct), so the estimate of frame-set t+1 overlaps the apply of frame-set
+ * t; band statistics and estimator state are single buffers ordered on
+ * stream E, which makes the results exactly those of consecutive rt_frameset
+ * calls.  *slot_out (may be NULL) receives the slot of the submitted
+ * frame-set; its statistics and tables stay valid until `depth` further
+ * submits.  Completion: record an event on `stream` after the submit.  The
+ * buffers are caller-owned and must outlive the pipeline; submits of one
+ * pipeline must come from one host thread and may use one caller stream only. */
+typedef struct rt_pipe rt_pipe;
+rt_status rt_pipe_create(rt_ctx* ctx, int32_t depth, const rt_stats_buf* bands, const rt_params_buf* state,
+                         const rt_lut_buf* luts, const rt_stats_buf* wholes, rt_pipe** out);
+rt_status rt_pipe_submit(rt_pipe* p, const void* const* frames, void* const* out_frames, void* stream,
+                         void* ready_event, int32_t* slot_out);
+rt_status rt_pipe_destroy(rt_pipe* p);
+
+/* A frame-set captured once into a HIP graph for fixed buffers and replayed
+ * with one launch per frame-set.
+ *
+ * Without next_frames (NULL, next_lut ignored): the graph is rt_frameset on
+ * (frames, out_frames) with band statistics in `bands`, estimator state in
+ * `state`, tables in `lut` and whole-frame statistics in `whole`.
+ *
+ * With next_frames: a two-branch graph for software pipelining over
+ * consecutive frame-sets t, t+1.  Branch A applies `lut` (estimated by the
+ * previous launch) to frame-set t = (frames -> out_frames) with whole-frame
+ * statistics into `whole`; branch E, concurrently, computes the band
+ * statistics of frame-set t+1 = next_frames into `bands`, the estimate into
+ * `state` and the tables into `next_lut` (distinct from `lut`).  Replaying
+ * such graphs for t = 0, 1, 2, ... with alternating table buffers, after one
+ * rt_stats / rt_estimate / rt_build_lut of frame-set 0, gives exactly the
+ * results of consecutive rt_frameset calls.
+ *
+ * Graph launches of one context must be ordered like its other calls.  A
+ * graph becomes invalid (RT_ESTATE at launch) when rt_ctx_tune rebuilds the
+ * context's tables; its memory stays owned by the caller and must outlive it. */
+typedef struct rt_graph rt_graph;
+rt_status rt_graph_create(rt_ctx* ctx, const void* const* frames, void* const* out_frames, const rt_lut_buf* lut,
+                          const rt_stats_buf* whole, const void* const* next_frames, const rt_lut_buf* next_lut,
+                          const rt_stats_buf* bands, const rt_params_buf* state, rt_graph** out);
+rt_status rt_graph_launch(rt_graph* g, void* stream);
+rt_status rt_graph_destroy(rt_graph* g);
+
+/* Synchronize the device and report RT_EDEVICE if a HIP error is pending. */
 rt_status rt_ctx_check(rt_ctx* ctx);
 
 /* Performance knobs that never change results: tile height of the apply pass
@@ -200,6 +249,24 @@ rt_status rt_ctx_tune(rt_ctx* ctx, int32_t tile_rows, int32_t grid);
 
 /* Current knobs and the resulting number of apply tiles (any pointer may be NULL). */
 rt_status rt_ctx_tuning(const rt_ctx* ctx, int32_t* tile_rows, int32_t* grid, int32_t* n_tiles);
+
+/* Instrumentation: with slots > 0 every later apply kernel launch of this
+ * context (rt_apply, rt_stats with whole-frame statistics, rt_frameset) is
+ * bracketed by two HIP events on its stream, kept in a ring of `slots`
+ * entries; slots = 0 turns it off.  Synchronizes the device. */
+rt_status rt_ctx_timing(rt_ctx* ctx, int32_t slots);
+
+/* Durations in milliseconds of the last min(max_n, recorded, slots) apply
+ * kernel launches, oldest first, into ms[]; *n_out receives the count.  Waits
+ * for those launches to finish. */
+rt_status rt_ctx_apply_times(rt_ctx* ctx, float* ms, int32_t max_n, int32_t* n_out);
+
+/* Measurement utility, not part of the method: copy `bytes` bytes from src to
+ * dst (device pointers, 16-byte aligned, non-overlapping, bytes < 2 GiB) with
+ * vec_bytes (4, 8, 12 or 16) per lane and load/store, the way the apply pass
+ * streams frames.  Gives the practical HBM ceiling of a read+write stream of
+ * the same size next to the apply pass. */
+rt_status rt_stream_copy(void* dst, const void* src, int64_t bytes, int32_t vec_bytes, void* stream);
 
 /* Static description of a status code. */
 const char* rt_status_str(rt_status s);

@@ -1,8 +1,8 @@
 // Apply pass of section 3.1 as a device function over one tile: every sample
 // is blended between the identity and its side's affine map with the Q8
 // weight of its column, y = ((256 - w) x + w f(x) + 128) >> 8, in exact
-// integers; optionally fused with the histogram (and, for 16-bit cameras,
-// the sums) of the input samples.
+// integers; optionally fused with the whole-frame histogram and sums of the
+// input samples.
 //
 // A thread owns groups of 4 consecutive pixels of a row (12 bytes for RGB8, 4
 // for gray8, 8 for gray16) and walks down the tile's rows, kUnroll rows at a
@@ -10,50 +10,66 @@
 // bases stay in registers.  Tables of the tile's block sit in LDS.  The
 // histogram is kept in kRep replicas interleaved bin by bin, lane l updating
 // replica l % kRep, so that lanes of one wave that see the same value mostly
-// hit different LDS words.  At the end of the tile the replicas are summed and
-// stored to the tile's slot in context scratch with plain stores.
+// hit different LDS words.  At the end of the tile the replicas are summed
+// and added to the camera's whole-frame statistics with global atomics (the
+// whole-frame buffers must be zero before the first tile).
 #pragma once
 
 #include "dev_estimate.h"
+#include "dev_stats.h"
 
 namespace rc {
 
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned int u32x3 __attribute__((ext_vector_type(3)));
 
-constexpr int kRep = 8;      // histogram replicas
-constexpr int kUnroll = 4;   // rows in flight per thread
+#ifndef RC_APPLY_REP
+#define RC_APPLY_REP 8
+#endif
+#ifndef RC_APPLY_UNROLL
+#define RC_APPLY_UNROLL 4
+#endif
+#ifndef RC_LOAD_POLICY
+#define RC_LOAD_POLICY 2      // non-temporal: every frame byte is touched exactly once
+#endif
+#ifndef RC_STORE_POLICY
+#define RC_STORE_POLICY 2
+#endif
+constexpr int kRep = RC_APPLY_REP;        // histogram replicas
+constexpr int kUnroll = RC_APPLY_UNROLL;  // rows in flight per thread
+constexpr int kLoadPolicy = RC_LOAD_POLICY;    // cache-policy bits of frame loads
+constexpr int kStorePolicy = RC_STORE_POLICY;  // cache-policy bits of frame stores
 
 struct ApplyLds {
   uint8_t lut[2 * kCS * kNB];          // [side][channel][x]
   int64_t q[4];                        // [side][A, Bq]
   uint32_t hist[kCS * kNB * kRep];     // [channel][bin][replica]
-  unsigned long long red[2 * 16];
+  unsigned long long red[9 * 16];
 };
 
-template <int NW>
+template <int NW, int POL = kLoadPolicy>
 __device__ inline void load_group(__amdgpu_buffer_rsrc_t r, int off, uint32_t (&d)[NW]) {
   if constexpr (NW == 3) {
-    u32x3 v = __builtin_amdgcn_raw_buffer_load_b96(r, off, 0, 0);
+    u32x3 v = __builtin_amdgcn_raw_buffer_load_b96(r, off, 0, POL);
     d[0] = v.x; d[1] = v.y; d[2] = v.z;
   } else if constexpr (NW == 2) {
-    u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+    u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, POL);
     d[0] = v.x; d[1] = v.y;
   } else {
-    d[0] = __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+    d[0] = __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, POL);
   }
 }
 
-template <int NW>
+template <int NW, int POL = kStorePolicy>
 __device__ inline void store_group(__amdgpu_buffer_rsrc_t r, int off, const uint32_t (&d)[NW]) {
   if constexpr (NW == 3) {
     u32x3 v = {d[0], d[1], d[2]};
-    __builtin_amdgcn_raw_buffer_store_b96(v, r, off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b96(v, r, off, 0, POL);
   } else if constexpr (NW == 2) {
     u32x2 v = {d[0], d[1]};
-    __builtin_amdgcn_raw_buffer_store_b64(v, r, off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, off, 0, POL);
   } else {
-    __builtin_amdgcn_raw_buffer_store_b32(d[0], r, off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(d[0], r, off, 0, POL);
   }
 }
 
@@ -200,21 +216,36 @@ __device__ void apply_tile(const Geo& g, const FramePtrs& fp, const Bufs& b, int
   }
 
   if (STATS) {
+    // The tile's histogram (replicas summed) and its share of (n, S1, S2) -
+    // linear in the histogram for 8-bit samples, from the sample sums for
+    // 16-bit ones - are added to the camera's whole-frame statistics.
     __syncthreads();
-    uint32_t* th = g.scr.tile_hist + (int64_t)ti * kCS * kNB;
-    for (int i = tid; i < kCS * kNB; i += kThreads) {
-      uint32_t s = 0;
-      if (i < C * kNB) {
+    uint32_t* gh = b.whole_hist + (int64_t)t.cam * kCS * kNB;
+    uint32_t h[kCS];
 #pragma unroll
-        for (int r = 0; r < kRep; ++r) s += L.hist[i * kRep + r];
+    for (int c = 0; c < kCS; ++c) {
+      uint32_t sum = 0;
+      if (c < C) {
+#pragma unroll
+        for (int r = 0; r < kRep; ++r) sum += L.hist[(c * kNB + tid) * kRep + r];
       }
-      th[i] = s;
+      h[c] = sum;
+      if (sum) atomicAdd(&gh[c * kNB + tid], sum);
     }
-    if (BPS == 2) {
-      block_sums(
-          2, [&](int i) { return i == 0 ? a1 : a2; },
-          [&](int i, unsigned long long tot) { g.scr.tile_sums[(int64_t)ti * 2 + i] = tot; }, L.red);
-    }
+    const unsigned long long x = (unsigned long long)tid;
+    block_sums(
+        (BPS == 2) ? 3 : 3 * C,
+        [&](int i) -> unsigned long long {
+          const int c = i / 3, m = i - 3 * (i / 3);
+          const unsigned long long hc = c == 0 ? h[0] : (c == 1 ? h[1] : h[2]);
+          if (m == 0) return hc;
+          if (BPS == 2) return m == 1 ? a1 : a2;
+          return m == 1 ? hc * x : hc * x * x;
+        },
+        [&](int i, unsigned long long tot) {
+          if (tot) atomicAdd((unsigned long long*)&b.whole_sums[(int64_t)t.cam * 9 + i], tot);
+        },
+        L.red);
   }
 }
 

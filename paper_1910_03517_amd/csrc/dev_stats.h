@@ -1,6 +1,6 @@
 // Statistics of section 3.1 as device functions: the band statistics of one
-// (camera, side, block) unit, and the whole-frame reduction of one camera
-// from the per-tile histograms left by the apply pass.
+// (camera, side, block) unit, and the clearing of the whole-frame statistics
+// that the apply pass accumulates.
 #pragma once
 
 #include "dev_common.h"
@@ -37,46 +37,59 @@ __device__ void band_unit(const Geo& g, const FramePtrs& fp, const Bufs& b, int 
   unsigned long long a1 = 0, a2 = 0;           // 16-bit sums
 
   if (band > 0 && rows > 0) {
-    const int drow = kThreads / dw, dq = kThreads % dw;
-    int row = tid / dw, q = tid % dw;
-    while (row < rows) {
-      const int rowoff = (int)((int64_t)(r0 + row) * cam.pitch);
-      const int boff = (q0 + q) * 4;           // byte offset of the dword in the row
-      uint32_t d;
-      if (boff + 4 <= cam.row_bytes) {
-        d = __builtin_amdgcn_raw_buffer_load_b32(rin, rowoff + boff, 0, 0);
-      } else {                                  // dword crossing the row end
-        d = 0;
-        for (int e = 0; boff + e < cam.row_bytes; ++e)
-          d |= (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(rin, rowoff + boff + e, 0, 0) << (8 * e);
-      }
-      if (BPS == 1) {
+    constexpr int kU = 4;                      // loads in flight per thread
+    const int total = rows * dw;
+    for (int base = tid; base < total; base += kU * kThreads) {
+      uint32_t d[kU];
+      int boffs[kU];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int o = boff + e;
-          if (o >= b0 && o < b1) {
-            const uint32_t v = (d >> (8 * e)) & 0xffu;
-            const int c = (C == 1) ? 0 : o % C;
-            __hip_atomic_fetch_add(&L.hist[c * kNB + v], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-          }
-        }
-      } else {
-#pragma unroll
-        for (int e = 0; e < 2; ++e) {
-          const int o = boff + 2 * e;
-          if (o >= b0 && o < b1) {
-            const uint32_t v = (d >> (16 * e)) & 0xffffu;
-            uint32_t bin = v >> shift;
-            bin = bin > 255u ? 255u : bin;
-            __hip_atomic_fetch_add(&L.hist[bin], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            a1 += v;
-            a2 += (unsigned long long)v * v;
+      for (int u = 0; u < kU; ++u) {
+        const int idx = base + u * kThreads;
+        d[u] = 0;
+        boffs[u] = -1;
+        if (idx < total) {
+          const int row = idx / dw;
+          const int q = idx - row * dw;
+          const int rowoff = (int)((int64_t)(r0 + row) * cam.pitch);
+          const int boff = (q0 + q) * 4;         // byte offset of the dword in the row
+          boffs[u] = boff;
+          if (boff + 4 <= cam.row_bytes) {
+            d[u] = __builtin_amdgcn_raw_buffer_load_b32(rin, rowoff + boff, 0, 0);
+          } else {                                // dword crossing the row end
+            for (int e = 0; boff + e < cam.row_bytes; ++e)
+              d[u] |= (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(rin, rowoff + boff + e, 0, 0) << (8 * e);
           }
         }
       }
-      row += drow;
-      q += dq;
-      if (q >= dw) { q -= dw; ++row; }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int boff = boffs[u];
+        if (boff < 0) continue;
+        if (BPS == 1) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int o = boff + e;
+            if (o >= b0 && o < b1) {
+              const uint32_t v = (d[u] >> (8 * e)) & 0xffu;
+              const int c = (C == 1) ? 0 : o % C;
+              __hip_atomic_fetch_add(&L.hist[c * kNB + v], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+          }
+        } else {
+#pragma unroll
+          for (int e = 0; e < 2; ++e) {
+            const int o = boff + 2 * e;
+            if (o >= b0 && o < b1) {
+              const uint32_t v = (d[u] >> (16 * e)) & 0xffffu;
+              uint32_t bin = v >> shift;
+              bin = bin > 255u ? 255u : bin;
+              __hip_atomic_fetch_add(&L.hist[bin], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+              a1 += v;
+              a2 += (unsigned long long)v * v;
+            }
+          }
+        }
+      }
     }
   }
   __syncthreads();
@@ -110,38 +123,11 @@ __device__ inline void band_unit_dispatch(const Geo& g, const FramePtrs& fp, con
   else band_unit<1, 1>(g, fp, b, k, s, j, L);
 }
 
-// Whole-frame statistics of camera k: the sum of its tiles' histograms, and
-// (n, S1, S2) from the exact histogram (8-bit) or from the tiles' sums (16-bit).
-__device__ inline void whole_reduce_cam(const Geo& g, const Bufs& b, int k, StatsLds& L) {
-  const int tid = threadIdx.x;
-  const DevCam cam = g.cams[k];
-  const uint32_t* th = g.scr.tile_hist;
-  uint32_t h[kCS];
-#pragma unroll
-  for (int c = 0; c < kCS; ++c) {
-    uint32_t sum = 0;
-    if (c < cam.channels)
-      for (int t = cam.tile_begin; t < cam.tile_end; ++t) sum += th[(int64_t)t * kCS * kNB + c * kNB + tid];
-    h[c] = sum;
-    b.whole_hist[((int64_t)k * kCS + c) * kNB + tid] = sum;
-  }
-  const unsigned long long x = (unsigned long long)tid;
-  const bool b16 = cam.bps == 2;
-  block_sums(
-      9,
-      [&](int i) -> unsigned long long {
-        const int c = i / 3, m = i - 3 * (i / 3);
-        const unsigned long long hc = c == 0 ? h[0] : (c == 1 ? h[1] : h[2]);
-        if (m == 0) return hc;
-        if (b16) {
-          if (c != 0 || tid != 0) return 0ull;
-          unsigned long long s = 0;
-          for (int t = cam.tile_begin; t < cam.tile_end; ++t) s += g.scr.tile_sums[(int64_t)t * 2 + (m - 1)];
-          return s;
-        }
-        return m == 1 ? hc * x : hc * x * x;
-      },
-      [&](int i, unsigned long long tot) { b.whole_sums[(int64_t)k * 9 + i] = tot; }, L.red);
+// Zero the whole-frame histogram and sums of every camera (grid-stride).
+__device__ inline void zero_whole(const Geo& g, const Bufs& b, int thread, int nthreads) {
+  const int nh = g.n_cams * kCS * kNB;
+  for (int i = thread; i < nh; i += nthreads) b.whole_hist[i] = 0u;
+  for (int i = thread; i < g.n_cams * 9; i += nthreads) b.whole_sums[i] = 0ull;
 }
 
 }  // namespace rc

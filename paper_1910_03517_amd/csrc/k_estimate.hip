@@ -2,6 +2,7 @@
 // block, channel) for the affine fit, one workgroup per (camera, side, block)
 // for the tables, one thread per column for the blend weights.
 #include "dev_estimate.h"
+#include "dev_stats.h"
 
 namespace rc {
 
@@ -36,6 +37,9 @@ __global__ __launch_bounds__(kThreads) void k_estimate_lut(Geo g, Bufs b) {
   if (u3 % (2 * nb) == 0)
     for (int col = tid; col < g.w_max; col += kThreads)
       b.weights[(int64_t)k * g.w_max + col] = (uint16_t)blend_weight(g.cams[k].width, col);
+  // Clear the whole-frame statistics that the apply pass of this frame-set
+  // accumulates (skipped when the caller clears them itself).
+  if (b.whole_hist) zero_whole(g, b, blockIdx.x * kThreads + tid, gridDim.x * kThreads);
 }
 
 hipError_t launch_estimate_lut(const Geo& g, const Bufs& b, hipStream_t st) {

@@ -1,6 +1,5 @@
 // Statistics kernels: band statistics of section 3.1 (one workgroup per
-// (camera, side, block)) and the whole-frame reduction (one workgroup per
-// camera) of the per-tile histograms left by the apply pass.
+// (camera, side, block)) and the clearing of the whole-frame statistics.
 #include "dev_stats.h"
 
 namespace rc {
@@ -10,9 +9,8 @@ __global__ __launch_bounds__(kThreads) void k_band_stats(Geo g, FramePtrs fp, Bu
   band_unit_dispatch(g, fp, b, blockIdx.x, L);
 }
 
-__global__ __launch_bounds__(kThreads) void k_whole_reduce(Geo g, Bufs b) {
-  __shared__ StatsLds L;
-  whole_reduce_cam(g, b, blockIdx.x, L);
+__global__ __launch_bounds__(kThreads) void k_zero_whole(Geo g, Bufs b) {
+  zero_whole(g, b, blockIdx.x * kThreads + threadIdx.x, gridDim.x * kThreads);
 }
 
 hipError_t launch_band_stats(const Geo& g, const FramePtrs& fp, const Bufs& b, hipStream_t st) {
@@ -20,8 +18,9 @@ hipError_t launch_band_stats(const Geo& g, const FramePtrs& fp, const Bufs& b, h
   return hipGetLastError();
 }
 
-hipError_t launch_whole_reduce(const Geo& g, const Bufs& b, hipStream_t st) {
-  hipLaunchKernelGGL(k_whole_reduce, dim3(g.n_cams), dim3(kThreads), 0, st, g, b);
+hipError_t launch_zero_whole(const Geo& g, const Bufs& b, hipStream_t st) {
+  const int n = g.n_cams * kCS * kNB;
+  hipLaunchKernelGGL(k_zero_whole, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, st, g, b);
   return hipGetLastError();
 }
 

@@ -26,11 +26,22 @@ struct rt_ctx {
   int grid = 0;             // persistent grid size (0 = fill the device)
   DevCam* dcams = nullptr;
   Tile* dtiles = nullptr;
-  uint32_t* tile_hist = nullptr;
-  unsigned long long* tile_sums = nullptr;
-  uint32_t* sync = nullptr;
-  int64_t sync_words = 0;
+
+  // Optional timing of the apply kernel: events recorded right before and
+  // after each apply launch, in a ring of n_timing slots.
+  int n_timing = 0;
+  int64_t n_timed = 0;
+  std::vector<hipEvent_t> ev_begin, ev_end;
+  bool capturing = false;   // no timing events inside a captured graph
+  int64_t generation = 0;   // bumped whenever device tables are rebuilt
   Geo geo{};
+};
+
+struct rt_graph {
+  rt_ctx* ctx = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int64_t generation = 0;
 };
 
 
@@ -55,7 +66,7 @@ rt_status hip_fail(hipError_t e, const char* what) {
 }
 
 constexpr int kMaxDim = 32768;
-constexpr int kDefaultTileRows = 16;
+constexpr int kDefaultTileRows = 32;
 
 bool aligned(const void* p, uintptr_t a) { return ((uintptr_t)p % a) == 0; }
 
@@ -92,6 +103,7 @@ static rt_status build_tables(rt_ctx* ctx, int tile_rows) {
   const int n_cams = ctx->n_cams;
   const int nb = ctx->opts.n_blocks;
   ctx->tile_rows = tile_rows;
+  ++ctx->generation;
   ctx->htiles.clear();
   for (int k = 0; k < n_cams; ++k) {
     const int H = ctx->cams[k].height;
@@ -108,19 +120,10 @@ static rt_status build_tables(rt_ctx* ctx, int tile_rows) {
   }
   const size_t nt = ctx->htiles.size();
   if (ctx->dtiles) (void)hipFree(ctx->dtiles);
-  if (ctx->tile_hist) (void)hipFree(ctx->tile_hist);
-  if (ctx->tile_sums) (void)hipFree(ctx->tile_sums);
-  ctx->dtiles = nullptr; ctx->tile_hist = nullptr; ctx->tile_sums = nullptr;
+  ctx->dtiles = nullptr;
   hipError_t e = hipSuccess;
   if (!ctx->dcams) e = hipMalloc((void**)&ctx->dcams, sizeof(DevCam) * n_cams);
   if (e == hipSuccess) e = hipMalloc((void**)&ctx->dtiles, sizeof(Tile) * nt);
-  if (e == hipSuccess) e = hipMalloc((void**)&ctx->tile_hist, sizeof(uint32_t) * nt * kCS * kNB);
-  if (e == hipSuccess) e = hipMalloc((void**)&ctx->tile_sums, sizeof(unsigned long long) * nt * 2);
-  ctx->sync_words = 4 + n_cams + 2 * (int64_t)n_cams * 2 * nb;
-  if (e == hipSuccess && !ctx->sync) {
-    e = hipMalloc((void**)&ctx->sync, sizeof(uint32_t) * ctx->sync_words);
-    if (e == hipSuccess) e = hipMemset(ctx->sync, 0, sizeof(uint32_t) * ctx->sync_words);
-  }
   if (e != hipSuccess) return fail(RT_ENOMEM, "device tables: %s", hipGetErrorString(e));
   e = hipMemcpy(ctx->dcams, ctx->hcams.data(), sizeof(DevCam) * n_cams, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(ctx->dtiles, ctx->htiles.data(), sizeof(Tile) * nt, hipMemcpyHostToDevice);
@@ -128,9 +131,6 @@ static rt_status build_tables(rt_ctx* ctx, int tile_rows) {
   Geo& g = ctx->geo;
   g.cams = ctx->dcams;
   g.tiles = ctx->dtiles;
-  g.scr.tile_hist = ctx->tile_hist;
-  g.scr.tile_sums = ctx->tile_sums;
-  g.scr.sync = ctx->sync;
   g.n_cams = n_cams;
   g.n_blocks = nb;
   g.w_max = ctx->w_max;
@@ -249,14 +249,21 @@ rt_status rt_ctx_create(const rt_camera_desc* cams, int32_t n_cams, const rt_opt
   return RT_OK;
 }
 
+static void free_timing(rt_ctx* ctx) {
+  for (hipEvent_t ev : ctx->ev_begin) (void)hipEventDestroy(ev);
+  for (hipEvent_t ev : ctx->ev_end) (void)hipEventDestroy(ev);
+  ctx->ev_begin.clear();
+  ctx->ev_end.clear();
+  ctx->n_timing = 0;
+  ctx->n_timed = 0;
+}
+
 rt_status rt_ctx_destroy(rt_ctx* ctx) {
   if (!ctx) return RT_OK;
   (void)hipDeviceSynchronize();
+  free_timing(ctx);
   if (ctx->dcams) (void)hipFree(ctx->dcams);
   if (ctx->dtiles) (void)hipFree(ctx->dtiles);
-  if (ctx->tile_hist) (void)hipFree(ctx->tile_hist);
-  if (ctx->tile_sums) (void)hipFree(ctx->tile_sums);
-  if (ctx->sync) (void)hipFree(ctx->sync);
   delete ctx;
   return RT_OK;
 }
@@ -314,11 +321,29 @@ static Bufs make_bufs(const rt_stats_buf* s, const rt_params_buf* p, const rt_lu
   return b;
 }
 
-static rt_status whole_pass(rt_ctx* ctx, const FramePtrs& fp, const Bufs& b, bool write, hipStream_t st) {
-  hipError_t e = launch_apply(ctx->geo, fp, b, write, true, st);
+// The apply kernel, bracketed by the context's timing events when enabled
+// (never inside a graph capture).
+static hipError_t timed_apply(rt_ctx* ctx, const FramePtrs& fp, const Bufs& b, bool write, bool stats,
+                              hipStream_t st) {
+  if (ctx->n_timing <= 0 || ctx->capturing) return launch_apply(ctx->geo, fp, b, write, stats, st);
+  const int slot = (int)(ctx->n_timed % ctx->n_timing);
+  hipError_t e = hipEventRecord(ctx->ev_begin[slot], st);
+  if (e == hipSuccess) e = launch_apply(ctx->geo, fp, b, write, stats, st);
+  if (e == hipSuccess) e = hipEventRecord(ctx->ev_end[slot], st);
+  if (e == hipSuccess) ++ctx->n_timed;
+  return e;
+}
+
+// Apply (or statistics only) with fused whole-frame statistics, accumulated
+// by the tiles into the whole-frame buffers.  zero_first clears them first
+// (the frame-set path clears them in its estimate kernel instead).
+static rt_status whole_pass(rt_ctx* ctx, const FramePtrs& fp, const Bufs& b, bool write, bool zero_first,
+                            hipStream_t st) {
+  hipError_t e = hipSuccess;
+  if (zero_first) e = launch_zero_whole(ctx->geo, b, st);
+  if (e != hipSuccess) return hip_fail(e, "clearing whole-frame statistics");
+  e = timed_apply(ctx, fp, b, write, true, st);
   if (e != hipSuccess) return hip_fail(e, write ? "apply" : "whole-frame statistics");
-  e = launch_whole_reduce(ctx->geo, b, st);
-  if (e != hipSuccess) return hip_fail(e, "whole-frame reduction");
   return RT_OK;
 }
 
@@ -334,7 +359,7 @@ rt_status rt_stats(rt_ctx* ctx, const void* const* frames, const rt_stats_buf* o
   const Bufs b = make_bufs(out, nullptr, nullptr);
   hipError_t e = launch_band_stats(ctx->geo, fp, b, st);
   if (e != hipSuccess) return hip_fail(e, "band statistics");
-  if (whole) return whole_pass(ctx, fp, b, false, st);
+  if (whole) return whole_pass(ctx, fp, b, false, true, st);
   return RT_OK;
 }
 
@@ -367,8 +392,8 @@ rt_status rt_apply(rt_ctx* ctx, const void* const* frames, void* const* out_fram
   hipStream_t st = (hipStream_t)stream;
   const FramePtrs fp = make_ptrs(ctx, frames, out_frames);
   const Bufs b = make_bufs(whole_out, nullptr, lut);
-  if (whole_out) return whole_pass(ctx, fp, b, true, st);
-  hipError_t e = launch_apply(ctx->geo, fp, b, true, false, st);
+  if (whole_out) return whole_pass(ctx, fp, b, true, true, st);
+  hipError_t e = timed_apply(ctx, fp, b, true, false, st);
   return e == hipSuccess ? RT_OK : hip_fail(e, "apply");
 }
 
@@ -388,21 +413,14 @@ rt_status rt_frameset(rt_ctx* ctx, const void* const* frames, void* const* out_f
   if (e != hipSuccess) return hip_fail(e, "band statistics");
   e = launch_estimate_lut(ctx->geo, b, st);
   if (e != hipSuccess) return hip_fail(e, "estimate and tables");
-  return whole_pass(ctx, fp, b, true, st);
+  return whole_pass(ctx, fp, b, true, false, st);
 }
 
 rt_status rt_ctx_check(rt_ctx* ctx) {
   if (!ctx) return fail(RT_EINVAL, "ctx is NULL");
   hipError_t e = hipDeviceSynchronize();
-  if (e != hipSuccess) return hip_fail(e, "synchronize");
-  uint32_t err = 0;
-  e = hipMemcpy(&err, ctx->sync + 3, sizeof err, hipMemcpyDeviceToHost);
-  if (e != hipSuccess) return hip_fail(e, "reading the error word");
-  if (err) {
-    const uint32_t zero = 0;
-    (void)hipMemcpy(ctx->sync + 3, &zero, sizeof zero, hipMemcpyHostToDevice);
-    return fail(RT_EDEVICE, "a frame-set wait expired on the device (results of that launch are invalid)");
-  }
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "device check");
   return RT_OK;
 }
 
@@ -418,6 +436,243 @@ rt_status rt_ctx_tune(rt_ctx* ctx, int32_t tile_rows, int32_t grid) {
   rt_status r = build_tables(ctx, tile_rows);
   ctx->geo.apply_grid = grid;
   return r;
+}
+
+rt_status rt_graph_create(rt_ctx* ctx, const void* const* frames, void* const* out_frames, const rt_lut_buf* lut,
+                          const rt_stats_buf* whole, const void* const* next_frames, const rt_lut_buf* next_lut,
+                          const rt_stats_buf* bands, const rt_params_buf* state, rt_graph** out) {
+  if (!out) return fail(RT_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!ctx) return fail(RT_EINVAL, "ctx is NULL");
+  const bool pipelined = next_frames != nullptr;
+  rt_status r = check_frames(ctx, frames, "frames");
+  if (r == RT_OK) r = check_frames(ctx, (const void* const*)out_frames, "out_frames");
+  if (r == RT_OK) r = check_lut(lut);
+  if (r == RT_OK) r = check_stats(whole, false, true);
+  if (r == RT_OK) r = check_stats(bands, true, false);
+  if (r == RT_OK) r = check_params(state);
+  if (r == RT_OK && pipelined) r = check_frames(ctx, next_frames, "next_frames");
+  if (r == RT_OK && pipelined) r = check_lut(next_lut);
+  if (r != RT_OK) return r;
+  if (pipelined && next_lut->lut8 == lut->lut8) return fail(RT_EINVAL, "next_lut must be distinct from lut");
+
+  rt_graph* g = new (std::nothrow) rt_graph();
+  if (!g) return fail(RT_ENOMEM, "host allocation failed");
+  g->ctx = ctx;
+  g->generation = ctx->generation;
+  hipStream_t s0 = nullptr, s1 = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&s0, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&s1, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&ev_join, hipEventDisableTiming);
+  bool begun = false;
+  if (e == hipSuccess) e = hipStreamBeginCapture(s0, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    begun = true;
+    ctx->capturing = true;
+    const FramePtrs fp = make_ptrs(ctx, frames, out_frames);
+    Bufs ba = make_bufs(whole, state, lut);          // apply branch
+    ba.band_hist = bands->band_hist;
+    ba.band_sums = bands->band_sums;
+    if (!pipelined) {
+      // bands -> estimate + tables (+ clearing the whole-frame statistics) -> apply -> reduction
+      e = launch_band_stats(ctx->geo, fp, ba, s0);
+      if (e == hipSuccess) e = launch_estimate_lut(ctx->geo, ba, s0);
+      if (e == hipSuccess) e = launch_apply(ctx->geo, fp, ba, true, true, s0);
+    } else {
+      // Branch E: statistics, estimate and tables of the next frame-set.
+      // Branch A: apply of this frame-set with the tables estimated one step earlier.
+      const FramePtrs fn = make_ptrs(ctx, next_frames, nullptr);
+      Bufs be = make_bufs(nullptr, state, next_lut);
+      be.band_hist = bands->band_hist;
+      be.band_sums = bands->band_sums;
+      e = hipEventRecord(ev_fork, s0);
+      if (e == hipSuccess) e = hipStreamWaitEvent(s1, ev_fork, 0);
+      if (e == hipSuccess) e = launch_band_stats(ctx->geo, fn, be, s1);
+      if (e == hipSuccess) e = launch_estimate_lut(ctx->geo, be, s1);
+      if (e == hipSuccess) e = launch_zero_whole(ctx->geo, ba, s0);
+      if (e == hipSuccess) e = launch_apply(ctx->geo, fp, ba, true, true, s0);
+      if (e == hipSuccess) e = hipEventRecord(ev_join, s1);
+      if (e == hipSuccess) e = hipStreamWaitEvent(s0, ev_join, 0);
+    }
+    ctx->capturing = false;
+    hipGraph_t graph = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(s0, &graph);
+    if (e == hipSuccess) e = e2;
+    g->graph = graph;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+  if (ev_fork) (void)hipEventDestroy(ev_fork);
+  if (ev_join) (void)hipEventDestroy(ev_join);
+  if (s1) (void)hipStreamDestroy(s1);
+  if (s0) (void)hipStreamDestroy(s0);
+  if (e != hipSuccess) {
+    (void)begun;
+    rt_graph_destroy(g);
+    return hip_fail(e, "capturing the frame-set graph");
+  }
+  *out = g;
+  return RT_OK;
+}
+
+rt_status rt_graph_launch(rt_graph* g, void* stream) {
+  if (!g || !g->exec) return fail(RT_EINVAL, "graph is NULL");
+  if (g->generation != g->ctx->generation)
+    return fail(RT_ESTATE, "the context's tables were rebuilt after this graph was captured; capture it again");
+  hipError_t e = hipGraphLaunch(g->exec, (hipStream_t)stream);
+  return e == hipSuccess ? RT_OK : hip_fail(e, "graph launch");
+}
+
+rt_status rt_graph_destroy(rt_graph* g) {
+  if (!g) return RT_OK;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
+  return RT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Two-stream frame-set pipeline (see ringcorr.h).
+// ---------------------------------------------------------------------------
+struct rt_pipe {
+  rt_ctx* ctx = nullptr;
+  int depth = 2;
+  hipStream_t s_est = nullptr;
+  std::vector<hipEvent_t> ev_lut, ev_done;      // per slot: tables ready / apply done
+  rt_stats_buf bands{};
+  rt_params_buf state{};
+  std::vector<rt_lut_buf> luts;
+  std::vector<rt_stats_buf> wholes;
+  int64_t submitted = 0;
+};
+
+rt_status rt_pipe_create(rt_ctx* ctx, int32_t depth, const rt_stats_buf* bands, const rt_params_buf* state,
+                         const rt_lut_buf* luts, const rt_stats_buf* wholes, rt_pipe** out) {
+  if (!out) return fail(RT_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!ctx) return fail(RT_EINVAL, "ctx is NULL");
+  if (depth < 1 || depth > 8) return fail(RT_EINVAL, "depth %d outside 1..8", depth);
+  if (!luts || !wholes) return fail(RT_EINVAL, "luts or wholes is NULL");
+  rt_status r = check_stats(bands, true, false);
+  if (r == RT_OK) r = check_params(state);
+  for (int i = 0; r == RT_OK && i < depth; ++i) r = check_lut(&luts[i]);
+  for (int i = 0; r == RT_OK && i < depth; ++i) r = check_stats(&wholes[i], false, true);
+  if (r != RT_OK) return r;
+  rt_pipe* p = new (std::nothrow) rt_pipe();
+  if (!p) return fail(RT_ENOMEM, "host allocation failed");
+  p->ctx = ctx;
+  p->depth = depth;
+  p->bands = *bands;
+  p->state = *state;
+  p->luts.assign(luts, luts + depth);
+  p->wholes.assign(wholes, wholes + depth);
+  hipError_t e = hipStreamCreateWithFlags(&p->s_est, hipStreamNonBlocking);
+  for (int i = 0; e == hipSuccess && i < depth; ++i) {
+    hipEvent_t a = nullptr, b = nullptr;
+    e = hipEventCreateWithFlags(&a, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b, hipEventDisableTiming);
+    if (a) p->ev_lut.push_back(a);
+    if (b) p->ev_done.push_back(b);
+  }
+  if (e != hipSuccess) {
+    rt_pipe_destroy(p);
+    return hip_fail(e, "creating the pipeline stream and events");
+  }
+  *out = p;
+  return RT_OK;
+}
+
+rt_status rt_pipe_submit(rt_pipe* p, const void* const* frames, void* const* out_frames, void* stream,
+                         void* ready_event, int32_t* slot_out) {
+  if (!p) return fail(RT_EINVAL, "pipe is NULL");
+  rt_ctx* ctx = p->ctx;
+  rt_status r = check_frames(ctx, frames, "frames");
+  if (r == RT_OK) r = check_frames(ctx, (const void* const*)out_frames, "out_frames");
+  if (r != RT_OK) return r;
+  hipStream_t sa = (hipStream_t)stream;
+  const int slot = (int)(p->submitted % p->depth);
+  const FramePtrs fp = make_ptrs(ctx, frames, out_frames);
+  Bufs be = make_bufs(&p->bands, &p->state, &p->luts[slot]);
+  be.whole_hist = p->wholes[slot].whole_hist;    // cleared by the estimate kernel
+  be.whole_sums = p->wholes[slot].whole_sums;
+  Bufs ba = make_bufs(&p->wholes[slot], nullptr, &p->luts[slot]);
+  // Stream E: after the frames are ready (ready_event) and after the apply
+  // that last used this slot: band statistics, estimate, tables, clearing.
+  hipError_t e = hipSuccess;
+  if (ready_event) e = hipStreamWaitEvent(p->s_est, (hipEvent_t)ready_event, 0);
+  if (e == hipSuccess && p->submitted >= p->depth) e = hipStreamWaitEvent(p->s_est, p->ev_done[slot], 0);
+  if (e == hipSuccess) e = launch_band_stats(ctx->geo, fp, be, p->s_est);
+  if (e == hipSuccess) e = launch_estimate_lut(ctx->geo, be, p->s_est);
+  if (e == hipSuccess) e = hipEventRecord(p->ev_lut[slot], p->s_est);
+  // Caller's stream: the apply pass with this slot's tables and statistics.
+  if (e == hipSuccess) e = hipStreamWaitEvent(sa, p->ev_lut[slot], 0);
+  if (e == hipSuccess) e = timed_apply(ctx, fp, ba, true, true, sa);
+  if (e == hipSuccess) e = hipEventRecord(p->ev_done[slot], sa);
+  if (e != hipSuccess) return hip_fail(e, "pipeline submit");
+  if (slot_out) *slot_out = slot;
+  ++p->submitted;
+  return RT_OK;
+}
+
+rt_status rt_pipe_destroy(rt_pipe* p) {
+  if (!p) return RT_OK;
+  if (p->s_est) (void)hipStreamSynchronize(p->s_est);
+  for (hipEvent_t ev : p->ev_done) (void)hipEventSynchronize(ev);
+  for (hipEvent_t ev : p->ev_lut) (void)hipEventDestroy(ev);
+  for (hipEvent_t ev : p->ev_done) (void)hipEventDestroy(ev);
+  if (p->s_est) (void)hipStreamDestroy(p->s_est);
+  delete p;
+  return RT_OK;
+}
+
+rt_status rt_ctx_timing(rt_ctx* ctx, int32_t slots) {
+  if (!ctx) return fail(RT_EINVAL, "ctx is NULL");
+  if (slots < 0 || slots > 65536) return fail(RT_EINVAL, "slots %d outside 0..65536", slots);
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "synchronize");
+  free_timing(ctx);
+  for (int i = 0; i < slots; ++i) {
+    hipEvent_t a = nullptr, b = nullptr;
+    e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    if (e != hipSuccess) {
+      if (a) (void)hipEventDestroy(a);
+      free_timing(ctx);
+      return hip_fail(e, "creating timing events");
+    }
+    ctx->ev_begin.push_back(a);
+    ctx->ev_end.push_back(b);
+  }
+  ctx->n_timing = slots;
+  return RT_OK;
+}
+
+rt_status rt_ctx_apply_times(rt_ctx* ctx, float* ms, int32_t max_n, int32_t* n_out) {
+  if (!ctx || !ms || !n_out || max_n < 0) return fail(RT_EINVAL, "ctx, ms or n_out is NULL, or max_n < 0");
+  *n_out = 0;
+  if (ctx->n_timing <= 0) return RT_OK;
+  const int64_t avail = std::min<int64_t>(ctx->n_timed, ctx->n_timing);
+  const int n = (int)std::min<int64_t>(avail, max_n);
+  for (int i = 0; i < n; ++i) {
+    const int slot = (int)((ctx->n_timed - n + i) % ctx->n_timing);
+    hipError_t e = hipEventSynchronize(ctx->ev_end[slot]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms[i], ctx->ev_begin[slot], ctx->ev_end[slot]);
+    if (e != hipSuccess) return hip_fail(e, "reading timing events");
+  }
+  *n_out = n;
+  return RT_OK;
+}
+
+rt_status rt_stream_copy(void* dst, const void* src, int64_t bytes, int32_t vec_bytes, void* stream) {
+  if (!dst || !src) return fail(RT_EINVAL, "dst or src is NULL");
+  if (bytes < 0) return fail(RT_EINVAL, "bytes < 0");
+  if (vec_bytes != 4 && vec_bytes != 8 && vec_bytes != 12 && vec_bytes != 16)
+    return fail(RT_EINVAL, "vec_bytes must be 4, 8, 12 or 16");
+  if (!aligned(dst, 16) || !aligned(src, 16)) return fail(RT_EINVAL, "dst and src must be 16-byte aligned");
+  if (bytes >= ((int64_t)1 << 31)) return fail(RT_EUNSUPPORTED, "copies of 2 GiB or more are not supported");
+  hipError_t e = launch_stream_copy(dst, src, bytes, vec_bytes, (hipStream_t)stream);
+  return e == hipSuccess ? RT_OK : hip_fail(e, "stream copy");
 }
 
 rt_status rt_ctx_tuning(const rt_ctx* ctx, int32_t* tile_rows, int32_t* grid, int32_t* n_tiles) {

@@ -50,18 +50,10 @@ struct Bufs {
   uint16_t* weights;
 };
 
-// Context-owned device scratch.
-struct Scratch {
-  uint32_t* tile_hist;                 // [n_tiles][kCS * kNB] histogram of each tile's input
-  unsigned long long* tile_sums;       // [n_tiles][2] (S1, S2) of 16-bit tiles
-  uint32_t* sync;                      // persistent-kernel state, see k_frameset.hip
-};
-
 // Context-wide constants passed to every kernel.
 struct Geo {
   const DevCam* cams;    // device array [K]
   const Tile* tiles;     // device array [n_tiles], camera-major
-  Scratch scr;
   int32_t n_cams, n_blocks, w_max, n_tiles;
   int32_t mode;
   int32_t apply_grid;    // 0: one workgroup per tile; > 0: that many workgroups stride over the tiles
@@ -88,6 +80,7 @@ hipError_t launch_estimate(const Geo& g, const Bufs& b, hipStream_t st);
 hipError_t launch_estimate_lut(const Geo& g, const Bufs& b, hipStream_t st);
 hipError_t launch_build_lut(const Geo& g, const Bufs& b, hipStream_t st);
 hipError_t launch_apply(const Geo& g, const FramePtrs& fp, const Bufs& b, bool write, bool stats, hipStream_t st);
-hipError_t launch_whole_reduce(const Geo& g, const Bufs& b, hipStream_t st);
+hipError_t launch_zero_whole(const Geo& g, const Bufs& b, hipStream_t st);
+hipError_t launch_stream_copy(void* dst, const void* src, int64_t bytes, int vec_bytes, hipStream_t st);
 
 }  // namespace rc

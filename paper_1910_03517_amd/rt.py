@@ -26,7 +26,9 @@ CSLOTS, NBINS = 3, 256
 
 EXPORTED = ["rt_ctx_create", "rt_ctx_destroy", "rt_ctx_sizes", "rt_stats", "rt_estimate",
             "rt_build_lut", "rt_apply", "rt_frameset", "rt_ctx_check", "rt_ctx_tune", "rt_ctx_tuning",
-            "rt_status_str", "rt_last_error"]
+            "rt_stream_copy", "rt_ctx_timing", "rt_ctx_apply_times", "rt_graph_create", "rt_graph_launch",
+            "rt_graph_destroy", "rt_pipe_create", "rt_pipe_submit", "rt_pipe_destroy", "rt_status_str",
+            "rt_last_error"]
 
 
 class rt_camera_desc(ct.Structure):
@@ -92,6 +94,18 @@ def load(path: str = LIB_PATH) -> ct.CDLL:
     lib.rt_ctx_tune.argtypes = [P, ct.c_int32, ct.c_int32]
     I = ct.POINTER(ct.c_int32)
     lib.rt_ctx_tuning.argtypes = [P, I, I, I]
+    lib.rt_stream_copy.argtypes = [P, P, ct.c_int64, ct.c_int32, P]
+    lib.rt_ctx_timing.argtypes = [P, ct.c_int32]
+    lib.rt_graph_create.argtypes = [P, ct.POINTER(P), ct.POINTER(P), ct.POINTER(rt_lut_buf), ct.POINTER(rt_stats_buf),
+                                    ct.POINTER(P), ct.POINTER(rt_lut_buf), ct.POINTER(rt_stats_buf),
+                                    ct.POINTER(rt_params_buf), ct.POINTER(P)]
+    lib.rt_graph_launch.argtypes = [P, P]
+    lib.rt_pipe_create.argtypes = [P, ct.c_int32, ct.POINTER(rt_stats_buf), ct.POINTER(rt_params_buf),
+                                   ct.POINTER(rt_lut_buf), ct.POINTER(rt_stats_buf), ct.POINTER(P)]
+    lib.rt_pipe_submit.argtypes = [P, ct.POINTER(P), ct.POINTER(P), P, P, ct.POINTER(ct.c_int32)]
+    lib.rt_pipe_destroy.argtypes = [P]
+    lib.rt_graph_destroy.argtypes = [P]
+    lib.rt_ctx_apply_times.argtypes = [P, ct.POINTER(ct.c_float), ct.c_int32, ct.POINTER(ct.c_int32)]
     for name in EXPORTED:
         getattr(lib, name).restype = ct.c_int32
     lib.rt_status_str.argtypes = [ct.c_int32]
@@ -160,6 +174,102 @@ def rt_ctx_tuning(ctx) -> tuple[int, int, int]:
     a, b, c = ct.c_int32(), ct.c_int32(), ct.c_int32()
     _check(load().rt_ctx_tuning(ctx, ct.byref(a), ct.byref(b), ct.byref(c)))
     return a.value, b.value, c.value
+
+
+class Pipe:
+    """rt_pipe: the estimate of frame-set t+1 overlaps the apply of frame-set t.
+
+    luts / wholes are sequences of `depth` objects with lut8, q16, weights /
+    whole_hist, whole_sums tensors; bufs provides band_hist, band_sums,
+    params, valid."""
+
+    def __init__(self, ctx, bufs, luts, wholes):
+        depth = len(luts)
+        assert len(wholes) == depth
+        la = (rt_lut_buf * depth)(*[rt_lut_buf(_p(l.lut8), _p(l.q16), _p(l.weights)) for l in luts])
+        wa = (rt_stats_buf * depth)(*[rt_stats_buf(None, None, _p(w.whole_hist), _p(w.whole_sums)) for w in wholes])
+        bb = rt_stats_buf(_p(bufs.band_hist), _p(bufs.band_sums), None, None)
+        pb = rt_params_buf(_p(bufs.params), _p(bufs.valid))
+        h = ct.c_void_p()
+        _check(load().rt_pipe_create(ctx, depth, ct.byref(bb), ct.byref(pb), la, wa, ct.byref(h)))
+        self.handle = h
+        self.depth = depth
+        self._keep = (bufs, luts, wholes)
+        self._slot = ct.c_int32()
+
+    def submit(self, frames, out_frames, stream=None, frame_ptrs=None, out_ptrs=None, ready_event=None) -> int:
+        """Enqueue one frame-set; returns its slot.  frame_ptrs / out_ptrs may
+        pass prebuilt pointer arrays (see ptr_array) to save host time;
+        ready_event (a torch.cuda.Event recorded after the frames were written)
+        orders the statistics after the frames' producer."""
+        fa = frame_ptrs if frame_ptrs is not None else _ptr_array(frames)
+        oa = out_ptrs if out_ptrs is not None else _ptr_array(out_frames)
+        ev = ct.c_void_p(ready_event.cuda_event) if ready_event is not None else None
+        _check(load().rt_pipe_submit(self.handle, fa, oa, _stream_handle(stream), ev, ct.byref(self._slot)))
+        return self._slot.value
+
+    def close(self) -> None:
+        if self.handle is not None:
+            load().rt_pipe_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ptr_array(tensors) -> ct.Array:
+    """Prebuilt C array of device pointers, reusable across calls."""
+    return _ptr_array(tensors)
+
+
+class Graph:
+    """A captured frame-set (rt_graph_create); launch() replays it."""
+
+    def __init__(self, ctx, frames, out_frames, lut, whole, bufs, next_frames=None, next_lut=None):
+        lb = rt_lut_buf(_p(lut.lut8), _p(lut.q16), _p(lut.weights))
+        wb = rt_stats_buf(None, None, _p(whole.whole_hist), _p(whole.whole_sums))
+        bb = rt_stats_buf(_p(bufs.band_hist), _p(bufs.band_sums), None, None)
+        pb = rt_params_buf(_p(bufs.params), _p(bufs.valid))
+        nf = _ptr_array(next_frames) if next_frames is not None else None
+        nl = ct.byref(rt_lut_buf(_p(next_lut.lut8), _p(next_lut.q16), _p(next_lut.weights))) if next_lut is not None else None
+        h = ct.c_void_p()
+        _check(load().rt_graph_create(ctx, _ptr_array(frames), _ptr_array(out_frames), ct.byref(lb), ct.byref(wb),
+                                      nf, nl, ct.byref(bb), ct.byref(pb), ct.byref(h)))
+        self.handle = h
+        self._keep = (frames, out_frames, lut, whole, bufs, next_frames, next_lut)
+
+    def launch(self, stream=None) -> None:
+        _check(load().rt_graph_launch(self.handle, _stream_handle(stream)))
+
+    def close(self) -> None:
+        if self.handle is not None:
+            load().rt_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def rt_ctx_timing(ctx, slots: int) -> None:
+    _check(load().rt_ctx_timing(ctx, slots))
+
+
+def rt_ctx_apply_times(ctx, max_n: int) -> list[float]:
+    buf = (ct.c_float * max(max_n, 1))()
+    n = ct.c_int32()
+    _check(load().rt_ctx_apply_times(ctx, buf, max_n, ct.byref(n)))
+    return [buf[i] for i in range(n.value)]
+
+
+def rt_stream_copy(dst, src, nbytes: int, vec_bytes: int = 16, stream=None) -> None:
+    _check(load().rt_stream_copy(ct.c_void_p(dst.data_ptr()), ct.c_void_p(src.data_ptr()), nbytes, vec_bytes,
+                                 _stream_handle(stream)))
 
 
 def rt_stats(ctx, frames, band_hist, band_sums, whole_hist=None, whole_sums=None, stream=None) -> None:

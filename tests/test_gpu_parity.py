@@ -202,3 +202,114 @@ def test_frameset_tuning_knobs_do_not_change_results(tile_rows, grid):
                          "is shown, and rt_frameset uses the four-kernel sequence")
 def test_persistent_single_launch_frameset():
     frameset_sequence(synth.rig14_1080p(), rt.Options(), 1)
+
+
+@pytest.mark.parametrize("vec", [4, 8, 12, 16])
+def test_stream_copy_utility(vec):
+    say(f"case: stream copy vec={vec}")
+    n = 1_000_003
+    src = torch.randint(0, 256, (n,), dtype=torch.uint8, device="cuda")
+    dst = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    rt.rt_stream_copy(dst, src, n, vec)
+    torch.cuda.synchronize()
+    assert torch.equal(src, dst)
+
+
+@pytest.mark.parametrize("depth", [1, 2, 3])
+def test_pipeline_matches_sequential_framesets(depth):
+    """Two-stream pipelining of consecutive frame-sets gives the results of
+    consecutive rt_frameset calls, bit for bit (smoothing mode, drifting gains)."""
+    from paper_1910_03517_amd.pipeline import Pipeline
+    say(f"case: pipeline depth {depth} vs sequential, 4x 480x200 rgb8, 5 frame-sets")
+    spec = synth.RigSpec("pipe 4x480x200", 11, [synth.CamSpec(480, 200, 3, 8, 0, p) for p in range(4)])
+    cams = rt_cams(spec.cams)
+    opts = rt.Options(n_blocks=8, band_width=16, smoothing=True)
+    seq = rt.Rig(cams, opts)
+    par = rt.Rig(cams, opts)
+    pipe = Pipeline(par, depth=depth)
+    frames_t = [synth.rig_frames(spec, t, drift=True) for t in range(5)]
+    dev = [seq.upload(f) for f in frames_t]
+    torch.cuda.synchronize()
+    outs_p = [par.alloc_frames() for _ in range(5)]
+    slots = [pipe.submit(dev[t], outs_p[t]) for t in range(5)]
+    torch.cuda.synchronize()
+    out_s = seq.alloc_frames()
+    for t in range(5):
+        seq.frameset(dev[t], out_s)
+        torch.cuda.synchronize()
+        hs = seq.bufs.host()
+        if t >= 5 - depth:   # slots of the last `depth` frame-sets are still intact
+            w = pipe.whole[slots[t]]
+            assert np.array_equal(w.whole_hist.cpu().numpy(), seq.bufs.whole_hist.cpu().numpy())
+            assert np.array_equal(w.whole_sums.cpu().numpy(), seq.bufs.whole_sums.cpu().numpy())
+            L = pipe.luts[slots[t]]
+            assert np.array_equal(L.lut8.cpu().numpy(), seq.bufs.lut8.cpu().numpy())
+        for a, b in zip(par.download(outs_p[t]), seq.download(out_s)):
+            assert np.array_equal(a, b), f"frame-set {t}"
+    hp = par.bufs.host()
+    assert np.array_equal(hp["params"].view(np.uint64), hs["params"].view(np.uint64))
+    pipe.close()
+    seq.close()
+    par.close()
+
+
+def _eager_sequence(cams, opts, dev_frames, order):
+    """Consecutive rt_frameset calls; per step copies of out, whole stats, params."""
+    rig = rt.Rig(cams, opts)
+    out = rig.alloc_frames()
+    res = []
+    for i in order:
+        rig.frameset(dev_frames[i], out)
+        torch.cuda.synchronize()
+        res.append(dict(out=rig.download(out), wh=rig.bufs.whole_hist.cpu().numpy().copy(),
+                        ws=rig.bufs.whole_sums.cpu().numpy().copy(), params=rig.bufs.params.cpu().numpy().copy()))
+    rig.close()
+    return res
+
+
+@pytest.mark.parametrize("pipelined", [False, True])
+def test_graph_replays_match_eager(pipelined):
+    """Captured frame-set graphs, replayed over a cycle of 4 input buffers for 8
+    steps with eager torch work and synchronizations between replays: every
+    replay equals the eager rt_frameset result of the same step."""
+    from paper_1910_03517_amd.pipeline import LutSet, WholeSet
+    say(f"case: graph replay pipelined={pipelined}, 3x352x144 rgb8 + 2x96x64 u12")
+    spec = synth.RigSpec("graph", 12, [synth.CamSpec(352, 144, 3, 8, 0, p) for p in range(3)]
+                         + [synth.CamSpec(96, 64, 1, 12, 1, p) for p in range(2)])
+    cams = rt_cams(spec.cams)
+    opts = rt.Options(n_blocks=6, band_width=12, smoothing=True)
+    rig = rt.Rig(cams, opts)
+    frames = [synth.rig_frames(spec, t, drift=True) for t in range(4)]
+    dev = [rig.upload(f) for f in frames]
+    torch.cuda.synchronize()
+    order = [t % 4 for t in range(8)]
+    eager = _eager_sequence(cams, opts, dev, order)
+    luts = [LutSet(rig.sizes) for _ in range(2)]
+    whole = WholeSet(rig.sizes)
+    out = rig.alloc_frames()
+    b = rig.bufs
+    if pipelined:
+        rt.rt_stats(rig.ctx, dev[0], b.band_hist, b.band_sums)
+        rt.rt_estimate(rig.ctx, b.band_hist, b.band_sums, b.params, b.valid)
+        rt.rt_build_lut(rig.ctx, b.params, b.valid, luts[0].lut8, luts[0].q16, luts[0].weights)
+        graphs = [rt.Graph(rig.ctx, dev[i], out, luts[i % 2], whole, b, dev[(i + 1) % 4], luts[(i + 1) % 2])
+                  for i in range(4)]
+    else:
+        graphs = [rt.Graph(rig.ctx, dev[i], out, luts[0], whole, b) for i in range(4)]
+    scratch = torch.zeros(1 << 20, device="cuda")
+    for t, i in enumerate(order):
+        graphs[i].launch()
+        torch.cuda.synchronize()
+        scratch.add_(1.0)                       # eager work between replays
+        torch.cuda.synchronize()
+        got = rig.download(out)
+        for k, (a, e) in enumerate(zip(got, eager[t]["out"])):
+            assert np.array_equal(a, e), f"step {t} camera {k}"
+        assert np.array_equal(whole.whole_hist.cpu().numpy(), eager[t]["wh"]), f"step {t} whole_hist"
+        assert np.array_equal(whole.whole_sums.cpu().numpy(), eager[t]["ws"]), f"step {t} whole_sums"
+        if not pipelined:
+            assert np.array_equal(b.params.cpu().numpy(), eager[t]["params"]), f"step {t} params"
+    rig.check()
+    for g in graphs:
+        g.close()
+    rig.close()
