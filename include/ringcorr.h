@@ -178,15 +178,27 @@ rt_status rt_apply(rt_ctx* ctx, const void* const* frames, void* const* out_fram
                    const rt_stats_buf* whole_out, void* stream);
 
 /* One whole frame-set: band statistics of frame t -> estimate (updating
- * `state`) -> tables and weights -> apply to frame t with fused whole-frame
- * statistics of the input -> per-camera reduction.  Four kernels, all cameras
- * of all rings batched in each; no kernel waits on another workgroup.  Same
- * results as rt_stats (bands), rt_estimate, rt_build_lut and rt_apply (with
- * whole statistics) in that order.  All buffers must be distinct.  The calls
- * use the context's device scratch, so frame-set and apply calls of one
- * context must be ordered (same stream, or synchronized). */
+ * `state`) -> tables and weights, clearing stats' whole-frame fields -> apply
+ * to frame t with the whole-frame statistics of the input accumulated in the
+ * same pass.  Three kernels, all cameras of all rings batched in each; no
+ * kernel waits on another workgroup.  Same results as rt_stats (bands),
+ * rt_estimate, rt_build_lut and rt_apply (with whole statistics) in that
+ * order.  stats, state and lut must not overlap each other or the frames. */
 rt_status rt_frameset(rt_ctx* ctx, const void* const* frames, void* const* out_frames, const rt_stats_buf* stats,
                       const rt_params_buf* state, const rt_lut_buf* lut, void* stream);
+
+/* rt_frameset over a subset of the cameras, for serving several rigs from one
+ * context: bit k of `active` selects camera k.  Only the active cameras'
+ * frames are read (frames[k], out_frames[k] of the others may be NULL), and
+ * only their outputs, band and whole statistics, state entries, tables and
+ * weights are written; everything of the inactive cameras is left as it was.
+ * A seam's estimate reads both of its bands, so `active` must hold every
+ * camera of a ring or none of them (RT_EINVAL otherwise, also for an empty
+ * mask or bits at or beyond n_cams).  With all cameras active this is
+ * rt_frameset. */
+rt_status rt_frameset_batch(rt_ctx* ctx, uint64_t active, const void* const* frames, void* const* out_frames,
+                            const rt_stats_buf* stats, const rt_params_buf* state, const rt_lut_buf* lut,
+                            void* stream);
 
 /* Two-stream frame-set pipeline.  rt_pipe_submit enqueues one frame-set: on
  * the pipeline's own stream E the band statistics, estimate and tables of
@@ -267,6 +279,74 @@ rt_status rt_ctx_apply_times(rt_ctx* ctx, float* ms, int32_t max_n, int32_t* n_o
  * streams frames.  Gives the practical HBM ceiling of a read+write stream of
  * the same size next to the apply pass. */
 rt_status rt_stream_copy(void* dst, const void* src, int64_t bytes, int32_t vec_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Learned surrogate of the estimate (not in the paper; specified here).
+ *
+ * Unit u3 = (k * 2 + s) * NB + j, a (camera, side, block) of an RGB camera.
+ * Input 576 float32 features: regions (0 the whole frame of camera k as
+ * passed in - at inference the previous frame-set's, 1 the own band, 2 the
+ * facing band of block j, zeros without one) x channels x 64 bins; each bin
+ * sums 4 adjacent 256-bins and is divided by the region-channel's sample
+ * count in binary64, rounded once to float32 (zeros for an empty region).
+ * Network 576 -> 256 (ReLU) -> 256 (ReLU) -> 6, y = x W + b, row-major
+ * weights W[in][out].  Output (a_R, a_G, a_B, b_R/255, b_G/255, b_B/255).
+ * Loss: mean of (y - t)^2 over the n x 6 outputs.  The plain estimate judges
+ * the network and is its fallback.
+ * ------------------------------------------------------------------------ */
+#define RT_MLP_IN 576
+#define RT_MLP_HID 256
+#define RT_MLP_OUT 6
+
+/* Device pointers of one set of network tensors (weights, gradients or Adam moments):
+ * w1 [576][256], b1 [256], w2 [256][256], b2 [256], w3 [256][6], b3 [6], float32. */
+typedef struct {
+  float* w1; float* b1; float* w2; float* b2; float* w3; float* b3;
+} rt_mlp;
+
+/* Features of every unit, X float32 [K*2*NB][576] (rows of non-RGB cameras
+ * zero), from stats->band_hist (this frame-set) and stats->whole_hist (the
+ * whole-frame histograms to use, normally the previous frame-set's). */
+rt_status rt_surrogate_features(rt_ctx* ctx, const rt_stats_buf* stats, float* X, void* stream);
+
+/* The plain estimate of section 3.1 before the temporal step: p_new f64
+ * [K][2][NB][3][2] (a, b) and status i32 [K][2][NB][3]: 1 new estimate, 0 an
+ * empty band (the state is kept), 2 no facing band (identity), 3 unused
+ * channel slot. */
+rt_status rt_estimate_new(rt_ctx* ctx, const rt_stats_buf* stats, double* p_new, int32_t* status, void* stream);
+
+/* Training targets T float32 [K*2*NB][6] from p_new, and mask u8 [K*2*NB]:
+ * 1 where the unit is RGB and its three channels hold a new estimate. */
+rt_status rt_surrogate_targets(rt_ctx* ctx, const double* p_new, const int32_t* status, float* T, uint8_t* mask,
+                               void* stream);
+
+/* Per unit: use the network output Y float32 [K*2*NB][6] iff the unit is
+ * eligible (RGB, three new estimates), every output is finite and the
+ * residual r = max_c max(|a^ - a|, |b^n - b/255|) against p_new is <= tol
+ * (binary64 on the float32 outputs); used units take (a, b) = (a^, 255 b^n).
+ * Then the temporal update of `state` exactly as rt_estimate does.  used u8
+ * [K*2*NB] and residual f32 [K*2*NB] (inf where not eligible) are written. */
+rt_status rt_surrogate_select(rt_ctx* ctx, const float* Y, const double* p_new, const int32_t* status, float tol,
+                              const rt_params_buf* state, uint8_t* used, float* residual, void* stream);
+
+/* Forward pass over n rows: H1, H2 float32 [n][256] (post-ReLU), Y [n][6]. */
+rt_status rt_mlp_forward(const rt_mlp* w, const float* X, int32_t n, float* H1, float* H2, float* Y, void* stream);
+
+/* Gradients of the mean squared error against T [n][6] into `grad`, from the
+ * forward pass's X, H1, H2, Y; workspace dY [n][6], dZ1 and dZ2 [n][256]. */
+rt_status rt_mlp_backward(const rt_mlp* w, const float* X, const float* H1, const float* H2, const float* Y,
+                          const float* T, int32_t n, const rt_mlp* grad, float* dY, float* dZ1, float* dZ2,
+                          void* stream);
+
+/* One Adam step (step >= 1 counts steps for the bias correction) updating w, m, v. */
+rt_status rt_mlp_adam(const rt_mlp* w, const rt_mlp* grad, const rt_mlp* m, const rt_mlp* v, int32_t step, float lr,
+                      float beta1, float beta2, float eps, void* stream);
+
+/* out[0] = mean of (Y - T)^2 over n x 6 values. */
+rt_status rt_mlp_mse(const float* Y, const float* T, int32_t n, float* out, void* stream);
+
+/* dst[r] = src[idx[r]] for n rows of row_len floats (mini-batch gather). */
+rt_status rt_gather_rows(const float* src, int32_t row_len, const int32_t* idx, int32_t n, float* dst, void* stream);
 
 /* Static description of a status code. */
 const char* rt_status_str(rt_status s);

@@ -28,42 +28,57 @@ __device__ inline Moments moments_of(uint64_t n, uint64_t s1, uint64_t s2) {
   return m;
 }
 
-// Unit u = ((k * 2 + s) * NB + j) * 3 + c.  Both sides of a seam derive the
-// same shared moments because binary64 addition is commutative.
-__device__ inline void estimate_unit(const Geo& g, const Bufs& b, int u) {
+// Status of a (camera, side, block, channel) unit after the fit.
+enum { kStNone = 0, kStNew = 1, kStIdentity = 2, kStUnused = 3 };
+
+// The plain estimate of unit u = ((k * 2 + s) * NB + j) * 3 + c, before any
+// temporal step: kStNew with (a, b), kStNone (an empty band: keep the state),
+// kStIdentity (no facing band), kStUnused (channel beyond the camera's).
+// Both sides of a seam derive the same shared moments because binary64
+// addition is commutative.
+__device__ inline int fit_new(const Geo& g, const uint64_t* band_sums, int u, double& a, double& bb) {
   const int nb = g.n_blocks;
   const int c = u % kCS;
   const int j = (u / kCS) % nb;
   const int s = (u / (kCS * nb)) & 1;
   const int k = u / (kCS * nb * 2);
   const DevCam& cam = g.cams[k];
-  double* p = b.params + (int64_t)u * 2;
-  if (c >= cam.channels) {
-    p[0] = 1.0; p[1] = 0.0; b.valid[u] = 0;
-    return;
-  }
+  a = 1.0;
+  bb = 0.0;
+  if (c >= cam.channels) return kStUnused;
   const int fc = cam.face_cam[s];
-  if (fc < 0) {                       // open chain end: identity
-    p[0] = 1.0; p[1] = 0.0; b.valid[u] = 1;
-    return;
-  }
+  if (fc < 0) return kStIdentity;
   const int64_t fu = unit_index(fc, cam.face_side[s], j, c, nb);
-  const uint64_t* own = b.band_sums + (int64_t)u * 3;
-  const uint64_t* fac = b.band_sums + fu * 3;
-  const bool had = b.valid[u] != 0;
-  if (own[0] == 0 || fac[0] == 0) {   // no estimate: keep the state
-    if (!had) { p[0] = 1.0; p[1] = 0.0; }
-    return;
-  }
+  const uint64_t* own = band_sums + (int64_t)u * 3;
+  const uint64_t* fac = band_sums + fu * 3;
+  if (own[0] == 0 || fac[0] == 0) return kStNone;
   const Moments mo = moments_of(own[0], own[1], own[2]);
   const Moments mf = moments_of(fac[0], fac[1], fac[2]);
   const double mu_s = (mo.mu + mf.mu) / 2.0;
   const double sd_s = (mo.sd + mf.sd) / 2.0;
-  double a = (mo.var == 0.0) ? 1.0 : sd_s / mo.sd;
-  a = a < g.a_min ? g.a_min : a;
-  a = a > g.a_max ? g.a_max : a;
-  const double am = a * mo.mu;
-  double bb = mu_s - am;
+  double aa = (mo.var == 0.0) ? 1.0 : sd_s / mo.sd;
+  aa = aa < g.a_min ? g.a_min : aa;
+  aa = aa > g.a_max ? g.a_max : aa;
+  const double am = aa * mo.mu;
+  a = aa;
+  bb = mu_s - am;
+  return kStNew;
+}
+
+// The state update of unit u from its fit (section 3.1's exponential
+// smoothing in smoothing mode; the first estimate is taken as is).
+__device__ inline void temporal_update(const Geo& g, double* params, uint8_t* valid, int u, int status, double a,
+                                       double bb) {
+  double* p = params + (int64_t)u * 2;
+  if (status == kStUnused || status == kStIdentity) {
+    p[0] = 1.0; p[1] = 0.0; valid[u] = status == kStIdentity ? 1 : 0;
+    return;
+  }
+  const bool had = valid[u] != 0;
+  if (status == kStNone) {            // no estimate: keep the state
+    if (!had) { p[0] = 1.0; p[1] = 0.0; }
+    return;
+  }
   if (g.mode == RT_MODE_SMOOTHING && had) {
     const double keep = 1.0 - g.alpha;
     const double ta = keep * p[0];
@@ -75,7 +90,13 @@ __device__ inline void estimate_unit(const Geo& g, const Bufs& b, int u) {
   }
   p[0] = a;
   p[1] = bb;
-  b.valid[u] = 1;
+  valid[u] = 1;
+}
+
+__device__ inline void estimate_unit(const Geo& g, const Bufs& b, int u) {
+  double a, bb;
+  const int st = fit_new(g, b.band_sums, u, a, bb);
+  temporal_update(g, b.params, b.valid, u, st, a, bb);
 }
 
 // Entry x of the three channel tables of unit (k, s, j) = `unit3` (the

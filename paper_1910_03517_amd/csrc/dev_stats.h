@@ -118,16 +118,19 @@ __device__ inline void band_unit_dispatch(const Geo& g, const FramePtrs& fp, con
   const int s = (unit / nb) & 1;
   const int j = unit % nb;
   const DevCam& cam = g.cams[k];
+  if (!cam_active(g, k)) return;
   if (cam.bps == 2) band_unit<1, 2>(g, fp, b, k, s, j, L);
   else if (cam.channels == 3) band_unit<3, 1>(g, fp, b, k, s, j, L);
   else band_unit<1, 1>(g, fp, b, k, s, j, L);
 }
 
-// Zero the whole-frame histogram and sums of every camera (grid-stride).
+// Zero the whole-frame histogram and sums of every active camera (grid-stride).
 __device__ inline void zero_whole(const Geo& g, const Bufs& b, int thread, int nthreads) {
   const int nh = g.n_cams * kCS * kNB;
-  for (int i = thread; i < nh; i += nthreads) b.whole_hist[i] = 0u;
-  for (int i = thread; i < g.n_cams * 9; i += nthreads) b.whole_sums[i] = 0ull;
+  for (int i = thread; i < nh; i += nthreads)
+    if (cam_active(g, i / (kCS * kNB))) b.whole_hist[i] = 0u;
+  for (int i = thread; i < g.n_cams * 9; i += nthreads)
+    if (cam_active(g, i / 9)) b.whole_sums[i] = 0ull;
 }
 
 }  // namespace rc

@@ -10,6 +10,7 @@ template <bool WRITE, bool STATS>
 __global__ __launch_bounds__(kThreads) void k_apply(Geo g, FramePtrs fp, Bufs b) {
   __shared__ ApplyLds L;
   for (int ti = blockIdx.x; ti < g.n_tiles; ti += gridDim.x) {
+    if (!cam_active(g, g.tiles[ti].cam)) continue;   // uniform over the workgroup
     apply_tile_dispatch<WRITE, STATS, true>(g, fp, b, ti, L);
     __syncthreads();
   }

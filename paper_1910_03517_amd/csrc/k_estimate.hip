@@ -8,10 +8,11 @@ namespace rc {
 
 __global__ __launch_bounds__(kThreads) void k_estimate(Geo g, Bufs b) {
   const int u = blockIdx.x * blockDim.x + threadIdx.x;
-  if (u < g.n_cams * 2 * g.n_blocks * kCS) estimate_unit(g, b, u);
+  if (u < g.n_cams * 2 * g.n_blocks * kCS && cam_active(g, u / (2 * g.n_blocks * kCS))) estimate_unit(g, b, u);
 }
 
 __global__ __launch_bounds__(kThreads) void k_build_lut(Geo g, Bufs b) {
+  if (!cam_active(g, blockIdx.x / (2 * g.n_blocks))) return;
   lut_entry(g, b, blockIdx.x, threadIdx.x);
 }
 
@@ -20,7 +21,7 @@ __global__ __launch_bounds__(kThreads) void k_weights(Geo g, Bufs b) {
   if (i >= (int64_t)g.n_cams * g.w_max) return;
   const int k = (int)(i / g.w_max);
   const int col = (int)(i - (int64_t)k * g.w_max);
-  b.weights[i] = (uint16_t)blend_weight(g.cams[k].width, col);
+  if (cam_active(g, k)) b.weights[i] = (uint16_t)blend_weight(g.cams[k].width, col);
 }
 
 // Estimate, tables and weights of one (camera, side, block) per workgroup:
@@ -29,17 +30,18 @@ __global__ __launch_bounds__(kThreads) void k_weights(Geo g, Bufs b) {
 __global__ __launch_bounds__(kThreads) void k_estimate_lut(Geo g, Bufs b) {
   const int u3 = blockIdx.x;                 // (k * 2 + s) * nb + j
   const int tid = threadIdx.x;
-  if (tid < kCS) estimate_unit(g, b, u3 * kCS + tid);
-  __syncthreads();
-  lut_entry(g, b, u3, tid);
   const int nb = g.n_blocks;
   const int k = u3 / (2 * nb);
-  if (u3 % (2 * nb) == 0)
-    for (int col = tid; col < g.w_max; col += kThreads)
-      b.weights[(int64_t)k * g.w_max + col] = (uint16_t)blend_weight(g.cams[k].width, col);
   // Clear the whole-frame statistics that the apply pass of this frame-set
   // accumulates (skipped when the caller clears them itself).
   if (b.whole_hist) zero_whole(g, b, blockIdx.x * kThreads + tid, gridDim.x * kThreads);
+  if (!cam_active(g, k)) return;
+  if (tid < kCS) estimate_unit(g, b, u3 * kCS + tid);
+  __syncthreads();
+  lut_entry(g, b, u3, tid);
+  if (u3 % (2 * nb) == 0)
+    for (int col = tid; col < g.w_max; col += kThreads)
+      b.weights[(int64_t)k * g.w_max + col] = (uint16_t)blend_weight(g.cams[k].width, col);
 }
 
 hipError_t launch_estimate_lut(const Geo& g, const Bufs& b, hipStream_t st) {

@@ -1,0 +1,216 @@
+// Kernels of the learned surrogate's MLP (576 -> 256 -> 256 -> 6, ReLU):
+// an FP32 GEMM on the matrix cores with fused bias / ReLU / ReLU-mask
+// epilogues, column sums for bias gradients, the MSE gradient and value,
+// Adam, and a row gather for mini-batches.
+#include "rt_internal.h"
+
+namespace rc {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int kGemmTile = 64;   // workgroup tile (rows and columns)
+constexpr int kGemmK = 32;      // k-slab staged in LDS
+
+enum { kEpiNone = 0, kEpiBias = 1, kEpiBiasRelu = 2, kEpiMask = 3 };
+
+// C[M][N] (row stride ldc) = A x B with A(i, k) = A[i * sai + k * sak] and
+// B(k, j) = B[k * sbk + j * sbj] (strides express transposes), then the
+// epilogue: + bias[j]; + bias[j] and ReLU; or times (mask[i][j] > 0).
+// Four waves each own a 32x32 sub-tile and accumulate it with
+// v_mfma_f32_32x32x2_f32: lane l supplies A(i = l % 32, k = l / 32) and
+// B(k = l / 32, j = l % 32) and holds D(i, j) for j = l % 32 and
+// i = 8 (r / 4) + 4 (l / 32) + r % 4 in accumulator register r.
+template <int EPI>
+__global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const float* __restrict__ A, int64_t sai,
+                                              int64_t sak, const float* __restrict__ B, int64_t sbk, int64_t sbj,
+                                              float* __restrict__ C, int ldc, const float* __restrict__ bias,
+                                              const float* __restrict__ mask, int ldm) {
+  __shared__ float As[kGemmK][kGemmTile + 1];
+  __shared__ float Bs[kGemmK][kGemmTile + 1];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int i0 = blockIdx.y * kGemmTile;
+  const int j0 = blockIdx.x * kGemmTile;
+  const int wi = (wave >> 1) * 32;
+  const int wj = (wave & 1) * 32;
+  f32x16 acc;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+
+  for (int k0 = 0; k0 < K; k0 += kGemmK) {
+    for (int e = tid; e < kGemmK * kGemmTile; e += 256) {
+      const int kk = e / kGemmTile, ii = e % kGemmTile;
+      const int gi = i0 + ii, gk = k0 + kk, gj = j0 + ii;
+      As[kk][ii] = (gi < M && gk < K) ? A[(int64_t)gi * sai + (int64_t)gk * sak] : 0.0f;
+      Bs[kk][ii] = (gk < K && gj < N) ? B[(int64_t)gk * sbk + (int64_t)gj * sbj] : 0.0f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < kGemmK; kk += 2) {
+      const float a = As[kk + (lane >> 5)][wi + (lane & 31)];
+      const float b = Bs[kk + (lane >> 5)][wj + (lane & 31)];
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+
+  const int j = j0 + wj + (lane & 31);
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int i = i0 + wi + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+    if (i < M && j < N) {
+      float v = acc[r];
+      if (EPI == kEpiBias || EPI == kEpiBiasRelu) v += bias[j];
+      if (EPI == kEpiBiasRelu) v = v > 0.0f ? v : 0.0f;
+      if (EPI == kEpiMask) v = mask[(int64_t)i * ldm + j] > 0.0f ? v : 0.0f;
+      C[(int64_t)i * ldc + j] = v;
+    }
+  }
+}
+
+template <int EPI>
+static hipError_t gemm(int M, int N, int K, const float* A, int64_t sai, int64_t sak, const float* B, int64_t sbk,
+                       int64_t sbj, float* C, int ldc, const float* bias, const float* mask, int ldm, hipStream_t st) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  const dim3 grid((N + kGemmTile - 1) / kGemmTile, (M + kGemmTile - 1) / kGemmTile);
+  hipLaunchKernelGGL((k_gemm<EPI>), grid, dim3(256), 0, st, M, N, K, A, sai, sak, B, sbk, sbj, C, ldc, bias, mask,
+                     ldm);
+  return hipGetLastError();
+}
+
+// out[j] = sum over rows i < M of A[i * lda + j], j < N; one thread per column.
+__global__ __launch_bounds__(256) void k_colsum(int M, int N, const float* __restrict__ A, int lda,
+                                                float* __restrict__ out) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= N) return;
+  float s = 0.0f;
+  for (int i = 0; i < M; ++i) s += A[(int64_t)i * lda + j];
+  out[j] = s;
+}
+
+static hipError_t colsum(int M, int N, const float* A, int lda, float* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_colsum, dim3((N + 255) / 256), dim3(256), 0, st, M, N, A, lda, out);
+  return hipGetLastError();
+}
+
+// dY = 2 (Y - T) / count, elementwise over count values.
+__global__ __launch_bounds__(256) void k_mse_grad(const float* __restrict__ Y, const float* __restrict__ T,
+                                                  int64_t count, float* __restrict__ dY) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < count) dY[i] = 2.0f * (Y[i] - T[i]) / (float)count;
+}
+
+// out[0] = mean of (Y - T)^2 over count values (one workgroup).
+__global__ __launch_bounds__(256) void k_mse(const float* __restrict__ Y, const float* __restrict__ T,
+                                             int64_t count, float* __restrict__ out) {
+  __shared__ float red[256];
+  float s = 0.0f;
+  for (int64_t i = threadIdx.x; i < count; i += 256) {
+    const float d = Y[i] - T[i];
+    s += d * d;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0] / (float)count;
+}
+
+// One Adam step over n parameters with bias-correction factors c1 = 1/(1 - beta1^t),
+// c2 = 1/(1 - beta2^t).
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float* __restrict__ g,
+                                              float* __restrict__ m, float* __restrict__ v, int64_t n, float lr,
+                                              float beta1, float beta2, float eps, float c1, float c2) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = beta1 * m[i] + (1.0f - beta1) * gi;
+  const float vi = beta2 * v[i] + (1.0f - beta2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float mh = mi * c1;
+  const float vh = vi * c2;
+  p[i] = p[i] - lr * mh / (__builtin_sqrtf(vh) + eps);
+}
+
+// dst[r][:] = src[idx[r]][:] for r < n rows of row_len floats.
+__global__ __launch_bounds__(256) void k_gather_rows(const float* __restrict__ src, int row_len,
+                                                     const int32_t* __restrict__ idx, int n, float* __restrict__ dst) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)n * row_len) return;
+  const int r = (int)(e / row_len);
+  const int c = (int)(e - (int64_t)r * row_len);
+  dst[e] = src[(int64_t)idx[r] * row_len + c];
+}
+
+// ----------------------------------------------------------------------------- launchers
+
+hipError_t mlp_forward(const float* const* w, const float* X, int n, float* H1, float* H2, float* Y, hipStream_t st) {
+  // w = {w1, b1, w2, b2, w3, b3}
+  hipError_t e = gemm<kEpiBiasRelu>(n, kMlpHid, kMlpIn, X, kMlpIn, 1, w[0], kMlpHid, 1, H1, kMlpHid, w[1], nullptr,
+                                    0, st);
+  if (e == hipSuccess)
+    e = gemm<kEpiBiasRelu>(n, kMlpHid, kMlpHid, H1, kMlpHid, 1, w[2], kMlpHid, 1, H2, kMlpHid, w[3], nullptr, 0, st);
+  if (e == hipSuccess)
+    e = gemm<kEpiBias>(n, kMlpOut, kMlpHid, H2, kMlpHid, 1, w[4], kMlpOut, 1, Y, kMlpOut, w[5], nullptr, 0, st);
+  return e;
+}
+
+hipError_t mlp_backward(const float* const* w, const float* X, const float* H1, const float* H2, const float* Y,
+                        const float* T, int n, float* const* g, float* dY, float* dZ1, float* dZ2, hipStream_t st) {
+  const int64_t cnt = (int64_t)n * kMlpOut;
+  hipLaunchKernelGGL(k_mse_grad, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, Y, T, cnt, dY);
+  hipError_t e = hipGetLastError();
+  // dW3 = H2^T dY, db3 = colsum dY
+  if (e == hipSuccess)
+    e = gemm<kEpiNone>(kMlpHid, kMlpOut, n, H2, 1, kMlpHid, dY, kMlpOut, 1, g[4], kMlpOut, nullptr, nullptr, 0, st);
+  if (e == hipSuccess) e = colsum(n, kMlpOut, dY, kMlpOut, g[5], st);
+  // dZ2 = (dY W3^T) * (H2 > 0)
+  if (e == hipSuccess)
+    e = gemm<kEpiMask>(n, kMlpHid, kMlpOut, dY, kMlpOut, 1, w[4], 1, kMlpOut, dZ2, kMlpHid, nullptr, H2, kMlpHid, st);
+  // dW2 = H1^T dZ2, db2 = colsum dZ2
+  if (e == hipSuccess)
+    e = gemm<kEpiNone>(kMlpHid, kMlpHid, n, H1, 1, kMlpHid, dZ2, kMlpHid, 1, g[2], kMlpHid, nullptr, nullptr, 0, st);
+  if (e == hipSuccess) e = colsum(n, kMlpHid, dZ2, kMlpHid, g[3], st);
+  // dZ1 = (dZ2 W2^T) * (H1 > 0)
+  if (e == hipSuccess)
+    e = gemm<kEpiMask>(n, kMlpHid, kMlpHid, dZ2, kMlpHid, 1, w[2], 1, kMlpHid, dZ1, kMlpHid, nullptr, H1, kMlpHid, st);
+  // dW1 = X^T dZ1, db1 = colsum dZ1
+  if (e == hipSuccess)
+    e = gemm<kEpiNone>(kMlpIn, kMlpHid, n, X, 1, kMlpIn, dZ1, kMlpHid, 1, g[0], kMlpHid, nullptr, nullptr, 0, st);
+  if (e == hipSuccess) e = colsum(n, kMlpHid, dZ1, kMlpHid, g[1], st);
+  return e;
+}
+
+hipError_t mlp_adam(float* const* w, const float* const* g, float* const* m, float* const* v, int step, float lr,
+                    float beta1, float beta2, float eps, hipStream_t st) {
+  const int64_t sizes[6] = {(int64_t)kMlpIn * kMlpHid, kMlpHid, (int64_t)kMlpHid * kMlpHid, kMlpHid,
+                            (int64_t)kMlpHid * kMlpOut, kMlpOut};
+  const float c1 = (float)(1.0 / (1.0 - pow((double)beta1, (double)step)));
+  const float c2 = (float)(1.0 / (1.0 - pow((double)beta2, (double)step)));
+  for (int t = 0; t < 6; ++t) {
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)((sizes[t] + 255) / 256)), dim3(256), 0, st, w[t], g[t], m[t], v[t],
+                       sizes[t], lr, beta1, beta2, eps, c1, c2);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t mlp_mse(const float* Y, const float* T, int n, float* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_mse, dim3(1), dim3(256), 0, st, Y, T, (int64_t)n * kMlpOut, out);
+  return hipGetLastError();
+}
+
+hipError_t gather_rows(const float* src, int row_len, const int32_t* idx, int n, float* dst, hipStream_t st) {
+  const int64_t total = (int64_t)n * row_len;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, src, row_len, idx, n,
+                     dst);
+  return hipGetLastError();
+}
+
+}  // namespace rc

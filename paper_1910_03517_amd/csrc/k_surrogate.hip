@@ -1,0 +1,153 @@
+// Learned surrogate of the estimate, per (camera, side, block) unit of the
+// RGB cameras: its 576 input features, the plain estimate before the temporal
+// step (which judges the network and is the fallback), the training targets,
+// and the per-unit choice between network and plain estimate followed by the
+// temporal update of the estimator state.
+#include "dev_estimate.h"
+
+namespace rc {
+
+// Features of unit u3 = (k * 2 + s) * NB + j: regions (whole frame of camera k
+// as given, own band, facing band), channels, 64 bins = sum of 4 adjacent
+// 256-bins / the region-channel's count, the quotient computed in binary64 and
+// rounded once to float32.  Rows of non-RGB cameras are zero.
+__global__ __launch_bounds__(kThreads) void k_features(Geo g, const uint32_t* __restrict__ band_hist,
+                                                       const uint32_t* __restrict__ whole_hist, float* __restrict__ X) {
+  __shared__ uint32_t h[3][kCS][kNB];
+  __shared__ uint32_t cnt[3][kCS];
+  const int u3 = blockIdx.x;
+  const int nb = g.n_blocks;
+  const int k = u3 / (2 * nb);
+  const int s = (u3 / nb) & 1;
+  const int j = u3 % nb;
+  const int tid = threadIdx.x;
+  const DevCam& cam = g.cams[k];
+  float* out = X + (int64_t)u3 * kMlpIn;
+  if (!cam_active(g, k)) return;
+  if (cam.channels != 3) {
+    for (int o = tid; o < kMlpIn; o += kThreads) out[o] = 0.0f;
+    return;
+  }
+  const int fc = cam.face_cam[s];
+  const uint32_t* src[3] = {whole_hist + (int64_t)k * kCS * kNB, band_hist + unit_index(k, s, j, 0, nb) * kNB,
+                            fc >= 0 ? band_hist + unit_index(fc, cam.face_side[s], j, 0, nb) * kNB : nullptr};
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < kCS; ++c) h[r][c][tid] = src[r] ? src[r][c * kNB + tid] : 0u;
+  if (tid < 9) cnt[tid / 3][tid % 3] = 0;
+  __syncthreads();
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < kCS; ++c) {
+      const uint32_t v = h[r][c][tid];
+      if (v) atomicAdd(&cnt[r][c], v);
+    }
+  __syncthreads();
+  for (int o = tid; o < kMlpIn; o += kThreads) {
+    const int r = o / (kCS * 64), c = (o / 64) % kCS, bin = o % 64;
+    const uint32_t n = cnt[r][c];
+    const uint32_t m = h[r][c][4 * bin] + h[r][c][4 * bin + 1] + h[r][c][4 * bin + 2] + h[r][c][4 * bin + 3];
+    out[o] = n ? (float)((double)m / (double)n) : 0.0f;
+  }
+}
+
+// The plain estimate of every (camera, side, block, channel) before the temporal step.
+__global__ __launch_bounds__(kThreads) void k_estimate_new(Geo g, const uint64_t* __restrict__ band_sums,
+                                                           double* __restrict__ p_new, int32_t* __restrict__ status) {
+  const int u = blockIdx.x * kThreads + threadIdx.x;
+  if (u >= g.n_cams * 2 * g.n_blocks * kCS || !cam_active(g, u / (2 * g.n_blocks * kCS))) return;
+  double a, b;
+  status[u] = fit_new(g, band_sums, u, a, b);
+  p_new[(int64_t)u * 2] = a;
+  p_new[(int64_t)u * 2 + 1] = b;
+}
+
+// Training targets (a_R, a_G, a_B, b_R/255, b_G/255, b_B/255) of every unit,
+// and mask[u3] = 1 where the unit is RGB and all three channels hold a new estimate.
+__global__ __launch_bounds__(kThreads) void k_targets(Geo g, const double* __restrict__ p_new,
+                                                      const int32_t* __restrict__ status, float* __restrict__ T,
+                                                      uint8_t* __restrict__ mask) {
+  const int u3 = blockIdx.x * kThreads + threadIdx.x;
+  if (u3 >= g.n_cams * 2 * g.n_blocks) return;
+  const int k = u3 / (2 * g.n_blocks);
+  bool ok = g.cams[k].channels == 3;
+  for (int c = 0; c < kCS; ++c) {
+    const int64_t u = (int64_t)u3 * kCS + c;
+    ok = ok && status[u] == kStNew;
+    T[(int64_t)u3 * kMlpOut + c] = (float)p_new[u * 2];
+    T[(int64_t)u3 * kMlpOut + 3 + c] = (float)(p_new[u * 2 + 1] / 255.0);
+  }
+  mask[u3] = ok ? 1 : 0;
+}
+
+// Per unit: take the network's prediction iff the unit is RGB, all three
+// channels hold a new plain estimate, every output is finite and
+// r = max_c max(|a^ - a|, |b^n - b / 255|) <= tol (binary64 on the float32
+// outputs); then the temporal update of the three channels.
+__global__ __launch_bounds__(kThreads) void k_select(Geo g, const float* __restrict__ Y,
+                                                     const double* __restrict__ p_new,
+                                                     const int32_t* __restrict__ status, float tol,
+                                                     double* __restrict__ params, uint8_t* __restrict__ valid,
+                                                     uint8_t* __restrict__ used, float* __restrict__ residual) {
+  const int u3 = blockIdx.x * kThreads + threadIdx.x;
+  if (u3 >= g.n_cams * 2 * g.n_blocks) return;
+  const int k = u3 / (2 * g.n_blocks);
+  if (!cam_active(g, k)) return;
+  const float* y = Y + (int64_t)u3 * kMlpOut;
+  bool eligible = g.cams[k].channels == 3;
+  for (int c = 0; c < kCS; ++c) eligible = eligible && status[(int64_t)u3 * kCS + c] == kStNew;
+  bool finite = true;
+  for (int o = 0; o < kMlpOut; ++o) finite = finite && __builtin_isfinite(y[o]);
+  double r = __builtin_inf();
+  if (eligible && finite) {
+    r = 0.0;
+    for (int c = 0; c < kCS; ++c) {
+      const int64_t u = (int64_t)u3 * kCS + c;
+      const double da = __builtin_fabs((double)y[c] - p_new[u * 2]);
+      const double db = __builtin_fabs((double)y[3 + c] - p_new[u * 2 + 1] / 255.0);
+      r = da > r ? da : r;
+      r = db > r ? db : r;
+    }
+  }
+  const bool use = eligible && finite && r <= (double)tol;
+  used[u3] = use ? 1 : 0;
+  residual[u3] = (float)r;
+  for (int c = 0; c < kCS; ++c) {
+    const int u = u3 * kCS + c;
+    double a = p_new[(int64_t)u * 2], b = p_new[(int64_t)u * 2 + 1];
+    if (use) {
+      a = (double)y[c];
+      b = 255.0 * (double)y[3 + c];
+    }
+    temporal_update(g, params, valid, u, status[u], a, b);
+  }
+}
+
+hipError_t launch_features(const Geo& g, const uint32_t* band_hist, const uint32_t* whole_hist, float* X,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_features, dim3(g.n_cams * 2 * g.n_blocks), dim3(kThreads), 0, st, g, band_hist, whole_hist, X);
+  return hipGetLastError();
+}
+
+hipError_t launch_estimate_new(const Geo& g, const uint64_t* band_sums, double* p_new, int32_t* status,
+                               hipStream_t st) {
+  const int n = g.n_cams * 2 * g.n_blocks * kCS;
+  hipLaunchKernelGGL(k_estimate_new, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, st, g, band_sums, p_new,
+                     status);
+  return hipGetLastError();
+}
+
+hipError_t launch_targets(const Geo& g, const double* p_new, const int32_t* status, float* T, uint8_t* mask,
+                          hipStream_t st) {
+  const int n = g.n_cams * 2 * g.n_blocks;
+  hipLaunchKernelGGL(k_targets, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, st, g, p_new, status, T, mask);
+  return hipGetLastError();
+}
+
+hipError_t launch_select(const Geo& g, const float* Y, const double* p_new, const int32_t* status, float tol,
+                         double* params, uint8_t* valid, uint8_t* used, float* residual, hipStream_t st) {
+  const int n = g.n_cams * 2 * g.n_blocks;
+  hipLaunchKernelGGL(k_select, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, st, g, Y, p_new, status, tol,
+                     params, valid, used, residual);
+  return hipGetLastError();
+}
+
+}  // namespace rc

@@ -79,21 +79,35 @@ rt_status check_frames(const rt_ctx* ctx, const void* const* frames, const char*
   return RT_OK;
 }
 
+// Frames of the cameras in `active` only (the others may be NULL).
+rt_status check_frames_masked(const rt_ctx* ctx, uint64_t active, const void* const* frames, const char* name) {
+  if (!frames) return fail(RT_EINVAL, "%s is NULL", name);
+  for (int k = 0; k < ctx->n_cams; ++k) {
+    if (!((active >> k) & 1ull)) continue;
+    if (!frames[k]) return fail(RT_EINVAL, "%s[%d] is NULL", name, k);
+    if (!aligned(frames[k], 16)) return fail(RT_EINVAL, "%s[%d] is not 16-byte aligned", name, k);
+  }
+  return RT_OK;
+}
+
 rt_status check_ptr(const void* p, uintptr_t align, const char* name) {
   if (!p) return fail(RT_EINVAL, "%s is NULL", name);
   if (!aligned(p, align)) return fail(RT_EINVAL, "%s is not %u-byte aligned", name, (unsigned)align);
   return RT_OK;
 }
 
-FramePtrs make_ptrs(const rt_ctx* ctx, const void* const* in, void* const* out) {
+FramePtrs make_ptrs(const rt_ctx* ctx, const void* const* in, void* const* out, uint64_t active = ~0ull) {
   FramePtrs fp;
   memset(&fp, 0, sizeof fp);
   for (int k = 0; k < ctx->n_cams; ++k) {
+    if (!((active >> k) & 1ull)) continue;
     fp.in[k] = (const uint8_t*)in[k];
     fp.out[k] = out ? (uint8_t*)out[k] : nullptr;
   }
   return fp;
 }
+
+uint64_t all_cams(int n) { return n >= 64 ? ~0ull : ((1ull << n) - 1ull); }
 
 }  // namespace
 
@@ -139,6 +153,7 @@ static rt_status build_tables(rt_ctx* ctx, int tile_rows) {
   g.alpha = ctx->opts.ema_alpha;
   g.a_min = ctx->opts.a_min;
   g.a_max = ctx->opts.a_max;
+  g.active = all_cams(n_cams);
   return RT_OK;
 }
 
@@ -323,12 +338,12 @@ static Bufs make_bufs(const rt_stats_buf* s, const rt_params_buf* p, const rt_lu
 
 // The apply kernel, bracketed by the context's timing events when enabled
 // (never inside a graph capture).
-static hipError_t timed_apply(rt_ctx* ctx, const FramePtrs& fp, const Bufs& b, bool write, bool stats,
-                              hipStream_t st) {
-  if (ctx->n_timing <= 0 || ctx->capturing) return launch_apply(ctx->geo, fp, b, write, stats, st);
+static hipError_t timed_apply(rt_ctx* ctx, const Geo& g, const FramePtrs& fp, const Bufs& b, bool write,
+                              bool stats, hipStream_t st) {
+  if (ctx->n_timing <= 0 || ctx->capturing) return launch_apply(g, fp, b, write, stats, st);
   const int slot = (int)(ctx->n_timed % ctx->n_timing);
   hipError_t e = hipEventRecord(ctx->ev_begin[slot], st);
-  if (e == hipSuccess) e = launch_apply(ctx->geo, fp, b, write, stats, st);
+  if (e == hipSuccess) e = launch_apply(g, fp, b, write, stats, st);
   if (e == hipSuccess) e = hipEventRecord(ctx->ev_end[slot], st);
   if (e == hipSuccess) ++ctx->n_timed;
   return e;
@@ -337,12 +352,12 @@ static hipError_t timed_apply(rt_ctx* ctx, const FramePtrs& fp, const Bufs& b, b
 // Apply (or statistics only) with fused whole-frame statistics, accumulated
 // by the tiles into the whole-frame buffers.  zero_first clears them first
 // (the frame-set path clears them in its estimate kernel instead).
-static rt_status whole_pass(rt_ctx* ctx, const FramePtrs& fp, const Bufs& b, bool write, bool zero_first,
-                            hipStream_t st) {
+static rt_status whole_pass(rt_ctx* ctx, const Geo& g, const FramePtrs& fp, const Bufs& b, bool write,
+                            bool zero_first, hipStream_t st) {
   hipError_t e = hipSuccess;
-  if (zero_first) e = launch_zero_whole(ctx->geo, b, st);
+  if (zero_first) e = launch_zero_whole(g, b, st);
   if (e != hipSuccess) return hip_fail(e, "clearing whole-frame statistics");
-  e = timed_apply(ctx, fp, b, write, true, st);
+  e = timed_apply(ctx, g, fp, b, write, true, st);
   if (e != hipSuccess) return hip_fail(e, write ? "apply" : "whole-frame statistics");
   return RT_OK;
 }
@@ -359,7 +374,7 @@ rt_status rt_stats(rt_ctx* ctx, const void* const* frames, const rt_stats_buf* o
   const Bufs b = make_bufs(out, nullptr, nullptr);
   hipError_t e = launch_band_stats(ctx->geo, fp, b, st);
   if (e != hipSuccess) return hip_fail(e, "band statistics");
-  if (whole) return whole_pass(ctx, fp, b, false, true, st);
+  if (whole) return whole_pass(ctx, ctx->geo, fp, b, false, true, st);
   return RT_OK;
 }
 
@@ -392,28 +407,55 @@ rt_status rt_apply(rt_ctx* ctx, const void* const* frames, void* const* out_fram
   hipStream_t st = (hipStream_t)stream;
   const FramePtrs fp = make_ptrs(ctx, frames, out_frames);
   const Bufs b = make_bufs(whole_out, nullptr, lut);
-  if (whole_out) return whole_pass(ctx, fp, b, true, true, st);
-  hipError_t e = timed_apply(ctx, fp, b, true, false, st);
+  if (whole_out) return whole_pass(ctx, ctx->geo, fp, b, true, true, st);
+  hipError_t e = timed_apply(ctx, ctx->geo, fp, b, true, false, st);
   return e == hipSuccess ? RT_OK : hip_fail(e, "apply");
 }
 
-rt_status rt_frameset(rt_ctx* ctx, const void* const* frames, void* const* out_frames, const rt_stats_buf* stats,
-                      const rt_params_buf* state, const rt_lut_buf* lut, void* stream) {
-  if (!ctx) return fail(RT_EINVAL, "ctx is NULL");
-  rt_status r = check_frames(ctx, frames, "frames");
-  if (r == RT_OK) r = check_frames(ctx, (const void* const*)out_frames, "out_frames");
+// The frame-set sequence over the cameras in `active`: band statistics,
+// estimate + tables + clearing of the whole-frame statistics, apply.
+static rt_status frameset_masked(rt_ctx* ctx, uint64_t active, const void* const* frames, void* const* out_frames,
+                                 const rt_stats_buf* stats, const rt_params_buf* state, const rt_lut_buf* lut,
+                                 void* stream) {
+  rt_status r = check_frames_masked(ctx, active, frames, "frames");
+  if (r == RT_OK) r = check_frames_masked(ctx, active, (const void* const*)out_frames, "out_frames");
   if (r == RT_OK) r = check_stats(stats, true, true);
   if (r == RT_OK) r = check_params(state);
   if (r == RT_OK) r = check_lut(lut);
   if (r != RT_OK) return r;
   hipStream_t st = (hipStream_t)stream;
-  const FramePtrs fp = make_ptrs(ctx, frames, out_frames);
+  Geo g = ctx->geo;
+  g.active = active;
+  const FramePtrs fp = make_ptrs(ctx, frames, out_frames, active);
   const Bufs b = make_bufs(stats, state, lut);
-  hipError_t e = launch_band_stats(ctx->geo, fp, b, st);
+  hipError_t e = launch_band_stats(g, fp, b, st);
   if (e != hipSuccess) return hip_fail(e, "band statistics");
-  e = launch_estimate_lut(ctx->geo, b, st);
+  e = launch_estimate_lut(g, b, st);
   if (e != hipSuccess) return hip_fail(e, "estimate and tables");
-  return whole_pass(ctx, fp, b, true, false, st);
+  return whole_pass(ctx, g, fp, b, true, false, st);
+}
+
+rt_status rt_frameset(rt_ctx* ctx, const void* const* frames, void* const* out_frames, const rt_stats_buf* stats,
+                      const rt_params_buf* state, const rt_lut_buf* lut, void* stream) {
+  if (!ctx) return fail(RT_EINVAL, "ctx is NULL");
+  return frameset_masked(ctx, all_cams(ctx->n_cams), frames, out_frames, stats, state, lut, stream);
+}
+
+rt_status rt_frameset_batch(rt_ctx* ctx, uint64_t active, const void* const* frames, void* const* out_frames,
+                            const rt_stats_buf* stats, const rt_params_buf* state, const rt_lut_buf* lut,
+                            void* stream) {
+  if (!ctx) return fail(RT_EINVAL, "ctx is NULL");
+  if (active == 0) return fail(RT_EINVAL, "active is empty");
+  if (active & ~all_cams(ctx->n_cams)) return fail(RT_EINVAL, "active names cameras beyond n_cams = %d", ctx->n_cams);
+  // A seam's estimate reads both of its bands, so a ring is active as a whole.
+  for (int k = 0; k < ctx->n_cams; ++k) {
+    if (!((active >> k) & 1ull)) continue;
+    for (int i = 0; i < ctx->n_cams; ++i)
+      if (ctx->cams[i].ring == ctx->cams[k].ring && !((active >> i) & 1ull))
+        return fail(RT_EINVAL, "active holds camera %d of ring %d but not camera %d of the same ring", k,
+                    ctx->cams[k].ring, i);
+  }
+  return frameset_masked(ctx, active, frames, out_frames, stats, state, lut, stream);
 }
 
 rt_status rt_ctx_check(rt_ctx* ctx) {
@@ -607,7 +649,7 @@ rt_status rt_pipe_submit(rt_pipe* p, const void* const* frames, void* const* out
   if (e == hipSuccess) e = hipEventRecord(p->ev_lut[slot], p->s_est);
   // Caller's stream: the apply pass with this slot's tables and statistics.
   if (e == hipSuccess) e = hipStreamWaitEvent(sa, p->ev_lut[slot], 0);
-  if (e == hipSuccess) e = timed_apply(ctx, fp, ba, true, true, sa);
+  if (e == hipSuccess) e = timed_apply(ctx, ctx->geo, fp, ba, true, true, sa);
   if (e == hipSuccess) e = hipEventRecord(p->ev_done[slot], sa);
   if (e != hipSuccess) return hip_fail(e, "pipeline submit");
   if (slot_out) *slot_out = slot;
@@ -624,6 +666,139 @@ rt_status rt_pipe_destroy(rt_pipe* p) {
   if (p->s_est) (void)hipStreamDestroy(p->s_est);
   delete p;
   return RT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Learned surrogate.
+// ---------------------------------------------------------------------------
+static rt_status check_mlp(const rt_mlp* m, const char* name) {
+  if (!m) return fail(RT_EINVAL, "%s is NULL", name);
+  const float* p[6] = {m->w1, m->b1, m->w2, m->b2, m->w3, m->b3};
+  for (int i = 0; i < 6; ++i)
+    if (!p[i] || !aligned(p[i], 4)) return fail(RT_EINVAL, "%s tensor %d is NULL or misaligned", name, i);
+  return RT_OK;
+}
+
+rt_status rt_surrogate_features(rt_ctx* ctx, const rt_stats_buf* stats, float* X, void* stream) {
+  if (!ctx) return fail(RT_EINVAL, "ctx is NULL");
+  rt_status r = check_stats(stats, true, false);
+  if (r == RT_OK) r = check_ptr(stats->whole_hist, 4, "whole_hist");
+  if (r == RT_OK) r = check_ptr(X, 4, "X");
+  if (r != RT_OK) return r;
+  hipError_t e = launch_features(ctx->geo, stats->band_hist, stats->whole_hist, X, (hipStream_t)stream);
+  return e == hipSuccess ? RT_OK : hip_fail(e, "surrogate features");
+}
+
+rt_status rt_estimate_new(rt_ctx* ctx, const rt_stats_buf* stats, double* p_new, int32_t* status, void* stream) {
+  if (!ctx) return fail(RT_EINVAL, "ctx is NULL");
+  rt_status r = check_stats(stats, true, false);
+  if (r == RT_OK) r = check_ptr(p_new, 8, "p_new");
+  if (r == RT_OK) r = check_ptr(status, 4, "status");
+  if (r != RT_OK) return r;
+  hipError_t e = launch_estimate_new(ctx->geo, stats->band_sums, p_new, status, (hipStream_t)stream);
+  return e == hipSuccess ? RT_OK : hip_fail(e, "plain estimate");
+}
+
+rt_status rt_surrogate_targets(rt_ctx* ctx, const double* p_new, const int32_t* status, float* T, uint8_t* mask,
+                               void* stream) {
+  if (!ctx) return fail(RT_EINVAL, "ctx is NULL");
+  rt_status r = check_ptr(p_new, 8, "p_new");
+  if (r == RT_OK) r = check_ptr(status, 4, "status");
+  if (r == RT_OK) r = check_ptr(T, 4, "T");
+  if (r == RT_OK) r = check_ptr(mask, 1, "mask");
+  if (r != RT_OK) return r;
+  hipError_t e = launch_targets(ctx->geo, p_new, status, T, mask, (hipStream_t)stream);
+  return e == hipSuccess ? RT_OK : hip_fail(e, "surrogate targets");
+}
+
+rt_status rt_surrogate_select(rt_ctx* ctx, const float* Y, const double* p_new, const int32_t* status, float tol,
+                              const rt_params_buf* state, uint8_t* used, float* residual, void* stream) {
+  if (!ctx) return fail(RT_EINVAL, "ctx is NULL");
+  rt_status r = check_ptr(Y, 4, "Y");
+  if (r == RT_OK) r = check_ptr(p_new, 8, "p_new");
+  if (r == RT_OK) r = check_ptr(status, 4, "status");
+  if (r == RT_OK) r = check_params(state);
+  if (r == RT_OK) r = check_ptr(used, 1, "used");
+  if (r == RT_OK) r = check_ptr(residual, 4, "residual");
+  if (r != RT_OK) return r;
+  if (!(tol >= 0.0f)) return fail(RT_EINVAL, "tol must be >= 0");
+  hipError_t e = launch_select(ctx->geo, Y, p_new, status, tol, state->params, state->valid, used, residual,
+                               (hipStream_t)stream);
+  return e == hipSuccess ? RT_OK : hip_fail(e, "surrogate select");
+}
+
+static void mlp_ptrs(const rt_mlp* m, float** out) {
+  out[0] = m->w1; out[1] = m->b1; out[2] = m->w2; out[3] = m->b2; out[4] = m->w3; out[5] = m->b3;
+}
+
+rt_status rt_mlp_forward(const rt_mlp* w, const float* X, int32_t n, float* H1, float* H2, float* Y, void* stream) {
+  rt_status r = check_mlp(w, "weights");
+  if (r == RT_OK) r = check_ptr(X, 4, "X");
+  if (r == RT_OK) r = check_ptr(H1, 4, "H1");
+  if (r == RT_OK) r = check_ptr(H2, 4, "H2");
+  if (r == RT_OK) r = check_ptr(Y, 4, "Y");
+  if (r != RT_OK) return r;
+  if (n < 0) return fail(RT_EINVAL, "n < 0");
+  float* wp[6];
+  mlp_ptrs(w, wp);
+  hipError_t e = mlp_forward(wp, X, n, H1, H2, Y, (hipStream_t)stream);
+  return e == hipSuccess ? RT_OK : hip_fail(e, "mlp forward");
+}
+
+rt_status rt_mlp_backward(const rt_mlp* w, const float* X, const float* H1, const float* H2, const float* Y,
+                          const float* T, int32_t n, const rt_mlp* grad, float* dY, float* dZ1, float* dZ2,
+                          void* stream) {
+  rt_status r = check_mlp(w, "weights");
+  if (r == RT_OK) r = check_mlp(grad, "grad");
+  const void* ps[8] = {X, H1, H2, Y, T, dY, dZ1, dZ2};
+  for (int i = 0; r == RT_OK && i < 8; ++i) r = check_ptr(ps[i], 4, "activation or workspace");
+  if (r != RT_OK) return r;
+  if (n < 1) return fail(RT_EINVAL, "n < 1");
+  float *wp[6], *gp[6];
+  mlp_ptrs(w, wp);
+  mlp_ptrs(grad, gp);
+  hipError_t e = mlp_backward(wp, X, H1, H2, Y, T, n, gp, dY, dZ1, dZ2, (hipStream_t)stream);
+  return e == hipSuccess ? RT_OK : hip_fail(e, "mlp backward");
+}
+
+rt_status rt_mlp_adam(const rt_mlp* w, const rt_mlp* grad, const rt_mlp* m, const rt_mlp* v, int32_t step, float lr,
+                      float beta1, float beta2, float eps, void* stream) {
+  rt_status r = check_mlp(w, "weights");
+  if (r == RT_OK) r = check_mlp(grad, "grad");
+  if (r == RT_OK) r = check_mlp(m, "m");
+  if (r == RT_OK) r = check_mlp(v, "v");
+  if (r != RT_OK) return r;
+  if (step < 1) return fail(RT_EINVAL, "step must be >= 1");
+  if (!(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f && eps > 0.0f && lr > 0.0f))
+    return fail(RT_EINVAL, "need 0 <= beta < 1, eps > 0, lr > 0");
+  float *wp[6], *gp[6], *mp[6], *vp[6];
+  mlp_ptrs(w, wp);
+  mlp_ptrs(grad, gp);
+  mlp_ptrs(m, mp);
+  mlp_ptrs(v, vp);
+  hipError_t e = mlp_adam(wp, gp, mp, vp, step, lr, beta1, beta2, eps, (hipStream_t)stream);
+  return e == hipSuccess ? RT_OK : hip_fail(e, "adam");
+}
+
+rt_status rt_mlp_mse(const float* Y, const float* T, int32_t n, float* out, void* stream) {
+  rt_status r = check_ptr(Y, 4, "Y");
+  if (r == RT_OK) r = check_ptr(T, 4, "T");
+  if (r == RT_OK) r = check_ptr(out, 4, "out");
+  if (r != RT_OK) return r;
+  if (n < 1) return fail(RT_EINVAL, "n < 1");
+  hipError_t e = mlp_mse(Y, T, n, out, (hipStream_t)stream);
+  return e == hipSuccess ? RT_OK : hip_fail(e, "mse");
+}
+
+rt_status rt_gather_rows(const float* src, int32_t row_len, const int32_t* idx, int32_t n, float* dst,
+                         void* stream) {
+  rt_status r = check_ptr(src, 4, "src");
+  if (r == RT_OK) r = check_ptr(idx, 4, "idx");
+  if (r == RT_OK) r = check_ptr(dst, 4, "dst");
+  if (r != RT_OK) return r;
+  if (row_len < 1 || n < 0) return fail(RT_EINVAL, "row_len < 1 or n < 0");
+  hipError_t e = gather_rows(src, row_len, idx, n, dst, (hipStream_t)stream);
+  return e == hipSuccess ? RT_OK : hip_fail(e, "gather rows");
 }
 
 rt_status rt_ctx_timing(rt_ctx* ctx, int32_t slots) {

@@ -11,6 +11,7 @@ namespace rc {
 constexpr int kCS = RT_CSLOTS;   // channel slots
 constexpr int kNB = RT_NBINS;    // histogram bins
 constexpr int kThreads = 256;    // threads of every workgroup
+constexpr int kMlpIn = RT_MLP_IN, kMlpHid = RT_MLP_HID, kMlpOut = RT_MLP_OUT;
 
 // Per-camera geometry as the kernels see it (uploaded once per context).
 struct DevCam {
@@ -58,7 +59,10 @@ struct Geo {
   int32_t mode;
   int32_t apply_grid;    // 0: one workgroup per tile; > 0: that many workgroups stride over the tiles
   double alpha, a_min, a_max;
+  uint64_t active;       // cameras processed by this launch (bit k = camera k)
 };
+
+__host__ __device__ inline bool cam_active(const Geo& g, int k) { return (g.active >> k) & 1ull; }
 
 // Buffer resource over one frame: loads beyond the last sample of the frame
 // return zero and stores there are dropped by the hardware range check.
@@ -82,5 +86,22 @@ hipError_t launch_build_lut(const Geo& g, const Bufs& b, hipStream_t st);
 hipError_t launch_apply(const Geo& g, const FramePtrs& fp, const Bufs& b, bool write, bool stats, hipStream_t st);
 hipError_t launch_zero_whole(const Geo& g, const Bufs& b, hipStream_t st);
 hipError_t launch_stream_copy(void* dst, const void* src, int64_t bytes, int vec_bytes, hipStream_t st);
+
+// Learned surrogate.
+hipError_t launch_features(const Geo& g, const uint32_t* band_hist, const uint32_t* whole_hist, float* X,
+                           hipStream_t st);
+hipError_t launch_estimate_new(const Geo& g, const uint64_t* band_sums, double* p_new, int32_t* status,
+                               hipStream_t st);
+hipError_t launch_targets(const Geo& g, const double* p_new, const int32_t* status, float* T, uint8_t* mask,
+                          hipStream_t st);
+hipError_t launch_select(const Geo& g, const float* Y, const double* p_new, const int32_t* status, float tol,
+                         double* params, uint8_t* valid, uint8_t* used, float* residual, hipStream_t st);
+hipError_t mlp_forward(const float* const* w, const float* X, int n, float* H1, float* H2, float* Y, hipStream_t st);
+hipError_t mlp_backward(const float* const* w, const float* X, const float* H1, const float* H2, const float* Y,
+                        const float* T, int n, float* const* g, float* dY, float* dZ1, float* dZ2, hipStream_t st);
+hipError_t mlp_adam(float* const* w, const float* const* g, float* const* m, float* const* v, int step, float lr,
+                    float beta1, float beta2, float eps, hipStream_t st);
+hipError_t mlp_mse(const float* Y, const float* T, int n, float* out, hipStream_t st);
+hipError_t gather_rows(const float* src, int row_len, const int32_t* idx, int n, float* dst, hipStream_t st);
 
 }  // namespace rc

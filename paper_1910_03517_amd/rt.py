@@ -25,10 +25,13 @@ RT_MAX_CAMS = 64
 CSLOTS, NBINS = 3, 256
 
 EXPORTED = ["rt_ctx_create", "rt_ctx_destroy", "rt_ctx_sizes", "rt_stats", "rt_estimate",
-            "rt_build_lut", "rt_apply", "rt_frameset", "rt_ctx_check", "rt_ctx_tune", "rt_ctx_tuning",
+            "rt_build_lut", "rt_apply", "rt_frameset", "rt_frameset_batch", "rt_ctx_check", "rt_ctx_tune", "rt_ctx_tuning",
             "rt_stream_copy", "rt_ctx_timing", "rt_ctx_apply_times", "rt_graph_create", "rt_graph_launch",
-            "rt_graph_destroy", "rt_pipe_create", "rt_pipe_submit", "rt_pipe_destroy", "rt_status_str",
-            "rt_last_error"]
+            "rt_graph_destroy", "rt_pipe_create", "rt_pipe_submit", "rt_pipe_destroy",
+            "rt_surrogate_features", "rt_estimate_new", "rt_surrogate_targets", "rt_surrogate_select",
+            "rt_mlp_forward", "rt_mlp_backward", "rt_mlp_adam", "rt_mlp_mse", "rt_gather_rows",
+            "rt_status_str", "rt_last_error"]
+MLP_IN, MLP_HID, MLP_OUT = 576, 256, 6
 
 
 class rt_camera_desc(ct.Structure):
@@ -63,6 +66,11 @@ class rt_lut_buf(ct.Structure):
     _fields_ = [("lut8", ct.c_void_p), ("q16", ct.c_void_p), ("weights", ct.c_void_p)]
 
 
+class rt_mlp(ct.Structure):
+    _fields_ = [("w1", ct.c_void_p), ("b1", ct.c_void_p), ("w2", ct.c_void_p), ("b2", ct.c_void_p),
+                ("w3", ct.c_void_p), ("b3", ct.c_void_p)]
+
+
 class RtError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"ringcorr status {status}: {msg}")
@@ -90,6 +98,8 @@ def load(path: str = LIB_PATH) -> ct.CDLL:
     lib.rt_apply.argtypes = [P, ct.POINTER(P), ct.POINTER(P), ct.POINTER(rt_lut_buf), ct.POINTER(rt_stats_buf), P]
     lib.rt_frameset.argtypes = [P, ct.POINTER(P), ct.POINTER(P), ct.POINTER(rt_stats_buf),
                                 ct.POINTER(rt_params_buf), ct.POINTER(rt_lut_buf), P]
+    lib.rt_frameset_batch.argtypes = [P, ct.c_uint64, ct.POINTER(P), ct.POINTER(P), ct.POINTER(rt_stats_buf),
+                                      ct.POINTER(rt_params_buf), ct.POINTER(rt_lut_buf), P]
     lib.rt_ctx_check.argtypes = [P]
     lib.rt_ctx_tune.argtypes = [P, ct.c_int32, ct.c_int32]
     I = ct.POINTER(ct.c_int32)
@@ -104,6 +114,16 @@ def load(path: str = LIB_PATH) -> ct.CDLL:
                                    ct.POINTER(rt_lut_buf), ct.POINTER(rt_stats_buf), ct.POINTER(P)]
     lib.rt_pipe_submit.argtypes = [P, ct.POINTER(P), ct.POINTER(P), P, P, ct.POINTER(ct.c_int32)]
     lib.rt_pipe_destroy.argtypes = [P]
+    M = ct.POINTER(rt_mlp)
+    lib.rt_surrogate_features.argtypes = [P, ct.POINTER(rt_stats_buf), P, P]
+    lib.rt_estimate_new.argtypes = [P, ct.POINTER(rt_stats_buf), P, P, P]
+    lib.rt_surrogate_targets.argtypes = [P, P, P, P, P, P]
+    lib.rt_surrogate_select.argtypes = [P, P, P, P, ct.c_float, ct.POINTER(rt_params_buf), P, P, P]
+    lib.rt_mlp_forward.argtypes = [M, P, ct.c_int32, P, P, P, P]
+    lib.rt_mlp_backward.argtypes = [M, P, P, P, P, P, ct.c_int32, M, P, P, P, P]
+    lib.rt_mlp_adam.argtypes = [M, M, M, M, ct.c_int32, ct.c_float, ct.c_float, ct.c_float, ct.c_float, P]
+    lib.rt_mlp_mse.argtypes = [P, P, ct.c_int32, P, P]
+    lib.rt_gather_rows.argtypes = [P, ct.c_int32, P, ct.c_int32, P, P]
     lib.rt_graph_destroy.argtypes = [P]
     lib.rt_ctx_apply_times.argtypes = [P, ct.POINTER(ct.c_float), ct.c_int32, ct.POINTER(ct.c_int32)]
     for name in EXPORTED:
@@ -129,9 +149,10 @@ def _stream_handle(stream) -> ct.c_void_p:
 
 
 def _ptr_array(tensors) -> ct.Array:
+    """Device pointers of tensors (or plain ints); None becomes NULL."""
     arr = (ct.c_void_p * len(tensors))()
     for i, t in enumerate(tensors):
-        arr[i] = t.data_ptr() if hasattr(t, "data_ptr") else int(t)
+        arr[i] = None if t is None else (t.data_ptr() if hasattr(t, "data_ptr") else int(t))
     return arr
 
 
@@ -220,6 +241,73 @@ class Pipe:
             pass
 
 
+class MlpTensors:
+    """One set of network tensors on the device (weights, gradients or moments)."""
+    NAMES = ("w1", "b1", "w2", "b2", "w3", "b3")
+    SHAPES = {"w1": (MLP_IN, MLP_HID), "b1": (MLP_HID,), "w2": (MLP_HID, MLP_HID), "b2": (MLP_HID,),
+              "w3": (MLP_HID, MLP_OUT), "b3": (MLP_OUT,)}
+
+    def __init__(self, arrays: dict | None = None, device="cuda"):
+        import torch
+        for n in self.NAMES:
+            if arrays is None:
+                t = torch.zeros(self.SHAPES[n], dtype=torch.float32, device=device)
+            else:
+                t = torch.as_tensor(np.asarray(arrays[n], np.float32), device=device).contiguous()
+                assert tuple(t.shape) == self.SHAPES[n], n
+            setattr(self, n, t)
+
+    def c(self) -> rt_mlp:
+        return rt_mlp(*[_p(getattr(self, n)) for n in self.NAMES])
+
+    def host(self) -> dict:
+        return {n: getattr(self, n).cpu().numpy().copy() for n in self.NAMES}
+
+
+def rt_surrogate_features(ctx, band_hist, whole_hist, X, stream=None) -> None:
+    sb = rt_stats_buf(_p(band_hist), None, _p(whole_hist), None)
+    _check(load().rt_surrogate_features(ctx, ct.byref(sb), _p(X), _stream_handle(stream)))
+
+
+def rt_estimate_new(ctx, band_sums, p_new, status, stream=None) -> None:
+    # band_hist is not read; the struct field is set to the sums to pass validation of a non-NULL pointer
+    sb = rt_stats_buf(_p(band_sums), _p(band_sums), None, None)
+    _check(load().rt_estimate_new(ctx, ct.byref(sb), _p(p_new), _p(status), _stream_handle(stream)))
+
+
+def rt_surrogate_targets(ctx, p_new, status, T, mask, stream=None) -> None:
+    _check(load().rt_surrogate_targets(ctx, _p(p_new), _p(status), _p(T), _p(mask), _stream_handle(stream)))
+
+
+def rt_surrogate_select(ctx, Y, p_new, status, tol, params, valid, used, residual, stream=None) -> None:
+    pb = rt_params_buf(_p(params), _p(valid))
+    _check(load().rt_surrogate_select(ctx, _p(Y), _p(p_new), _p(status), float(tol), ct.byref(pb), _p(used),
+                                      _p(residual), _stream_handle(stream)))
+
+
+def rt_mlp_forward(w: MlpTensors, X, n, H1, H2, Y, stream=None) -> None:
+    _check(load().rt_mlp_forward(ct.byref(w.c()), _p(X), n, _p(H1), _p(H2), _p(Y), _stream_handle(stream)))
+
+
+def rt_mlp_backward(w: MlpTensors, X, H1, H2, Y, T, n, grad: MlpTensors, dY, dZ1, dZ2, stream=None) -> None:
+    _check(load().rt_mlp_backward(ct.byref(w.c()), _p(X), _p(H1), _p(H2), _p(Y), _p(T), n, ct.byref(grad.c()),
+                                  _p(dY), _p(dZ1), _p(dZ2), _stream_handle(stream)))
+
+
+def rt_mlp_adam(w: MlpTensors, grad: MlpTensors, m: MlpTensors, v: MlpTensors, step: int, lr: float,
+                beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8, stream=None) -> None:
+    _check(load().rt_mlp_adam(ct.byref(w.c()), ct.byref(grad.c()), ct.byref(m.c()), ct.byref(v.c()), step, lr,
+                              beta1, beta2, eps, _stream_handle(stream)))
+
+
+def rt_mlp_mse(Y, T, n, out, stream=None) -> None:
+    _check(load().rt_mlp_mse(_p(Y), _p(T), n, _p(out), _stream_handle(stream)))
+
+
+def rt_gather_rows(src, row_len, idx, n, dst, stream=None) -> None:
+    _check(load().rt_gather_rows(_p(src), row_len, _p(idx), n, _p(dst), _stream_handle(stream)))
+
+
 def ptr_array(tensors) -> ct.Array:
     """Prebuilt C array of device pointers, reusable across calls."""
     return _ptr_array(tensors)
@@ -304,6 +392,14 @@ def rt_frameset(ctx, frames, out_frames, bufs: "Buffers", stream=None) -> None:
     lb = rt_lut_buf(_p(bufs.lut8), _p(bufs.q16), _p(bufs.weights))
     _check(load().rt_frameset(ctx, _ptr_array(frames), _ptr_array(out_frames), ct.byref(sb), ct.byref(pb),
                               ct.byref(lb), _stream_handle(stream)))
+
+
+def rt_frameset_batch(ctx, active: int, frames, out_frames, bufs: "Buffers", stream=None) -> None:
+    sb = rt_stats_buf(_p(bufs.band_hist), _p(bufs.band_sums), _p(bufs.whole_hist), _p(bufs.whole_sums))
+    pb = rt_params_buf(_p(bufs.params), _p(bufs.valid))
+    lb = rt_lut_buf(_p(bufs.lut8), _p(bufs.q16), _p(bufs.weights))
+    _check(load().rt_frameset_batch(ctx, ct.c_uint64(active), _ptr_array(frames), _ptr_array(out_frames),
+                                    ct.byref(sb), ct.byref(pb), ct.byref(lb), _stream_handle(stream)))
 
 
 # ----------------------------------------------------------------------------- convenience
@@ -450,6 +546,11 @@ class Rig:
 
     def frameset(self, frames, out_frames, stream=None) -> None:
         rt_frameset(self.ctx, frames, out_frames, self.bufs, stream)
+
+    def frameset_batch(self, active: int, frames, out_frames, stream=None) -> None:
+        """Frame-set of the cameras in bitmask `active` (whole rings); the
+        entries of inactive cameras in frames / out_frames may be None."""
+        rt_frameset_batch(self.ctx, active, frames, out_frames, self.bufs, stream)
 
     def check(self) -> None:
         rt_ctx_check(self.ctx)

@@ -186,3 +186,25 @@ def tiny_frame(height: int, width: int, channels: int, bit_depth: int, rng: np.r
     """Uniform random frame for brute-force and fuzz cases."""
     dt = np.uint8 if bit_depth == 8 else np.uint16
     return rng.integers(0, 1 << bit_depth, (height, width, channels), dtype=np.int64).astype(dt)
+
+
+def mlp_init(seed: int, n_in: int = 576, n_hid: int = 256, n_out: int = 6) -> dict:
+    """Seeded He initialisation of the surrogate MLP (weights N(0, 2/fan_in), zero biases), float32."""
+    rng = _rng(77, seed)
+    f = np.float32
+    return {"w1": (rng.standard_normal((n_in, n_hid)) * np.sqrt(2.0 / n_in)).astype(f), "b1": np.zeros(n_hid, f),
+            "w2": (rng.standard_normal((n_hid, n_hid)) * np.sqrt(2.0 / n_hid)).astype(f), "b2": np.zeros(n_hid, f),
+            "w3": (rng.standard_normal((n_hid, n_out)) * np.sqrt(2.0 / n_hid)).astype(f), "b3": np.zeros(n_out, f)}
+
+
+def distort_device(base, gains: np.ndarray, cams, out) -> None:
+    """Device-side gain distortion of undistorted frames (training-data synthesis):
+    out = clamp(round(gain_kc * x)) per camera and channel, on torch tensors of
+    shape (H, pitch) bytes holding each camera's rows (8-bit cameras only)."""
+    import torch
+    for k, (b, o, c) in enumerate(zip(base, out, cams)):
+        rb = c.width * c.channels
+        x = b[:, :rb].reshape(c.height, c.width, c.channels).to(torch.float32)
+        g = torch.as_tensor(np.asarray(gains[k], np.float32), device=x.device)
+        y = torch.clamp(torch.round(x * g), 0, 255).to(torch.uint8)
+        o[:, :rb].copy_(y.reshape(c.height, rb))

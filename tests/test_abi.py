@@ -86,6 +86,7 @@ def test_null_arguments_are_rejected():
     assert lib.rt_build_lut(None, None, None, None) == rt.RT_EINVAL
     assert lib.rt_apply(None, None, None, None, None, None) == rt.RT_EINVAL
     assert lib.rt_frameset(None, None, None, None, None, None, None) == rt.RT_EINVAL
+    assert lib.rt_frameset_batch(None, 1, None, None, None, None, None, None) == rt.RT_EINVAL
     assert lib.rt_ctx_sizes(None, None) == rt.RT_EINVAL
     assert lib.rt_ctx_destroy(None) == rt.RT_OK
     assert lib.rt_ctx_check(None) == rt.RT_EINVAL
@@ -99,4 +100,13 @@ def test_null_arguments_are_rejected():
     assert lib.rt_pipe_create(None, 2, None, None, None, None, None) == rt.RT_EINVAL
     assert lib.rt_pipe_submit(None, None, None, None, None, None) == rt.RT_EINVAL
     assert lib.rt_pipe_destroy(None) == rt.RT_OK
+    assert lib.rt_surrogate_features(None, None, None, None) == rt.RT_EINVAL
+    assert lib.rt_estimate_new(None, None, None, None, None) == rt.RT_EINVAL
+    assert lib.rt_surrogate_targets(None, None, None, None, None, None) == rt.RT_EINVAL
+    assert lib.rt_surrogate_select(None, None, None, None, 1e-3, None, None, None, None) == rt.RT_EINVAL
+    assert lib.rt_mlp_forward(None, None, 1, None, None, None, None) == rt.RT_EINVAL
+    assert lib.rt_mlp_backward(None, None, None, None, None, None, 1, None, None, None, None, None) == rt.RT_EINVAL
+    assert lib.rt_mlp_adam(None, None, None, None, 1, 1e-3, 0.9, 0.999, 1e-8, None) == rt.RT_EINVAL
+    assert lib.rt_mlp_mse(None, None, 1, None, None) == rt.RT_EINVAL
+    assert lib.rt_gather_rows(None, 1, None, 1, None, None) == rt.RT_EINVAL
     assert lib.rt_ctx_apply_times(None, None, 0, None) == rt.RT_EINVAL

@@ -1,0 +1,133 @@
+"""GPU parity of rt_frameset_batch: frame-sets of a subset of the rings of one
+context.  Every step is compared with the oracle (bit-exact statistics,
+tables, pixels; parameters bitwise), each ring's results in the mix equal
+those of the ring served alone, and nothing of an inactive camera changes."""
+import numpy as np
+import pytest
+
+from tests.gpu_helpers import compare_step, oracle_cams, oracle_opts, rt_cams, say, assert_ints_equal
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_1910_03517_amd import rt, synth  # noqa: E402
+
+PER_CAMERA = ("band_hist", "band_sums", "whole_hist", "whole_sums", "params", "valid", "lut8", "q16", "weights")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    rt.load()
+
+
+def three_rings():
+    cams = (synth.ring_of(3, 320, 96, ring=0) + synth.ring_of(2, 256, 64, ring=1)
+            + synth.ring_of(4, 200, 50, ring=2))
+    return synth.RigSpec("3 rings: 3x320x96 + 2x256x64 + 4x200x50 rgb8", 9, cams)
+
+
+def ring_indices(spec, r):
+    return sorted((i for i, c in enumerate(spec.cams) if c.ring == r), key=lambda i: spec.cams[i].pos)
+
+
+def cam_mask(idx):
+    m = 0
+    for i in idx:
+        m |= 1 << i
+    return m
+
+
+def slice_host(h, idx, w_max):
+    out = {n: h[n][idx] for n in PER_CAMERA}
+    out["weights"] = out["weights"][:, :w_max]
+    return out
+
+
+def ring_frames(spec, r, t):
+    frames = synth.rig_frames(spec, t, drift=True)
+    return [frames[i] for i in ring_indices(spec, r)]
+
+
+def test_batched_rings_match_oracle_and_alone():
+    spec = three_rings()
+    cams = rt_cams(spec.cams)
+    opts = rt.Options(n_blocks=4, band_width=16, smoothing=True)
+    mix = rt.Rig(cams, opts)
+    rings = spec.rings
+    idx = {r: ring_indices(spec, r) for r in rings}
+    sub_cams = {r: [cams[i] for i in idx[r]] for r in rings}
+    alone = {r: rt.Rig(sub_cams[r], opts) for r in rings}
+    in_mix = mix.alloc_frames()
+    out_mix = mix.alloc_frames()
+    t_of = {r: 0 for r in rings}
+    prev = {r: (None, None) for r in rings}
+    schedule = [(0, 1, 2), (0,), (1, 2), (1,), (0, 1, 2), (2,), (0, 2)]
+    for step, active in enumerate(schedule):
+        say(f"case: batch step {step} rings {active}")
+        before = mix.bufs.host()
+        out_before = mix.download(out_mix)
+        frames_in = [None] * len(cams)
+        frames_out = [None] * len(cams)
+        mask = 0
+        for r in active:
+            fr = ring_frames(spec, r, t_of[r])
+            for n, i in enumerate(idx[r]):
+                raw = np.ascontiguousarray(fr[n]).view(np.uint8).reshape(cams[i].height, cams[i].row_bytes)
+                in_mix[i][:, :cams[i].row_bytes].copy_(torch.from_numpy(raw))
+                frames_in[i], frames_out[i] = in_mix[i], out_mix[i]
+            mask |= cam_mask(idx[r])
+        mix.frameset_batch(mask, frames_in, frames_out)
+        torch.cuda.synchronize()
+        h = mix.bufs.host()
+        outs = mix.download(out_mix)
+        for r in rings:
+            if r in active:
+                continue
+            for i in idx[r]:
+                for n in PER_CAMERA:
+                    assert np.array_equal(h[n][i], before[n][i]), f"inactive camera {i}: {n} changed"
+                assert np.array_equal(outs[i], out_before[i]), f"inactive camera {i}: output changed"
+        for r in active:
+            fr = ring_frames(spec, r, t_of[r])
+            co, oo = oracle_cams(sub_cams[r]), oracle_opts(opts)
+            g = slice_host(h, idx[r], max(c.width for c in sub_cams[r]))
+            g["out"] = [outs[i] for i in idx[r]]
+            res = compare_step(co, oo, fr, g, *prev[r])
+            assert res["bitwise"], f"step {step} ring {r}: params not bitwise equal"
+            prev[r] = (res["ref"]["params"], res["ref"]["valid"])
+            # The same frame-set served alone, in its own context.
+            a = alone[r]
+            dev = a.upload(fr)
+            o = a.alloc_frames()
+            a.frameset(dev, o)
+            torch.cuda.synchronize()
+            ha = a.bufs.host()
+            for n in PER_CAMERA:
+                ga = ha[n] if n != "weights" else ha[n][:, :g["weights"].shape[1]]
+                assert np.array_equal(ga, g[n]), f"step {step} ring {r}: {n} differs alone vs mix"
+            for x, y in zip(a.download(o), g["out"]):
+                assert np.array_equal(x, y), f"step {step} ring {r}: output differs alone vs mix"
+            t_of[r] += 1
+    for a in alone.values():
+        a.close()
+    mix.close()
+
+
+def test_batch_mask_validation():
+    spec = three_rings()
+    cams = rt_cams(spec.cams)
+    rig = rt.Rig(cams, rt.Options(n_blocks=2))
+    dev = rig.alloc_frames()
+    out = rig.alloc_frames()
+    ring0 = cam_mask(ring_indices(spec, 0))
+    for bad, needle in [(0, "empty"), (ring0 & ~1, "ring"), (1 << len(cams), "beyond")]:
+        with pytest.raises(rt.RtError, match=needle):
+            rig.frameset_batch(bad, dev, out)
+    frames = [d if (ring0 >> i) & 1 else None for i, d in enumerate(dev)]
+    with pytest.raises(rt.RtError, match="NULL"):
+        rig.frameset_batch(ring0 | cam_mask(ring_indices(spec, 1)), frames, out)
+    rig.frameset_batch(ring0, frames, [o if f is not None else None for o, f in zip(out, frames)])
+    rig.check()
+    rig.close()

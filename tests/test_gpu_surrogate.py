@@ -1,0 +1,251 @@
+"""GPU parity of the learned surrogate against its oracle, the fallback rule,
+and what training gains over the untrained network and over no correction.
+
+Features, plain estimates, targets and selections are compared bit for bit
+(the selection takes the GPU's float32 predictions on both sides, so the
+integer decision is made on the same numbers); forward, backward and Adam
+against the binary64 oracle within 1e-4 relative (per-tensor norm)."""
+import numpy as np
+import pytest
+
+from tests.gpu_helpers import oracle_cams, oracle_opts, rt_cams, say
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle import ringcorr as rc  # noqa: E402
+from oracle import surrogate as sg  # noqa: E402
+from paper_1910_03517_amd import rt, synth  # noqa: E402
+from paper_1910_03517_amd import surrogate as su  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    rt.load()
+
+
+def small_rig(seed=0, n=4, W=352, H=160, nb=8):
+    spec = synth.RigSpec("surrogate", 21, [synth.CamSpec(W, H, 3, 8, 0, p) for p in range(n)]
+                         + [synth.CamSpec(96, 64, 1, 12, 1, p) for p in range(2)])
+    cams = rt_cams(spec.cams)
+    opts = rt.Options(n_blocks=nb, band_width=16)
+    return spec, cams, opts
+
+
+def rel(a, b):
+    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+
+
+def stats_of(rig, dev):
+    b = rig.bufs
+    rt.rt_stats(rig.ctx, dev, b.band_hist, b.band_sums, b.whole_hist, b.whole_sums)
+    torch.cuda.synchronize()
+    return rig.bufs.host()
+
+
+def test_features_estimate_new_targets_bit_exact():
+    say("case: surrogate features / estimate_new / targets, 4x352x160 + 2x96x64")
+    spec, cams, opts = small_rig()
+    rig = rt.Rig(cams, opts)
+    frames = synth.rig_frames(spec, 0)
+    dev = rig.upload(frames)
+    h = stats_of(rig, dev)
+    ws = su.Workspace(rig.sizes)
+    b = rig.bufs
+    rt.rt_surrogate_features(rig.ctx, b.band_hist, b.whole_hist, ws.X)
+    rt.rt_estimate_new(rig.ctx, b.band_sums, ws.p_new, ws.status)
+    rt.rt_surrogate_targets(rig.ctx, ws.p_new, ws.status, ws.T, ws.mask)
+    torch.cuda.synchronize()
+    co, oo = oracle_cams(cams), oracle_opts(opts)
+    Xo = sg.all_features(co, oo, h["band_hist"].astype(np.int64), h["whole_hist"].astype(np.int64))
+    assert np.array_equal(ws.X.cpu().numpy().view(np.uint32), Xo.view(np.uint32))
+    p_o, st_o = sg.estimate_new(co, oo, h["band_sums"].astype(np.int64))
+    assert np.array_equal(ws.status.cpu().numpy(), st_o)
+    assert np.array_equal(ws.p_new.cpu().numpy().view(np.uint64), p_o.view(np.uint64))
+    T = ws.T.cpu().numpy()
+    mask = ws.mask.cpu().numpy()
+    for k, c in enumerate(co):
+        for s in (0, 1):
+            for j in range(opts.n_blocks):
+                u = (k * 2 + s) * opts.n_blocks + j
+                ok = c.channels == 3 and np.all(st_o[k, s, j] == sg.NEW)
+                assert mask[u] == ok
+                assert np.array_equal(T[u], sg.targets(p_o[k, s, j]).astype(np.float32))
+    rig.close()
+
+
+def test_forward_backward_adam_against_fp64():
+    say("case: mlp forward/backward/adam vs fp64, batch 96")
+    rng = np.random.default_rng(3)
+    P = synth.mlp_init(5)
+    P["b1"] = rng.normal(0, 0.05, 256).astype(np.float32)     # non-zero biases exercise the epilogues
+    P["b3"] = rng.normal(0, 0.05, 6).astype(np.float32)
+    n = 96
+    X = rng.uniform(0, 0.2, (n, 576)).astype(np.float32)
+    X[:, rng.integers(0, 576, 200)] = 0.0
+    T = rng.normal(1.0, 0.3, (n, 6)).astype(np.float32)
+    w = rt.MlpTensors(P)
+    g = rt.MlpTensors(None)
+    e = dict(device="cuda", dtype=torch.float32)
+    Xd, Td = torch.as_tensor(X, device="cuda"), torch.as_tensor(T, device="cuda")
+    H1, H2, Y = torch.zeros((n, 256), **e), torch.zeros((n, 256), **e), torch.zeros((n, 6), **e)
+    dY, dZ1, dZ2 = torch.zeros((n, 6), **e), torch.zeros((n, 256), **e), torch.zeros((n, 256), **e)
+    rt.rt_mlp_forward(w, Xd, n, H1, H2, Y)
+    rt.rt_mlp_backward(w, Xd, H1, H2, Y, Td, n, g, dY, dZ1, dZ2)
+    loss = torch.zeros(1, **e)
+    rt.rt_mlp_mse(Y, Td, n, loss)
+    torch.cuda.synchronize()
+    Po = {k: v.astype(np.float64) for k, v in P.items()}
+    Yo, H1o, H2o = sg.forward(Po, X)
+    Go = sg.backward(Po, X, H1o, H2o, Yo, T)
+    assert rel(Y.cpu().numpy(), Yo) < 1e-4
+    assert rel(H1.cpu().numpy(), H1o) < 1e-4 and rel(H2.cpu().numpy(), H2o) < 1e-4
+    assert abs(loss.item() - sg.mse(Yo, T)) <= 1e-4 * sg.mse(Yo, T)
+    gh = g.host()
+    for k in rt.MlpTensors.NAMES:
+        assert rel(gh[k], Go[k]) < 1e-4, k
+    # Adam from the GPU's own gradient on both sides, two steps.
+    m, v = rt.MlpTensors(None), rt.MlpTensors(None)
+    Pa, Ma, Va = dict(Po), {k: np.zeros_like(x) for k, x in Po.items()}, {k: np.zeros_like(x) for k, x in Po.items()}
+    Gd = {k: x.astype(np.float64) for k, x in gh.items()}
+    for step in (1, 2):
+        rt.rt_mlp_adam(w, g, m, v, step, 1e-3)
+        Pa, Ma, Va = sg.adam(Pa, Gd, Ma, Va, step, 1e-3, 0.9, 0.999, 1e-8)
+    torch.cuda.synchronize()
+    wh = w.host()
+    for k in rt.MlpTensors.NAMES:
+        assert np.max(np.abs(wh[k] - Pa[k])) < 1e-6 + 1e-5 * np.max(np.abs(Pa[k])), k
+
+
+def test_select_and_state_update_bit_exact():
+    say("case: surrogate select vs oracle on GPU predictions")
+    spec, cams, opts = small_rig(nb=4)
+    for smoothing in (False, True):
+        opts_s = rt.Options(n_blocks=4, band_width=16, smoothing=smoothing)
+        rig = rt.Rig(cams, opts_s)
+        frames = synth.rig_frames(spec, 1)
+        dev = rig.upload(frames)
+        stats_of(rig, dev)
+        ws = su.Workspace(rig.sizes)
+        b = rig.bufs
+        rt.rt_estimate_new(rig.ctx, b.band_sums, ws.p_new, ws.status)
+        torch.cuda.synchronize()
+        p_new, st = ws.p_new.cpu().numpy(), ws.status.cpu().numpy()
+        # Predictions: exact for some units, off by more than tol for others, NaN for one.
+        U = ws.n
+        pred = np.zeros((U, 6), np.float32)
+        for k in range(len(cams)):
+            for s in (0, 1):
+                for j in range(4):
+                    u = (k * 2 + s) * 4 + j
+                    pred[u] = sg.targets(p_new[k, s, j]).astype(np.float32)
+        pred[1::3] += np.float32(5e-3)
+        pred[2, 0] = np.nan
+        prev_p = np.random.default_rng(4).uniform(0.8, 1.2, b.params.shape)
+        prev_v = (np.arange(b.valid.numel()).reshape(b.valid.shape) % 2).astype(np.uint8)
+        b.params.copy_(torch.as_tensor(prev_p, device="cuda"))
+        b.valid.copy_(torch.as_tensor(prev_v, device="cuda"))
+        ws.Y.copy_(torch.as_tensor(pred, device="cuda"))
+        rt.rt_surrogate_select(rig.ctx, ws.Y, ws.p_new, ws.status, 1e-3, b.params, b.valid, ws.used, ws.residual)
+        torch.cuda.synchronize()
+        co, oo = oracle_cams(cams), oracle_opts(opts_s)
+        chosen, used, res = sg.select(pred, p_new, st, co, 1e-3)
+        ref_p, ref_v = sg.temporal(oo, chosen, st, prev_p, prev_v)
+        assert np.array_equal(ws.used.cpu().numpy(), used)
+        assert np.array_equal(ws.residual.cpu().numpy(), res)
+        assert np.array_equal(b.params.cpu().numpy().view(np.uint64), ref_p.view(np.uint64))
+        assert np.array_equal(b.valid.cpu().numpy(), ref_v)
+        assert used.sum() > 0 and used.sum() < U
+        rig.close()
+
+
+def test_corrupted_weights_fall_back_to_plain():
+    """NaN and huge weights: every unit falls back, and the frame-set equals the plain path's."""
+    say("case: surrogate fallback with corrupted weights")
+    spec, cams, opts = small_rig()
+    frames = synth.rig_frames(spec, 2)
+    plain = rt.Rig(cams, opts)
+    dev = plain.upload(frames)
+    out_p = plain.alloc_frames()
+    plain.frameset(dev, out_p)
+    for corrupt in ("nan", "huge"):
+        P = synth.mlp_init(1)
+        if corrupt == "nan":
+            P["w3"][3, 2] = np.nan
+        else:
+            P["w1"] *= 1e30
+        rig = rt.Rig(cams, opts)
+        ws = su.Workspace(rig.sizes)
+        sur = su.Surrogate(rt.MlpTensors(P), tol=1e-3)
+        out = rig.alloc_frames()
+        sur.frameset(rig, dev, out, plain.bufs.whole_hist, ws)
+        torch.cuda.synchronize()
+        assert ws.used.sum().item() == 0
+        for a, c in zip(rig.download(out), plain.download(out_p)):
+            assert np.array_equal(a, c)
+        assert np.array_equal(rig.bufs.params.cpu().numpy(), plain.bufs.params.cpu().numpy())
+        rig.close()
+    plain.close()
+
+
+def test_training_gain_over_untrained_and_no_correction():
+    """Train on seeded synthetic rigs with the library's kernels; on held-out rigs
+    the trained network's parameter error is far below the untrained network's
+    and below no correction at all, and correcting with the network's raw output
+    lowers the seam gradient cost relative to the uncorrected frames."""
+    say("case: surrogate training gain, small rigs")
+    opts = rt.Options(n_blocks=8, band_width=16)
+    train = su.build_dataset("small", n_bases=6, draws_per_base=40, seed=1, opts=opts)
+    held = su.build_dataset("small", n_bases=2, draws_per_base=10, seed=99, opts=opts)
+    assert train.X.shape[0] > 10000
+    tr = su.Trainer(synth.mlp_init(7), lr=1e-3, batch=256, seed=0)
+    untrained = rt.MlpTensors(synth.mlp_init(7))
+    losses = [tr.epoch(train) for _ in range(6)]
+    assert losses[-1] < 0.2 * losses[0], losses
+    Th = held.T.cpu().numpy().astype(np.float64)
+
+    def err(Y):
+        return float(np.sqrt(np.mean((Y.astype(np.float64) - Th) ** 2)))
+
+    e_trained = err(su.predict(tr.w, held.X).cpu().numpy())
+    e_untrained = err(su.predict(untrained, held.X).cpu().numpy())
+    identity = np.tile(np.array([1, 1, 1, 0, 0, 0], np.float32), (Th.shape[0], 1))
+    e_identity = err(identity)
+    say(f"held-out rmse: trained {e_trained:.4f} untrained {e_untrained:.4f} identity {e_identity:.4f}")
+    assert e_trained < 0.2 * e_untrained and e_trained < 0.5 * e_identity
+
+    # Seam cost on a held-out frame-set corrected with the network's raw parameters.
+    specs = su.rig_specs("small")
+    spec = synth.RigSpec("held", 1099, specs)
+    cams = rt_cams(specs)
+    frames = synth.rig_frames(spec, 0, seed=123)
+    rig = rt.Rig(cams, opts)
+    dev = rig.upload(frames)
+    ws = su.Workspace(rig.sizes)
+    b = rig.bufs
+    rt.rt_stats(rig.ctx, dev, b.band_hist, b.band_sums, b.whole_hist, b.whole_sums)
+    rt.rt_surrogate_features(rig.ctx, b.band_hist, b.whole_hist, ws.X)
+    Y = su.predict(tr.w, ws.X).cpu().numpy()
+    co, oo = oracle_cams(cams), oracle_opts(opts)
+    params = np.zeros((len(cams), 2, opts.n_blocks, 3, 2))
+    for k in range(len(cams)):
+        for s in (0, 1):
+            for j in range(opts.n_blocks):
+                u = (k * 2 + s) * opts.n_blocks + j
+                params[k, s, j, :, 0] = Y[u, :3].astype(np.float64)
+                params[k, s, j, :, 1] = 255.0 * Y[u, 3:].astype(np.float64)
+    lut8, q16 = rc.build_luts(co, oo, params)
+    corrected = [rc.apply_camera(f, c, oo, lut8[k], q16[k]) for k, (f, c) in enumerate(zip(frames, co))]
+    plain = rc.frameset(co, oo, frames)["out"]
+    K = len(cams)
+
+    def ring_cost(fr):
+        return np.mean([rc.seam_cost(fr[k], fr[(k + 1) % K], 8) for k in range(K)])
+
+    c_unc, c_net, c_plain = ring_cost(frames), ring_cost(corrected), ring_cost(plain)
+    say(f"seam cost: uncorrected {c_unc:.2f} network {c_net:.2f} plain {c_plain:.2f}")
+    assert c_net < c_unc
+    rig.close()
