@@ -188,17 +188,27 @@ rt_status rt_frameset(rt_ctx* ctx, const void* const* frames, void* const* out_f
                       const rt_params_buf* state, const rt_lut_buf* lut, void* stream);
 
 /* rt_frameset over a subset of the cameras, for serving several rigs from one
- * context: bit k of `active` selects camera k.  Only the active cameras'
- * frames are read (frames[k], out_frames[k] of the others may be NULL), and
- * only their outputs, band and whole statistics, state entries, tables and
- * weights are written; everything of the inactive cameras is left as it was.
- * A seam's estimate reads both of its bands, so `active` must hold every
- * camera of a ring or none of them (RT_EINVAL otherwise, also for an empty
- * mask or bits at or beyond n_cams).  With all cameras active this is
- * rt_frameset. */
+ * context: bit k of `active` selects camera k (this call only; the
+ * context's own set, see rt_ctx_set_active, is not consulted).  Only the
+ * active cameras' frames are read (frames[k], out_frames[k] of the others may
+ * be NULL), and only their outputs, band and whole statistics, state
+ * entries, tables and weights are written; everything of the inactive
+ * cameras is left as it was.  A seam's estimate reads both of its bands, so
+ * `active` must hold every camera of a ring or none of them (RT_EINVAL
+ * otherwise, also for an empty mask or bits at or beyond n_cams).  With all
+ * cameras active this is rt_frameset. */
 rt_status rt_frameset_batch(rt_ctx* ctx, uint64_t active, const void* const* frames, void* const* out_frames,
                             const rt_stats_buf* stats, const rt_params_buf* state, const rt_lut_buf* lut,
                             void* stream);
+
+/* Restricts every later call on ctx that takes frames or runs per-camera
+ * kernels (all entry points above and below except rt_frameset_batch) to the
+ * cameras in `active`, with the semantics rt_frameset_batch documents: the
+ * others' frame pointers may be NULL and nothing of theirs is read or
+ * written.  Same validity rules as rt_frameset_batch.  After rt_ctx_create
+ * every camera is active.  The set is read when a call enqueues its kernels,
+ * so work already enqueued (and captured graphs) keep the set they had. */
+rt_status rt_ctx_set_active(rt_ctx* ctx, uint64_t active);
 
 /* Two-stream frame-set pipeline.  rt_pipe_submit enqueues one frame-set: on
  * the pipeline's own stream E the band statistics, estimate and tables of

@@ -70,15 +70,6 @@ constexpr int kDefaultTileRows = 32;
 
 bool aligned(const void* p, uintptr_t a) { return ((uintptr_t)p % a) == 0; }
 
-rt_status check_frames(const rt_ctx* ctx, const void* const* frames, const char* name) {
-  if (!frames) return fail(RT_EINVAL, "%s is NULL", name);
-  for (int k = 0; k < ctx->n_cams; ++k) {
-    if (!frames[k]) return fail(RT_EINVAL, "%s[%d] is NULL", name, k);
-    if (!aligned(frames[k], 16)) return fail(RT_EINVAL, "%s[%d] is not 16-byte aligned", name, k);
-  }
-  return RT_OK;
-}
-
 // Frames of the cameras in `active` only (the others may be NULL).
 rt_status check_frames_masked(const rt_ctx* ctx, uint64_t active, const void* const* frames, const char* name) {
   if (!frames) return fail(RT_EINVAL, "%s is NULL", name);
@@ -90,13 +81,18 @@ rt_status check_frames_masked(const rt_ctx* ctx, uint64_t active, const void* co
   return RT_OK;
 }
 
+// Frames of the context's active cameras.
+rt_status check_frames(const rt_ctx* ctx, const void* const* frames, const char* name) {
+  return check_frames_masked(ctx, ctx->geo.active, frames, name);
+}
+
 rt_status check_ptr(const void* p, uintptr_t align, const char* name) {
   if (!p) return fail(RT_EINVAL, "%s is NULL", name);
   if (!aligned(p, align)) return fail(RT_EINVAL, "%s is not %u-byte aligned", name, (unsigned)align);
   return RT_OK;
 }
 
-FramePtrs make_ptrs(const rt_ctx* ctx, const void* const* in, void* const* out, uint64_t active = ~0ull) {
+FramePtrs make_ptrs_masked(const rt_ctx* ctx, const void* const* in, void* const* out, uint64_t active) {
   FramePtrs fp;
   memset(&fp, 0, sizeof fp);
   for (int k = 0; k < ctx->n_cams; ++k) {
@@ -107,7 +103,26 @@ FramePtrs make_ptrs(const rt_ctx* ctx, const void* const* in, void* const* out, 
   return fp;
 }
 
+FramePtrs make_ptrs(const rt_ctx* ctx, const void* const* in, void* const* out) {
+  return make_ptrs_masked(ctx, in, out, ctx->geo.active);
+}
+
 uint64_t all_cams(int n) { return n >= 64 ? ~0ull : ((1ull << n) - 1ull); }
+
+// A non-empty set of whole rings within the context.
+rt_status check_active(const rt_ctx* ctx, uint64_t active) {
+  if (active == 0) return fail(RT_EINVAL, "active is empty");
+  if (active & ~all_cams(ctx->n_cams)) return fail(RT_EINVAL, "active names cameras beyond n_cams = %d", ctx->n_cams);
+  // A seam's estimate reads both of its bands, so a ring is active as a whole.
+  for (int k = 0; k < ctx->n_cams; ++k) {
+    if (!((active >> k) & 1ull)) continue;
+    for (int i = 0; i < ctx->n_cams; ++i)
+      if (ctx->cams[i].ring == ctx->cams[k].ring && !((active >> i) & 1ull))
+        return fail(RT_EINVAL, "active holds camera %d of ring %d but not camera %d of the same ring", k,
+                    ctx->cams[k].ring, i);
+  }
+  return RT_OK;
+}
 
 }  // namespace
 
@@ -153,7 +168,7 @@ static rt_status build_tables(rt_ctx* ctx, int tile_rows) {
   g.alpha = ctx->opts.ema_alpha;
   g.a_min = ctx->opts.a_min;
   g.a_max = ctx->opts.a_max;
-  g.active = all_cams(n_cams);
+  if (g.active == 0) g.active = all_cams(n_cams);
   return RT_OK;
 }
 
@@ -426,7 +441,7 @@ static rt_status frameset_masked(rt_ctx* ctx, uint64_t active, const void* const
   hipStream_t st = (hipStream_t)stream;
   Geo g = ctx->geo;
   g.active = active;
-  const FramePtrs fp = make_ptrs(ctx, frames, out_frames, active);
+  const FramePtrs fp = make_ptrs_masked(ctx, frames, out_frames, active);
   const Bufs b = make_bufs(stats, state, lut);
   hipError_t e = launch_band_stats(g, fp, b, st);
   if (e != hipSuccess) return hip_fail(e, "band statistics");
@@ -438,24 +453,23 @@ static rt_status frameset_masked(rt_ctx* ctx, uint64_t active, const void* const
 rt_status rt_frameset(rt_ctx* ctx, const void* const* frames, void* const* out_frames, const rt_stats_buf* stats,
                       const rt_params_buf* state, const rt_lut_buf* lut, void* stream) {
   if (!ctx) return fail(RT_EINVAL, "ctx is NULL");
-  return frameset_masked(ctx, all_cams(ctx->n_cams), frames, out_frames, stats, state, lut, stream);
+  return frameset_masked(ctx, ctx->geo.active, frames, out_frames, stats, state, lut, stream);
 }
 
 rt_status rt_frameset_batch(rt_ctx* ctx, uint64_t active, const void* const* frames, void* const* out_frames,
                             const rt_stats_buf* stats, const rt_params_buf* state, const rt_lut_buf* lut,
                             void* stream) {
   if (!ctx) return fail(RT_EINVAL, "ctx is NULL");
-  if (active == 0) return fail(RT_EINVAL, "active is empty");
-  if (active & ~all_cams(ctx->n_cams)) return fail(RT_EINVAL, "active names cameras beyond n_cams = %d", ctx->n_cams);
-  // A seam's estimate reads both of its bands, so a ring is active as a whole.
-  for (int k = 0; k < ctx->n_cams; ++k) {
-    if (!((active >> k) & 1ull)) continue;
-    for (int i = 0; i < ctx->n_cams; ++i)
-      if (ctx->cams[i].ring == ctx->cams[k].ring && !((active >> i) & 1ull))
-        return fail(RT_EINVAL, "active holds camera %d of ring %d but not camera %d of the same ring", k,
-                    ctx->cams[k].ring, i);
-  }
+  rt_status r = check_active(ctx, active);
+  if (r != RT_OK) return r;
   return frameset_masked(ctx, active, frames, out_frames, stats, state, lut, stream);
+}
+
+rt_status rt_ctx_set_active(rt_ctx* ctx, uint64_t active) {
+  if (!ctx) return fail(RT_EINVAL, "ctx is NULL");
+  rt_status r = check_active(ctx, active);
+  if (r == RT_OK) ctx->geo.active = active;
+  return r;
 }
 
 rt_status rt_ctx_check(rt_ctx* ctx) {

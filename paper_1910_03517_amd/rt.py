@@ -25,7 +25,7 @@ RT_MAX_CAMS = 64
 CSLOTS, NBINS = 3, 256
 
 EXPORTED = ["rt_ctx_create", "rt_ctx_destroy", "rt_ctx_sizes", "rt_stats", "rt_estimate",
-            "rt_build_lut", "rt_apply", "rt_frameset", "rt_frameset_batch", "rt_ctx_check", "rt_ctx_tune", "rt_ctx_tuning",
+            "rt_build_lut", "rt_apply", "rt_frameset", "rt_frameset_batch", "rt_ctx_set_active", "rt_ctx_check", "rt_ctx_tune", "rt_ctx_tuning",
             "rt_stream_copy", "rt_ctx_timing", "rt_ctx_apply_times", "rt_graph_create", "rt_graph_launch",
             "rt_graph_destroy", "rt_pipe_create", "rt_pipe_submit", "rt_pipe_destroy",
             "rt_surrogate_features", "rt_estimate_new", "rt_surrogate_targets", "rt_surrogate_select",
@@ -100,6 +100,7 @@ def load(path: str = LIB_PATH) -> ct.CDLL:
                                 ct.POINTER(rt_params_buf), ct.POINTER(rt_lut_buf), P]
     lib.rt_frameset_batch.argtypes = [P, ct.c_uint64, ct.POINTER(P), ct.POINTER(P), ct.POINTER(rt_stats_buf),
                                       ct.POINTER(rt_params_buf), ct.POINTER(rt_lut_buf), P]
+    lib.rt_ctx_set_active.argtypes = [P, ct.c_uint64]
     lib.rt_ctx_check.argtypes = [P]
     lib.rt_ctx_tune.argtypes = [P, ct.c_int32, ct.c_int32]
     I = ct.POINTER(ct.c_int32)
@@ -402,6 +403,10 @@ def rt_frameset_batch(ctx, active: int, frames, out_frames, bufs: "Buffers", str
                                     ct.byref(sb), ct.byref(pb), ct.byref(lb), _stream_handle(stream)))
 
 
+def rt_ctx_set_active(ctx, active: int) -> None:
+    _check(load().rt_ctx_set_active(ctx, ct.c_uint64(active)))
+
+
 # ----------------------------------------------------------------------------- convenience
 
 @dataclass(frozen=True)
@@ -551,6 +556,10 @@ class Rig:
         """Frame-set of the cameras in bitmask `active` (whole rings); the
         entries of inactive cameras in frames / out_frames may be None."""
         rt_frameset_batch(self.ctx, active, frames, out_frames, self.bufs, stream)
+
+    def set_active(self, active: int) -> None:
+        """Restrict later calls to the cameras in bitmask `active` (whole rings)."""
+        rt_ctx_set_active(self.ctx, active)
 
     def check(self) -> None:
         rt_ctx_check(self.ctx)

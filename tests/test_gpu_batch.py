@@ -131,3 +131,54 @@ def test_batch_mask_validation():
     rig.frameset_batch(ring0, frames, [o if f is not None else None for o, f in zip(out, frames)])
     rig.check()
     rig.close()
+
+
+def test_context_active_set_separate_calls():
+    """rt_ctx_set_active restricts rt_stats / rt_estimate / rt_build_lut /
+    rt_apply: a ring's results equal the oracle's, the other rings' buffers
+    and outputs stay as they were."""
+    spec = three_rings()
+    cams = rt_cams(spec.cams)
+    opts = rt.Options(n_blocks=3, band_width=24)
+    rig = rt.Rig(cams, opts)
+    dev = rig.upload(synth.rig_frames(spec, 0))
+    out = rig.alloc_frames()
+    rig.frameset(dev, out)
+    torch.cuda.synchronize()
+    r = 2
+    idx = ring_indices(spec, r)
+    mask = cam_mask(idx)
+    before = rig.bufs.host()
+    out_before = rig.download(out)
+    fr = ring_frames(spec, r, 5)
+    for n, i in enumerate(idx):
+        raw = np.ascontiguousarray(fr[n]).view(np.uint8).reshape(cams[i].height, cams[i].row_bytes)
+        dev[i][:, :cams[i].row_bytes].copy_(torch.from_numpy(raw))
+    rig.set_active(mask)
+    fin = [d if (mask >> i) & 1 else None for i, d in enumerate(dev)]
+    fout = [o if (mask >> i) & 1 else None for i, o in enumerate(out)]
+    prev_p, prev_v = before["params"][idx], before["valid"][idx]
+    say("case: set_active ring 2, separate calls")
+    rig.stats(fin, whole=False)
+    rig.estimate()
+    rig.build_lut()
+    rig.apply(fin, fout, whole=True)
+    torch.cuda.synchronize()
+    h = rig.bufs.host()
+    outs = rig.download(out)
+    for i in range(len(cams)):
+        if (mask >> i) & 1:
+            continue
+        for n in PER_CAMERA:
+            assert np.array_equal(h[n][i], before[n][i]), f"inactive camera {i}: {n} changed"
+        assert np.array_equal(outs[i], out_before[i])
+    sub = [cams[i] for i in idx]
+    g = slice_host(h, idx, max(c.width for c in sub))
+    g["out"] = [outs[i] for i in idx]
+    res = compare_step(oracle_cams(sub), oracle_opts(opts), fr, g, prev_p, prev_v)
+    assert res["bitwise"]
+    # The context's set does not leak into rt_frameset_batch, and can be widened again.
+    rig.set_active(cam_mask(range(len(cams))))
+    rig.frameset(dev, out)
+    rig.check()
+    rig.close()

@@ -1,0 +1,120 @@
+"""The server on the device: three rigs in one context, continuously batched.
+Each rig's outputs in the mix equal the oracle's frame-set sequence of that
+rig (bit for bit), and equal the rig served alone; with the surrogate
+(forced to be used wherever eligible) the mix equals the rig alone."""
+import numpy as np
+import pytest
+
+from tests.gpu_helpers import oracle_cams, oracle_opts, rt_cams, say
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle import ringcorr as rc  # noqa: E402
+from paper_1910_03517_amd import rt, synth  # noqa: E402
+from paper_1910_03517_amd.serving import GpuBackend, Server  # noqa: E402
+from paper_1910_03517_amd.surrogate import Surrogate, Workspace  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    rt.load()
+
+
+RIGS = [synth.ring_of(3, 320, 96), synth.ring_of(2, 256, 64), synth.ring_of(4, 200, 48)]
+OPTS = rt.Options(n_blocks=4, band_width=16, smoothing=True)
+N_PER_RIG = [5, 3, 4]
+
+
+def rig_frames(r, t):
+    spec = synth.RigSpec(f"serving rig {r}", 40 + r, RIGS[r])
+    return synth.rig_frames(spec, t, drift=True)
+
+
+def to_device(cams, frames):
+    out = []
+    for c, f in zip(cams, frames):
+        d = torch.zeros((c.height, c.pitch_bytes), dtype=torch.uint8, device="cuda")
+        raw = np.ascontiguousarray(f).view(np.uint8).reshape(c.height, c.row_bytes)
+        d[:, :c.row_bytes].copy_(torch.from_numpy(raw))
+        out.append(d)
+    return out
+
+
+def host_out(cams, outs):
+    res = []
+    for d, c in zip(outs, cams):
+        raw = d[:, :c.row_bytes].cpu().numpy()
+        res.append(np.ascontiguousarray(raw).reshape(c.height, c.width, c.channels))
+    return res
+
+
+def serve(surrogate=None):
+    backend = GpuBackend(RIGS, OPTS, surrogate=surrogate)
+    results = {}
+
+    def on_done(req):
+        cams = [backend.cams[i] for i in backend.idx[req.rig]]
+        results[(req.rig, req.seq)] = host_out(cams, req.out)
+
+    srv = Server(backend, mem_budget=3 * sum(backend.frameset_bytes(r) for r in range(3)),
+                 max_batches_in_flight=2, on_done=on_done)
+    inputs = {}
+    order = [(r, t) for t in range(max(N_PER_RIG)) for r in range(3) if t < N_PER_RIG[r]]
+    for r, t in order:
+        cams = [backend.cams[i] for i in backend.idx[r]]
+        inputs[(r, t)] = to_device(cams, rig_frames(r, t))
+    for r, t in order:
+        req = srv.submit(r, inputs[(r, t)])
+        assert req.seq == t
+        srv.poll()
+    srv.drain(timeout=60)
+    rep = srv.report()
+    say(f"serving report: {rep}")
+    assert rep["done"] == sum(N_PER_RIG), rep
+    assert max(srv.batch_sizes) > 1, "no batching happened"
+    backend.close()
+    return results
+
+
+def test_serving_mix_matches_oracle_and_alone():
+    say("case: serving plain, 3 rigs")
+    results = serve()
+    for r in range(3):
+        cams = rt_cams(RIGS[r])
+        co, oo = oracle_cams(cams), oracle_opts(OPTS)
+        prev_p = prev_v = None
+        alone = rt.Rig(cams, OPTS)
+        for t in range(N_PER_RIG[r]):
+            fr = rig_frames(r, t)
+            ref = rc.frameset(co, oo, fr, prev_p, prev_v)
+            prev_p, prev_v = ref["params"], ref["valid"]
+            dev = alone.upload(fr)
+            out = alone.alloc_frames()
+            alone.frameset(dev, out)
+            got_alone = alone.download(out)
+            for k in range(len(cams)):
+                assert np.array_equal(results[(r, t)][k], ref["out"][k]), f"rig {r} t {t} cam {k} vs oracle"
+                assert np.array_equal(results[(r, t)][k], got_alone[k]), f"rig {r} t {t} cam {k} vs alone"
+        alone.close()
+
+
+def test_serving_surrogate_mix_matches_alone():
+    say("case: serving surrogate, 3 rigs")
+    w = rt.MlpTensors(synth.mlp_init(3))
+    sur = Surrogate(w, tol=1e30)          # use the network wherever a unit is eligible
+    results = serve(sur)
+    for r in range(3):
+        cams = rt_cams(RIGS[r])
+        alone = rt.Rig(cams, OPTS)
+        ws = Workspace(alone.sizes)
+        for t in range(N_PER_RIG[r]):
+            dev = alone.upload(rig_frames(r, t))
+            out = alone.alloc_frames()
+            sur.frameset(alone, dev, out, alone.bufs.whole_hist, ws)
+            got = alone.download(out)
+            for k in range(len(cams)):
+                assert np.array_equal(results[(r, t)][k], got[k]), f"rig {r} t {t} cam {k}"
+        alone.close()
