@@ -12,7 +12,11 @@ repeats.
 
     python bench.py [--gpus 1] [--steps 300] [--warmup 20] [--config rig14]
 
-Prints ONE JSON line.  The roofline figure is for the dominant kernel (the
+Prints ONE JSON line.  After the timed region, two further legs add their
+own objects to it: "surrogate" (the network trained on the device from the
+plain estimator, then its inference path against the plain one) and
+"serving" (three rigs behind the server, paced at 30 fps and saturated).
+The roofline figure is for the dominant kernel (the
 apply pass with fused statistics), timed by events the library records right
 around each of its launches in the timed region, next to the streaming-copy
 ceiling of the same bytes.  The CPU baseline leg times the CPU oracle (test
@@ -36,6 +40,11 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "corrected GPix/s and % HBM roofline; p50/p99 frame-set latency, plain vs surrogate"
 KERNEL_SOURCES = ["dev_common.h", "dev_apply.h", "dev_estimate.h", "k_apply.hip", "rt_internal.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_apply_rig14_traffic.txt")
+
+
+def log(msg: str) -> None:
+    """Progress on stderr (stdout carries only the JSON line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def kernel_hash() -> str:
@@ -113,6 +122,154 @@ def apply_bytes(cams) -> int:
     return sum(2 * c.width * c.height * c.channels * (1 if c.bit_depth == 8 else 2) for c in cams)
 
 
+MLP_FLOP_PER_SAMPLE_STEP = 3 * 2 * (576 * 256 + 256 * 256 + 256 * 6)   # forward + backward (2x forward)
+
+
+def surrogate_leg(args, rig, ins, outs):
+    """Train the surrogate on the device (dataset from the plain estimator on
+    seeded rigs), then time its inference path on the benchmark rig and
+    report how often and how closely it replaces the plain estimate."""
+    import torch
+    from paper_1910_03517_amd import rt, synth
+    from paper_1910_03517_amd import surrogate as sg
+
+    log("surrogate: building the dataset")
+    t0 = time.perf_counter()
+    data = sg.build_dataset("rig14", n_bases=args.sur_bases, draws_per_base=args.sur_draws, seed=0)
+    held = sg.build_dataset("rig14", n_bases=1, draws_per_base=16, seed=1)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    n = int(data.X.shape[0])
+    log(f"surrogate: {n} samples in {t_data:.1f} s; training")
+    tr = sg.Trainer(synth.mlp_init(0), lr=args.sur_lr, batch=1024)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    losses = [tr.epoch(data)]                      # first epoch: warm-up, not timed
+    steps0 = tr.step
+    e0.record()
+    for _ in range(args.sur_epochs - 1):
+        losses.append(tr.epoch(data))
+    e1.record()
+    torch.cuda.synchronize()
+    train_s = e0.elapsed_time(e1) / 1e3
+    samples = (tr.step - steps0) * tr.batch
+    # Held-out residuals (max over the unit's six outputs, normalised units).
+    y = sg.predict(tr.w, held.X)
+    res = (y - held.T).abs().amax(dim=1).cpu().numpy()
+
+    log(f"surrogate: trained, loss {losses[0]:.3g} -> {losses[-1]:.3g}; timing inference")
+    # Inference: the surrogate frame-set on the benchmark rig, eager, against the plain one.
+    sur = sg.Surrogate(tr.w, tol=args.sur_tol)
+    ws = sg.Workspace(rig.sizes)
+    b = rig.bufs
+    px = sum(c.width * c.height for c in rig.cams)
+    nb = len(ins)
+
+    def timed(fn, k):
+        for i in range(5):
+            fn(i)
+        torch.cuda.synchronize()
+        a, z = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for i in range(k):
+            fn(i)
+        z.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(z) / k
+
+    k = max(args.steps // 3, 20)
+    ms_plain = timed(lambda i: rig.frameset(ins[i % nb], outs[i % nb]), k)
+    ms_sur = timed(lambda i: sur.frameset(rig, ins[i % nb], outs[i % nb], b.whole_hist, ws), k)
+    used = ws.used.float().mean().item()
+    r_used = ws.residual[ws.used.bool()]
+    rig.check()
+    return tr.w, {
+        "dataset": {"samples": n, "build_s": round(t_data, 2), "source": "plain estimator on seeded 14x1920x1080 rigs",
+                    "bases": args.sur_bases, "draws_per_base": args.sur_draws},
+        "training": {"epochs": args.sur_epochs, "batch": tr.batch, "lr": args.sur_lr,
+                     "loss_first_epoch": round(losses[0], 7), "loss_last_epoch": round(losses[-1], 7),
+                     "samples_per_s": round(samples / train_s, 1),
+                     "TFLOP_s": round(samples * MLP_FLOP_PER_SAMPLE_STEP / train_s / 1e12, 3),
+                     "fp32_peak_TFLOP_s": 157.3},
+        "held_out_residual": {"p50": float(np.percentile(res, 50)), "p90": float(np.percentile(res, 90)),
+                              "used_at": {str(t): float((res <= t).mean()) for t in (1e-3, 3e-3, 1e-2, 3e-2)}},
+        "inference": {"tol": args.sur_tol, "GPix_s": round(px / (ms_sur / 1e3) / 1e9, 2),
+                      "plain_GPix_s": round(px / (ms_plain / 1e3) / 1e9, 2),
+                      "ms_per_frameset": round(ms_sur, 4), "plain_ms_per_frameset": round(ms_plain, 4),
+                      "used_fraction": round(used, 4),
+                      "max_residual_used": float(r_used.max().item()) if r_used.numel() else None,
+                      "launch": "eager, one stream, both paths"},
+    }
+
+
+def serving_leg(args, base, surrogate_w=None) -> dict:
+    """Three rigs of the benchmark camera ring in one context behind the
+    server: paced (30 fps per rig, exponential jitter of mean 2 ms) and
+    saturated (every frame-set submitted at once)."""
+    import threading
+
+    import torch
+    from paper_1910_03517_amd import synth
+    from paper_1910_03517_amd.serving import GpuBackend, Server
+    from paper_1910_03517_amd.surrogate import Surrogate
+
+    spec = synth.rig14_1080p()
+    n_rigs, pool = 3, 4
+    out = {"rigs": n_rigs, "rig": spec.name, "fps": 30, "jitter_ms": 2.0}
+    for path in ("plain", "surrogate"):
+        if path == "surrogate" and surrogate_w is None:
+            continue
+        sur = Surrogate(surrogate_w, tol=args.sur_tol) if path == "surrogate" else None
+        be = GpuBackend([spec.cams] * n_rigs, surrogate=sur)
+        frames = []
+        for r in range(n_rigs):
+            cams = [be.cams[i] for i in be.idx[r]]
+            per = []
+            for i in range(pool):
+                dev = [torch.zeros((c.height, c.pitch_bytes), dtype=torch.uint8, device="cuda") for c in cams]
+                for d, c, f in zip(dev, cams, base[(r + i) % len(base)]):
+                    raw = np.ascontiguousarray(f).view(np.uint8).reshape(c.height, c.row_bytes)
+                    d[:, :c.row_bytes].copy_(torch.from_numpy(raw))
+                per.append(dev)
+            frames.append(per)
+        torch.cuda.synchronize()
+        fs_bytes = be.frameset_bytes(0)
+        res = {}
+        # Paced: arrivals of each rig at phase + i/30 s + Exp(2 ms), seeded.
+        rng = np.random.default_rng([1910, 5])
+        n_each = int(args.serve_seconds * 30)
+        arrivals = sorted((float(rng.uniform(0, 1 / 30)) + i / 30 + float(rng.exponential(2e-3)), r, i)
+                          for r in range(n_rigs) for i in range(n_each))
+        for mode in ("paced", "saturated"):
+            log(f"serving: {path} {mode}")
+            srv = Server(be, mem_budget=8 * fs_bytes, max_batches_in_flight=3, queue_limit=1 << 20)
+            # warm-up outside the measurement
+            for r in range(n_rigs):
+                srv.submit(r, frames[r][0])
+            srv.drain()
+            srv.finished.clear()
+            srv.batch_sizes.clear()
+            srv.start()
+            if mode == "paced":
+                t_start = time.perf_counter()
+                for t, r, i in arrivals:
+                    dt = t_start + t - time.perf_counter()
+                    if dt > 0:
+                        time.sleep(dt)
+                    srv.submit(r, frames[r][i % pool])
+            else:
+                n_sat = args.serve_saturated
+                for i in range(n_sat):
+                    for r in range(n_rigs):
+                        srv.submit(r, frames[r][i % pool])
+            srv.stop(drain=True)
+            rep = srv.report()
+            res[mode] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in rep.items()}
+        res["offered_GPix_s"] = round(n_rigs * 30 * be.rig_pixels(0) / 1e9, 3)
+        be.close()
+        out[path] = res
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -129,6 +286,15 @@ def main() -> int:
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--depth", type=int, default=2, help="slots of the pipe mode")
     ap.add_argument("--copy-only", action="store_true", help="time the streaming copy of the frame bytes only")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate training/inference leg")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
+    ap.add_argument("--sur-bases", type=int, default=4)
+    ap.add_argument("--sur-draws", type=int, default=112, help="gain draws per base scene (448 units each)")
+    ap.add_argument("--sur-epochs", type=int, default=8)
+    ap.add_argument("--sur-lr", type=float, default=1e-3)
+    ap.add_argument("--sur-tol", type=float, default=1e-2)
+    ap.add_argument("--serve-seconds", type=float, default=2.0)
+    ap.add_argument("--serve-saturated", type=int, default=40, help="frame-sets per rig in the saturated run")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported (the correction of one rig "
@@ -207,6 +373,7 @@ def main() -> int:
         else:
             rig.frameset(ins[i % args.nbuf], outs[i % args.nbuf])
 
+    log(f"timing {args.steps} steps ({args.mode})")
     for i in range(args.warmup):
         step(i)
     torch.cuda.synchronize()
@@ -270,7 +437,13 @@ def main() -> int:
         "roofline": roof,
         "kernel_hash": khash,
     }
+    sur_w = None
+    if not args.no_surrogate and args.config == "rig14":
+        sur_w, out["surrogate"] = surrogate_leg(args, rig, ins, outs)
+    if not args.no_serving and args.config == "rig14":
+        out["serving"] = serving_leg(args, base, sur_w)
     if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(rig_spec, opts)
     rig.close()
     print(json.dumps(out), flush=True)

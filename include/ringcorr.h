@@ -316,13 +316,14 @@ typedef struct {
 
 /* Features of every unit, X float32 [K*2*NB][576] (rows of non-RGB cameras
  * zero), from stats->band_hist (this frame-set) and stats->whole_hist (the
- * whole-frame histograms to use, normally the previous frame-set's). */
+ * whole-frame histograms to use, normally the previous frame-set's); its
+ * sums fields are not read and may be NULL. */
 rt_status rt_surrogate_features(rt_ctx* ctx, const rt_stats_buf* stats, float* X, void* stream);
 
 /* The plain estimate of section 3.1 before the temporal step: p_new f64
  * [K][2][NB][3][2] (a, b) and status i32 [K][2][NB][3]: 1 new estimate, 0 an
  * empty band (the state is kept), 2 no facing band (identity), 3 unused
- * channel slot. */
+ * channel slot.  Reads stats->band_sums only (the other fields may be NULL). */
 rt_status rt_estimate_new(rt_ctx* ctx, const rt_stats_buf* stats, double* p_new, int32_t* status, void* stream);
 
 /* Training targets T float32 [K*2*NB][6] from p_new, and mask u8 [K*2*NB]:

@@ -695,7 +695,8 @@ static rt_status check_mlp(const rt_mlp* m, const char* name) {
 
 rt_status rt_surrogate_features(rt_ctx* ctx, const rt_stats_buf* stats, float* X, void* stream) {
   if (!ctx) return fail(RT_EINVAL, "ctx is NULL");
-  rt_status r = check_stats(stats, true, false);
+  if (!stats) return fail(RT_EINVAL, "stats buffer struct is NULL");
+  rt_status r = check_ptr(stats->band_hist, 4, "band_hist");
   if (r == RT_OK) r = check_ptr(stats->whole_hist, 4, "whole_hist");
   if (r == RT_OK) r = check_ptr(X, 4, "X");
   if (r != RT_OK) return r;
@@ -705,7 +706,8 @@ rt_status rt_surrogate_features(rt_ctx* ctx, const rt_stats_buf* stats, float* X
 
 rt_status rt_estimate_new(rt_ctx* ctx, const rt_stats_buf* stats, double* p_new, int32_t* status, void* stream) {
   if (!ctx) return fail(RT_EINVAL, "ctx is NULL");
-  rt_status r = check_stats(stats, true, false);
+  if (!stats) return fail(RT_EINVAL, "stats buffer struct is NULL");
+  rt_status r = check_ptr(stats->band_sums, 8, "band_sums");
   if (r == RT_OK) r = check_ptr(p_new, 8, "p_new");
   if (r == RT_OK) r = check_ptr(status, 4, "status");
   if (r != RT_OK) return r;

@@ -271,8 +271,7 @@ def rt_surrogate_features(ctx, band_hist, whole_hist, X, stream=None) -> None:
 
 
 def rt_estimate_new(ctx, band_sums, p_new, status, stream=None) -> None:
-    # band_hist is not read; the struct field is set to the sums to pass validation of a non-NULL pointer
-    sb = rt_stats_buf(_p(band_sums), _p(band_sums), None, None)
+    sb = rt_stats_buf(None, _p(band_sums), None, None)
     _check(load().rt_estimate_new(ctx, ct.byref(sb), _p(p_new), _p(status), _stream_handle(stream)))
 
 
