@@ -292,7 +292,7 @@ def main() -> int:
     ap.add_argument("--sur-draws", type=int, default=112, help="gain draws per base scene (448 units each)")
     ap.add_argument("--sur-epochs", type=int, default=8)
     ap.add_argument("--sur-lr", type=float, default=1e-3)
-    ap.add_argument("--sur-tol", type=float, default=1e-2)
+    ap.add_argument("--sur-tol", type=float, default=1e-3)
     ap.add_argument("--serve-seconds", type=float, default=2.0)
     ap.add_argument("--serve-saturated", type=int, default=40, help="frame-sets per rig in the saturated run")
     args = ap.parse_args()

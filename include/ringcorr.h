@@ -297,8 +297,9 @@ rt_status rt_stream_copy(void* dst, const void* src, int64_t bytes, int32_t vec_
  * Input 576 float32 features: regions (0 the whole frame of camera k as
  * passed in - at inference the previous frame-set's, 1 the own band, 2 the
  * facing band of block j, zeros without one) x channels x 64 bins; each bin
- * sums 4 adjacent 256-bins and is divided by the region-channel's sample
- * count in binary64, rounded once to float32 (zeros for an empty region).
+ * sums 4 adjacent 256-bins, times 64, divided by the region-channel's sample
+ * count, in binary64 rounded once to float32 (a density relative to a flat
+ * histogram; zeros for an empty region).
  * Network 576 -> 256 (ReLU) -> 256 (ReLU) -> 6, y = x W + b, row-major
  * weights W[in][out].  Output (a_R, a_G, a_B, b_R/255, b_G/255, b_B/255).
  * Loss: mean of (y - t)^2 over the n x 6 outputs.  The plain estimate judges

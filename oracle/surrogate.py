@@ -11,9 +11,10 @@ Features    576 = 3 regions x 3 channels x 64 bins, region-major, then channel,
             then bin.  Regions: 0 the whole frame of camera k as passed in (the
             previous frame-set's at inference), 1 the unit's own band, 2 the
             facing band of the same block (zeros without one).  Each 64-bin
-            histogram sums 4 adjacent 256-bins and divides by the region's
-            sample count (zeros when it is 0); the quotient is rounded once to
-            float32.
+            histogram sums 4 adjacent 256-bins, times 64, divided by the
+            region's sample count (a density relative to a flat histogram, so
+            that inputs are of order one; zeros when the count is 0), computed
+            in binary64 and rounded once to float32.
 Targets     6 = (a_R, a_G, a_B, b_R/255, b_G/255, b_B/255) of the plain
             estimate of the unit (before any temporal smoothing).
 Network     576 -> 256 (ReLU) -> 256 (ReLU) -> 6, y = x W + b per layer.
@@ -45,14 +46,14 @@ def merge64(h256: np.ndarray) -> np.ndarray:
 
 
 def region_features(h3x256: np.ndarray) -> np.ndarray:
-    """192 float32 features of one region: per channel, 64 merged bins / count."""
+    """192 float32 features of one region: per channel, 64 * merged bins / count."""
     out = np.zeros((3, BINS), np.float32)
     for c in range(3):
         n = int(np.asarray(h3x256[c], dtype=np.int64).sum())
         if n == 0:
             continue
         m = merge64(h3x256[c])
-        out[c] = np.array([np.float32(float(v) / float(n)) for v in m], np.float32)
+        out[c] = np.array([np.float32(float(v) * 64.0 / float(n)) for v in m], np.float32)
     return out.ravel()
 
 

@@ -10,9 +10,14 @@
 // bases stay in registers.  Tables of the tile's block sit in LDS.  The
 // histogram is kept in kRep replicas interleaved bin by bin, lane l updating
 // replica l % kRep, so that lanes of one wave that see the same value mostly
-// hit different LDS words.  At the end of the tile the replicas are summed
-// and added to the camera's whole-frame statistics with global atomics (the
-// whole-frame buffers must be zero before the first tile).
+// hit different LDS words.  In the packed layout (kPack) two adjacent bins
+// share a word as 16-bit halves, which halves the footprint and allows 32
+// replicas: lanes of a half-wave then always hit 32 distinct words in 32
+// distinct banks, whatever the data; the tile table bounds every tile so that
+// no half can reach 2^16 (see the host's tile builder).  At the end of the
+// tile the replicas are summed and added to the camera's whole-frame
+// statistics with global atomics (the whole-frame buffers must be zero before
+// the first tile).
 #pragma once
 
 #include "dev_estimate.h"
@@ -23,9 +28,6 @@ namespace rc {
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned int u32x3 __attribute__((ext_vector_type(3)));
 
-#ifndef RC_APPLY_REP
-#define RC_APPLY_REP 8
-#endif
 #ifndef RC_APPLY_UNROLL
 #define RC_APPLY_UNROLL 4
 #endif
@@ -35,7 +37,9 @@ typedef unsigned int u32x3 __attribute__((ext_vector_type(3)));
 #ifndef RC_STORE_POLICY
 #define RC_STORE_POLICY 2
 #endif
+constexpr bool kPack = RC_APPLY_PACK != 0;  // two 16-bit bins per histogram word
 constexpr int kRep = RC_APPLY_REP;        // histogram replicas
+constexpr int kHistWords = kCS * (kPack ? kNB / 2 : kNB) * kRep;
 constexpr int kUnroll = RC_APPLY_UNROLL;  // rows in flight per thread
 constexpr int kLoadPolicy = RC_LOAD_POLICY;    // cache-policy bits of frame loads
 constexpr int kStorePolicy = RC_STORE_POLICY;  // cache-policy bits of frame stores
@@ -43,7 +47,7 @@ constexpr int kStorePolicy = RC_STORE_POLICY;  // cache-policy bits of frame sto
 struct ApplyLds {
   uint8_t lut[2 * kCS * kNB];          // [side][channel][x]
   int64_t q[4];                        // [side][A, Bq]
-  uint32_t hist[kCS * kNB * kRep];     // [channel][bin][replica]
+  uint32_t hist[kHistWords];           // [channel][bin (pair when packed)][replica]
   unsigned long long red[9 * 16];
 };
 
@@ -86,8 +90,12 @@ __device__ inline uint32_t one_sample(uint32_t x, int c, int p, const PixConst& 
   if (STATS) {
     uint32_t bin = x;
     if (BPS == 2) { bin = x >> shift; bin = bin > 255u ? 255u : bin; }
-    __hip_atomic_fetch_add(&L.hist[(c * kNB + bin) * kRep + hrep], 1u, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (kPack)
+      __hip_atomic_fetch_add(&L.hist[(c * (kNB / 2) + (bin >> 1)) * kRep + hrep], 1u << ((bin & 1u) << 4),
+                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    else
+      __hip_atomic_fetch_add(&L.hist[(c * kNB + bin) * kRep + hrep], 1u, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_WORKGROUP);
     if (BPS == 2) { a1 += x; a2 += (unsigned long long)x * x; }
   }
   if (!WRITE) return 0;
@@ -109,8 +117,8 @@ __device__ void apply_tile(const Geo& g, const FramePtrs& fp, const Bufs& b, int
   constexpr int NW = C * BPS;    // dwords per 4-pixel group
   constexpr int SPG = 4 * C;     // samples per group
   const int tid = threadIdx.x;
-  const Tile t = g.tiles[ti];
-  const DevCam cam = g.cams[t.cam];
+  const Tile t = uniform_tile(g.tiles[ti]);
+  const DevCam cam = uniform_cam(g.cams[t.cam]);
   const int W = cam.width;
   const int half = cam.half;
   const int shift = cam.bit_depth - 8;
@@ -134,7 +142,7 @@ __device__ void apply_tile(const Geo& g, const FramePtrs& fp, const Bufs& b, int
     }
   }
   if (STATS) {
-    for (int i = tid; i < C * kNB * kRep; i += kThreads) L.hist[i] = 0;
+    for (int i = tid; i < kHistWords / kCS * C; i += kThreads) L.hist[i] = 0;
   }
   __syncthreads();
 
@@ -226,18 +234,28 @@ __device__ void apply_tile(const Geo& g, const FramePtrs& fp, const Bufs& b, int
     for (int c = 0; c < kCS; ++c) {
       uint32_t sum = 0;
       if (c < C) {
+        if (kPack) {
+          // Thread tid owns bin tid; the replica order is rotated per bin pair
+          // so that a half-wave reads 16 distinct banks (pairs share a word).
+          const int pair = tid >> 1, sh = (tid & 1) << 4;
+#pragma unroll 8
+          for (int i = 0; i < kRep; ++i)
+            sum += (L.hist[(c * (kNB / 2) + pair) * kRep + ((i + pair) & (kRep - 1))] >> sh) & 0xffffu;
+        } else {
 #pragma unroll
-        for (int r = 0; r < kRep; ++r) sum += L.hist[(c * kNB + tid) * kRep + r];
+          for (int r = 0; r < kRep; ++r) sum += L.hist[(c * kNB + tid) * kRep + r];
+        }
       }
       h[c] = sum;
       if (sum) atomicAdd(&gh[c * kNB + tid], sum);
     }
     const unsigned long long x = (unsigned long long)tid;
+    const unsigned long long h0 = h[0], h1 = h[1], h2 = h[2];
     block_sums(
         (BPS == 2) ? 3 : 3 * C,
-        [&](int i) -> unsigned long long {
+        [=](int i) -> unsigned long long {
           const int c = i / 3, m = i - 3 * (i / 3);
-          const unsigned long long hc = c == 0 ? h[0] : (c == 1 ? h[1] : h[2]);
+          const unsigned long long hc = c == 0 ? h0 : (c == 1 ? h1 : h2);
           if (m == 0) return hc;
           if (BPS == 2) return m == 1 ? a1 : a2;
           return m == 1 ? hc * x : hc * x * x;

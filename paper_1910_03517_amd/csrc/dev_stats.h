@@ -19,7 +19,7 @@ struct StatsLds {
 template <int C, int BPS>
 __device__ void band_unit(const Geo& g, const FramePtrs& fp, const Bufs& b, int k, int s, int j, StatsLds& L) {
   const int tid = threadIdx.x;
-  const DevCam cam = g.cams[k];
+  const DevCam cam = uniform_cam(g.cams[k]);
   for (int i = tid; i < kCS * kNB; i += kThreads) L.hist[i] = 0;
   __syncthreads();
 
@@ -36,8 +36,65 @@ __device__ void band_unit(const Geo& g, const FramePtrs& fp, const Bufs& b, int 
   const __amdgpu_buffer_rsrc_t rin = frame_rsrc(fp.in[k], cam);
   unsigned long long a1 = 0, a2 = 0;           // 16-bit sums
 
-  if (band > 0 && rows > 0) {
-    constexpr int kU = 4;                      // loads in flight per thread
+  // One sample (byte offset o of the row) into the histogram.
+  auto count = [&](uint32_t d, int boff) {
+    if (BPS == 1) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int o = boff + e;
+        if (o >= b0 && o < b1) {
+          const uint32_t v = (d >> (8 * e)) & 0xffu;
+          const int c = (C == 1) ? 0 : o % C;
+          __hip_atomic_fetch_add(&L.hist[c * kNB + v], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const int o = boff + 2 * e;
+        if (o >= b0 && o < b1) {
+          const uint32_t v = (d >> (16 * e)) & 0xffffu;
+          uint32_t bin = v >> shift;
+          bin = bin > 255u ? 255u : bin;
+          __hip_atomic_fetch_add(&L.hist[bin], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          a1 += v;
+          a2 += (unsigned long long)v * v;
+        }
+      }
+    }
+  };
+  // A dword of the band row at byte offset boff; the one crossing the row end
+  // is assembled from single bytes.
+  auto load = [&](int rowoff, int boff) -> uint32_t {
+    if (boff + 4 <= cam.row_bytes) return __builtin_amdgcn_raw_buffer_load_b32(rin, rowoff + boff, 0, 0);
+    uint32_t d = 0;
+    for (int e = 0; boff + e < cam.row_bytes; ++e)
+      d |= (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(rin, rowoff + boff + e, 0, 0) << (8 * e);
+    return d;
+  };
+
+  constexpr int kU = 4;                        // loads in flight per thread
+  if (band > 0 && rows > 0 && dw <= kThreads) {
+    // Thread tid keeps one dword column q of the band and walks the rows
+    // tid / dw, + rstep, ...: no division per load.
+    const int rstep = kThreads / dw;
+    const int q = tid % dw;
+    const int boff = (q0 + q) * 4;
+    constexpr int kR = 2 * kU;                 // a 67-row block of a 32-pixel RGB band in one round
+    if (tid < rstep * dw) {
+      for (int row = tid / dw; row < rows; row += kR * rstep) {
+        uint32_t d[kR];
+#pragma unroll
+        for (int u = 0; u < kR; ++u) {
+          const int r = row + u * rstep;
+          d[u] = r < rows ? load((int)((int64_t)(r0 + r) * cam.pitch), boff) : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < kR; ++u)
+          if (row + u * rstep < rows) count(d[u], boff);
+      }
+    }
+  } else if (band > 0 && rows > 0) {
     const int total = rows * dw;
     for (int base = tid; base < total; base += kU * kThreads) {
       uint32_t d[kU];
@@ -50,46 +107,13 @@ __device__ void band_unit(const Geo& g, const FramePtrs& fp, const Bufs& b, int 
         if (idx < total) {
           const int row = idx / dw;
           const int q = idx - row * dw;
-          const int rowoff = (int)((int64_t)(r0 + row) * cam.pitch);
-          const int boff = (q0 + q) * 4;         // byte offset of the dword in the row
-          boffs[u] = boff;
-          if (boff + 4 <= cam.row_bytes) {
-            d[u] = __builtin_amdgcn_raw_buffer_load_b32(rin, rowoff + boff, 0, 0);
-          } else {                                // dword crossing the row end
-            for (int e = 0; boff + e < cam.row_bytes; ++e)
-              d[u] |= (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(rin, rowoff + boff + e, 0, 0) << (8 * e);
-          }
+          boffs[u] = (q0 + q) * 4;
+          d[u] = load((int)((int64_t)(r0 + row) * cam.pitch), boffs[u]);
         }
       }
 #pragma unroll
-      for (int u = 0; u < kU; ++u) {
-        const int boff = boffs[u];
-        if (boff < 0) continue;
-        if (BPS == 1) {
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int o = boff + e;
-            if (o >= b0 && o < b1) {
-              const uint32_t v = (d[u] >> (8 * e)) & 0xffu;
-              const int c = (C == 1) ? 0 : o % C;
-              __hip_atomic_fetch_add(&L.hist[c * kNB + v], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            }
-          }
-        } else {
-#pragma unroll
-          for (int e = 0; e < 2; ++e) {
-            const int o = boff + 2 * e;
-            if (o >= b0 && o < b1) {
-              const uint32_t v = (d[u] >> (16 * e)) & 0xffffu;
-              uint32_t bin = v >> shift;
-              bin = bin > 255u ? 255u : bin;
-              __hip_atomic_fetch_add(&L.hist[bin], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-              a1 += v;
-              a2 += (unsigned long long)v * v;
-            }
-          }
-        }
-      }
+      for (int u = 0; u < kU; ++u)
+        if (boffs[u] >= 0) count(d[u], boffs[u]);
     }
   }
   __syncthreads();

@@ -1,7 +1,8 @@
 // Kernels of the learned surrogate's MLP (576 -> 256 -> 256 -> 6, ReLU):
 // an FP32 GEMM on the matrix cores with fused bias / ReLU / ReLU-mask
-// epilogues, column sums for bias gradients, the MSE gradient and value,
-// Adam, and a row gather for mini-batches.
+// epilogues and an optional ones row for bias gradients, the MSE gradient and
+// value, Adam over the whole network in one launch, and a row gather for
+// mini-batches.
 #include "rt_internal.h"
 
 namespace rc {
@@ -15,16 +16,22 @@ enum { kEpiNone = 0, kEpiBias = 1, kEpiBiasRelu = 2, kEpiMask = 3 };
 
 // C[M][N] (row stride ldc) = A x B with A(i, k) = A[i * sai + k * sak] and
 // B(k, j) = B[k * sbk + j * sbj] (strides express transposes), then the
-// epilogue: + bias[j]; + bias[j] and ReLU; or times (mask[i][j] > 0).
+// epilogue: + bias[j]; + bias[j] and ReLU; or times (mask[i][j] > 0).  With
+// ones_row non-NULL the product also gets a row M of A equal to all ones, so
+// that row M of the result, the column sums of B, is stored to ones_row[j]
+// (the bias gradient next to a weight gradient).
 // Four waves each own a 32x32 sub-tile and accumulate it with
 // v_mfma_f32_32x32x2_f32: lane l supplies A(i = l % 32, k = l / 32) and
 // B(k = l / 32, j = l % 32) and holds D(i, j) for j = l % 32 and
-// i = 8 (r / 4) + 4 (l / 32) + r % 4 in accumulator register r.
+// i = 8 (r / 4) + 4 (l / 32) + r % 4 in accumulator register r.  The next
+// K-slab is fetched into registers while the current one is multiplied.
 template <int EPI>
 __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const float* __restrict__ A, int64_t sai,
                                               int64_t sak, const float* __restrict__ B, int64_t sbk, int64_t sbj,
                                               float* __restrict__ C, int ldc, const float* __restrict__ bias,
-                                              const float* __restrict__ mask, int ldm) {
+                                              const float* __restrict__ mask, int ldm,
+                                              float* __restrict__ ones_row) {
+  constexpr int kPer = kGemmK * kGemmTile / 256;   // staged elements per thread and operand
   __shared__ float As[kGemmK][kGemmTile + 1];
   __shared__ float Bs[kGemmK][kGemmTile + 1];
   const int tid = threadIdx.x;
@@ -34,18 +41,37 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const float* 
   const int j0 = blockIdx.x * kGemmTile;
   const int wi = (wave >> 1) * 32;
   const int wj = (wave & 1) * 32;
+  const int MA = ones_row ? M + 1 : M;             // rows of A including the ones row
   f32x16 acc;
 #pragma unroll
   for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
 
-  for (int k0 = 0; k0 < K; k0 += kGemmK) {
-    for (int e = tid; e < kGemmK * kGemmTile; e += 256) {
+  float ra[kPer], rb[kPer];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int e = tid + q * 256;
       const int kk = e / kGemmTile, ii = e % kGemmTile;
       const int gi = i0 + ii, gk = k0 + kk, gj = j0 + ii;
-      As[kk][ii] = (gi < M && gk < K) ? A[(int64_t)gi * sai + (int64_t)gk * sak] : 0.0f;
-      Bs[kk][ii] = (gk < K && gj < N) ? B[(int64_t)gk * sbk + (int64_t)gj * sbj] : 0.0f;
+      float a = 0.0f;
+      if (gk < K) {
+        if (gi < M) a = A[(int64_t)gi * sai + (int64_t)gk * sak];
+        else if (gi < MA) a = 1.0f;
+      }
+      ra[q] = a;
+      rb[q] = (gk < K && gj < N) ? B[(int64_t)gk * sbk + (int64_t)gj * sbj] : 0.0f;
+    }
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < K; k0 += kGemmK) {
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int e = tid + q * 256;
+      As[e / kGemmTile][e % kGemmTile] = ra[q];
+      Bs[e / kGemmTile][e % kGemmTile] = rb[q];
     }
     __syncthreads();
+    if (k0 + kGemmK < K) fetch(k0 + kGemmK);
 #pragma unroll
     for (int kk = 0; kk < kGemmK; kk += 2) {
       const float a = As[kk + (lane >> 5)][wi + (lane & 31)];
@@ -59,38 +85,28 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const float* 
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int i = i0 + wi + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-    if (i < M && j < N) {
+    if (j >= N) continue;
+    if (i < M) {
       float v = acc[r];
       if (EPI == kEpiBias || EPI == kEpiBiasRelu) v += bias[j];
       if (EPI == kEpiBiasRelu) v = v > 0.0f ? v : 0.0f;
       if (EPI == kEpiMask) v = mask[(int64_t)i * ldm + j] > 0.0f ? v : 0.0f;
       C[(int64_t)i * ldc + j] = v;
+    } else if (i == M && ones_row) {
+      ones_row[j] = acc[r];
     }
   }
 }
 
 template <int EPI>
 static hipError_t gemm(int M, int N, int K, const float* A, int64_t sai, int64_t sak, const float* B, int64_t sbk,
-                       int64_t sbj, float* C, int ldc, const float* bias, const float* mask, int ldm, hipStream_t st) {
+                       int64_t sbj, float* C, int ldc, const float* bias, const float* mask, int ldm, hipStream_t st,
+                       float* ones_row = nullptr) {
   if (M <= 0 || N <= 0) return hipSuccess;
-  const dim3 grid((N + kGemmTile - 1) / kGemmTile, (M + kGemmTile - 1) / kGemmTile);
+  const int MA = ones_row ? M + 1 : M;
+  const dim3 grid((N + kGemmTile - 1) / kGemmTile, (MA + kGemmTile - 1) / kGemmTile);
   hipLaunchKernelGGL((k_gemm<EPI>), grid, dim3(256), 0, st, M, N, K, A, sai, sak, B, sbk, sbj, C, ldc, bias, mask,
-                     ldm);
-  return hipGetLastError();
-}
-
-// out[j] = sum over rows i < M of A[i * lda + j], j < N; one thread per column.
-__global__ __launch_bounds__(256) void k_colsum(int M, int N, const float* __restrict__ A, int lda,
-                                                float* __restrict__ out) {
-  const int j = blockIdx.x * 256 + threadIdx.x;
-  if (j >= N) return;
-  float s = 0.0f;
-  for (int i = 0; i < M; ++i) s += A[(int64_t)i * lda + j];
-  out[j] = s;
-}
-
-static hipError_t colsum(int M, int N, const float* A, int lda, float* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_colsum, dim3((N + 255) / 256), dim3(256), 0, st, M, N, A, lda, out);
+                     ldm, ones_row);
   return hipGetLastError();
 }
 
@@ -119,21 +135,33 @@ __global__ __launch_bounds__(256) void k_mse(const float* __restrict__ Y, const 
   if (threadIdx.x == 0) out[0] = red[0] / (float)count;
 }
 
-// One Adam step over n parameters with bias-correction factors c1 = 1/(1 - beta1^t),
-// c2 = 1/(1 - beta2^t).
-__global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float* __restrict__ g,
-                                              float* __restrict__ m, float* __restrict__ v, int64_t n, float lr,
-                                              float beta1, float beta2, float eps, float c1, float c2) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
-  const float gi = g[i];
-  const float mi = beta1 * m[i] + (1.0f - beta1) * gi;
-  const float vi = beta2 * v[i] + (1.0f - beta2) * gi * gi;
-  m[i] = mi;
-  v[i] = vi;
+// The six tensors of one network as one index space for a single Adam launch.
+struct AdamSet {
+  float* p[6];
+  const float* g[6];
+  float* m[6];
+  float* v[6];
+  int64_t start[7];   // element e of the set is element e - start[t] of tensor t
+};
+
+// One Adam step over every parameter of the network, with bias-correction
+// factors c1 = 1/(1 - beta1^t), c2 = 1/(1 - beta2^t).
+__global__ __launch_bounds__(256) void k_adam(AdamSet a, float lr, float beta1, float beta2, float eps, float c1,
+                                              float c2) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= a.start[6]) return;
+  int t = 0;
+#pragma unroll
+  for (int q = 1; q < 6; ++q) t += e >= a.start[q];
+  const int64_t i = e - a.start[t];
+  const float gi = a.g[t][i];
+  const float mi = beta1 * a.m[t][i] + (1.0f - beta1) * gi;
+  const float vi = beta2 * a.v[t][i] + (1.0f - beta2) * gi * gi;
+  a.m[t][i] = mi;
+  a.v[t][i] = vi;
   const float mh = mi * c1;
   const float vh = vi * c2;
-  p[i] = p[i] - lr * mh / (__builtin_sqrtf(vh) + eps);
+  a.p[t][i] = a.p[t][i] - lr * mh / (__builtin_sqrtf(vh) + eps);
 }
 
 // dst[r][:] = src[idx[r]][:] for r < n rows of row_len floats.
@@ -164,24 +192,24 @@ hipError_t mlp_backward(const float* const* w, const float* X, const float* H1, 
   const int64_t cnt = (int64_t)n * kMlpOut;
   hipLaunchKernelGGL(k_mse_grad, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, Y, T, cnt, dY);
   hipError_t e = hipGetLastError();
-  // dW3 = H2^T dY, db3 = colsum dY
+  // dW3 = H2^T dY and, as the ones row of the same product, db3 = colsum dY
   if (e == hipSuccess)
-    e = gemm<kEpiNone>(kMlpHid, kMlpOut, n, H2, 1, kMlpHid, dY, kMlpOut, 1, g[4], kMlpOut, nullptr, nullptr, 0, st);
-  if (e == hipSuccess) e = colsum(n, kMlpOut, dY, kMlpOut, g[5], st);
+    e = gemm<kEpiNone>(kMlpHid, kMlpOut, n, H2, 1, kMlpHid, dY, kMlpOut, 1, g[4], kMlpOut, nullptr, nullptr, 0, st,
+                       g[5]);
   // dZ2 = (dY W3^T) * (H2 > 0)
   if (e == hipSuccess)
     e = gemm<kEpiMask>(n, kMlpHid, kMlpOut, dY, kMlpOut, 1, w[4], 1, kMlpOut, dZ2, kMlpHid, nullptr, H2, kMlpHid, st);
   // dW2 = H1^T dZ2, db2 = colsum dZ2
   if (e == hipSuccess)
-    e = gemm<kEpiNone>(kMlpHid, kMlpHid, n, H1, 1, kMlpHid, dZ2, kMlpHid, 1, g[2], kMlpHid, nullptr, nullptr, 0, st);
-  if (e == hipSuccess) e = colsum(n, kMlpHid, dZ2, kMlpHid, g[3], st);
+    e = gemm<kEpiNone>(kMlpHid, kMlpHid, n, H1, 1, kMlpHid, dZ2, kMlpHid, 1, g[2], kMlpHid, nullptr, nullptr, 0, st,
+                       g[3]);
   // dZ1 = (dZ2 W2^T) * (H1 > 0)
   if (e == hipSuccess)
     e = gemm<kEpiMask>(n, kMlpHid, kMlpHid, dZ2, kMlpHid, 1, w[2], 1, kMlpHid, dZ1, kMlpHid, nullptr, H1, kMlpHid, st);
   // dW1 = X^T dZ1, db1 = colsum dZ1
   if (e == hipSuccess)
-    e = gemm<kEpiNone>(kMlpIn, kMlpHid, n, X, 1, kMlpIn, dZ1, kMlpHid, 1, g[0], kMlpHid, nullptr, nullptr, 0, st);
-  if (e == hipSuccess) e = colsum(n, kMlpHid, dZ1, kMlpHid, g[1], st);
+    e = gemm<kEpiNone>(kMlpIn, kMlpHid, n, X, 1, kMlpIn, dZ1, kMlpHid, 1, g[0], kMlpHid, nullptr, nullptr, 0, st,
+                       g[1]);
   return e;
 }
 
@@ -191,13 +219,18 @@ hipError_t mlp_adam(float* const* w, const float* const* g, float* const* m, flo
                             (int64_t)kMlpHid * kMlpOut, kMlpOut};
   const float c1 = (float)(1.0 / (1.0 - pow((double)beta1, (double)step)));
   const float c2 = (float)(1.0 / (1.0 - pow((double)beta2, (double)step)));
+  AdamSet a;
+  a.start[0] = 0;
   for (int t = 0; t < 6; ++t) {
-    hipLaunchKernelGGL(k_adam, dim3((unsigned)((sizes[t] + 255) / 256)), dim3(256), 0, st, w[t], g[t], m[t], v[t],
-                       sizes[t], lr, beta1, beta2, eps, c1, c2);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    a.p[t] = w[t];
+    a.g[t] = g[t];
+    a.m[t] = m[t];
+    a.v[t] = v[t];
+    a.start[t + 1] = a.start[t] + sizes[t];
   }
-  return hipSuccess;
+  hipLaunchKernelGGL(k_adam, dim3((unsigned)((a.start[6] + 255) / 256)), dim3(256), 0, st, a, lr, beta1, beta2, eps,
+                     c1, c2);
+  return hipGetLastError();
 }
 
 hipError_t mlp_mse(const float* Y, const float* T, int n, float* out, hipStream_t st) {

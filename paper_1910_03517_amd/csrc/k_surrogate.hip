@@ -8,8 +8,8 @@
 namespace rc {
 
 // Features of unit u3 = (k * 2 + s) * NB + j: regions (whole frame of camera k
-// as given, own band, facing band), channels, 64 bins = sum of 4 adjacent
-// 256-bins / the region-channel's count, the quotient computed in binary64 and
+// as given, own band, facing band), channels, 64 bins = 64 * (sum of 4
+// adjacent 256-bins) / the region-channel's count, computed in binary64 and
 // rounded once to float32.  Rows of non-RGB cameras are zero.
 __global__ __launch_bounds__(kThreads) void k_features(Geo g, const uint32_t* __restrict__ band_hist,
                                                        const uint32_t* __restrict__ whole_hist, float* __restrict__ X) {
@@ -45,7 +45,7 @@ __global__ __launch_bounds__(kThreads) void k_features(Geo g, const uint32_t* __
     const int r = o / (kCS * 64), c = (o / 64) % kCS, bin = o % 64;
     const uint32_t n = cnt[r][c];
     const uint32_t m = h[r][c][4 * bin] + h[r][c][4 * bin + 1] + h[r][c][4 * bin + 2] + h[r][c][4 * bin + 3];
-    out[o] = n ? (float)((double)m / (double)n) : 0.0f;
+    out[o] = n ? (float)((double)m * 64.0 / (double)n) : 0.0f;
   }
 }
 

@@ -127,7 +127,8 @@ rt_status check_active(const rt_ctx* ctx, uint64_t active) {
 }  // namespace
 
 // Tile table and device tables.  Every block is split into
-// ceil(rows / tile_rows) tiles of equal height (+-1 row); tiles are camera-major.
+// ceil(rows / cap) tiles of equal height (+-1 row), cap = tile_rows or less
+// where the apply pass's packed histogram needs it; tiles are camera-major.
 static rt_status build_tables(rt_ctx* ctx, int tile_rows) {
   const int n_cams = ctx->n_cams;
   const int nb = ctx->opts.n_blocks;
@@ -136,12 +137,13 @@ static rt_status build_tables(rt_ctx* ctx, int tile_rows) {
   ctx->htiles.clear();
   for (int k = 0; k < n_cams; ++k) {
     const int H = ctx->cams[k].height;
+    const int cap = std::min(tile_rows, max_tile_rows(ctx->cams[k].width));
     ctx->hcams[k].tile_begin = (int32_t)ctx->htiles.size();
     for (int j = 0; j < nb; ++j) {
       const int r0 = (int)((int64_t)j * H / nb), r1 = (int)((int64_t)(j + 1) * H / nb);
       const int rows = r1 - r0;
       if (rows <= 0) continue;
-      const int parts = (rows + tile_rows - 1) / tile_rows;
+      const int parts = (rows + cap - 1) / cap;
       for (int p = 0; p < parts; ++p)
         ctx->htiles.push_back(Tile{k, j, r0 + (int)((int64_t)p * rows / parts), r0 + (int)((int64_t)(p + 1) * rows / parts)});
     }

@@ -13,6 +13,27 @@ constexpr int kNB = RT_NBINS;    // histogram bins
 constexpr int kThreads = 256;    // threads of every workgroup
 constexpr int kMlpIn = RT_MLP_IN, kMlpHid = RT_MLP_HID, kMlpOut = RT_MLP_OUT;
 
+// Whole-frame histogram of the apply pass: replicas, and whether two bins
+// share a word as 16-bit halves.
+#ifndef RC_APPLY_PACK
+#define RC_APPLY_PACK 0
+#endif
+#ifndef RC_APPLY_REP
+#define RC_APPLY_REP (RC_APPLY_PACK ? 32 : 8)
+#endif
+static_assert(kThreads % RC_APPLY_REP == 0 && (RC_APPLY_REP & (RC_APPLY_REP - 1)) == 0, "replicas");
+
+// Most rows one apply tile of a camera of this width may hold so that no
+// packed 16-bit counter overflows: replica r is updated by the threads with
+// tid % REP == r, which own the 4-pixel column groups g with g % REP == r, so
+// a tile adds at most 4 * ceil(groups / REP) * rows to one counter.
+__host__ __device__ inline int max_tile_rows(int width) {
+  if (!RC_APPLY_PACK) return 1 << 30;
+  const int groups = (width + 3) / 4;
+  const int per_rep = (groups + RC_APPLY_REP - 1) / RC_APPLY_REP;
+  return 65535 / (4 * per_rep);
+}
+
 // Per-camera geometry as the kernels see it (uploaded once per context).
 struct DevCam {
   int32_t width, height, channels, bit_depth;
@@ -68,9 +89,43 @@ __host__ __device__ inline bool cam_active(const Geo& g, int k) { return (g.acti
 // return zero and stores there are dropped by the hardware range check.
 constexpr int kRsrcWord3 = 0x00020000;   // raw dword access on gfx9-family parts
 
+// Values the caller knows to be the same in every lane of the wave, moved to
+// scalar registers.  Table entries read from global memory land in vector
+// registers; without this a buffer resource built from them would be
+// non-uniform and every access through it would be wrapped in a loop over
+// the distinct values.
+__device__ inline int32_t uniform(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ inline int64_t uniform(int64_t v) {
+  const uint64_t u = (uint64_t)v;
+  return (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(u >> 32)) << 32) |
+                   (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)u));
+}
+template <typename T>
+__device__ inline T* uniform_ptr(T* p) {
+  return reinterpret_cast<T*>(uniform((int64_t)reinterpret_cast<uintptr_t>(p)));
+}
+
+__device__ inline DevCam uniform_cam(const DevCam& c) {
+  DevCam u;
+  u.width = uniform(c.width); u.height = uniform(c.height); u.channels = uniform(c.channels);
+  u.bit_depth = uniform(c.bit_depth); u.bps = uniform(c.bps); u.band = uniform(c.band); u.half = uniform(c.half);
+  u.row_bytes = uniform(c.row_bytes);
+  u.face_cam[0] = uniform(c.face_cam[0]); u.face_cam[1] = uniform(c.face_cam[1]);
+  u.face_side[0] = uniform(c.face_side[0]); u.face_side[1] = uniform(c.face_side[1]);
+  u.tile_begin = uniform(c.tile_begin); u.tile_end = uniform(c.tile_end);
+  u.pitch = uniform(c.pitch);
+  return u;
+}
+
+__device__ inline Tile uniform_tile(const Tile& t) {
+  return Tile{uniform(t.cam), uniform(t.block), uniform(t.r0), uniform(t.r1)};
+}
+
+// p and cam must be uniform over the wave (see uniform_cam).
 __device__ inline __amdgpu_buffer_rsrc_t frame_rsrc(const void* p, const DevCam& cam) {
   const int64_t bytes = (int64_t)(cam.height - 1) * cam.pitch + cam.row_bytes;
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, kRsrcWord3);
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(uniform_ptr(p)), (short)0, uniform((int32_t)bytes),
+                                           kRsrcWord3);
 }
 
 // Index of a (camera, side, block, channel) unit in the caller layouts.

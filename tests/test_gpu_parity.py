@@ -313,3 +313,24 @@ def test_graph_replays_match_eager(pipelined):
     for g in graphs:
         g.close()
     rig.close()
+
+
+@pytest.mark.parametrize("channels,bit_depth", [(3, 8), (1, 16)])
+def test_whole_histogram_counters_do_not_overflow(channels, bit_depth):
+    """A flat 8192-wide frame puts every sample of a tile into one bin; with
+    tile_rows 4096 no counter of the apply pass's histogram may wrap (with the
+    packed 16-bit layout the tile builder splits the 300-row block)."""
+    say(f"case: flat 8192x300 c{channels} b{bit_depth}, tile_rows 4096")
+    W, H = 8192, 300
+    spec = [synth.CamSpec(W, H, channels, bit_depth, 0, 0)]
+    cams = rt_cams(spec)
+    opts = rt.Options(n_blocks=1)
+    rig = rt.Rig(cams, opts)
+    rig.tune(4096, 0)
+    dt = np.uint8 if bit_depth == 8 else np.uint16
+    frame = np.full((H, W, channels), 200 if bit_depth == 8 else 51234, dt)
+    dev = rig.upload([frame])
+    out = rig.alloc_frames()
+    g = gpu_chain_separate(rig, dev, out)
+    compare_step(oracle_cams(cams), oracle_opts(opts), [frame], g)
+    rig.close()

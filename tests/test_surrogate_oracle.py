@@ -22,13 +22,15 @@ def test_merge_and_region_features_bruteforce():
     for c in range(3):
         n = h[c].sum()
         for b in range(64):
-            ref = 0.0 if n == 0 else np.float32(sum(int(h[c, 4 * b + i]) for i in range(4)) / n)
+            ref = 0.0 if n == 0 else np.float32(64 * sum(int(h[c, 4 * b + i]) for i in range(4)) / n)
             assert f[c, b] == ref
-    assert abs(f[0].astype(np.float64).sum() - 1.0) < 1e-5 and np.all(f[1] == 0)
+    assert abs(f[0].astype(np.float64).sum() - 64.0) < 64e-5 and np.all(f[1] == 0)
+    flat = np.full((3, 256), 5, np.int64)
+    assert np.all(sg.region_features(flat) == 1.0)            # a flat histogram has density 1 everywhere
     one = np.zeros((3, 256), np.int64)
     one[2, 21] = 7
     g = sg.region_features(one).reshape(3, 64)
-    assert g[2, 5] == 1.0 and g.sum() == 1.0
+    assert g[2, 5] == 64.0 and g.sum() == 64.0
 
 
 def test_unit_feature_layout_and_facing():
@@ -41,8 +43,8 @@ def test_unit_feature_layout_and_facing():
     bh[2, 0, 0, :, 200] = 1               # facing band (camera 2 left) -> bin 50
     x = sg.unit_features(cams, opts, bh, wh, 1, 1, 0).reshape(3, 3, 64)
     for c in range(3):
-        assert x[0, c, 2] == 1 and x[1, c, 25] == 1 and x[2, c, 50] == 1
-    assert x.sum() == 9
+        assert x[0, c, 2] == 64 and x[1, c, 25] == 64 and x[2, c, 50] == 64
+    assert x.sum() == 9 * 64
     x_end = sg.unit_features(cams, opts, bh, wh, 2, 1, 0).reshape(3, 3, 64)   # open chain end: no facing band
     assert np.all(x_end[2] == 0)
     X = sg.all_features(cams + [rc.Camera(8, 8, 1, 12, ring=1)], opts, np.concatenate([bh, bh[:1]]),
