@@ -1,13 +1,18 @@
-// Apply kernel of section 3.1, weights read from the caller's table.  With statistics, each tile leaves its input histogram in
-// context scratch for the whole-frame reduction.
+// Apply kernel of section 3.1, weights read from the caller's table.  With
+// statistics, each tile adds its input histogram and sums to the camera's
+// whole-frame statistics with atomics.
 #include "dev_apply.h"
 
 namespace rc {
 
 // Workgroups stride over the tiles (one tile each when the grid equals the
 // tile count).  Tiles are independent: no workgroup waits for another.
+#ifndef RC_APPLY_WAVES
+#define RC_APPLY_WAVES 1
+#endif
 template <bool WRITE, bool STATS>
-__global__ __launch_bounds__(kThreads) void k_apply(Geo g, FramePtrs fp, Bufs b) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(RC_APPLY_WAVES)))
+void k_apply(Geo g, FramePtrs fp, Bufs b) {
   __shared__ ApplyLds L;
   for (int ti = blockIdx.x; ti < g.n_tiles; ti += gridDim.x) {
     if (!cam_active(g, g.tiles[ti].cam)) continue;   // uniform over the workgroup
