@@ -31,6 +31,9 @@ typedef unsigned int u32x3 __attribute__((ext_vector_type(3)));
 #ifndef RC_APPLY_UNROLL
 #define RC_APPLY_UNROLL 4
 #endif
+#ifndef RC_APPLY_DIRECT
+#define RC_APPLY_DIRECT 1     // evaluate 8-bit maps from their Q16 pairs instead of the LDS tables
+#endif
 #ifndef RC_LOAD_POLICY
 #define RC_LOAD_POLICY 2      // non-temporal: every frame byte is touched exactly once
 #endif
@@ -82,9 +85,22 @@ struct PixConst {
   uint32_t w[4], iw[4];   // weight and 256 - weight
   int lb[4];              // table base of the pixel's side
   int64_t qa[4], qb[4];   // 16-bit map of the pixel's side
+  int32_t da[4][3];       // direct 8-bit map of the pixel's side: A and Bq + 2^15 per channel
+  int32_t dc[4][3];
 };
 
-template <int BPS, bool WRITE, bool STATS>
+// The 8-bit table entry f(x) = clamp((A x + Bq + 2^15) >> 16, 0, 255) can be
+// evaluated directly in 32-bit integers, bit for bit equal to the table, when
+// |A| < 2^23 (a 24-bit multiply) and A x + Bq + 2^15 stays inside int32 for
+// x in [0, 255].  The check is made once per tile on its six (A, Bq) pairs.
+__device__ inline bool direct_ok(int64_t A, int64_t Bq) {
+  if (A >= (1 << 23) || A < -(1 << 23)) return false;
+  const int64_t c = Bq + 32768, e = 255 * A + c;
+  const int64_t lo = c < e ? c : e, hi = c < e ? e : c;
+  return lo >= INT32_MIN && hi <= INT32_MAX;
+}
+
+template <int BPS, bool WRITE, bool STATS, bool DIRECT = false>
 __device__ inline uint32_t one_sample(uint32_t x, int c, int p, const PixConst& pc, ApplyLds& L, int hrep,
                                       int shift, uint32_t maxv, unsigned long long& a1, unsigned long long& a2) {
   if (STATS) {
@@ -100,7 +116,13 @@ __device__ inline uint32_t one_sample(uint32_t x, int c, int p, const PixConst& 
   }
   if (!WRITE) return 0;
   uint32_t f;
-  if (BPS == 1) {
+  if (BPS == 1 && DIRECT) {
+    // da holds a sign-extended 24-bit value (see direct_ok), so this is a 24-bit multiply.
+    const int32_t a24 = (int32_t)((uint32_t)pc.da[p][c] << 8) >> 8;
+    int32_t y = (a24 * (int32_t)x + pc.dc[p][c]) >> 16;
+    y = y < 0 ? 0 : (y > 255 ? 255 : y);
+    f = (uint32_t)y;
+  } else if (BPS == 1) {
     f = L.lut[pc.lb[p] + c * kNB + x];
   } else {
     int64_t y = (pc.qa[p] * (int64_t)x + pc.qb[p] + 32768) >> 16;
@@ -112,7 +134,7 @@ __device__ inline uint32_t one_sample(uint32_t x, int c, int p, const PixConst& 
 
 // Tile ti of the context.  WTAB: weights from the caller's table (true) or
 // from their closed form (false); both give the same integers.
-template <int C, int BPS, bool WRITE, bool STATS, bool WTAB>
+template <int C, int BPS, bool WRITE, bool STATS, bool WTAB, bool DIRECT>
 __device__ void apply_tile(const Geo& g, const FramePtrs& fp, const Bufs& b, int ti, ApplyLds& L) {
   constexpr int NW = C * BPS;    // dwords per 4-pixel group
   constexpr int SPG = 4 * C;     // samples per group
@@ -128,7 +150,18 @@ __device__ void apply_tile(const Geo& g, const FramePtrs& fp, const Bufs& b, int
   // Stage the tables of both sides of the tile's block; clear the histogram.
   const int64_t u_left = unit_index(t.cam, 0, t.block, 0, g.n_blocks);
   const int64_t u_right = unit_index(t.cam, 1, t.block, 0, g.n_blocks);
-  if (WRITE) {
+  int32_t dA[2][kCS], dC[2][kCS];    // direct 8-bit maps, uniform over the tile
+  if (WRITE && DIRECT) {
+#pragma unroll
+    for (int sd = 0; sd < 2; ++sd)
+#pragma unroll
+      for (int c = 0; c < kCS; ++c) {
+        const int64_t u = (sd ? u_right : u_left) + c;
+        dA[sd][c] = uniform((int32_t)b.q16[u * 2]);
+        dC[sd][c] = uniform((int32_t)(b.q16[u * 2 + 1] + 32768));
+      }
+  }
+  if (WRITE && !DIRECT) {
     if (BPS == 1) {
       constexpr int DW = C * kNB / 4;   // dwords of one side's tables
       for (int i = tid; i < 2 * DW; i += kThreads) {
@@ -168,6 +201,13 @@ __device__ void apply_tile(const Geo& g, const FramePtrs& fp, const Bufs& b, int
       pc.iw[p] = 256u - w;
       pc.lb[p] = side * kCS * kNB;
       if (BPS == 2 && WRITE) { pc.qa[p] = L.q[side * 2]; pc.qb[p] = L.q[side * 2 + 1]; }
+      if (DIRECT && WRITE) {
+#pragma unroll
+        for (int c = 0; c < kCS; ++c) {
+          pc.da[p][c] = side ? dA[1][c] : dA[0][c];
+          pc.dc[p][c] = side ? dC[1][c] : dC[0][c];
+        }
+      }
     }
     const int cbyte = col0 * C * BPS;
 
@@ -190,7 +230,7 @@ __device__ void apply_tile(const Geo& g, const FramePtrs& fp, const Bufs& b, int
               uint32_t x;
               if (BPS == 1) x = (d[u][i >> 2] >> (8 * (i & 3))) & 0xffu;
               else x = (d[u][i >> 1] >> (16 * (i & 1))) & 0xffffu;
-              const uint32_t y = one_sample<BPS, WRITE, STATS>(x, c, p, pc, L, hrep, shift, maxv, a1, a2);
+              const uint32_t y = one_sample<BPS, WRITE, STATS, DIRECT>(x, c, p, pc, L, hrep, shift, maxv, a1, a2);
               if (WRITE) {
                 if (BPS == 1) o[i >> 2] |= y << (8 * (i & 3));
                 else o[i >> 1] |= y << (16 * (i & 1));
@@ -212,7 +252,7 @@ __device__ void apply_tile(const Geo& g, const FramePtrs& fp, const Bufs& b, int
             uint32_t x;
             if (BPS == 1) x = __builtin_amdgcn_raw_buffer_load_b8(rin, off + i, 0, 0);
             else x = __builtin_amdgcn_raw_buffer_load_b16(rin, off + 2 * i, 0, 0);
-            const uint32_t y = one_sample<BPS, WRITE, STATS>(x, c, p, pc, L, hrep, shift, maxv, a1, a2);
+            const uint32_t y = one_sample<BPS, WRITE, STATS, DIRECT>(x, c, p, pc, L, hrep, shift, maxv, a1, a2);
             if (WRITE) {
               if (BPS == 1) __builtin_amdgcn_raw_buffer_store_b8((uint8_t)y, rout, off + i, 0, 0);
               else __builtin_amdgcn_raw_buffer_store_b16((uint16_t)y, rout, off + 2 * i, 0, 0);
@@ -267,12 +307,32 @@ __device__ void apply_tile(const Geo& g, const FramePtrs& fp, const Bufs& b, int
   }
 }
 
+// Whether the tile's six 8-bit maps can be evaluated directly (uniform).
+__device__ inline bool tile_direct(const Geo& g, const Bufs& b, int ti) {
+  const Tile t = uniform_tile(g.tiles[ti]);
+  bool ok = true;
+#pragma unroll
+  for (int sd = 0; sd < 2; ++sd)
+#pragma unroll
+    for (int c = 0; c < kCS; ++c) {
+      const int64_t u = unit_index(t.cam, sd, t.block, c, g.n_blocks);
+      ok = ok && direct_ok(uniform(b.q16[u * 2]), uniform(b.q16[u * 2 + 1]));
+    }
+  return ok;
+}
+
 template <bool WRITE, bool STATS, bool WTAB>
 __device__ inline void apply_tile_dispatch(const Geo& g, const FramePtrs& fp, const Bufs& b, int ti, ApplyLds& L) {
-  const DevCam& cam = g.cams[g.tiles[ti].cam];
-  if (cam.bps == 2) apply_tile<1, 2, WRITE, STATS, WTAB>(g, fp, b, ti, L);
-  else if (cam.channels == 3) apply_tile<3, 1, WRITE, STATS, WTAB>(g, fp, b, ti, L);
-  else apply_tile<1, 1, WRITE, STATS, WTAB>(g, fp, b, ti, L);
+  const DevCam cam = uniform_cam(g.cams[uniform(g.tiles[ti].cam)]);
+  if (cam.bps == 2) apply_tile<1, 2, WRITE, STATS, WTAB, false>(g, fp, b, ti, L);
+  else if (WRITE && STATS && RC_APPLY_DIRECT && tile_direct(g, b, ti)) {
+    // Measured on MI355X: faster than the LDS tables when the pass also
+    // builds the histogram (the LDS is then busy with its atomics), slower
+    // for the apply alone.
+    if (cam.channels == 3) apply_tile<3, 1, WRITE, STATS, WTAB, true>(g, fp, b, ti, L);
+    else apply_tile<1, 1, WRITE, STATS, WTAB, true>(g, fp, b, ti, L);
+  } else if (cam.channels == 3) apply_tile<3, 1, WRITE, STATS, WTAB, false>(g, fp, b, ti, L);
+  else apply_tile<1, 1, WRITE, STATS, WTAB, false>(g, fp, b, ti, L);
 }
 
 }  // namespace rc

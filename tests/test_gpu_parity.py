@@ -334,3 +334,27 @@ def test_whole_histogram_counters_do_not_overflow(channels, bit_depth):
     g = gpu_chain_separate(rig, dev, out)
     compare_step(oracle_cams(cams), oracle_opts(opts), [frame], g)
     rig.close()
+
+
+def test_huge_gains_use_the_tables():
+    """Gains whose Q16 slope needs more than 24 bits (a up to a_max = 1000)
+    cannot be evaluated directly in 32-bit integers; those tiles must take the
+    table path and still match the oracle bit for bit."""
+    say("case: huge gains, a_max 1000")
+    rng = np.random.default_rng(77)
+    W, H = 128, 64
+    spec = [synth.CamSpec(W, H, 3, 8, 0, p) for p in range(2)]
+    f0 = np.full((H, W, 3), 100, np.uint8)
+    f0[::7, ::5, :] = 101                          # nearly flat: tiny but non-zero spread
+    f1 = rng.integers(0, 256, (H, W, 3)).astype(np.uint8)
+    cams = rt_cams(spec)
+    opts = rt.Options(n_blocks=2, band_width=16, a_max=1000.0)
+    rig = rt.Rig(cams, opts)
+    dev = rig.upload([f0, f1])
+    out = rig.alloc_frames()
+    g = gpu_chain_separate(rig, dev, out)
+    assert np.abs(g["q16"][..., 0]).max() >= (1 << 23), "the case must exceed the direct range"
+    compare_step(oracle_cams(cams), oracle_opts(opts), [f0, f1], g)
+    rig.frameset(dev, out)
+    rig.check()
+    rig.close()
