@@ -272,11 +272,14 @@ rt_status rt_ctx_tune(rt_ctx* ctx, int32_t tile_rows, int32_t grid);
 /* Current knobs and the resulting number of apply tiles (any pointer may be NULL). */
 rt_status rt_ctx_tuning(const rt_ctx* ctx, int32_t* tile_rows, int32_t* grid, int32_t* n_tiles);
 
-/* Instrumentation: with slots > 0 every later apply kernel launch of this
- * context (rt_apply, rt_stats with whole-frame statistics, rt_frameset) is
- * bracketed by two HIP events on its stream, kept in a ring of `slots`
- * entries; slots = 0 turns it off.  Synchronizes the device. */
-rt_status rt_ctx_timing(rt_ctx* ctx, int32_t slots);
+/* Instrumentation: with slots > 0, every `every`-th later apply kernel launch
+ * of this context (rt_apply, rt_stats with whole-frame statistics,
+ * rt_frameset, rt_pipe_submit; the first one included) is bracketed by two HIP
+ * events on its stream, kept in a ring of `slots` entries; slots = 0 turns it
+ * off.  Each recorded event pair costs the stream a few microseconds, so a
+ * stride above 1 keeps the timed work close to the untimed.  every >= 1.
+ * Synchronizes the device. */
+rt_status rt_ctx_timing(rt_ctx* ctx, int32_t slots, int32_t every);
 
 /* Durations in milliseconds of the last min(max_n, recorded, slots) apply
  * kernel launches, oldest first, into ms[]; *n_out receives the count.  Waits

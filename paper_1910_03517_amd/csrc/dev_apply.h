@@ -80,9 +80,11 @@ __device__ inline void store_group(__amdgpu_buffer_rsrc_t r, int off, const uint
   }
 }
 
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
 // Per-pixel constants of a thread's group.
 struct PixConst {
-  uint32_t w[4], iw[4];   // weight and 256 - weight
+  uint32_t wp[4];         // Q8 weight pair: (256 - w) in the low half, w in the high half
   int lb[4];              // table base of the pixel's side
   int64_t qa[4], qb[4];   // 16-bit map of the pixel's side
   int32_t da[4][3];       // direct 8-bit map of the pixel's side: A and Bq + 2^15 per channel
@@ -115,13 +117,15 @@ __device__ inline uint32_t one_sample(uint32_t x, int c, int p, const PixConst& 
     if (BPS == 2) { a1 += x; a2 += (unsigned long long)x * x; }
   }
   if (!WRITE) return 0;
-  uint32_t f;
+  uint32_t f, xf;
   if (BPS == 1 && DIRECT) {
     // da holds a sign-extended 24-bit value (see direct_ok), so this is a 24-bit multiply.
+    // clamp(v >> 16, 0, 255) << 16 == clamp(v, 0, 2^24 - 1) & 0xffff0000 for the
+    // arithmetic shift, so f lands in the high half of (x, f) directly.
     const int32_t a24 = (int32_t)((uint32_t)pc.da[p][c] << 8) >> 8;
-    int32_t y = (a24 * (int32_t)x + pc.dc[p][c]) >> 16;
-    y = y < 0 ? 0 : (y > 255 ? 255 : y);
-    f = (uint32_t)y;
+    int32_t v = a24 * (int32_t)x + pc.dc[p][c];
+    v = v < 0 ? 0 : (v > 0xffffff ? 0xffffff : v);
+    xf = ((uint32_t)v & 0xffff0000u) | x;
   } else if (BPS == 1) {
     f = L.lut[pc.lb[p] + c * kNB + x];
   } else {
@@ -129,7 +133,9 @@ __device__ inline uint32_t one_sample(uint32_t x, int c, int p, const PixConst& 
     y = y < 0 ? 0 : (y > (int64_t)maxv ? (int64_t)maxv : y);
     f = (uint32_t)y;
   }
-  return (pc.iw[p] * x + pc.w[p] * f + 128u) >> 8;
+  // ((256 - w) x + w f + 128) >> 8 as one dot product of (x, f) with (256 - w, w).
+  if (!(BPS == 1 && DIRECT)) xf = x | (f << 16);
+  return __builtin_amdgcn_udot2(__builtin_bit_cast(u16x2, xf), __builtin_bit_cast(u16x2, pc.wp[p]), 128u, false) >> 8;
 }
 
 // Tile ti of the context.  WTAB: weights from the caller's table (true) or
@@ -197,8 +203,7 @@ __device__ void apply_tile(const Geo& g, const FramePtrs& fp, const Bufs& b, int
       const int side = col < half ? 0 : 1;
       uint32_t w = 0;
       if (WRITE && p < npx) w = WTAB ? (uint32_t)wrow[col] : blend_weight(W, col);
-      pc.w[p] = w;
-      pc.iw[p] = 256u - w;
+      pc.wp[p] = (256u - w) | (w << 16);
       pc.lb[p] = side * kCS * kNB;
       if (BPS == 2 && WRITE) { pc.qa[p] = L.q[side * 2]; pc.qb[p] = L.q[side * 2 + 1]; }
       if (DIRECT && WRITE) {

@@ -7,10 +7,30 @@ namespace rc {
 
 constexpr int kWave = 64;
 
+// v moved by one DPP row operation (both 32-bit halves from the same source
+// lane); lanes without a source lane, or outside row_mask, get 0.
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ inline unsigned long long dpp_u64(unsigned long long v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, CTRL, ROW_MASK, 0xf, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), CTRL, ROW_MASK, 0xf, false);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+// Sum of v over the 64 lanes of the wave (all lanes active), returned to every
+// lane.  Inclusive prefix sums within each row of 16 lanes (row_shr 1, 2, 4,
+// 8), then the last lane of row 0 added to rows 1 and 3 (row_bcast:15) and the
+// last lane of row 1 to rows 2 and 3 (row_bcast:31): lane 63 holds the total.
+// DPP moves stay in the vector ALU, unlike lane shuffles through the LDS.
 __device__ inline unsigned long long wave_sum_u64(unsigned long long v) {
-#pragma unroll
-  for (int m = kWave / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m, kWave);
-  return v;
+  v += dpp_u64<0x111>(v);          // row_shr:1
+  v += dpp_u64<0x112>(v);          // row_shr:2
+  v += dpp_u64<0x114>(v);          // row_shr:4
+  v += dpp_u64<0x118>(v);          // row_shr:8
+  v += dpp_u64<0x142, 0xa>(v);     // row_bcast:15 into rows 1 and 3
+  v += dpp_u64<0x143, 0xc>(v);     // row_bcast:31 into rows 2 and 3
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 63);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 63);
+  return ((unsigned long long)hi << 32) | lo;
 }
 
 // Workgroup sums of n 64-bit quantities (n <= 16), one after the other to

@@ -20,8 +20,10 @@ template <int C, int BPS>
 __device__ void band_unit(const Geo& g, const FramePtrs& fp, const Bufs& b, int k, int s, int j, StatsLds& L) {
   const int tid = threadIdx.x;
   const DevCam cam = uniform_cam(g.cams[k]);
-  for (int i = tid; i < kCS * kNB; i += kThreads) L.hist[i] = 0;
-  __syncthreads();
+  auto clear = [&]() {
+    for (int i = tid; i < kCS * kNB; i += kThreads) L.hist[i] = 0;
+    __syncthreads();
+  };
 
   const int r0 = (int)((int64_t)j * cam.height / g.n_blocks);
   const int r1 = (int)((int64_t)(j + 1) * cam.height / g.n_blocks);
@@ -81,20 +83,28 @@ __device__ void band_unit(const Geo& g, const FramePtrs& fp, const Bufs& b, int 
     const int q = tid % dw;
     const int boff = (q0 + q) * 4;
     constexpr int kR = 2 * kU;                 // a 67-row block of a 32-pixel RGB band in one round
-    if (tid < rstep * dw) {
-      for (int row = tid / dw; row < rows; row += kR * rstep) {
-        uint32_t d[kR];
+    const bool active = tid < rstep * dw;
+    uint32_t d[kR];
+    auto fetch = [&](int row) {
 #pragma unroll
-        for (int u = 0; u < kR; ++u) {
-          const int r = row + u * rstep;
-          d[u] = r < rows ? load((int)((int64_t)(r0 + r) * cam.pitch), boff) : 0u;
-        }
+      for (int u = 0; u < kR; ++u) {
+        const int r = row + u * rstep;
+        d[u] = r < rows ? load((int)((int64_t)(r0 + r) * cam.pitch), boff) : 0u;
+      }
+    };
+    // The first round of loads is in flight while the histogram is cleared.
+    if (active) fetch(tid / dw);
+    clear();
+    if (active) {
+      for (int row = tid / dw; row < rows; row += kR * rstep) {
+        if (row != tid / dw) fetch(row);
 #pragma unroll
         for (int u = 0; u < kR; ++u)
           if (row + u * rstep < rows) count(d[u], boff);
       }
     }
   } else if (band > 0 && rows > 0) {
+    clear();
     const int total = rows * dw;
     for (int base = tid; base < total; base += kU * kThreads) {
       uint32_t d[kU];
@@ -115,6 +125,8 @@ __device__ void band_unit(const Geo& g, const FramePtrs& fp, const Bufs& b, int 
       for (int u = 0; u < kU; ++u)
         if (boffs[u] >= 0) count(d[u], boffs[u]);
     }
+  } else {
+    clear();
   }
   __syncthreads();
 

@@ -30,7 +30,9 @@ struct rt_ctx {
   // Optional timing of the apply kernel: events recorded right before and
   // after each apply launch, in a ring of n_timing slots.
   int n_timing = 0;
+  int timing_every = 1;
   int64_t n_timed = 0;
+  int64_t n_applies = 0;
   std::vector<hipEvent_t> ev_begin, ev_end;
   bool capturing = false;   // no timing events inside a captured graph
   int64_t generation = 0;   // bumped whenever device tables are rebuilt
@@ -358,6 +360,7 @@ static Bufs make_bufs(const rt_stats_buf* s, const rt_params_buf* p, const rt_lu
 static hipError_t timed_apply(rt_ctx* ctx, const Geo& g, const FramePtrs& fp, const Bufs& b, bool write,
                               bool stats, hipStream_t st) {
   if (ctx->n_timing <= 0 || ctx->capturing) return launch_apply(g, fp, b, write, stats, st);
+  if (ctx->n_applies++ % ctx->timing_every != 0) return launch_apply(g, fp, b, write, stats, st);
   const int slot = (int)(ctx->n_timed % ctx->n_timing);
   hipError_t e = hipEventRecord(ctx->ev_begin[slot], st);
   if (e == hipSuccess) e = launch_apply(g, fp, b, write, stats, st);
@@ -819,12 +822,15 @@ rt_status rt_gather_rows(const float* src, int32_t row_len, const int32_t* idx, 
   return e == hipSuccess ? RT_OK : hip_fail(e, "gather rows");
 }
 
-rt_status rt_ctx_timing(rt_ctx* ctx, int32_t slots) {
+rt_status rt_ctx_timing(rt_ctx* ctx, int32_t slots, int32_t every) {
   if (!ctx) return fail(RT_EINVAL, "ctx is NULL");
   if (slots < 0 || slots > 65536) return fail(RT_EINVAL, "slots %d outside 0..65536", slots);
+  if (every < 1) return fail(RT_EINVAL, "every %d < 1", every);
   hipError_t e = hipDeviceSynchronize();
   if (e != hipSuccess) return hip_fail(e, "synchronize");
   free_timing(ctx);
+  ctx->timing_every = every;
+  ctx->n_applies = 0;
   for (int i = 0; i < slots; ++i) {
     hipEvent_t a = nullptr, b = nullptr;
     e = hipEventCreate(&a);

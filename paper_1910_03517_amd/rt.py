@@ -106,7 +106,7 @@ def load(path: str = LIB_PATH) -> ct.CDLL:
     I = ct.POINTER(ct.c_int32)
     lib.rt_ctx_tuning.argtypes = [P, I, I, I]
     lib.rt_stream_copy.argtypes = [P, P, ct.c_int64, ct.c_int32, P]
-    lib.rt_ctx_timing.argtypes = [P, ct.c_int32]
+    lib.rt_ctx_timing.argtypes = [P, ct.c_int32, ct.c_int32]
     lib.rt_graph_create.argtypes = [P, ct.POINTER(P), ct.POINTER(P), ct.POINTER(rt_lut_buf), ct.POINTER(rt_stats_buf),
                                     ct.POINTER(P), ct.POINTER(rt_lut_buf), ct.POINTER(rt_stats_buf),
                                     ct.POINTER(rt_params_buf), ct.POINTER(P)]
@@ -344,8 +344,8 @@ class Graph:
             pass
 
 
-def rt_ctx_timing(ctx, slots: int) -> None:
-    _check(load().rt_ctx_timing(ctx, slots))
+def rt_ctx_timing(ctx, slots: int, every: int = 1) -> None:
+    _check(load().rt_ctx_timing(ctx, slots, every))
 
 
 def rt_ctx_apply_times(ctx, max_n: int) -> list[float]:

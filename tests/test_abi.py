@@ -94,7 +94,7 @@ def test_null_arguments_are_rejected():
     assert lib.rt_ctx_tune(None, 8, 0) == rt.RT_EINVAL
     assert lib.rt_ctx_tuning(None, None, None, None) == rt.RT_EINVAL
     assert lib.rt_stream_copy(None, None, 16, 16, None) == rt.RT_EINVAL
-    assert lib.rt_ctx_timing(None, 4) == rt.RT_EINVAL
+    assert lib.rt_ctx_timing(None, 4, 1) == rt.RT_EINVAL
     assert lib.rt_graph_create(None, None, None, None, None, None, None, None, None, None) == rt.RT_EINVAL
     assert lib.rt_graph_launch(None, None) == rt.RT_EINVAL
     assert lib.rt_graph_destroy(None) == rt.RT_OK
