@@ -321,6 +321,7 @@ def main() -> int:
                     help="time every n-th apply launch of the timed region with HIP events")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate training/inference leg")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
+    ap.add_argument("--no-vga", action="store_true", help="skip the 1x640x480 per-call leg")
     ap.add_argument("--sur-bases", type=int, default=4)
     ap.add_argument("--sur-draws", type=int, default=112, help="gain draws per base scene (448 units each)")
     ap.add_argument("--sur-epochs", type=int, default=30)
@@ -485,7 +486,7 @@ def main() -> int:
         "roofline": roof,
         "kernel_hash": khash,
     }
-    if args.config == "rig14":
+    if args.config == "rig14" and not args.no_vga:
         log("vga calls")
         out["vga"] = vga_leg()
     sur_w = None
