@@ -348,10 +348,15 @@ rt_status rt_surrogate_select(rt_ctx* ctx, const float* Y, const double* p_new, 
 rt_status rt_mlp_forward(const rt_mlp* w, const float* X, int32_t n, float* H1, float* H2, float* Y, void* stream);
 
 /* Gradients of the mean squared error against T [n][6] into `grad`, from the
- * forward pass's X, H1, H2, Y; workspace dY [n][6], dZ1 and dZ2 [n][256]. */
+ * forward pass's X, H1, H2, Y; workspace dY [n][6], dZ1 and dZ2 [n][256].
+ * part (may be NULL): optional float32 workspace of part_floats values; when
+ * given, the two large weight gradients are summed over n in up to 8 slices
+ * (deterministic order), which shares the long reductions among more
+ * workgroups; 8 * 577 * 256 floats always suffice.  The result then differs
+ * from the unsplit one by rounding only. */
 rt_status rt_mlp_backward(const rt_mlp* w, const float* X, const float* H1, const float* H2, const float* Y,
                           const float* T, int32_t n, const rt_mlp* grad, float* dY, float* dZ1, float* dZ2,
-                          void* stream);
+                          float* part, int64_t part_floats, void* stream);
 
 /* One Adam step (step >= 1 counts steps for the bias correction) updating w, m, v. */
 rt_status rt_mlp_adam(const rt_mlp* w, const rt_mlp* grad, const rt_mlp* m, const rt_mlp* v, int32_t step, float lr,
@@ -362,6 +367,27 @@ rt_status rt_mlp_mse(const float* Y, const float* T, int32_t n, float* out, void
 
 /* dst[r] = src[idx[r]] for n rows of row_len floats (mini-batch gather). */
 rt_status rt_gather_rows(const float* src, int32_t row_len, const int32_t* idx, int32_t n, float* dst, void* stream);
+
+/* Workspace of rt_mlp_train for mini-batches of `batch` rows, float32 device
+ * buffers: xb [batch][576], tb [batch][6], h1, h2, dz1, dz2 [batch][256],
+ * y, dy [batch][6]; part / part_floats as for rt_mlp_backward (part may be
+ * NULL). */
+typedef struct {
+  float* xb; float* tb; float* h1; float* h2; float* y; float* dy; float* dz1; float* dz2;
+  float* part; int64_t part_floats;
+} rt_mlp_work;
+
+/* n_steps mini-batch steps of the surrogate's training, enqueued from the
+ * library: step s gathers rows idx[s * batch .. (s + 1) * batch) of X
+ * [n_rows][576] and T [n_rows][6] (device int32 indices, each < n_rows), runs
+ * the forward, the loss (losses[s], device float32), the backward and one Adam
+ * step numbered step0 + s (>= 1).  Exactly the sequence of rt_gather_rows,
+ * rt_mlp_forward, rt_mlp_backward, rt_mlp_adam and rt_mlp_mse calls per step,
+ * without a host round trip between steps. */
+rt_status rt_mlp_train(const rt_mlp* w, const rt_mlp* grad, const rt_mlp* m, const rt_mlp* v, const float* X,
+                       const float* T, int32_t n_rows, const int32_t* idx, int32_t batch, int32_t n_steps,
+                       int32_t step0, float lr, float beta1, float beta2, float eps, const rt_mlp_work* work,
+                       float* losses, void* stream);
 
 /* Static description of a status code. */
 const char* rt_status_str(rt_status s);

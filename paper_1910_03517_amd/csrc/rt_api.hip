@@ -768,17 +768,19 @@ rt_status rt_mlp_forward(const rt_mlp* w, const float* X, int32_t n, float* H1, 
 
 rt_status rt_mlp_backward(const rt_mlp* w, const float* X, const float* H1, const float* H2, const float* Y,
                           const float* T, int32_t n, const rt_mlp* grad, float* dY, float* dZ1, float* dZ2,
-                          void* stream) {
+                          float* part, int64_t part_floats, void* stream) {
   rt_status r = check_mlp(w, "weights");
   if (r == RT_OK) r = check_mlp(grad, "grad");
   const void* ps[8] = {X, H1, H2, Y, T, dY, dZ1, dZ2};
   for (int i = 0; r == RT_OK && i < 8; ++i) r = check_ptr(ps[i], 4, "activation or workspace");
   if (r != RT_OK) return r;
   if (n < 1) return fail(RT_EINVAL, "n < 1");
+  if (part && (!aligned(part, 4) || part_floats < 0)) return fail(RT_EINVAL, "part misaligned or part_floats < 0");
   float *wp[6], *gp[6];
   mlp_ptrs(w, wp);
   mlp_ptrs(grad, gp);
-  hipError_t e = mlp_backward(wp, X, H1, H2, Y, T, n, gp, dY, dZ1, dZ2, (hipStream_t)stream);
+  hipError_t e = mlp_backward(wp, X, H1, H2, Y, T, n, gp, dY, dZ1, dZ2, part, part ? part_floats : 0,
+                              (hipStream_t)stream);
   return e == hipSuccess ? RT_OK : hip_fail(e, "mlp backward");
 }
 
@@ -820,6 +822,49 @@ rt_status rt_gather_rows(const float* src, int32_t row_len, const int32_t* idx, 
   if (row_len < 1 || n < 0) return fail(RT_EINVAL, "row_len < 1 or n < 0");
   hipError_t e = gather_rows(src, row_len, idx, n, dst, (hipStream_t)stream);
   return e == hipSuccess ? RT_OK : hip_fail(e, "gather rows");
+}
+
+rt_status rt_mlp_train(const rt_mlp* w, const rt_mlp* grad, const rt_mlp* m, const rt_mlp* v, const float* X,
+                       const float* T, int32_t n_rows, const int32_t* idx, int32_t batch, int32_t n_steps,
+                       int32_t step0, float lr, float beta1, float beta2, float eps, const rt_mlp_work* work,
+                       float* losses, void* stream) {
+  rt_status r = check_mlp(w, "weights");
+  if (r == RT_OK) r = check_mlp(grad, "grad");
+  if (r == RT_OK) r = check_mlp(m, "m");
+  if (r == RT_OK) r = check_mlp(v, "v");
+  if (r == RT_OK) r = check_ptr(X, 4, "X");
+  if (r == RT_OK) r = check_ptr(T, 4, "T");
+  if (r == RT_OK) r = check_ptr(idx, 4, "idx");
+  if (r == RT_OK) r = check_ptr(losses, 4, "losses");
+  if (r == RT_OK && !work) r = fail(RT_EINVAL, "work is NULL");
+  if (r == RT_OK) {
+    const void* ws[8] = {work->xb, work->tb, work->h1, work->h2, work->y, work->dy, work->dz1, work->dz2};
+    for (int i = 0; r == RT_OK && i < 8; ++i) r = check_ptr(ws[i], 4, "workspace");
+  }
+  if (r != RT_OK) return r;
+  if (n_rows < 1 || batch < 1 || n_steps < 0) return fail(RT_EINVAL, "need n_rows >= 1, batch >= 1, n_steps >= 0");
+  if (step0 < 1) return fail(RT_EINVAL, "step0 must be >= 1");
+  if (!(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f && eps > 0.0f && lr > 0.0f))
+    return fail(RT_EINVAL, "need 0 <= beta < 1, eps > 0, lr > 0");
+  float *wp[6], *gp[6], *mp[6], *vp[6];
+  mlp_ptrs(w, wp);
+  mlp_ptrs(grad, gp);
+  mlp_ptrs(m, mp);
+  mlp_ptrs(v, vp);
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = hipSuccess;
+  for (int s = 0; e == hipSuccess && s < n_steps; ++s) {
+    const int32_t* ix = idx + (int64_t)s * batch;
+    e = gather_rows(X, kMlpIn, ix, batch, work->xb, st);
+    if (e == hipSuccess) e = gather_rows(T, kMlpOut, ix, batch, work->tb, st);
+    if (e == hipSuccess) e = mlp_forward(wp, work->xb, batch, work->h1, work->h2, work->y, st);
+    if (e == hipSuccess)
+      e = mlp_backward(wp, work->xb, work->h1, work->h2, work->y, work->tb, batch, gp, work->dy, work->dz1,
+                       work->dz2, work->part, work->part ? work->part_floats : 0, st);
+    if (e == hipSuccess) e = mlp_adam(wp, gp, mp, vp, step0 + s, lr, beta1, beta2, eps, st);
+    if (e == hipSuccess) e = mlp_mse(work->y, work->tb, batch, losses + s, st);
+  }
+  return e == hipSuccess ? RT_OK : hip_fail(e, "mlp train");
 }
 
 rt_status rt_ctx_timing(rt_ctx* ctx, int32_t slots, int32_t every) {

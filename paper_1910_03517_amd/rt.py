@@ -29,7 +29,7 @@ EXPORTED = ["rt_ctx_create", "rt_ctx_destroy", "rt_ctx_sizes", "rt_stats", "rt_e
             "rt_stream_copy", "rt_ctx_timing", "rt_ctx_apply_times", "rt_graph_create", "rt_graph_launch",
             "rt_graph_destroy", "rt_pipe_create", "rt_pipe_submit", "rt_pipe_destroy",
             "rt_surrogate_features", "rt_estimate_new", "rt_surrogate_targets", "rt_surrogate_select",
-            "rt_mlp_forward", "rt_mlp_backward", "rt_mlp_adam", "rt_mlp_mse", "rt_gather_rows",
+            "rt_mlp_forward", "rt_mlp_backward", "rt_mlp_adam", "rt_mlp_mse", "rt_gather_rows", "rt_mlp_train",
             "rt_status_str", "rt_last_error"]
 MLP_IN, MLP_HID, MLP_OUT = 576, 256, 6
 
@@ -69,6 +69,11 @@ class rt_lut_buf(ct.Structure):
 class rt_mlp(ct.Structure):
     _fields_ = [("w1", ct.c_void_p), ("b1", ct.c_void_p), ("w2", ct.c_void_p), ("b2", ct.c_void_p),
                 ("w3", ct.c_void_p), ("b3", ct.c_void_p)]
+
+
+class rt_mlp_work(ct.Structure):
+    _fields_ = [(n, ct.c_void_p) for n in ("xb", "tb", "h1", "h2", "y", "dy", "dz1", "dz2", "part")] + [
+        ("part_floats", ct.c_int64)]
 
 
 class RtError(RuntimeError):
@@ -121,10 +126,13 @@ def load(path: str = LIB_PATH) -> ct.CDLL:
     lib.rt_surrogate_targets.argtypes = [P, P, P, P, P, P]
     lib.rt_surrogate_select.argtypes = [P, P, P, P, ct.c_float, ct.POINTER(rt_params_buf), P, P, P]
     lib.rt_mlp_forward.argtypes = [M, P, ct.c_int32, P, P, P, P]
-    lib.rt_mlp_backward.argtypes = [M, P, P, P, P, P, ct.c_int32, M, P, P, P, P]
+    lib.rt_mlp_backward.argtypes = [M, P, P, P, P, P, ct.c_int32, M, P, P, P, P, ct.c_int64, P]
     lib.rt_mlp_adam.argtypes = [M, M, M, M, ct.c_int32, ct.c_float, ct.c_float, ct.c_float, ct.c_float, P]
     lib.rt_mlp_mse.argtypes = [P, P, ct.c_int32, P, P]
     lib.rt_gather_rows.argtypes = [P, ct.c_int32, P, ct.c_int32, P, P]
+    M = ct.POINTER(rt_mlp)
+    lib.rt_mlp_train.argtypes = [M, M, M, M, P, P, ct.c_int32, P, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_float,
+                                 ct.c_float, ct.c_float, ct.c_float, ct.POINTER(rt_mlp_work), P, P]
     lib.rt_graph_destroy.argtypes = [P]
     lib.rt_ctx_apply_times.argtypes = [P, ct.POINTER(ct.c_float), ct.c_int32, ct.POINTER(ct.c_int32)]
     for name in EXPORTED:
@@ -289,9 +297,11 @@ def rt_mlp_forward(w: MlpTensors, X, n, H1, H2, Y, stream=None) -> None:
     _check(load().rt_mlp_forward(ct.byref(w.c()), _p(X), n, _p(H1), _p(H2), _p(Y), _stream_handle(stream)))
 
 
-def rt_mlp_backward(w: MlpTensors, X, H1, H2, Y, T, n, grad: MlpTensors, dY, dZ1, dZ2, stream=None) -> None:
+def rt_mlp_backward(w: MlpTensors, X, H1, H2, Y, T, n, grad: MlpTensors, dY, dZ1, dZ2, stream=None,
+                    part=None) -> None:
     _check(load().rt_mlp_backward(ct.byref(w.c()), _p(X), _p(H1), _p(H2), _p(Y), _p(T), n, ct.byref(grad.c()),
-                                  _p(dY), _p(dZ1), _p(dZ2), _stream_handle(stream)))
+                                  _p(dY), _p(dZ1), _p(dZ2), _p(part), 0 if part is None else part.numel(),
+                                  _stream_handle(stream)))
 
 
 def rt_mlp_adam(w: MlpTensors, grad: MlpTensors, m: MlpTensors, v: MlpTensors, step: int, lr: float,
@@ -306,6 +316,18 @@ def rt_mlp_mse(Y, T, n, out, stream=None) -> None:
 
 def rt_gather_rows(src, row_len, idx, n, dst, stream=None) -> None:
     _check(load().rt_gather_rows(_p(src), row_len, _p(idx), n, _p(dst), _stream_handle(stream)))
+
+
+def rt_mlp_train(w, g, m, v, X, T, idx, batch: int, n_steps: int, step0: int, lr: float, work: dict, losses,
+                 beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8, stream=None) -> None:
+    """n_steps Adam steps on mini-batches idx[s*batch:(s+1)*batch] of (X, T); work: dict of the
+    rt_mlp_work tensors; losses: device float32 [n_steps]."""
+    part = work.get("part")
+    wk = rt_mlp_work(*[_p(work[n]) for n in ("xb", "tb", "h1", "h2", "y", "dy", "dz1", "dz2")], _p(part),
+                     0 if part is None else part.numel())
+    _check(load().rt_mlp_train(ct.byref(w.c()), ct.byref(g.c()), ct.byref(m.c()), ct.byref(v.c()), _p(X), _p(T),
+                               int(X.shape[0]), _p(idx), batch, n_steps, step0, lr, beta1, beta2, eps,
+                               ct.byref(wk), _p(losses), _stream_handle(stream)))
 
 
 def ptr_array(tensors) -> ct.Array:

@@ -78,12 +78,12 @@ def test_features_estimate_new_targets_bit_exact():
 
 
 def test_forward_backward_adam_against_fp64():
-    say("case: mlp forward/backward/adam vs fp64, batch 96")
+    say("case: mlp forward/backward/adam vs fp64, batch 300")
     rng = np.random.default_rng(3)
     P = synth.mlp_init(5)
     P["b1"] = rng.normal(0, 0.05, 256).astype(np.float32)     # non-zero biases exercise the epilogues
     P["b3"] = rng.normal(0, 0.05, 6).astype(np.float32)
-    n = 96
+    n = 300                                  # >= 256: the split-K path is taken, with a ragged slice
     X = rng.uniform(0, 0.2, (n, 576)).astype(np.float32)
     X[:, rng.integers(0, 576, 200)] = 0.0
     T = rng.normal(1.0, 0.3, (n, 6)).astype(np.float32)
@@ -107,6 +107,14 @@ def test_forward_backward_adam_against_fp64():
     gh = g.host()
     for k in rt.MlpTensors.NAMES:
         assert rel(gh[k], Go[k]) < 1e-4, k
+    # The same with the weight gradients summed in split-K slices.
+    gs = rt.MlpTensors(None)
+    part = torch.zeros(8 * 577 * 256, **e)
+    rt.rt_mlp_backward(w, Xd, H1, H2, Y, Td, n, gs, dY, dZ1, dZ2, part=part)
+    torch.cuda.synchronize()
+    gsh = gs.host()
+    for k in rt.MlpTensors.NAMES:
+        assert rel(gsh[k], Go[k]) < 1e-4, k
     # Adam from the GPU's own gradient on both sides, two steps.
     m, v = rt.MlpTensors(None), rt.MlpTensors(None)
     Pa, Ma, Va = dict(Po), {k: np.zeros_like(x) for k, x in Po.items()}, {k: np.zeros_like(x) for k, x in Po.items()}
@@ -189,6 +197,29 @@ def test_corrupted_weights_fall_back_to_plain():
         assert np.array_equal(rig.bufs.params.cpu().numpy(), plain.bufs.params.cpu().numpy())
         rig.close()
     plain.close()
+
+
+def test_library_training_loop_equals_stepwise_calls():
+    """rt_mlp_train (all steps enqueued by the library) gives bit for bit the
+    weights, moments and losses of the per-step calls."""
+    say("case: rt_mlp_train vs per-step calls, 3 epochs of 4 batches")
+    rng = np.random.default_rng(11)
+    n = 4 * 64 + 17                          # a ragged tail that no batch covers
+    X = torch.as_tensor(rng.uniform(0, 2, (n, 576)).astype(np.float32), device="cuda")
+    T = torch.as_tensor(rng.normal(1, 0.3, (n, 6)).astype(np.float32), device="cuda")
+    data = su.Dataset(X, T)
+    a = su.Trainer(synth.mlp_init(2), lr=3e-3, batch=64, seed=5)
+    b = su.Trainer(synth.mlp_init(2), lr=3e-3, batch=64, seed=5)
+    for _ in range(3):
+        la = a.epoch(data)
+        lb = b.epoch_stepwise(data)
+        assert abs(la - lb) <= 1e-6 * abs(lb)     # same per-step losses; the mean may reduce differently
+    torch.cuda.synchronize()
+    assert a.step == b.step == 12
+    for x, y in ((a.w, b.w), (a.m, b.m), (a.v, b.v)):
+        hx, hy = x.host(), y.host()
+        for k in rt.MlpTensors.NAMES:
+            assert np.array_equal(hx[k], hy[k]), k
 
 
 def test_training_gain_over_untrained_and_no_correction():
