@@ -344,6 +344,33 @@ rt_status rt_surrogate_targets(rt_ctx* ctx, const double* p_new, const int32_t* 
 rt_status rt_surrogate_select(rt_ctx* ctx, const float* Y, const double* p_new, const int32_t* status, float tol,
                               const rt_params_buf* state, uint8_t* used, float* residual, void* stream);
 
+/* Device workspace of rt_surrogate_frameset for a context with U = K*2*NB
+ * units: X f32 [U][576], H1 and H2 f32 [U][256], Y f32 [U][6], p_new f64
+ * [U][3][2], status i32 [U][3], used u8 [U], residual f32 [U].  All owned by
+ * the caller; after the call they hold what rt_surrogate_features,
+ * rt_estimate_new, rt_mlp_forward and rt_surrogate_select would have written. */
+typedef struct {
+  float* X; float* H1; float* H2; float* Y;
+  double* p_new; int32_t* status; uint8_t* used; float* residual;
+} rt_surrogate_work;
+
+/* One frame-set with the learned surrogate in place of the estimate (the
+ * data-parallel step of Sec. 3.1 with its per-unit fit predicted): band
+ * statistics of `frames` into stats, features against whole_hist_prev
+ * (u32 [K][3][256], the previous frame-set's whole-frame histograms; it may
+ * be stats->whole_hist itself), plain estimate, network, choice with
+ * fallback and temporal update of `state`, tables into `lut`, then the
+ * corrected frames and the new whole-frame statistics into stats.  Results
+ * are identical to rt_stats (band only), rt_surrogate_features,
+ * rt_estimate_new, rt_mlp_forward, rt_surrogate_select, rt_build_lut and
+ * rt_apply (with whole-frame statistics) called in turn; seven launches
+ * instead of eleven.  Restricted to the context's active set (rt_ctx_set_active).
+ * Errors: RT_EINVAL for NULL or misaligned pointers or tol < 0 (or NaN). */
+rt_status rt_surrogate_frameset(rt_ctx* ctx, const rt_mlp* w, float tol, const void* const* frames,
+                                void* const* out_frames, const rt_stats_buf* stats, const uint32_t* whole_hist_prev,
+                                const rt_params_buf* state, const rt_lut_buf* lut, const rt_surrogate_work* work,
+                                void* stream);
+
 /* Forward pass over n rows: H1, H2 float32 [n][256] (post-ReLU), Y [n][6]. */
 rt_status rt_mlp_forward(const rt_mlp* w, const float* X, int32_t n, float* H1, float* H2, float* Y, void* stream);
 

@@ -4,6 +4,7 @@
 // and the per-unit choice between network and plain estimate followed by the
 // temporal update of the estimator state.
 #include "dev_estimate.h"
+#include "dev_stats.h"
 
 namespace rc {
 
@@ -11,11 +12,12 @@ namespace rc {
 // as given, own band, facing band), channels, 64 bins = 64 * (sum of 4
 // adjacent 256-bins) / the region-channel's count, computed in binary64 and
 // rounded once to float32.  Rows of non-RGB cameras are zero.
-__global__ __launch_bounds__(kThreads) void k_features(Geo g, const uint32_t* __restrict__ band_hist,
-                                                       const uint32_t* __restrict__ whole_hist, float* __restrict__ X) {
+// Features of unit u3 (one workgroup): see the file comment for the layout.
+__device__ __forceinline__ void features_unit(const Geo& g, const uint32_t* __restrict__ band_hist,
+                                              const uint32_t* __restrict__ whole_hist, float* __restrict__ X,
+                                              int u3) {
   __shared__ uint32_t h[3][kCS][kNB];
   __shared__ uint32_t cnt[3][kCS];
-  const int u3 = blockIdx.x;
   const int nb = g.n_blocks;
   const int k = u3 / (2 * nb);
   const int s = (u3 / nb) & 1;
@@ -23,7 +25,6 @@ __global__ __launch_bounds__(kThreads) void k_features(Geo g, const uint32_t* __
   const int tid = threadIdx.x;
   const DevCam& cam = g.cams[k];
   float* out = X + (int64_t)u3 * kMlpIn;
-  if (!cam_active(g, k)) return;
   if (cam.channels != 3) {
     for (int o = tid; o < kMlpIn; o += kThreads) out[o] = 0.0f;
     return;
@@ -47,6 +48,13 @@ __global__ __launch_bounds__(kThreads) void k_features(Geo g, const uint32_t* __
     const uint32_t m = h[r][c][4 * bin] + h[r][c][4 * bin + 1] + h[r][c][4 * bin + 2] + h[r][c][4 * bin + 3];
     out[o] = n ? (float)((double)m * 64.0 / (double)n) : 0.0f;
   }
+}
+
+__global__ __launch_bounds__(kThreads) void k_features(Geo g, const uint32_t* __restrict__ band_hist,
+                                                       const uint32_t* __restrict__ whole_hist, float* __restrict__ X) {
+  const int u3 = blockIdx.x;
+  if (!cam_active(g, u3 / (2 * g.n_blocks))) return;
+  features_unit(g, band_hist, whole_hist, X, u3);
 }
 
 // The plain estimate of every (camera, side, block, channel) before the temporal step.
@@ -82,15 +90,11 @@ __global__ __launch_bounds__(kThreads) void k_targets(Geo g, const double* __res
 // channels hold a new plain estimate, every output is finite and
 // r = max_c max(|a^ - a|, |b^n - b / 255|) <= tol (binary64 on the float32
 // outputs); then the temporal update of the three channels.
-__global__ __launch_bounds__(kThreads) void k_select(Geo g, const float* __restrict__ Y,
-                                                     const double* __restrict__ p_new,
-                                                     const int32_t* __restrict__ status, float tol,
-                                                     double* __restrict__ params, uint8_t* __restrict__ valid,
-                                                     uint8_t* __restrict__ used, float* __restrict__ residual) {
-  const int u3 = blockIdx.x * kThreads + threadIdx.x;
-  if (u3 >= g.n_cams * 2 * g.n_blocks) return;
+__device__ inline void select_unit(const Geo& g, const float* __restrict__ Y, const double* __restrict__ p_new,
+                                   const int32_t* __restrict__ status, float tol, double* __restrict__ params,
+                                   uint8_t* __restrict__ valid, uint8_t* __restrict__ used,
+                                   float* __restrict__ residual, int u3) {
   const int k = u3 / (2 * g.n_blocks);
-  if (!cam_active(g, k)) return;
   const float* y = Y + (int64_t)u3 * kMlpOut;
   bool eligible = g.cams[k].channels == 3;
   for (int c = 0; c < kCS; ++c) eligible = eligible && status[(int64_t)u3 * kCS + c] == kStNew;
@@ -121,6 +125,58 @@ __global__ __launch_bounds__(kThreads) void k_select(Geo g, const float* __restr
   }
 }
 
+__global__ __launch_bounds__(kThreads) void k_select(Geo g, const float* __restrict__ Y,
+                                                     const double* __restrict__ p_new,
+                                                     const int32_t* __restrict__ status, float tol,
+                                                     double* __restrict__ params, uint8_t* __restrict__ valid,
+                                                     uint8_t* __restrict__ used, float* __restrict__ residual) {
+  const int u3 = blockIdx.x * kThreads + threadIdx.x;
+  if (u3 >= g.n_cams * 2 * g.n_blocks) return;
+  if (!cam_active(g, u3 / (2 * g.n_blocks))) return;
+  select_unit(g, Y, p_new, status, tol, params, valid, used, residual, u3);
+}
+
+// Surrogate frame-set, step 1 (one workgroup per unit u3): the unit's
+// features, and its three channels' plain estimate (threads 0..2).
+__global__ __launch_bounds__(kThreads) void k_features_new(Geo g, const uint32_t* __restrict__ band_hist,
+                                                           const uint64_t* __restrict__ band_sums,
+                                                           const uint32_t* __restrict__ whole_hist,
+                                                           float* __restrict__ X, double* __restrict__ p_new,
+                                                           int32_t* __restrict__ status) {
+  const int u3 = blockIdx.x;
+  if (!cam_active(g, u3 / (2 * g.n_blocks))) return;
+  const int tid = threadIdx.x;
+  if (tid < kCS) {
+    const int u = u3 * kCS + tid;
+    double a, b;
+    status[u] = fit_new(g, band_sums, u, a, b);
+    p_new[(int64_t)u * 2] = a;
+    p_new[(int64_t)u * 2 + 1] = b;
+  }
+  features_unit(g, band_hist, whole_hist, X, u3);
+}
+
+// Surrogate frame-set, step 3 (one workgroup per unit u3): the choice and
+// state update (thread 0), the unit's tables, the camera's weights (first
+// unit), and clearing the whole-frame statistics the apply accumulates.
+__global__ __launch_bounds__(kThreads) void k_select_lut(Geo g, const float* __restrict__ Y,
+                                                         const double* __restrict__ p_new,
+                                                         const int32_t* __restrict__ status, float tol, Bufs b,
+                                                         uint8_t* __restrict__ used, float* __restrict__ residual) {
+  const int u3 = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int nb = g.n_blocks;
+  const int k = u3 / (2 * nb);
+  if (b.whole_hist) zero_whole(g, b, blockIdx.x * kThreads + tid, gridDim.x * kThreads);
+  if (!cam_active(g, k)) return;
+  if (tid == 0) select_unit(g, Y, p_new, status, tol, b.params, b.valid, used, residual, u3);
+  __syncthreads();
+  lut_entry(g, b, u3, tid);
+  if (u3 % (2 * nb) == 0)
+    for (int col = tid; col < g.w_max; col += kThreads)
+      b.weights[(int64_t)k * g.w_max + col] = (uint16_t)blend_weight(g.cams[k].width, col);
+}
+
 hipError_t launch_features(const Geo& g, const uint32_t* band_hist, const uint32_t* whole_hist, float* X,
                            hipStream_t st) {
   hipLaunchKernelGGL(k_features, dim3(g.n_cams * 2 * g.n_blocks), dim3(kThreads), 0, st, g, band_hist, whole_hist, X);
@@ -139,6 +195,20 @@ hipError_t launch_targets(const Geo& g, const double* p_new, const int32_t* stat
                           hipStream_t st) {
   const int n = g.n_cams * 2 * g.n_blocks;
   hipLaunchKernelGGL(k_targets, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, st, g, p_new, status, T, mask);
+  return hipGetLastError();
+}
+
+hipError_t launch_features_new(const Geo& g, const uint32_t* band_hist, const uint64_t* band_sums,
+                               const uint32_t* whole_hist, float* X, double* p_new, int32_t* status, hipStream_t st) {
+  hipLaunchKernelGGL(k_features_new, dim3(g.n_cams * 2 * g.n_blocks), dim3(kThreads), 0, st, g, band_hist, band_sums,
+                     whole_hist, X, p_new, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_select_lut(const Geo& g, const float* Y, const double* p_new, const int32_t* status, float tol,
+                             const Bufs& b, uint8_t* used, float* residual, hipStream_t st) {
+  hipLaunchKernelGGL(k_select_lut, dim3(g.n_cams * 2 * g.n_blocks), dim3(kThreads), 0, st, g, Y, p_new, status, tol,
+                     b, used, residual);
   return hipGetLastError();
 }
 

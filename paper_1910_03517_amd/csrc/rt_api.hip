@@ -752,6 +752,46 @@ static void mlp_ptrs(const rt_mlp* m, float** out) {
   out[0] = m->w1; out[1] = m->b1; out[2] = m->w2; out[3] = m->b2; out[4] = m->w3; out[5] = m->b3;
 }
 
+rt_status rt_surrogate_frameset(rt_ctx* ctx, const rt_mlp* w, float tol, const void* const* frames,
+                                void* const* out_frames, const rt_stats_buf* stats, const uint32_t* whole_hist_prev,
+                                const rt_params_buf* state, const rt_lut_buf* lut, const rt_surrogate_work* work,
+                                void* stream) {
+  if (!ctx) return fail(RT_EINVAL, "ctx is NULL");
+  const uint64_t active = ctx->geo.active;
+  rt_status r = check_mlp(w, "weights");
+  if (r == RT_OK) r = check_frames_masked(ctx, active, frames, "frames");
+  if (r == RT_OK) r = check_frames_masked(ctx, active, (const void* const*)out_frames, "out_frames");
+  if (r == RT_OK) r = check_stats(stats, true, true);
+  if (r == RT_OK) r = check_ptr(whole_hist_prev, 4, "whole_hist_prev");
+  if (r == RT_OK) r = check_params(state);
+  if (r == RT_OK) r = check_lut(lut);
+  if (r != RT_OK) return r;
+  if (!work) return fail(RT_EINVAL, "work struct is NULL");
+  const void* fw[4] = {work->X, work->H1, work->H2, work->Y};
+  for (int i = 0; i < 4; ++i)
+    if ((r = check_ptr(fw[i], 4, "work activation")) != RT_OK) return r;
+  if ((r = check_ptr(work->p_new, 8, "work p_new")) != RT_OK) return r;
+  if ((r = check_ptr(work->status, 4, "work status")) != RT_OK) return r;
+  if ((r = check_ptr(work->used, 1, "work used")) != RT_OK) return r;
+  if ((r = check_ptr(work->residual, 4, "work residual")) != RT_OK) return r;
+  if (!(tol >= 0.0f)) return fail(RT_EINVAL, "tol must be >= 0");
+  hipStream_t st = (hipStream_t)stream;
+  const Geo& g = ctx->geo;
+  const FramePtrs fp = make_ptrs_masked(ctx, frames, out_frames, active);
+  const Bufs b = make_bufs(stats, state, lut);
+  hipError_t e = launch_band_stats(g, fp, b, st);
+  if (e != hipSuccess) return hip_fail(e, "band statistics");
+  e = launch_features_new(g, b.band_hist, b.band_sums, whole_hist_prev, work->X, work->p_new, work->status, st);
+  if (e != hipSuccess) return hip_fail(e, "surrogate features and plain estimate");
+  float* wp[6];
+  mlp_ptrs(w, wp);
+  e = mlp_forward(wp, work->X, g.n_cams * 2 * g.n_blocks, work->H1, work->H2, work->Y, st);
+  if (e != hipSuccess) return hip_fail(e, "mlp forward");
+  e = launch_select_lut(g, work->Y, work->p_new, work->status, tol, b, work->used, work->residual, st);
+  if (e != hipSuccess) return hip_fail(e, "surrogate choice and tables");
+  return whole_pass(ctx, g, fp, b, true, false, st);
+}
+
 rt_status rt_mlp_forward(const rt_mlp* w, const float* X, int32_t n, float* H1, float* H2, float* Y, void* stream) {
   rt_status r = check_mlp(w, "weights");
   if (r == RT_OK) r = check_ptr(X, 4, "X");

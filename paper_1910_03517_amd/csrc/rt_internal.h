@@ -149,6 +149,10 @@ hipError_t launch_estimate_new(const Geo& g, const uint64_t* band_sums, double* 
                                hipStream_t st);
 hipError_t launch_targets(const Geo& g, const double* p_new, const int32_t* status, float* T, uint8_t* mask,
                           hipStream_t st);
+hipError_t launch_features_new(const Geo& g, const uint32_t* band_hist, const uint64_t* band_sums,
+                               const uint32_t* whole_hist, float* X, double* p_new, int32_t* status, hipStream_t st);
+hipError_t launch_select_lut(const Geo& g, const float* Y, const double* p_new, const int32_t* status, float tol,
+                             const Bufs& b, uint8_t* used, float* residual, hipStream_t st);
 hipError_t launch_select(const Geo& g, const float* Y, const double* p_new, const int32_t* status, float tol,
                          double* params, uint8_t* valid, uint8_t* used, float* residual, hipStream_t st);
 hipError_t mlp_forward(const float* const* w, const float* X, int n, float* H1, float* H2, float* Y, hipStream_t st);

@@ -29,6 +29,7 @@ EXPORTED = ["rt_ctx_create", "rt_ctx_destroy", "rt_ctx_sizes", "rt_stats", "rt_e
             "rt_stream_copy", "rt_ctx_timing", "rt_ctx_apply_times", "rt_graph_create", "rt_graph_launch",
             "rt_graph_destroy", "rt_pipe_create", "rt_pipe_submit", "rt_pipe_destroy",
             "rt_surrogate_features", "rt_estimate_new", "rt_surrogate_targets", "rt_surrogate_select",
+            "rt_surrogate_frameset",
             "rt_mlp_forward", "rt_mlp_backward", "rt_mlp_adam", "rt_mlp_mse", "rt_gather_rows", "rt_mlp_train",
             "rt_status_str", "rt_last_error"]
 MLP_IN, MLP_HID, MLP_OUT = 576, 256, 6
@@ -74,6 +75,10 @@ class rt_mlp(ct.Structure):
 class rt_mlp_work(ct.Structure):
     _fields_ = [(n, ct.c_void_p) for n in ("xb", "tb", "h1", "h2", "y", "dy", "dz1", "dz2", "part")] + [
         ("part_floats", ct.c_int64)]
+
+
+class rt_surrogate_work(ct.Structure):
+    _fields_ = [(n, ct.c_void_p) for n in ("X", "H1", "H2", "Y", "p_new", "status", "used", "residual")]
 
 
 class RtError(RuntimeError):
@@ -125,6 +130,9 @@ def load(path: str = LIB_PATH) -> ct.CDLL:
     lib.rt_estimate_new.argtypes = [P, ct.POINTER(rt_stats_buf), P, P, P]
     lib.rt_surrogate_targets.argtypes = [P, P, P, P, P, P]
     lib.rt_surrogate_select.argtypes = [P, P, P, P, ct.c_float, ct.POINTER(rt_params_buf), P, P, P]
+    lib.rt_surrogate_frameset.argtypes = [P, M, ct.c_float, ct.POINTER(P), ct.POINTER(P), ct.POINTER(rt_stats_buf),
+                                          P, ct.POINTER(rt_params_buf), ct.POINTER(rt_lut_buf),
+                                          ct.POINTER(rt_surrogate_work), P]
     lib.rt_mlp_forward.argtypes = [M, P, ct.c_int32, P, P, P, P]
     lib.rt_mlp_backward.argtypes = [M, P, P, P, P, P, ct.c_int32, M, P, P, P, P, ct.c_int64, P]
     lib.rt_mlp_adam.argtypes = [M, M, M, M, ct.c_int32, ct.c_float, ct.c_float, ct.c_float, ct.c_float, P]
@@ -291,6 +299,18 @@ def rt_surrogate_select(ctx, Y, p_new, status, tol, params, valid, used, residua
     pb = rt_params_buf(_p(params), _p(valid))
     _check(load().rt_surrogate_select(ctx, _p(Y), _p(p_new), _p(status), float(tol), ct.byref(pb), _p(used),
                                       _p(residual), _stream_handle(stream)))
+
+
+def rt_surrogate_frameset(ctx, w: MlpTensors, tol, frames, out_frames, bufs: "Buffers", whole_hist_prev, work,
+                          stream=None) -> None:
+    """work: any object with X, H1, H2, Y, p_new, status, used, residual tensors."""
+    sb = rt_stats_buf(_p(bufs.band_hist), _p(bufs.band_sums), _p(bufs.whole_hist), _p(bufs.whole_sums))
+    pb = rt_params_buf(_p(bufs.params), _p(bufs.valid))
+    lb = rt_lut_buf(_p(bufs.lut8), _p(bufs.q16), _p(bufs.weights))
+    wk = rt_surrogate_work(*[_p(getattr(work, n)) for n, _ in rt_surrogate_work._fields_])
+    _check(load().rt_surrogate_frameset(ctx, ct.byref(w.c()), float(tol), _ptr_array(frames), _ptr_array(out_frames),
+                                        ct.byref(sb), _p(whole_hist_prev), ct.byref(pb), ct.byref(lb), ct.byref(wk),
+                                        _stream_handle(stream)))
 
 
 def rt_mlp_forward(w: MlpTensors, X, n, H1, H2, Y, stream=None) -> None:

@@ -62,8 +62,14 @@ class Surrogate:
                                stream)
 
     def frameset(self, rig: rt.Rig, frames, out_frames, whole_hist_prev, ws: Workspace, stream=None) -> None:
-        """One frame-set with the surrogate estimate; the whole-frame statistics
-        of this frame-set land in rig.bufs (the next call's whole_hist_prev)."""
+        """One frame-set with the surrogate estimate (rt_surrogate_frameset);
+        the whole-frame statistics of this frame-set land in rig.bufs (the next
+        call's whole_hist_prev)."""
+        rt.rt_surrogate_frameset(rig.ctx, self.w, self.tol, frames, out_frames, rig.bufs, whole_hist_prev, ws, stream)
+
+    def frameset_stepwise(self, rig: rt.Rig, frames, out_frames, whole_hist_prev, ws: Workspace,
+                          stream=None) -> None:
+        """The same frame-set as the sequence of the fine-grained calls."""
         b = rig.bufs
         rt.rt_stats(rig.ctx, frames, b.band_hist, b.band_sums, None, None, stream)
         self.estimate(rig, whole_hist_prev, ws, stream)

@@ -105,6 +105,8 @@ def test_null_arguments_are_rejected():
     assert lib.rt_estimate_new(None, None, None, None, None) == rt.RT_EINVAL
     assert lib.rt_surrogate_targets(None, None, None, None, None, None) == rt.RT_EINVAL
     assert lib.rt_surrogate_select(None, None, None, None, 1e-3, None, None, None, None) == rt.RT_EINVAL
+    assert lib.rt_surrogate_frameset(None, None, 1e-3, None, None, None, None, None, None, None,
+                                     None) == rt.RT_EINVAL
     assert lib.rt_mlp_forward(None, None, 1, None, None, None, None) == rt.RT_EINVAL
     assert lib.rt_mlp_backward(None, None, None, None, None, None, 1, None, None, None, None, None, 0,
                                None) == rt.RT_EINVAL

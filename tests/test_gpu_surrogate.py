@@ -285,3 +285,73 @@ def test_training_gain_over_untrained_and_no_correction():
         f"plain {c_plain:.2f}")
     assert c_sur < 0.5 * c_unc
     rig.close()
+
+
+WS_FIELDS = ("X", "H1", "H2", "Y", "p_new", "status", "used", "residual")
+BUF_FIELDS = ("band_hist", "band_sums", "whole_hist", "whole_sums", "params", "valid", "lut8", "q16", "weights")
+
+
+@pytest.mark.parametrize("tol", [0.0, 0.05, 1e30])
+def test_fused_frameset_equals_stepwise_calls(tol):
+    """rt_surrogate_frameset (seven launches) leaves bit for bit what the
+    fine-grained calls leave: outputs, statistics, state, tables and the
+    whole workspace, over a sequence of frame-sets (the temporal state and the
+    previous whole-frame histograms carry over), then restricted to one ring."""
+    say(f"case: fused surrogate frame-set vs stepwise, tol {tol}")
+    spec, cams, opts = small_rig(nb=6)
+    opts = rt.Options(n_blocks=6, band_width=16, smoothing=True)
+    sur = su.Surrogate(rt.MlpTensors(synth.mlp_init(4)), tol=tol)
+    rigs = [rt.Rig(cams, opts) for _ in range(2)]
+    wss = [su.Workspace(r.sizes) for r in rigs]
+    outs = [r.alloc_frames() for r in rigs]
+    used_total = 0
+    for t in range(4):
+        if t == 3:
+            ring0 = sum(1 << i for i, c in enumerate(spec.cams) if c.ring == 0)
+            for r in rigs:
+                r.set_active(ring0)
+        dev = rigs[0].upload(synth.rig_frames(spec, t, drift=True))
+        sur.frameset(rigs[0], dev, outs[0], rigs[0].bufs.whole_hist, wss[0])
+        sur.frameset_stepwise(rigs[1], dev, outs[1], rigs[1].bufs.whole_hist, wss[1])
+        torch.cuda.synchronize()
+        ha, hb = rigs[0].bufs.host(), rigs[1].bufs.host()
+        for n in BUF_FIELDS:
+            assert np.array_equal(ha[n], hb[n]), f"t {t}: {n}"
+        for x, y in zip(rigs[0].download(outs[0]), rigs[1].download(outs[1])):
+            assert np.array_equal(x, y), f"t {t}: output"
+        for n in WS_FIELDS:
+            a, b = getattr(wss[0], n).cpu().numpy(), getattr(wss[1], n).cpu().numpy()
+            if t == 3:                 # only the active ring's units (cameras 0..3) are defined
+                a, b = a.reshape(len(cams), -1)[:4], b.reshape(len(cams), -1)[:4]
+            assert np.array_equal(a.view(np.uint8), b.view(np.uint8)), f"t {t}: work {n}"
+        used_total += int(wss[0].used[: 4 * 2 * 6].sum().item())
+    if tol == 0.0:
+        assert used_total == 0
+    if tol == 1e30:
+        assert used_total > 0
+    for r in rigs:
+        r.close()
+
+
+def test_fused_frameset_validation():
+    spec, cams, opts = small_rig(nb=2)
+    rig = rt.Rig(cams, opts)
+    ws = su.Workspace(rig.sizes)
+    dev = rig.alloc_frames()
+    out = rig.alloc_frames()
+    w = rt.MlpTensors(synth.mlp_init(0))
+    with pytest.raises(rt.RtError, match="tol"):
+        rt.rt_surrogate_frameset(rig.ctx, w, -1.0, dev, out, rig.bufs, rig.bufs.whole_hist, ws)
+    with pytest.raises(rt.RtError, match="whole_hist_prev"):
+        rt.rt_surrogate_frameset(rig.ctx, w, 0.1, dev, out, rig.bufs, None, ws)
+
+    class Missing:
+        pass
+    bad = Missing()
+    for n in WS_FIELDS:
+        setattr(bad, n, getattr(ws, n))
+    bad.residual = None
+    with pytest.raises(rt.RtError, match="residual"):
+        rt.rt_surrogate_frameset(rig.ctx, w, 0.1, dev, out, rig.bufs, rig.bufs.whole_hist, bad)
+    rig.check()
+    rig.close()
