@@ -363,7 +363,7 @@ typedef struct {
  * corrected frames and the new whole-frame statistics into stats.  Results
  * are identical to rt_stats (band only), rt_surrogate_features,
  * rt_estimate_new, rt_mlp_forward, rt_surrogate_select, rt_build_lut and
- * rt_apply (with whole-frame statistics) called in turn; seven launches
+ * rt_apply (with whole-frame statistics) called in turn; six launches
  * instead of eleven.  Restricted to the context's active set (rt_ctx_set_active).
  * Errors: RT_EINVAL for NULL or misaligned pointers or tol < 0 (or NaN). */
 rt_status rt_surrogate_frameset(rt_ctx* ctx, const rt_mlp* w, float tol, const void* const* frames,

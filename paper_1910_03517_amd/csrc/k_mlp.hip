@@ -3,7 +3,7 @@
 // epilogues and an optional ones row for bias gradients, the MSE gradient and
 // value, Adam over the whole network in one launch, and a row gather for
 // mini-batches.
-#include "rt_internal.h"
+#include "dev_mlp.h"
 
 namespace rc {
 
@@ -11,6 +11,7 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int kGemmTile = 64;   // workgroup tile (rows and columns)
 constexpr int kGemmK = 32;      // k-slab staged in LDS
+constexpr int kWsMaxRows = 2048;  // up to this many rows, row-major products use the k-split tile kernel
 
 enum { kEpiNone = 0, kEpiBias = 1, kEpiBiasRelu = 2, kEpiMask = 3 };
 
@@ -120,23 +121,6 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const float* 
   k_gemm_body<EPI>(M, N, K, A, sai, sak, B, sbk, sbj, C, ldc, bias, mask, ldm, ones_row);
 }
 
-// Sum of v over the 64 lanes of the wave (all lanes active) with DPP row
-// operations, in a fixed order; the total is returned to every lane.
-template <int CTRL, int ROW_MASK = 0xf>
-__device__ inline float dpp_f32(float v) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROW_MASK, 0xf,
-                                                                 false));
-}
-__device__ inline float wave_sum_f32(float v) {
-  v += dpp_f32<0x111>(v);
-  v += dpp_f32<0x112>(v);
-  v += dpp_f32<0x114>(v);
-  v += dpp_f32<0x118>(v);
-  v += dpp_f32<0x142, 0xa>(v);
-  v += dpp_f32<0x143, 0xc>(v);
-  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
-}
-
 // The same product for N <= kSkinnyN columns: one wave per output row, lanes
 // striding over k, each column's sum reduced across the wave.  (A 64-wide
 // tile would leave most of the matrix cores idle for the network's 6 outputs.)
@@ -176,6 +160,90 @@ __global__ __launch_bounds__(256) void k_gemm_skinny(int M, int N, int K, const 
   }
 }
 
+// The same product for few rows (the forward's layers at inference and
+// mini-batch sizes), where 64 x 64 tiles would leave most compute units idle
+// and each wave a long serial chain of MFMAs.  A workgroup of kWsWaves waves
+// owns a 32 x 32 tile; wave w sums k over its own range [w kw, (w + 1) kw)
+// (kw a multiple of 8) straight from global memory: per 8 k, lane l loads
+// A(i, k0 + 4 g .. k0 + 4 g + 3) and B(k0 + 4 g + c, j) (g = l / 32, i and j =
+// l % 32; coalesced rows of B) and issues 4 MFMAs, the c-th pairing
+// k0 + c with k0 + 4 + c.  The waves' tiles are added in LDS in wave order,
+// then the epilogue.  Requires A contiguous along k and B along j.
+constexpr int kWsWaves = 8;
+constexpr int kWsTile = 32;
+template <int EPI>
+__global__ __launch_bounds__(kWsWaves * 64) void k_gemm_wsplit(int M, int N, int K, int kw,
+                                                               const float* __restrict__ A, int64_t lda,
+                                                               const float* __restrict__ B, int64_t ldb,
+                                                               float* __restrict__ C, int ldc,
+                                                               const float* __restrict__ bias,
+                                                               const float* __restrict__ mask, int ldm) {
+  __shared__ float red[kWsWaves][16][64];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int g = lane >> 5;
+  const int i0 = blockIdx.y * kWsTile, j0 = blockIdx.x * kWsTile;
+  const int ia = i0 + (lane & 31), jb = j0 + (lane & 31);
+  const bool arow = ia < M, bcol = jb < N;
+  const float* pa = A + (int64_t)(arow ? ia : 0) * lda;
+  const float* pb = B + (bcol ? jb : 0);
+  const int kbeg = wave * kw;
+  const int kend = (K - kbeg) < kw ? K : kbeg + kw;
+  f32x16 acc;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+  float a[4], b[4], an[4], bn[4];
+  auto load = [&](int k0, float* av, float* bv) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int kk = k0 + 4 * g + c;
+      const bool in = kk < kend;
+      av[c] = (in && arow) ? pa[kk] : 0.0f;
+      bv[c] = (in && bcol) ? pb[(int64_t)kk * ldb] : 0.0f;
+    }
+  };
+  if (kbeg < kend) load(kbeg, a, b);
+  for (int k0 = kbeg; k0 < kend; k0 += 8) {
+    if (k0 + 8 < kend) load(k0 + 8, an, bn);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[c], b[c], acc, 0, 0, 0);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      a[c] = an[c];
+      b[c] = bn[c];
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 16; ++r) red[wave][r][lane] = acc[r];
+  __syncthreads();
+  for (int e = tid; e < 16 * 64; e += kWsWaves * 64) {
+    const int r = e >> 6, l = e & 63;
+    float v = 0.0f;
+#pragma unroll
+    for (int w = 0; w < kWsWaves; ++w) v += red[w][r][l];
+    const int i = i0 + 8 * (r >> 2) + 4 * (l >> 5) + (r & 3);
+    const int j = j0 + (l & 31);
+    if (i >= M || j >= N) continue;
+    if (EPI == kEpiBias || EPI == kEpiBiasRelu) v += bias[j];
+    if (EPI == kEpiBiasRelu) v = v > 0.0f ? v : 0.0f;
+    if (EPI == kEpiMask) v = mask[(int64_t)i * ldm + j] > 0.0f ? v : 0.0f;
+    C[(int64_t)i * ldc + j] = v;
+  }
+}
+
+// The network's output layer, Y = H2 W3 + b3, one wave per row.
+__global__ __launch_bounds__(256) void k_out_layer(int M, const float* __restrict__ H2, const float* __restrict__ W3,
+                                                   const float* __restrict__ b3, float* __restrict__ Y) {
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= M) return;                                    // whole waves
+  float acc[kMlpOut];
+  wave_row_dot<kMlpOut>(H2 + (int64_t)i * kMlpHid, W3, b3, kMlpHid, kMlpOut, acc);
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int o = 0; o < kMlpOut; ++o) Y[(int64_t)i * kMlpOut + o] = acc[o];
+}
+
 // Split-K: slice z of the product over k in [z * kc, (z + 1) * kc) into
 // part + z * MA * N (rows of A including the ones row, row-major, no epilogue).
 __global__ __launch_bounds__(256) void k_gemm_part(int M, int N, int K, int kc, const float* __restrict__ A,
@@ -213,6 +281,13 @@ static hipError_t gemm(int M, int N, int K, const float* A, int64_t sai, int64_t
   if (N <= kSkinnyN) {
     hipLaunchKernelGGL((k_gemm_skinny<EPI>), dim3((MA + 3) / 4), dim3(256), 0, st, M, N, K, A, sai, sak, B, sbk, sbj,
                        C, ldc, bias, mask, ldm, ones_row);
+    return hipGetLastError();
+  }
+  if (sak == 1 && sbj == 1 && !ones_row && M <= kWsMaxRows && K >= 64) {
+    const int kw = ((K + kWsWaves - 1) / kWsWaves + 7) / 8 * 8;
+    const dim3 g2((N + kWsTile - 1) / kWsTile, (M + kWsTile - 1) / kWsTile);
+    hipLaunchKernelGGL((k_gemm_wsplit<EPI>), g2, dim3(kWsWaves * 64), 0, st, M, N, K, kw, A, sai, B, sbk, C, ldc,
+                       bias, mask, ldm);
     return hipGetLastError();
   }
   const dim3 grid((N + kGemmTile - 1) / kGemmTile, (MA + kGemmTile - 1) / kGemmTile);
@@ -306,15 +381,20 @@ __global__ __launch_bounds__(256) void k_gather_rows(const float* __restrict__ s
 
 // ----------------------------------------------------------------------------- launchers
 
-hipError_t mlp_forward(const float* const* w, const float* X, int n, float* H1, float* H2, float* Y, hipStream_t st) {
+hipError_t mlp_hidden(const float* const* w, const float* X, int n, float* H1, float* H2, hipStream_t st) {
   // w = {w1, b1, w2, b2, w3, b3}
   hipError_t e = gemm<kEpiBiasRelu>(n, kMlpHid, kMlpIn, X, kMlpIn, 1, w[0], kMlpHid, 1, H1, kMlpHid, w[1], nullptr,
                                     0, st);
   if (e == hipSuccess)
     e = gemm<kEpiBiasRelu>(n, kMlpHid, kMlpHid, H1, kMlpHid, 1, w[2], kMlpHid, 1, H2, kMlpHid, w[3], nullptr, 0, st);
-  if (e == hipSuccess)
-    e = gemm<kEpiBias>(n, kMlpOut, kMlpHid, H2, kMlpHid, 1, w[4], kMlpOut, 1, Y, kMlpOut, w[5], nullptr, 0, st);
   return e;
+}
+
+hipError_t mlp_forward(const float* const* w, const float* X, int n, float* H1, float* H2, float* Y, hipStream_t st) {
+  hipError_t e = mlp_hidden(w, X, n, H1, H2, st);
+  if (e != hipSuccess || n <= 0) return e;
+  hipLaunchKernelGGL(k_out_layer, dim3((n + 3) / 4), dim3(256), 0, st, n, H2, w[4], w[5], Y);
+  return hipGetLastError();
 }
 
 hipError_t mlp_backward(const float* const* w, const float* X, const float* H1, const float* H2, const float* Y,

@@ -5,6 +5,7 @@
 // temporal update of the estimator state.
 #include "dev_estimate.h"
 #include "dev_stats.h"
+#include "dev_mlp.h"
 
 namespace rc {
 
@@ -12,17 +13,18 @@ namespace rc {
 // as given, own band, facing band), channels, 64 bins = 64 * (sum of 4
 // adjacent 256-bins) / the region-channel's count, computed in binary64 and
 // rounded once to float32.  Rows of non-RGB cameras are zero.
-// Features of unit u3 (one workgroup): see the file comment for the layout.
+// Features of unit u3 (one workgroup): wave w takes the region-channel pairs
+// rc = w, w + 4, w + 8 (rc = 3 r + c, features rc * 64 .. rc * 64 + 63); lane
+// l holds bin l's four 256-bins, and the pair's count is the wave's sum.
 __device__ __forceinline__ void features_unit(const Geo& g, const uint32_t* __restrict__ band_hist,
                                               const uint32_t* __restrict__ whole_hist, float* __restrict__ X,
                                               int u3) {
-  __shared__ uint32_t h[3][kCS][kNB];
-  __shared__ uint32_t cnt[3][kCS];
   const int nb = g.n_blocks;
   const int k = u3 / (2 * nb);
   const int s = (u3 / nb) & 1;
   const int j = u3 % nb;
   const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
   const DevCam& cam = g.cams[k];
   float* out = X + (int64_t)u3 * kMlpIn;
   if (cam.channels != 3) {
@@ -30,23 +32,17 @@ __device__ __forceinline__ void features_unit(const Geo& g, const uint32_t* __re
     return;
   }
   const int fc = cam.face_cam[s];
-  const uint32_t* src[3] = {whole_hist + (int64_t)k * kCS * kNB, band_hist + unit_index(k, s, j, 0, nb) * kNB,
-                            fc >= 0 ? band_hist + unit_index(fc, cam.face_side[s], j, 0, nb) * kNB : nullptr};
-  for (int r = 0; r < 3; ++r)
-    for (int c = 0; c < kCS; ++c) h[r][c][tid] = src[r] ? src[r][c * kNB + tid] : 0u;
-  if (tid < 9) cnt[tid / 3][tid % 3] = 0;
-  __syncthreads();
-  for (int r = 0; r < 3; ++r)
-    for (int c = 0; c < kCS; ++c) {
-      const uint32_t v = h[r][c][tid];
-      if (v) atomicAdd(&cnt[r][c], v);
+  const uint32_t* base[3] = {whole_hist + (int64_t)k * kCS * kNB, band_hist + unit_index(k, s, j, 0, nb) * kNB,
+                             fc >= 0 ? band_hist + unit_index(fc, cam.face_side[s], j, 0, nb) * kNB : nullptr};
+  for (int rc = tid / kWave; rc < 3 * kCS; rc += kThreads / kWave) {
+    const uint32_t* h = base[rc / kCS];
+    uint32_t m = 0;
+    if (h) {
+      h += (rc % kCS) * kNB + 4 * lane;
+      m = h[0] + h[1] + h[2] + h[3];
     }
-  __syncthreads();
-  for (int o = tid; o < kMlpIn; o += kThreads) {
-    const int r = o / (kCS * 64), c = (o / 64) % kCS, bin = o % 64;
-    const uint32_t n = cnt[r][c];
-    const uint32_t m = h[r][c][4 * bin] + h[r][c][4 * bin + 1] + h[r][c][4 * bin + 2] + h[r][c][4 * bin + 3];
-    out[o] = n ? (float)((double)m * 64.0 / (double)n) : 0.0f;
+    const unsigned long long n = wave_sum_u64(m);
+    out[rc * 64 + lane] = n ? (float)((double)m * 64.0 / (double)n) : 0.0f;
   }
 }
 
@@ -137,7 +133,7 @@ __global__ __launch_bounds__(kThreads) void k_select(Geo g, const float* __restr
 }
 
 // Surrogate frame-set, step 1 (one workgroup per unit u3): the unit's
-// features, and its three channels' plain estimate (threads 0..2).
+// features, and its three channels' plain estimate (three lanes of the last wave).
 __global__ __launch_bounds__(kThreads) void k_features_new(Geo g, const uint32_t* __restrict__ band_hist,
                                                            const uint64_t* __restrict__ band_sums,
                                                            const uint32_t* __restrict__ whole_hist,
@@ -145,8 +141,8 @@ __global__ __launch_bounds__(kThreads) void k_features_new(Geo g, const uint32_t
                                                            int32_t* __restrict__ status) {
   const int u3 = blockIdx.x;
   if (!cam_active(g, u3 / (2 * g.n_blocks))) return;
-  const int tid = threadIdx.x;
-  if (tid < kCS) {
+  const int tid = threadIdx.x - (kThreads - kWave);   // the last wave, which has the fewest feature pairs
+  if (tid >= 0 && tid < kCS) {
     const int u = u3 * kCS + tid;
     double a, b;
     status[u] = fit_new(g, band_sums, u, a, b);
@@ -156,11 +152,14 @@ __global__ __launch_bounds__(kThreads) void k_features_new(Geo g, const uint32_t
   features_unit(g, band_hist, whole_hist, X, u3);
 }
 
-// Surrogate frame-set, step 3 (one workgroup per unit u3): the choice and
-// state update (thread 0), the unit's tables, the camera's weights (first
-// unit), and clearing the whole-frame statistics the apply accumulates.
-__global__ __launch_bounds__(kThreads) void k_select_lut(Geo g, const float* __restrict__ Y,
-                                                         const double* __restrict__ p_new,
+// Surrogate frame-set, step 3 (one workgroup per unit u3): the network's
+// output row (wave 0, the routine of the forward pass's output layer), the
+// choice and state update (thread 0, which stored that row), the unit's
+// tables, the camera's weights (first unit), and clearing the whole-frame
+// statistics the apply accumulates.
+__global__ __launch_bounds__(kThreads) void k_select_lut(Geo g, const float* __restrict__ H2,
+                                                         const float* __restrict__ W3, const float* __restrict__ b3,
+                                                         float* __restrict__ Y, const double* __restrict__ p_new,
                                                          const int32_t* __restrict__ status, float tol, Bufs b,
                                                          uint8_t* __restrict__ used, float* __restrict__ residual) {
   const int u3 = blockIdx.x;
@@ -169,7 +168,15 @@ __global__ __launch_bounds__(kThreads) void k_select_lut(Geo g, const float* __r
   const int k = u3 / (2 * nb);
   if (b.whole_hist) zero_whole(g, b, blockIdx.x * kThreads + tid, gridDim.x * kThreads);
   if (!cam_active(g, k)) return;
-  if (tid == 0) select_unit(g, Y, p_new, status, tol, b.params, b.valid, used, residual, u3);
+  if (tid < kWave) {
+    float acc[kMlpOut];
+    wave_row_dot<kMlpOut>(H2 + (int64_t)u3 * kMlpHid, W3, b3, kMlpHid, kMlpOut, acc);
+    if (tid == 0) {
+#pragma unroll
+      for (int o = 0; o < kMlpOut; ++o) Y[(int64_t)u3 * kMlpOut + o] = acc[o];
+      select_unit(g, Y, p_new, status, tol, b.params, b.valid, used, residual, u3);
+    }
+  }
   __syncthreads();
   lut_entry(g, b, u3, tid);
   if (u3 % (2 * nb) == 0)
@@ -205,10 +212,11 @@ hipError_t launch_features_new(const Geo& g, const uint32_t* band_hist, const ui
   return hipGetLastError();
 }
 
-hipError_t launch_select_lut(const Geo& g, const float* Y, const double* p_new, const int32_t* status, float tol,
-                             const Bufs& b, uint8_t* used, float* residual, hipStream_t st) {
-  hipLaunchKernelGGL(k_select_lut, dim3(g.n_cams * 2 * g.n_blocks), dim3(kThreads), 0, st, g, Y, p_new, status, tol,
-                     b, used, residual);
+hipError_t launch_select_lut(const Geo& g, const float* H2, const float* W3, const float* b3, float* Y,
+                             const double* p_new, const int32_t* status, float tol, const Bufs& b, uint8_t* used,
+                             float* residual, hipStream_t st) {
+  hipLaunchKernelGGL(k_select_lut, dim3(g.n_cams * 2 * g.n_blocks), dim3(kThreads), 0, st, g, H2, W3, b3, Y, p_new,
+                     status, tol, b, used, residual);
   return hipGetLastError();
 }
 

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "rt_internal.h"
+#include "rt_surrogate_internal.h"
 
 using namespace rc;
 
@@ -785,9 +786,10 @@ rt_status rt_surrogate_frameset(rt_ctx* ctx, const rt_mlp* w, float tol, const v
   if (e != hipSuccess) return hip_fail(e, "surrogate features and plain estimate");
   float* wp[6];
   mlp_ptrs(w, wp);
-  e = mlp_forward(wp, work->X, g.n_cams * 2 * g.n_blocks, work->H1, work->H2, work->Y, st);
-  if (e != hipSuccess) return hip_fail(e, "mlp forward");
-  e = launch_select_lut(g, work->Y, work->p_new, work->status, tol, b, work->used, work->residual, st);
+  e = mlp_hidden(wp, work->X, g.n_cams * 2 * g.n_blocks, work->H1, work->H2, st);
+  if (e != hipSuccess) return hip_fail(e, "mlp hidden layers");
+  e = launch_select_lut(g, work->H2, w->w3, w->b3, work->Y, work->p_new, work->status, tol, b, work->used,
+                        work->residual, st);
   if (e != hipSuccess) return hip_fail(e, "surrogate choice and tables");
   return whole_pass(ctx, g, fp, b, true, false, st);
 }

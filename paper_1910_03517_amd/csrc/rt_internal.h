@@ -142,26 +142,4 @@ hipError_t launch_apply(const Geo& g, const FramePtrs& fp, const Bufs& b, bool w
 hipError_t launch_zero_whole(const Geo& g, const Bufs& b, hipStream_t st);
 hipError_t launch_stream_copy(void* dst, const void* src, int64_t bytes, int vec_bytes, hipStream_t st);
 
-// Learned surrogate.
-hipError_t launch_features(const Geo& g, const uint32_t* band_hist, const uint32_t* whole_hist, float* X,
-                           hipStream_t st);
-hipError_t launch_estimate_new(const Geo& g, const uint64_t* band_sums, double* p_new, int32_t* status,
-                               hipStream_t st);
-hipError_t launch_targets(const Geo& g, const double* p_new, const int32_t* status, float* T, uint8_t* mask,
-                          hipStream_t st);
-hipError_t launch_features_new(const Geo& g, const uint32_t* band_hist, const uint64_t* band_sums,
-                               const uint32_t* whole_hist, float* X, double* p_new, int32_t* status, hipStream_t st);
-hipError_t launch_select_lut(const Geo& g, const float* Y, const double* p_new, const int32_t* status, float tol,
-                             const Bufs& b, uint8_t* used, float* residual, hipStream_t st);
-hipError_t launch_select(const Geo& g, const float* Y, const double* p_new, const int32_t* status, float tol,
-                         double* params, uint8_t* valid, uint8_t* used, float* residual, hipStream_t st);
-hipError_t mlp_forward(const float* const* w, const float* X, int n, float* H1, float* H2, float* Y, hipStream_t st);
-hipError_t mlp_backward(const float* const* w, const float* X, const float* H1, const float* H2, const float* Y,
-                        const float* T, int n, float* const* g, float* dY, float* dZ1, float* dZ2, float* part,
-                        int64_t part_floats, hipStream_t st);
-hipError_t mlp_adam(float* const* w, const float* const* g, float* const* m, float* const* v, int step, float lr,
-                    float beta1, float beta2, float eps, hipStream_t st);
-hipError_t mlp_mse(const float* Y, const float* T, int n, float* out, hipStream_t st);
-hipError_t gather_rows(const float* src, int row_len, const int32_t* idx, int n, float* dst, hipStream_t st);
-
 }  // namespace rc

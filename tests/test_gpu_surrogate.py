@@ -128,6 +128,29 @@ def test_forward_backward_adam_against_fp64():
         assert np.max(np.abs(wh[k] - Pa[k])) < 1e-6 + 1e-5 * np.max(np.abs(Pa[k])), k
 
 
+@pytest.mark.parametrize("n", [1, 5, 33, 96, 448, 2048, 2049])
+def test_forward_sizes_against_fp64(n):
+    """Forward at row counts around the tile sizes and across the switch from
+    the k-split 32 x 32 tiles (<= 2048 rows) to the 64 x 64 tiles."""
+    say(f"case: mlp forward vs fp64, {n} rows")
+    rng = np.random.default_rng(40 + n)
+    P = synth.mlp_init(6)
+    P["b1"] = rng.normal(0, 0.05, 256).astype(np.float32)
+    P["b2"] = rng.normal(0, 0.05, 256).astype(np.float32)
+    P["b3"] = rng.normal(0, 0.05, 6).astype(np.float32)
+    X = rng.uniform(0, 0.2, (n, 576)).astype(np.float32)
+    w = rt.MlpTensors(P)
+    e = dict(device="cuda", dtype=torch.float32)
+    H1, H2, Y = torch.full((n, 256), -1.0, **e), torch.full((n, 256), -1.0, **e), torch.full((n, 6), -1.0, **e)
+    rt.rt_mlp_forward(w, torch.as_tensor(X, device="cuda"), n, H1, H2, Y)
+    torch.cuda.synchronize()
+    Yo, H1o, H2o = sg.forward({k: v.astype(np.float64) for k, v in P.items()}, X)
+    assert rel(H1.cpu().numpy(), H1o) < 1e-5
+    assert rel(H2.cpu().numpy(), H2o) < 1e-5
+    assert rel(Y.cpu().numpy(), Yo) < 1e-5
+    assert np.abs(Y.cpu().numpy() - Yo).max() < 1e-5 * max(1.0, np.abs(Yo).max())
+
+
 def test_select_and_state_update_bit_exact():
     say("case: surrogate select vs oracle on GPU predictions")
     spec, cams, opts = small_rig(nb=4)
