@@ -8,6 +8,7 @@
 namespace rc {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kGemmTile = 64;   // workgroup tile (rows and columns)
 constexpr int kGemmK = 32;      // k-slab staged in LDS
@@ -160,25 +161,26 @@ __global__ __launch_bounds__(256) void k_gemm_skinny(int M, int N, int K, const 
   }
 }
 
-// The same product for few rows (the forward's layers at inference and
-// mini-batch sizes), where 64 x 64 tiles would leave most compute units idle
-// and each wave a long serial chain of MFMAs.  A workgroup of kWsWaves waves
-// owns a 32 x 32 tile; wave w sums k over its own range [w kw, (w + 1) kw)
-// (kw a multiple of 8) straight from global memory: per 8 k, lane l loads
-// A(i, k0 + 4 g .. k0 + 4 g + 3) and B(k0 + 4 g + c, j) (g = l / 32, i and j =
-// l % 32; coalesced rows of B) and issues 4 MFMAs, the c-th pairing
-// k0 + c with k0 + 4 + c.  The waves' tiles are added in LDS in wave order,
-// then the epilogue.  Requires A contiguous along k and B along j.
-constexpr int kWsWaves = 8;
+// The same product for few output rows (every product of the network at
+// inference and mini-batch sizes), where 64 x 64 tiles would leave most
+// compute units idle and each wave a long serial chain of MFMAs.  A
+// workgroup of W waves owns a 32 x 32 tile; wave w sums k over its own range
+// [w kw, (w + 1) kw) (kw a multiple of 8) straight from global memory: per 8
+// k, lane l supplies A(i, k0 + 4 g + c) and B(k0 + 4 g + c, j) for c = 0..3
+// (g = l / 32, i and j = l % 32), the c-th of 4 MFMAs pairing k0 + c with
+// k0 + 4 + c.  The loads of kWsChunk such steps are in flight together, and
+// the next chunk's are issued before the current chunk's MFMAs.  The waves'
+// tiles are added in LDS in wave order, then the epilogue; row M is the ones
+// row when ones_row is given (stored without epilogue).
 constexpr int kWsTile = 32;
-template <int EPI>
-__global__ __launch_bounds__(kWsWaves * 64) void k_gemm_wsplit(int M, int N, int K, int kw,
-                                                               const float* __restrict__ A, int64_t lda,
-                                                               const float* __restrict__ B, int64_t ldb,
-                                                               float* __restrict__ C, int ldc,
-                                                               const float* __restrict__ bias,
-                                                               const float* __restrict__ mask, int ldm) {
-  __shared__ float red[kWsWaves][16][64];
+constexpr int kWsChunk = 4;
+template <int EPI, int W>
+__global__ __launch_bounds__(W * 64) void k_gemm_wsplit(int M, int N, int K, int kw, const float* __restrict__ A,
+                                                        int64_t sai, int64_t sak, const float* __restrict__ B,
+                                                        int64_t sbk, int64_t sbj, float* __restrict__ C, int ldc,
+                                                        const float* __restrict__ bias, const float* __restrict__ mask,
+                                                        int ldm, float* __restrict__ ones_row) {
+  __shared__ float red[W][16][64];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -186,49 +188,80 @@ __global__ __launch_bounds__(kWsWaves * 64) void k_gemm_wsplit(int M, int N, int
   const int i0 = blockIdx.y * kWsTile, j0 = blockIdx.x * kWsTile;
   const int ia = i0 + (lane & 31), jb = j0 + (lane & 31);
   const bool arow = ia < M, bcol = jb < N;
-  const float* pa = A + (int64_t)(arow ? ia : 0) * lda;
-  const float* pb = B + (bcol ? jb : 0);
+  const float aone = (ones_row && ia == M) ? 1.0f : 0.0f;   // the ones row, or padding
+  const float* pa = A + (int64_t)(arow ? ia : 0) * sai;
+  const float* pb = B + (int64_t)(bcol ? jb : 0) * sbj;
   const int kbeg = wave * kw;
   const int kend = (K - kbeg) < kw ? K : kbeg + kw;
   f32x16 acc;
 #pragma unroll
   for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
-  float a[4], b[4], an[4], bn[4];
-  auto load = [&](int k0, float* av, float* bv) {
+  float a[kWsChunk][4], b[kWsChunk][4], an[kWsChunk][4], bn[kWsChunk][4];
+  // An operand contiguous along k is read 16 bytes per lane (one load for
+  // the four k of a step) where the whole quad is in range.
+  const bool a_vec = sak == 1, b_vec = sbk == 1;
+  auto load = [&](int k0, float (*av)[4], float (*bv)[4]) {
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int kk = k0 + 4 * g + c;
-      const bool in = kk < kend;
-      av[c] = (in && arow) ? pa[kk] : 0.0f;
-      bv[c] = (in && bcol) ? pb[(int64_t)kk * ldb] : 0.0f;
+    for (int s = 0; s < kWsChunk; ++s) {
+      const int kq = k0 + 8 * s + 4 * g;
+      const bool quad = kq + 3 < kend;
+      if (a_vec && arow && quad) {
+        f32x4 v;
+        __builtin_memcpy(&v, pa + kq, sizeof v);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) av[s][c] = v[c];
+      } else {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) av[s][c] = kq + c < kend ? (arow ? pa[(int64_t)(kq + c) * sak] : aone) : 0.0f;
+      }
+      if (b_vec && bcol && quad) {
+        f32x4 v;
+        __builtin_memcpy(&v, pb + kq, sizeof v);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) bv[s][c] = v[c];
+      } else {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) bv[s][c] = (kq + c < kend && bcol) ? pb[(int64_t)(kq + c) * sbk] : 0.0f;
+      }
     }
   };
+  constexpr int kSpan = 8 * kWsChunk;
   if (kbeg < kend) load(kbeg, a, b);
-  for (int k0 = kbeg; k0 < kend; k0 += 8) {
-    if (k0 + 8 < kend) load(k0 + 8, an, bn);
+  for (int k0 = kbeg; k0 < kend; k0 += kSpan) {
+    if (k0 + kSpan < kend) load(k0 + kSpan, an, bn);
 #pragma unroll
-    for (int c = 0; c < 4; ++c) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[c], b[c], acc, 0, 0, 0);
+    for (int s = 0; s < kWsChunk; ++s) {
+      if (k0 + 8 * s >= kend) break;                // wave-uniform
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      a[c] = an[c];
-      b[c] = bn[c];
+      for (int c = 0; c < 4; ++c) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s][c], b[s][c], acc, 0, 0, 0);
     }
+#pragma unroll
+    for (int s = 0; s < kWsChunk; ++s)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        a[s][c] = an[s][c];
+        b[s][c] = bn[s][c];
+      }
   }
 #pragma unroll
   for (int r = 0; r < 16; ++r) red[wave][r][lane] = acc[r];
   __syncthreads();
-  for (int e = tid; e < 16 * 64; e += kWsWaves * 64) {
+  for (int e = tid; e < 16 * 64; e += W * 64) {
     const int r = e >> 6, l = e & 63;
     float v = 0.0f;
 #pragma unroll
-    for (int w = 0; w < kWsWaves; ++w) v += red[w][r][l];
+    for (int w = 0; w < W; ++w) v += red[w][r][l];
     const int i = i0 + 8 * (r >> 2) + 4 * (l >> 5) + (r & 3);
     const int j = j0 + (l & 31);
-    if (i >= M || j >= N) continue;
-    if (EPI == kEpiBias || EPI == kEpiBiasRelu) v += bias[j];
-    if (EPI == kEpiBiasRelu) v = v > 0.0f ? v : 0.0f;
-    if (EPI == kEpiMask) v = mask[(int64_t)i * ldm + j] > 0.0f ? v : 0.0f;
-    C[(int64_t)i * ldc + j] = v;
+    if (j >= N) continue;
+    if (i < M) {
+      if (EPI == kEpiBias || EPI == kEpiBiasRelu) v += bias[j];
+      if (EPI == kEpiBiasRelu) v = v > 0.0f ? v : 0.0f;
+      if (EPI == kEpiMask) v = mask[(int64_t)i * ldm + j] > 0.0f ? v : 0.0f;
+      C[(int64_t)i * ldc + j] = v;
+    } else if (i == M && ones_row) {
+      ones_row[j] = v;
+    }
   }
 }
 
@@ -278,16 +311,22 @@ static hipError_t gemm(int M, int N, int K, const float* A, int64_t sai, int64_t
                        float* ones_row = nullptr, float* part = nullptr, int64_t part_floats = 0) {
   if (M <= 0 || N <= 0) return hipSuccess;
   const int MA = ones_row ? M + 1 : M;
+  if (MA <= kWsMaxRows) {
+    const dim3 g2((N + kWsTile - 1) / kWsTile, (MA + kWsTile - 1) / kWsTile);
+    if (K >= 512) {            // long sums: 16 waves share k
+      const int kw = ((K + 15) / 16 + 7) / 8 * 8;
+      hipLaunchKernelGGL((k_gemm_wsplit<EPI, 16>), g2, dim3(16 * 64), 0, st, M, N, K, kw, A, sai, sak, B, sbk, sbj,
+                         C, ldc, bias, mask, ldm, ones_row);
+    } else {
+      const int kw = ((K + 7) / 8 + 7) / 8 * 8;
+      hipLaunchKernelGGL((k_gemm_wsplit<EPI, 8>), g2, dim3(8 * 64), 0, st, M, N, K, kw, A, sai, sak, B, sbk, sbj,
+                         C, ldc, bias, mask, ldm, ones_row);
+    }
+    return hipGetLastError();
+  }
   if (N <= kSkinnyN) {
     hipLaunchKernelGGL((k_gemm_skinny<EPI>), dim3((MA + 3) / 4), dim3(256), 0, st, M, N, K, A, sai, sak, B, sbk, sbj,
                        C, ldc, bias, mask, ldm, ones_row);
-    return hipGetLastError();
-  }
-  if (sak == 1 && sbj == 1 && !ones_row && M <= kWsMaxRows && K >= 64) {
-    const int kw = ((K + kWsWaves - 1) / kWsWaves + 7) / 8 * 8;
-    const dim3 g2((N + kWsTile - 1) / kWsTile, (M + kWsTile - 1) / kWsTile);
-    hipLaunchKernelGGL((k_gemm_wsplit<EPI>), g2, dim3(kWsWaves * 64), 0, st, M, N, K, kw, A, sai, B, sbk, C, ldc,
-                       bias, mask, ldm);
     return hipGetLastError();
   }
   const dim3 grid((N + kGemmTile - 1) / kGemmTile, (MA + kGemmTile - 1) / kGemmTile);
@@ -322,22 +361,33 @@ __global__ __launch_bounds__(256) void k_mse_grad(const float* __restrict__ Y, c
   if (i < count) dY[i] = 2.0f * (Y[i] - T[i]) / (float)count;
 }
 
-// out[0] = mean of (Y - T)^2 over count values (one workgroup).
-__global__ __launch_bounds__(256) void k_mse(const float* __restrict__ Y, const float* __restrict__ T,
-                                             int64_t count, float* __restrict__ out) {
-  __shared__ float red[256];
+// out[0] = mean of (Y - T)^2 over count values (one workgroup of 1024
+// threads): thread t sums elements t, t + 1024, ... (eight loads in flight
+// at a time), then the waves' sums, then the 16 wave totals in order.
+__global__ __launch_bounds__(1024) void k_mse(const float* __restrict__ Y, const float* __restrict__ T,
+                                              int64_t count, float* __restrict__ out) {
+  __shared__ float red[16];
+  constexpr int kU = 8;
+  const int tid = threadIdx.x;
   float s = 0.0f;
-  for (int64_t i = threadIdx.x; i < count; i += 256) {
-    const float d = Y[i] - T[i];
-    s += d * d;
+  for (int64_t base = 0; base < count; base += 1024 * kU) {
+    float d[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int64_t i = base + (int64_t)u * 1024 + tid;
+      d[u] = i < count ? Y[i] - T[i] : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) s += d[u] * d[u];
   }
-  red[threadIdx.x] = s;
+  s = wave_sum_f32(s);
+  if ((tid & 63) == 0) red[tid >> 6] = s;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
+  if (tid == 0) {
+    float t = 0.0f;
+    for (int w = 0; w < 16; ++w) t += red[w];
+    out[0] = t / (float)count;
   }
-  if (threadIdx.x == 0) out[0] = red[0] / (float)count;
 }
 
 // The six tensors of one network as one index space for a single Adam launch.
@@ -445,7 +495,7 @@ hipError_t mlp_adam(float* const* w, const float* const* g, float* const* m, flo
 }
 
 hipError_t mlp_mse(const float* Y, const float* T, int n, float* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_mse, dim3(1), dim3(256), 0, st, Y, T, (int64_t)n * kMlpOut, out);
+  hipLaunchKernelGGL(k_mse, dim3(1), dim3(1024), 0, st, Y, T, (int64_t)n * kMlpOut, out);
   return hipGetLastError();
 }
 
