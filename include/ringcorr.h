@@ -375,15 +375,10 @@ rt_status rt_surrogate_frameset(rt_ctx* ctx, const rt_mlp* w, float tol, const v
 rt_status rt_mlp_forward(const rt_mlp* w, const float* X, int32_t n, float* H1, float* H2, float* Y, void* stream);
 
 /* Gradients of the mean squared error against T [n][6] into `grad`, from the
- * forward pass's X, H1, H2, Y; workspace dY [n][6], dZ1 and dZ2 [n][256].
- * part (may be NULL): optional float32 workspace of part_floats values; when
- * given, the two large weight gradients are summed over n in up to 8 slices
- * (deterministic order), which shares the long reductions among more
- * workgroups; 8 * 577 * 256 floats always suffice.  The result then differs
- * from the unsplit one by rounding only. */
+ * forward pass's X, H1, H2, Y; workspace dY [n][6], dZ1 and dZ2 [n][256]. */
 rt_status rt_mlp_backward(const rt_mlp* w, const float* X, const float* H1, const float* H2, const float* Y,
                           const float* T, int32_t n, const rt_mlp* grad, float* dY, float* dZ1, float* dZ2,
-                          float* part, int64_t part_floats, void* stream);
+                          void* stream);
 
 /* One Adam step (step >= 1 counts steps for the bias correction) updating w, m, v. */
 rt_status rt_mlp_adam(const rt_mlp* w, const rt_mlp* grad, const rt_mlp* m, const rt_mlp* v, int32_t step, float lr,
@@ -397,11 +392,9 @@ rt_status rt_gather_rows(const float* src, int32_t row_len, const int32_t* idx, 
 
 /* Workspace of rt_mlp_train for mini-batches of `batch` rows, float32 device
  * buffers: xb [batch][576], tb [batch][6], h1, h2, dz1, dz2 [batch][256],
- * y, dy [batch][6]; part / part_floats as for rt_mlp_backward (part may be
- * NULL). */
+ * y, dy [batch][6]. */
 typedef struct {
   float* xb; float* tb; float* h1; float* h2; float* y; float* dy; float* dz1; float* dz2;
-  float* part; int64_t part_floats;
 } rt_mlp_work;
 
 /* n_steps mini-batch steps of the surrogate's training, enqueued from the

@@ -122,45 +122,6 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const float* 
   k_gemm_body<EPI>(M, N, K, A, sai, sak, B, sbk, sbj, C, ldc, bias, mask, ldm, ones_row);
 }
 
-// The same product for N <= kSkinnyN columns: one wave per output row, lanes
-// striding over k, each column's sum reduced across the wave.  (A 64-wide
-// tile would leave most of the matrix cores idle for the network's 6 outputs.)
-constexpr int kSkinnyN = 8;
-template <int EPI>
-__global__ __launch_bounds__(256) void k_gemm_skinny(int M, int N, int K, const float* __restrict__ A, int64_t sai,
-                                                     int64_t sak, const float* __restrict__ B, int64_t sbk,
-                                                     int64_t sbj, float* __restrict__ C, int ldc,
-                                                     const float* __restrict__ bias, const float* __restrict__ mask,
-                                                     int ldm, float* __restrict__ ones_row) {
-  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);     // output row of this wave
-  const int lane = threadIdx.x & 63;
-  const int MA = ones_row ? M + 1 : M;
-  if (i >= MA) return;                                   // whole waves
-  float acc[kSkinnyN];
-#pragma unroll
-  for (int j = 0; j < kSkinnyN; ++j) acc[j] = 0.0f;
-  for (int k = lane; k < K; k += 64) {
-    const float a = i < M ? A[(int64_t)i * sai + (int64_t)k * sak] : 1.0f;
-#pragma unroll
-    for (int j = 0; j < kSkinnyN; ++j)
-      if (j < N) acc[j] += a * B[(int64_t)k * sbk + (int64_t)j * sbj];
-  }
-#pragma unroll
-  for (int j = 0; j < kSkinnyN; ++j) acc[j] = wave_sum_f32(acc[j]);
-  if (lane == 0) {
-#pragma unroll
-    for (int j = 0; j < kSkinnyN; ++j) {
-      if (j >= N) break;
-      float v = acc[j];
-      if (i == M) { ones_row[j] = v; continue; }
-      if (EPI == kEpiBias || EPI == kEpiBiasRelu) v += bias[j];
-      if (EPI == kEpiBiasRelu) v = v > 0.0f ? v : 0.0f;
-      if (EPI == kEpiMask) v = mask[(int64_t)i * ldm + j] > 0.0f ? v : 0.0f;
-      C[(int64_t)i * ldc + j] = v;
-    }
-  }
-}
-
 // The same product for few output rows (every product of the network at
 // inference and mini-batch sizes), where 64 x 64 tiles would leave most
 // compute units idle and each wave a long serial chain of MFMAs.  A
@@ -277,38 +238,10 @@ __global__ __launch_bounds__(256) void k_out_layer(int M, const float* __restric
     for (int o = 0; o < kMlpOut; ++o) Y[(int64_t)i * kMlpOut + o] = acc[o];
 }
 
-// Split-K: slice z of the product over k in [z * kc, (z + 1) * kc) into
-// part + z * MA * N (rows of A including the ones row, row-major, no epilogue).
-__global__ __launch_bounds__(256) void k_gemm_part(int M, int N, int K, int kc, const float* __restrict__ A,
-                                                   int64_t sai, int64_t sak, const float* __restrict__ B, int64_t sbk,
-                                                   int64_t sbj, float* __restrict__ part, int MA) {
-  const int z = blockIdx.z;
-  const int k0 = z * kc;
-  const int kn = (K - k0) < kc ? (K - k0) : kc;
-  if (kn <= 0) return;
-  // The slice is a product of its own: offset the operands to k0 and reuse the tile kernel's body.
-  float* slice = part + (int64_t)z * MA * N;
-  k_gemm_body<kEpiNone>(M, N, kn, A + (int64_t)k0 * sak, sai, sak, B + (int64_t)k0 * sbk, sbk, sbj, slice, N,
-                        nullptr, nullptr, 0, MA > M ? slice + (int64_t)M * N : nullptr);
-}
-
-// C = sum over the splits of the partial products, in split order; row M
-// (the ones row, if any) goes to ones_row.
-__global__ __launch_bounds__(256) void k_gemm_reduce(int M, int N, int MA, int splits, const float* __restrict__ part,
-                                                     float* __restrict__ C, int ldc, float* __restrict__ ones_row) {
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= (int64_t)MA * N) return;
-  const int i = (int)(e / N), j = (int)(e - (int64_t)i * N);
-  float v = 0.0f;
-  for (int z = 0; z < splits; ++z) v += part[(int64_t)z * MA * N + e];
-  if (i < M) C[(int64_t)i * ldc + j] = v;
-  else ones_row[j] = v;
-}
-
 template <int EPI>
 static hipError_t gemm(int M, int N, int K, const float* A, int64_t sai, int64_t sak, const float* B, int64_t sbk,
                        int64_t sbj, float* C, int ldc, const float* bias, const float* mask, int ldm, hipStream_t st,
-                       float* ones_row = nullptr, float* part = nullptr, int64_t part_floats = 0) {
+                       float* ones_row = nullptr) {
   if (M <= 0 || N <= 0) return hipSuccess;
   const int MA = ones_row ? M + 1 : M;
   if (MA <= kWsMaxRows) {
@@ -324,31 +257,7 @@ static hipError_t gemm(int M, int N, int K, const float* A, int64_t sai, int64_t
     }
     return hipGetLastError();
   }
-  if (N <= kSkinnyN) {
-    hipLaunchKernelGGL((k_gemm_skinny<EPI>), dim3((MA + 3) / 4), dim3(256), 0, st, M, N, K, A, sai, sak, B, sbk, sbj,
-                       C, ldc, bias, mask, ldm, ones_row);
-    return hipGetLastError();
-  }
   const dim3 grid((N + kGemmTile - 1) / kGemmTile, (MA + kGemmTile - 1) / kGemmTile);
-  // Long reductions (the weight gradients, K = batch) on few output tiles:
-  // split K so that more workgroups share the work, then sum the slices.
-  int splits = 1;
-  if (EPI == kEpiNone && part && grid.x * grid.y < 128 && K >= 256) {
-    splits = (int)((256 + grid.x * grid.y - 1) / (grid.x * grid.y));
-    if (splits > 8) splits = 8;
-    while (splits > 1 && (int64_t)splits * MA * N > part_floats) --splits;
-  }
-  if (splits > 1) {
-    const int kc = ((K + splits - 1) / splits + kGemmK - 1) / kGemmK * kGemmK;
-    hipLaunchKernelGGL(k_gemm_part, dim3(grid.x, grid.y, splits), dim3(256), 0, st, M, N, K, kc, A, sai, sak, B, sbk,
-                       sbj, part, MA);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    const int64_t total = (int64_t)MA * N;
-    hipLaunchKernelGGL(k_gemm_reduce, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, M, N, MA, splits, part,
-                       C, ldc, ones_row);
-    return hipGetLastError();
-  }
   hipLaunchKernelGGL((k_gemm<EPI>), grid, dim3(256), 0, st, M, N, K, A, sai, sak, B, sbk, sbj, C, ldc, bias, mask,
                      ldm, ones_row);
   return hipGetLastError();
@@ -448,8 +357,7 @@ hipError_t mlp_forward(const float* const* w, const float* X, int n, float* H1, 
 }
 
 hipError_t mlp_backward(const float* const* w, const float* X, const float* H1, const float* H2, const float* Y,
-                        const float* T, int n, float* const* g, float* dY, float* dZ1, float* dZ2, float* part,
-                        int64_t part_floats, hipStream_t st) {
+                        const float* T, int n, float* const* g, float* dY, float* dZ1, float* dZ2, hipStream_t st) {
   const int64_t cnt = (int64_t)n * kMlpOut;
   hipLaunchKernelGGL(k_mse_grad, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, Y, T, cnt, dY);
   hipError_t e = hipGetLastError();
@@ -463,14 +371,14 @@ hipError_t mlp_backward(const float* const* w, const float* X, const float* H1, 
   // dW2 = H1^T dZ2, db2 = colsum dZ2
   if (e == hipSuccess)
     e = gemm<kEpiNone>(kMlpHid, kMlpHid, n, H1, 1, kMlpHid, dZ2, kMlpHid, 1, g[2], kMlpHid, nullptr, nullptr, 0, st,
-                       g[3], part, part_floats);
+                       g[3]);
   // dZ1 = (dZ2 W2^T) * (H1 > 0)
   if (e == hipSuccess)
     e = gemm<kEpiMask>(n, kMlpHid, kMlpHid, dZ2, kMlpHid, 1, w[2], 1, kMlpHid, dZ1, kMlpHid, nullptr, H1, kMlpHid, st);
   // dW1 = X^T dZ1, db1 = colsum dZ1
   if (e == hipSuccess)
     e = gemm<kEpiNone>(kMlpIn, kMlpHid, n, X, 1, kMlpIn, dZ1, kMlpHid, 1, g[0], kMlpHid, nullptr, nullptr, 0, st,
-                       g[1], part, part_floats);
+                       g[1]);
   return e;
 }
 

@@ -810,19 +810,17 @@ rt_status rt_mlp_forward(const rt_mlp* w, const float* X, int32_t n, float* H1, 
 
 rt_status rt_mlp_backward(const rt_mlp* w, const float* X, const float* H1, const float* H2, const float* Y,
                           const float* T, int32_t n, const rt_mlp* grad, float* dY, float* dZ1, float* dZ2,
-                          float* part, int64_t part_floats, void* stream) {
+                          void* stream) {
   rt_status r = check_mlp(w, "weights");
   if (r == RT_OK) r = check_mlp(grad, "grad");
   const void* ps[8] = {X, H1, H2, Y, T, dY, dZ1, dZ2};
   for (int i = 0; r == RT_OK && i < 8; ++i) r = check_ptr(ps[i], 4, "activation or workspace");
   if (r != RT_OK) return r;
   if (n < 1) return fail(RT_EINVAL, "n < 1");
-  if (part && (!aligned(part, 4) || part_floats < 0)) return fail(RT_EINVAL, "part misaligned or part_floats < 0");
   float *wp[6], *gp[6];
   mlp_ptrs(w, wp);
   mlp_ptrs(grad, gp);
-  hipError_t e = mlp_backward(wp, X, H1, H2, Y, T, n, gp, dY, dZ1, dZ2, part, part ? part_floats : 0,
-                              (hipStream_t)stream);
+  hipError_t e = mlp_backward(wp, X, H1, H2, Y, T, n, gp, dY, dZ1, dZ2, (hipStream_t)stream);
   return e == hipSuccess ? RT_OK : hip_fail(e, "mlp backward");
 }
 
@@ -902,7 +900,7 @@ rt_status rt_mlp_train(const rt_mlp* w, const rt_mlp* grad, const rt_mlp* m, con
     if (e == hipSuccess) e = mlp_forward(wp, work->xb, batch, work->h1, work->h2, work->y, st);
     if (e == hipSuccess)
       e = mlp_backward(wp, work->xb, work->h1, work->h2, work->y, work->tb, batch, gp, work->dy, work->dz1,
-                       work->dz2, work->part, work->part ? work->part_floats : 0, st);
+                       work->dz2, st);
     if (e == hipSuccess) e = mlp_adam(wp, gp, mp, vp, step0 + s, lr, beta1, beta2, eps, st);
     if (e == hipSuccess) e = mlp_mse(work->y, work->tb, batch, losses + s, st);
   }

@@ -25,8 +25,7 @@ hipError_t launch_select(const Geo& g, const float* Y, const double* p_new, cons
 hipError_t mlp_hidden(const float* const* w, const float* X, int n, float* H1, float* H2, hipStream_t st);
 hipError_t mlp_forward(const float* const* w, const float* X, int n, float* H1, float* H2, float* Y, hipStream_t st);
 hipError_t mlp_backward(const float* const* w, const float* X, const float* H1, const float* H2, const float* Y,
-                        const float* T, int n, float* const* g, float* dY, float* dZ1, float* dZ2, float* part,
-                        int64_t part_floats, hipStream_t st);
+                        const float* T, int n, float* const* g, float* dY, float* dZ1, float* dZ2, hipStream_t st);
 hipError_t mlp_adam(float* const* w, const float* const* g, float* const* m, float* const* v, int step, float lr,
                     float beta1, float beta2, float eps, hipStream_t st);
 hipError_t mlp_mse(const float* Y, const float* T, int n, float* out, hipStream_t st);

@@ -73,8 +73,7 @@ class rt_mlp(ct.Structure):
 
 
 class rt_mlp_work(ct.Structure):
-    _fields_ = [(n, ct.c_void_p) for n in ("xb", "tb", "h1", "h2", "y", "dy", "dz1", "dz2", "part")] + [
-        ("part_floats", ct.c_int64)]
+    _fields_ = [(n, ct.c_void_p) for n in ("xb", "tb", "h1", "h2", "y", "dy", "dz1", "dz2")]
 
 
 class rt_surrogate_work(ct.Structure):
@@ -134,7 +133,7 @@ def load(path: str = LIB_PATH) -> ct.CDLL:
                                           P, ct.POINTER(rt_params_buf), ct.POINTER(rt_lut_buf),
                                           ct.POINTER(rt_surrogate_work), P]
     lib.rt_mlp_forward.argtypes = [M, P, ct.c_int32, P, P, P, P]
-    lib.rt_mlp_backward.argtypes = [M, P, P, P, P, P, ct.c_int32, M, P, P, P, P, ct.c_int64, P]
+    lib.rt_mlp_backward.argtypes = [M, P, P, P, P, P, ct.c_int32, M, P, P, P, P]
     lib.rt_mlp_adam.argtypes = [M, M, M, M, ct.c_int32, ct.c_float, ct.c_float, ct.c_float, ct.c_float, P]
     lib.rt_mlp_mse.argtypes = [P, P, ct.c_int32, P, P]
     lib.rt_gather_rows.argtypes = [P, ct.c_int32, P, ct.c_int32, P, P]
@@ -317,11 +316,9 @@ def rt_mlp_forward(w: MlpTensors, X, n, H1, H2, Y, stream=None) -> None:
     _check(load().rt_mlp_forward(ct.byref(w.c()), _p(X), n, _p(H1), _p(H2), _p(Y), _stream_handle(stream)))
 
 
-def rt_mlp_backward(w: MlpTensors, X, H1, H2, Y, T, n, grad: MlpTensors, dY, dZ1, dZ2, stream=None,
-                    part=None) -> None:
+def rt_mlp_backward(w: MlpTensors, X, H1, H2, Y, T, n, grad: MlpTensors, dY, dZ1, dZ2, stream=None) -> None:
     _check(load().rt_mlp_backward(ct.byref(w.c()), _p(X), _p(H1), _p(H2), _p(Y), _p(T), n, ct.byref(grad.c()),
-                                  _p(dY), _p(dZ1), _p(dZ2), _p(part), 0 if part is None else part.numel(),
-                                  _stream_handle(stream)))
+                                  _p(dY), _p(dZ1), _p(dZ2), _stream_handle(stream)))
 
 
 def rt_mlp_adam(w: MlpTensors, grad: MlpTensors, m: MlpTensors, v: MlpTensors, step: int, lr: float,
@@ -342,9 +339,7 @@ def rt_mlp_train(w, g, m, v, X, T, idx, batch: int, n_steps: int, step0: int, lr
                  beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8, stream=None) -> None:
     """n_steps Adam steps on mini-batches idx[s*batch:(s+1)*batch] of (X, T); work: dict of the
     rt_mlp_work tensors; losses: device float32 [n_steps]."""
-    part = work.get("part")
-    wk = rt_mlp_work(*[_p(work[n]) for n in ("xb", "tb", "h1", "h2", "y", "dy", "dz1", "dz2")], _p(part),
-                     0 if part is None else part.numel())
+    wk = rt_mlp_work(*[_p(work[n]) for n in ("xb", "tb", "h1", "h2", "y", "dy", "dz1", "dz2")])
     _check(load().rt_mlp_train(ct.byref(w.c()), ct.byref(g.c()), ct.byref(m.c()), ct.byref(v.c()), _p(X), _p(T),
                                int(X.shape[0]), _p(idx), batch, n_steps, step0, lr, beta1, beta2, eps,
                                ct.byref(wk), _p(losses), _stream_handle(stream)))

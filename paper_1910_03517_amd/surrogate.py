@@ -152,8 +152,6 @@ class Trainer:
         self.dz1 = torch.zeros((B, rt.MLP_HID), **e)
         self.dz2 = torch.zeros((B, rt.MLP_HID), **e)
         self.loss = torch.zeros(1, **e)
-        # split-K slices of the weight gradients (8 slices of the largest, 577 x 256)
-        self.part = torch.zeros(8 * (rt.MLP_IN + 1) * rt.MLP_HID, **e)
         self.device = device
 
     def epoch(self, data: Dataset) -> float:
@@ -167,7 +165,7 @@ class Trainer:
             return float("nan")
         losses = torch.zeros(steps, dtype=torch.float32, device=self.device)
         work = {"xb": self.xb, "tb": self.tb, "h1": self.h1, "h2": self.h2, "y": self.y, "dy": self.dy,
-                "dz1": self.dz1, "dz2": self.dz2, "part": self.part}
+                "dz1": self.dz1, "dz2": self.dz2}
         rt.rt_mlp_train(self.w, self.g, self.m, self.v, data.X, data.T, perm, self.batch, steps, self.step + 1,
                         self.lr, work, losses)
         self.step += steps
@@ -186,7 +184,7 @@ class Trainer:
             rt.rt_gather_rows(data.T, rt.MLP_OUT, idx, B, self.tb)
             rt.rt_mlp_forward(self.w, self.xb, B, self.h1, self.h2, self.y)
             rt.rt_mlp_backward(self.w, self.xb, self.h1, self.h2, self.y, self.tb, B, self.g, self.dy, self.dz1,
-                               self.dz2, part=self.part)
+                               self.dz2)
             self.step += 1
             rt.rt_mlp_adam(self.w, self.g, self.m, self.v, self.step, self.lr)
             rt.rt_mlp_mse(self.y, self.tb, B, self.loss)

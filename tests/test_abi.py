@@ -108,7 +108,7 @@ def test_null_arguments_are_rejected():
     assert lib.rt_surrogate_frameset(None, None, 1e-3, None, None, None, None, None, None, None,
                                      None) == rt.RT_EINVAL
     assert lib.rt_mlp_forward(None, None, 1, None, None, None, None) == rt.RT_EINVAL
-    assert lib.rt_mlp_backward(None, None, None, None, None, None, 1, None, None, None, None, None, 0,
+    assert lib.rt_mlp_backward(None, None, None, None, None, None, 1, None, None, None, None,
                                None) == rt.RT_EINVAL
     assert lib.rt_mlp_adam(None, None, None, None, 1, 1e-3, 0.9, 0.999, 1e-8, None) == rt.RT_EINVAL
     assert lib.rt_mlp_mse(None, None, 1, None, None) == rt.RT_EINVAL

@@ -107,14 +107,25 @@ def test_forward_backward_adam_against_fp64():
     gh = g.host()
     for k in rt.MlpTensors.NAMES:
         assert rel(gh[k], Go[k]) < 1e-4, k
-    # The same with the weight gradients summed in split-K slices.
-    gs = rt.MlpTensors(None)
-    part = torch.zeros(8 * 577 * 256, **e)
-    rt.rt_mlp_backward(w, Xd, H1, H2, Y, Td, n, gs, dY, dZ1, dZ2, part=part)
+    # A batch above 2048 rows: the products with one row per sample take the
+    # 64 x 64 tile kernel (with the ReLU-mask epilogue), the weight gradients
+    # still the k-split tiles, over a long sum.
+    nb = 2100
+    Xb = rng.uniform(0, 0.2, (nb, 576)).astype(np.float32)
+    Tb = rng.normal(1.0, 0.3, (nb, 6)).astype(np.float32)
+    Xbd, Tbd = torch.as_tensor(Xb, device="cuda"), torch.as_tensor(Tb, device="cuda")
+    B1, B2, BY = torch.zeros((nb, 256), **e), torch.zeros((nb, 256), **e), torch.zeros((nb, 6), **e)
+    bY, bZ1, bZ2 = torch.zeros((nb, 6), **e), torch.zeros((nb, 256), **e), torch.zeros((nb, 256), **e)
+    gb = rt.MlpTensors(None)
+    rt.rt_mlp_forward(w, Xbd, nb, B1, B2, BY)
+    rt.rt_mlp_backward(w, Xbd, B1, B2, BY, Tbd, nb, gb, bY, bZ1, bZ2)
     torch.cuda.synchronize()
-    gsh = gs.host()
+    Ybo, B1o, B2o = sg.forward(Po, Xb)
+    Gbo = sg.backward(Po, Xb, B1o, B2o, Ybo, Tb)
+    assert rel(BY.cpu().numpy(), Ybo) < 1e-4
+    gbh = gb.host()
     for k in rt.MlpTensors.NAMES:
-        assert rel(gsh[k], Go[k]) < 1e-4, k
+        assert rel(gbh[k], Gbo[k]) < 1e-4, k
     # Adam from the GPU's own gradient on both sides, two steps.
     m, v = rt.MlpTensors(None), rt.MlpTensors(None)
     Pa, Ma, Va = dict(Po), {k: np.zeros_like(x) for k, x in Po.items()}, {k: np.zeros_like(x) for k, x in Po.items()}
