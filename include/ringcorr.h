@@ -262,14 +262,18 @@ rt_status rt_graph_destroy(rt_graph* g);
 /* Synchronize the device and report RT_EDEVICE if a HIP error is pending. */
 rt_status rt_ctx_check(rt_ctx* ctx);
 
-/* Performance knobs that never change results: tile height of the apply pass
- * (rows, 1..4096; each vertical block is split into tiles of equal height of
- * at most this many rows) and the apply grid (workgroups striding over the
- * tiles; 0 = one workgroup per tile).  Synchronizes the device; rebuilds the
- * context's tile table. */
+/* Performance knobs that never change results.  grid == 0 (the default):
+ * each vertical block of each camera is cut into tiles of equal height of at
+ * most tile_rows rows (1..4096), one apply workgroup per tile.  grid > 0
+ * (up to 65536): that many workgroups, each on a contiguous share of all
+ * rows (cameras in index order) of equal bytes, +- one row, cut into
+ * segments at camera and block boundaries and at most tile_rows rows; this
+ * balances the work per compute unit when the tile count does not divide
+ * evenly over them.  Synchronizes the device; rebuilds the context's tables. */
 rt_status rt_ctx_tune(rt_ctx* ctx, int32_t tile_rows, int32_t grid);
 
-/* Current knobs and the resulting number of apply tiles (any pointer may be NULL). */
+/* Current knobs (grid as requested, 0 = the default) and the resulting
+ * number of apply segments (any pointer may be NULL). */
 rt_status rt_ctx_tuning(const rt_ctx* ctx, int32_t* tile_rows, int32_t* grid, int32_t* n_tiles);
 
 /* Instrumentation: with slots > 0, every `every`-th later apply kernel launch

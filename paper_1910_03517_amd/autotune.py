@@ -1,6 +1,6 @@
-"""Autotuner for the apply pass's tile shape.
+"""Autotuner for the apply pass's work split.
 
-Searches the runtime knobs of a context (tile height in rows and apply
+Searches the runtime knobs of a context (segment height in rows and apply
 grid; see rt_ctx_tune) by timing the full frame-set on the device, and
 caches the winner per (GPU architecture, rig signature, options) in a JSON
 file.  The knobs never change results, only speed.
@@ -17,8 +17,8 @@ import os
 from dataclasses import asdict, dataclass
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "ringcorr", "autotune.json")
-TILE_ROWS = (8, 16, 24, 32, 48, 64, 96)
-GRIDS = (0, 1024, 2048)
+TILE_ROWS = (8, 16, 32, 64)
+GRIDS = (0, 512, 1024, 1280)
 
 
 @dataclass(frozen=True)

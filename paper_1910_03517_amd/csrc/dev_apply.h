@@ -138,10 +138,18 @@ __device__ inline uint32_t one_sample(uint32_t x, int c, int p, const PixConst& 
   return __builtin_amdgcn_udot2(__builtin_bit_cast(u16x2, xf), __builtin_bit_cast(u16x2, pc.wp[p]), 128u, false) >> 8;
 }
 
-// Tile ti of the context.  WTAB: weights from the caller's table (true) or
-// from their closed form (false); both give the same integers.
+// Segment ti of the context.  WTAB: weights from the caller's table (true) or
+// from their closed form (false); both give the same integers.  With
+// statistics, `first` clears the LDS histogram (the first segment of its
+// camera in this workgroup's run) and `last` adds it to the whole-frame
+// statistics (the camera's last segment in the run); 16-bit samples, whose
+// sums are kept in registers, and the packed histogram, whose counters are
+// bounded per segment, do both on every segment.
 template <int C, int BPS, bool WRITE, bool STATS, bool WTAB, bool DIRECT>
-__device__ void apply_tile(const Geo& g, const FramePtrs& fp, const Bufs& b, int ti, ApplyLds& L) {
+__device__ void apply_tile(const Geo& g, const FramePtrs& fp, const Bufs& b, int ti, ApplyLds& L, bool first,
+                           bool last) {
+  const bool clear = first || BPS == 2 || kPack;
+  const bool flush = last || BPS == 2 || kPack;
   constexpr int NW = C * BPS;    // dwords per 4-pixel group
   constexpr int SPG = 4 * C;     // samples per group
   const int tid = threadIdx.x;
@@ -180,7 +188,7 @@ __device__ void apply_tile(const Geo& g, const FramePtrs& fp, const Bufs& b, int
       L.q[tid] = b.q16[((tid >> 1) ? u_right : u_left) * 2 + (tid & 1)];
     }
   }
-  if (STATS) {
+  if (STATS && clear) {
     for (int i = tid; i < kHistWords / kCS * C; i += kThreads) L.hist[i] = 0;
   }
   __syncthreads();
@@ -268,8 +276,8 @@ __device__ void apply_tile(const Geo& g, const FramePtrs& fp, const Bufs& b, int
     }
   }
 
-  if (STATS) {
-    // The tile's histogram (replicas summed) and its share of (n, S1, S2) -
+  if (STATS && flush) {
+    // The run's histogram of the camera (replicas summed) and its share of (n, S1, S2) -
     // linear in the histogram for 8-bit samples, from the sample sums for
     // 16-bit ones - are added to the camera's whole-frame statistics.
     __syncthreads();
@@ -327,17 +335,18 @@ __device__ inline bool tile_direct(const Geo& g, const Bufs& b, int ti) {
 }
 
 template <bool WRITE, bool STATS, bool WTAB>
-__device__ inline void apply_tile_dispatch(const Geo& g, const FramePtrs& fp, const Bufs& b, int ti, ApplyLds& L) {
+__device__ inline void apply_tile_dispatch(const Geo& g, const FramePtrs& fp, const Bufs& b, int ti, ApplyLds& L,
+                                           bool first, bool last) {
   const DevCam cam = uniform_cam(g.cams[uniform(g.tiles[ti].cam)]);
-  if (cam.bps == 2) apply_tile<1, 2, WRITE, STATS, WTAB, false>(g, fp, b, ti, L);
+  if (cam.bps == 2) apply_tile<1, 2, WRITE, STATS, WTAB, false>(g, fp, b, ti, L, first, last);
   else if (WRITE && STATS && RC_APPLY_DIRECT && tile_direct(g, b, ti)) {
     // Measured on MI355X: faster than the LDS tables when the pass also
     // builds the histogram (the LDS is then busy with its atomics), slower
     // for the apply alone.
-    if (cam.channels == 3) apply_tile<3, 1, WRITE, STATS, WTAB, true>(g, fp, b, ti, L);
-    else apply_tile<1, 1, WRITE, STATS, WTAB, true>(g, fp, b, ti, L);
-  } else if (cam.channels == 3) apply_tile<3, 1, WRITE, STATS, WTAB, false>(g, fp, b, ti, L);
-  else apply_tile<1, 1, WRITE, STATS, WTAB, false>(g, fp, b, ti, L);
+    if (cam.channels == 3) apply_tile<3, 1, WRITE, STATS, WTAB, true>(g, fp, b, ti, L, first, last);
+    else apply_tile<1, 1, WRITE, STATS, WTAB, true>(g, fp, b, ti, L, first, last);
+  } else if (cam.channels == 3) apply_tile<3, 1, WRITE, STATS, WTAB, false>(g, fp, b, ti, L, first, last);
+  else apply_tile<1, 1, WRITE, STATS, WTAB, false>(g, fp, b, ti, L, first, last);
 }
 
 }  // namespace rc

@@ -5,8 +5,10 @@
 
 namespace rc {
 
-// Workgroups stride over the tiles (one tile each when the grid equals the
-// tile count).  Tiles are independent: no workgroup waits for another.
+// Workgroup w takes its run of segments (one tile, or a contiguous share of
+// all rows balanced by bytes); the histogram of a camera stays in LDS across
+// the run's segments of that camera and is added to the whole-frame
+// statistics once, after its last one.  No workgroup waits for another.
 #ifndef RC_APPLY_WAVES
 #define RC_APPLY_WAVES 1
 #endif
@@ -14,16 +16,21 @@ template <bool WRITE, bool STATS>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(RC_APPLY_WAVES)))
 void k_apply(Geo g, FramePtrs fp, Bufs b) {
   __shared__ ApplyLds L;
-  for (int ti = blockIdx.x; ti < g.n_tiles; ti += gridDim.x) {
-    if (!cam_active(g, g.tiles[ti].cam)) continue;   // uniform over the workgroup
-    apply_tile_dispatch<WRITE, STATS, true>(g, fp, b, ti, L);
+  const int s0 = uniform(g.wg_seg[blockIdx.x]), s1 = uniform(g.wg_seg[blockIdx.x + 1]);
+  int prev = -1;
+  for (int s = s0; s < s1; ++s) {
+    const int cam = uniform(g.tiles[s].cam);
+    if (!cam_active(g, cam)) continue;   // uniform over the workgroup
+    const bool first = cam != prev;
+    const bool last = s + 1 == s1 || uniform(g.tiles[s + 1].cam) != cam;
+    apply_tile_dispatch<WRITE, STATS, true>(g, fp, b, s, L, first, last);
     __syncthreads();
+    prev = cam;
   }
 }
 
 hipError_t launch_apply(const Geo& g, const FramePtrs& fp, const Bufs& b, bool write, bool stats, hipStream_t st) {
-  const int n = (g.apply_grid > 0 && g.apply_grid < g.n_tiles) ? g.apply_grid : g.n_tiles;
-  const dim3 grid(n), block(kThreads);
+  const dim3 grid(g.n_wg), block(kThreads);
   if (write && stats) hipLaunchKernelGGL((k_apply<true, true>), grid, block, 0, st, g, fp, b);
   else if (write) hipLaunchKernelGGL((k_apply<true, false>), grid, block, 0, st, g, fp, b);
   else if (stats) hipLaunchKernelGGL((k_apply<false, true>), grid, block, 0, st, g, fp, b);

@@ -24,9 +24,10 @@ struct rt_ctx {
   std::vector<Tile> htiles;
   int w_max = 0;
   int tile_rows = 0;
-  int grid = 0;             // persistent grid size (0 = fill the device)
+  int grid = 0;             // apply workgroups (0 = one per tile)
   DevCam* dcams = nullptr;
   Tile* dtiles = nullptr;
+  int32_t* dwg = nullptr;   // [n_wg + 1] first segment of each apply workgroup
 
   // Optional timing of the apply kernel: events recorded right before and
   // after each apply launch, in a ring of n_timing slots.
@@ -70,6 +71,7 @@ rt_status hip_fail(hipError_t e, const char* what) {
 
 constexpr int kMaxDim = 32768;
 constexpr int kDefaultTileRows = 32;
+constexpr int kMaxApplyGrid = 1 << 16;
 
 bool aligned(const void* p, uintptr_t a) { return ((uintptr_t)p % a) == 0; }
 
@@ -132,39 +134,93 @@ rt_status check_active(const rt_ctx* ctx, uint64_t active) {
 // Tile table and device tables.  Every block is split into
 // ceil(rows / cap) tiles of equal height (+-1 row), cap = tile_rows or less
 // where the apply pass's packed histogram needs it; tiles are camera-major.
-static rt_status build_tables(rt_ctx* ctx, int tile_rows) {
+// Apply work.  grid == 0: every vertical block of every camera is cut into
+// ceil(rows / cap) tiles of equal height (+-1 row), one workgroup per tile.
+// grid > 0: `grid` workgroups, each on a contiguous share of all rows
+// (cameras in index order) of equal bytes, +-1 row, cut into segments at
+// camera and block boundaries and at most cap rows.  cap = tile_rows, or
+// less where the packed histogram needs it.
+static rt_status build_tables(rt_ctx* ctx, int tile_rows, int grid) {
   const int n_cams = ctx->n_cams;
   const int nb = ctx->opts.n_blocks;
   ctx->tile_rows = tile_rows;
+  ctx->grid = grid;
   ++ctx->generation;
   ctx->htiles.clear();
-  for (int k = 0; k < n_cams; ++k) {
+  // Rows [a, e) of camera k, cut at block boundaries and at most cap rows.
+  auto emit = [&](int k, int a, int e) {
     const int H = ctx->cams[k].height;
     const int cap = std::min(tile_rows, max_tile_rows(ctx->cams[k].width));
-    ctx->hcams[k].tile_begin = (int32_t)ctx->htiles.size();
     for (int j = 0; j < nb; ++j) {
-      const int r0 = (int)((int64_t)j * H / nb), r1 = (int)((int64_t)(j + 1) * H / nb);
-      const int rows = r1 - r0;
+      const int b0 = std::max(a, (int)((int64_t)j * H / nb)), b1 = std::min(e, (int)((int64_t)(j + 1) * H / nb));
+      const int rows = b1 - b0;
       if (rows <= 0) continue;
       const int parts = (rows + cap - 1) / cap;
       for (int p = 0; p < parts; ++p)
-        ctx->htiles.push_back(Tile{k, j, r0 + (int)((int64_t)p * rows / parts), r0 + (int)((int64_t)(p + 1) * rows / parts)});
+        ctx->htiles.push_back(
+            Tile{k, j, b0 + (int)((int64_t)p * rows / parts), b0 + (int)((int64_t)(p + 1) * rows / parts)});
     }
-    ctx->hcams[k].tile_end = (int32_t)ctx->htiles.size();
+  };
+  std::vector<int32_t> wg;
+  int G = 0;
+  if (grid == 0) {
+    for (int k = 0; k < n_cams; ++k) emit(k, 0, ctx->cams[k].height);
+    G = (int)ctx->htiles.size();
+    wg.resize(G + 1);
+    for (int w = 0; w <= G; ++w) wg[w] = w;
+  } else {
+    // Share w of G starts at the first row whose byte offset reaches w / G of the total.
+    G = grid;
+    std::vector<int64_t> base(n_cams + 1, 0);
+    for (int k = 0; k < n_cams; ++k)
+      base[k + 1] = base[k] + (int64_t)ctx->cams[k].height * ctx->hcams[k].row_bytes;
+    auto share_start = [&](int w, int& cam, int& row) {
+      const int64_t target = (int64_t)((__int128)w * base[n_cams] / G);
+      cam = 0;
+      while (cam < n_cams && base[cam + 1] <= target) ++cam;
+      if (cam == n_cams) { row = 0; return; }
+      const int64_t rb = ctx->hcams[cam].row_bytes;
+      row = (int)((target - base[cam] + rb - 1) / rb);
+      if (row >= ctx->cams[cam].height) { ++cam; row = 0; }
+    };
+    wg.resize(G + 1);
+    int c0, r0s;
+    share_start(0, c0, r0s);
+    for (int w = 0; w < G; ++w) {
+      int c1, r1s;
+      share_start(w + 1, c1, r1s);
+      wg[w] = (int32_t)ctx->htiles.size();
+      for (int k = c0; k <= c1 && k < n_cams; ++k) emit(k, k == c0 ? r0s : 0, k == c1 ? r1s : ctx->cams[k].height);
+      c0 = c1;
+      r0s = r1s;
+    }
+  }
+  wg[G] = (int32_t)ctx->htiles.size();
+  for (int k = 0; k < n_cams; ++k) ctx->hcams[k].tile_begin = ctx->hcams[k].tile_end = 0;
+  for (size_t i = ctx->htiles.size(); i-- > 0;) {
+    DevCam& d = ctx->hcams[ctx->htiles[i].cam];
+    if (d.tile_end == 0) d.tile_end = (int32_t)i + 1;
+    d.tile_begin = (int32_t)i;
   }
   const size_t nt = ctx->htiles.size();
   if (ctx->dtiles) (void)hipFree(ctx->dtiles);
+  if (ctx->dwg) (void)hipFree(ctx->dwg);
   ctx->dtiles = nullptr;
+  ctx->dwg = nullptr;
   hipError_t e = hipSuccess;
   if (!ctx->dcams) e = hipMalloc((void**)&ctx->dcams, sizeof(DevCam) * n_cams);
-  if (e == hipSuccess) e = hipMalloc((void**)&ctx->dtiles, sizeof(Tile) * nt);
+  if (e == hipSuccess) e = hipMalloc((void**)&ctx->dtiles, sizeof(Tile) * std::max<size_t>(nt, 1));
+  if (e == hipSuccess) e = hipMalloc((void**)&ctx->dwg, sizeof(int32_t) * wg.size());
   if (e != hipSuccess) return fail(RT_ENOMEM, "device tables: %s", hipGetErrorString(e));
   e = hipMemcpy(ctx->dcams, ctx->hcams.data(), sizeof(DevCam) * n_cams, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(ctx->dtiles, ctx->htiles.data(), sizeof(Tile) * nt, hipMemcpyHostToDevice);
+  if (e == hipSuccess && nt) e = hipMemcpy(ctx->dtiles, ctx->htiles.data(), sizeof(Tile) * nt, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(ctx->dwg, wg.data(), sizeof(int32_t) * wg.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e, "uploading context tables");
   Geo& g = ctx->geo;
   g.cams = ctx->dcams;
   g.tiles = ctx->dtiles;
+  g.wg_seg = ctx->dwg;
+  g.n_wg = G;
   g.n_cams = n_cams;
   g.n_blocks = nb;
   g.w_max = ctx->w_max;
@@ -275,7 +331,7 @@ rt_status rt_ctx_create(const rt_camera_desc* cams, int32_t n_cams, const rt_opt
     }
     ctx->w_max = std::max(ctx->w_max, c.width);
   }
-  rt_status st = build_tables(ctx, kDefaultTileRows);
+  rt_status st = build_tables(ctx, kDefaultTileRows, 0);
   if (st != RT_OK) {
     rt_ctx_destroy(ctx);
     return st;
@@ -299,6 +355,7 @@ rt_status rt_ctx_destroy(rt_ctx* ctx) {
   free_timing(ctx);
   if (ctx->dcams) (void)hipFree(ctx->dcams);
   if (ctx->dtiles) (void)hipFree(ctx->dtiles);
+  if (ctx->dwg) (void)hipFree(ctx->dwg);
   delete ctx;
   return RT_OK;
 }
@@ -489,15 +546,11 @@ rt_status rt_ctx_check(rt_ctx* ctx) {
 rt_status rt_ctx_tune(rt_ctx* ctx, int32_t tile_rows, int32_t grid) {
   if (!ctx) return fail(RT_EINVAL, "ctx is NULL");
   if (tile_rows < 1 || tile_rows > 4096) return fail(RT_EINVAL, "tile_rows %d outside 1..4096", tile_rows);
-  if (grid < 0) return fail(RT_EINVAL, "grid %d < 0", grid);
+  if (grid < 0 || grid > kMaxApplyGrid) return fail(RT_EINVAL, "grid %d outside 0..%d", grid, kMaxApplyGrid);
   hipError_t e = hipDeviceSynchronize();
   if (e != hipSuccess) return hip_fail(e, "synchronize");
-  ctx->grid = grid;
-  ctx->geo.apply_grid = grid;
-  if (tile_rows == ctx->tile_rows) return RT_OK;
-  rt_status r = build_tables(ctx, tile_rows);
-  ctx->geo.apply_grid = grid;
-  return r;
+  if (tile_rows == ctx->tile_rows && grid == ctx->grid) return RT_OK;
+  return build_tables(ctx, tile_rows, grid);
 }
 
 rt_status rt_graph_create(rt_ctx* ctx, const void* const* frames, void* const* out_frames, const rt_lut_buf* lut,

@@ -48,7 +48,8 @@ struct DevCam {
   int64_t pitch;         // bytes between rows
 };
 
-// One unit of the apply pass: rows [r0, r1) of block `block` of camera `cam`.
+// One segment of the apply pass: rows [r0, r1) of block `block` of camera
+// `cam`.  Each apply workgroup takes a contiguous run of segments.
 struct Tile {
   int32_t cam, block, r0, r1;
 };
@@ -76,9 +77,10 @@ struct Bufs {
 struct Geo {
   const DevCam* cams;    // device array [K]
   const Tile* tiles;     // device array [n_tiles], camera-major
+  const int32_t* wg_seg; // device array [n_wg + 1]: workgroup w takes segments [wg_seg[w], wg_seg[w + 1])
   int32_t n_cams, n_blocks, w_max, n_tiles;
   int32_t mode;
-  int32_t apply_grid;    // 0: one workgroup per tile; > 0: that many workgroups stride over the tiles
+  int32_t n_wg;          // apply workgroups
   double alpha, a_min, a_max;
   uint64_t active;       // cameras processed by this launch (bit k = camera k)
 };

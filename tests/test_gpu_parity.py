@@ -171,10 +171,12 @@ def test_determinism_repeated_runs():
     rig.close()
 
 
-@pytest.mark.parametrize("tile_rows,grid", [(1, 0), (3, 1), (16, 7), (64, 0), (4096, 2)])
+@pytest.mark.parametrize("tile_rows,grid", [(1, 0), (3, 1), (16, 7), (64, 0), (4096, 2), (2, 5000), (5, 3)])
 def test_frameset_tuning_knobs_do_not_change_results(tile_rows, grid):
-    """Tile height and apply grid (down to one workgroup striding over every
-    tile) are performance knobs only."""
+    """Segment height and apply grid are performance knobs only: one
+    workgroup over every row of every camera (the histogram of each camera
+    carried across its segments, 8-bit and 12-bit cameras in one run), shares
+    that cross cameras, and more workgroups than rows (empty shares)."""
     say(f"case: knobs tile_rows={tile_rows} grid={grid}")
     rng = np.random.default_rng(tile_rows * 31 + grid)
     spec = ([synth.CamSpec(300, 77, 3, 8, 0, p) for p in range(3)]
