@@ -265,11 +265,13 @@ rt_status rt_ctx_check(rt_ctx* ctx);
 /* Performance knobs that never change results.  grid == 0 (the default):
  * each vertical block of each camera is cut into tiles of equal height of at
  * most tile_rows rows (1..4096), one apply workgroup per tile.  grid > 0
- * (up to 65536): that many workgroups, each on a contiguous share of all
- * rows (cameras in index order) of equal bytes, +- one row, cut into
- * segments at camera and block boundaries and at most tile_rows rows; this
- * balances the work per compute unit when the tile count does not divide
- * evenly over them.  Synchronizes the device; rebuilds the context's tables. */
+ * (up to 65536): that many workgroups, each on a contiguous share of rows,
+ * cut into segments at block boundaries and at most tile_rows rows; with at
+ * least one workgroup per camera every camera gets a whole number of shares
+ * (one plus its part of the rest by bytes) split evenly by rows, with fewer
+ * the shares are equal in bytes and run across cameras.  This balances the
+ * work per compute unit when the tile count does not divide evenly over them.
+ * Synchronizes the device; rebuilds the context's tables. */
 rt_status rt_ctx_tune(rt_ctx* ctx, int32_t tile_rows, int32_t grid);
 
 /* Current knobs (grid as requested, 0 = the default) and the resulting

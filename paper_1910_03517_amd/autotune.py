@@ -18,7 +18,7 @@ from dataclasses import asdict, dataclass
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "ringcorr", "autotune.json")
 TILE_ROWS = (8, 16, 32, 64)
-GRIDS = (0, 512, 1024, 1280)
+GRIDS = (0, 512, 768, 1024)
 
 
 @dataclass(frozen=True)

@@ -138,16 +138,66 @@ __device__ inline uint32_t one_sample(uint32_t x, int c, int p, const PixConst& 
   return __builtin_amdgcn_udot2(__builtin_bit_cast(u16x2, xf), __builtin_bit_cast(u16x2, pc.wp[p]), 128u, false) >> 8;
 }
 
-// Segment ti of the context.  WTAB: weights from the caller's table (true) or
-// from their closed form (false); both give the same integers.  With
-// statistics, `first` clears the LDS histogram (the first segment of its
-// camera in this workgroup's run) and `last` adds it to the whole-frame
-// statistics (the camera's last segment in the run); 16-bit samples, whose
-// sums are kept in registers, and the packed histogram, whose counters are
-// bounded per segment, do both on every segment.
+// Adds the workgroup's LDS histogram of camera `cam` (replicas summed) and
+// its share of (n, S1, S2) - linear in the histogram for 8-bit samples, from
+// the sample sums a1, a2 for 16-bit ones - to the camera's whole-frame
+// statistics.
+template <int C, int BPS>
+__device__ inline void flush_whole(const Geo& g, const Bufs& b, int cam, ApplyLds& L, unsigned long long a1,
+                                   unsigned long long a2) {
+  const int tid = threadIdx.x;
+  __syncthreads();
+  uint32_t* gh = b.whole_hist + (int64_t)cam * kCS * kNB;
+  uint32_t h[kCS];
+#pragma unroll
+  for (int c = 0; c < kCS; ++c) {
+    uint32_t sum = 0;
+    if (c < C) {
+      if (kPack) {
+        // Thread tid owns bin tid; the replica order is rotated per bin pair
+        // so that a half-wave reads 16 distinct banks (pairs share a word).
+        const int pair = tid >> 1, sh = (tid & 1) << 4;
+#pragma unroll 8
+        for (int i = 0; i < kRep; ++i)
+          sum += (L.hist[(c * (kNB / 2) + pair) * kRep + ((i + pair) & (kRep - 1))] >> sh) & 0xffffu;
+      } else {
+#pragma unroll
+        for (int r = 0; r < kRep; ++r) sum += L.hist[(c * kNB + tid) * kRep + r];
+      }
+    }
+    h[c] = sum;
+    if (sum) atomicAdd(&gh[c * kNB + tid], sum);
+  }
+  const unsigned long long x = (unsigned long long)tid;
+  const unsigned long long h0 = h[0], h1 = h[1], h2 = h[2];
+  block_sums(
+      (BPS == 2) ? 3 : 3 * C,
+      [=](int i) -> unsigned long long {
+        const int c = i / 3, m = i - 3 * (i / 3);
+        const unsigned long long hc = c == 0 ? h0 : (c == 1 ? h1 : h2);
+        if (m == 0) return hc;
+        if (BPS == 2) return m == 1 ? a1 : a2;
+        return m == 1 ? hc * x : hc * x * x;
+      },
+      [&](int i, unsigned long long tot) {
+        if (tot) atomicAdd((unsigned long long*)&b.whole_sums[(int64_t)cam * 9 + i], tot);
+      },
+      L.red);
+}
+
+// Segments [ti, te) of the context, all of one camera (te = ti + 1 unless
+// DIRECT: the direct maps of each segment's block are switched inside the
+// column-group loop, so a thread keeps its weights across the segments).
+// WTAB: weights from the caller's table (true) or from their closed form
+// (false); both give the same integers.  With statistics, `first` clears the
+// LDS histogram (the first segment of its camera in this workgroup's run) and
+// `last` adds it to the whole-frame statistics (the camera's last segment in
+// the run); 16-bit samples, whose sums are kept in registers, and the packed
+// histogram, whose counters are bounded per segment, do both on every
+// segment.
 template <int C, int BPS, bool WRITE, bool STATS, bool WTAB, bool DIRECT>
-__device__ void apply_tile(const Geo& g, const FramePtrs& fp, const Bufs& b, int ti, ApplyLds& L, bool first,
-                           bool last) {
+__device__ void apply_tile(const Geo& g, const FramePtrs& fp, const Bufs& b, int ti, int te, ApplyLds& L,
+                           bool first, bool last) {
   const bool clear = first || BPS == 2 || kPack;
   const bool flush = last || BPS == 2 || kPack;
   constexpr int NW = C * BPS;    // dwords per 4-pixel group
@@ -164,16 +214,25 @@ __device__ void apply_tile(const Geo& g, const FramePtrs& fp, const Bufs& b, int
   // Stage the tables of both sides of the tile's block; clear the histogram.
   const int64_t u_left = unit_index(t.cam, 0, t.block, 0, g.n_blocks);
   const int64_t u_right = unit_index(t.cam, 1, t.block, 0, g.n_blocks);
-  int32_t dA[2][kCS], dC[2][kCS];    // direct 8-bit maps, uniform over the tile
-  if (WRITE && DIRECT) {
+  // Direct 8-bit maps (uniform): those of the first two segments' blocks are
+  // loaded here, before the column loop, so that switching between them
+  // costs no memory latency; later segments of a longer run load theirs.
+  int32_t dA[2][2][kCS], dC[2][2][kCS];
+  auto load_direct = [&](int block, int32_t (&A)[2][kCS], int32_t (&Cc)[2][kCS]) {
+    const int64_t ul = unit_index(t.cam, 0, block, 0, g.n_blocks), ur = unit_index(t.cam, 1, block, 0, g.n_blocks);
 #pragma unroll
     for (int sd = 0; sd < 2; ++sd)
 #pragma unroll
       for (int c = 0; c < kCS; ++c) {
-        const int64_t u = (sd ? u_right : u_left) + c;
-        dA[sd][c] = uniform((int32_t)b.q16[u * 2]);
-        dC[sd][c] = uniform((int32_t)(b.q16[u * 2 + 1] + 32768));
+        const int64_t u = (sd ? ur : ul) + c;
+        A[sd][c] = uniform((int32_t)b.q16[u * 2]);
+        Cc[sd][c] = uniform((int32_t)(b.q16[u * 2 + 1] + 32768));
       }
+  };
+  const Tile t1 = (DIRECT && te - ti > 1) ? uniform_tile(g.tiles[ti + 1]) : t;
+  if (WRITE && DIRECT) {
+    load_direct(t.block, dA[0], dC[0]);
+    if (te - ti > 1) load_direct(t1.block, dA[1], dC[1]);
   }
   if (WRITE && !DIRECT) {
     if (BPS == 1) {
@@ -214,25 +273,34 @@ __device__ void apply_tile(const Geo& g, const FramePtrs& fp, const Bufs& b, int
       pc.wp[p] = (256u - w) | (w << 16);
       pc.lb[p] = side * kCS * kNB;
       if (BPS == 2 && WRITE) { pc.qa[p] = L.q[side * 2]; pc.qb[p] = L.q[side * 2 + 1]; }
-      if (DIRECT && WRITE) {
-#pragma unroll
-        for (int c = 0; c < kCS; ++c) {
-          pc.da[p][c] = side ? dA[1][c] : dA[0][c];
-          pc.dc[p][c] = side ? dC[1][c] : dC[0][c];
-        }
-      }
     }
     const int cbyte = col0 * C * BPS;
 
+   for (int si = ti; si < te; ++si) {
+    const Tile ts = si == ti ? t : (si == ti + 1 ? t1 : uniform_tile(g.tiles[si]));
+    if (DIRECT && WRITE) {
+      const int q = si == ti ? 0 : 1;
+      if (si > ti + 1) load_direct(ts.block, dA[1], dC[1]);
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        const bool right = col0 + p >= half;
+#pragma unroll
+        for (int c = 0; c < kCS; ++c) {
+          pc.da[p][c] = right ? dA[q][1][c] : dA[q][0][c];
+          pc.dc[p][c] = right ? dC[q][1][c] : dC[q][0][c];
+        }
+      }
+    }
+
     if (npx == 4) {
-      for (int row = t.r0; row < t.r1; row += kUnroll) {
+      for (int row = ts.r0; row < ts.r1; row += kUnroll) {
         uint32_t d[kUnroll][NW];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u)
-          if (row + u < t.r1) load_group<NW>(rin, (row + u) * pitch + cbyte, d[u]);
+          if (row + u < ts.r1) load_group<NW>(rin, (row + u) * pitch + cbyte, d[u]);
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
-          if (row + u < t.r1) {
+          if (row + u < ts.r1) {
             uint32_t o[NW];
 #pragma unroll
             for (int q = 0; q < NW; ++q) o[q] = 0;
@@ -255,7 +323,7 @@ __device__ void apply_tile(const Geo& g, const FramePtrs& fp, const Bufs& b, int
       }
     } else {
       // Ragged end of the row: sample by sample, touching only the row's bytes.
-      for (int row = t.r0; row < t.r1; ++row) {
+      for (int row = ts.r0; row < ts.r1; ++row) {
         const int off = row * pitch + cbyte;
 #pragma unroll
         for (int i = 0; i < SPG; ++i) {
@@ -274,50 +342,142 @@ __device__ void apply_tile(const Geo& g, const FramePtrs& fp, const Bufs& b, int
         }
       }
     }
+   }
   }
 
-  if (STATS && flush) {
-    // The run's histogram of the camera (replicas summed) and its share of (n, S1, S2) -
-    // linear in the histogram for 8-bit samples, from the sample sums for
-    // 16-bit ones - are added to the camera's whole-frame statistics.
-    __syncthreads();
-    uint32_t* gh = b.whole_hist + (int64_t)t.cam * kCS * kNB;
-    uint32_t h[kCS];
+  if (STATS && flush) flush_whole<C, BPS>(g, b, t.cam, L, a1, a2);
+}
+
+// One 8-bit sample through the direct map of constants (a, c) (scalar: the
+// wave lies on one side of the frame), blended with the weight pair wp.
+__device__ inline uint32_t direct_sample(uint32_t x, int32_t a, int32_t c, uint32_t wp) {
+  const int32_t a24 = (int32_t)((uint32_t)a << 8) >> 8;
+  int32_t v = a24 * (int32_t)x + c;
+  v = v < 0 ? 0 : (v > 0xffffff ? 0xffffff : v);
+  const uint32_t xf = ((uint32_t)v & 0xffff0000u) | x;
+  return __builtin_amdgcn_udot2(__builtin_bit_cast(u16x2, xf), __builtin_bit_cast(u16x2, wp), 128u, false) >> 8;
+}
+
+// Direct-map constants of this many blocks fit in the LDS table area.
+constexpr int kRunBlocks = (int)(sizeof(ApplyLds::lut) / (2 * kCS * 2 * sizeof(int32_t)));
+
+// Apply with statistics over segments [ti, te) of one 8-bit camera: their
+// rows are consecutive, every block among them has direct maps (at most
+// kRunBlocks blocks), and the frame's half width is a multiple of 4.  The
+// 4-pixel groups of each half are numbered separately, the right half's
+// starting at a multiple of 64, so every wave lies on one side and its map
+// constants are scalar; one row loop covers all the segments, taking the next
+// block's constants (staged in LDS) at its first row.  Same results as
+// apply_tile.
+template <int C, bool WTAB>
+__device__ void apply_run_direct(const Geo& g, const FramePtrs& fp, const Bufs& b, int ti, int te, ApplyLds& L,
+                                 bool first, bool last) {
+  constexpr int NW = C;          // dwords per 4-pixel group
+  const int tid = threadIdx.x;
+  const Tile t0 = uniform_tile(g.tiles[ti]);
+  const int R0 = t0.r0, R1 = uniform(g.tiles[te - 1].r1);
+  const int j0 = t0.block, j1 = uniform(g.tiles[te - 1].block);
+  const DevCam cam = uniform_cam(g.cams[t0.cam]);
+  const int W = cam.width, half = cam.half, H = cam.height, nb = g.n_blocks;
+  const int pitch = (int)cam.pitch;
+
+  // [block - j0][side][channel][a, c]
+  int32_t* cst = reinterpret_cast<int32_t*>(L.lut);
+  for (int i = tid; i < (j1 - j0 + 1) * 2 * kCS; i += kThreads) {
+    const int jj = i / (2 * kCS), sd = (i / kCS) & 1, c = i % kCS;
+    const int64_t u = unit_index(t0.cam, sd, j0 + jj, c, nb);
+    cst[i * 2] = (int32_t)b.q16[u * 2];
+    cst[i * 2 + 1] = (int32_t)(b.q16[u * 2 + 1] + 32768);
+  }
+  if (first)
+    for (int i = tid; i < kHistWords / kCS * C; i += kThreads) L.hist[i] = 0;
+  __syncthreads();
+
+  const __amdgpu_buffer_rsrc_t rin = frame_rsrc(fp.in[t0.cam], cam);
+  const __amdgpu_buffer_rsrc_t rout = frame_rsrc(fp.out[t0.cam], cam);
+  const uint16_t* wrow = b.weights + (int64_t)t0.cam * g.w_max;
+  const int hrep = tid & (kRep - 1);
+  const int ngl = half >> 2;                     // groups of the left half
+  const int ngr = (W - half + 3) >> 2;           // groups of the right half (the last may be ragged)
+  const int ngl_pad = (ngl + 63) & ~63;
+
+  for (int gi = tid; gi < ngl_pad + ngr; gi += kThreads) {
+    const int side = uniform(gi >= ngl_pad ? 1 : 0);   // the same in every lane of the wave
+    const int lgi = side ? gi - ngl_pad : gi;
+    if (lgi >= (side ? ngr : ngl)) continue;          // padding of the left half
+    const int col0 = (side ? half : 0) + 4 * lgi;
+    const int npx = min(4, (side ? W : half) - col0);
+    uint32_t wp[4];
 #pragma unroll
-    for (int c = 0; c < kCS; ++c) {
-      uint32_t sum = 0;
-      if (c < C) {
-        if (kPack) {
-          // Thread tid owns bin tid; the replica order is rotated per bin pair
-          // so that a half-wave reads 16 distinct banks (pairs share a word).
-          const int pair = tid >> 1, sh = (tid & 1) << 4;
-#pragma unroll 8
-          for (int i = 0; i < kRep; ++i)
-            sum += (L.hist[(c * (kNB / 2) + pair) * kRep + ((i + pair) & (kRep - 1))] >> sh) & 0xffffu;
-        } else {
+    for (int p = 0; p < 4; ++p) {
+      const uint32_t w = p < npx ? (WTAB ? (uint32_t)wrow[col0 + p] : blend_weight(W, col0 + p)) : 0u;
+      wp[p] = (256u - w) | (w << 16);
+    }
+    const int cbyte = col0 * C;
+    int jb = j0;
+    int rb = min(R1, (int)((int64_t)(jb + 1) * H / nb));   // first row of the next block
+    int32_t A[kCS], Cc[kCS];
+    auto fetch = [&]() {
 #pragma unroll
-          for (int r = 0; r < kRep; ++r) sum += L.hist[(c * kNB + tid) * kRep + r];
+      for (int c = 0; c < kCS; ++c) {
+        const int i = (((jb - j0) * 2 + side) * kCS + c) * 2;
+        A[c] = uniform(cst[i]);
+        Cc[c] = uniform(cst[i + 1]);
+      }
+    };
+    fetch();
+    auto next_block = [&](int r) {
+      if (r == rb) {                                  // uniform
+        ++jb;
+        rb = min(R1, (int)((int64_t)(jb + 1) * H / nb));
+        fetch();
+      }
+    };
+
+    if (npx == 4) {
+      for (int row = R0; row < R1; row += kUnroll) {
+        uint32_t d[kUnroll][NW];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u)
+          if (row + u < R1) load_group<NW>(rin, (row + u) * pitch + cbyte, d[u]);
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          if (row + u < R1) {
+            next_block(row + u);
+            uint32_t o[NW];
+#pragma unroll
+            for (int q = 0; q < NW; ++q) o[q] = 0;
+#pragma unroll
+            for (int i = 0; i < 4 * C; ++i) {
+              const int p = i / C, c = i - (i / C) * C;
+              const uint32_t x = (d[u][i >> 2] >> (8 * (i & 3))) & 0xffu;
+              __hip_atomic_fetch_add(&L.hist[(c * kNB + x) * kRep + hrep], 1u, __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_WORKGROUP);
+              o[i >> 2] |= direct_sample(x, A[c], Cc[c], wp[p]) << (8 * (i & 3));
+            }
+            store_group<NW>(rout, (row + u) * pitch + cbyte, o);
+          }
         }
       }
-      h[c] = sum;
-      if (sum) atomicAdd(&gh[c * kNB + tid], sum);
+    } else {
+      // Ragged end of the right half: sample by sample, touching only the row's bytes.
+      for (int row = R0; row < R1; ++row) {
+        next_block(row);
+        const int off = row * pitch + cbyte;
+#pragma unroll
+        for (int i = 0; i < 4 * C; ++i) {
+          const int p = i / C, c = i - (i / C) * C;
+          if (p < npx) {
+            const uint32_t x = __builtin_amdgcn_raw_buffer_load_b8(rin, off + i, 0, 0);
+            __hip_atomic_fetch_add(&L.hist[(c * kNB + x) * kRep + hrep], 1u, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+            __builtin_amdgcn_raw_buffer_store_b8((uint8_t)direct_sample(x, A[c], Cc[c], wp[p]), rout, off + i, 0, 0);
+          }
+        }
+      }
     }
-    const unsigned long long x = (unsigned long long)tid;
-    const unsigned long long h0 = h[0], h1 = h[1], h2 = h[2];
-    block_sums(
-        (BPS == 2) ? 3 : 3 * C,
-        [=](int i) -> unsigned long long {
-          const int c = i / 3, m = i - 3 * (i / 3);
-          const unsigned long long hc = c == 0 ? h0 : (c == 1 ? h1 : h2);
-          if (m == 0) return hc;
-          if (BPS == 2) return m == 1 ? a1 : a2;
-          return m == 1 ? hc * x : hc * x * x;
-        },
-        [&](int i, unsigned long long tot) {
-          if (tot) atomicAdd((unsigned long long*)&b.whole_sums[(int64_t)t.cam * 9 + i], tot);
-        },
-        L.red);
   }
+  if (last) flush_whole<C, 1>(g, b, t0.cam, L, 0ull, 0ull);
 }
 
 // Whether the tile's six 8-bit maps can be evaluated directly (uniform).
@@ -334,19 +494,37 @@ __device__ inline bool tile_direct(const Geo& g, const Bufs& b, int ti) {
   return ok;
 }
 
+// The segments from ti on, up to se, that one apply_tile call takes: with the
+// direct maps (8-bit samples, apply with statistics, every segment's maps
+// direct), the whole run of the camera's consecutive segments; otherwise one.
+// Returns the end of the segments taken; `last` is set when they end the
+// camera's run in this workgroup.
 template <bool WRITE, bool STATS, bool WTAB>
-__device__ inline void apply_tile_dispatch(const Geo& g, const FramePtrs& fp, const Bufs& b, int ti, ApplyLds& L,
-                                           bool first, bool last) {
-  const DevCam cam = uniform_cam(g.cams[uniform(g.tiles[ti].cam)]);
-  if (cam.bps == 2) apply_tile<1, 2, WRITE, STATS, WTAB, false>(g, fp, b, ti, L, first, last);
-  else if (WRITE && STATS && RC_APPLY_DIRECT && tile_direct(g, b, ti)) {
+__device__ inline int apply_tile_dispatch(const Geo& g, const FramePtrs& fp, const Bufs& b, int ti, int se,
+                                          ApplyLds& L, bool first) {
+  const int k = uniform(g.tiles[ti].cam);
+  const DevCam cam = uniform_cam(g.cams[k]);
+  int te = ti + 1;
+  const bool direct = cam.bps == 1 && WRITE && STATS && RC_APPLY_DIRECT && tile_direct(g, b, ti);
+  const int j0 = uniform(g.tiles[ti].block);
+  if (direct)
+    while (te < se && uniform(g.tiles[te].cam) == k && uniform(g.tiles[te].block) - j0 < kRunBlocks &&
+           tile_direct(g, b, te))
+      ++te;
+  const bool last = te == se || uniform(g.tiles[te].cam) != k;
+  if (cam.bps == 2) apply_tile<1, 2, WRITE, STATS, WTAB, false>(g, fp, b, ti, te, L, first, last);
+  else if (direct) {
     // Measured on MI355X: faster than the LDS tables when the pass also
     // builds the histogram (the LDS is then busy with its atomics), slower
     // for the apply alone.
-    if (cam.channels == 3) apply_tile<3, 1, WRITE, STATS, WTAB, true>(g, fp, b, ti, L, first, last);
-    else apply_tile<1, 1, WRITE, STATS, WTAB, true>(g, fp, b, ti, L, first, last);
-  } else if (cam.channels == 3) apply_tile<3, 1, WRITE, STATS, WTAB, false>(g, fp, b, ti, L, first, last);
-  else apply_tile<1, 1, WRITE, STATS, WTAB, false>(g, fp, b, ti, L, first, last);
+    if (WRITE && STATS && (cam.half & 3) == 0) {
+      if (cam.channels == 3) apply_run_direct<3, WTAB>(g, fp, b, ti, te, L, first, last);
+      else apply_run_direct<1, WTAB>(g, fp, b, ti, te, L, first, last);
+    } else if (cam.channels == 3) apply_tile<3, 1, WRITE, STATS, WTAB, true>(g, fp, b, ti, te, L, first, last);
+    else apply_tile<1, 1, WRITE, STATS, WTAB, true>(g, fp, b, ti, te, L, first, last);
+  } else if (cam.channels == 3) apply_tile<3, 1, WRITE, STATS, WTAB, false>(g, fp, b, ti, te, L, first, last);
+  else apply_tile<1, 1, WRITE, STATS, WTAB, false>(g, fp, b, ti, te, L, first, last);
+  return te;
 }
 
 }  // namespace rc

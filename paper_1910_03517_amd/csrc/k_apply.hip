@@ -18,12 +18,13 @@ void k_apply(Geo g, FramePtrs fp, Bufs b) {
   __shared__ ApplyLds L;
   const int s0 = uniform(g.wg_seg[blockIdx.x]), s1 = uniform(g.wg_seg[blockIdx.x + 1]);
   int prev = -1;
-  for (int s = s0; s < s1; ++s) {
+  for (int s = s0; s < s1;) {
     const int cam = uniform(g.tiles[s].cam);
-    if (!cam_active(g, cam)) continue;   // uniform over the workgroup
-    const bool first = cam != prev;
-    const bool last = s + 1 == s1 || uniform(g.tiles[s + 1].cam) != cam;
-    apply_tile_dispatch<WRITE, STATS, true>(g, fp, b, s, L, first, last);
+    if (!cam_active(g, cam)) {   // uniform over the workgroup
+      ++s;
+      continue;
+    }
+    s = apply_tile_dispatch<WRITE, STATS, true>(g, fp, b, s, s1, L, cam != prev);
     __syncthreads();
     prev = cam;
   }

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <functional>
 #include <new>
 #include <string>
 #include <vector>
@@ -136,10 +137,10 @@ rt_status check_active(const rt_ctx* ctx, uint64_t active) {
 // where the apply pass's packed histogram needs it; tiles are camera-major.
 // Apply work.  grid == 0: every vertical block of every camera is cut into
 // ceil(rows / cap) tiles of equal height (+-1 row), one workgroup per tile.
-// grid > 0: `grid` workgroups, each on a contiguous share of all rows
-// (cameras in index order) of equal bytes, +-1 row, cut into segments at
-// camera and block boundaries and at most cap rows.  cap = tile_rows, or
-// less where the packed histogram needs it.
+// grid > 0: `grid` workgroups, each on a contiguous share of rows, the
+// shares as even in bytes as whole cameras allow, cut into segments at block
+// boundaries and at most cap rows.  cap = tile_rows, or less where the packed
+// histogram needs it.
 static rt_status build_tables(rt_ctx* ctx, int tile_rows, int grid) {
   const int n_cams = ctx->n_cams;
   const int nb = ctx->opts.n_blocks;
@@ -168,8 +169,36 @@ static rt_status build_tables(rt_ctx* ctx, int tile_rows, int grid) {
     G = (int)ctx->htiles.size();
     wg.resize(G + 1);
     for (int w = 0; w <= G; ++w) wg[w] = w;
+  } else if (grid >= n_cams) {
+    // Every camera gets a whole number of shares, one plus its part of the
+    // other G - K by bytes (largest remainders), and its rows are split
+    // evenly among them: no share spans two cameras.
+    G = grid;
+    int64_t total = 0;
+    for (int k = 0; k < n_cams; ++k) total += (int64_t)ctx->cams[k].height * ctx->hcams[k].row_bytes;
+    std::vector<int> n(n_cams, 1);
+    std::vector<std::pair<int64_t, int>> rem(n_cams);
+    int given = n_cams;
+    for (int k = 0; k < n_cams; ++k) {
+      const __int128 q = (__int128)(G - n_cams) * ((int64_t)ctx->cams[k].height * ctx->hcams[k].row_bytes);
+      n[k] += (int)(q / total);
+      given += (int)(q / total);
+      rem[k] = {(int64_t)(q % total), -k};
+    }
+    std::sort(rem.begin(), rem.end(), std::greater<std::pair<int64_t, int>>());
+    for (int i = 0; given < G; ++i, ++given) ++n[-rem[i].second];
+    wg.resize(G + 1);
+    int w = 0;
+    for (int k = 0; k < n_cams; ++k) {
+      const int H = ctx->cams[k].height;
+      for (int i = 0; i < n[k]; ++i, ++w) {
+        wg[w] = (int32_t)ctx->htiles.size();
+        emit(k, (int)((int64_t)i * H / n[k]), (int)((int64_t)(i + 1) * H / n[k]));
+      }
+    }
   } else {
-    // Share w of G starts at the first row whose byte offset reaches w / G of the total.
+    // Fewer workgroups than cameras: share w starts at the first row whose
+    // byte offset reaches w / G of the total, so shares span cameras.
     G = grid;
     std::vector<int64_t> base(n_cams + 1, 0);
     for (int k = 0; k < n_cams; ++k)
