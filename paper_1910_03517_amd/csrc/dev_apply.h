@@ -47,6 +47,21 @@ constexpr int kUnroll = RC_APPLY_UNROLL;  // rows in flight per thread
 constexpr int kLoadPolicy = RC_LOAD_POLICY;    // cache-policy bits of frame loads
 constexpr int kStorePolicy = RC_STORE_POLICY;  // cache-policy bits of frame stores
 
+// Word (before the replica index) and bit offset of (channel c, bin) in the
+// LDS histogram.  Unpacked: a word per bin.  RC_APPLY_PACK 1: bins 2i and
+// 2i + 1 share word i; RC_APPLY_PACK 2: bins i and i + 128 share word i, so
+// that neighbouring values, frequent within a region, fall in different words.
+__device__ inline int hist_word(int c, uint32_t bin) {
+  if (RC_APPLY_PACK == 1) return c * (kNB / 2) + (int)(bin >> 1);
+  if (RC_APPLY_PACK == 2) return c * (kNB / 2) + (int)(bin & (kNB / 2 - 1));
+  return c * kNB + (int)bin;
+}
+__device__ inline uint32_t hist_shift(uint32_t bin) {
+  if (RC_APPLY_PACK == 1) return (bin & 1u) << 4;
+  if (RC_APPLY_PACK == 2) return (bin >> 7) << 4;
+  return 0u;
+}
+
 struct ApplyLds {
   uint8_t lut[2 * kCS * kNB];          // [side][channel][x]
   int64_t q[4];                        // [side][A, Bq]
@@ -108,12 +123,8 @@ __device__ inline uint32_t one_sample(uint32_t x, int c, int p, const PixConst& 
   if (STATS) {
     uint32_t bin = x;
     if (BPS == 2) { bin = x >> shift; bin = bin > 255u ? 255u : bin; }
-    if (kPack)
-      __hip_atomic_fetch_add(&L.hist[(c * (kNB / 2) + (bin >> 1)) * kRep + hrep], 1u << ((bin & 1u) << 4),
-                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    else
-      __hip_atomic_fetch_add(&L.hist[(c * kNB + bin) * kRep + hrep], 1u, __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_fetch_add(&L.hist[hist_word(c, bin) * kRep + hrep], 1u << hist_shift(bin), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
     if (BPS == 2) { a1 += x; a2 += (unsigned long long)x * x; }
   }
   if (!WRITE) return 0;
@@ -154,12 +165,12 @@ __device__ inline void flush_whole(const Geo& g, const Bufs& b, int cam, ApplyLd
     uint32_t sum = 0;
     if (c < C) {
       if (kPack) {
-        // Thread tid owns bin tid; the replica order is rotated per bin pair
-        // so that a half-wave reads 16 distinct banks (pairs share a word).
-        const int pair = tid >> 1, sh = (tid & 1) << 4;
+        // Thread tid owns bin tid; the replica order is rotated per word so
+        // that the lanes of a wave read distinct banks.
+        const int wd = hist_word(c, (uint32_t)tid);
+        const uint32_t sh = hist_shift((uint32_t)tid);
 #pragma unroll 8
-        for (int i = 0; i < kRep; ++i)
-          sum += (L.hist[(c * (kNB / 2) + pair) * kRep + ((i + pair) & (kRep - 1))] >> sh) & 0xffffu;
+        for (int i = 0; i < kRep; ++i) sum += (L.hist[wd * kRep + ((i + wd) & (kRep - 1))] >> sh) & 0xffffu;
       } else {
 #pragma unroll
         for (int r = 0; r < kRep; ++r) sum += L.hist[(c * kNB + tid) * kRep + r];
@@ -389,7 +400,7 @@ __device__ void apply_run_direct(const Geo& g, const FramePtrs& fp, const Bufs& 
     cst[i * 2] = (int32_t)b.q16[u * 2];
     cst[i * 2 + 1] = (int32_t)(b.q16[u * 2 + 1] + 32768);
   }
-  if (first)
+  if (first || kPack)
     for (int i = tid; i < kHistWords / kCS * C; i += kThreads) L.hist[i] = 0;
   __syncthreads();
 
@@ -451,7 +462,7 @@ __device__ void apply_run_direct(const Geo& g, const FramePtrs& fp, const Bufs& 
             for (int i = 0; i < 4 * C; ++i) {
               const int p = i / C, c = i - (i / C) * C;
               const uint32_t x = (d[u][i >> 2] >> (8 * (i & 3))) & 0xffu;
-              __hip_atomic_fetch_add(&L.hist[(c * kNB + x) * kRep + hrep], 1u, __ATOMIC_RELAXED,
+              __hip_atomic_fetch_add(&L.hist[hist_word(c, x) * kRep + hrep], 1u << hist_shift(x), __ATOMIC_RELAXED,
                                      __HIP_MEMORY_SCOPE_WORKGROUP);
               o[i >> 2] |= direct_sample(x, A[c], Cc[c], wp[p]) << (8 * (i & 3));
             }
@@ -469,7 +480,7 @@ __device__ void apply_run_direct(const Geo& g, const FramePtrs& fp, const Bufs& 
           const int p = i / C, c = i - (i / C) * C;
           if (p < npx) {
             const uint32_t x = __builtin_amdgcn_raw_buffer_load_b8(rin, off + i, 0, 0);
-            __hip_atomic_fetch_add(&L.hist[(c * kNB + x) * kRep + hrep], 1u, __ATOMIC_RELAXED,
+            __hip_atomic_fetch_add(&L.hist[hist_word(c, x) * kRep + hrep], 1u << hist_shift(x), __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_WORKGROUP);
             __builtin_amdgcn_raw_buffer_store_b8((uint8_t)direct_sample(x, A[c], Cc[c], wp[p]), rout, off + i, 0, 0);
           }
@@ -477,7 +488,7 @@ __device__ void apply_run_direct(const Geo& g, const FramePtrs& fp, const Bufs& 
       }
     }
   }
-  if (last) flush_whole<C, 1>(g, b, t0.cam, L, 0ull, 0ull);
+  if (last || kPack) flush_whole<C, 1>(g, b, t0.cam, L, 0ull, 0ull);
 }
 
 // Whether the tile's six 8-bit maps can be evaluated directly (uniform).
@@ -507,9 +518,11 @@ __device__ inline int apply_tile_dispatch(const Geo& g, const FramePtrs& fp, con
   int te = ti + 1;
   const bool direct = cam.bps == 1 && WRITE && STATS && RC_APPLY_DIRECT && tile_direct(g, b, ti);
   const int j0 = uniform(g.tiles[ti].block);
+  // Packed counters bound the rows between flushes.
+  const int cap = max_tile_rows(cam.width), r0 = uniform(g.tiles[ti].r0);
   if (direct)
     while (te < se && uniform(g.tiles[te].cam) == k && uniform(g.tiles[te].block) - j0 < kRunBlocks &&
-           tile_direct(g, b, te))
+           uniform(g.tiles[te].r1) - r0 <= cap && tile_direct(g, b, te))
       ++te;
   const bool last = te == se || uniform(g.tiles[te].cam) != k;
   if (cam.bps == 2) apply_tile<1, 2, WRITE, STATS, WTAB, false>(g, fp, b, ti, te, L, first, last);

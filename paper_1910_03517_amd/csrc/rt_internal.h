@@ -14,12 +14,12 @@ constexpr int kThreads = 256;    // threads of every workgroup
 constexpr int kMlpIn = RT_MLP_IN, kMlpHid = RT_MLP_HID, kMlpOut = RT_MLP_OUT;
 
 // Whole-frame histogram of the apply pass: replicas, and whether two bins
-// share a word as 16-bit halves.
+// share a word as 16-bit halves (1: bins 2i, 2i + 1; 2: bins i, i + 128).
 #ifndef RC_APPLY_PACK
 #define RC_APPLY_PACK 0
 #endif
 #ifndef RC_APPLY_REP
-#define RC_APPLY_REP (RC_APPLY_PACK ? 32 : 8)
+#define RC_APPLY_REP (RC_APPLY_PACK ? 16 : 8)
 #endif
 static_assert(kThreads % RC_APPLY_REP == 0 && (RC_APPLY_REP & (RC_APPLY_REP - 1)) == 0, "replicas");
 
