@@ -196,19 +196,17 @@ __device__ inline void flush_whole(const Geo& g, const Bufs& b, int cam, ApplyLd
       L.red);
 }
 
-// Segments [ti, te) of the context, all of one camera (te = ti + 1 unless
-// DIRECT: the direct maps of each segment's block are switched inside the
-// column-group loop, so a thread keeps its weights across the segments).
-// WTAB: weights from the caller's table (true) or from their closed form
-// (false); both give the same integers.  With statistics, `first` clears the
-// LDS histogram (the first segment of its camera in this workgroup's run) and
-// `last` adds it to the whole-frame statistics (the camera's last segment in
-// the run); 16-bit samples, whose sums are kept in registers, and the packed
-// histogram, whose counters are bounded per segment, do both on every
-// segment.
-template <int C, int BPS, bool WRITE, bool STATS, bool WTAB, bool DIRECT>
-__device__ void apply_tile(const Geo& g, const FramePtrs& fp, const Bufs& b, int ti, int te, ApplyLds& L,
-                           bool first, bool last) {
+// Segment ti of the context through the block's tables (8-bit samples:
+// staged in LDS; 16-bit: the Q16 pairs).  WTAB: weights from the caller's
+// table (true) or from their closed form (false); both give the same
+// integers.  With statistics, `first` clears the LDS histogram (the first
+// segment of its camera in this workgroup's run) and `last` adds it to the
+// whole-frame statistics (the camera's last segment in the run); 16-bit
+// samples, whose sums are kept in registers, and the packed histogram, whose
+// counters are bounded per segment, do both on every segment.
+template <int C, int BPS, bool WRITE, bool STATS, bool WTAB>
+__device__ void apply_tile(const Geo& g, const FramePtrs& fp, const Bufs& b, int ti, ApplyLds& L, bool first,
+                           bool last) {
   const bool clear = first || BPS == 2 || kPack;
   const bool flush = last || BPS == 2 || kPack;
   constexpr int NW = C * BPS;    // dwords per 4-pixel group
@@ -225,27 +223,7 @@ __device__ void apply_tile(const Geo& g, const FramePtrs& fp, const Bufs& b, int
   // Stage the tables of both sides of the tile's block; clear the histogram.
   const int64_t u_left = unit_index(t.cam, 0, t.block, 0, g.n_blocks);
   const int64_t u_right = unit_index(t.cam, 1, t.block, 0, g.n_blocks);
-  // Direct 8-bit maps (uniform): those of the first two segments' blocks are
-  // loaded here, before the column loop, so that switching between them
-  // costs no memory latency; later segments of a longer run load theirs.
-  int32_t dA[2][2][kCS], dC[2][2][kCS];
-  auto load_direct = [&](int block, int32_t (&A)[2][kCS], int32_t (&Cc)[2][kCS]) {
-    const int64_t ul = unit_index(t.cam, 0, block, 0, g.n_blocks), ur = unit_index(t.cam, 1, block, 0, g.n_blocks);
-#pragma unroll
-    for (int sd = 0; sd < 2; ++sd)
-#pragma unroll
-      for (int c = 0; c < kCS; ++c) {
-        const int64_t u = (sd ? ur : ul) + c;
-        A[sd][c] = uniform((int32_t)b.q16[u * 2]);
-        Cc[sd][c] = uniform((int32_t)(b.q16[u * 2 + 1] + 32768));
-      }
-  };
-  const Tile t1 = (DIRECT && te - ti > 1) ? uniform_tile(g.tiles[ti + 1]) : t;
-  if (WRITE && DIRECT) {
-    load_direct(t.block, dA[0], dC[0]);
-    if (te - ti > 1) load_direct(t1.block, dA[1], dC[1]);
-  }
-  if (WRITE && !DIRECT) {
+  if (WRITE) {
     if (BPS == 1) {
       constexpr int DW = C * kNB / 4;   // dwords of one side's tables
       for (int i = tid; i < 2 * DW; i += kThreads) {
@@ -286,22 +264,7 @@ __device__ void apply_tile(const Geo& g, const FramePtrs& fp, const Bufs& b, int
       if (BPS == 2 && WRITE) { pc.qa[p] = L.q[side * 2]; pc.qb[p] = L.q[side * 2 + 1]; }
     }
     const int cbyte = col0 * C * BPS;
-
-   for (int si = ti; si < te; ++si) {
-    const Tile ts = si == ti ? t : (si == ti + 1 ? t1 : uniform_tile(g.tiles[si]));
-    if (DIRECT && WRITE) {
-      const int q = si == ti ? 0 : 1;
-      if (si > ti + 1) load_direct(ts.block, dA[1], dC[1]);
-#pragma unroll
-      for (int p = 0; p < 4; ++p) {
-        const bool right = col0 + p >= half;
-#pragma unroll
-        for (int c = 0; c < kCS; ++c) {
-          pc.da[p][c] = right ? dA[q][1][c] : dA[q][0][c];
-          pc.dc[p][c] = right ? dC[q][1][c] : dC[q][0][c];
-        }
-      }
-    }
+    const Tile& ts = t;
 
     if (npx == 4) {
       for (int row = ts.r0; row < ts.r1; row += kUnroll) {
@@ -322,7 +285,7 @@ __device__ void apply_tile(const Geo& g, const FramePtrs& fp, const Bufs& b, int
               uint32_t x;
               if (BPS == 1) x = (d[u][i >> 2] >> (8 * (i & 3))) & 0xffu;
               else x = (d[u][i >> 1] >> (16 * (i & 1))) & 0xffffu;
-              const uint32_t y = one_sample<BPS, WRITE, STATS, DIRECT>(x, c, p, pc, L, hrep, shift, maxv, a1, a2);
+              const uint32_t y = one_sample<BPS, WRITE, STATS, false>(x, c, p, pc, L, hrep, shift, maxv, a1, a2);
               if (WRITE) {
                 if (BPS == 1) o[i >> 2] |= y << (8 * (i & 3));
                 else o[i >> 1] |= y << (16 * (i & 1));
@@ -344,7 +307,7 @@ __device__ void apply_tile(const Geo& g, const FramePtrs& fp, const Bufs& b, int
             uint32_t x;
             if (BPS == 1) x = __builtin_amdgcn_raw_buffer_load_b8(rin, off + i, 0, 0);
             else x = __builtin_amdgcn_raw_buffer_load_b16(rin, off + 2 * i, 0, 0);
-            const uint32_t y = one_sample<BPS, WRITE, STATS, DIRECT>(x, c, p, pc, L, hrep, shift, maxv, a1, a2);
+            const uint32_t y = one_sample<BPS, WRITE, STATS, false>(x, c, p, pc, L, hrep, shift, maxv, a1, a2);
             if (WRITE) {
               if (BPS == 1) __builtin_amdgcn_raw_buffer_store_b8((uint8_t)y, rout, off + i, 0, 0);
               else __builtin_amdgcn_raw_buffer_store_b16((uint16_t)y, rout, off + 2 * i, 0, 0);
@@ -353,32 +316,20 @@ __device__ void apply_tile(const Geo& g, const FramePtrs& fp, const Bufs& b, int
         }
       }
     }
-   }
   }
 
   if (STATS && flush) flush_whole<C, BPS>(g, b, t.cam, L, a1, a2);
-}
-
-// One 8-bit sample through the direct map of constants (a, c) (scalar: the
-// wave lies on one side of the frame), blended with the weight pair wp.
-__device__ inline uint32_t direct_sample(uint32_t x, int32_t a, int32_t c, uint32_t wp) {
-  const int32_t a24 = (int32_t)((uint32_t)a << 8) >> 8;
-  int32_t v = a24 * (int32_t)x + c;
-  v = v < 0 ? 0 : (v > 0xffffff ? 0xffffff : v);
-  const uint32_t xf = ((uint32_t)v & 0xffff0000u) | x;
-  return __builtin_amdgcn_udot2(__builtin_bit_cast(u16x2, xf), __builtin_bit_cast(u16x2, wp), 128u, false) >> 8;
 }
 
 // Direct-map constants of this many blocks fit in the LDS table area.
 constexpr int kRunBlocks = (int)(sizeof(ApplyLds::lut) / (2 * kCS * 2 * sizeof(int32_t)));
 
 // Apply with statistics over segments [ti, te) of one 8-bit camera: their
-// rows are consecutive, every block among them has direct maps (at most
-// kRunBlocks blocks), and the frame's half width is a multiple of 4.  The
-// 4-pixel groups of each half are numbered separately, the right half's
-// starting at a multiple of 64, so every wave lies on one side and its map
-// constants are scalar; one row loop covers all the segments, taking the next
-// block's constants (staged in LDS) at its first row.  Same results as
+// rows are consecutive and every block among them has direct maps (at most
+// kRunBlocks blocks).  One row loop covers all the segments: the blocks'
+// constants are staged in LDS, and at a block's first row each thread
+// re-selects its pixels' constants (by side) from them, so a block boundary
+// costs no memory latency and no partly filled unroll step.  Same results as
 // apply_tile.
 template <int C, bool WTAB>
 __device__ void apply_run_direct(const Geo& g, const FramePtrs& fp, const Bufs& b, int ti, int te, ApplyLds& L,
@@ -408,42 +359,49 @@ __device__ void apply_run_direct(const Geo& g, const FramePtrs& fp, const Bufs& 
   const __amdgpu_buffer_rsrc_t rout = frame_rsrc(fp.out[t0.cam], cam);
   const uint16_t* wrow = b.weights + (int64_t)t0.cam * g.w_max;
   const int hrep = tid & (kRep - 1);
-  const int ngl = half >> 2;                     // groups of the left half
-  const int ngr = (W - half + 3) >> 2;           // groups of the right half (the last may be ragged)
-  const int ngl_pad = (ngl + 63) & ~63;
+  const int ngroups = (W + 3) >> 2;
+  unsigned long long a1 = 0, a2 = 0;
 
-  for (int gi = tid; gi < ngl_pad + ngr; gi += kThreads) {
-    const int side = uniform(gi >= ngl_pad ? 1 : 0);   // the same in every lane of the wave
-    const int lgi = side ? gi - ngl_pad : gi;
-    if (lgi >= (side ? ngr : ngl)) continue;          // padding of the left half
-    const int col0 = (side ? half : 0) + 4 * lgi;
-    const int npx = min(4, (side ? W : half) - col0);
-    uint32_t wp[4];
+  for (int grp = tid; grp < ngroups; grp += kThreads) {
+    const int col0 = grp * 4;
+    const int npx = min(4, W - col0);
+    PixConst pc;
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
       const uint32_t w = p < npx ? (WTAB ? (uint32_t)wrow[col0 + p] : blend_weight(W, col0 + p)) : 0u;
-      wp[p] = (256u - w) | (w << 16);
+      pc.wp[p] = (256u - w) | (w << 16);
     }
-    const int cbyte = col0 * C;
     int jb = j0;
     int rb = min(R1, (int)((int64_t)(jb + 1) * H / nb));   // first row of the next block
-    int32_t A[kCS], Cc[kCS];
-    auto fetch = [&]() {
+    auto select = [&]() {
+      int32_t A[2][kCS], Cc[2][kCS];
 #pragma unroll
-      for (int c = 0; c < kCS; ++c) {
-        const int i = (((jb - j0) * 2 + side) * kCS + c) * 2;
-        A[c] = uniform(cst[i]);
-        Cc[c] = uniform(cst[i + 1]);
+      for (int sd = 0; sd < 2; ++sd)
+#pragma unroll
+        for (int c = 0; c < kCS; ++c) {
+          const int i = (((jb - j0) * 2 + sd) * kCS + c) * 2;
+          A[sd][c] = uniform(cst[i]);
+          Cc[sd][c] = uniform(cst[i + 1]);
+        }
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        const bool right = col0 + p >= half;
+#pragma unroll
+        for (int c = 0; c < kCS; ++c) {
+          pc.da[p][c] = right ? A[1][c] : A[0][c];
+          pc.dc[p][c] = right ? Cc[1][c] : Cc[0][c];
+        }
       }
     };
-    fetch();
+    select();
     auto next_block = [&](int r) {
       if (r == rb) {                                  // uniform
         ++jb;
         rb = min(R1, (int)((int64_t)(jb + 1) * H / nb));
-        fetch();
+        select();
       }
     };
+    const int cbyte = col0 * C;
 
     if (npx == 4) {
       for (int row = R0; row < R1; row += kUnroll) {
@@ -462,16 +420,14 @@ __device__ void apply_run_direct(const Geo& g, const FramePtrs& fp, const Bufs& 
             for (int i = 0; i < 4 * C; ++i) {
               const int p = i / C, c = i - (i / C) * C;
               const uint32_t x = (d[u][i >> 2] >> (8 * (i & 3))) & 0xffu;
-              __hip_atomic_fetch_add(&L.hist[hist_word(c, x) * kRep + hrep], 1u << hist_shift(x), __ATOMIC_RELAXED,
-                                     __HIP_MEMORY_SCOPE_WORKGROUP);
-              o[i >> 2] |= direct_sample(x, A[c], Cc[c], wp[p]) << (8 * (i & 3));
+              o[i >> 2] |= one_sample<1, true, true, true>(x, c, p, pc, L, hrep, 0, 255u, a1, a2) << (8 * (i & 3));
             }
             store_group<NW>(rout, (row + u) * pitch + cbyte, o);
           }
         }
       }
     } else {
-      // Ragged end of the right half: sample by sample, touching only the row's bytes.
+      // Ragged end of the row: sample by sample, touching only the row's bytes.
       for (int row = R0; row < R1; ++row) {
         next_block(row);
         const int off = row * pitch + cbyte;
@@ -480,9 +436,8 @@ __device__ void apply_run_direct(const Geo& g, const FramePtrs& fp, const Bufs& 
           const int p = i / C, c = i - (i / C) * C;
           if (p < npx) {
             const uint32_t x = __builtin_amdgcn_raw_buffer_load_b8(rin, off + i, 0, 0);
-            __hip_atomic_fetch_add(&L.hist[hist_word(c, x) * kRep + hrep], 1u << hist_shift(x), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_WORKGROUP);
-            __builtin_amdgcn_raw_buffer_store_b8((uint8_t)direct_sample(x, A[c], Cc[c], wp[p]), rout, off + i, 0, 0);
+            const uint32_t y = one_sample<1, true, true, true>(x, c, p, pc, L, hrep, 0, 255u, a1, a2);
+            __builtin_amdgcn_raw_buffer_store_b8((uint8_t)y, rout, off + i, 0, 0);
           }
         }
       }
@@ -505,11 +460,11 @@ __device__ inline bool tile_direct(const Geo& g, const Bufs& b, int ti) {
   return ok;
 }
 
-// The segments from ti on, up to se, that one apply_tile call takes: with the
-// direct maps (8-bit samples, apply with statistics, every segment's maps
-// direct), the whole run of the camera's consecutive segments; otherwise one.
-// Returns the end of the segments taken; `last` is set when they end the
-// camera's run in this workgroup.
+// The segments from ti on, up to se, that one call takes: with the direct
+// maps (8-bit samples, apply with statistics, every segment's maps direct),
+// the camera's consecutive segments (apply_run_direct); otherwise one
+// (apply_tile).  Returns the end of the segments taken; `last` is set when
+// they end the camera's run in this workgroup.
 template <bool WRITE, bool STATS, bool WTAB>
 __device__ inline int apply_tile_dispatch(const Geo& g, const FramePtrs& fp, const Bufs& b, int ti, int se,
                                           ApplyLds& L, bool first) {
@@ -525,18 +480,15 @@ __device__ inline int apply_tile_dispatch(const Geo& g, const FramePtrs& fp, con
            uniform(g.tiles[te].r1) - r0 <= cap && tile_direct(g, b, te))
       ++te;
   const bool last = te == se || uniform(g.tiles[te].cam) != k;
-  if (cam.bps == 2) apply_tile<1, 2, WRITE, STATS, WTAB, false>(g, fp, b, ti, te, L, first, last);
+  if (cam.bps == 2) apply_tile<1, 2, WRITE, STATS, WTAB>(g, fp, b, ti, L, first, last);
   else if (direct) {
     // Measured on MI355X: faster than the LDS tables when the pass also
     // builds the histogram (the LDS is then busy with its atomics), slower
     // for the apply alone.
-    if (WRITE && STATS && (cam.half & 3) == 0) {
-      if (cam.channels == 3) apply_run_direct<3, WTAB>(g, fp, b, ti, te, L, first, last);
-      else apply_run_direct<1, WTAB>(g, fp, b, ti, te, L, first, last);
-    } else if (cam.channels == 3) apply_tile<3, 1, WRITE, STATS, WTAB, true>(g, fp, b, ti, te, L, first, last);
-    else apply_tile<1, 1, WRITE, STATS, WTAB, true>(g, fp, b, ti, te, L, first, last);
-  } else if (cam.channels == 3) apply_tile<3, 1, WRITE, STATS, WTAB, false>(g, fp, b, ti, te, L, first, last);
-  else apply_tile<1, 1, WRITE, STATS, WTAB, false>(g, fp, b, ti, te, L, first, last);
+    if (cam.channels == 3) apply_run_direct<3, WTAB>(g, fp, b, ti, te, L, first, last);
+    else apply_run_direct<1, WTAB>(g, fp, b, ti, te, L, first, last);
+  } else if (cam.channels == 3) apply_tile<3, 1, WRITE, STATS, WTAB>(g, fp, b, ti, L, first, last);
+  else apply_tile<1, 1, WRITE, STATS, WTAB>(g, fp, b, ti, L, first, last);
   return te;
 }
 
