@@ -232,6 +232,19 @@ rt_status rt_pipe_submit(rt_pipe* p, const void* const* frames, void* const* out
                          void* ready_event, int32_t* slot_out);
 rt_status rt_pipe_destroy(rt_pipe* p);
 
+/* The same pipeline with two slots (luts[2], wholes[2]) in which whole
+ * frame-sets alternate between the caller's stream (even submits) and the
+ * pipeline's own stream (odd submits): each runs its band statistics,
+ * estimate and apply on its stream, and its statistics wait only for the
+ * previous frame-set's estimate, so the next frame-set's statistics and
+ * estimate overlap the current apply, and two applies may overlap each other.
+ * Results are those of consecutive rt_frameset calls.  Completion of the odd
+ * frame-sets is not ordered on the caller's stream: rt_pipe_join(p, stream)
+ * makes `stream` wait for everything submitted so far. */
+rt_status rt_pipe_create_alternating(rt_ctx* ctx, const rt_stats_buf* bands, const rt_params_buf* state,
+                                     const rt_lut_buf* luts, const rt_stats_buf* wholes, rt_pipe** out);
+rt_status rt_pipe_join(rt_pipe* p, void* stream);
+
 /* A frame-set captured once into a HIP graph for fixed buffers and replayed
  * with one launch per frame-set.
  *

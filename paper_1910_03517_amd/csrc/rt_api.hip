@@ -682,6 +682,7 @@ rt_status rt_graph_destroy(rt_graph* g) {
 struct rt_pipe {
   rt_ctx* ctx = nullptr;
   int depth = 2;
+  bool alternate = false;   // whole frame-sets alternate between the caller's stream and s_est
   hipStream_t s_est = nullptr;
   std::vector<hipEvent_t> ev_lut, ev_done;      // per slot: tables ready / apply done
   rt_stats_buf bands{};
@@ -735,6 +736,30 @@ rt_status rt_pipe_submit(rt_pipe* p, const void* const* frames, void* const* out
   if (r == RT_OK) r = check_frames(ctx, (const void* const*)out_frames, "out_frames");
   if (r != RT_OK) return r;
   hipStream_t sa = (hipStream_t)stream;
+  if (p->alternate) {
+    // Frame-set t runs whole (statistics, estimate, apply) on stream t % 2;
+    // its statistics wait for the previous frame-set's estimate (state and
+    // band buffers), the only dependency between the two streams.
+    const int slot = (int)(p->submitted & 1);
+    hipStream_t s = slot ? p->s_est : sa;
+    const FramePtrs fp = make_ptrs(ctx, frames, out_frames);
+    Bufs be = make_bufs(&p->bands, &p->state, &p->luts[slot]);
+    be.whole_hist = p->wholes[slot].whole_hist;    // cleared by the estimate kernel
+    be.whole_sums = p->wholes[slot].whole_sums;
+    const Bufs ba = make_bufs(&p->wholes[slot], nullptr, &p->luts[slot]);
+    hipError_t e = hipSuccess;
+    if (ready_event) e = hipStreamWaitEvent(s, (hipEvent_t)ready_event, 0);
+    if (e == hipSuccess && p->submitted > 0) e = hipStreamWaitEvent(s, p->ev_lut[slot ^ 1], 0);
+    if (e == hipSuccess) e = launch_band_stats(ctx->geo, fp, be, s);
+    if (e == hipSuccess) e = launch_estimate_lut(ctx->geo, be, s);
+    if (e == hipSuccess) e = hipEventRecord(p->ev_lut[slot], s);
+    if (e == hipSuccess) e = timed_apply(ctx, ctx->geo, fp, ba, true, true, s);
+    if (e == hipSuccess) e = hipEventRecord(p->ev_done[slot], s);
+    if (e != hipSuccess) return hip_fail(e, "pipeline submit");
+    if (slot_out) *slot_out = slot;
+    ++p->submitted;
+    return RT_OK;
+  }
   const int slot = (int)(p->submitted % p->depth);
   const FramePtrs fp = make_ptrs(ctx, frames, out_frames);
   Bufs be = make_bufs(&p->bands, &p->state, &p->luts[slot]);
@@ -757,6 +782,20 @@ rt_status rt_pipe_submit(rt_pipe* p, const void* const* frames, void* const* out
   if (slot_out) *slot_out = slot;
   ++p->submitted;
   return RT_OK;
+}
+
+rt_status rt_pipe_create_alternating(rt_ctx* ctx, const rt_stats_buf* bands, const rt_params_buf* state,
+                                     const rt_lut_buf* luts, const rt_stats_buf* wholes, rt_pipe** out) {
+  rt_status r = rt_pipe_create(ctx, 2, bands, state, luts, wholes, out);
+  if (r == RT_OK) (*out)->alternate = true;
+  return r;
+}
+
+rt_status rt_pipe_join(rt_pipe* p, void* stream) {
+  if (!p) return fail(RT_EINVAL, "pipe is NULL");
+  if (!p->alternate || p->submitted < 2) return RT_OK;
+  hipError_t e = hipStreamWaitEvent((hipStream_t)stream, p->ev_done[1], 0);
+  return e == hipSuccess ? RT_OK : hip_fail(e, "pipeline join");
 }
 
 rt_status rt_pipe_destroy(rt_pipe* p) {

@@ -32,14 +32,18 @@ class WholeSet:
 
 
 class Pipeline:
-    """Overlaps the estimate of frame-set t+1 with the apply of frame-set t."""
+    """Overlaps the estimate of frame-set t+1 with the apply of frame-set t.
 
-    def __init__(self, rig: rt.Rig, depth: int = 2):
+    alternate=True: whole frame-sets alternate between the caller's stream and
+    the pipeline's own (rt_pipe_create_alternating); call join() before
+    depending on the caller's stream for all submitted work."""
+
+    def __init__(self, rig: rt.Rig, depth: int = 2, alternate: bool = False):
         self.rig = rig
-        self.depth = depth
-        self.luts = [LutSet(rig.sizes, rig.device) for _ in range(depth)]
-        self.whole = [WholeSet(rig.sizes, rig.device) for _ in range(depth)]
-        self.pipe = rt.Pipe(rig.ctx, rig.bufs, self.luts, self.whole)
+        self.depth = 2 if alternate else depth
+        self.luts = [LutSet(rig.sizes, rig.device) for _ in range(self.depth)]
+        self.whole = [WholeSet(rig.sizes, rig.device) for _ in range(self.depth)]
+        self.pipe = rt.Pipe(rig.ctx, rig.bufs, self.luts, self.whole, alternate=alternate)
 
     def submit(self, frames, out_frames, stream=None, frame_ptrs=None, out_ptrs=None, ready_event=None) -> int:
         """Enqueue one frame-set on `stream` (default: torch's current stream); returns its slot.
@@ -48,6 +52,9 @@ class Pipeline:
         ready_event (recorded after the write) unless they were written and
         synchronized earlier."""
         return self.pipe.submit(frames, out_frames, stream, frame_ptrs, out_ptrs, ready_event)
+
+    def join(self, stream=None) -> None:
+        self.pipe.join(stream)
 
     def close(self) -> None:
         self.pipe.close()

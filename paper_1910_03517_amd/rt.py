@@ -28,6 +28,7 @@ EXPORTED = ["rt_ctx_create", "rt_ctx_destroy", "rt_ctx_sizes", "rt_stats", "rt_e
             "rt_build_lut", "rt_apply", "rt_frameset", "rt_frameset_batch", "rt_ctx_set_active", "rt_ctx_check", "rt_ctx_tune", "rt_ctx_tuning",
             "rt_stream_copy", "rt_ctx_timing", "rt_ctx_apply_times", "rt_graph_create", "rt_graph_launch",
             "rt_graph_destroy", "rt_pipe_create", "rt_pipe_submit", "rt_pipe_destroy",
+            "rt_pipe_create_alternating", "rt_pipe_join",
             "rt_surrogate_features", "rt_estimate_new", "rt_surrogate_targets", "rt_surrogate_select",
             "rt_surrogate_frameset",
             "rt_mlp_forward", "rt_mlp_backward", "rt_mlp_adam", "rt_mlp_mse", "rt_gather_rows", "rt_mlp_train",
@@ -124,6 +125,9 @@ def load(path: str = LIB_PATH) -> ct.CDLL:
                                    ct.POINTER(rt_lut_buf), ct.POINTER(rt_stats_buf), ct.POINTER(P)]
     lib.rt_pipe_submit.argtypes = [P, ct.POINTER(P), ct.POINTER(P), P, P, ct.POINTER(ct.c_int32)]
     lib.rt_pipe_destroy.argtypes = [P]
+    lib.rt_pipe_create_alternating.argtypes = [P, ct.POINTER(rt_stats_buf), ct.POINTER(rt_params_buf),
+                                               ct.POINTER(rt_lut_buf), ct.POINTER(rt_stats_buf), ct.POINTER(P)]
+    lib.rt_pipe_join.argtypes = [P, P]
     M = ct.POINTER(rt_mlp)
     lib.rt_surrogate_features.argtypes = [P, ct.POINTER(rt_stats_buf), P, P]
     lib.rt_estimate_new.argtypes = [P, ct.POINTER(rt_stats_buf), P, P, P]
@@ -220,7 +224,7 @@ class Pipe:
     whole_hist, whole_sums tensors; bufs provides band_hist, band_sums,
     params, valid."""
 
-    def __init__(self, ctx, bufs, luts, wholes):
+    def __init__(self, ctx, bufs, luts, wholes, alternate: bool = False):
         depth = len(luts)
         assert len(wholes) == depth
         la = (rt_lut_buf * depth)(*[rt_lut_buf(_p(l.lut8), _p(l.q16), _p(l.weights)) for l in luts])
@@ -228,7 +232,11 @@ class Pipe:
         bb = rt_stats_buf(_p(bufs.band_hist), _p(bufs.band_sums), None, None)
         pb = rt_params_buf(_p(bufs.params), _p(bufs.valid))
         h = ct.c_void_p()
-        _check(load().rt_pipe_create(ctx, depth, ct.byref(bb), ct.byref(pb), la, wa, ct.byref(h)))
+        if alternate:
+            assert depth == 2, "the alternating pipeline has two slots"
+            _check(load().rt_pipe_create_alternating(ctx, ct.byref(bb), ct.byref(pb), la, wa, ct.byref(h)))
+        else:
+            _check(load().rt_pipe_create(ctx, depth, ct.byref(bb), ct.byref(pb), la, wa, ct.byref(h)))
         self.handle = h
         self.depth = depth
         self._keep = (bufs, luts, wholes)
@@ -244,6 +252,10 @@ class Pipe:
         ev = ct.c_void_p(ready_event.cuda_event) if ready_event is not None else None
         _check(load().rt_pipe_submit(self.handle, fa, oa, _stream_handle(stream), ev, ct.byref(self._slot)))
         return self._slot.value
+
+    def join(self, stream=None) -> None:
+        """Order `stream` after every frame-set submitted so far (alternating pipelines)."""
+        _check(load().rt_pipe_join(self.handle, _stream_handle(stream)))
 
     def close(self) -> None:
         if self.handle is not None:

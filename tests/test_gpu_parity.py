@@ -217,23 +217,27 @@ def test_stream_copy_utility(vec):
     assert torch.equal(src, dst)
 
 
-@pytest.mark.parametrize("depth", [1, 2, 3])
+@pytest.mark.parametrize("depth", [1, 2, 3, 0])
 def test_pipeline_matches_sequential_framesets(depth):
     """Two-stream pipelining of consecutive frame-sets gives the results of
-    consecutive rt_frameset calls, bit for bit (smoothing mode, drifting gains)."""
+    consecutive rt_frameset calls, bit for bit (smoothing mode, drifting gains).
+    depth 0 stands for the alternating pipeline (two slots)."""
     from paper_1910_03517_amd.pipeline import Pipeline
     say(f"case: pipeline depth {depth} vs sequential, 4x 480x200 rgb8, 5 frame-sets")
+    alternate = depth == 0
+    depth = 2 if alternate else depth
     spec = synth.RigSpec("pipe 4x480x200", 11, [synth.CamSpec(480, 200, 3, 8, 0, p) for p in range(4)])
     cams = rt_cams(spec.cams)
     opts = rt.Options(n_blocks=8, band_width=16, smoothing=True)
     seq = rt.Rig(cams, opts)
     par = rt.Rig(cams, opts)
-    pipe = Pipeline(par, depth=depth)
+    pipe = Pipeline(par, depth=depth, alternate=alternate)
     frames_t = [synth.rig_frames(spec, t, drift=True) for t in range(5)]
     dev = [seq.upload(f) for f in frames_t]
     torch.cuda.synchronize()
     outs_p = [par.alloc_frames() for _ in range(5)]
     slots = [pipe.submit(dev[t], outs_p[t]) for t in range(5)]
+    pipe.join()
     torch.cuda.synchronize()
     out_s = seq.alloc_frames()
     for t in range(5):
