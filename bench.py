@@ -19,8 +19,8 @@ own objects to it: "surrogate" (the network trained on the device from the
 plain estimator, then its inference path against the plain one) and
 "serving" (three rigs behind the server, paced at 30 fps and saturated).
 The roofline figure is for the dominant kernel (the
-apply pass with fused statistics), timed by events the library records right
-around each of its launches in the timed region, next to the streaming-copy
+apply pass with fused statistics), timed by HIP events the library attaches to
+its dispatches in the timed region (every n-th), next to the streaming-copy
 ceiling of the same bytes.  The CPU baseline leg times the CPU oracle (test
 infrastructure) on a bounded sample of the same workload.
 """
@@ -418,8 +418,8 @@ def main() -> int:
     first = args.warmup          # continue the step sequence (pipelined graphs chain step to step)
 
     # Timed region: exactly `steps` frame-sets back to back, bracketed by a
-    # start and an end event.  The library records its own events right around
-    # every apply launch in the region (the dominant kernel's durations).
+    # start and an end event.  The library attaches its own events to every
+    # n-th apply dispatch in the region (the dominant kernel's durations).
     rt.rt_ctx_timing(rig.ctx, args.steps, args.timing_every)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()

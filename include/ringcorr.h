@@ -293,11 +293,10 @@ rt_status rt_ctx_tuning(const rt_ctx* ctx, int32_t* tile_rows, int32_t* grid, in
 
 /* Instrumentation: with slots > 0, every `every`-th later apply kernel launch
  * of this context (rt_apply, rt_stats with whole-frame statistics,
- * rt_frameset, rt_pipe_submit; the first one included) is bracketed by two HIP
- * events on its stream, kept in a ring of `slots` entries; slots = 0 turns it
- * off.  Each recorded event pair costs the stream a few microseconds, so a
- * stride above 1 keeps the timed work close to the untimed.  every >= 1.
- * Synchronizes the device. */
+ * rt_frameset, rt_pipe_submit; the first one included) takes two HIP events
+ * attached to its dispatch (the kernel's own start and end, no marker packets
+ * around it), kept in a ring of `slots` entries; slots = 0 turns it off.
+ * every >= 1.  Synchronizes the device. */
 rt_status rt_ctx_timing(rt_ctx* ctx, int32_t slots, int32_t every);
 
 /* Durations in milliseconds of the last min(max_n, recorded, slots) apply

@@ -1,6 +1,8 @@
 // Apply kernel of section 3.1, weights read from the caller's table.  With
 // statistics, each tile adds its input histogram and sums to the camera's
 // whole-frame statistics with atomics.
+#include <hip/hip_ext.h>
+
 #include "dev_apply.h"
 
 namespace rc {
@@ -30,11 +32,14 @@ void k_apply(Geo g, FramePtrs fp, Bufs b) {
   }
 }
 
-hipError_t launch_apply(const Geo& g, const FramePtrs& fp, const Bufs& b, bool write, bool stats, hipStream_t st) {
+// start / stop (may be NULL): events that take the dispatch's own start and
+// end times (no marker packets around it).
+hipError_t launch_apply(const Geo& g, const FramePtrs& fp, const Bufs& b, bool write, bool stats, hipStream_t st,
+                        hipEvent_t start, hipEvent_t stop) {
   const dim3 grid(g.n_wg), block(kThreads);
-  if (write && stats) hipLaunchKernelGGL((k_apply<true, true>), grid, block, 0, st, g, fp, b);
-  else if (write) hipLaunchKernelGGL((k_apply<true, false>), grid, block, 0, st, g, fp, b);
-  else if (stats) hipLaunchKernelGGL((k_apply<false, true>), grid, block, 0, st, g, fp, b);
+  if (write && stats) hipExtLaunchKernelGGL((k_apply<true, true>), grid, block, 0, st, start, stop, 0u, g, fp, b);
+  else if (write) hipExtLaunchKernelGGL((k_apply<true, false>), grid, block, 0, st, start, stop, 0u, g, fp, b);
+  else if (stats) hipExtLaunchKernelGGL((k_apply<false, true>), grid, block, 0, st, start, stop, 0u, g, fp, b);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }

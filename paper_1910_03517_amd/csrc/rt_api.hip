@@ -442,16 +442,14 @@ static Bufs make_bufs(const rt_stats_buf* s, const rt_params_buf* p, const rt_lu
   return b;
 }
 
-// The apply kernel, bracketed by the context's timing events when enabled
+// The apply kernel, its dispatch timed by the context's events when enabled
 // (never inside a graph capture).
 static hipError_t timed_apply(rt_ctx* ctx, const Geo& g, const FramePtrs& fp, const Bufs& b, bool write,
                               bool stats, hipStream_t st) {
   if (ctx->n_timing <= 0 || ctx->capturing) return launch_apply(g, fp, b, write, stats, st);
   if (ctx->n_applies++ % ctx->timing_every != 0) return launch_apply(g, fp, b, write, stats, st);
   const int slot = (int)(ctx->n_timed % ctx->n_timing);
-  hipError_t e = hipEventRecord(ctx->ev_begin[slot], st);
-  if (e == hipSuccess) e = launch_apply(g, fp, b, write, stats, st);
-  if (e == hipSuccess) e = hipEventRecord(ctx->ev_end[slot], st);
+  const hipError_t e = launch_apply(g, fp, b, write, stats, st, ctx->ev_begin[slot], ctx->ev_end[slot]);
   if (e == hipSuccess) ++ctx->n_timed;
   return e;
 }

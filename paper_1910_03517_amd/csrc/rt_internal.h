@@ -140,7 +140,8 @@ hipError_t launch_band_stats(const Geo& g, const FramePtrs& fp, const Bufs& b, h
 hipError_t launch_estimate(const Geo& g, const Bufs& b, hipStream_t st);
 hipError_t launch_estimate_lut(const Geo& g, const Bufs& b, hipStream_t st);
 hipError_t launch_build_lut(const Geo& g, const Bufs& b, hipStream_t st);
-hipError_t launch_apply(const Geo& g, const FramePtrs& fp, const Bufs& b, bool write, bool stats, hipStream_t st);
+hipError_t launch_apply(const Geo& g, const FramePtrs& fp, const Bufs& b, bool write, bool stats, hipStream_t st,
+                        hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
 hipError_t launch_zero_whole(const Geo& g, const Bufs& b, hipStream_t st);
 hipError_t launch_stream_copy(void* dst, const void* src, int64_t bytes, int vec_bytes, hipStream_t st);
 
