@@ -50,10 +50,15 @@ def log(msg: str) -> None:
 
 
 def kernel_hash() -> str:
+    """Hash of the apply kernel's sources without comments and blank lines (a
+    comment edit does not make the stored traffic measurement stale)."""
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_1910_03517_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1910_03517_amd", "csrc", f)) as fh:
+            for line in fh:
+                code = line.split("//", 1)[0].rstrip()
+                if code:
+                    h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

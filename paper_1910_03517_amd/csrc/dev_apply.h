@@ -1,23 +1,20 @@
-// Apply pass of section 3.1 as a device function over one tile: every sample
-// is blended between the identity and its side's affine map with the Q8
-// weight of its column, y = ((256 - w) x + w f(x) + 128) >> 8, in exact
+// Apply pass of section 3.1 as device functions over segments of rows: every
+// sample is blended between the identity and its side's affine map with the
+// Q8 weight of its column, y = ((256 - w) x + w f(x) + 128) >> 8, in exact
 // integers; optionally fused with the whole-frame histogram and sums of the
 // input samples.
 //
 // A thread owns groups of 4 consecutive pixels of a row (12 bytes for RGB8, 4
-// for gray8, 8 for gray16) and walks down the tile's rows, kUnroll rows at a
-// time so that several loads are in flight; its pixels' weights and table
-// bases stay in registers.  Tables of the tile's block sit in LDS.  The
-// histogram is kept in kRep replicas interleaved bin by bin, lane l updating
-// replica l % kRep, so that lanes of one wave that see the same value mostly
-// hit different LDS words.  In the packed layout (kPack) two adjacent bins
-// share a word as 16-bit halves, which halves the footprint and allows 32
-// replicas: lanes of a half-wave then always hit 32 distinct words in 32
-// distinct banks, whatever the data; the tile table bounds every tile so that
-// no half can reach 2^16 (see the host's tile builder).  At the end of the
-// tile the replicas are summed and added to the camera's whole-frame
-// statistics with global atomics (the whole-frame buffers must be zero before
-// the first tile).
+// for gray8, 8 for gray16) and walks down its segments' rows, kUnroll rows at
+// a time so that several loads are in flight; its pixels' weights and map
+// constants stay in registers.  The histogram is kept in LDS in kRep replicas
+// interleaved bin by bin, lane l updating replica l % kRep, so that lanes of
+// one wave that see the same value mostly hit different LDS words (packed
+// variants, two 16-bit bins per word, are compile-time options; the segment
+// tables then bound the rows between flushes so that no half can reach
+// 2^16).  After a workgroup's last segment of a camera the replicas are summed
+// and added to the camera's whole-frame statistics with global atomics (the
+// whole-frame buffers must be zero before the first segment).
 #pragma once
 
 #include "dev_estimate.h"
@@ -109,7 +106,7 @@ struct PixConst {
 // The 8-bit table entry f(x) = clamp((A x + Bq + 2^15) >> 16, 0, 255) can be
 // evaluated directly in 32-bit integers, bit for bit equal to the table, when
 // |A| < 2^23 (a 24-bit multiply) and A x + Bq + 2^15 stays inside int32 for
-// x in [0, 255].  The check is made once per tile on its six (A, Bq) pairs.
+// x in [0, 255].  The check is made once per segment on its six (A, Bq) pairs.
 __device__ inline bool direct_ok(int64_t A, int64_t Bq) {
   if (A >= (1 << 23) || A < -(1 << 23)) return false;
   const int64_t c = Bq + 32768, e = 255 * A + c;
@@ -220,7 +217,7 @@ __device__ void apply_tile(const Geo& g, const FramePtrs& fp, const Bufs& b, int
   const uint32_t maxv = (1u << cam.bit_depth) - 1u;
   const int pitch = (int)cam.pitch;
 
-  // Stage the tables of both sides of the tile's block; clear the histogram.
+  // Stage the tables of both sides of the segment's block; clear the histogram.
   const int64_t u_left = unit_index(t.cam, 0, t.block, 0, g.n_blocks);
   const int64_t u_right = unit_index(t.cam, 1, t.block, 0, g.n_blocks);
   if (WRITE) {
@@ -446,7 +443,7 @@ __device__ void apply_run_direct(const Geo& g, const FramePtrs& fp, const Bufs& 
   if (last || kPack) flush_whole<C, 1>(g, b, t0.cam, L, 0ull, 0ull);
 }
 
-// Whether the tile's six 8-bit maps can be evaluated directly (uniform).
+// Whether the six 8-bit maps of segment ti can be evaluated directly (uniform).
 __device__ inline bool tile_direct(const Geo& g, const Bufs& b, int ti) {
   const Tile t = uniform_tile(g.tiles[ti]);
   bool ok = true;
