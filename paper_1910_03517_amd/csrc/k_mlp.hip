@@ -226,6 +226,154 @@ __global__ __launch_bounds__(W * 64) void k_gemm_wsplit(int M, int N, int K, int
   }
 }
 
+// Weight-gradient products C = A^T B over a long k (the mini-batch), both
+// operands stored k-major: A(i, k) = A[k lda + i], B(k, j) = B[k ldb + j];
+// with ones_row, row M of A is all ones and row M of the product (the column
+// sums of B, the bias gradient) goes to ones_row.  Read one float per lane
+// and k, as the k-split kernel must for such operands, the loads are bound
+// by the compute unit's vector-memory issue rate; here each wave stages its
+// k-range 32 k at a time into its own LDS slabs with 16-byte loads (8 lanes
+// per k row, the next chunk's loads in flight meanwhile) and feeds the
+// MFMAs from LDS in the k-split kernel's lane layout.  A workgroup of
+// kWgWaves waves owns a 32 x 32 tile; the waves' partial tiles are added in
+// LDS in wave order.
+constexpr int kWgWaves = 16, kWgChunk = 32, kWgPad = 33;
+struct WgradProblem {
+  int M, N, K, kw, tiles_x;
+  const float* A;
+  int64_t lda;
+  const float* B;
+  int64_t ldb;
+  float* C;
+  int ldc;
+  float* ones_row;
+};
+// Up to three products in one launch (the backward's three weight gradients
+// share K): problem q owns workgroups [start[q], start[q + 1]).
+struct WgradSet {
+  int n;
+  int start[4];
+  WgradProblem p[3];
+};
+
+__device__ __forceinline__ void wgrad_tile(const WgradProblem& P, int bx, int by) {
+  __shared__ float stage[kWgWaves][2][kWgChunk][kWgPad];
+  static_assert(sizeof(stage) >= sizeof(float) * kWgWaves * 16 * 64, "reduction area");
+  float (*red)[16][64] = reinterpret_cast<float (*)[16][64]>(&stage[0][0][0][0]);
+  const int M = P.M, N = P.N, K = P.K, kw = P.kw;
+  const float* __restrict__ A = P.A;
+  const float* __restrict__ B = P.B;
+  const int64_t lda = P.lda, ldb = P.ldb;
+  float* ones_row = P.ones_row;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int g = lane >> 5;
+  const int i0 = by * kWsTile, j0 = bx * kWsTile;
+  const int kbeg = wave * kw;
+  const int kend = (K - kbeg) < kw ? K : kbeg + kw;
+  const int lr = lane >> 3, lc = 4 * (lane & 7);     // loader: rows lr + 8 q, columns lc .. lc + 3
+  float ra[4][4], rb[4][4];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int kk = k0 + 8 * q + lr;
+      const bool krow = kk < kend;
+      const int ia = i0 + lc, jb = j0 + lc;
+      if (krow && ia + 3 < M) {
+        f32x4 v;
+        __builtin_memcpy(&v, A + (int64_t)kk * lda + ia, sizeof v);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) ra[q][e] = v[e];
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          ra[q][e] = !krow ? 0.0f : (ia + e < M ? A[(int64_t)kk * lda + ia + e] : (ones_row && ia + e == M ? 1.0f : 0.0f));
+      }
+      if (krow && jb + 3 < N) {
+        f32x4 v;
+        __builtin_memcpy(&v, B + (int64_t)kk * ldb + jb, sizeof v);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) rb[q][e] = v[e];
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) rb[q][e] = (krow && jb + e < N) ? B[(int64_t)kk * ldb + jb + e] : 0.0f;
+      }
+    }
+  };
+  f32x16 acc;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+  if (kbeg < kend) gload(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += kWgChunk) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        stage[wave][0][8 * q + lr][lc + e] = ra[q][e];
+        stage[wave][1][8 * q + lr][lc + e] = rb[q][e];
+      }
+    // The slabs are this wave's own: order its lanes' writes before their reads.
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (k0 + kWgChunk < kend) gload(k0 + kWgChunk);
+#pragma unroll
+    for (int s = 0; s < kWgChunk / 8; ++s)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int kk = 8 * s + 4 * g + c;
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(stage[wave][0][kk][lane & 31], stage[wave][1][kk][lane & 31],
+                                                   acc, 0, 0, 0);
+      }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  __syncthreads();                                   // every wave is done with the slabs
+#pragma unroll
+  for (int r = 0; r < 16; ++r) red[wave][r][lane] = acc[r];
+  __syncthreads();
+  for (int e = tid; e < 16 * 64; e += kWgWaves * 64) {
+    const int r = e >> 6, l = e & 63;
+    float v = 0.0f;
+#pragma unroll
+    for (int w = 0; w < kWgWaves; ++w) v += red[w][r][l];
+    const int i = i0 + 8 * (r >> 2) + 4 * (l >> 5) + (r & 3);
+    const int j = j0 + (l & 31);
+    if (j >= N) continue;
+    if (i < M) P.C[(int64_t)i * P.ldc + j] = v;
+    else if (i == M && ones_row) ones_row[j] = v;
+  }
+}
+
+__global__ __launch_bounds__(kWgWaves * 64) void k_gemm_wgrad(WgradSet s) {
+  int q = 0;
+  while (q + 1 < s.n && (int)blockIdx.x >= s.start[q + 1]) ++q;
+  const int t = (int)blockIdx.x - s.start[q];
+  wgrad_tile(s.p[q], t % s.p[q].tiles_x, t / s.p[q].tiles_x);
+}
+
+// Adds C = A^T B (+ ones row) to a set, both operands k-major.
+static void wgrad_add(WgradSet& s, int M, int N, int K, const float* A, int64_t lda, const float* B, int64_t ldb,
+                      float* C, int ldc, float* ones_row) {
+  WgradProblem& P = s.p[s.n];
+  const int MA = ones_row ? M + 1 : M;
+  P.M = M; P.N = N; P.K = K;
+  P.kw = ((K + kWgWaves - 1) / kWgWaves + kWgChunk - 1) / kWgChunk * kWgChunk;
+  P.tiles_x = (N + kWsTile - 1) / kWsTile;
+  P.A = A; P.lda = lda; P.B = B; P.ldb = ldb; P.C = C; P.ldc = ldc; P.ones_row = ones_row;
+  if (s.n == 0) s.start[0] = 0;
+  s.start[s.n + 1] = s.start[s.n] + P.tiles_x * ((MA + kWsTile - 1) / kWsTile);
+  ++s.n;
+}
+
+static hipError_t wgrad_launch(const WgradSet& s, hipStream_t st) {
+  if (s.n == 0 || s.start[s.n] == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gemm_wgrad, dim3(s.start[s.n]), dim3(kWgWaves * 64), 0, st, s);
+  return hipGetLastError();
+}
+
 // The network's output layer, Y = H2 W3 + b3, one wave per row.
 __global__ __launch_bounds__(256) void k_out_layer(int M, const float* __restrict__ H2, const float* __restrict__ W3,
                                                    const float* __restrict__ b3, float* __restrict__ Y) {
@@ -246,6 +394,11 @@ static hipError_t gemm(int M, int N, int K, const float* A, int64_t sai, int64_t
   const int MA = ones_row ? M + 1 : M;
   if (MA <= kWsMaxRows) {
     const dim3 g2((N + kWsTile - 1) / kWsTile, (MA + kWsTile - 1) / kWsTile);
+    if (EPI == kEpiNone && sai == 1 && sbj == 1 && K >= 256) {   // weight gradients: both operands k-major
+      WgradSet set{};
+      wgrad_add(set, M, N, K, A, sak, B, sbk, C, ldc, ones_row);
+      return wgrad_launch(set, st);
+    }
     if (K >= 512) {            // long sums: 16 waves share k
       const int kw = ((K + 15) / 16 + 7) / 8 * 8;
       hipLaunchKernelGGL((k_gemm_wsplit<EPI, 16>), g2, dim3(16 * 64), 0, st, M, N, K, kw, A, sai, sak, B, sbk, sbj,
@@ -361,24 +514,28 @@ hipError_t mlp_backward(const float* const* w, const float* X, const float* H1, 
   const int64_t cnt = (int64_t)n * kMlpOut;
   hipLaunchKernelGGL(k_mse_grad, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, Y, T, cnt, dY);
   hipError_t e = hipGetLastError();
-  // dW3 = H2^T dY and, as the ones row of the same product, db3 = colsum dY
-  if (e == hipSuccess)
-    e = gemm<kEpiNone>(kMlpHid, kMlpOut, n, H2, 1, kMlpHid, dY, kMlpOut, 1, g[4], kMlpOut, nullptr, nullptr, 0, st,
-                       g[5]);
-  // dZ2 = (dY W3^T) * (H2 > 0)
+  // dZ2 = (dY W3^T) * (H2 > 0), dZ1 = (dZ2 W2^T) * (H1 > 0)
   if (e == hipSuccess)
     e = gemm<kEpiMask>(n, kMlpHid, kMlpOut, dY, kMlpOut, 1, w[4], 1, kMlpOut, dZ2, kMlpHid, nullptr, H2, kMlpHid, st);
-  // dW2 = H1^T dZ2, db2 = colsum dZ2
+  if (e == hipSuccess)
+    e = gemm<kEpiMask>(n, kMlpHid, kMlpHid, dZ2, kMlpHid, 1, w[2], 1, kMlpHid, dZ1, kMlpHid, nullptr, H1, kMlpHid, st);
+  if (e != hipSuccess) return e;
+  // dW1 = X^T dZ1, dW2 = H1^T dZ2, dW3 = H2^T dY, each with its bias gradient
+  // (column sums of the second operand) as the ones row of the same product.
+  if (n >= 256 && kMlpIn + 1 <= kWsMaxRows) {       // long sums: the three in one launch
+    WgradSet set{};
+    wgrad_add(set, kMlpIn, kMlpHid, n, X, kMlpIn, dZ1, kMlpHid, g[0], kMlpHid, g[1]);
+    wgrad_add(set, kMlpHid, kMlpHid, n, H1, kMlpHid, dZ2, kMlpHid, g[2], kMlpHid, g[3]);
+    wgrad_add(set, kMlpHid, kMlpOut, n, H2, kMlpHid, dY, kMlpOut, g[4], kMlpOut, g[5]);
+    return wgrad_launch(set, st);
+  }
+  e = gemm<kEpiNone>(kMlpIn, kMlpHid, n, X, 1, kMlpIn, dZ1, kMlpHid, 1, g[0], kMlpHid, nullptr, nullptr, 0, st, g[1]);
   if (e == hipSuccess)
     e = gemm<kEpiNone>(kMlpHid, kMlpHid, n, H1, 1, kMlpHid, dZ2, kMlpHid, 1, g[2], kMlpHid, nullptr, nullptr, 0, st,
                        g[3]);
-  // dZ1 = (dZ2 W2^T) * (H1 > 0)
   if (e == hipSuccess)
-    e = gemm<kEpiMask>(n, kMlpHid, kMlpHid, dZ2, kMlpHid, 1, w[2], 1, kMlpHid, dZ1, kMlpHid, nullptr, H1, kMlpHid, st);
-  // dW1 = X^T dZ1, db1 = colsum dZ1
-  if (e == hipSuccess)
-    e = gemm<kEpiNone>(kMlpIn, kMlpHid, n, X, 1, kMlpIn, dZ1, kMlpHid, 1, g[0], kMlpHid, nullptr, nullptr, 0, st,
-                       g[1]);
+    e = gemm<kEpiNone>(kMlpHid, kMlpOut, n, H2, 1, kMlpHid, dY, kMlpOut, 1, g[4], kMlpOut, nullptr, nullptr, 0, st,
+                       g[5]);
   return e;
 }
 

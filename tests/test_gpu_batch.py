@@ -50,11 +50,15 @@ def ring_frames(spec, r, t):
     return [frames[i] for i in ring_indices(spec, r)]
 
 
-def test_batched_rings_match_oracle_and_alone():
+@pytest.mark.parametrize("grid", [0, 5, 40])
+def test_batched_rings_match_oracle_and_alone(grid):
+    """grid 0: one workgroup per tile; 5: fewer workgroups than cameras (shares
+    run across cameras and rings); 40: whole shares per camera."""
     spec = three_rings()
     cams = rt_cams(spec.cams)
     opts = rt.Options(n_blocks=4, band_width=16, smoothing=True)
     mix = rt.Rig(cams, opts)
+    mix.tune(16, grid)
     rings = spec.rings
     idx = {r: ring_indices(spec, r) for r in rings}
     sub_cams = {r: [cams[i] for i in idx[r]] for r in rings}
@@ -65,7 +69,7 @@ def test_batched_rings_match_oracle_and_alone():
     prev = {r: (None, None) for r in rings}
     schedule = [(0, 1, 2), (0,), (1, 2), (1,), (0, 1, 2), (2,), (0, 2)]
     for step, active in enumerate(schedule):
-        say(f"case: batch step {step} rings {active}")
+        say(f"case: batch grid {grid} step {step} rings {active}")
         before = mix.bufs.host()
         out_before = mix.download(out_mix)
         frames_in = [None] * len(cams)
