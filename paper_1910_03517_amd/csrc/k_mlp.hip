@@ -374,16 +374,25 @@ static hipError_t wgrad_launch(const WgradSet& s, hipStream_t st) {
   return hipGetLastError();
 }
 
-// The network's output layer, Y = H2 W3 + b3, one wave per row.
+// The network's output layer, Y = H2 W3 + b3, one wave per row.  With T
+// (training), also the loss gradient dY = 2 (Y - T) / (M * 6), the same
+// expression k_mse_grad evaluates.
 __global__ __launch_bounds__(256) void k_out_layer(int M, const float* __restrict__ H2, const float* __restrict__ W3,
-                                                   const float* __restrict__ b3, float* __restrict__ Y) {
+                                                   const float* __restrict__ b3, float* __restrict__ Y,
+                                                   const float* __restrict__ T, float* __restrict__ dY) {
   const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (i >= M) return;                                    // whole waves
   float acc[kMlpOut];
   wave_row_dot<kMlpOut>(H2 + (int64_t)i * kMlpHid, W3, b3, kMlpHid, kMlpOut, acc);
-  if ((threadIdx.x & 63) == 0)
+  if ((threadIdx.x & 63) == 0) {
+    const float count = (float)((int64_t)M * kMlpOut);
 #pragma unroll
-    for (int o = 0; o < kMlpOut; ++o) Y[(int64_t)i * kMlpOut + o] = acc[o];
+    for (int o = 0; o < kMlpOut; ++o) {
+      const int64_t e = (int64_t)i * kMlpOut + o;
+      Y[e] = acc[o];
+      if (T) dY[e] = 2.0f * (acc[o] - T[e]) / count;
+    }
+  }
 }
 
 template <int EPI>
@@ -481,6 +490,25 @@ __global__ __launch_bounds__(256) void k_adam(AdamSet a, float lr, float beta1, 
   a.p[t][i] = a.p[t][i] - lr * mh / (__builtin_sqrtf(vh) + eps);
 }
 
+// The rows idx[r] of two tables at once (a mini-batch's inputs and targets):
+// elements [0, n la) of the grid copy rows of a (row length la), the rest
+// rows of b.
+__global__ __launch_bounds__(256) void k_gather_rows2(const float* __restrict__ a, int la, float* __restrict__ da,
+                                                      const float* __restrict__ b, int lb, float* __restrict__ db,
+                                                      const int32_t* __restrict__ idx, int n) {
+  int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t na = (int64_t)n * la;
+  if (e < na) {
+    const int r = (int)(e / la);
+    da[e] = a[(int64_t)idx[r] * la + (e - (int64_t)r * la)];
+    return;
+  }
+  e -= na;
+  if (e >= (int64_t)n * lb) return;
+  const int r = (int)(e / lb);
+  db[e] = b[(int64_t)idx[r] * lb + (e - (int64_t)r * lb)];
+}
+
 // dst[r][:] = src[idx[r]][:] for r < n rows of row_len floats.
 __global__ __launch_bounds__(256) void k_gather_rows(const float* __restrict__ src, int row_len,
                                                      const int32_t* __restrict__ idx, int n, float* __restrict__ dst) {
@@ -502,18 +530,23 @@ hipError_t mlp_hidden(const float* const* w, const float* X, int n, float* H1, f
   return e;
 }
 
-hipError_t mlp_forward(const float* const* w, const float* X, int n, float* H1, float* H2, float* Y, hipStream_t st) {
+hipError_t mlp_forward(const float* const* w, const float* X, int n, float* H1, float* H2, float* Y, hipStream_t st,
+                       const float* T, float* dY) {
   hipError_t e = mlp_hidden(w, X, n, H1, H2, st);
   if (e != hipSuccess || n <= 0) return e;
-  hipLaunchKernelGGL(k_out_layer, dim3((n + 3) / 4), dim3(256), 0, st, n, H2, w[4], w[5], Y);
+  hipLaunchKernelGGL(k_out_layer, dim3((n + 3) / 4), dim3(256), 0, st, n, H2, w[4], w[5], Y, T, dY);
   return hipGetLastError();
 }
 
 hipError_t mlp_backward(const float* const* w, const float* X, const float* H1, const float* H2, const float* Y,
-                        const float* T, int n, float* const* g, float* dY, float* dZ1, float* dZ2, hipStream_t st) {
+                        const float* T, int n, float* const* g, float* dY, float* dZ1, float* dZ2, hipStream_t st,
+                        bool dy_ready) {
   const int64_t cnt = (int64_t)n * kMlpOut;
-  hipLaunchKernelGGL(k_mse_grad, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, Y, T, cnt, dY);
-  hipError_t e = hipGetLastError();
+  hipError_t e = hipSuccess;
+  if (!dy_ready) {
+    hipLaunchKernelGGL(k_mse_grad, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, Y, T, cnt, dY);
+    e = hipGetLastError();
+  }
   // dZ2 = (dY W3^T) * (H2 > 0), dZ1 = (dZ2 W2^T) * (H1 > 0)
   if (e == hipSuccess)
     e = gemm<kEpiMask>(n, kMlpHid, kMlpOut, dY, kMlpOut, 1, w[4], 1, kMlpOut, dZ2, kMlpHid, nullptr, H2, kMlpHid, st);
@@ -561,6 +594,15 @@ hipError_t mlp_adam(float* const* w, const float* const* g, float* const* m, flo
 
 hipError_t mlp_mse(const float* Y, const float* T, int n, float* out, hipStream_t st) {
   hipLaunchKernelGGL(k_mse, dim3(1), dim3(1024), 0, st, Y, T, (int64_t)n * kMlpOut, out);
+  return hipGetLastError();
+}
+
+hipError_t gather_rows2(const float* a, int la, float* da, const float* b, int lb, float* db, const int32_t* idx, int n,
+                       hipStream_t st) {
+  const int64_t total = (int64_t)n * (la + lb);
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_rows2, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, a, la, da, b, lb, db,
+                     idx, n);
   return hipGetLastError();
 }
 

@@ -1014,12 +1014,13 @@ rt_status rt_mlp_train(const rt_mlp* w, const rt_mlp* grad, const rt_mlp* m, con
   hipError_t e = hipSuccess;
   for (int s = 0; e == hipSuccess && s < n_steps; ++s) {
     const int32_t* ix = idx + (int64_t)s * batch;
-    e = gather_rows(X, kMlpIn, ix, batch, work->xb, st);
-    if (e == hipSuccess) e = gather_rows(T, kMlpOut, ix, batch, work->tb, st);
-    if (e == hipSuccess) e = mlp_forward(wp, work->xb, batch, work->h1, work->h2, work->y, st);
+    // The per-step calls' sequence with the two gathers in one launch and the
+    // loss gradient computed by the output layer (the same arithmetic).
+    e = gather_rows2(X, kMlpIn, work->xb, T, kMlpOut, work->tb, ix, batch, st);
+    if (e == hipSuccess) e = mlp_forward(wp, work->xb, batch, work->h1, work->h2, work->y, st, work->tb, work->dy);
     if (e == hipSuccess)
       e = mlp_backward(wp, work->xb, work->h1, work->h2, work->y, work->tb, batch, gp, work->dy, work->dz1,
-                       work->dz2, st);
+                       work->dz2, st, true);
     if (e == hipSuccess) e = mlp_adam(wp, gp, mp, vp, step0 + s, lr, beta1, beta2, eps, st);
     if (e == hipSuccess) e = mlp_mse(work->y, work->tb, batch, losses + s, st);
   }

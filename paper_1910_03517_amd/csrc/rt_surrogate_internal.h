@@ -23,12 +23,17 @@ hipError_t launch_select(const Geo& g, const float* Y, const double* p_new, cons
 // The two hidden layers only (H1, H2); the output layer is then
 // wave_row_dot per row, as in mlp_forward.
 hipError_t mlp_hidden(const float* const* w, const float* X, int n, float* H1, float* H2, hipStream_t st);
-hipError_t mlp_forward(const float* const* w, const float* X, int n, float* H1, float* H2, float* Y, hipStream_t st);
+// With T, the output layer also writes the loss gradient dY (training).
+hipError_t mlp_forward(const float* const* w, const float* X, int n, float* H1, float* H2, float* Y, hipStream_t st,
+                       const float* T = nullptr, float* dY = nullptr);
 hipError_t mlp_backward(const float* const* w, const float* X, const float* H1, const float* H2, const float* Y,
-                        const float* T, int n, float* const* g, float* dY, float* dZ1, float* dZ2, hipStream_t st);
+                        const float* T, int n, float* const* g, float* dY, float* dZ1, float* dZ2, hipStream_t st,
+                        bool dy_ready = false);   // dy_ready: dY already holds the loss gradient
 hipError_t mlp_adam(float* const* w, const float* const* g, float* const* m, float* const* v, int step, float lr,
                     float beta1, float beta2, float eps, hipStream_t st);
 hipError_t mlp_mse(const float* Y, const float* T, int n, float* out, hipStream_t st);
 hipError_t gather_rows(const float* src, int row_len, const int32_t* idx, int n, float* dst, hipStream_t st);
+hipError_t gather_rows2(const float* a, int la, float* da, const float* b, int lb, float* db, const int32_t* idx, int n,
+                       hipStream_t st);
 
 }  // namespace rc
