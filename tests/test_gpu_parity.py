@@ -13,6 +13,7 @@ from tests.gpu_helpers import (compare_step, gpu_chain_separate, oracle_cams, or
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
+from oracle import ringcorr as rc  # noqa: E402
 from paper_1910_03517_amd import rt, synth  # noqa: E402
 
 
@@ -141,6 +142,44 @@ def test_rig14_frameset_standard():
 
 def test_rig14_frameset_smoothing():
     frameset_sequence(synth.rig14_1080p(), rt.Options(smoothing=True), 3)
+
+
+def test_rig14_alternating_pipeline_matches_oracle():
+    """The bench's launch configuration at its full size: four 14x1920x1080
+    frame-sets (drifting gains, smoothing) through the alternating pipeline,
+    every output against the oracle's frame-set sequence, the last two
+    frame-sets' whole-frame statistics and the final state bitwise."""
+    from paper_1910_03517_amd.pipeline import Pipeline
+    spec = synth.rig14_1080p()
+    cams = rt_cams(spec.cams)
+    opts = rt.Options(smoothing=True)
+    rig = rt.Rig(cams, opts)
+    pipe = Pipeline(rig, alternate=True)
+    n = 4
+    frames = [synth.rig_frames(spec, t, drift=True) for t in range(n)]
+    dev = [rig.upload(f) for f in frames]
+    outs = [rig.alloc_frames() for _ in range(n)]
+    torch.cuda.synchronize()
+    say("case: rig14 alternating pipeline, 4 frame-sets")
+    slots = [pipe.submit(dev[t], outs[t]) for t in range(n)]
+    pipe.join()
+    torch.cuda.synchronize()
+    rig.check()
+    co, oo = oracle_cams(cams), oracle_opts(opts)
+    prev_p = prev_v = None
+    for t in range(n):
+        ref = rc.frameset(co, oo, frames[t], prev_p, prev_v)
+        prev_p, prev_v = ref["params"], ref["valid"]
+        for k, (x, y) in enumerate(zip(rig.download(outs[t]), ref["out"])):
+            assert np.array_equal(x, y), f"frame-set {t} camera {k}"
+        if t >= n - 2:
+            w = pipe.whole[slots[t]]
+            assert np.array_equal(w.whole_hist.cpu().numpy().astype(np.int64), ref["whole_hist"]), f"t {t}"
+    h = rig.bufs.host()
+    assert np.array_equal(h["params"].view(np.uint64), prev_p.view(np.uint64))
+    assert np.array_equal(h["valid"], prev_v)
+    pipe.close()
+    rig.close()
 
 
 def test_uneven_rig_frameset():
