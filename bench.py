@@ -2,12 +2,12 @@
 
 One step = one frame-set through every step of the path: band statistics,
 estimate, tables, apply with fused whole-frame statistics.  By default steps
-go through the alternating pipeline (whole frame-sets alternate between two
-streams, so the statistics and estimate of frame-set t+1 and its apply
-overlap the apply of frame-set t); --mode pipe uses rt_pipe (only the
-statistics and estimate on a second stream), --mode eager issues one
-rt_frameset per step on one stream, --mode graph / graph-pipelined replay
-captured HIP graphs.  Inputs are
+go through rt_pipe with several apply lanes (the statistics and estimates of
+consecutive frame-sets run in order on one stream, ahead of the applies,
+which go round-robin over LANES streams, so that consecutive applies
+overlap); --lanes 1 keeps every apply on the caller's stream, --mode eager
+issues one rt_frameset per step on one stream, --mode graph / graph-pipelined
+replay captured HIP graphs.  Inputs are
 seeded synthetic rigs already resident in HBM; NBUF distinct input/output
 frame-set buffers rotate so that the 256 MB Infinity Cache cannot serve
 repeats.
@@ -316,14 +316,15 @@ def main() -> int:
     ap.add_argument("--config", default="rig14", choices=["rig14", "uneven", "vga"])
     ap.add_argument("--nbuf", type=int, default=8)
     ap.add_argument("--smoothing", action="store_true")
-    ap.add_argument("--mode", default="alt", choices=["alt", "pipe", "graph-pipelined", "graph", "eager"],
-                    help="alt: alternating pipeline (whole frame-sets alternate between two streams); pipe: "
-                         "rt_pipe_submit per step (the estimate of t+1 overlaps the apply of t on two streams); "
-                         "graph-pipelined: one two-branch graph launch per step; graph: one captured rt_frameset "
-                         "per step; eager: one rt_frameset call per step")
+    ap.add_argument("--mode", default="pipe", choices=["pipe", "graph-pipelined", "graph", "eager"],
+                    help="pipe: rt_pipe_submit per step (statistics and estimates on their own stream, applies "
+                         "round-robin over --lanes streams); graph-pipelined: one two-branch graph launch per step; "
+                         "graph: one captured rt_frameset per step; eager: one rt_frameset call per step")
+    ap.add_argument("--lanes", type=int, default=2, help="apply streams of the pipe mode")
+    ap.add_argument("--group", type=int, default=4, help="frame-sets whose applies the pipe mode issues together")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile-rows", type=int, default=0)
-    ap.add_argument("--depth", type=int, default=2, help="slots of the pipe mode")
+    ap.add_argument("--depth", type=int, default=8, help="slots of the pipe mode (>= lanes, >= group, divides --nbuf)")
     ap.add_argument("--copy-only", action="store_true", help="time the streaming copy of the frame bytes only")
     ap.add_argument("--timing-every", type=int, default=30,
                     help="time every n-th apply launch of the timed region with HIP events")
@@ -388,8 +389,12 @@ def main() -> int:
     stream = torch.cuda.current_stream()
     pipe, graphs = None, None
     b = rig.bufs
-    if args.mode in ("pipe", "alt"):
-        pipe = Pipeline(rig, depth=args.depth, alternate=args.mode == "alt")
+    if args.mode == "pipe":
+        # A frame-set's buffers are reused `nbuf` steps later: with nbuf a
+        # multiple of depth that apply starts only after the earlier one ended.
+        assert max(args.lanes, args.group) <= args.depth and args.nbuf % args.depth == 0, \
+            "need lanes, group <= depth and depth | nbuf"
+        pipe = Pipeline(rig, depth=args.depth, lanes=args.lanes, group=args.group)
         in_ptrs = [rt.ptr_array(x) for x in ins]
         out_ptrs = [rt.ptr_array(x) for x in outs]
     elif args.mode == "graph":
@@ -406,12 +411,12 @@ def main() -> int:
                            ins[(i + 1) % args.nbuf], luts[(i + 1) % 2]) for i in range(args.nbuf)]
     s_first = s_last = stream
 
-    def step(i):
+    def step(i, ready=None):
         if graphs is not None:
             graphs[i % args.nbuf].launch(stream)
         elif pipe is not None:
             j = i % args.nbuf
-            pipe.submit(ins[j], outs[j], stream, in_ptrs[j], out_ptrs[j])
+            pipe.submit(ins[j], outs[j], stream, in_ptrs[j], out_ptrs[j], ready_event=ready)
         else:
             rig.frameset(ins[i % args.nbuf], outs[i % args.nbuf])
 
@@ -432,9 +437,10 @@ def main() -> int:
     ev0.record(s_first)
     for i in range(args.steps):
         step(first + i)
-    if args.mode == "alt":
+    if pipe is not None:
         pipe.join(s_last)
     ev1.record(s_last)
+    host_issue = time.perf_counter() - w0
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
     rig.check()
@@ -454,6 +460,17 @@ def main() -> int:
         apply_ms = np.array(rt.rt_ctx_apply_times(rig.ctx, args.steps))
         rt.rt_ctx_timing(rig.ctx, 0)
 
+    # The same kernel with no other work beside it (one stream, launches back to back).
+    alone_ms = None
+    if pipe is not None and args.lanes > 1:
+        rt.rt_ctx_timing(rig.ctx, args.steps)
+        for i in range(args.steps):
+            rt.rt_apply(rig.ctx, ins[i % args.nbuf], outs[i % args.nbuf], b.lut8, b.q16, b.weights,
+                        b.whole_hist, b.whole_sums, stream=stream)
+        torch.cuda.synchronize()
+        alone_ms = np.array(rt.rt_ctx_apply_times(rig.ctx, args.steps))
+        rt.rt_ctx_timing(rig.ctx, 0)
+
     # Frame-set latency, outside the timed region: per-step start and end events.
     n_lat = min(args.steps, 100)
     ev_s = [torch.cuda.Event(enable_timing=True) for _ in range(n_lat)]
@@ -461,8 +478,10 @@ def main() -> int:
     torch.cuda.synchronize()
     for i in range(n_lat):
         ev_s[i].record(s_first)
-        step(first + i)
-        if args.mode == "alt":
+        # The pipeline's statistics stream waits for the start event as for
+        # arriving frames, so that no part of the step runs before it.
+        step(first + i, ev_s[i])
+        if pipe is not None:
             pipe.join(s_last)
         ev_e[i].record(s_last)
     torch.cuda.synchronize()
@@ -480,19 +499,26 @@ def main() -> int:
             "kernel": "k_apply<true,true> (apply + fused whole-frame statistics)", "bytes_per_launch": ab,
             "launch_us": round(launch_us, 2), "launch_timing": apply_where, "launches_timed": int(apply_ms.size), "copy_ceiling_GBs": round(copy_gbs, 1),
             "frac_of_copy_ceiling": round(achieved / copy_gbs, 4)}
-    if args.mode == "alt":
+    if pipe is not None and args.lanes > 1:
         # Applies of consecutive frame-sets overlap here, so a launch's own
         # duration overstates its share of the time: also the apply bytes of
-        # one frame-set over the measured time per frame-set.
+        # one frame-set over the measured time per frame-set, and the launch
+        # duration with nothing beside it.
         step_gbs = ab / (ms_total / args.steps * 1e-3) / 1e9
         roof["per_step"] = {"achieved": round(step_gbs, 1), "frac": round(step_gbs / HBM_PEAK_GBS, 4),
                             "what": "apply bytes per frame-set / time per frame-set (launches overlap)"}
+        alone_us = float(alone_ms.mean() * 1e3)
+        alone_gbs = ab / (alone_us * 1e-6) / 1e9
+        roof["alone"] = {"launch_us": round(alone_us, 2), "achieved": round(alone_gbs, 1),
+                         "frac": round(alone_gbs / HBM_PEAK_GBS, 4), "launches_timed": int(alone_ms.size),
+                         "what": "the same launches back to back on one stream after the timed region"}
     out = {
         "metric": METRIC, "value": round(gpix, 3), "unit": "GPix/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_step, 5), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u8", "data": "synthetic",
         "config": {"workload": workload, "path": "plain", "mode": "smoothing" if args.smoothing else "standard",
-                   "launch_mode": args.mode,
+                   "launch_mode": args.mode + (f", {args.lanes} apply lanes, depth {args.depth}, group {args.group}"
+                                               if pipe is not None else ""),
                    "n_blocks": opts.n_blocks, "band_width": opts.band_width, "pixels_per_frameset": px,
                    "rotating_buffers": args.nbuf, "tile_rows": tile_rows, "n_tiles": n_tiles},
         "hbm_frac": round(alg_bytes * args.steps / (ms_total / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
@@ -502,6 +528,7 @@ def main() -> int:
                        "what": "start to end of each step's GPU work, steps back to back, measured after the timed "
                                "region (in graph-pipelined mode a frame-set's estimate ran one step earlier)"},
         "wall_s": round(wall, 4),
+        "host_issue_us_per_step": round(host_issue / args.steps * 1e6, 2),
         "roofline": roof,
         "kernel_hash": khash,
     }

@@ -180,10 +180,13 @@ rt_status rt_apply(rt_ctx* ctx, const void* const* frames, void* const* out_fram
 /* One whole frame-set: band statistics of frame t -> estimate (updating
  * `state`) -> tables and weights, clearing stats' whole-frame fields -> apply
  * to frame t with the whole-frame statistics of the input accumulated in the
- * same pass.  Three kernels, all cameras of all rings batched in each; no
- * kernel waits on another workgroup.  Same results as rt_stats (bands),
- * rt_estimate, rt_build_lut and rt_apply (with whole statistics) in that
- * order.  stats, state and lut must not overlap each other or the frames. */
+ * same pass.  Two kernels, all cameras of all rings batched in each: the
+ * first takes each seam block whole (the band statistics of both facing
+ * bands, then their estimates and tables), the second applies; no kernel
+ * waits on another workgroup.  Same
+ * results as rt_stats (bands), rt_estimate, rt_build_lut and rt_apply (with
+ * whole statistics) in that order.  stats, state and lut must not overlap
+ * each other or the frames. */
 rt_status rt_frameset(rt_ctx* ctx, const void* const* frames, void* const* out_frames, const rt_stats_buf* stats,
                       const rt_params_buf* state, const rt_lut_buf* lut, void* stream);
 
@@ -210,40 +213,43 @@ rt_status rt_frameset_batch(rt_ctx* ctx, uint64_t active, const void* const* fra
  * so work already enqueued (and captured graphs) keep the set they had. */
 rt_status rt_ctx_set_active(rt_ctx* ctx, uint64_t active);
 
-/* Two-stream frame-set pipeline.  rt_pipe_submit enqueues one frame-set: on
- * the pipeline's own stream E the band statistics, estimate and tables of
- * that frame-set (after `ready_event`, a hipEvent_t passed as void*, if not
- * NULL: the caller records it once the frames are written; stream E does not
- * otherwise wait for the caller's stream), and on the caller's `stream` the
- * apply pass with fused whole-frame statistics.  Consecutive frame-sets rotate over `depth`
- * table and whole-frame-statistics slots (luts[depth], wholes[depth], all
- * distinct), so the estimate of frame-set t+1 overlaps the apply of frame-set
- * t; band statistics and estimator state are single buffers ordered on
- * stream E, which makes the results exactly those of consecutive rt_frameset
- * calls.  *slot_out (may be NULL) receives the slot of the submitted
- * frame-set; its statistics and tables stay valid until `depth` further
- * submits.  Completion: record an event on `stream` after the submit.  The
+/* Frame-set pipeline.  rt_pipe_submit enqueues one frame-set: on the
+ * pipeline's own stream E the band statistics, estimate and tables of that
+ * frame-set (after `ready_event`, a hipEvent_t passed as void*, if not NULL:
+ * the caller records it once the frames are written; stream E does not
+ * otherwise wait for the caller's stream), and on the frame-set's lane the
+ * apply pass with fused whole-frame statistics, after its tables.  Lanes are
+ * taken round-robin: lane 0 is the caller's `stream`, lanes 1.. are streams
+ * of the pipeline, so the applies of consecutive frame-sets on different
+ * lanes may run concurrently.  Applies are issued `group` frame-sets at a
+ * time (when the group is full, or at rt_pipe_join): one cross-stream
+ * dependency per lane and group instead of one per frame-set, which is what
+ * bounds the host's submission rate.  Consecutive frame-sets rotate over
+ * `depth` table and whole-frame-statistics slots (luts[depth], wholes[depth],
+ * all distinct); the statistics of frame-set t wait for the apply of
+ * frame-set t - depth (depth >= 2 * group lets stream E run a group ahead of
+ * the applies), so the apply of frame-set t + depth starts only after that of
+ * t has finished (frame buffers may be reused from then on).  Band statistics
+ * and estimator state are single buffers ordered on stream E, which makes the
+ * results exactly those of consecutive rt_frameset calls.  *slot_out (may be
+ * NULL) receives the slot of the submitted frame-set; its statistics and
+ * tables stay valid until `depth` further submits.  rt_pipe_join(p, stream)
+ * issues the pending applies and makes `stream` wait for everything
+ * submitted so far; call it before depending on any frame-set's results.
+ * 1 <= lanes <= 4, lanes <= depth <= 8, 1 <= group <= depth; rt_pipe_create
+ * is lanes = group = 1 (each submit issues its apply on `stream`).  The
  * buffers are caller-owned and must outlive the pipeline; submits of one
  * pipeline must come from one host thread and may use one caller stream only. */
 typedef struct rt_pipe rt_pipe;
 rt_status rt_pipe_create(rt_ctx* ctx, int32_t depth, const rt_stats_buf* bands, const rt_params_buf* state,
                          const rt_lut_buf* luts, const rt_stats_buf* wholes, rt_pipe** out);
+rt_status rt_pipe_create_lanes(rt_ctx* ctx, int32_t depth, int32_t lanes, int32_t group, const rt_stats_buf* bands,
+                               const rt_params_buf* state, const rt_lut_buf* luts, const rt_stats_buf* wholes,
+                               rt_pipe** out);
 rt_status rt_pipe_submit(rt_pipe* p, const void* const* frames, void* const* out_frames, void* stream,
                          void* ready_event, int32_t* slot_out);
-rt_status rt_pipe_destroy(rt_pipe* p);
-
-/* The same pipeline with two slots (luts[2], wholes[2]) in which whole
- * frame-sets alternate between the caller's stream (even submits) and the
- * pipeline's own stream (odd submits): each runs its band statistics,
- * estimate and apply on its stream, and its statistics wait only for the
- * previous frame-set's estimate, so the next frame-set's statistics and
- * estimate overlap the current apply, and two applies may overlap each other.
- * Results are those of consecutive rt_frameset calls.  Completion of the odd
- * frame-sets is not ordered on the caller's stream: rt_pipe_join(p, stream)
- * makes `stream` wait for everything submitted so far. */
-rt_status rt_pipe_create_alternating(rt_ctx* ctx, const rt_stats_buf* bands, const rt_params_buf* state,
-                                     const rt_lut_buf* luts, const rt_stats_buf* wholes, rt_pipe** out);
 rt_status rt_pipe_join(rt_pipe* p, void* stream);
+rt_status rt_pipe_destroy(rt_pipe* p);
 
 /* A frame-set captured once into a HIP graph for fixed buffers and replayed
  * with one launch per frame-set.

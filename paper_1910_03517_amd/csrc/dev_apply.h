@@ -114,7 +114,9 @@ __device__ inline bool direct_ok(int64_t A, int64_t Bq) {
   return lo >= INT32_MIN && hi <= INT32_MAX;
 }
 
-template <int BPS, bool WRITE, bool STATS, bool DIRECT = false>
+// Returns the blended sample, or with RAW the dot product itself: the sample
+// is then its byte 1 and bytes 2-3 are zero (the sum stays below 2^16).
+template <int BPS, bool WRITE, bool STATS, bool DIRECT = false, bool RAW = false>
 __device__ inline uint32_t one_sample(uint32_t x, int c, int p, const PixConst& pc, ApplyLds& L, int hrep,
                                       int shift, uint32_t maxv, unsigned long long& a1, unsigned long long& a2) {
   if (STATS) {
@@ -143,7 +145,15 @@ __device__ inline uint32_t one_sample(uint32_t x, int c, int p, const PixConst& 
   }
   // ((256 - w) x + w f + 128) >> 8 as one dot product of (x, f) with (256 - w, w).
   if (!(BPS == 1 && DIRECT)) xf = x | (f << 16);
-  return __builtin_amdgcn_udot2(__builtin_bit_cast(u16x2, xf), __builtin_bit_cast(u16x2, pc.wp[p]), 128u, false) >> 8;
+  const uint32_t dot =
+      __builtin_amdgcn_udot2(__builtin_bit_cast(u16x2, xf), __builtin_bit_cast(u16x2, pc.wp[p]), 128u, false);
+  return RAW ? dot : dot >> 8;
+}
+
+// Four raw dot products (see one_sample) to one dword of samples: byte 1 of
+// each, in order, by two byte permutes (selector byte 0x0c gives zero).
+__device__ inline uint32_t pack_raw4(uint32_t r0, uint32_t r1, uint32_t r2, uint32_t r3) {
+  return __builtin_amdgcn_perm(r1, r0, 0x0c0c0501u) | __builtin_amdgcn_perm(r3, r2, 0x05010c0cu);
 }
 
 // Adds the workgroup's LDS histogram of camera `cam` (replicas summed) and
@@ -410,15 +420,15 @@ __device__ void apply_run_direct(const Geo& g, const FramePtrs& fp, const Bufs& 
         for (int u = 0; u < kUnroll; ++u) {
           if (row + u < R1) {
             next_block(row + u);
-            uint32_t o[NW];
-#pragma unroll
-            for (int q = 0; q < NW; ++q) o[q] = 0;
+            uint32_t r[4 * C], o[NW];
 #pragma unroll
             for (int i = 0; i < 4 * C; ++i) {
               const int p = i / C, c = i - (i / C) * C;
               const uint32_t x = (d[u][i >> 2] >> (8 * (i & 3))) & 0xffu;
-              o[i >> 2] |= one_sample<1, true, true, true>(x, c, p, pc, L, hrep, 0, 255u, a1, a2) << (8 * (i & 3));
+              r[i] = one_sample<1, true, true, true, true>(x, c, p, pc, L, hrep, 0, 255u, a1, a2);
             }
+#pragma unroll
+            for (int q = 0; q < NW; ++q) o[q] = pack_raw4(r[4 * q], r[4 * q + 1], r[4 * q + 2], r[4 * q + 3]);
             store_group<NW>(rout, (row + u) * pitch + cbyte, o);
           }
         }

@@ -31,26 +31,18 @@ __device__ inline Moments moments_of(uint64_t n, uint64_t s1, uint64_t s2) {
 // Status of a (camera, side, block, channel) unit after the fit.
 enum { kStNone = 0, kStNew = 1, kStIdentity = 2, kStUnused = 3 };
 
-// The plain estimate of unit u = ((k * 2 + s) * NB + j) * 3 + c, before any
-// temporal step: kStNew with (a, b), kStNone (an empty band: keep the state),
-// kStIdentity (no facing band), kStUnused (channel beyond the camera's).
-// Both sides of a seam derive the same shared moments because binary64
-// addition is commutative.
-__device__ inline int fit_new(const Geo& g, const uint64_t* band_sums, int u, double& a, double& bb) {
-  const int nb = g.n_blocks;
-  const int c = u % kCS;
-  const int j = (u / kCS) % nb;
-  const int s = (u / (kCS * nb)) & 1;
-  const int k = u / (kCS * nb * 2);
-  const DevCam& cam = g.cams[k];
+// The plain estimate of channel c of a unit of a camera with `channels`
+// channels from the (n, S1, S2) of its own band and of the band it faces
+// (fac NULL: no facing band), before any temporal step: kStNew with (a, b),
+// kStNone (an empty band: keep the state), kStIdentity (no facing band),
+// kStUnused (channel beyond the camera's).  Both sides of a seam derive the
+// same shared moments because binary64 addition is commutative.
+__device__ inline int fit_sums(const Geo& g, int channels, int c, const uint64_t* own, const uint64_t* fac, double& a,
+                               double& bb) {
   a = 1.0;
   bb = 0.0;
-  if (c >= cam.channels) return kStUnused;
-  const int fc = cam.face_cam[s];
-  if (fc < 0) return kStIdentity;
-  const int64_t fu = unit_index(fc, cam.face_side[s], j, c, nb);
-  const uint64_t* own = band_sums + (int64_t)u * 3;
-  const uint64_t* fac = band_sums + fu * 3;
+  if (c >= channels) return kStUnused;
+  if (!fac) return kStIdentity;
   if (own[0] == 0 || fac[0] == 0) return kStNone;
   const Moments mo = moments_of(own[0], own[1], own[2]);
   const Moments mf = moments_of(fac[0], fac[1], fac[2]);
@@ -65,34 +57,60 @@ __device__ inline int fit_new(const Geo& g, const uint64_t* band_sums, int u, do
   return kStNew;
 }
 
-// The state update of unit u from its fit (section 3.1's exponential
-// smoothing in smoothing mode; the first estimate is taken as is).
-__device__ inline void temporal_update(const Geo& g, double* params, uint8_t* valid, int u, int status, double a,
-                                       double bb) {
-  double* p = params + (int64_t)u * 2;
+// fit_sums of unit u = ((k * 2 + s) * NB + j) * 3 + c from the band sums in
+// the caller layout.
+__device__ inline int fit_new(const Geo& g, const uint64_t* band_sums, int u, double& a, double& bb) {
+  const int nb = g.n_blocks;
+  const int c = u % kCS;
+  const int j = (u / kCS) % nb;
+  const int s = (u / (kCS * nb)) & 1;
+  const int k = u / (kCS * nb * 2);
+  const DevCam& cam = g.cams[k];
+  const int fc = cam.face_cam[s];
+  const uint64_t* fac = fc < 0 ? nullptr : band_sums + unit_index(fc, cam.face_side[s], j, c, nb) * 3;
+  return fit_sums(g, cam.channels, c, band_sums + (int64_t)u * 3, fac, a, bb);
+}
+
+// The state (p0, p1, v) of a unit after its fit, in place (section 3.1's
+// exponential smoothing in smoothing mode; the first estimate is taken as is).
+__device__ inline void temporal_step(const Geo& g, int status, double a, double bb, double& p0, double& p1,
+                                     uint8_t& v) {
   if (status == kStUnused || status == kStIdentity) {
-    p[0] = 1.0; p[1] = 0.0; valid[u] = status == kStIdentity ? 1 : 0;
+    p0 = 1.0; p1 = 0.0; v = status == kStIdentity ? 1 : 0;
     return;
   }
-  const bool had = valid[u] != 0;
+  const bool had = v != 0;
   if (status == kStNone) {            // no estimate: keep the state
-    if (!had) { p[0] = 1.0; p[1] = 0.0; }
+    if (!had) { p0 = 1.0; p1 = 0.0; }
     return;
   }
   if (g.mode == RT_MODE_SMOOTHING && had) {
     const double keep = 1.0 - g.alpha;
-    const double ta = keep * p[0];
+    const double ta = keep * p0;
     const double na = g.alpha * a;
-    const double tb = keep * p[1];
+    const double tb = keep * p1;
     const double nbv = g.alpha * bb;
     a = ta + na;
     bb = tb + nbv;
   }
-  p[0] = a;
-  p[1] = bb;
-  valid[u] = 1;
+  p0 = a;
+  p1 = bb;
+  v = 1;
 }
 
+// temporal_step on the state of unit u in the caller's buffers.
+__device__ inline void temporal_update(const Geo& g, double* params, uint8_t* valid, int u, int status, double a,
+                                       double bb) {
+  double* p = params + (int64_t)u * 2;
+  double p0 = p[0], p1 = p[1];
+  uint8_t v = valid[u];
+  temporal_step(g, status, a, bb, p0, p1, v);
+  p[0] = p0;
+  p[1] = p1;
+  valid[u] = v;
+}
+
+// Fit and state update of unit u from the caller's buffers.
 __device__ inline void estimate_unit(const Geo& g, const Bufs& b, int u) {
   double a, bb;
   const int st = fit_new(g, b.band_sums, u, a, bb);
@@ -100,17 +118,16 @@ __device__ inline void estimate_unit(const Geo& g, const Bufs& b, int u) {
 }
 
 // Entry x of the three channel tables of unit (k, s, j) = `unit3` (the
-// channel-0 unit index divided by 3); thread x == 0 also stores the q16 pairs.
-__device__ inline void lut_entry(const Geo& g, const Bufs& b, int unit3, int x) {
+// channel-0 unit index divided by 3) from the maps ab[c] = (a, b); thread
+// x == 0 also stores the q16 pairs.
+__device__ inline void lut_entry_ab(const Geo& g, const Bufs& b, int unit3, int x, const double (*ab)[2]) {
   const int k = unit3 / (2 * g.n_blocks);
   const DevCam& cam = g.cams[k];
 #pragma unroll
   for (int c = 0; c < kCS; ++c) {
     const int64_t u = (int64_t)unit3 * kCS + c;
-    const double a = b.params[u * 2 + 0];
-    const double bv = b.params[u * 2 + 1];
-    const int64_t A = (int64_t)__builtin_rint(a * 65536.0);
-    const int64_t Bq = (int64_t)__builtin_rint(bv * 65536.0);
+    const int64_t A = (int64_t)__builtin_rint(ab[c][0] * 65536.0);
+    const int64_t Bq = (int64_t)__builtin_rint(ab[c][1] * 65536.0);
     if (x == 0) {
       b.q16[u * 2 + 0] = A;
       b.q16[u * 2 + 1] = Bq;
@@ -121,6 +138,18 @@ __device__ inline void lut_entry(const Geo& g, const Bufs& b, int unit3, int x) 
       b.lut8[u * kNB + x] = (uint8_t)y;
     }
   }
+}
+
+// lut_entry_ab with the maps read from the caller's parameters.
+__device__ inline void lut_entry(const Geo& g, const Bufs& b, int unit3, int x) {
+  double ab[kCS][2];
+#pragma unroll
+  for (int c = 0; c < kCS; ++c) {
+    const int64_t u = (int64_t)unit3 * kCS + c;
+    ab[c][0] = b.params[u * 2 + 0];
+    ab[c][1] = b.params[u * 2 + 1];
+  }
+  lut_entry_ab(g, b, unit3, x, ab);
 }
 
 // Q8 blend weight of column col of a camera of width W: h = floor(W/2); the

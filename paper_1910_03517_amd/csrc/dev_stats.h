@@ -17,7 +17,8 @@ struct StatsLds {
 // consecutive 8-bit samples or 2 16-bit samples of the row, and only the bytes
 // inside the band count.  8-bit sums follow from the exact histogram.
 template <int C, int BPS>
-__device__ void band_unit(const Geo& g, const FramePtrs& fp, const Bufs& b, int k, int s, int j, StatsLds& L) {
+__device__ void band_unit(const Geo& g, const FramePtrs& fp, const Bufs& b, int k, int s, int j, StatsLds& L,
+                          uint64_t* sums_out) {
   const int tid = threadIdx.x;
   const DevCam cam = uniform_cam(g.cams[k]);
   auto clear = [&]() {
@@ -145,19 +146,26 @@ __device__ void band_unit(const Geo& g, const FramePtrs& fp, const Bufs& b, int 
         if (BPS == 2) return m == 1 ? a1 : a2;
         return m == 1 ? h * x : h * x * x;
       },
-      [&](int i, unsigned long long tot) { b.band_sums[u0 * 3 + i] = tot; }, L.red);
+      [&](int i, unsigned long long tot) {
+        b.band_sums[u0 * 3 + i] = tot;
+        if (sums_out) sums_out[i] = tot;
+      },
+      L.red);
 }
 
-__device__ inline void band_unit_dispatch(const Geo& g, const FramePtrs& fp, const Bufs& b, int unit, StatsLds& L) {
+// Band statistics of unit (camera, side, block) = `unit`; with sums_out
+// (LDS) its nine sums are also left there for the workgroup.
+__device__ inline void band_unit_dispatch(const Geo& g, const FramePtrs& fp, const Bufs& b, int unit, StatsLds& L,
+                                          uint64_t* sums_out = nullptr) {
   const int nb = g.n_blocks;
   const int k = unit / (2 * nb);
   const int s = (unit / nb) & 1;
   const int j = unit % nb;
   const DevCam& cam = g.cams[k];
   if (!cam_active(g, k)) return;
-  if (cam.bps == 2) band_unit<1, 2>(g, fp, b, k, s, j, L);
-  else if (cam.channels == 3) band_unit<3, 1>(g, fp, b, k, s, j, L);
-  else band_unit<1, 1>(g, fp, b, k, s, j, L);
+  if (cam.bps == 2) band_unit<1, 2>(g, fp, b, k, s, j, L, sums_out);
+  else if (cam.channels == 3) band_unit<3, 1>(g, fp, b, k, s, j, L, sums_out);
+  else band_unit<1, 1>(g, fp, b, k, s, j, L, sums_out);
 }
 
 // Zero the whole-frame histogram and sums of every active camera (grid-stride).

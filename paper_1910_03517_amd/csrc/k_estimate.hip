@@ -24,28 +24,84 @@ __global__ __launch_bounds__(kThreads) void k_weights(Geo g, Bufs b) {
   if (cam_active(g, k)) b.weights[i] = (uint16_t)blend_weight(g.cams[k].width, col);
 }
 
-// Estimate, tables and weights of one (camera, side, block) per workgroup:
-// threads 0..2 fit the three channels, then every thread builds one table
-// entry.  Workgroups of side 0, block 0 also write their camera's weights.
-__global__ __launch_bounds__(kThreads) void k_estimate_lut(Geo g, Bufs b) {
-  const int u3 = blockIdx.x;                 // (k * 2 + s) * nb + j
-  const int tid = threadIdx.x;
+// Band statistics, estimate and tables of a frame-set in one launch, one
+// workgroup per (camera k, block j): it takes the right band of camera k, the
+// band that faces it (the left band of the next camera of the ring) and, at
+// the start of an open ring, camera k's left band, which faces nothing.
+// Every unit is taken exactly once, and a unit's estimate needs only its own
+// band and the one it faces, so after the statistics of its bands the
+// workgroup fits those units and builds their tables with no other
+// workgroup involved.  Same results as k_band_stats, k_estimate, k_build_lut
+// and k_weights in sequence (the whole-frame statistics that the frame-set's
+// apply pass accumulates are cleared here too, when given).
+__global__ __launch_bounds__(kThreads) void k_band_estimate(Geo g, FramePtrs fp, Bufs b) {
+  // This kernel's chain of dependent steps is what the next apply waits
+  // for; its waves take issue priority over the apply waves they share
+  // compute units with (measured on MI355X: 628 -> 674 GPix/s in the
+  // pipelined frame-set loop).
+  __builtin_amdgcn_s_setprio(3);
+  __shared__ StatsLds L;
+  __shared__ uint64_t sums[3][9];            // (n, S1, S2) per channel of the units taken
+  __shared__ double ab[3][kCS][2];           // their maps after the fit
   const int nb = g.n_blocks;
-  const int k = u3 / (2 * nb);
-  // Clear the whole-frame statistics that the apply pass of this frame-set
-  // accumulates (skipped when the caller clears them itself).
+  const int k = blockIdx.x / nb, j = blockIdx.x - (blockIdx.x / nb) * nb;
+  const int tid = threadIdx.x;
   if (b.whole_hist) zero_whole(g, b, blockIdx.x * kThreads + tid, gridDim.x * kThreads);
   if (!cam_active(g, k)) return;
-  if (tid < kCS) estimate_unit(g, b, u3 * kCS + tid);
-  __syncthreads();
-  lut_entry(g, b, u3, tid);
-  if (u3 % (2 * nb) == 0)
+  const DevCam& cam = g.cams[k];
+  int unit[3];
+  unit[0] = (k * 2 + 1) * nb + j;
+  const int fc = uniform(cam.face_cam[1]);
+  unit[1] = fc < 0 ? -1 : (fc * 2 + uniform(cam.face_side[1])) * nb + j;
+  unit[2] = uniform(cam.face_cam[0]) < 0 ? k * 2 * nb + j : -1;
+  // Thread 64 t + c fits channel c of unit t: its state is read now, ahead
+  // of the band passes.
+  const int t = tid / kWave, c = tid % kWave;
+  const bool fitter = t < 3 && c < kCS && unit[t < 3 ? t : 0] >= 0;
+  const int64_t u = fitter ? (int64_t)unit[t] * kCS + c : 0;
+  double p0 = 0.0, p1 = 0.0;
+  uint8_t v = 0;
+  if (fitter) {
+    p0 = b.params[u * 2];
+    p1 = b.params[u * 2 + 1];
+    v = b.valid[u];
+  }
+  band_unit_dispatch(g, fp, b, unit[0], L, sums[0]);
+  if (unit[1] >= 0) {
+    __syncthreads();
+    band_unit_dispatch(g, fp, b, unit[1], L, sums[1]);
+  }
+  if (unit[2] >= 0) {
+    __syncthreads();
+    band_unit_dispatch(g, fp, b, unit[2], L, sums[2]);
+  }
+  if (j == 0)
     for (int col = tid; col < g.w_max; col += kThreads)
-      b.weights[(int64_t)k * g.w_max + col] = (uint16_t)blend_weight(g.cams[k].width, col);
+      b.weights[(int64_t)k * g.w_max + col] = (uint16_t)blend_weight(cam.width, col);
+  __syncthreads();
+  if (fitter) {
+    // Units 0 and 1 face each other; unit 2 faces nothing (nor does unit 0
+    // without unit 1).
+    const int other = t == 0 ? 1 : (t == 1 ? 0 : -1);
+    const uint64_t* fac = (other >= 0 && unit[other] >= 0) ? &sums[other][c * 3] : nullptr;
+    const int channels = uniform(g.cams[unit[t] / (2 * nb)].channels);
+    double a, bb;
+    const int st = fit_sums(g, channels, c, &sums[t][c * 3], fac, a, bb);
+    temporal_step(g, st, a, bb, p0, p1, v);
+    b.params[u * 2] = p0;
+    b.params[u * 2 + 1] = p1;
+    b.valid[u] = v;
+    ab[t][c][0] = p0;
+    ab[t][c][1] = p1;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int w = 0; w < 3; ++w)
+    if (unit[w] >= 0) lut_entry_ab(g, b, unit[w], tid, ab[w]);
 }
 
-hipError_t launch_estimate_lut(const Geo& g, const Bufs& b, hipStream_t st) {
-  hipLaunchKernelGGL(k_estimate_lut, dim3(g.n_cams * 2 * g.n_blocks), dim3(kThreads), 0, st, g, b);
+hipError_t launch_band_estimate(const Geo& g, const FramePtrs& fp, const Bufs& b, hipStream_t st) {
+  hipLaunchKernelGGL(k_band_estimate, dim3(g.n_cams * g.n_blocks), dim3(kThreads), 0, st, g, fp, b);
   return hipGetLastError();
 }
 

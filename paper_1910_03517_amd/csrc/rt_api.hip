@@ -533,10 +533,8 @@ static rt_status frameset_masked(rt_ctx* ctx, uint64_t active, const void* const
   g.active = active;
   const FramePtrs fp = make_ptrs_masked(ctx, frames, out_frames, active);
   const Bufs b = make_bufs(stats, state, lut);
-  hipError_t e = launch_band_stats(g, fp, b, st);
-  if (e != hipSuccess) return hip_fail(e, "band statistics");
-  e = launch_estimate_lut(g, b, st);
-  if (e != hipSuccess) return hip_fail(e, "estimate and tables");
+  const hipError_t e = launch_band_estimate(g, fp, b, st);
+  if (e != hipSuccess) return hip_fail(e, "band statistics, estimate and tables");
   return whole_pass(ctx, g, fp, b, true, false, st);
 }
 
@@ -619,8 +617,7 @@ rt_status rt_graph_create(rt_ctx* ctx, const void* const* frames, void* const* o
     ba.band_sums = bands->band_sums;
     if (!pipelined) {
       // bands -> estimate + tables (+ clearing the whole-frame statistics) -> apply -> reduction
-      e = launch_band_stats(ctx->geo, fp, ba, s0);
-      if (e == hipSuccess) e = launch_estimate_lut(ctx->geo, ba, s0);
+      e = launch_band_estimate(ctx->geo, fp, ba, s0);
       if (e == hipSuccess) e = launch_apply(ctx->geo, fp, ba, true, true, s0);
     } else {
       // Branch E: statistics, estimate and tables of the next frame-set.
@@ -631,8 +628,7 @@ rt_status rt_graph_create(rt_ctx* ctx, const void* const* frames, void* const* o
       be.band_sums = bands->band_sums;
       e = hipEventRecord(ev_fork, s0);
       if (e == hipSuccess) e = hipStreamWaitEvent(s1, ev_fork, 0);
-      if (e == hipSuccess) e = launch_band_stats(ctx->geo, fn, be, s1);
-      if (e == hipSuccess) e = launch_estimate_lut(ctx->geo, be, s1);
+      if (e == hipSuccess) e = launch_band_estimate(ctx->geo, fn, be, s1);
       if (e == hipSuccess) e = launch_zero_whole(ctx->geo, ba, s0);
       if (e == hipSuccess) e = launch_apply(ctx->geo, fp, ba, true, true, s0);
       if (e == hipSuccess) e = hipEventRecord(ev_join, s1);
@@ -675,27 +671,78 @@ rt_status rt_graph_destroy(rt_graph* g) {
 }
 
 // ---------------------------------------------------------------------------
-// Two-stream frame-set pipeline (see ringcorr.h).
+// Frame-set pipeline (see ringcorr.h).
+//
+// Host cost decides the design: on this runtime a kernel launch costs the
+// host about 1 us, an event record about 5 us and a stream wait on an event
+// that has not completed yet about 12 us (on a completed one about 1 us).
+// So the statistics and estimates are launched on stream E as frame-sets
+// are submitted, and the applies are issued a group at a time: one record
+// on E after the group's estimates, then per lane one wait, the lane's
+// applies of the group and one record.  Slot reuse waits on the record that
+// covers the slot's previous apply, skipped when the event has completed.
 // ---------------------------------------------------------------------------
+constexpr int kMaxLanes = 4;
+constexpr int kGroupRing = 12;                   // a slot's last apply is at most depth + 1 groups old
+
 struct rt_pipe {
   rt_ctx* ctx = nullptr;
-  int depth = 2;
-  bool alternate = false;   // whole frame-sets alternate between the caller's stream and s_est
-  hipStream_t s_est = nullptr;
-  std::vector<hipEvent_t> ev_lut, ev_done;      // per slot: tables ready / apply done
+  int depth = 2, lanes = 1, group = 1;
+  hipStream_t s_est = nullptr;                   // band statistics, estimate, tables (in order)
+  hipStream_t s_lane[kMaxLanes - 1] = {};        // lanes 1..; lane 0 is the caller's stream
+  hipEvent_t ev_est[kGroupRing] = {};            // per group: its estimates done (on E)
+  hipEvent_t ev_lane[kGroupRing][kMaxLanes] = {};  // per group and lane: the lane's applies done
+  std::vector<int64_t> slot_group;               // group of the slot's last apply (-1: none)
+  std::vector<int> slot_lane;                    // its lane
+  int last_group[kMaxLanes] = {-1, -1, -1, -1};  // per lane: last group with an apply on it
   rt_stats_buf bands{};
   rt_params_buf state{};
   std::vector<rt_lut_buf> luts;
   std::vector<rt_stats_buf> wholes;
-  int64_t submitted = 0;
+  struct Pending { FramePtrs fp; int slot; int lane; };
+  std::vector<Pending> pending;                  // estimated, apply not yet issued
+  hipStream_t caller = nullptr;                  // lane 0 of the pending applies
+  int64_t submitted = 0, groups = 0;
 };
 
-rt_status rt_pipe_create(rt_ctx* ctx, int32_t depth, const rt_stats_buf* bands, const rt_params_buf* state,
-                         const rt_lut_buf* luts, const rt_stats_buf* wholes, rt_pipe** out) {
+// Issues the pending applies as one group (see above).
+static hipError_t pipe_flush(rt_pipe* p) {
+  if (p->pending.empty()) return hipSuccess;
+  rt_ctx* ctx = p->ctx;
+  const int g = (int)(p->groups % kGroupRing);
+  hipError_t e = hipEventRecord(p->ev_est[g], p->s_est);
+  bool used[kMaxLanes] = {};
+  for (const auto& q : p->pending) used[q.lane] = true;
+  for (int l = 0; e == hipSuccess && l < p->lanes; ++l) {
+    if (!used[l]) continue;
+    hipStream_t sl = l ? p->s_lane[l - 1] : p->caller;
+    e = hipStreamWaitEvent(sl, p->ev_est[g], 0);
+    for (size_t i = 0; e == hipSuccess && i < p->pending.size(); ++i) {
+      const auto& q = p->pending[i];
+      if (q.lane != l) continue;
+      const Bufs ba = make_bufs(&p->wholes[q.slot], nullptr, &p->luts[q.slot]);
+      e = timed_apply(ctx, ctx->geo, q.fp, ba, true, true, sl);
+      p->slot_group[q.slot] = p->groups;
+      p->slot_lane[q.slot] = l;
+    }
+    if (e == hipSuccess) e = hipEventRecord(p->ev_lane[g][l], sl);
+    p->last_group[l] = (int)g;
+  }
+  p->pending.clear();
+  ++p->groups;
+  return e;
+}
+
+rt_status rt_pipe_create_lanes(rt_ctx* ctx, int32_t depth, int32_t lanes, int32_t group, const rt_stats_buf* bands,
+                               const rt_params_buf* state, const rt_lut_buf* luts, const rt_stats_buf* wholes,
+                               rt_pipe** out) {
   if (!out) return fail(RT_EINVAL, "out is NULL");
   *out = nullptr;
   if (!ctx) return fail(RT_EINVAL, "ctx is NULL");
   if (depth < 1 || depth > 8) return fail(RT_EINVAL, "depth %d outside 1..8", depth);
+  if (lanes < 1 || lanes > kMaxLanes) return fail(RT_EINVAL, "lanes %d outside 1..%d", lanes, kMaxLanes);
+  if (depth < lanes) return fail(RT_EINVAL, "depth %d below lanes %d", depth, lanes);
+  if (group < 1 || group > depth) return fail(RT_EINVAL, "group %d outside 1..depth (%d)", group, depth);
   if (!luts || !wholes) return fail(RT_EINVAL, "luts or wholes is NULL");
   rt_status r = check_stats(bands, true, false);
   if (r == RT_OK) r = check_params(state);
@@ -706,24 +753,32 @@ rt_status rt_pipe_create(rt_ctx* ctx, int32_t depth, const rt_stats_buf* bands, 
   if (!p) return fail(RT_ENOMEM, "host allocation failed");
   p->ctx = ctx;
   p->depth = depth;
+  p->lanes = lanes;
+  p->group = group;
   p->bands = *bands;
   p->state = *state;
   p->luts.assign(luts, luts + depth);
   p->wholes.assign(wholes, wholes + depth);
+  p->slot_group.assign(depth, -1);
+  p->slot_lane.assign(depth, 0);
+  p->pending.reserve(group);
   hipError_t e = hipStreamCreateWithFlags(&p->s_est, hipStreamNonBlocking);
-  for (int i = 0; e == hipSuccess && i < depth; ++i) {
-    hipEvent_t a = nullptr, b = nullptr;
-    e = hipEventCreateWithFlags(&a, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&b, hipEventDisableTiming);
-    if (a) p->ev_lut.push_back(a);
-    if (b) p->ev_done.push_back(b);
+  for (int l = 0; e == hipSuccess && l < lanes - 1; ++l) e = hipStreamCreateWithFlags(&p->s_lane[l], hipStreamNonBlocking);
+  for (int g = 0; e == hipSuccess && g < kGroupRing; ++g) {
+    e = hipEventCreateWithFlags(&p->ev_est[g], hipEventDisableTiming);
+    for (int l = 0; e == hipSuccess && l < lanes; ++l) e = hipEventCreateWithFlags(&p->ev_lane[g][l], hipEventDisableTiming);
   }
   if (e != hipSuccess) {
     rt_pipe_destroy(p);
-    return hip_fail(e, "creating the pipeline stream and events");
+    return hip_fail(e, "creating the pipeline streams and events");
   }
   *out = p;
   return RT_OK;
+}
+
+rt_status rt_pipe_create(rt_ctx* ctx, int32_t depth, const rt_stats_buf* bands, const rt_params_buf* state,
+                         const rt_lut_buf* luts, const rt_stats_buf* wholes, rt_pipe** out) {
+  return rt_pipe_create_lanes(ctx, depth, 1, 1, bands, state, luts, wholes, out);
 }
 
 rt_status rt_pipe_submit(rt_pipe* p, const void* const* frames, void* const* out_frames, void* stream,
@@ -733,75 +788,59 @@ rt_status rt_pipe_submit(rt_pipe* p, const void* const* frames, void* const* out
   rt_status r = check_frames(ctx, frames, "frames");
   if (r == RT_OK) r = check_frames(ctx, (const void* const*)out_frames, "out_frames");
   if (r != RT_OK) return r;
-  hipStream_t sa = (hipStream_t)stream;
-  if (p->alternate) {
-    // Frame-set t runs whole (statistics, estimate, apply) on stream t % 2;
-    // its statistics wait for the previous frame-set's estimate (state and
-    // band buffers), the only dependency between the two streams.
-    const int slot = (int)(p->submitted & 1);
-    hipStream_t s = slot ? p->s_est : sa;
-    const FramePtrs fp = make_ptrs(ctx, frames, out_frames);
-    Bufs be = make_bufs(&p->bands, &p->state, &p->luts[slot]);
-    be.whole_hist = p->wholes[slot].whole_hist;    // cleared by the estimate kernel
-    be.whole_sums = p->wholes[slot].whole_sums;
-    const Bufs ba = make_bufs(&p->wholes[slot], nullptr, &p->luts[slot]);
-    hipError_t e = hipSuccess;
-    if (ready_event) e = hipStreamWaitEvent(s, (hipEvent_t)ready_event, 0);
-    if (e == hipSuccess && p->submitted > 0) e = hipStreamWaitEvent(s, p->ev_lut[slot ^ 1], 0);
-    if (e == hipSuccess) e = launch_band_stats(ctx->geo, fp, be, s);
-    if (e == hipSuccess) e = launch_estimate_lut(ctx->geo, be, s);
-    if (e == hipSuccess) e = hipEventRecord(p->ev_lut[slot], s);
-    if (e == hipSuccess) e = timed_apply(ctx, ctx->geo, fp, ba, true, true, s);
-    if (e == hipSuccess) e = hipEventRecord(p->ev_done[slot], s);
-    if (e != hipSuccess) return hip_fail(e, "pipeline submit");
-    if (slot_out) *slot_out = slot;
-    ++p->submitted;
-    return RT_OK;
-  }
   const int slot = (int)(p->submitted % p->depth);
+  hipError_t e = hipSuccess;
+  // The slot's previous apply may still be pending: issue it first.
+  for (const auto& q : p->pending)
+    if (q.slot == slot) { e = pipe_flush(p); break; }
+  p->caller = (hipStream_t)stream;
   const FramePtrs fp = make_ptrs(ctx, frames, out_frames);
   Bufs be = make_bufs(&p->bands, &p->state, &p->luts[slot]);
   be.whole_hist = p->wholes[slot].whole_hist;    // cleared by the estimate kernel
   be.whole_sums = p->wholes[slot].whole_sums;
-  Bufs ba = make_bufs(&p->wholes[slot], nullptr, &p->luts[slot]);
-  // Stream E: after the frames are ready (ready_event) and after the apply
-  // that last used this slot: band statistics, estimate, tables, clearing.
-  hipError_t e = hipSuccess;
-  if (ready_event) e = hipStreamWaitEvent(p->s_est, (hipEvent_t)ready_event, 0);
-  if (e == hipSuccess && p->submitted >= p->depth) e = hipStreamWaitEvent(p->s_est, p->ev_done[slot], 0);
-  if (e == hipSuccess) e = launch_band_stats(ctx->geo, fp, be, p->s_est);
-  if (e == hipSuccess) e = launch_estimate_lut(ctx->geo, be, p->s_est);
-  if (e == hipSuccess) e = hipEventRecord(p->ev_lut[slot], p->s_est);
-  // Caller's stream: the apply pass with this slot's tables and statistics.
-  if (e == hipSuccess) e = hipStreamWaitEvent(sa, p->ev_lut[slot], 0);
-  if (e == hipSuccess) e = timed_apply(ctx, ctx->geo, fp, ba, true, true, sa);
-  if (e == hipSuccess) e = hipEventRecord(p->ev_done[slot], sa);
+  // Stream E, in submission order: after the frames are ready (ready_event)
+  // and after the apply that last used this slot, the band statistics,
+  // estimate and tables.  Band statistics and estimator state are single
+  // buffers, so their order on E gives the results of consecutive frame-sets.
+  if (e == hipSuccess && ready_event) e = hipStreamWaitEvent(p->s_est, (hipEvent_t)ready_event, 0);
+  if (e == hipSuccess && p->slot_group[slot] >= 0) {
+    hipEvent_t prev = p->ev_lane[p->slot_group[slot] % kGroupRing][p->slot_lane[slot]];
+    const hipError_t q = hipEventQuery(prev);
+    if (q == hipErrorNotReady) e = hipStreamWaitEvent(p->s_est, prev, 0);
+    else if (q != hipSuccess) e = q;
+  }
+  if (e == hipSuccess) e = launch_band_estimate(ctx->geo, fp, be, p->s_est);
+  if (e == hipSuccess) {
+    p->pending.push_back({fp, slot, (int)(p->submitted % p->lanes)});
+    if ((int)p->pending.size() == p->group) e = pipe_flush(p);
+  }
   if (e != hipSuccess) return hip_fail(e, "pipeline submit");
   if (slot_out) *slot_out = slot;
   ++p->submitted;
   return RT_OK;
 }
 
-rt_status rt_pipe_create_alternating(rt_ctx* ctx, const rt_stats_buf* bands, const rt_params_buf* state,
-                                     const rt_lut_buf* luts, const rt_stats_buf* wholes, rt_pipe** out) {
-  rt_status r = rt_pipe_create(ctx, 2, bands, state, luts, wholes, out);
-  if (r == RT_OK) (*out)->alternate = true;
-  return r;
-}
-
 rt_status rt_pipe_join(rt_pipe* p, void* stream) {
   if (!p) return fail(RT_EINVAL, "pipe is NULL");
-  if (!p->alternate || p->submitted < 2) return RT_OK;
-  hipError_t e = hipStreamWaitEvent((hipStream_t)stream, p->ev_done[1], 0);
+  hipError_t e = pipe_flush(p);
+  for (int l = 0; e == hipSuccess && l < p->lanes; ++l)
+    if (p->last_group[l] >= 0) e = hipStreamWaitEvent((hipStream_t)stream, p->ev_lane[p->last_group[l]][l], 0);
   return e == hipSuccess ? RT_OK : hip_fail(e, "pipeline join");
 }
 
 rt_status rt_pipe_destroy(rt_pipe* p) {
   if (!p) return RT_OK;
+  (void)pipe_flush(p);
   if (p->s_est) (void)hipStreamSynchronize(p->s_est);
-  for (hipEvent_t ev : p->ev_done) (void)hipEventSynchronize(ev);
-  for (hipEvent_t ev : p->ev_lut) (void)hipEventDestroy(ev);
-  for (hipEvent_t ev : p->ev_done) (void)hipEventDestroy(ev);
+  for (int l = 0; l < p->lanes; ++l)
+    if (p->last_group[l] >= 0) (void)hipEventSynchronize(p->ev_lane[p->last_group[l]][l]);
+  for (int g = 0; g < kGroupRing; ++g) {
+    if (p->ev_est[g]) (void)hipEventDestroy(p->ev_est[g]);
+    for (int l = 0; l < kMaxLanes; ++l)
+      if (p->ev_lane[g][l]) (void)hipEventDestroy(p->ev_lane[g][l]);
+  }
+  for (int l = 0; l < kMaxLanes - 1; ++l)
+    if (p->s_lane[l]) (void)hipStreamDestroy(p->s_lane[l]);
   if (p->s_est) (void)hipStreamDestroy(p->s_est);
   delete p;
   return RT_OK;

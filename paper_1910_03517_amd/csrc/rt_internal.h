@@ -138,7 +138,7 @@ __host__ __device__ inline int64_t unit_index(int k, int s, int j, int c, int nb
 // Launchers (each defined next to its kernels).  All return hipError_t of the launch.
 hipError_t launch_band_stats(const Geo& g, const FramePtrs& fp, const Bufs& b, hipStream_t st);
 hipError_t launch_estimate(const Geo& g, const Bufs& b, hipStream_t st);
-hipError_t launch_estimate_lut(const Geo& g, const Bufs& b, hipStream_t st);
+hipError_t launch_band_estimate(const Geo& g, const FramePtrs& fp, const Bufs& b, hipStream_t st);
 hipError_t launch_build_lut(const Geo& g, const Bufs& b, hipStream_t st);
 hipError_t launch_apply(const Geo& g, const FramePtrs& fp, const Bufs& b, bool write, bool stats, hipStream_t st,
                         hipEvent_t start = nullptr, hipEvent_t stop = nullptr);

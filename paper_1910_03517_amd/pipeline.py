@@ -1,13 +1,13 @@
 """Frame-set pipeline over the C-ABI (rt_pipe).
 
-Per frame-set the same kernels as rt_frameset run, split over two HIP
-streams by the library: the band statistics, estimate and tables of
-frame-set t+1 run on the pipeline's own stream while the bandwidth-bound
-apply of frame-set t runs on the caller's stream.  Tables and whole-frame
-statistics rotate over `depth` slots; band statistics and the estimator
-state are single buffers, so the results are exactly those of consecutive
-rt_frameset calls.  This module only allocates the slot buffers and
-marshals arguments.
+Per frame-set the same kernels as rt_frameset run, split over HIP streams by
+the library: the band statistics, estimate and tables of each frame-set run
+in order on the pipeline's own stream, ahead of the bandwidth-bound applies,
+which go round-robin over one or more lanes (the caller's stream, then
+streams of the pipeline).  Tables and whole-frame statistics rotate over
+`depth` slots; band statistics and the estimator state are single buffers,
+so the results are exactly those of consecutive rt_frameset calls.  This
+module only allocates the slot buffers and marshals arguments.
 """
 from __future__ import annotations
 
@@ -32,18 +32,24 @@ class WholeSet:
 
 
 class Pipeline:
-    """Overlaps the estimate of frame-set t+1 with the apply of frame-set t.
+    """Band statistics and estimates of consecutive frame-sets run in order on
+    the pipeline's stream while the applies go round-robin over `lanes`
+    streams (the caller's first), so the estimate of frame-set t+1 overlaps
+    the apply of frame-set t, and with lanes > 1 the applies of consecutive
+    frame-sets overlap each other.  Applies are issued `group` frame-sets at
+    a time (one cross-stream dependency per lane and group).  `depth` slots
+    of tables and whole-frame statistics (>= lanes, >= group; 2 * group lets
+    the estimates run a group ahead).  Call join() before depending on the
+    results of submitted frame-sets."""
 
-    alternate=True: whole frame-sets alternate between the caller's stream and
-    the pipeline's own (rt_pipe_create_alternating); call join() before
-    depending on the caller's stream for all submitted work."""
-
-    def __init__(self, rig: rt.Rig, depth: int = 2, alternate: bool = False):
+    def __init__(self, rig: rt.Rig, depth: int = 2, lanes: int = 1, group: int = 1):
         self.rig = rig
-        self.depth = 2 if alternate else depth
+        self.depth = depth
+        self.lanes = lanes
+        self.group = group
         self.luts = [LutSet(rig.sizes, rig.device) for _ in range(self.depth)]
         self.whole = [WholeSet(rig.sizes, rig.device) for _ in range(self.depth)]
-        self.pipe = rt.Pipe(rig.ctx, rig.bufs, self.luts, self.whole, alternate=alternate)
+        self.pipe = rt.Pipe(rig.ctx, rig.bufs, self.luts, self.whole, lanes=lanes, group=group)
 
     def submit(self, frames, out_frames, stream=None, frame_ptrs=None, out_ptrs=None, ready_event=None) -> int:
         """Enqueue one frame-set on `stream` (default: torch's current stream); returns its slot.

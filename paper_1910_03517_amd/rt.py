@@ -28,7 +28,7 @@ EXPORTED = ["rt_ctx_create", "rt_ctx_destroy", "rt_ctx_sizes", "rt_stats", "rt_e
             "rt_build_lut", "rt_apply", "rt_frameset", "rt_frameset_batch", "rt_ctx_set_active", "rt_ctx_check", "rt_ctx_tune", "rt_ctx_tuning",
             "rt_stream_copy", "rt_ctx_timing", "rt_ctx_apply_times", "rt_graph_create", "rt_graph_launch",
             "rt_graph_destroy", "rt_pipe_create", "rt_pipe_submit", "rt_pipe_destroy",
-            "rt_pipe_create_alternating", "rt_pipe_join",
+            "rt_pipe_create_lanes", "rt_pipe_join",
             "rt_surrogate_features", "rt_estimate_new", "rt_surrogate_targets", "rt_surrogate_select",
             "rt_surrogate_frameset",
             "rt_mlp_forward", "rt_mlp_backward", "rt_mlp_adam", "rt_mlp_mse", "rt_gather_rows", "rt_mlp_train",
@@ -125,8 +125,9 @@ def load(path: str = LIB_PATH) -> ct.CDLL:
                                    ct.POINTER(rt_lut_buf), ct.POINTER(rt_stats_buf), ct.POINTER(P)]
     lib.rt_pipe_submit.argtypes = [P, ct.POINTER(P), ct.POINTER(P), P, P, ct.POINTER(ct.c_int32)]
     lib.rt_pipe_destroy.argtypes = [P]
-    lib.rt_pipe_create_alternating.argtypes = [P, ct.POINTER(rt_stats_buf), ct.POINTER(rt_params_buf),
-                                               ct.POINTER(rt_lut_buf), ct.POINTER(rt_stats_buf), ct.POINTER(P)]
+    lib.rt_pipe_create_lanes.argtypes = [P, ct.c_int32, ct.c_int32, ct.c_int32, ct.POINTER(rt_stats_buf),
+                                         ct.POINTER(rt_params_buf), ct.POINTER(rt_lut_buf), ct.POINTER(rt_stats_buf),
+                                         ct.POINTER(P)]
     lib.rt_pipe_join.argtypes = [P, P]
     M = ct.POINTER(rt_mlp)
     lib.rt_surrogate_features.argtypes = [P, ct.POINTER(rt_stats_buf), P, P]
@@ -218,13 +219,15 @@ def rt_ctx_tuning(ctx) -> tuple[int, int, int]:
 
 
 class Pipe:
-    """rt_pipe: the estimate of frame-set t+1 overlaps the apply of frame-set t.
+    """rt_pipe: statistics and estimates on the pipeline's stream, applies
+    round-robin over `lanes` streams (the caller's first), issued `group`
+    frame-sets at a time.
 
     luts / wholes are sequences of `depth` objects with lut8, q16, weights /
     whole_hist, whole_sums tensors; bufs provides band_hist, band_sums,
     params, valid."""
 
-    def __init__(self, ctx, bufs, luts, wholes, alternate: bool = False):
+    def __init__(self, ctx, bufs, luts, wholes, lanes: int = 1, group: int = 1):
         depth = len(luts)
         assert len(wholes) == depth
         la = (rt_lut_buf * depth)(*[rt_lut_buf(_p(l.lut8), _p(l.q16), _p(l.weights)) for l in luts])
@@ -232,13 +235,12 @@ class Pipe:
         bb = rt_stats_buf(_p(bufs.band_hist), _p(bufs.band_sums), None, None)
         pb = rt_params_buf(_p(bufs.params), _p(bufs.valid))
         h = ct.c_void_p()
-        if alternate:
-            assert depth == 2, "the alternating pipeline has two slots"
-            _check(load().rt_pipe_create_alternating(ctx, ct.byref(bb), ct.byref(pb), la, wa, ct.byref(h)))
-        else:
-            _check(load().rt_pipe_create(ctx, depth, ct.byref(bb), ct.byref(pb), la, wa, ct.byref(h)))
+        _check(load().rt_pipe_create_lanes(ctx, depth, lanes, group, ct.byref(bb), ct.byref(pb), la, wa,
+                                           ct.byref(h)))
         self.handle = h
         self.depth = depth
+        self.lanes = lanes
+        self.group = group
         self._keep = (bufs, luts, wholes)
         self._slot = ct.c_int32()
 
@@ -254,7 +256,7 @@ class Pipe:
         return self._slot.value
 
     def join(self, stream=None) -> None:
-        """Order `stream` after every frame-set submitted so far (alternating pipelines)."""
+        """Issue pending applies; order `stream` after every frame-set submitted so far."""
         _check(load().rt_pipe_join(self.handle, _stream_handle(stream)))
 
     def close(self) -> None:

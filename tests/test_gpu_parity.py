@@ -144,23 +144,25 @@ def test_rig14_frameset_smoothing():
     frameset_sequence(synth.rig14_1080p(), rt.Options(smoothing=True), 3)
 
 
-def test_rig14_alternating_pipeline_matches_oracle():
-    """The bench's launch configuration at its full size: four 14x1920x1080
-    frame-sets (drifting gains, smoothing) through the alternating pipeline,
-    every output against the oracle's frame-set sequence, the last two
-    frame-sets' whole-frame statistics and the final state bitwise."""
+def test_rig14_lanes_pipeline_matches_oracle():
+    """The bench's launch configuration at its full size: ten 14x1920x1080
+    frame-sets (drifting gains, smoothing) through the pipeline with 2 apply
+    lanes, 8 slots (two reused) and applies issued 4 frame-sets at a time (the
+    last group partial), every output against the oracle's frame-set
+    sequence, the last two frame-sets' whole-frame statistics and the final
+    state bitwise."""
     from paper_1910_03517_amd.pipeline import Pipeline
     spec = synth.rig14_1080p()
     cams = rt_cams(spec.cams)
     opts = rt.Options(smoothing=True)
     rig = rt.Rig(cams, opts)
-    pipe = Pipeline(rig, alternate=True)
-    n = 4
+    pipe = Pipeline(rig, depth=8, lanes=2, group=4)
+    n = 10
     frames = [synth.rig_frames(spec, t, drift=True) for t in range(n)]
     dev = [rig.upload(f) for f in frames]
     outs = [rig.alloc_frames() for _ in range(n)]
     torch.cuda.synchronize()
-    say("case: rig14 alternating pipeline, 4 frame-sets")
+    say("case: rig14 pipeline, 2 lanes, depth 8, group 4, 10 frame-sets")
     slots = [pipe.submit(dev[t], outs[t]) for t in range(n)]
     pipe.join()
     torch.cuda.synchronize()
@@ -256,34 +258,36 @@ def test_stream_copy_utility(vec):
     assert torch.equal(src, dst)
 
 
-@pytest.mark.parametrize("depth", [1, 2, 3, 0])
-def test_pipeline_matches_sequential_framesets(depth):
-    """Two-stream pipelining of consecutive frame-sets gives the results of
-    consecutive rt_frameset calls, bit for bit (smoothing mode, drifting gains).
-    depth 0 stands for the alternating pipeline (two slots)."""
+@pytest.mark.parametrize("depth,lanes,group", [(1, 1, 1), (2, 1, 1), (3, 1, 1), (2, 2, 1), (3, 2, 1), (4, 3, 1),
+                                               (4, 4, 1), (4, 2, 2), (3, 1, 3), (5, 3, 3), (8, 2, 4)])
+def test_pipeline_matches_sequential_framesets(depth, lanes, group):
+    """Pipelining of consecutive frame-sets (statistics and estimates on one
+    stream, applies round-robin over `lanes` streams and issued `group` at a
+    time, `depth` slots reused over 11 frame-sets, the last group partial)
+    gives the results of consecutive rt_frameset calls, bit for bit
+    (smoothing mode, drifting gains)."""
     from paper_1910_03517_amd.pipeline import Pipeline
-    say(f"case: pipeline depth {depth} vs sequential, 4x 480x200 rgb8, 5 frame-sets")
-    alternate = depth == 0
-    depth = 2 if alternate else depth
+    say(f"case: pipeline depth {depth} lanes {lanes} group {group} vs sequential, 4x 480x200 rgb8, 11 frame-sets")
     spec = synth.RigSpec("pipe 4x480x200", 11, [synth.CamSpec(480, 200, 3, 8, 0, p) for p in range(4)])
     cams = rt_cams(spec.cams)
     opts = rt.Options(n_blocks=8, band_width=16, smoothing=True)
     seq = rt.Rig(cams, opts)
     par = rt.Rig(cams, opts)
-    pipe = Pipeline(par, depth=depth, alternate=alternate)
-    frames_t = [synth.rig_frames(spec, t, drift=True) for t in range(5)]
+    pipe = Pipeline(par, depth=depth, lanes=lanes, group=group)
+    T = 11
+    frames_t = [synth.rig_frames(spec, t, drift=True) for t in range(T)]
     dev = [seq.upload(f) for f in frames_t]
     torch.cuda.synchronize()
-    outs_p = [par.alloc_frames() for _ in range(5)]
-    slots = [pipe.submit(dev[t], outs_p[t]) for t in range(5)]
+    outs_p = [par.alloc_frames() for _ in range(T)]
+    slots = [pipe.submit(dev[t], outs_p[t]) for t in range(T)]
     pipe.join()
     torch.cuda.synchronize()
     out_s = seq.alloc_frames()
-    for t in range(5):
+    for t in range(T):
         seq.frameset(dev[t], out_s)
         torch.cuda.synchronize()
         hs = seq.bufs.host()
-        if t >= 5 - depth:   # slots of the last `depth` frame-sets are still intact
+        if t >= T - depth:   # slots of the last `depth` frame-sets are still intact
             w = pipe.whole[slots[t]]
             assert np.array_equal(w.whole_hist.cpu().numpy(), seq.bufs.whole_hist.cpu().numpy())
             assert np.array_equal(w.whole_sums.cpu().numpy(), seq.bufs.whole_sums.cpu().numpy())
@@ -296,6 +300,19 @@ def test_pipeline_matches_sequential_framesets(depth):
     pipe.close()
     seq.close()
     par.close()
+
+
+def test_pipeline_rejects_bad_lanes_and_groups():
+    from paper_1910_03517_amd.pipeline import LutSet, WholeSet
+    spec = synth.RigSpec("pipe 2x64x32", 12, [synth.CamSpec(64, 32, 3, 8, 0, p) for p in range(2)])
+    rig = rt.Rig(rt_cams(spec.cams), rt.Options(n_blocks=2, band_width=8))
+    for depth, lanes, group, needle in [(2, 0, 1, "lanes"), (4, 5, 1, "lanes"), (2, 3, 1, "below"),
+                                        (2, 1, 0, "group"), (2, 1, 3, "group")]:
+        luts = [LutSet(rig.sizes) for _ in range(depth)]
+        wholes = [WholeSet(rig.sizes) for _ in range(depth)]
+        with pytest.raises(rt.RtError, match=needle):
+            rt.Pipe(rig.ctx, rig.bufs, luts, wholes, lanes=lanes, group=group)
+    rig.close()
 
 
 def _eager_sequence(cams, opts, dev_frames, order):
