@@ -320,8 +320,8 @@ def main() -> int:
                     help="pipe: rt_pipe_submit per step (statistics and estimates on their own stream, applies "
                          "round-robin over --lanes streams); graph-pipelined: one two-branch graph launch per step; "
                          "graph: one captured rt_frameset per step; eager: one rt_frameset call per step")
-    ap.add_argument("--lanes", type=int, default=2, help="apply streams of the pipe mode")
-    ap.add_argument("--group", type=int, default=4, help="frame-sets whose applies the pipe mode issues together")
+    ap.add_argument("--lanes", type=int, default=3, help="apply streams of the pipe mode")
+    ap.add_argument("--group", type=int, default=3, help="frame-sets whose applies the pipe mode issues together")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--depth", type=int, default=8, help="slots of the pipe mode (>= lanes, >= group, divides --nbuf)")

@@ -146,8 +146,8 @@ def test_rig14_frameset_smoothing():
 
 def test_rig14_lanes_pipeline_matches_oracle():
     """The bench's launch configuration at its full size: ten 14x1920x1080
-    frame-sets (drifting gains, smoothing) through the pipeline with 2 apply
-    lanes, 8 slots (two reused) and applies issued 4 frame-sets at a time (the
+    frame-sets (drifting gains, smoothing) through the pipeline with 3 apply
+    lanes, 8 slots (two reused) and applies issued 3 frame-sets at a time (the
     last group partial), every output against the oracle's frame-set
     sequence, the last two frame-sets' whole-frame statistics and the final
     state bitwise."""
@@ -156,13 +156,13 @@ def test_rig14_lanes_pipeline_matches_oracle():
     cams = rt_cams(spec.cams)
     opts = rt.Options(smoothing=True)
     rig = rt.Rig(cams, opts)
-    pipe = Pipeline(rig, depth=8, lanes=2, group=4)
+    pipe = Pipeline(rig, depth=8, lanes=3, group=3)
     n = 10
     frames = [synth.rig_frames(spec, t, drift=True) for t in range(n)]
     dev = [rig.upload(f) for f in frames]
     outs = [rig.alloc_frames() for _ in range(n)]
     torch.cuda.synchronize()
-    say("case: rig14 pipeline, 2 lanes, depth 8, group 4, 10 frame-sets")
+    say("case: rig14 pipeline, 3 lanes, depth 8, group 3, 10 frame-sets")
     slots = [pipe.submit(dev[t], outs[t]) for t in range(n)]
     pipe.join()
     torch.cuda.synchronize()
