@@ -74,6 +74,35 @@ def test_small_geometries(case):
     run_separate(spec, opts, frames, pad)
 
 
+@pytest.mark.parametrize("case", SMALL_CASES, ids=[f"{c[0]}x{c[1]}x{c[2]}b{c[3]}k{c[4]}" for c in SMALL_CASES])
+def test_small_geometries_frameset(case):
+    """The same geometries through rt_frameset, whose first kernel takes each
+    seam block whole (both facing bands, their fits and tables; at the start
+    of an open chain also the left band that faces nothing): two frame-sets
+    with smoothing, each against the oracle's frame-set sequence."""
+    W, H, C, bd, K, closed, NB, B, pad = case
+    say("case: frameset", case)
+    rng = np.random.default_rng((abs(hash(case)) + 1) % (2 ** 32))
+    spec = [synth.CamSpec(W, H, C, bd, 0, p) for p in range(K)]
+    cams = rt_cams(spec, pad)
+    opts = rt.Options(n_blocks=NB, band_width=B, closed_ring=closed, smoothing=True)
+    rig = rt.Rig(cams, opts)
+    co, oo = oracle_cams(cams), oracle_opts(opts)
+    out = rig.alloc_frames()
+    prev_p = prev_v = None
+    for t in range(2):
+        frames = [synth.tiny_frame(H, W, C, bd, rng) for _ in range(K)]
+        dev = rig.upload(frames)
+        rig.frameset(dev, out)
+        torch.cuda.synchronize()
+        g = rig.bufs.host()
+        g["out"] = rig.download(out)
+        res = compare_step(co, oo, frames, g, prev_p, prev_v)
+        assert res["bitwise"], f"frame-set {t}: params not bitwise equal"
+        prev_p, prev_v = res["ref"]["params"], res["ref"]["valid"]
+    rig.close()
+
+
 def test_flat_and_saturated_bands():
     """sigma = 0 bands (a = 1 path) and fully saturated cameras."""
     say("case: flat/saturated 3x 96x64")
