@@ -252,12 +252,13 @@ def serving_leg(args, base, surrogate_w=None) -> dict:
 
     spec = synth.rig14_1080p()
     n_rigs, pool = 3, 4
-    out = {"rigs": n_rigs, "rig": spec.name, "fps": 30, "jitter_ms": 2.0, "mem_budget_framesets": 4}
+    out = {"rigs": n_rigs, "rig": spec.name, "fps": 30, "jitter_ms": 2.0, "mem_budget_framesets": 4,
+           "plain_apply_lanes": args.serve_lanes}
     for path in ("plain", "surrogate"):
         if path == "surrogate" and surrogate_w is None:
             continue
         sur = Surrogate(surrogate_w, tol=args.sur_tol) if path == "surrogate" else None
-        be = GpuBackend([spec.cams] * n_rigs, surrogate=sur)
+        be = GpuBackend([spec.cams] * n_rigs, surrogate=sur, lanes=args.serve_lanes)
         frames = []
         for r in range(n_rigs):
             cams = [be.cams[i] for i in be.idx[r]]
@@ -337,6 +338,8 @@ def main() -> int:
     ap.add_argument("--sur-lr", type=float, default=1e-3)
     ap.add_argument("--sur-tol", type=float, default=1e-3)
     ap.add_argument("--serve-seconds", type=float, default=10.0, help="paced serving: 30 frame-sets per second per rig")
+    ap.add_argument("--serve-lanes", type=int, default=1,
+                    help="apply lanes of the serving backend's frame-set pipeline (plain path; 1 = one stream)")
     ap.add_argument("--serve-saturated", type=int, default=40, help="frame-sets per rig in the saturated run")
     args = ap.parse_args()
     if args.gpus != 1:

@@ -251,6 +251,18 @@ rt_status rt_pipe_submit(rt_pipe* p, const void* const* frames, void* const* out
 rt_status rt_pipe_join(rt_pipe* p, void* stream);
 rt_status rt_pipe_destroy(rt_pipe* p);
 
+/* rt_pipe_submit for the cameras in bitmask `active` only (whole rings, as
+ * for rt_frameset_batch; the frames and out_frames entries of the other
+ * cameras may be NULL), for serving several rigs from one context: the
+ * frame-set's statistics, estimate, tables and whole-frame statistics are
+ * written for the active cameras and its slot's entries of the others keep
+ * their values.  done_event (a hipEvent_t as void*, may be NULL) is recorded
+ * on the frame-set's lane right after its apply, so its completion means
+ * that this frame-set's outputs and slot are ready; it needs group = 1
+ * (RT_EINVAL otherwise). */
+rt_status rt_pipe_submit_batch(rt_pipe* p, uint64_t active, const void* const* frames, void* const* out_frames,
+                               void* stream, void* ready_event, void* done_event, int32_t* slot_out);
+
 /* A frame-set captured once into a HIP graph for fixed buffers and replayed
  * with one launch per frame-set.
  *

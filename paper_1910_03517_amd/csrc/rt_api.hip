@@ -699,7 +699,7 @@ struct rt_pipe {
   rt_params_buf state{};
   std::vector<rt_lut_buf> luts;
   std::vector<rt_stats_buf> wholes;
-  struct Pending { FramePtrs fp; int slot; int lane; };
+  struct Pending { FramePtrs fp; uint64_t active; hipEvent_t done; int slot; int lane; };
   std::vector<Pending> pending;                  // estimated, apply not yet issued
   hipStream_t caller = nullptr;                  // lane 0 of the pending applies
   int64_t submitted = 0, groups = 0;
@@ -721,7 +721,10 @@ static hipError_t pipe_flush(rt_pipe* p) {
       const auto& q = p->pending[i];
       if (q.lane != l) continue;
       const Bufs ba = make_bufs(&p->wholes[q.slot], nullptr, &p->luts[q.slot]);
-      e = timed_apply(ctx, ctx->geo, q.fp, ba, true, true, sl);
+      Geo g = ctx->geo;
+      g.active = q.active;
+      e = timed_apply(ctx, g, q.fp, ba, true, true, sl);
+      if (e == hipSuccess && q.done) e = hipEventRecord(q.done, sl);
       p->slot_group[q.slot] = p->groups;
       p->slot_lane[q.slot] = l;
     }
@@ -781,20 +784,22 @@ rt_status rt_pipe_create(rt_ctx* ctx, int32_t depth, const rt_stats_buf* bands, 
   return rt_pipe_create_lanes(ctx, depth, 1, 1, bands, state, luts, wholes, out);
 }
 
-rt_status rt_pipe_submit(rt_pipe* p, const void* const* frames, void* const* out_frames, void* stream,
-                         void* ready_event, int32_t* slot_out) {
-  if (!p) return fail(RT_EINVAL, "pipe is NULL");
+static rt_status pipe_submit(rt_pipe* p, uint64_t active, const void* const* frames, void* const* out_frames,
+                             void* stream, void* ready_event, void* done_event, int32_t* slot_out) {
   rt_ctx* ctx = p->ctx;
-  rt_status r = check_frames(ctx, frames, "frames");
-  if (r == RT_OK) r = check_frames(ctx, (const void* const*)out_frames, "out_frames");
+  rt_status r = check_frames_masked(ctx, active, frames, "frames");
+  if (r == RT_OK) r = check_frames_masked(ctx, active, (const void* const*)out_frames, "out_frames");
   if (r != RT_OK) return r;
+  if (done_event && p->group != 1) return fail(RT_EINVAL, "done_event needs a pipeline with group 1");
   const int slot = (int)(p->submitted % p->depth);
   hipError_t e = hipSuccess;
   // The slot's previous apply may still be pending: issue it first.
   for (const auto& q : p->pending)
     if (q.slot == slot) { e = pipe_flush(p); break; }
   p->caller = (hipStream_t)stream;
-  const FramePtrs fp = make_ptrs(ctx, frames, out_frames);
+  Geo g = ctx->geo;
+  g.active = active;
+  const FramePtrs fp = make_ptrs_masked(ctx, frames, out_frames, active);
   Bufs be = make_bufs(&p->bands, &p->state, &p->luts[slot]);
   be.whole_hist = p->wholes[slot].whole_hist;    // cleared by the estimate kernel
   be.whole_sums = p->wholes[slot].whole_sums;
@@ -809,15 +814,29 @@ rt_status rt_pipe_submit(rt_pipe* p, const void* const* frames, void* const* out
     if (q == hipErrorNotReady) e = hipStreamWaitEvent(p->s_est, prev, 0);
     else if (q != hipSuccess) e = q;
   }
-  if (e == hipSuccess) e = launch_band_estimate(ctx->geo, fp, be, p->s_est);
+  if (e == hipSuccess) e = launch_band_estimate(g, fp, be, p->s_est);
   if (e == hipSuccess) {
-    p->pending.push_back({fp, slot, (int)(p->submitted % p->lanes)});
+    p->pending.push_back({fp, active, (hipEvent_t)done_event, slot, (int)(p->submitted % p->lanes)});
     if ((int)p->pending.size() == p->group) e = pipe_flush(p);
   }
   if (e != hipSuccess) return hip_fail(e, "pipeline submit");
   if (slot_out) *slot_out = slot;
   ++p->submitted;
   return RT_OK;
+}
+
+rt_status rt_pipe_submit(rt_pipe* p, const void* const* frames, void* const* out_frames, void* stream,
+                         void* ready_event, int32_t* slot_out) {
+  if (!p) return fail(RT_EINVAL, "pipe is NULL");
+  return pipe_submit(p, p->ctx->geo.active, frames, out_frames, stream, ready_event, nullptr, slot_out);
+}
+
+rt_status rt_pipe_submit_batch(rt_pipe* p, uint64_t active, const void* const* frames, void* const* out_frames,
+                               void* stream, void* ready_event, void* done_event, int32_t* slot_out) {
+  if (!p) return fail(RT_EINVAL, "pipe is NULL");
+  const rt_status r = check_active(p->ctx, active);
+  if (r != RT_OK) return r;
+  return pipe_submit(p, active, frames, out_frames, stream, ready_event, done_event, slot_out);
 }
 
 rt_status rt_pipe_join(rt_pipe* p, void* stream) {

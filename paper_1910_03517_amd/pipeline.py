@@ -59,6 +59,10 @@ class Pipeline:
         synchronized earlier."""
         return self.pipe.submit(frames, out_frames, stream, frame_ptrs, out_ptrs, ready_event)
 
+    def submit_batch(self, active: int, frames, out_frames, stream=None, ready_event=None, done_event=None) -> int:
+        """submit() for the cameras in bitmask `active` (whole rings); see rt_pipe_submit_batch."""
+        return self.pipe.submit_batch(active, frames, out_frames, stream, ready_event, done_event)
+
     def join(self, stream=None) -> None:
         self.pipe.join(stream)
 

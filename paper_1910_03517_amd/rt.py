@@ -28,7 +28,7 @@ EXPORTED = ["rt_ctx_create", "rt_ctx_destroy", "rt_ctx_sizes", "rt_stats", "rt_e
             "rt_build_lut", "rt_apply", "rt_frameset", "rt_frameset_batch", "rt_ctx_set_active", "rt_ctx_check", "rt_ctx_tune", "rt_ctx_tuning",
             "rt_stream_copy", "rt_ctx_timing", "rt_ctx_apply_times", "rt_graph_create", "rt_graph_launch",
             "rt_graph_destroy", "rt_pipe_create", "rt_pipe_submit", "rt_pipe_destroy",
-            "rt_pipe_create_lanes", "rt_pipe_join",
+            "rt_pipe_create_lanes", "rt_pipe_join", "rt_pipe_submit_batch",
             "rt_surrogate_features", "rt_estimate_new", "rt_surrogate_targets", "rt_surrogate_select",
             "rt_surrogate_frameset",
             "rt_mlp_forward", "rt_mlp_backward", "rt_mlp_adam", "rt_mlp_mse", "rt_gather_rows", "rt_mlp_train",
@@ -129,6 +129,8 @@ def load(path: str = LIB_PATH) -> ct.CDLL:
                                          ct.POINTER(rt_params_buf), ct.POINTER(rt_lut_buf), ct.POINTER(rt_stats_buf),
                                          ct.POINTER(P)]
     lib.rt_pipe_join.argtypes = [P, P]
+    lib.rt_pipe_submit_batch.argtypes = [P, ct.c_uint64, ct.POINTER(P), ct.POINTER(P), P, P, P,
+                                         ct.POINTER(ct.c_int32)]
     M = ct.POINTER(rt_mlp)
     lib.rt_surrogate_features.argtypes = [P, ct.POINTER(rt_stats_buf), P, P]
     lib.rt_estimate_new.argtypes = [P, ct.POINTER(rt_stats_buf), P, P, P]
@@ -253,6 +255,22 @@ class Pipe:
         oa = out_ptrs if out_ptrs is not None else _ptr_array(out_frames)
         ev = ct.c_void_p(ready_event.cuda_event) if ready_event is not None else None
         _check(load().rt_pipe_submit(self.handle, fa, oa, _stream_handle(stream), ev, ct.byref(self._slot)))
+        return self._slot.value
+
+    def submit_batch(self, active: int, frames, out_frames, stream=None, ready_event=None, done_event=None) -> int:
+        """submit() for the cameras in bitmask `active` (whole rings); entries of
+        the other cameras may be None.  done_event (a torch.cuda.Event) is
+        recorded right after this frame-set's apply (pipelines with group 1)."""
+        ev = ct.c_void_p(ready_event.cuda_event) if ready_event is not None else None
+        if done_event is not None and not done_event.cuda_event:
+            # torch creates an event's HIP handle at its first record; the
+            # library's record after the apply supersedes this one.
+            import torch
+            done_event.record(stream if stream is not None else torch.cuda.current_stream())
+        dv = ct.c_void_p(done_event.cuda_event) if done_event is not None else None
+        _check(load().rt_pipe_submit_batch(self.handle, ct.c_uint64(active), _ptr_array(frames),
+                                           _ptr_array(out_frames), _stream_handle(stream), ev, dv,
+                                           ct.byref(self._slot)))
         return self._slot.value
 
     def join(self, stream=None) -> None:

@@ -340,11 +340,16 @@ class Server:
 
 class GpuBackend(Backend):
     """The library behind the server: one context holding every rig's cameras
-    (rig r = ring r), one device stream, pooled output frames.  With a
+    (rig r = ring r), pooled output frames.  With lanes = 1, each batch is one
+    rt_frameset_batch on one device stream.  With lanes > 1 (plain path), the
+    batches go through the frame-set pipeline (rt_pipe_submit_batch): their
+    statistics and estimates in order on one stream, their applies
+    round-robin over `lanes` streams, so that consecutive batches overlap;
+    tables and whole-frame statistics rotate over `depth` slots.  With a
     surrogate, the estimate of each frame-set goes through the network with
-    the plain estimate as fallback."""
+    the plain estimate as fallback (one stream)."""
 
-    def __init__(self, rigs, opts=None, surrogate=None, stream=None, device="cuda"):
+    def __init__(self, rigs, opts=None, surrogate=None, stream=None, device="cuda", lanes=1, depth=4):
         import torch
 
         from . import rt
@@ -370,6 +375,10 @@ class GpuBackend(Backend):
         self._pool = [[] for _ in range(self.n_rigs)]
         self._bytes = [sum(cams[i].height * cams[i].pitch_bytes for i in ids) for ids in self.idx]
         self._pixels = [sum(cams[i].width * cams[i].height for i in ids) for ids in self.idx]
+        self.pipe = None
+        if lanes > 1 and surrogate is None:
+            from .pipeline import Pipeline
+            self.pipe = Pipeline(self.rig, depth=depth, lanes=lanes, group=1)
 
     def frameset_bytes(self, rig: int) -> int:
         return self._bytes[rig]
@@ -412,12 +421,15 @@ class GpuBackend(Backend):
             for n, i in enumerate(self.idx[req.rig]):
                 frames[i], outs[i] = req.frames[n], req.out[n]
         st = self.stream
+        ev = self.torch.cuda.Event()
+        if self.pipe is not None:
+            self.pipe.submit_batch(mask, frames, outs, st, done_event=ev)
+            return ev
         if self.surrogate is None:
             self.rig.frameset_batch(mask, frames, outs, st)
         else:
             self.rig.set_active(mask)
             self.surrogate.frameset(self.rig, frames, outs, self.rig.bufs.whole_hist, self.ws, st)
-        ev = self.torch.cuda.Event()
         ev.record(st)
         return ev
 
@@ -428,5 +440,7 @@ class GpuBackend(Backend):
         token.synchronize()
 
     def close(self) -> None:
+        if self.pipe is not None:
+            self.pipe.close()
         self.stream.synchronize()
         self.rig.close()

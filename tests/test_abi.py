@@ -103,6 +103,7 @@ def test_null_arguments_are_rejected():
     assert lib.rt_pipe_destroy(None) == rt.RT_OK
     assert lib.rt_pipe_create_lanes(None, 2, 2, 1, None, None, None, None, None) == rt.RT_EINVAL
     assert lib.rt_pipe_join(None, None) == rt.RT_EINVAL
+    assert lib.rt_pipe_submit_batch(None, 1, None, None, None, None, None, None) == rt.RT_EINVAL
     assert lib.rt_surrogate_features(None, None, None, None) == rt.RT_EINVAL
     assert lib.rt_estimate_new(None, None, None, None, None) == rt.RT_EINVAL
     assert lib.rt_surrogate_targets(None, None, None, None, None, None) == rt.RT_EINVAL

@@ -331,6 +331,46 @@ def test_pipeline_matches_sequential_framesets(depth, lanes, group):
     par.close()
 
 
+def test_pipeline_waits_for_ready_event():
+    """Frames written on a side stream right before each submit, ordered
+    only by the ready event the submit passes: the results equal consecutive
+    rt_frameset calls on the same frames."""
+    from paper_1910_03517_amd.pipeline import Pipeline
+    say("case: pipeline ready_event, 3 lanes, 4x 480x200 rgb8, 7 frame-sets")
+    spec = synth.RigSpec("pipe 4x480x200", 13, [synth.CamSpec(480, 200, 3, 8, 0, p) for p in range(4)])
+    cams = rt_cams(spec.cams)
+    opts = rt.Options(n_blocks=8, band_width=16, smoothing=True)
+    seq = rt.Rig(cams, opts)
+    par = rt.Rig(cams, opts)
+    pipe = Pipeline(par, depth=6, lanes=3, group=3)
+    T = 7
+    frames_t = [synth.rig_frames(spec, t, drift=True) for t in range(T)]
+    src = [seq.upload(f) for f in frames_t]          # device copies, written once
+    torch.cuda.synchronize()
+    dst = [par.alloc_frames() for _ in range(T)]     # written on the side stream below
+    outs = [par.alloc_frames() for _ in range(T)]
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    for t in range(T):
+        with torch.cuda.stream(side):
+            for a, b in zip(dst[t], src[t]):
+                a.copy_(b, non_blocking=True)
+        ready = torch.cuda.Event()
+        ready.record(side)
+        pipe.submit(dst[t], outs[t], ready_event=ready)
+    pipe.join()
+    torch.cuda.synchronize()
+    out_s = seq.alloc_frames()
+    for t in range(T):
+        seq.frameset(src[t], out_s)
+        torch.cuda.synchronize()
+        for a, b in zip(par.download(outs[t]), seq.download(out_s)):
+            assert np.array_equal(a, b), f"frame-set {t}"
+    pipe.close()
+    seq.close()
+    par.close()
+
+
 def test_pipeline_rejects_bad_lanes_and_groups():
     from paper_1910_03517_amd.pipeline import LutSet, WholeSet
     spec = synth.RigSpec("pipe 2x64x32", 12, [synth.CamSpec(64, 32, 3, 8, 0, p) for p in range(2)])

@@ -51,8 +51,8 @@ def host_out(cams, outs):
     return res
 
 
-def serve(surrogate=None):
-    backend = GpuBackend(RIGS, OPTS, surrogate=surrogate)
+def serve(surrogate=None, lanes=1):
+    backend = GpuBackend(RIGS, OPTS, surrogate=surrogate, lanes=lanes)
     results = {}
 
     def on_done(req):
@@ -66,6 +66,7 @@ def serve(surrogate=None):
     for r, t in order:
         cams = [backend.cams[i] for i in backend.idx[r]]
         inputs[(r, t)] = to_device(cams, rig_frames(r, t))
+    torch.cuda.synchronize()                     # the backend's streams do not wait for this one
     # Everything arrives before the first scheduling pass, so launches carry
     # one frame-set of every rig that still has one (batches of 3, 3, 3, 2, 1).
     for r, t in order:
@@ -80,9 +81,12 @@ def serve(surrogate=None):
     return results
 
 
-def test_serving_mix_matches_oracle_and_alone():
-    say("case: serving plain, 3 rigs")
-    results = serve()
+@pytest.mark.parametrize("lanes", [1, 2])
+def test_serving_mix_matches_oracle_and_alone(lanes):
+    """lanes 1: one rt_frameset_batch per batch on one stream; lanes 2: the
+    batches through the frame-set pipeline, consecutive ones overlapping."""
+    say(f"case: serving plain, 3 rigs, {lanes} lanes")
+    results = serve(lanes=lanes)
     for r in range(3):
         cams = rt_cams(RIGS[r])
         co, oo = oracle_cams(cams), oracle_opts(OPTS)
