@@ -325,6 +325,7 @@ def main() -> int:
     ap.add_argument("--group", type=int, default=3, help="frame-sets whose applies the pipe mode issues together")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile-rows", type=int, default=0)
+    ap.add_argument("--grid", type=int, default=0, help="apply workgroups (rt_ctx_tune; 0 = one per tile)")
     ap.add_argument("--depth", type=int, default=8, help="slots of the pipe mode (>= lanes, >= group, divides --nbuf)")
     ap.add_argument("--copy-only", action="store_true", help="time the streaming copy of the frame bytes only")
     ap.add_argument("--timing-every", type=int, default=30,
@@ -377,8 +378,8 @@ def main() -> int:
 
     opts = rt.Options(smoothing=args.smoothing)
     rig = rt.Rig(cams, opts)
-    if args.tile_rows:
-        rig.tune(args.tile_rows, 0)
+    if args.tile_rows or args.grid:
+        rig.tune(args.tile_rows or rig.tuning()[0], args.grid)
     tile_rows, grid, n_tiles = rig.tuning()
     alg_bytes = algorithmic_bytes(cams, opts.band_width)
 
@@ -523,7 +524,7 @@ def main() -> int:
                    "launch_mode": args.mode + (f", {args.lanes} apply lanes, depth {args.depth}, group {args.group}"
                                                if pipe is not None else ""),
                    "n_blocks": opts.n_blocks, "band_width": opts.band_width, "pixels_per_frameset": px,
-                   "rotating_buffers": args.nbuf, "tile_rows": tile_rows, "n_tiles": n_tiles},
+                   "rotating_buffers": args.nbuf, "tile_rows": tile_rows, "apply_grid": grid, "n_tiles": n_tiles},
         "hbm_frac": round(alg_bytes * args.steps / (ms_total / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
         "algorithmic_bytes_per_frameset": alg_bytes,
         "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 4),
