@@ -33,14 +33,15 @@ __device__ inline unsigned long long wave_sum_u64(unsigned long long v) {
   return ((unsigned long long)hi << 32) | lo;
 }
 
-// Workgroup sums of n 64-bit quantities (n <= 16), one after the other to
-// keep register pressure low: value(i) gives this thread's share of quantity
-// i; thread i then receives the total as store(i, total).  `red` is LDS
-// scratch of n * 16 words.  Contains __syncthreads(): call from uniform
-// control flow with blockDim.x == kThreads.
+// Sums over kThreads threads of n 64-bit quantities (n <= 16), one after
+// the other to keep register pressure low: value(i) gives this thread's share
+// of quantity i; thread i then receives the total as store(i, total).  `red`
+// is LDS scratch of n * 16 words.  tid is the thread's index among the
+// kThreads (the workgroup, or one part of a larger workgroup whose other
+// parts make their own calls with their own `red`).  Contains two
+// __syncthreads(): every wave of the workgroup must make the call.
 template <typename Value, typename Store>
-__device__ inline void block_sums(int n, Value value, Store store, unsigned long long* red) {
-  const int tid = threadIdx.x;
+__device__ inline void block_sums(int n, Value value, Store store, unsigned long long* red, int tid) {
   const int wave = tid / kWave;
   const int lane = tid % kWave;
 #pragma unroll 1
@@ -55,6 +56,11 @@ __device__ inline void block_sums(int n, Value value, Store store, unsigned long
     store(tid, s);
   }
   __syncthreads();
+}
+
+template <typename Value, typename Store>
+__device__ inline void block_sums(int n, Value value, Store store, unsigned long long* red) {
+  block_sums(n, value, store, red, (int)threadIdx.x);
 }
 
 }  // namespace rc

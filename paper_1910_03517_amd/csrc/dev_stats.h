@@ -16,10 +16,14 @@ struct StatsLds {
 // band's samples.  Threads walk the band as (row, dword) pairs; a dword holds 4
 // consecutive 8-bit samples or 2 16-bit samples of the row, and only the bytes
 // inside the band count.  8-bit sums follow from the exact histogram.
+// Barriers (__syncthreads) that band_unit passes, on every path.
+constexpr int kBandBarriers = 4;
+
+// (Inlined: an outlined call would take the kernel's by-value arguments by
+// address, in scratch memory.)
 template <int C, int BPS>
-__device__ void band_unit(const Geo& g, const FramePtrs& fp, const Bufs& b, int k, int s, int j, StatsLds& L,
-                          uint64_t* sums_out) {
-  const int tid = threadIdx.x;
+__device__ __attribute__((always_inline)) void band_unit(const Geo& g, const FramePtrs& fp, const Bufs& b, int k,
+                                                         int s, int j, StatsLds& L, uint64_t* sums_out, int tid) {
   const DevCam cam = uniform_cam(g.cams[k]);
   auto clear = [&]() {
     for (int i = tid; i < kCS * kNB; i += kThreads) L.hist[i] = 0;
@@ -150,22 +154,26 @@ __device__ void band_unit(const Geo& g, const FramePtrs& fp, const Bufs& b, int 
         b.band_sums[u0 * 3 + i] = tot;
         if (sums_out) sums_out[i] = tot;
       },
-      L.red);
+      L.red, tid);
 }
 
-// Band statistics of unit (camera, side, block) = `unit`; with sums_out
-// (LDS) its nine sums are also left there for the workgroup.
-__device__ inline void band_unit_dispatch(const Geo& g, const FramePtrs& fp, const Bufs& b, int unit, StatsLds& L,
-                                          uint64_t* sums_out = nullptr) {
+// Band statistics of unit (camera, side, block) = `unit` by kThreads threads
+// (tid: the thread's index among them; -1: the workgroup's threadIdx.x); with
+// sums_out (LDS) its nine sums are also left there for the workgroup.
+__device__ __attribute__((always_inline)) inline void band_unit_dispatch(const Geo& g, const FramePtrs& fp,
+                                                                         const Bufs& b, int unit, StatsLds& L,
+                                                                         uint64_t* sums_out = nullptr,
+                                                                         int tid = -1) {
+  if (tid < 0) tid = (int)threadIdx.x;
   const int nb = g.n_blocks;
   const int k = unit / (2 * nb);
   const int s = (unit / nb) & 1;
   const int j = unit % nb;
   const DevCam& cam = g.cams[k];
   if (!cam_active(g, k)) return;
-  if (cam.bps == 2) band_unit<1, 2>(g, fp, b, k, s, j, L, sums_out);
-  else if (cam.channels == 3) band_unit<3, 1>(g, fp, b, k, s, j, L, sums_out);
-  else band_unit<1, 1>(g, fp, b, k, s, j, L, sums_out);
+  if (cam.bps == 2) band_unit<1, 2>(g, fp, b, k, s, j, L, sums_out, tid);
+  else if (cam.channels == 3) band_unit<3, 1>(g, fp, b, k, s, j, L, sums_out, tid);
+  else band_unit<1, 1>(g, fp, b, k, s, j, L, sums_out, tid);
 }
 
 // Zero the whole-frame histogram and sums of every active camera (grid-stride).

@@ -31,34 +31,49 @@ __global__ __launch_bounds__(kThreads) void k_weights(Geo g, Bufs b) {
 // Every unit is taken exactly once, and a unit's estimate needs only its own
 // band and the one it faces, so after the statistics of its bands the
 // workgroup fits those units and builds their tables with no other
-// workgroup involved.  Same results as k_band_stats, k_estimate, k_build_lut
-// and k_weights in sequence (the whole-frame statistics that the frame-set's
-// apply pass accumulates are cleared here too, when given).
-__global__ __launch_bounds__(kThreads) void k_band_estimate(Geo g, FramePtrs fp, Bufs b) {
+// workgroup involved.  WIDE: 2 x kThreads threads whose halves gather two
+// bands at the same time (for rigs with few seam blocks, where the launch
+// is latency-bound; beside the apply kernels of a pipeline the 256-thread
+// form is faster, as its workgroups fit more easily on busy compute units).
+// Same results as k_band_stats, k_estimate, k_build_lut and k_weights in
+// sequence (the whole-frame statistics that the frame-set's apply pass
+// accumulates are cleared here too, when given).
+template <bool WIDE>
+__global__ __launch_bounds__(WIDE ? 2 * kThreads : kThreads) void k_band_estimate(Geo g, FramePtrs fp, Bufs b) {
+  constexpr int NT = WIDE ? 2 * kThreads : kThreads;
   // This kernel's chain of dependent steps is what the next apply waits
   // for; its waves take issue priority over the apply waves they share
   // compute units with (measured on MI355X: 628 -> 674 GPix/s in the
   // pipelined frame-set loop).
   __builtin_amdgcn_s_setprio(3);
-  __shared__ StatsLds L;
+  __shared__ StatsLds L[WIDE ? 2 : 1];
   __shared__ uint64_t sums[3][9];            // (n, S1, S2) per channel of the units taken
   __shared__ double ab[3][kCS][2];           // their maps after the fit
   const int nb = g.n_blocks;
   const int k = blockIdx.x / nb, j = blockIdx.x - (blockIdx.x / nb) * nb;
   const int tid = threadIdx.x;
-  if (b.whole_hist) zero_whole(g, b, blockIdx.x * kThreads + tid, gridDim.x * kThreads);
+  // WIDE: each half is whole waves, so its unit (camera, frame pointer) is
+  // uniform per wave and stays in scalar registers.
+  const int half = WIDE ? uniform((int32_t)(tid / kThreads)) : 0, ltid = tid - half * kThreads;
+  if (b.whole_hist) zero_whole(g, b, blockIdx.x * NT + tid, gridDim.x * NT);
   if (!cam_active(g, k)) return;
   const DevCam& cam = g.cams[k];
-  int unit[3];
-  unit[0] = (k * 2 + 1) * nb + j;
+  // Units taken, n of them: u0 the right band of camera k; u1 the band it
+  // faces, if any; then the left band of camera k if it faces nothing.
+  // Only u0 and u1 face each other.
   const int fc = uniform(cam.face_cam[1]);
-  unit[1] = fc < 0 ? -1 : (fc * 2 + uniform(cam.face_side[1])) * nb + j;
-  unit[2] = uniform(cam.face_cam[0]) < 0 ? k * 2 * nb + j : -1;
+  const int u0 = (k * 2 + 1) * nb + j;
+  const int uf = fc < 0 ? -1 : (fc * 2 + uniform(cam.face_side[1])) * nb + j;
+  const int ul = uniform(cam.face_cam[0]) < 0 ? k * 2 * nb + j : -1;
+  const int u1 = uf >= 0 ? uf : ul;
+  const int u2 = uf >= 0 ? ul : -1;
+  const int n = 1 + (u1 >= 0) + (u2 >= 0);
+  auto unit_at = [&](int i) { return i == 0 ? u0 : (i == 1 ? u1 : u2); };
   // Thread 64 t + c fits channel c of unit t: its state is read now, ahead
   // of the band passes.
   const int t = tid / kWave, c = tid % kWave;
-  const bool fitter = t < 3 && c < kCS && unit[t < 3 ? t : 0] >= 0;
-  const int64_t u = fitter ? (int64_t)unit[t] * kCS + c : 0;
+  const bool fitter = t < n && c < kCS;
+  const int64_t u = fitter ? (int64_t)unit_at(t) * kCS + c : 0;
   double p0 = 0.0, p1 = 0.0;
   uint8_t v = 0;
   if (fitter) {
@@ -66,25 +81,32 @@ __global__ __launch_bounds__(kThreads) void k_band_estimate(Geo g, FramePtrs fp,
     p1 = b.params[u * 2 + 1];
     v = b.valid[u];
   }
-  band_unit_dispatch(g, fp, b, unit[0], L, sums[0]);
-  if (unit[1] >= 0) {
-    __syncthreads();
-    band_unit_dispatch(g, fp, b, unit[1], L, sums[1]);
-  }
-  if (unit[2] >= 0) {
-    __syncthreads();
-    band_unit_dispatch(g, fp, b, unit[2], L, sums[2]);
+  if (WIDE) {
+    // Units 2p and 2p + 1 in pass p, one per half; a half without a unit
+    // passes the same barriers.
+    for (int p = 0; 2 * p < n; ++p) {
+      if (p) __syncthreads();
+      const int i = 2 * p + half;
+      if (i < n) {
+        band_unit_dispatch(g, fp, b, unit_at(i), L[WIDE ? half : 0], sums[i], ltid);
+      } else {
+        for (int w = 0; w < kBandBarriers; ++w) __syncthreads();
+      }
+    }
+  } else {
+    for (int i = 0; i < n; ++i) {
+      if (i) __syncthreads();
+      band_unit_dispatch(g, fp, b, unit_at(i), L[0], sums[i], tid);
+    }
   }
   if (j == 0)
-    for (int col = tid; col < g.w_max; col += kThreads)
+    for (int col = tid; col < g.w_max; col += NT)
       b.weights[(int64_t)k * g.w_max + col] = (uint16_t)blend_weight(cam.width, col);
   __syncthreads();
   if (fitter) {
-    // Units 0 and 1 face each other; unit 2 faces nothing (nor does unit 0
-    // without unit 1).
-    const int other = t == 0 ? 1 : (t == 1 ? 0 : -1);
-    const uint64_t* fac = (other >= 0 && unit[other] >= 0) ? &sums[other][c * 3] : nullptr;
-    const int channels = uniform(g.cams[unit[t] / (2 * nb)].channels);
+    const int other = (uf >= 0 && t < 2) ? 1 - t : -1;
+    const uint64_t* fac = other >= 0 ? &sums[other][c * 3] : nullptr;
+    const int channels = uniform(g.cams[unit_at(t) / (2 * nb)].channels);
     double a, bb;
     const int st = fit_sums(g, channels, c, &sums[t][c * 3], fac, a, bb);
     temporal_step(g, st, a, bb, p0, p1, v);
@@ -95,13 +117,18 @@ __global__ __launch_bounds__(kThreads) void k_band_estimate(Geo g, FramePtrs fp,
     ab[t][c][1] = p1;
   }
   __syncthreads();
-#pragma unroll
-  for (int w = 0; w < 3; ++w)
-    if (unit[w] >= 0) lut_entry_ab(g, b, unit[w], tid, ab[w]);
+  for (int w = half; w < n; w += (WIDE ? 2 : 1)) lut_entry_ab(g, b, unit_at(w), ltid, ab[w]);
 }
 
+// Seam blocks up to which the wide form is launched.
+constexpr int kWideSeamBlocks = 64;
+
 hipError_t launch_band_estimate(const Geo& g, const FramePtrs& fp, const Bufs& b, hipStream_t st) {
-  hipLaunchKernelGGL(k_band_estimate, dim3(g.n_cams * g.n_blocks), dim3(kThreads), 0, st, g, fp, b);
+  const int blocks = g.n_cams * g.n_blocks;
+  if (blocks <= kWideSeamBlocks)
+    hipLaunchKernelGGL(k_band_estimate<true>, dim3(blocks), dim3(2 * kThreads), 0, st, g, fp, b);
+  else
+    hipLaunchKernelGGL(k_band_estimate<false>, dim3(blocks), dim3(kThreads), 0, st, g, fp, b);
   return hipGetLastError();
 }
 
