@@ -331,6 +331,53 @@ def test_pipeline_matches_sequential_framesets(depth, lanes, group):
     par.close()
 
 
+def test_pipeline_mixed_rings_matches_sequential():
+    """Mixed rings through the pipeline (3 lanes, groups of 3): a closed RGB8
+    ring, an open gray16 chain and a one-camera RGB8 ring, 7 frame-sets with
+    smoothing; every output and the final state equal consecutive rt_frameset
+    calls, and the last frame-sets' whole-frame statistics and tables equal
+    theirs."""
+    from paper_1910_03517_amd.pipeline import Pipeline
+    say("case: pipeline mixed rings, 3 lanes, depth 6, group 3, 7 frame-sets")
+    cams_spec = ([synth.CamSpec(200, 90, 3, 8, 0, p) for p in (1, 0, 2)]
+                 + [synth.CamSpec(120, 64, 1, 16, 4, p) for p in (1, 0)]
+                 + [synth.CamSpec(160, 48, 3, 8, 9, 0)])
+    cams = rt_cams(cams_spec, 1)
+    opts = rt.Options(n_blocks=5, band_width=12, smoothing=True, closed_ring=False)
+    seq = rt.Rig(cams, opts)
+    par = rt.Rig(cams, opts)
+    depth = 6
+    pipe = Pipeline(par, depth=depth, lanes=3, group=3)
+    rng = np.random.default_rng(21)
+    T = 7
+    frames_t = [[synth.tiny_frame(c.height, c.width, c.channels, c.bit_depth, rng) for c in cams_spec]
+                for _ in range(T)]
+    dev = [seq.upload(f) for f in frames_t]
+    outs_p = [par.alloc_frames() for _ in range(T)]
+    torch.cuda.synchronize()
+    slots = [pipe.submit(dev[t], outs_p[t]) for t in range(T)]
+    pipe.join()
+    torch.cuda.synchronize()
+    out_s = seq.alloc_frames()
+    for t in range(T):
+        seq.frameset(dev[t], out_s)
+        torch.cuda.synchronize()
+        if t >= T - depth:
+            w = pipe.whole[slots[t]]
+            assert np.array_equal(w.whole_hist.cpu().numpy(), seq.bufs.whole_hist.cpu().numpy()), f"t {t}"
+            assert np.array_equal(w.whole_sums.cpu().numpy(), seq.bufs.whole_sums.cpu().numpy()), f"t {t}"
+            L = pipe.luts[slots[t]]
+            assert np.array_equal(L.q16.cpu().numpy(), seq.bufs.q16.cpu().numpy()), f"t {t}"
+        for k, (a, b) in enumerate(zip(par.download(outs_p[t]), seq.download(out_s))):
+            assert np.array_equal(a, b), f"frame-set {t} camera {k}"
+    hp, hs = par.bufs.host(), seq.bufs.host()
+    assert np.array_equal(hp["params"].view(np.uint64), hs["params"].view(np.uint64))
+    assert np.array_equal(hp["valid"], hs["valid"])
+    pipe.close()
+    seq.close()
+    par.close()
+
+
 def test_pipeline_waits_for_ready_event():
     """Frames written on a side stream right before each submit, ordered
     only by the ready event the submit passes: the results equal consecutive
