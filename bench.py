@@ -6,11 +6,10 @@ go through rt_pipe with several apply lanes (the statistics and estimates of
 consecutive frame-sets run in order on one stream, ahead of the applies,
 which go round-robin over LANES streams, so that consecutive applies
 overlap); --lanes 1 keeps every apply on the caller's stream, --mode eager
-issues one rt_frameset per step on one stream, --mode graph / graph-pipelined
-replay captured HIP graphs.  Inputs are
-seeded synthetic rigs already resident in HBM; NBUF distinct input/output
-frame-set buffers rotate so that the 256 MB Infinity Cache cannot serve
-repeats.
+issues one rt_frameset per step on one stream, --mode graph /
+graph-pipelined replay captured HIP graphs.  Inputs are seeded synthetic
+rigs already resident in HBM; NBUF distinct input/output frame-set buffers
+rotate so that the 256 MB Infinity Cache cannot serve repeats.
 
     python bench.py [--gpus 1] [--steps 300] [--warmup 20] [--config rig14]
 
@@ -18,11 +17,14 @@ Prints ONE JSON line.  After the timed region, two further legs add their
 own objects to it: "surrogate" (the network trained on the device from the
 plain estimator, then its inference path against the plain one) and
 "serving" (three rigs behind the server, paced at 30 fps and saturated).
-The roofline figure is for the dominant kernel (the
-apply pass with fused statistics), timed by HIP events the library attaches to
-its dispatches in the timed region (every n-th), next to the streaming-copy
-ceiling of the same bytes.  The CPU baseline leg times the CPU oracle (test
-infrastructure) on a bounded sample of the same workload.
+The roofline figure is for the dominant kernel (the apply pass with fused
+statistics), timed by HIP events the library attaches to its dispatches in
+the timed region (every n-th), next to the streaming-copy ceiling of the
+same bytes; with overlapping apply lanes it also gives the apply bytes per
+frame-set over the time per frame-set ("per_step") and the same launches
+back to back on one stream after the timed region ("alone").  The CPU
+baseline leg times the CPU oracle (test infrastructure) on a bounded sample
+of the same workload.
 """
 from __future__ import annotations
 
