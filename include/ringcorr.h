@@ -239,7 +239,10 @@ rt_status rt_ctx_set_active(rt_ctx* ctx, uint64_t active);
  * 1 <= lanes <= 4, lanes <= depth <= 8, 1 <= group <= depth; rt_pipe_create
  * is lanes = group = 1 (each submit issues its apply on `stream`).  The
  * buffers are caller-owned and must outlive the pipeline; submits of one
- * pipeline must come from one host thread and may use one caller stream only. */
+ * pipeline must come from one host thread.  A submit on another stream than
+ * the previous one first issues the pending applies (lane 0 of those is the
+ * stream they were submitted on), so each stream must stay alive until the
+ * next submit or rt_pipe_join. */
 typedef struct rt_pipe rt_pipe;
 rt_status rt_pipe_create(rt_ctx* ctx, int32_t depth, const rt_stats_buf* bands, const rt_params_buf* state,
                          const rt_lut_buf* luts, const rt_stats_buf* wholes, rt_pipe** out);

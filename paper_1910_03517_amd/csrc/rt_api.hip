@@ -796,6 +796,8 @@ static rt_status pipe_submit(rt_pipe* p, uint64_t active, const void* const* fra
   // The slot's previous apply may still be pending: issue it first.
   for (const auto& q : p->pending)
     if (q.slot == slot) { e = pipe_flush(p); break; }
+  // Pending applies run on the stream they were submitted on.
+  if (e == hipSuccess && !p->pending.empty() && p->caller != (hipStream_t)stream) e = pipe_flush(p);
   p->caller = (hipStream_t)stream;
   Geo g = ctx->geo;
   g.active = active;

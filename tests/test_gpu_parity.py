@@ -331,6 +331,42 @@ def test_pipeline_matches_sequential_framesets(depth, lanes, group):
     par.close()
 
 
+def test_pipeline_caller_stream_changes():
+    """Submits that switch between two caller streams inside groups of 3
+    (3 lanes, 6 slots, 8 frame-sets): a stream change issues the pending
+    applies on their own stream first, and the outputs and final state equal
+    consecutive rt_frameset calls bit for bit."""
+    from paper_1910_03517_amd.pipeline import Pipeline
+    say("case: pipeline 3 lanes, depth 6, group 3, caller stream alternating, 4x 480x200 rgb8, 8 frame-sets")
+    spec = synth.RigSpec("pipe streams 4x480x200", 12, [synth.CamSpec(480, 200, 3, 8, 0, p) for p in range(4)])
+    cams = rt_cams(spec.cams)
+    opts = rt.Options(n_blocks=8, band_width=16, smoothing=True)
+    seq = rt.Rig(cams, opts)
+    par = rt.Rig(cams, opts)
+    pipe = Pipeline(par, depth=6, lanes=3, group=3)
+    T = 8
+    dev = [seq.upload(synth.rig_frames(spec, t, drift=True)) for t in range(T)]
+    outs_p = [par.alloc_frames() for _ in range(T)]
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    for t in range(T):
+        pipe.submit(dev[t], outs_p[t], stream=streams[(t // 2) % 2])
+    for s in streams:
+        pipe.join(s)
+    torch.cuda.synchronize()
+    out_s = seq.alloc_frames()
+    for t in range(T):
+        seq.frameset(dev[t], out_s)
+        torch.cuda.synchronize()
+        for a, b in zip(par.download(outs_p[t]), seq.download(out_s)):
+            assert np.array_equal(a, b), f"frame-set {t}"
+    hp, hs = par.bufs.host(), seq.bufs.host()
+    assert np.array_equal(hp["params"].view(np.uint64), hs["params"].view(np.uint64))
+    pipe.close()
+    seq.close()
+    par.close()
+
+
 def test_pipeline_mixed_rings_matches_sequential():
     """Mixed rings through the pipeline (3 lanes, groups of 3): a closed RGB8
     ring, an open gray16 chain and a one-camera RGB8 ring, 7 frame-sets with
