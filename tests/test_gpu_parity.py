@@ -173,25 +173,22 @@ def test_rig14_frameset_smoothing():
     frameset_sequence(synth.rig14_1080p(), rt.Options(smoothing=True), 3)
 
 
-def test_rig14_lanes_pipeline_matches_oracle():
-    """The bench's launch configuration at its full size: ten 14x1920x1080
-    frame-sets (drifting gains, smoothing) through the pipeline with 3 apply
-    lanes, 8 slots (two reused) and applies issued 3 frame-sets at a time (the
-    last group partial), every output against the oracle's frame-set
-    sequence, the last two frame-sets' whole-frame statistics and the final
-    state bitwise."""
+def pipeline_vs_oracle(spec, n, label):
+    """n frame-sets of `spec` (drifting gains, smoothing) through the
+    pipeline in the bench's launch configuration (3 apply lanes, 8 slots,
+    applies issued 3 frame-sets at a time, the last group partial): every
+    output against the oracle's frame-set sequence, the last two frame-sets'
+    whole-frame statistics and the final state bitwise."""
     from paper_1910_03517_amd.pipeline import Pipeline
-    spec = synth.rig14_1080p()
     cams = rt_cams(spec.cams)
     opts = rt.Options(smoothing=True)
     rig = rt.Rig(cams, opts)
     pipe = Pipeline(rig, depth=8, lanes=3, group=3)
-    n = 10
     frames = [synth.rig_frames(spec, t, drift=True) for t in range(n)]
     dev = [rig.upload(f) for f in frames]
     outs = [rig.alloc_frames() for _ in range(n)]
     torch.cuda.synchronize()
-    say("case: rig14 pipeline, 3 lanes, depth 8, group 3, 10 frame-sets")
+    say(f"case: {label} pipeline, 3 lanes, depth 8, group 3, {n} frame-sets")
     slots = [pipe.submit(dev[t], outs[t]) for t in range(n)]
     pipe.join()
     torch.cuda.synchronize()
@@ -211,6 +208,19 @@ def test_rig14_lanes_pipeline_matches_oracle():
     assert np.array_equal(h["valid"], prev_v)
     pipe.close()
     rig.close()
+
+
+def test_rig14_lanes_pipeline_matches_oracle():
+    """Ten 14x1920x1080 RGB8 frame-sets (two slots reused) through the
+    pipeline against the oracle."""
+    pipeline_vs_oracle(synth.rig14_1080p(), 10, "rig14")
+
+
+def test_uneven_rig_lanes_pipeline_matches_oracle():
+    """Five frame-sets of the uneven three-ring rig (4x4096x2160 RGB8,
+    8x1920x1080 RGB8, 4x640x512 gray16) through the pipeline against the
+    oracle."""
+    pipeline_vs_oracle(synth.uneven_rig(), 5, "uneven rig")
 
 
 def test_uneven_rig_frameset():
