@@ -327,7 +327,8 @@ def main() -> int:
     ap.add_argument("--group", type=int, default=3, help="frame-sets whose applies the pipe mode issues together")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile-rows", type=int, default=0)
-    ap.add_argument("--grid", type=int, default=0, help="apply workgroups (rt_ctx_tune; 0 = one per tile)")
+    ap.add_argument("--grid", type=int, default=None,
+                    help="apply workgroups (rt_ctx_tune; 0 = one per tile; default: the context's own choice)")
     ap.add_argument("--depth", type=int, default=8, help="slots of the pipe mode (>= lanes, >= group, divides --nbuf)")
     ap.add_argument("--copy-only", action="store_true", help="time the streaming copy of the frame bytes only")
     ap.add_argument("--timing-every", type=int, default=30,
@@ -380,8 +381,8 @@ def main() -> int:
 
     opts = rt.Options(smoothing=args.smoothing)
     rig = rt.Rig(cams, opts)
-    if args.tile_rows or args.grid:
-        rig.tune(args.tile_rows or rig.tuning()[0], args.grid)
+    if args.tile_rows or args.grid is not None:
+        rig.tune(args.tile_rows or rig.tuning()[0], rig.tuning()[1] if args.grid is None else args.grid)
     tile_rows, grid, n_tiles = rig.tuning()
     alg_bytes = algorithmic_bytes(cams, opts.band_width)
 
