@@ -65,6 +65,7 @@ def kernel_hash() -> str:
 
 
 def config(name: str):
+    """Rig of a workload name (rig14, uneven, vga)."""
     from paper_1910_03517_amd import synth
     if name == "rig14":
         return synth.rig14_1080p()
@@ -72,7 +73,7 @@ def config(name: str):
         return synth.uneven_rig()
     if name == "vga":
         return synth.single_vga()
-    raise SystemExit(f"unknown config {name}")
+    raise ValueError(f"unknown config {name}")
 
 
 def algorithmic_bytes(cams, band_width: int) -> int:
@@ -104,13 +105,16 @@ def traffic_from_profile(khash: str, workload: str):
         return None
 
 
-def cpu_baseline(rig, opts_rt, budget_s: float = 12.0) -> dict:
-    """The oracle as it stands, single process, on whole frame-sets of the same workload."""
+def oracle_setup(rig, smoothing: bool):
     from oracle import ringcorr as rc
-    from paper_1910_03517_amd import synth
     cams = [rc.Camera(c.width, c.height, c.channels, c.bit_depth, c.ring, c.pos) for c in rig.cams]
-    opts = rc.Options(n_blocks=opts_rt.n_blocks, band_width=opts_rt.band_width, closed_ring=opts_rt.closed_ring,
-                      smoothing=opts_rt.smoothing)
+    return rc, cams, rc.Options(smoothing=smoothing)
+
+
+def cpu_baseline(rig, smoothing: bool, budget_s: float = 10.0) -> dict:
+    """The oracle as it stands, single process, on whole frame-sets of the same workload."""
+    from paper_1910_03517_amd import synth
+    rc, cams, opts = oracle_setup(rig, smoothing)
     frames = synth.rig_frames(rig, 0)
     px = sum(c.width * c.height for c in cams)
     n, t_total = 0, 0.0
@@ -124,6 +128,72 @@ def cpu_baseline(rig, opts_rt, budget_s: float = 12.0) -> dict:
     return {"value": round(px * n / t_total / 1e9, 6), "unit": "GPix/s", "cores": 1, "kind": "oracle",
             "sample": f"{n} whole frame-sets of {rig.name} ({px * n / 1e6:.1f} MPix) through the numpy oracle, "
                       f"{t_total:.1f} s single process"}
+
+
+# Worker state of the process-pool baseline (each worker process builds the
+# same seeded frame-set once, outside the timed loop).
+_POOL = {}
+
+
+def _pool_init(config_name: str, smoothing: bool) -> None:
+    # A failing initializer would make the pool start workers over and over:
+    # keep the error and let every task raise it instead.
+    try:
+        from paper_1910_03517_amd import synth
+        rig = config(config_name)
+        rc, cams, opts = oracle_setup(rig, smoothing)
+        _POOL.update(rc=rc, cams=cams, opts=opts, frames=synth.rig_frames(rig, 0))
+    except BaseException as e:  # noqa: BLE001 - reported by the first task
+        _POOL["error"] = repr(e)
+
+
+def _pool_stats(k: int):
+    if "error" in _POOL:
+        raise RuntimeError("pool worker set-up failed: " + _POOL["error"])
+    rc, cam, f = _POOL["rc"], _POOL["cams"][k], _POOL["frames"][k]
+    bh, bs = rc.band_stats(f, cam, _POOL["opts"])
+    wh, ws = rc.whole_stats(f, cam)
+    return bh, bs, wh, ws
+
+
+def _pool_apply(args):
+    k, params_k = args
+    rc, cam, opts = _POOL["rc"], _POOL["cams"][k], _POOL["opts"]
+    lut8, qq = rc.build_luts([cam], opts, params_k[None])
+    out = rc.apply_camera(_POOL["frames"][k], cam, opts, lut8[0], qq[0])
+    return int(out[::97, ::89].sum())     # the corrected frame stays in the worker
+
+
+def cpu_baseline_pool(config_name: str, smoothing: bool, budget_s: float = 10.0) -> dict:
+    """The same oracle functions over a process pool, one task per camera:
+    statistics of every camera, the estimate in the parent, then tables and
+    apply of every camera.  Workers = the host cores this process may use
+    (at most 16, the host share of one GPU)."""
+    import multiprocessing as mp
+    rig = config(config_name)
+    rc, cams, opts = oracle_setup(rig, smoothing)
+    K = len(cams)
+    workers = max(1, min(len(os.sched_getaffinity(0)), 16))
+    px = sum(c.width * c.height for c in cams)
+    ctx = mp.get_context("spawn")   # fresh interpreters: nothing of this process's device state is inherited
+    with ctx.Pool(workers, initializer=_pool_init, initargs=(config_name, smoothing)) as pool:
+        pool.map(_pool_stats, range(K))          # every worker initialised before timing
+        n, t_total = 0, 0.0
+        prev_p = prev_v = None
+        while t_total < budget_s or n == 0:
+            t0 = time.perf_counter()
+            st = pool.map(_pool_stats, range(K), chunksize=1)
+            bs = np.stack([x[1] for x in st])
+            params, valid = rc.estimate(cams, opts, bs, prev_p, prev_v)
+            pool.map(_pool_apply, [(k, params[k]) for k in range(K)], chunksize=1)
+            t_total += time.perf_counter() - t0
+            prev_p, prev_v = params, valid
+            n += 1
+    return {"value": round(px * n / t_total / 1e9, 6), "unit": "GPix/s", "cores": min(workers, K),
+            "workers": workers, "host_cores_available": len(os.sched_getaffinity(0)), "kind": "oracle",
+            "sample": f"{n} whole frame-sets of {rig.name} ({px * n / 1e6:.1f} MPix) through the numpy oracle, "
+                      f"{t_total:.1f} s over a pool of {workers} processes, one task per camera "
+                      f"(corrected frames stay in the workers)"}
 
 
 def apply_bytes(cams) -> int:
@@ -311,73 +381,35 @@ def serving_leg(args, base, surrogate_w=None) -> dict:
     return out
 
 
-def main() -> int:
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=300)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--config", default="rig14", choices=["rig14", "uneven", "vga"])
-    ap.add_argument("--nbuf", type=int, default=8)
-    ap.add_argument("--smoothing", action="store_true")
-    ap.add_argument("--mode", default="pipe", choices=["pipe", "graph-pipelined", "graph", "eager"],
-                    help="pipe: rt_pipe_submit per step (statistics and estimates on their own stream, applies "
-                         "round-robin over --lanes streams); graph-pipelined: one two-branch graph launch per step; "
-                         "graph: one captured rt_frameset per step; eager: one rt_frameset call per step")
-    ap.add_argument("--lanes", type=int, default=3, help="apply streams of the pipe mode")
-    ap.add_argument("--group", type=int, default=3, help="frame-sets whose applies the pipe mode issues together")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--tile-rows", type=int, default=0)
-    ap.add_argument("--grid", type=int, default=None,
-                    help="apply workgroups (rt_ctx_tune; 0 = one per tile; default: the context's own choice)")
-    ap.add_argument("--depth", type=int, default=8, help="slots of the pipe mode (>= lanes, >= group, divides --nbuf)")
-    ap.add_argument("--copy-only", action="store_true", help="time the streaming copy of the frame bytes only")
-    ap.add_argument("--timing-every", type=int, default=30,
-                    help="time every n-th apply launch of the timed region with HIP events")
-    ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate training/inference leg")
-    ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
-    ap.add_argument("--no-vga", action="store_true", help="skip the 1x640x480 per-call leg")
-    ap.add_argument("--sur-bases", type=int, default=4)
-    ap.add_argument("--sur-draws", type=int, default=112, help="gain draws per base scene (448 units each)")
-    ap.add_argument("--sur-epochs", type=int, default=30)
-    ap.add_argument("--sur-lr", type=float, default=1e-3)
-    ap.add_argument("--sur-tol", type=float, default=1e-3)
-    ap.add_argument("--serve-seconds", type=float, default=10.0, help="paced serving: 30 frame-sets per second per rig")
-    ap.add_argument("--serve-lanes", type=int, default=1,
-                    help="apply lanes of the serving backend's frame-set pipeline (plain path; 1 = one stream)")
-    ap.add_argument("--serve-saturated", type=int, default=40, help="frame-sets per rig in the saturated run")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported (the correction of one rig "
-              f"runs on one device; see the sharding notes of the design document)", file=sys.stderr)
-        return 2
-
-    import torch
-    from paper_1910_03517_amd import rt, synth
-    from paper_1910_03517_amd.pipeline import Pipeline
-
-    torch.cuda.set_device(0)
-    rig_spec = config(args.config)
-    cams = [rt.Camera(c.width, c.height, c.channels, c.bit_depth, c.ring, c.pos).with_pitch() for c in rig_spec.cams]
-    px = sum(c.width * c.height for c in cams)
-    frame_bytes = apply_bytes(cams) // 2
-
-    # Practical ceiling: a read+write stream of the same bytes with the same vector width.
-    src = [torch.empty(frame_bytes, dtype=torch.uint8, device="cuda") for _ in range(args.nbuf)]
-    dst = [torch.empty(frame_bytes, dtype=torch.uint8, device="cuda") for _ in range(args.nbuf)]
-    for i in range(args.warmup):
-        rt.rt_stream_copy(dst[i % args.nbuf], src[i % args.nbuf], frame_bytes, 12)
+def copy_ceiling(rt, torch, frame_bytes: int, nbuf: int, steps: int, warmup: int) -> float:
+    """GB/s of a read+write stream of the same bytes with the apply's vector width."""
+    src = [torch.empty(frame_bytes, dtype=torch.uint8, device="cuda") for _ in range(nbuf)]
+    dst = [torch.empty(frame_bytes, dtype=torch.uint8, device="cuda") for _ in range(nbuf)]
+    for i in range(warmup):
+        rt.rt_stream_copy(dst[i % nbuf], src[i % nbuf], frame_bytes, 12)
     c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     c0.record()
-    for i in range(args.steps):
-        rt.rt_stream_copy(dst[i % args.nbuf], src[i % args.nbuf], frame_bytes, 12)
+    for i in range(steps):
+        rt.rt_stream_copy(dst[i % nbuf], src[i % nbuf], frame_bytes, 12)
     c1.record()
     torch.cuda.synchronize()
-    copy_gbs = 2 * frame_bytes * args.steps / (c0.elapsed_time(c1) / 1e3) / 1e9
-    del src, dst
-    if args.copy_only:
-        print(json.dumps({"copy_bytes_per_launch": 2 * frame_bytes, "copy_GBs": round(copy_gbs, 1)}), flush=True)
-        return 0
+    return 2 * frame_bytes * steps / (c0.elapsed_time(c1) / 1e3) / 1e9
+
+
+def plain_leg(args, rig_spec, steps: int, warmup: int, timing_every: int):
+    """The timed region of the plain path on one rig: `steps` frame-sets back
+    to back in the chosen launch mode, the apply launches timed by the
+    library's events, then the same launches alone and the frame-set latency.
+    Returns (rig, report, ins, outs, base)."""
+    import torch
+    from paper_1910_03517_amd import rt, synth
+    from paper_1910_03517_amd.pipeline import LutSet, Pipeline, WholeSet
+
+    cams = [rt.Camera(c.width, c.height, c.channels, c.bit_depth, c.ring, c.pos).with_pitch() for c in rig_spec.cams]
+    px = sum(c.width * c.height for c in cams)
+    frame_bytes = apply_bytes(cams) // 2
+    copy_gbs = copy_ceiling(rt, torch, frame_bytes, args.nbuf, steps, warmup)
 
     opts = rt.Options(smoothing=args.smoothing)
     rig = rt.Rig(cams, opts)
@@ -392,7 +424,6 @@ def main() -> int:
     outs = [rig.alloc_frames() for _ in range(args.nbuf)]
     torch.cuda.synchronize()
 
-    from paper_1910_03517_amd.pipeline import LutSet, WholeSet
     stream = torch.cuda.current_stream()
     pipe, graphs = None, None
     b = rig.bufs
@@ -416,7 +447,6 @@ def main() -> int:
         rt.rt_build_lut(rig.ctx, b.params, b.valid, luts[0].lut8, luts[0].q16, luts[0].weights)
         graphs = [rt.Graph(rig.ctx, ins[i], outs[i], luts[i % 2], wholes[i % 2], b,
                            ins[(i + 1) % args.nbuf], luts[(i + 1) % 2]) for i in range(args.nbuf)]
-    s_first = s_last = stream
 
     def step(i, ready=None):
         if graphs is not None:
@@ -427,115 +457,188 @@ def main() -> int:
         else:
             rig.frameset(ins[i % args.nbuf], outs[i % args.nbuf])
 
-    log(f"timing {args.steps} steps ({args.mode})")
-    for i in range(args.warmup):
+    log(f"{rig_spec.name}: timing {steps} steps ({args.mode})")
+    for i in range(warmup):
         step(i)
+    if pipe is not None:
+        pipe.join(stream)
     torch.cuda.synchronize()
     rig.check()
-    first = args.warmup          # continue the step sequence (pipelined graphs chain step to step)
+    first = warmup          # continue the step sequence (pipelined graphs chain step to step)
 
     # Timed region: exactly `steps` frame-sets back to back, bracketed by a
     # start and an end event.  The library attaches its own events to every
     # n-th apply dispatch in the region (the dominant kernel's durations).
-    rt.rt_ctx_timing(rig.ctx, args.steps, args.timing_every)
+    rt.rt_ctx_timing(rig.ctx, steps, timing_every)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     w0 = time.perf_counter()
-    ev0.record(s_first)
-    for i in range(args.steps):
+    ev0.record(stream)
+    for i in range(steps):
         step(first + i)
     if pipe is not None:
-        pipe.join(s_last)
-    ev1.record(s_last)
+        pipe.join(stream)
+    ev1.record(stream)
     host_issue = time.perf_counter() - w0
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
     rig.check()
     ms_total = ev0.elapsed_time(ev1)
-    apply_ms = np.array(rt.rt_ctx_apply_times(rig.ctx, args.steps))
+    apply_ms = np.array(rt.rt_ctx_apply_times(rig.ctx, steps))
     rt.rt_ctx_timing(rig.ctx, 0)
-    first += args.steps
-    apply_where = f"inside the timed region, every {args.timing_every}th apply launch"
+    first += steps
+    apply_where = f"inside the timed region, every {timing_every}th apply launch"
     if apply_ms.size == 0:
         # Captured graphs carry no timing events: time the apply launches on their own.
         apply_where = "separate loop (graph modes record no events inside the graph)"
-        rt.rt_ctx_timing(rig.ctx, args.steps)
-        for i in range(args.steps):
+        rt.rt_ctx_timing(rig.ctx, steps)
+        for i in range(steps):
             rt.rt_apply(rig.ctx, ins[i % args.nbuf], outs[i % args.nbuf], b.lut8, b.q16, b.weights,
                         b.whole_hist, b.whole_sums, stream=stream)
         torch.cuda.synchronize()
-        apply_ms = np.array(rt.rt_ctx_apply_times(rig.ctx, args.steps))
+        apply_ms = np.array(rt.rt_ctx_apply_times(rig.ctx, steps))
         rt.rt_ctx_timing(rig.ctx, 0)
 
     # The same kernel with no other work beside it (one stream, launches back to back).
-    alone_ms = None
-    if pipe is not None and args.lanes > 1:
-        rt.rt_ctx_timing(rig.ctx, args.steps)
-        for i in range(args.steps):
-            rt.rt_apply(rig.ctx, ins[i % args.nbuf], outs[i % args.nbuf], b.lut8, b.q16, b.weights,
-                        b.whole_hist, b.whole_sums, stream=stream)
-        torch.cuda.synchronize()
-        alone_ms = np.array(rt.rt_ctx_apply_times(rig.ctx, args.steps))
-        rt.rt_ctx_timing(rig.ctx, 0)
+    rt.rt_ctx_timing(rig.ctx, steps)
+    for i in range(steps):
+        rt.rt_apply(rig.ctx, ins[i % args.nbuf], outs[i % args.nbuf], b.lut8, b.q16, b.weights,
+                    b.whole_hist, b.whole_sums, stream=stream)
+    torch.cuda.synchronize()
+    alone_ms = np.array(rt.rt_ctx_apply_times(rig.ctx, steps))
+    rt.rt_ctx_timing(rig.ctx, 0)
 
     # Frame-set latency, outside the timed region: per-step start and end events.
-    n_lat = min(args.steps, 100)
+    n_lat = min(steps, 100)
     ev_s = [torch.cuda.Event(enable_timing=True) for _ in range(n_lat)]
     ev_e = [torch.cuda.Event(enable_timing=True) for _ in range(n_lat)]
     torch.cuda.synchronize()
     for i in range(n_lat):
-        ev_s[i].record(s_first)
+        ev_s[i].record(stream)
         # The pipeline's statistics stream waits for the start event as for
         # arriving frames, so that no part of the step runs before it.
         step(first + i, ev_s[i])
         if pipe is not None:
-            pipe.join(s_last)
-        ev_e[i].record(s_last)
+            pipe.join(stream)
+        ev_e[i].record(stream)
     torch.cuda.synchronize()
-    lat_ms = np.array([a.elapsed_time(b) for a, b in zip(ev_s, ev_e)])
-    ms_step = ms_total / args.steps
-    gpix = px * args.steps / (ms_total / 1e3) / 1e9
+    lat_ms = np.array([a.elapsed_time(z) for a, z in zip(ev_s, ev_e)])
+    if pipe is not None:
+        pipe.close()
+    ms_step = ms_total / steps
+    gpix = px * steps / (ms_total / 1e3) / 1e9
 
-    khash = kernel_hash()
-    workload = rig_spec.name
     ab = apply_bytes(cams)
     launch_us = float(apply_ms.mean() * 1e3)
     achieved = ab / (launch_us * 1e-6) / 1e9
+    alone_us = float(alone_ms.mean() * 1e3)
+    alone_gbs = ab / (alone_us * 1e-6) / 1e9
+    step_gbs = ab / (ms_step * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profile(khash, workload),
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
             "kernel": "k_apply<true,true> (apply + fused whole-frame statistics)", "bytes_per_launch": ab,
-            "launch_us": round(launch_us, 2), "launch_timing": apply_where, "launches_timed": int(apply_ms.size), "copy_ceiling_GBs": round(copy_gbs, 1),
-            "frac_of_copy_ceiling": round(achieved / copy_gbs, 4)}
-    if pipe is not None and args.lanes > 1:
-        # Applies of consecutive frame-sets overlap here, so a launch's own
-        # duration overstates its share of the time: also the apply bytes of
-        # one frame-set over the measured time per frame-set, and the launch
-        # duration with nothing beside it.
-        step_gbs = ab / (ms_total / args.steps * 1e-3) / 1e9
-        roof["per_step"] = {"achieved": round(step_gbs, 1), "frac": round(step_gbs / HBM_PEAK_GBS, 4),
-                            "what": "apply bytes per frame-set / time per frame-set (launches overlap)"}
-        alone_us = float(alone_ms.mean() * 1e3)
-        alone_gbs = ab / (alone_us * 1e-6) / 1e9
-        roof["alone"] = {"launch_us": round(alone_us, 2), "achieved": round(alone_gbs, 1),
-                         "frac": round(alone_gbs / HBM_PEAK_GBS, 4), "launches_timed": int(alone_ms.size),
-                         "what": "the same launches back to back on one stream after the timed region"}
-    out = {
-        "metric": METRIC, "value": round(gpix, 3), "unit": "GPix/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(ms_step, 5), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "u8", "data": "synthetic",
-        "config": {"workload": workload, "path": "plain", "mode": "smoothing" if args.smoothing else "standard",
-                   "launch_mode": args.mode + (f", {args.lanes} apply lanes, depth {args.depth}, group {args.group}"
-                                               if pipe is not None else ""),
-                   "n_blocks": opts.n_blocks, "band_width": opts.band_width, "pixels_per_frameset": px,
-                   "rotating_buffers": args.nbuf, "tile_rows": tile_rows, "apply_grid": grid, "n_tiles": n_tiles},
-        "hbm_frac": round(alg_bytes * args.steps / (ms_total / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
-        "algorithmic_bytes_per_frameset": alg_bytes,
+            "launch_us": round(launch_us, 2), "launch_timing": apply_where, "launches_timed": int(apply_ms.size),
+            "copy_ceiling_GBs": round(copy_gbs, 1), "frac_of_copy_ceiling": round(achieved / copy_gbs, 4),
+            "alone": {"launch_us": round(alone_us, 2), "achieved": round(alone_gbs, 1),
+                      "frac": round(alone_gbs / HBM_PEAK_GBS, 4), "frac_of_copy_ceiling": round(alone_gbs / copy_gbs, 4),
+                      "launches_timed": int(alone_ms.size),
+                      "what": "the same launches back to back on one stream after the timed region"},
+            "per_step": {"achieved": round(step_gbs, 1), "frac": round(step_gbs / HBM_PEAK_GBS, 4),
+                         "what": "apply bytes per frame-set / time per frame-set (launches may overlap)"}}
+    rep = {
+        "workload": rig_spec.name, "GPix_s": round(gpix, 3), "ms_per_step": round(ms_step, 5),
+        "hbm_frac": round(alg_bytes * steps / (ms_total / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+        "algorithmic_bytes_per_frameset": alg_bytes, "pixels_per_frameset": px,
+        "n_blocks": opts.n_blocks, "band_width": opts.band_width,
+        "tile_rows": tile_rows, "apply_grid": grid, "n_tiles": n_tiles,
         "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 4),
                        "p99": round(float(np.percentile(lat_ms, 99)), 4),
                        "what": "start to end of each step's GPU work, steps back to back, measured after the timed "
                                "region (in graph-pipelined mode a frame-set's estimate ran one step earlier)"},
-        "wall_s": round(wall, 4),
-        "host_issue_us_per_step": round(host_issue / args.steps * 1e6, 2),
+        "wall_s": round(wall, 4), "host_issue_us_per_step": round(host_issue / steps * 1e6, 2),
+        "roofline": roof,
+    }
+    return rig, rep, ins, outs, base
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--config", default="rig14", choices=["rig14", "uneven", "vga"])
+    ap.add_argument("--nbuf", type=int, default=8)
+    ap.add_argument("--smoothing", action="store_true")
+    ap.add_argument("--mode", default="pipe", choices=["pipe", "graph-pipelined", "graph", "eager"],
+                    help="pipe: rt_pipe_submit per step (statistics and estimates on their own stream, applies "
+                         "round-robin over --lanes streams); graph-pipelined: one two-branch graph launch per step; "
+                         "graph: one captured rt_frameset per step; eager: one rt_frameset call per step")
+    ap.add_argument("--lanes", type=int, default=3, help="apply streams of the pipe mode")
+    ap.add_argument("--group", type=int, default=3, help="frame-sets whose applies the pipe mode issues together")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tile-rows", type=int, default=0)
+    ap.add_argument("--grid", type=int, default=None,
+                    help="apply workgroups (rt_ctx_tune; 0 = one per tile; default: the context's own choice)")
+    ap.add_argument("--depth", type=int, default=8, help="slots of the pipe mode (>= lanes, >= group, divides --nbuf)")
+    ap.add_argument("--copy-only", action="store_true", help="time the streaming copy of the frame bytes only")
+    ap.add_argument("--timing-every", type=int, default=0,
+                    help="time every n-th apply launch of the timed region with HIP events "
+                         "(default: steps // 10, at least 1, so that about ten launches are timed)")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate training/inference leg")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
+    ap.add_argument("--no-vga", action="store_true", help="skip the 1x640x480 per-call leg")
+    ap.add_argument("--no-uneven", action="store_true", help="skip the uneven three-ring rig leg")
+    ap.add_argument("--uneven-steps", type=int, default=0, help="steps of the uneven leg (default: --steps)")
+    ap.add_argument("--sur-bases", type=int, default=4)
+    ap.add_argument("--sur-draws", type=int, default=112, help="gain draws per base scene (448 units each)")
+    ap.add_argument("--sur-epochs", type=int, default=30)
+    ap.add_argument("--sur-lr", type=float, default=1e-3)
+    ap.add_argument("--sur-tol", type=float, default=1e-3)
+    ap.add_argument("--serve-seconds", type=float, default=10.0, help="paced serving: 30 frame-sets per second per rig")
+    ap.add_argument("--serve-lanes", type=int, default=1,
+                    help="apply lanes of the serving backend's frame-set pipeline (plain path; 1 = one stream)")
+    ap.add_argument("--serve-saturated", type=int, default=40, help="frame-sets per rig in the saturated run")
+    ap.add_argument("--cpu-budget", type=float, default=10.0, help="seconds of oracle work per CPU-baseline leg")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported (the correction of one rig "
+              f"runs on one device; see the sharding notes of the design document)", file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_1910_03517_amd import rt
+
+    torch.cuda.set_device(0)
+    rig_spec = config(args.config)
+    timing_every = args.timing_every or max(1, args.steps // 10)
+    if args.copy_only:
+        cams = [rt.Camera(c.width, c.height, c.channels, c.bit_depth, c.ring, c.pos).with_pitch()
+                for c in rig_spec.cams]
+        frame_bytes = apply_bytes(cams) // 2
+        gbs = copy_ceiling(rt, torch, frame_bytes, args.nbuf, args.steps, args.warmup)
+        print(json.dumps({"copy_bytes_per_launch": 2 * frame_bytes, "copy_GBs": round(gbs, 1)}), flush=True)
+        return 0
+
+    rig, rep, ins, outs, base = plain_leg(args, rig_spec, args.steps, args.warmup, timing_every)
+    khash = kernel_hash()
+    workload = rig_spec.name
+    roof = rep.pop("roofline")
+    roof["traffic"] = traffic_from_profile(khash, workload)
+    out = {
+        "metric": METRIC, "value": rep["GPix_s"], "unit": "GPix/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": rep["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": workload, "path": "plain", "mode": "smoothing" if args.smoothing else "standard",
+                   "launch_mode": args.mode + (f", {args.lanes} apply lanes, depth {args.depth}, group {args.group}"
+                                               if args.mode == "pipe" else ""),
+                   "n_blocks": rep["n_blocks"], "band_width": rep["band_width"],
+                   "pixels_per_frameset": rep["pixels_per_frameset"], "rotating_buffers": args.nbuf,
+                   "tile_rows": rep["tile_rows"], "apply_grid": rep["apply_grid"], "n_tiles": rep["n_tiles"]},
+        "hbm_frac": rep["hbm_frac"],
+        "algorithmic_bytes_per_frameset": rep["algorithmic_bytes_per_frameset"],
+        "latency_ms": rep["latency_ms"],
+        "wall_s": rep["wall_s"],
+        "host_issue_us_per_step": rep["host_issue_us_per_step"],
         "roofline": roof,
         "kernel_hash": khash,
     }
@@ -545,12 +648,26 @@ def main() -> int:
     sur_w = None
     if not args.no_surrogate and args.config == "rig14":
         sur_w, out["surrogate"] = surrogate_leg(args, rig, ins, outs)
+    rig.close()
+    del ins, outs
     if not args.no_serving and args.config == "rig14":
         out["serving"] = serving_leg(args, base, sur_w)
+    if not args.no_uneven and args.config == "rig14":
+        # The uneven three-ring rig (4 x 4096x2160 RGB8, 8 x 1920x1080 RGB8,
+        # 4 x 640x512 gray16) in the same launch configuration.
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        us = args.uneven_steps or args.steps
+        urig, urep, _, _, _ = plain_leg(args, config("uneven"), us, args.warmup, args.timing_every or max(1, us // 10))
+        urig.close()
+        uroof = urep.pop("roofline")
+        out["uneven"] = {**urep, "steps": us, "roofline": {k: uroof[k] for k in (
+            "achieved", "frac", "launch_us", "launches_timed", "copy_ceiling_GBs", "alone", "per_step")}}
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(rig_spec, opts)
-    rig.close()
+        out["cpu_baseline"] = cpu_baseline(rig_spec, args.smoothing, args.cpu_budget)
+        log("cpu baseline (oracle, process pool over cameras)")
+        out["cpu_baseline_pool"] = cpu_baseline_pool(args.config, args.smoothing, args.cpu_budget)
     print(json.dumps(out), flush=True)
     return 0
 

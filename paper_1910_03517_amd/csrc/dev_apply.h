@@ -401,12 +401,16 @@ __device__ void apply_run_direct(const Geo& g, const FramePtrs& fp, const Bufs& 
       }
     };
     select();
+    // Row r starts block jb + 1 when r == rb.  Blocks hold no rows when
+    // H < NB, so several block starts can fall on one row: step over every
+    // empty block to the one that holds r (uniform over the wave).
     auto next_block = [&](int r) {
-      if (r == rb) {                                  // uniform
+      if (r != rb) return;
+      while (r == rb && jb < j1) {
         ++jb;
         rb = min(R1, (int)((int64_t)(jb + 1) * H / nb));
-        select();
       }
+      select();
     };
     const int cbyte = col0 * C;
 

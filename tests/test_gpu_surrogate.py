@@ -4,10 +4,13 @@ and what training gains over the untrained network and over no correction.
 Features, plain estimates, targets and selections are compared bit for bit
 (the selection takes the GPU's float32 predictions on both sides, so the
 integer decision is made on the same numbers); forward, backward and Adam
-against the binary64 oracle within 1e-4 relative (per-tensor norm)."""
+against the binary64 oracle element by element: |gpu - ref| <= 1e-4 |ref|
+plus the float32 rounding bound of the products involved (tests/mlp_bounds.py
+states it), for every activation, workspace value and gradient."""
 import numpy as np
 import pytest
 
+from tests import mlp_bounds as mb
 from tests.gpu_helpers import oracle_cams, oracle_opts, rt_cams, say
 
 torch = pytest.importorskip("torch")
@@ -100,13 +103,21 @@ def test_forward_backward_adam_against_fp64():
     torch.cuda.synchronize()
     Po = {k: v.astype(np.float64) for k, v in P.items()}
     Yo, H1o, H2o = sg.forward(Po, X)
-    Go = sg.backward(Po, X, H1o, H2o, Yo, T)
-    assert rel(Y.cpu().numpy(), Yo) < 1e-4
-    assert rel(H1.cpu().numpy(), H1o) < 1e-4 and rel(H2.cpu().numpy(), H2o) < 1e-4
-    assert abs(loss.item() - sg.mse(Yo, T)) <= 1e-4 * sg.mse(Yo, T)
+    hg = {k: t.cpu().numpy() for k, t in (("H1", H1), ("H2", H2), ("Y", Y), ("dY", dY), ("dZ1", dZ1),
+                                          ("dZ2", dZ2))}
     gh = g.host()
+    # Element by element: each product from the device's own inputs, then
+    # against the oracle's binary64 chain with the rounding bounds carried.
+    mb.check_forward_layers(P, X, hg["H1"], hg["H2"], hg["Y"])
+    mb.check_forward_end_to_end(P, X, hg["H1"], hg["H2"], hg["Y"])
+    mb.check_backward_layers(P, X, hg["H1"], hg["H2"], hg["Y"], T, hg["dY"], hg["dZ2"], hg["dZ1"], gh)
+    mb.check_backward_end_to_end(P, X, hg["H1"], hg["H2"], hg["Y"], T, gh)
+    # The oracle's own backward (its masks from its own activations) agrees too
+    # wherever no pre-activation lies within the rounding bound of zero.
+    Go = sg.backward(Po, X, H1o, H2o, Yo, T)
     for k in rt.MlpTensors.NAMES:
         assert rel(gh[k], Go[k]) < 1e-4, k
+    assert abs(loss.item() - sg.mse(Yo, T)) <= 1e-4 * sg.mse(Yo, T)
     # A batch above 2048 rows: the products with one row per sample take the
     # 64 x 64 tile kernel (with the ReLU-mask epilogue), the weight gradients
     # still the k-split tiles, over a long sum.
@@ -120,12 +131,13 @@ def test_forward_backward_adam_against_fp64():
     rt.rt_mlp_forward(w, Xbd, nb, B1, B2, BY)
     rt.rt_mlp_backward(w, Xbd, B1, B2, BY, Tbd, nb, gb, bY, bZ1, bZ2)
     torch.cuda.synchronize()
-    Ybo, B1o, B2o = sg.forward(Po, Xb)
-    Gbo = sg.backward(Po, Xb, B1o, B2o, Ybo, Tb)
-    assert rel(BY.cpu().numpy(), Ybo) < 1e-4
+    hb = {k: t.cpu().numpy() for k, t in (("H1", B1), ("H2", B2), ("Y", BY), ("dY", bY), ("dZ1", bZ1),
+                                          ("dZ2", bZ2))}
     gbh = gb.host()
-    for k in rt.MlpTensors.NAMES:
-        assert rel(gbh[k], Gbo[k]) < 1e-4, k
+    mb.check_forward_layers(P, Xb, hb["H1"], hb["H2"], hb["Y"])
+    mb.check_forward_end_to_end(P, Xb, hb["H1"], hb["H2"], hb["Y"])
+    mb.check_backward_layers(P, Xb, hb["H1"], hb["H2"], hb["Y"], Tb, hb["dY"], hb["dZ2"], hb["dZ1"], gbh)
+    mb.check_backward_end_to_end(P, Xb, hb["H1"], hb["H2"], hb["Y"], Tb, gbh)
     # Adam from the GPU's own gradient on both sides, two steps.
     m, v = rt.MlpTensors(None), rt.MlpTensors(None)
     Pa, Ma, Va = dict(Po), {k: np.zeros_like(x) for k, x in Po.items()}, {k: np.zeros_like(x) for k, x in Po.items()}
@@ -135,8 +147,11 @@ def test_forward_backward_adam_against_fp64():
         Pa, Ma, Va = sg.adam(Pa, Gd, Ma, Va, step, 1e-3, 0.9, 0.999, 1e-8)
     torch.cuda.synchronize()
     wh = w.host()
+    # Per element and step: the float32 update w - lr m^/(sqrt(v^) + eps)
+    # rounds w once (u |w|) and the ratio a few ulps at most (|ratio| <= 4
+    # in the first steps); the bar allows 4 u |w| + 256 u lr per step.
     for k in rt.MlpTensors.NAMES:
-        assert np.max(np.abs(wh[k] - Pa[k])) < 1e-6 + 1e-5 * np.max(np.abs(Pa[k])), k
+        mb.check(f"adam {k}", wh[k], Pa[k], 2 * (4 * mb.U32 * np.abs(Pa[k]) + 256 * mb.U32 * 1e-3))
 
 
 @pytest.mark.parametrize("n", [1, 5, 33, 96, 448, 2048, 2049])
@@ -155,11 +170,9 @@ def test_forward_sizes_against_fp64(n):
     H1, H2, Y = torch.full((n, 256), -1.0, **e), torch.full((n, 256), -1.0, **e), torch.full((n, 6), -1.0, **e)
     rt.rt_mlp_forward(w, torch.as_tensor(X, device="cuda"), n, H1, H2, Y)
     torch.cuda.synchronize()
-    Yo, H1o, H2o = sg.forward({k: v.astype(np.float64) for k, v in P.items()}, X)
-    assert rel(H1.cpu().numpy(), H1o) < 1e-5
-    assert rel(H2.cpu().numpy(), H2o) < 1e-5
-    assert rel(Y.cpu().numpy(), Yo) < 1e-5
-    assert np.abs(Y.cpu().numpy() - Yo).max() < 1e-5 * max(1.0, np.abs(Yo).max())
+    h1, h2, y = H1.cpu().numpy(), H2.cpu().numpy(), Y.cpu().numpy()
+    mb.check_forward_layers(P, X, h1, h2, y)
+    mb.check_forward_end_to_end(P, X, h1, h2, y)
 
 
 def test_select_and_state_update_bit_exact():

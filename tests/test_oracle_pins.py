@@ -372,6 +372,38 @@ def test_weights_against_rationals():
             assert w[0] == 256 and w[-1] == 256
 
 
+def test_weights_table_golden():
+    """The per-camera table the tables step writes: one row per camera of
+    W_max entries, each camera's own weights then zeros (hand-worked)."""
+    g = golden("weights_table_worked.json")
+    cams = [rc.Camera(w, 4, pos=i) for i, w in enumerate(g["widths"])]
+    t = rc.weights_table(cams)
+    assert t.dtype == np.uint16 and t.shape == (3, 8)
+    assert t.tolist() == g["table"]
+
+
+def test_weights_table_rows_against_rationals():
+    """Rows of uneven rigs: row k, columns < W_k, is round_half_up(256 d / h)
+    by exact rationals (d counted from the centre), every later entry is 0;
+    row order follows the camera list, not ring position."""
+    widths = [17, 1, 64, 2, 33, 7]
+    cams = [rc.Camera(w, 3, ring=i % 2, pos=i // 2) for i, w in enumerate(widths)]
+    t = rc.weights_table(cams)
+    assert t.shape == (len(widths), max(widths))
+    for k, W in enumerate(widths):
+        h = W // 2
+        for col in range(max(widths)):
+            if col >= W:
+                ref = 0
+            elif col < h:
+                ref = rhu(Fraction(256 * (h - col), h))
+            elif col >= W - h:
+                ref = rhu(Fraction(256 * (col - (W - h) + 1), h))
+            else:
+                ref = 0
+            assert int(t[k, col]) == ref, (k, col)
+
+
 @pytest.mark.parametrize("bit_depth", [8, 12])
 def test_apply_bruteforce(bit_depth):
     """Per-pixel loop: block by closed form, weight by rationals, map by rationals."""

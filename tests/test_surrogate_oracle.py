@@ -136,3 +136,59 @@ def test_select_rule():
     edge = pred.copy()
     edge[0, 0] = np.float32(1.25) + np.float32(9.5367431640625e-4)   # residual just under 1e-3 -> used
     assert sg.select(edge, p_new, st, cams, 1e-3)[1][0] == 1
+
+
+def test_targets_order_and_scale_hand_cases():
+    """Hand-worked: the unit's [channel][a, b] parameters become (a_R, a_G,
+    a_B, b_R/255, b_G/255, b_B/255), gains first in channel order, offsets
+    in grey levels divided by 255."""
+    p = np.array([[1.5, 51.0], [2.0, -25.5], [0.5, 255.0]])
+    assert sg.targets(p).tolist() == [1.5, 2.0, 0.5, 0.2, -0.1, 1.0]
+    q = np.array([[1.0, 0.0], [1.0, 0.0], [1.0, 0.0]])
+    assert sg.targets(q).tolist() == [1.0, 1.0, 1.0, 0.0, 0.0, 0.0]
+    r = np.array([[0.125, -12.75], [8.0, 25.5], [3.0, 127.5]])       # offsets exact in binary
+    assert sg.targets(r).tolist() == [0.125, 8.0, 3.0, -0.05, 0.1, 0.5]
+
+
+def test_targets_of_known_gains():
+    """Closed form: a seam whose two bands are one scene under gains gP and
+    gQ = 2 gP (integer samples, no clipping) has a_P = 1.5 and b_P = 0 in
+    every channel, so the own unit's target is (1.5, 1.5, 1.5, 0, 0, 0) and
+    the facing unit's (0.75, 0.75, 0.75, 0, 0, 0) - with the offset term
+    unscaled by 255 this would not tell them apart, with the order swapped
+    the first three would be 0."""
+    rng = np.random.default_rng(11)
+    s = rng.integers(16, 97, (16, 8, 3)).astype(np.int64)
+    cams = [rc.Camera(16, 16, pos=0), rc.Camera(16, 16, pos=1)]
+    opts = rc.Options(n_blocks=1, band_width=8, closed_ring=False)
+    frames = [np.zeros((16, 16, 3), np.uint8) for _ in range(2)]
+    frames[0][:, 8:] = s.astype(np.uint8)           # right band of camera 0
+    frames[1][:, :8] = (2 * s).astype(np.uint8)     # left band of camera 1 (facing it)
+    bs = np.stack([rc.band_stats(f, c, opts)[1] for f, c in zip(frames, cams)])
+    p_new, st = sg.estimate_new(cams, opts, bs)
+    assert np.all(st[0, 1, 0] == sg.NEW) and np.all(st[1, 0, 0] == sg.NEW)
+    t_own = sg.targets(p_new[0, 1, 0])
+    t_fac = sg.targets(p_new[1, 0, 0])
+    assert np.allclose(t_own, [1.5, 1.5, 1.5, 0, 0, 0], rtol=0, atol=1e-12)
+    assert np.allclose(t_fac, [0.75, 0.75, 0.75, 0, 0, 0], rtol=0, atol=1e-12)
+
+
+def test_targets_as_prediction_have_zero_residual_and_restore_the_estimate():
+    """A network that outputs exactly the targets (as float32) is within the
+    float32 rounding of the plain estimate under the fallback rule's residual,
+    and a used prediction gives back (a, 255 b/255) of the estimate."""
+    rng = np.random.default_rng(12)
+    cams = [rc.Camera(8, 8, pos=0), rc.Camera(8, 8, pos=1)]
+    p_new = np.zeros((2, 2, 1, 3, 2))
+    p_new[..., 0] = rng.uniform(0.5, 2.0, (2, 2, 1, 3))
+    p_new[..., 1] = rng.uniform(-40.0, 40.0, (2, 2, 1, 3))
+    st = np.full((2, 2, 1, 3), sg.NEW, np.int32)
+    pred = np.array([sg.targets(p_new[k, s, 0]) for k in range(2) for s in range(2)], np.float32)
+    for u in range(4):
+        k, s = divmod(u, 2)
+        r = sg.residual(pred[u], p_new[k, s, 0])
+        assert r <= 2.0 ** -23 * 4            # one float32 rounding of values below 4 in magnitude
+    out, used, _ = sg.select(pred, p_new, st, cams, 1e-6)
+    assert used.tolist() == [1, 1, 1, 1]
+    assert np.allclose(out[..., 0], p_new[..., 0], rtol=2.0 ** -23, atol=0)
+    assert np.allclose(out[..., 1], p_new[..., 1], rtol=0, atol=255 * 2.0 ** -24 * 1.0)
