@@ -266,6 +266,59 @@ rt_status rt_pipe_destroy(rt_pipe* p);
 rt_status rt_pipe_submit_batch(rt_pipe* p, uint64_t active, const void* const* frames, void* const* out_frames,
                                void* stream, void* ready_event, void* done_event, int32_t* slot_out);
 
+/* ------------------------------------------------------------------------
+ * Object removal with the smoothing fallback (section 3.1: the two
+ * supplemental methods for objects that move across a seam; section 4.1
+ * prefers removal where enough of a block remains, and section 5 leaves the
+ * automatic choice between them open - it is made here per seam unit).
+ *
+ * A band pixel is moving when the absolute difference of one of its samples
+ * to the same sample of the previous frame of that camera exceeds
+ * tau << (bit_depth - 8) (tau in 8-bit units).  Kept sums: kept_sums uint64
+ * [K][2][NB][3][3] = (n, S1, S2) over the band's pixels that do not move
+ * (n repeated for every channel of the camera, zero for unused slots).
+ * Per seam unit (camera, side, block) the method is
+ *   RT_METHOD_REMOVAL   when both facing bands keep at least min_kept of their
+ *                       pixels (kept_n / n in binary64): the affine fit of
+ *                       rt_estimate from the kept sums, then the context's
+ *                       temporal mode;
+ *   RT_METHOD_SMOOTHING otherwise: the fit of the whole bands, blended as
+ *                       E = (1 - alpha) E_prev + alpha E_new (alpha of the
+ *                       context's options; the first estimate taken as is);
+ *   RT_METHOD_NONE      without a facing band or with an empty band (the
+ *                       state is kept as rt_estimate keeps it).
+ * Both sides of a seam take the same method.  method uint8 [K][2][NB].
+ * prev_frames NULL: no previous frame-set, nothing moves (kept = whole band).
+ * Previous frames have the geometry of the context's cameras.
+ * ------------------------------------------------------------------------ */
+enum { RT_METHOD_NONE = 0, RT_METHOD_REMOVAL = 1, RT_METHOD_SMOOTHING = 2 };
+
+/* tau >= 0 (paper: a thresholded frame difference; default 20), 0 <= min_kept <= 1
+ * (default 0.25). */
+typedef struct {
+  int32_t tau;
+  int32_t reserved;
+  double min_kept;
+} rt_removal_opts;
+
+/* Band statistics as rt_stats writes them (whole bands; out->whole_* are
+ * not used) and the kept sums against prev_frames. */
+rt_status rt_motion_stats(rt_ctx* ctx, const void* const* frames, const void* const* prev_frames,
+                          const rt_removal_opts* ro, const rt_stats_buf* out, uint64_t* kept_sums, void* stream);
+
+/* The per-unit choice and state update above from stats->band_sums and
+ * kept_sums; method may be NULL. */
+rt_status rt_estimate_removal(rt_ctx* ctx, const rt_stats_buf* stats, const uint64_t* kept_sums,
+                              const rt_removal_opts* ro, const rt_params_buf* state, uint8_t* method, void* stream);
+
+/* rt_frameset with object removal: rt_motion_stats, rt_estimate_removal,
+ * rt_build_lut and rt_apply (with whole-frame statistics) in that order, in
+ * two kernels as rt_frameset.  Restricted to the context's active set. */
+rt_status rt_frameset_removal(rt_ctx* ctx, const void* const* frames, const void* const* prev_frames,
+                              void* const* out_frames, const rt_removal_opts* ro, const rt_stats_buf* stats,
+                              uint64_t* kept_sums, const rt_params_buf* state, const rt_lut_buf* lut,
+                              uint8_t* method, void* stream);
+
 /* A frame-set captured once into a HIP graph for fixed buffers and replayed
  * with one launch per frame-set.
  *

@@ -274,6 +274,120 @@ def estimate(cams: list[Camera], opts: Options, band_sums: np.ndarray,
 
 
 # --------------------------------------------------------------------------
+# Object removal with the smoothing fallback (section 3.1, the two
+# supplemental methods for moving objects; section 4.1 prefers removal when
+# enough of the block remains)
+# --------------------------------------------------------------------------
+#
+# R-move    a pixel is moving when its thresholded absolute difference to the
+#           previous frame of the same camera exceeds tau on some channel:
+#           max_c |x_t - x_{t-1}| > tau << (bit_depth - 8), tau in 8-bit
+#           units (tau = 20 by default).  Without a previous frame nothing
+#           moves.
+# R-kept    removal drops the moving pixels from the band statistics: the
+#           kept sums (n, S1, S2) of a band count only the pixels that do
+#           not move.
+# R-select  per seam unit, the removal fit (kept sums of both facing bands,
+#           then the context's temporal mode) is used when at least a
+#           fraction min_kept (0.25 by default) of each band's pixels is
+#           kept, the fraction computed in binary64 as kept_n / n; otherwise
+#           the smoothing fallback: the fit of the full bands blended as
+#           E = (1 - alpha) E_prev + alpha E_new (the first estimate taken as
+#           is).  Both sides of a seam see the same two fractions, so they
+#           take the same method.
+
+REMOVAL_TAU = 20
+REMOVAL_MIN_KEPT = 0.25
+METHOD_NONE, METHOD_REMOVAL, METHOD_SMOOTHING = 0, 1, 2
+
+
+def moving_mask(frame: np.ndarray, prev: np.ndarray | None, bit_depth: int, tau: int) -> np.ndarray:
+    """bool (rows, cols): the pixels whose difference to `prev` exceeds the threshold (R-move)."""
+    if prev is None:
+        return np.zeros(frame.shape[:2], bool)
+    d = np.abs(frame.astype(np.int64) - prev.astype(np.int64)).max(axis=2)
+    return d > (tau << (bit_depth - 8))
+
+
+def kept_band_sums(frame: np.ndarray, prev: np.ndarray | None, cam: Camera, opts: Options,
+                   tau: int = REMOVAL_TAU) -> np.ndarray:
+    """(n, S1, S2) of the kept pixels of every (side, block) band, [2][NB][CSLOTS][3] (R-kept)."""
+    nb = opts.n_blocks
+    out = np.zeros((2, nb, CSLOTS, 3), np.int64)
+    moving = moving_mask(frame, prev, cam.bit_depth, tau)
+    cols = band_columns(cam.width, opts.band_width)
+    for j, (r0, r1) in enumerate(block_bounds(cam.height, nb)):
+        for s in (LEFT, RIGHT):
+            c0, c1 = cols[s]
+            keep = ~moving[r0:r1, c0:c1]
+            for c in range(cam.channels):
+                v = frame[r0:r1, c0:c1, c].astype(np.int64)[keep]
+                out[s, j, c] = (v.size, int(v.sum()), int((v * v).sum()))
+    return out
+
+
+def estimate_removal(cams: list[Camera], opts: Options, band_sums: np.ndarray, kept_sums: np.ndarray,
+                     prev_params: np.ndarray | None = None, prev_valid: np.ndarray | None = None,
+                     min_kept: float = REMOVAL_MIN_KEPT):
+    """Per unit: the removal fit or the smoothing fallback (R-select).
+
+    Returns (params, valid, method); method u8 [K][2][NB] is METHOD_REMOVAL,
+    METHOD_SMOOTHING, or METHOD_NONE where no new estimate was made (no facing
+    band, or an empty band).
+    """
+    K, nb = len(cams), opts.n_blocks
+    if prev_params is None:
+        prev_params = np.zeros((K, 2, nb, CSLOTS, 2), np.float64)
+        prev_params[..., 0] = 1.0
+    if prev_valid is None:
+        prev_valid = np.zeros((K, 2, nb, CSLOTS), np.uint8)
+    params = np.zeros((K, 2, nb, CSLOTS, 2), np.float64)
+    valid = np.zeros((K, 2, nb, CSLOTS), np.uint8)
+    method = np.zeros((K, 2, nb), np.uint8)
+    for k, cam in enumerate(cams):
+        for s in (LEFT, RIGHT):
+            fc = facing(cams, opts, k, s)
+            for j in range(nb):
+                m = METHOD_NONE
+                if fc is not None:
+                    n_own, n_fac = int(band_sums[k, s, j, 0, 0]), int(band_sums[fc[0], fc[1], j, 0, 0])
+                    if n_own > 0 and n_fac > 0:
+                        kn_own, kn_fac = int(kept_sums[k, s, j, 0, 0]), int(kept_sums[fc[0], fc[1], j, 0, 0])
+                        f_own = float(kn_own) / float(n_own)
+                        f_fac = float(kn_fac) / float(n_fac)
+                        ok = kn_own > 0 and kn_fac > 0 and f_own >= min_kept and f_fac >= min_kept
+                        m = METHOD_REMOVAL if ok else METHOD_SMOOTHING
+                method[k, s, j] = m
+                for c in range(CSLOTS):
+                    if c >= cam.channels:
+                        params[k, s, j, c] = (1.0, 0.0)
+                        continue
+                    if fc is None:
+                        params[k, s, j, c] = (1.0, 0.0)
+                        valid[k, s, j, c] = 1
+                        continue
+                    had = bool(prev_valid[k, s, j, c])
+                    if m == METHOD_NONE:
+                        if had:
+                            params[k, s, j, c] = prev_params[k, s, j, c]
+                            valid[k, s, j, c] = 1
+                        else:
+                            params[k, s, j, c] = (1.0, 0.0)
+                        continue
+                    src = kept_sums if m == METHOD_REMOVAL else band_sums
+                    own = tuple(int(v) for v in src[k, s, j, c])
+                    fac = tuple(int(v) for v in src[fc[0], fc[1], j, c])
+                    a, b = fit_side(own, fac, opts.a_min, opts.a_max)
+                    smooth = opts.smoothing if m == METHOD_REMOVAL else True
+                    if smooth and had:
+                        a = ema(float(prev_params[k, s, j, c, 0]), a, opts.ema_alpha)
+                        b = ema(float(prev_params[k, s, j, c, 1]), b, opts.ema_alpha)
+                    params[k, s, j, c] = (a, b)
+                    valid[k, s, j, c] = 1
+    return params, valid, method
+
+
+# --------------------------------------------------------------------------
 # LUTs and column weights (section 3.1: the map and its convex blend)
 # --------------------------------------------------------------------------
 
@@ -389,6 +503,23 @@ def frameset(cams: list[Camera], opts: Options, frames: list[np.ndarray],
     outs = [apply_camera(f, cam, opts, lut8[k], qq[k]) for k, (cam, f) in enumerate(zip(cams, frames))]
     return dict(band_hist=bh, band_sums=bs, whole_hist=wh, whole_sums=ws, params=params,
                 valid=valid, lut8=lut8, q16=qq, weights=weights_table(cams), out=outs)
+
+
+def frameset_removal(cams: list[Camera], opts: Options, frames: list[np.ndarray],
+                     prev_frames: list[np.ndarray] | None, prev_params: np.ndarray | None = None,
+                     prev_valid: np.ndarray | None = None, tau: int = REMOVAL_TAU,
+                     min_kept: float = REMOVAL_MIN_KEPT) -> dict:
+    """frameset() with object removal and the smoothing fallback: the band
+    statistics of the whole bands, the kept sums against the previous frames
+    (None: nothing moves), the estimate by R-select, tables and apply."""
+    r = frameset(cams, opts, frames, prev_params, prev_valid)
+    kept = np.stack([kept_band_sums(f, None if prev_frames is None else prev_frames[k], cam, opts, tau)
+                     for k, (cam, f) in enumerate(zip(cams, frames))])
+    params, valid, method = estimate_removal(cams, opts, r["band_sums"], kept, prev_params, prev_valid, min_kept)
+    lut8, qq = build_luts(cams, opts, params)
+    outs = [apply_camera(f, cam, opts, lut8[k], qq[k]) for k, (cam, f) in enumerate(zip(cams, frames))]
+    r.update(kept_sums=kept, params=params, valid=valid, method=method, lut8=lut8, q16=qq, out=outs)
+    return r
 
 
 # --------------------------------------------------------------------------

@@ -73,8 +73,8 @@ __device__ inline int fit_new(const Geo& g, const uint64_t* band_sums, int u, do
 
 // The state (p0, p1, v) of a unit after its fit, in place (section 3.1's
 // exponential smoothing in smoothing mode; the first estimate is taken as is).
-__device__ inline void temporal_step(const Geo& g, int status, double a, double bb, double& p0, double& p1,
-                                     uint8_t& v) {
+__device__ inline void temporal_step_mode(const Geo& g, int mode, int status, double a, double bb, double& p0,
+                                          double& p1, uint8_t& v) {
   if (status == kStUnused || status == kStIdentity) {
     p0 = 1.0; p1 = 0.0; v = status == kStIdentity ? 1 : 0;
     return;
@@ -84,7 +84,7 @@ __device__ inline void temporal_step(const Geo& g, int status, double a, double 
     if (!had) { p0 = 1.0; p1 = 0.0; }
     return;
   }
-  if (g.mode == RT_MODE_SMOOTHING && had) {
+  if (mode == RT_MODE_SMOOTHING && had) {
     const double keep = 1.0 - g.alpha;
     const double ta = keep * p0;
     const double na = g.alpha * a;
@@ -96,6 +96,43 @@ __device__ inline void temporal_step(const Geo& g, int status, double a, double 
   p0 = a;
   p1 = bb;
   v = 1;
+}
+
+// temporal_step_mode in the context's temporal mode.
+__device__ inline void temporal_step(const Geo& g, int status, double a, double bb, double& p0, double& p1,
+                                     uint8_t& v) {
+  temporal_step_mode(g, g.mode, status, a, bb, p0, p1, v);
+}
+
+// Object removal with the smoothing fallback (section 3.1; section 4.1
+// prefers removal when enough of a block remains).  Method of a seam unit
+// from the channel-0 counts of the whole bands (own, fac) and of their kept
+// pixels (kown, kfac): removal when both bands keep at least min_kept of
+// their pixels (fractions in binary64), the smoothing fallback otherwise,
+// none without a facing band or with an empty band.  Both sides of a seam
+// see the same two fractions.
+enum { kMethodNone = 0, kMethodRemoval = 1, kMethodSmoothing = 2 };
+
+__device__ inline int removal_method(const uint64_t* own, const uint64_t* fac, const uint64_t* kown,
+                                     const uint64_t* kfac, double min_kept) {
+  if (!fac || own[0] == 0 || fac[0] == 0) return kMethodNone;
+  const double fo = (double)kown[0] / (double)own[0];
+  const double ff = (double)kfac[0] / (double)fac[0];
+  return (kown[0] > 0 && kfac[0] > 0 && fo >= min_kept && ff >= min_kept) ? kMethodRemoval : kMethodSmoothing;
+}
+
+// Fit and state step of channel c of a unit under the method m: the removal
+// fit from the kept sums in the context's mode, the fallback from the whole
+// bands' sums, always smoothed (the first estimate taken as is).  own/fac and
+// kown/kfac point at channel c's (n, S1, S2); fac and kfac NULL without a
+// facing band.
+__device__ inline void removal_step(const Geo& g, int m, int channels, int c, const uint64_t* own,
+                                    const uint64_t* fac, const uint64_t* kown, const uint64_t* kfac, double& p0,
+                                    double& p1, uint8_t& v) {
+  double a, bb;
+  const bool kept = m == kMethodRemoval;
+  const int st = fit_sums(g, channels, c, kept ? kown : own, kept ? kfac : fac, a, bb);
+  temporal_step_mode(g, m == kMethodSmoothing ? (int)RT_MODE_SMOOTHING : g.mode, st, a, bb, p0, p1, v);
 }
 
 // temporal_step on the state of unit u in the caller's buffers.

@@ -2,6 +2,7 @@
 // block, channel) for the affine fit, one workgroup per (camera, side, block)
 // for the tables, one thread per column for the blend weights.
 #include "dev_estimate.h"
+#include "dev_motion.h"
 #include "dev_stats.h"
 
 namespace rc {
@@ -37,17 +38,22 @@ __global__ __launch_bounds__(kThreads) void k_weights(Geo g, Bufs b) {
 // form is faster, as its workgroups fit more easily on busy compute units).
 // Same results as k_band_stats, k_estimate, k_build_lut and k_weights in
 // sequence (the whole-frame statistics that the frame-set's apply pass
-// accumulates are cleared here too, when given).
-template <bool WIDE>
-__global__ __launch_bounds__(WIDE ? 2 * kThreads : kThreads) void k_band_estimate(Geo g, FramePtrs fp, Bufs b) {
+// accumulates are cleared here too, when given).  REMOVAL: the band passes
+// also sum the pixels that do not move against the previous frames, and
+// each unit takes the object-removal fit or the smoothing fallback
+// (removal_step), as k_motion_stats and k_estimate_removal would.
+template <bool WIDE, bool REMOVAL, typename Lds>
+__device__ __attribute__((always_inline)) void band_estimate_body(const Geo& g, const FramePtrs& fp,
+                                                                  const PrevPtrs& pp, const Bufs& b,
+                                                                  const Removal& rm, Lds* L) {
   constexpr int NT = WIDE ? 2 * kThreads : kThreads;
   // This kernel's chain of dependent steps is what the next apply waits
   // for; its waves take issue priority over the apply waves they share
   // compute units with (measured on MI355X: 628 -> 674 GPix/s in the
   // pipelined frame-set loop).
   __builtin_amdgcn_s_setprio(3);
-  __shared__ StatsLds L[WIDE ? 2 : 1];
   __shared__ uint64_t sums[3][9];            // (n, S1, S2) per channel of the units taken
+  __shared__ uint64_t kept[REMOVAL ? 3 : 1][9];   // the same over their kept pixels
   __shared__ double ab[3][kCS][2];           // their maps after the fit
   const int nb = g.n_blocks;
   const int k = blockIdx.x / nb, j = blockIdx.x - (blockIdx.x / nb) * nb;
@@ -69,6 +75,11 @@ __global__ __launch_bounds__(WIDE ? 2 * kThreads : kThreads) void k_band_estimat
   const int u2 = uf >= 0 ? ul : -1;
   const int n = 1 + (u1 >= 0) + (u2 >= 0);
   auto unit_at = [&](int i) { return i == 0 ? u0 : (i == 1 ? u1 : u2); };
+  auto band_pass = [&](int i, Lds& Li, int t) {
+    if constexpr (REMOVAL) band_unit_motion_dispatch(g, fp, pp, b, rm, unit_at(i), Li, sums[i], kept[i], t);
+    else band_unit_dispatch(g, fp, b, unit_at(i), Li, sums[i], t);
+  };
+  constexpr int kBarriers = REMOVAL ? kMotionBarriers : kBandBarriers;
   // Thread 64 t + c fits channel c of unit t: its state is read now, ahead
   // of the band passes.
   const int t = tid / kWave, c = tid % kWave;
@@ -88,15 +99,15 @@ __global__ __launch_bounds__(WIDE ? 2 * kThreads : kThreads) void k_band_estimat
       if (p) __syncthreads();
       const int i = 2 * p + half;
       if (i < n) {
-        band_unit_dispatch(g, fp, b, unit_at(i), L[WIDE ? half : 0], sums[i], ltid);
+        band_pass(i, L[WIDE ? half : 0], ltid);
       } else {
-        for (int w = 0; w < kBandBarriers; ++w) __syncthreads();
+        for (int w = 0; w < kBarriers; ++w) __syncthreads();
       }
     }
   } else {
     for (int i = 0; i < n; ++i) {
       if (i) __syncthreads();
-      band_unit_dispatch(g, fp, b, unit_at(i), L[0], sums[i], tid);
+      band_pass(i, L[0], tid);
     }
   }
   if (j == 0)
@@ -107,9 +118,17 @@ __global__ __launch_bounds__(WIDE ? 2 * kThreads : kThreads) void k_band_estimat
     const int other = (uf >= 0 && t < 2) ? 1 - t : -1;
     const uint64_t* fac = other >= 0 ? &sums[other][c * 3] : nullptr;
     const int channels = uniform(g.cams[unit_at(t) / (2 * nb)].channels);
-    double a, bb;
-    const int st = fit_sums(g, channels, c, &sums[t][c * 3], fac, a, bb);
-    temporal_step(g, st, a, bb, p0, p1, v);
+    if constexpr (REMOVAL) {
+      const uint64_t* kfac = other >= 0 ? &kept[other][c * 3] : nullptr;
+      const int m = removal_method(&sums[t][0], other >= 0 ? &sums[other][0] : nullptr, &kept[t][0],
+                                   other >= 0 ? &kept[other][0] : nullptr, rm.min_kept);
+      removal_step(g, m, channels, c, &sums[t][c * 3], fac, &kept[t][c * 3], kfac, p0, p1, v);
+      if (c == 0 && rm.method) rm.method[unit_at(t)] = (uint8_t)m;
+    } else {
+      double a, bb;
+      const int st = fit_sums(g, channels, c, &sums[t][c * 3], fac, a, bb);
+      temporal_step(g, st, a, bb, p0, p1, v);
+    }
     b.params[u * 2] = p0;
     b.params[u * 2 + 1] = p1;
     b.valid[u] = v;
@@ -118,6 +137,56 @@ __global__ __launch_bounds__(WIDE ? 2 * kThreads : kThreads) void k_band_estimat
   }
   __syncthreads();
   for (int w = half; w < n; w += (WIDE ? 2 : 1)) lut_entry_ab(g, b, unit_at(w), ltid, ab[w]);
+}
+
+template <bool WIDE>
+__global__ __launch_bounds__(WIDE ? 2 * kThreads : kThreads) void k_band_estimate(Geo g, FramePtrs fp, Bufs b) {
+  __shared__ StatsLds L[WIDE ? 2 : 1];
+  PrevPtrs pp;
+  Removal rm;
+  band_estimate_body<WIDE, false>(g, fp, pp, b, rm, L);
+}
+
+template <bool WIDE>
+__global__ __launch_bounds__(WIDE ? 2 * kThreads : kThreads) void k_band_estimate_removal(Geo g, FramePtrs fp,
+                                                                                          PrevPtrs pp, Bufs b,
+                                                                                          Removal rm) {
+  __shared__ MotionLds L[WIDE ? 2 : 1];
+  band_estimate_body<WIDE, true>(g, fp, pp, b, rm, L);
+}
+
+// Band statistics with the kept sums, one workgroup per (camera, side, block).
+__global__ __launch_bounds__(kThreads) void k_motion_stats(Geo g, FramePtrs fp, PrevPtrs pp, Bufs b, Removal rm) {
+  __shared__ MotionLds L;
+  band_unit_motion_dispatch(g, fp, pp, b, rm, blockIdx.x, L, nullptr, nullptr, threadIdx.x);
+}
+
+// Removal fit or fallback of every (camera, side, block, channel) unit from
+// the band and kept sums in the caller's layout; the channel-0 thread of a
+// unit writes its method.
+__global__ __launch_bounds__(kThreads) void k_estimate_removal(Geo g, Bufs b, Removal rm) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= g.n_cams * 2 * g.n_blocks * kCS) return;
+  const int nb = g.n_blocks;
+  const int c = u % kCS, j = (u / kCS) % nb, s = (u / (kCS * nb)) & 1, k = u / (kCS * nb * 2);
+  if (!cam_active(g, k)) return;
+  const DevCam& cam = g.cams[k];
+  const int fc = cam.face_cam[s];
+  const int64_t uo = unit_index(k, s, j, 0, nb);
+  const int64_t uf = fc < 0 ? -1 : unit_index(fc, cam.face_side[s], j, 0, nb);
+  const uint64_t* own = b.band_sums + uo * 3;
+  const uint64_t* kown = rm.kept_sums + uo * 3;
+  const uint64_t* fac = uf < 0 ? nullptr : b.band_sums + uf * 3;
+  const uint64_t* kfac = uf < 0 ? nullptr : rm.kept_sums + uf * 3;
+  const int m = removal_method(own, fac, kown, kfac, rm.min_kept);
+  double p0 = b.params[(int64_t)u * 2], p1 = b.params[(int64_t)u * 2 + 1];
+  uint8_t v = b.valid[u];
+  removal_step(g, m, cam.channels, c, own + c * 3, fac ? fac + c * 3 : nullptr, kown + c * 3,
+               kfac ? kfac + c * 3 : nullptr, p0, p1, v);
+  b.params[(int64_t)u * 2] = p0;
+  b.params[(int64_t)u * 2 + 1] = p1;
+  b.valid[u] = v;
+  if (c == 0 && rm.method) rm.method[u / kCS] = (uint8_t)m;
 }
 
 // Seam blocks up to which the wide form is launched.
@@ -129,6 +198,28 @@ hipError_t launch_band_estimate(const Geo& g, const FramePtrs& fp, const Bufs& b
     hipLaunchKernelGGL(k_band_estimate<true>, dim3(blocks), dim3(2 * kThreads), 0, st, g, fp, b);
   else
     hipLaunchKernelGGL(k_band_estimate<false>, dim3(blocks), dim3(kThreads), 0, st, g, fp, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_band_estimate_removal(const Geo& g, const FramePtrs& fp, const PrevPtrs& pp, const Bufs& b,
+                                        const Removal& rm, hipStream_t st) {
+  const int blocks = g.n_cams * g.n_blocks;
+  if (blocks <= kWideSeamBlocks)
+    hipLaunchKernelGGL(k_band_estimate_removal<true>, dim3(blocks), dim3(2 * kThreads), 0, st, g, fp, pp, b, rm);
+  else
+    hipLaunchKernelGGL(k_band_estimate_removal<false>, dim3(blocks), dim3(kThreads), 0, st, g, fp, pp, b, rm);
+  return hipGetLastError();
+}
+
+hipError_t launch_motion_stats(const Geo& g, const FramePtrs& fp, const PrevPtrs& pp, const Bufs& b,
+                               const Removal& rm, hipStream_t st) {
+  hipLaunchKernelGGL(k_motion_stats, dim3(g.n_cams * 2 * g.n_blocks), dim3(kThreads), 0, st, g, fp, pp, b, rm);
+  return hipGetLastError();
+}
+
+hipError_t launch_estimate_removal(const Geo& g, const Bufs& b, const Removal& rm, hipStream_t st) {
+  const int total = g.n_cams * 2 * g.n_blocks * kCS;
+  hipLaunchKernelGGL(k_estimate_removal, dim3((total + kThreads - 1) / kThreads), dim3(kThreads), 0, st, g, b, rm);
   return hipGetLastError();
 }
 

@@ -11,6 +11,7 @@
 #include <string>
 #include <vector>
 
+#include "dev_motion.h"
 #include "rt_internal.h"
 #include "rt_surrogate_internal.h"
 
@@ -576,6 +577,90 @@ rt_status rt_ctx_tune(rt_ctx* ctx, int32_t tile_rows, int32_t grid) {
   if (e != hipSuccess) return hip_fail(e, "synchronize");
   if (tile_rows == ctx->tile_rows && grid == ctx->grid) return RT_OK;
   return build_tables(ctx, tile_rows, grid);
+}
+
+// ---------------------------------------------------------------------------
+// Object removal with the smoothing fallback (see ringcorr.h).
+// ---------------------------------------------------------------------------
+static rt_status check_removal(const rt_removal_opts* ro) {
+  if (!ro) return fail(RT_EINVAL, "removal options are NULL");
+  if (ro->tau < 0 || ro->tau > 255) return fail(RT_EINVAL, "tau %d outside 0..255", ro->tau);
+  if (!(ro->min_kept >= 0.0 && ro->min_kept <= 1.0)) return fail(RT_EINVAL, "min_kept must lie in [0, 1]");
+  return RT_OK;
+}
+
+static Removal make_removal(const rt_removal_opts* ro, uint64_t* kept_sums, uint8_t* method, bool has_prev) {
+  Removal rm;
+  memset(&rm, 0, sizeof rm);
+  rm.kept_sums = kept_sums;
+  rm.method = method;
+  rm.tau = ro->tau;
+  rm.has_prev = has_prev ? 1 : 0;
+  rm.min_kept = ro->min_kept;
+  return rm;
+}
+
+static PrevPtrs make_prev(const rt_ctx* ctx, const void* const* prev, uint64_t active) {
+  PrevPtrs pp;
+  memset(&pp, 0, sizeof pp);
+  for (int k = 0; prev && k < ctx->n_cams; ++k)
+    if ((active >> k) & 1ull) pp.in[k] = (const uint8_t*)prev[k];
+  return pp;
+}
+
+rt_status rt_motion_stats(rt_ctx* ctx, const void* const* frames, const void* const* prev_frames,
+                          const rt_removal_opts* ro, const rt_stats_buf* out, uint64_t* kept_sums, void* stream) {
+  if (!ctx) return fail(RT_EINVAL, "ctx is NULL");
+  rt_status r = check_frames(ctx, frames, "frames");
+  if (r == RT_OK && prev_frames) r = check_frames(ctx, prev_frames, "prev_frames");
+  if (r == RT_OK) r = check_removal(ro);
+  if (r == RT_OK) r = check_stats(out, true, false);
+  if (r == RT_OK) r = check_ptr(kept_sums, 8, "kept_sums");
+  if (r != RT_OK) return r;
+  const FramePtrs fp = make_ptrs(ctx, frames, nullptr);
+  const PrevPtrs pp = make_prev(ctx, prev_frames, ctx->geo.active);
+  const Removal rm = make_removal(ro, kept_sums, nullptr, prev_frames != nullptr);
+  hipError_t e = launch_motion_stats(ctx->geo, fp, pp, make_bufs(out, nullptr, nullptr), rm, (hipStream_t)stream);
+  return e == hipSuccess ? RT_OK : hip_fail(e, "motion statistics");
+}
+
+rt_status rt_estimate_removal(rt_ctx* ctx, const rt_stats_buf* stats, const uint64_t* kept_sums,
+                              const rt_removal_opts* ro, const rt_params_buf* state, uint8_t* method, void* stream) {
+  if (!ctx) return fail(RT_EINVAL, "ctx is NULL");
+  rt_status r = check_stats(stats, true, false);
+  if (r == RT_OK) r = check_removal(ro);
+  if (r == RT_OK) r = check_ptr(kept_sums, 8, "kept_sums");
+  if (r == RT_OK) r = check_params(state);
+  if (r != RT_OK) return r;
+  const Removal rm = make_removal(ro, const_cast<uint64_t*>(kept_sums), method, true);
+  hipError_t e = launch_estimate_removal(ctx->geo, make_bufs(stats, state, nullptr), rm, (hipStream_t)stream);
+  return e == hipSuccess ? RT_OK : hip_fail(e, "removal estimate");
+}
+
+rt_status rt_frameset_removal(rt_ctx* ctx, const void* const* frames, const void* const* prev_frames,
+                              void* const* out_frames, const rt_removal_opts* ro, const rt_stats_buf* stats,
+                              uint64_t* kept_sums, const rt_params_buf* state, const rt_lut_buf* lut,
+                              uint8_t* method, void* stream) {
+  if (!ctx) return fail(RT_EINVAL, "ctx is NULL");
+  const uint64_t active = ctx->geo.active;
+  rt_status r = check_frames_masked(ctx, active, frames, "frames");
+  if (r == RT_OK && prev_frames) r = check_frames_masked(ctx, active, prev_frames, "prev_frames");
+  if (r == RT_OK) r = check_frames_masked(ctx, active, (const void* const*)out_frames, "out_frames");
+  if (r == RT_OK) r = check_removal(ro);
+  if (r == RT_OK) r = check_stats(stats, true, true);
+  if (r == RT_OK) r = check_ptr(kept_sums, 8, "kept_sums");
+  if (r == RT_OK) r = check_params(state);
+  if (r == RT_OK) r = check_lut(lut);
+  if (r != RT_OK) return r;
+  hipStream_t st = (hipStream_t)stream;
+  const Geo& g = ctx->geo;
+  const FramePtrs fp = make_ptrs_masked(ctx, frames, out_frames, active);
+  const PrevPtrs pp = make_prev(ctx, prev_frames, active);
+  const Removal rm = make_removal(ro, kept_sums, method, prev_frames != nullptr);
+  const Bufs b = make_bufs(stats, state, lut);
+  const hipError_t e = launch_band_estimate_removal(g, fp, pp, b, rm, st);
+  if (e != hipSuccess) return hip_fail(e, "band statistics with object removal, estimate and tables");
+  return whole_pass(ctx, g, fp, b, true, false, st);
 }
 
 rt_status rt_graph_create(rt_ctx* ctx, const void* const* frames, void* const* out_frames, const rt_lut_buf* lut,

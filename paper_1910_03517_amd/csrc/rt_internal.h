@@ -143,6 +143,13 @@ hipError_t launch_build_lut(const Geo& g, const Bufs& b, hipStream_t st);
 hipError_t launch_apply(const Geo& g, const FramePtrs& fp, const Bufs& b, bool write, bool stats, hipStream_t st,
                         hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
 hipError_t launch_zero_whole(const Geo& g, const Bufs& b, hipStream_t st);
+struct PrevPtrs;
+struct Removal;
+hipError_t launch_band_estimate_removal(const Geo& g, const FramePtrs& fp, const PrevPtrs& pp, const Bufs& b,
+                                        const Removal& rm, hipStream_t st);
+hipError_t launch_motion_stats(const Geo& g, const FramePtrs& fp, const PrevPtrs& pp, const Bufs& b,
+                               const Removal& rm, hipStream_t st);
+hipError_t launch_estimate_removal(const Geo& g, const Bufs& b, const Removal& rm, hipStream_t st);
 hipError_t launch_stream_copy(void* dst, const void* src, int64_t bytes, int vec_bytes, hipStream_t st);
 
 }  // namespace rc

@@ -32,7 +32,9 @@ EXPORTED = ["rt_ctx_create", "rt_ctx_destroy", "rt_ctx_sizes", "rt_stats", "rt_e
             "rt_surrogate_features", "rt_estimate_new", "rt_surrogate_targets", "rt_surrogate_select",
             "rt_surrogate_frameset",
             "rt_mlp_forward", "rt_mlp_backward", "rt_mlp_adam", "rt_mlp_mse", "rt_gather_rows", "rt_mlp_train",
+            "rt_motion_stats", "rt_estimate_removal", "rt_frameset_removal",
             "rt_status_str", "rt_last_error"]
+RT_METHOD_NONE, RT_METHOD_REMOVAL, RT_METHOD_SMOOTHING = 0, 1, 2
 MLP_IN, MLP_HID, MLP_OUT = 576, 256, 6
 
 
@@ -79,6 +81,10 @@ class rt_mlp_work(ct.Structure):
 
 class rt_surrogate_work(ct.Structure):
     _fields_ = [(n, ct.c_void_p) for n in ("X", "H1", "H2", "Y", "p_new", "status", "used", "residual")]
+
+
+class rt_removal_opts(ct.Structure):
+    _fields_ = [("tau", ct.c_int32), ("reserved", ct.c_int32), ("min_kept", ct.c_double)]
 
 
 class RtError(RuntimeError):
@@ -147,6 +153,11 @@ def load(path: str = LIB_PATH) -> ct.CDLL:
     M = ct.POINTER(rt_mlp)
     lib.rt_mlp_train.argtypes = [M, M, M, M, P, P, ct.c_int32, P, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_float,
                                  ct.c_float, ct.c_float, ct.c_float, ct.POINTER(rt_mlp_work), P, P]
+    R = ct.POINTER(rt_removal_opts)
+    lib.rt_motion_stats.argtypes = [P, ct.POINTER(P), ct.POINTER(P), R, ct.POINTER(rt_stats_buf), P, P]
+    lib.rt_estimate_removal.argtypes = [P, ct.POINTER(rt_stats_buf), P, R, ct.POINTER(rt_params_buf), P, P]
+    lib.rt_frameset_removal.argtypes = [P, ct.POINTER(P), ct.POINTER(P), ct.POINTER(P), R, ct.POINTER(rt_stats_buf),
+                                        P, ct.POINTER(rt_params_buf), ct.POINTER(rt_lut_buf), P, P]
     lib.rt_graph_destroy.argtypes = [P]
     lib.rt_ctx_apply_times.argtypes = [P, ct.POINTER(ct.c_float), ct.c_int32, ct.POINTER(ct.c_int32)]
     for name in EXPORTED:
@@ -475,6 +486,39 @@ def rt_ctx_set_active(ctx, active: int) -> None:
     _check(load().rt_ctx_set_active(ctx, ct.c_uint64(active)))
 
 
+def _removal(tau: int, min_kept: float) -> rt_removal_opts:
+    return rt_removal_opts(int(tau), 0, float(min_kept))
+
+
+def rt_motion_stats(ctx, frames, prev_frames, tau, min_kept, band_hist, band_sums, kept_sums, stream=None) -> None:
+    ro = _removal(tau, min_kept)
+    sb = rt_stats_buf(_p(band_hist), _p(band_sums), None, None)
+    pf = None if prev_frames is None else _ptr_array(prev_frames)
+    _check(load().rt_motion_stats(ctx, _ptr_array(frames), pf, ct.byref(ro), ct.byref(sb), _p(kept_sums),
+                                  _stream_handle(stream)))
+
+
+def rt_estimate_removal(ctx, band_hist, band_sums, kept_sums, tau, min_kept, params, valid, method=None,
+                        stream=None) -> None:
+    ro = _removal(tau, min_kept)
+    sb = rt_stats_buf(_p(band_hist), _p(band_sums), None, None)
+    pb = rt_params_buf(_p(params), _p(valid))
+    _check(load().rt_estimate_removal(ctx, ct.byref(sb), _p(kept_sums), ct.byref(ro), ct.byref(pb), _p(method),
+                                      _stream_handle(stream)))
+
+
+def rt_frameset_removal(ctx, frames, prev_frames, out_frames, tau, min_kept, bufs: "Buffers", kept_sums,
+                        method=None, stream=None) -> None:
+    ro = _removal(tau, min_kept)
+    sb = rt_stats_buf(_p(bufs.band_hist), _p(bufs.band_sums), _p(bufs.whole_hist), _p(bufs.whole_sums))
+    pb = rt_params_buf(_p(bufs.params), _p(bufs.valid))
+    lb = rt_lut_buf(_p(bufs.lut8), _p(bufs.q16), _p(bufs.weights))
+    pf = None if prev_frames is None else _ptr_array(prev_frames)
+    _check(load().rt_frameset_removal(ctx, _ptr_array(frames), pf, _ptr_array(out_frames), ct.byref(ro),
+                                      ct.byref(sb), _p(kept_sums), ct.byref(pb), ct.byref(lb), _p(method),
+                                      _stream_handle(stream)))
+
+
 # ----------------------------------------------------------------------------- convenience
 
 @dataclass(frozen=True)
@@ -619,6 +663,14 @@ class Rig:
 
     def frameset(self, frames, out_frames, stream=None) -> None:
         rt_frameset(self.ctx, frames, out_frames, self.bufs, stream)
+
+    def frameset_removal(self, frames, prev_frames, out_frames, kept_sums, method=None, tau: int = 20,
+                         min_kept: float = 0.25, stream=None) -> None:
+        """Frame-set with object removal against prev_frames (None: nothing moves)
+        and the smoothing fallback; kept_sums int64 [K][2][NB][3][3], method
+        uint8 [K][2][NB] (may be None)."""
+        rt_frameset_removal(self.ctx, frames, prev_frames, out_frames, tau, min_kept, self.bufs, kept_sums, method,
+                            stream)
 
     def frameset_batch(self, active: int, frames, out_frames, stream=None) -> None:
         """Frame-set of the cameras in bitmask `active` (whole rings); the

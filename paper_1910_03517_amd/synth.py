@@ -147,12 +147,52 @@ def cut(pano: np.ndarray, widths: list[int]) -> list[np.ndarray]:
     return out
 
 
+@dataclass(frozen=True)
+class MovingObject:
+    """A textured rectangle (a vehicle seen from the tower) moving along the
+    panorama of one ring: its left edge is at x0 + speed * frame (periodic in
+    x), rows [y0, y0 + h), colour rgb plus a seeded stripe pattern."""
+    x0: float
+    y0: int
+    w: int
+    h: int
+    speed: float
+    rgb: tuple = (235.0, 40.0, 30.0)
+    ring: int = 0
+
+    def draw(self, pano: np.ndarray, frame: int) -> None:
+        H, W = pano.shape[:2]
+        x = int(round(self.x0 + self.speed * frame)) % W
+        cols = (np.arange(self.w) + x) % W
+        rows = np.arange(self.y0, min(self.y0 + self.h, H))
+        stripes = (np.arange(self.w) // 8) % 2 * 25.0
+        for c in range(min(3, pano.shape[2])):
+            patch = np.clip(self.rgb[c] - stripes[None, :] + np.zeros((rows.size, 1)), 0, 255)
+            pano[np.ix_(rows, cols, [c])] = np.rint(patch)[:, :, None].astype(pano.dtype)
+
+
+def seam_crossing(rig: RigSpec, cam_pos: int = 0, speed: float = 24.0, frames: int = 12,
+                  rows=(0.62, 0.70), width_frac: float = 0.08) -> MovingObject:
+    """An object that crosses the seam between ring-0 positions cam_pos and
+    cam_pos + 1 in the ground region, half way through `frames` frames."""
+    cams = sorted((c for c in rig.cams if c.ring == 0), key=lambda c: c.pos)
+    seam = sum(c.width for c in cams[:cam_pos + 1])
+    h = cams[0].height
+    w = max(4, int(round(width_frac * cams[0].width)))
+    y0 = int(rows[0] * h)
+    return MovingObject(x0=seam - w / 2 - speed * frames / 2, y0=y0, w=w, h=max(2, int((rows[1] - rows[0]) * h)),
+                        speed=speed)
+
+
 def rig_frames(rig: RigSpec, frame: int = 0, drift: bool = False, seed: int = 0,
-               gamma: bool = False, no_clip: bool = False, distortion: bool = True) -> list[np.ndarray]:
+               gamma: bool = False, no_clip: bool = False, distortion: bool = True,
+               objects: tuple = (), noise_sigma: float = 4.0) -> list[np.ndarray]:
     """Distorted frames of every camera of `rig` for frame index `frame`.
 
     Gains are drawn once per (rig, seed); with drift they vary smoothly over
-    a 300-frame period.  Scene noise is redrawn for every frame.
+    a 300-frame period.  Scene noise is redrawn for every frame.  `objects`
+    (MovingObject) are drawn into their ring's panorama before it is cut and
+    distorted.
     """
     frames: list[np.ndarray | None] = [None] * len(rig.cams)
     for ring in rig.rings:
@@ -163,9 +203,12 @@ def rig_frames(rig: RigSpec, frame: int = 0, drift: bool = False, seed: int = 0,
         widths = [c.width for c in cams]
         rng = _rng(rig.config_id, seed, frame, ring)
         if cams[0].bit_depth == 8:
-            pano = scene_rgb(h, sum(widths), rng, no_clip=no_clip)
+            pano = scene_rgb(h, sum(widths), rng, noise_sigma=noise_sigma, no_clip=no_clip)
         else:
             pano = scene_ir(h, sum(widths), rng)
+        for ob in objects:
+            if ob.ring == ring and cams[0].bit_depth == 8:
+                ob.draw(pano, frame)
         parts = cut(pano, widths)
         if cams[0].channels == 1 and parts[0].shape[2] == 3:
             parts = [p[:, :, :1].copy() for p in parts]
