@@ -404,7 +404,6 @@ def plain_leg(args, rig_spec, steps: int, warmup: int, timing_every: int):
     Returns (rig, report, ins, outs, base)."""
     import torch
     from paper_1910_03517_amd import rt, synth
-    from paper_1910_03517_amd.pipeline import LutSet, Pipeline, WholeSet
 
     cams = [rt.Camera(c.width, c.height, c.channels, c.bit_depth, c.ring, c.pos).with_pitch() for c in rig_spec.cams]
     px = sum(c.width * c.height for c in cams)
@@ -432,16 +431,16 @@ def plain_leg(args, rig_spec, steps: int, warmup: int, timing_every: int):
         # multiple of depth that apply starts only after the earlier one ended.
         assert max(args.lanes, args.group) <= args.depth and args.nbuf % args.depth == 0, \
             "need lanes, group <= depth and depth | nbuf"
-        pipe = Pipeline(rig, depth=args.depth, lanes=args.lanes, group=args.group)
+        pipe = rt.Pipe.for_rig(rig, depth=args.depth, lanes=args.lanes, group=args.group)
         in_ptrs = [rt.ptr_array(x) for x in ins]
         out_ptrs = [rt.ptr_array(x) for x in outs]
     elif args.mode == "graph":
-        whole = WholeSet(rig.sizes)
-        graphs = [rt.Graph(rig.ctx, ins[i], outs[i], LutSet(rig.sizes), whole, b) for i in range(args.nbuf)]
+        whole = rt.WholeSet(rig.sizes)
+        graphs = [rt.Graph(rig.ctx, ins[i], outs[i], rt.LutSet(rig.sizes), whole, b) for i in range(args.nbuf)]
     elif args.mode == "graph-pipelined":
         assert args.nbuf % 2 == 0
-        luts = [LutSet(rig.sizes) for _ in range(2)]
-        wholes = [WholeSet(rig.sizes) for _ in range(2)]
+        luts = [rt.LutSet(rig.sizes) for _ in range(2)]
+        wholes = [rt.WholeSet(rig.sizes) for _ in range(2)]
         rt.rt_stats(rig.ctx, ins[0], b.band_hist, b.band_sums)
         rt.rt_estimate(rig.ctx, b.band_hist, b.band_sums, b.params, b.valid)
         rt.rt_build_lut(rig.ctx, b.params, b.valid, luts[0].lut8, luts[0].q16, luts[0].weights)

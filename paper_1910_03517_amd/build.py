@@ -32,9 +32,9 @@ CFLAGS = [
 ]
 
 
-def _compile(src: str, build_dir: str = BUILD, defines: tuple = ()) -> str:
+def _compile(src: str, build_dir: str = BUILD, defines: tuple = (), extra: tuple = ()) -> str:
     obj = os.path.join(build_dir, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *CFLAGS, *[f"-D{d}" for d in defines], "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *CFLAGS, *extra, *[f"-D{d}" for d in defines], "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{r.stdout}\n{r.stderr}")
@@ -44,16 +44,19 @@ def _compile(src: str, build_dir: str = BUILD, defines: tuple = ()) -> str:
     return obj
 
 
-def build(verbose: bool = True, out: str = LIB, build_dir: str = BUILD, defines: tuple = ()) -> str:
+def build(verbose: bool = True, out: str = LIB, build_dir: str = BUILD, defines: tuple = (),
+          extra: tuple = (), link_extra: tuple = ()) -> str:
     """Compile every HIP source for gfx950 and link libringcorr.so; returns its path.
 
     `defines` (NAME=VALUE strings) override compile-time kernel parameters; the
-    defaults are the tuned ones."""
+    defaults are the tuned ones.  `extra` / `link_extra` are further compiler /
+    linker flags (the host-sanitizer build of the tests passes its
+    host-only instrumentation here)."""
     os.makedirs(build_dir, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
-        objs = list(ex.map(lambda s: _compile(s, build_dir, defines), SOURCES))
+        objs = list(ex.map(lambda s: _compile(s, build_dir, defines, extra), SOURCES))
     tmp = out + ".tmp"
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *link_extra, "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")

@@ -231,14 +231,51 @@ def rt_ctx_tuning(ctx) -> tuple[int, int, int]:
     return a.value, b.value, c.value
 
 
+class LutSet:
+    """One slot of tables (lut8, q16, weights) of a context's sizes."""
+
+    def __init__(self, sizes: rt_sizes, device="cuda"):
+        import torch
+        K, NB, WM = sizes.n_cams, sizes.n_blocks, max(sizes.w_max, 1)
+        self.lut8 = torch.zeros((K, 2, NB, CSLOTS, NBINS), dtype=torch.uint8, device=device)
+        self.q16 = torch.zeros((K, 2, NB, CSLOTS, 2), dtype=torch.int64, device=device)
+        self.weights = torch.zeros((K, WM), dtype=torch.int16, device=device)
+
+
+class WholeSet:
+    """One slot of whole-frame statistics (whole_hist, whole_sums) of a context's sizes."""
+
+    def __init__(self, sizes: rt_sizes, device="cuda"):
+        import torch
+        K = sizes.n_cams
+        self.whole_hist = torch.zeros((K, CSLOTS, NBINS), dtype=torch.int32, device=device)
+        self.whole_sums = torch.zeros((K, CSLOTS, 3), dtype=torch.int64, device=device)
+
+
 class Pipe:
-    """rt_pipe: statistics and estimates on the pipeline's stream, applies
+    """rt_pipe, the frame-set pipeline: per frame-set the kernels of
+    rt_frameset, split over HIP streams by the library.  The band statistics,
+    estimate and tables of consecutive frame-sets run in order on the
+    pipeline's own stream, ahead of the bandwidth-bound applies, which go
     round-robin over `lanes` streams (the caller's first), issued `group`
-    frame-sets at a time.
+    frame-sets at a time, so that the estimate of frame-set t+1 overlaps the
+    apply of t and, with lanes > 1, consecutive applies overlap each other.
+    Tables and whole-frame statistics rotate over `depth` slots (>= lanes,
+    >= group); band statistics and the estimator state are single buffers,
+    so the results are exactly those of consecutive rt_frameset calls.  Call
+    join() before depending on the results of submitted frame-sets.
 
     luts / wholes are sequences of `depth` objects with lut8, q16, weights /
     whole_hist, whole_sums tensors; bufs provides band_hist, band_sums,
-    params, valid."""
+    params, valid.  Pipe.for_rig allocates the slots of a Rig."""
+
+    @classmethod
+    def for_rig(cls, rig: "Rig", depth: int = 2, lanes: int = 1, group: int = 1) -> "Pipe":
+        luts = [LutSet(rig.sizes, rig.device) for _ in range(depth)]
+        wholes = [WholeSet(rig.sizes, rig.device) for _ in range(depth)]
+        p = cls(rig.ctx, rig.bufs, luts, wholes, lanes=lanes, group=group)
+        p.luts, p.whole = luts, wholes
+        return p
 
     def __init__(self, ctx, bufs, luts, wholes, lanes: int = 1, group: int = 1):
         depth = len(luts)

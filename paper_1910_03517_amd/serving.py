@@ -64,6 +64,7 @@ class Request:
     status: str = "queued"       # queued, admitted, running, done, failed, expired, rejected
     out: Any = None              # output frames from the pool while admitted
     error: str = ""
+    ready: Any = None            # device event after which the frames are written (None: already written)
 
     @property
     def latency(self) -> float:
@@ -143,12 +144,15 @@ class Server:
         self._stop = threading.Event()
 
     # ------------------------------------------------------------------ producers
-    def submit(self, rig: int, frames, t_arrival: float | None = None) -> Request:
-        """Queue one frame-set of `rig` (thread-safe)."""
+    def submit(self, rig: int, frames, t_arrival: float | None = None, ready=None) -> Request:
+        """Queue one frame-set of `rig` (thread-safe).  `ready` is an event of
+        the frames' producer (e.g. a decoder stream), recorded after it wrote
+        them: the device work of this frame-set waits for it.  Without one the
+        frames must already be complete."""
         if not 0 <= rig < self.b.n_rigs:
             raise ValueError(f"rig {rig} outside 0..{self.b.n_rigs - 1}")
         with self._lock:
-            req = Request(rig, self._seq[rig], frames, self.clock() if t_arrival is None else t_arrival)
+            req = Request(rig, self._seq[rig], frames, self.clock() if t_arrival is None else t_arrival, ready=ready)
             self._seq[rig] += 1
             if rig in self.closed_rigs or self.broken is not None:
                 req.status, req.error = "rejected", "rig closed" if rig in self.closed_rigs else "server stopped"
@@ -377,8 +381,7 @@ class GpuBackend(Backend):
         self._pixels = [sum(cams[i].width * cams[i].height for i in ids) for ids in self.idx]
         self.pipe = None
         if lanes > 1 and surrogate is None:
-            from .pipeline import Pipeline
-            self.pipe = Pipeline(self.rig, depth=depth, lanes=lanes, group=1)
+            self.pipe = rt.Pipe.for_rig(self.rig, depth=depth, lanes=lanes, group=1)
 
     def frameset_bytes(self, rig: int) -> int:
         return self._bytes[rig]
@@ -421,9 +424,21 @@ class GpuBackend(Backend):
             for n, i in enumerate(self.idx[req.rig]):
                 frames[i], outs[i] = req.frames[n], req.out[n]
         st = self.stream
+        # The frames' producers: the launch stream waits for every ready event
+        # (the pipeline's statistics stream waits for one event recorded after
+        # those waits).
+        ready = [req.ready for req in batch if req.ready is not None]
+        for e in ready:
+            st.wait_event(e)
         ev = self.torch.cuda.Event()
         if self.pipe is not None:
-            self.pipe.submit_batch(mask, frames, outs, st, done_event=ev)
+            merged = None
+            if len(ready) == 1:
+                merged = ready[0]
+            elif ready:
+                merged = self.torch.cuda.Event()
+                merged.record(st)
+            self.pipe.submit_batch(mask, frames, outs, st, ready_event=merged, done_event=ev)
             return ev
         if self.surrogate is None:
             self.rig.frameset_batch(mask, frames, outs, st)

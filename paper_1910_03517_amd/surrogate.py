@@ -15,6 +15,7 @@ computation runs in the library's kernels.
 """
 from __future__ import annotations
 
+import json
 import os
 from dataclasses import dataclass, field
 
@@ -192,21 +193,36 @@ class Trainer:
         return float(torch.stack(losses).mean().item()) if losses else float("nan")
 
     def save(self, path: str) -> None:
+        """Checkpoint: weights, Adam moments, step count, learning rate, batch
+        size and the state of the mini-batch permutation generator, so that
+        training resumed from it continues bit for bit as it would have."""
         arr = {}
         for tag, t in (("w", self.w), ("m", self.m), ("v", self.v)):
             for k, v in t.host().items():
                 arr[f"{tag}_{k}"] = v
-        arr["step"] = np.array(self.step)
+        arr["step"] = np.array(self.step, np.int64)
+        arr["lr"] = np.array(self.lr, np.float64)
+        arr["batch"] = np.array(self.batch, np.int64)
+        arr["rng_state"] = np.array(json.dumps(self.rng.bit_generator.state))
         os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
         np.savez(path, **arr)
 
     def load(self, path: str) -> None:
+        """Restore a checkpoint written by save (plain arrays and a JSON
+        string; nothing in the file is executed)."""
         import torch
         with np.load(path, allow_pickle=False) as z:
+            if int(z["batch"]) != self.batch:
+                raise ValueError(f"checkpoint batch {int(z['batch'])} differs from the trainer's {self.batch}")
             for tag, t in (("w", self.w), ("m", self.m), ("v", self.v)):
                 for k in rt.MlpTensors.NAMES:
                     getattr(t, k).copy_(torch.as_tensor(z[f"{tag}_{k}"], device=self.device))
             self.step = int(z["step"])
+            self.lr = float(z["lr"])
+            state = json.loads(str(z["rng_state"]))
+        rng = np.random.default_rng()
+        rng.bit_generator.state = state
+        self.rng = rng
 
 
 def predict(w: rt.MlpTensors, X, device="cuda"):

@@ -192,14 +192,13 @@ def test_pipe_submit_batch_validation():
     """rt_pipe_submit_batch rejects an empty mask, a mask that splits a ring,
     and a completion event on a pipeline that issues applies in groups; a
     rejected call enqueues nothing and the pipeline stays usable."""
-    from paper_1910_03517_amd.pipeline import Pipeline
     spec = three_rings()
     cams = rt_cams(spec.cams)
     rig = rt.Rig(cams, rt.Options(n_blocks=2))
     dev = rig.alloc_frames()
     out = rig.alloc_frames()
     ring0 = cam_mask(ring_indices(spec, 0))
-    grouped = Pipeline(rig, depth=4, lanes=2, group=2)
+    grouped = rt.Pipe.for_rig(rig, depth=4, lanes=2, group=2)
     for bad, needle in [(0, "empty"), (ring0 & ~1, "ring")]:
         with pytest.raises(rt.RtError, match=needle):
             grouped.submit_batch(bad, dev, out)
@@ -208,7 +207,7 @@ def test_pipe_submit_batch_validation():
     grouped.submit_batch(ring0, dev, out)
     grouped.join()
     grouped.close()
-    single = Pipeline(rig, depth=2, lanes=2, group=1)
+    single = rt.Pipe.for_rig(rig, depth=2, lanes=2, group=1)
     done = torch.cuda.Event()
     single.submit_batch(ring0, [d if (ring0 >> i) & 1 else None for i, d in enumerate(dev)],
                         [o if (ring0 >> i) & 1 else None for i, o in enumerate(out)], done_event=done)

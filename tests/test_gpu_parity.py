@@ -179,11 +179,10 @@ def pipeline_vs_oracle(spec, n, label):
     applies issued 3 frame-sets at a time, the last group partial): every
     output against the oracle's frame-set sequence, the last two frame-sets'
     whole-frame statistics and the final state bitwise."""
-    from paper_1910_03517_amd.pipeline import Pipeline
     cams = rt_cams(spec.cams)
     opts = rt.Options(smoothing=True)
     rig = rt.Rig(cams, opts)
-    pipe = Pipeline(rig, depth=8, lanes=3, group=3)
+    pipe = rt.Pipe.for_rig(rig, depth=8, lanes=3, group=3)
     frames = [synth.rig_frames(spec, t, drift=True) for t in range(n)]
     dev = [rig.upload(f) for f in frames]
     outs = [rig.alloc_frames() for _ in range(n)]
@@ -330,14 +329,13 @@ def test_pipeline_matches_sequential_framesets(depth, lanes, group):
     time, `depth` slots reused over 11 frame-sets, the last group partial)
     gives the results of consecutive rt_frameset calls, bit for bit
     (smoothing mode, drifting gains)."""
-    from paper_1910_03517_amd.pipeline import Pipeline
     say(f"case: pipeline depth {depth} lanes {lanes} group {group} vs sequential, 4x 480x200 rgb8, 11 frame-sets")
     spec = synth.RigSpec("pipe 4x480x200", 11, [synth.CamSpec(480, 200, 3, 8, 0, p) for p in range(4)])
     cams = rt_cams(spec.cams)
     opts = rt.Options(n_blocks=8, band_width=16, smoothing=True)
     seq = rt.Rig(cams, opts)
     par = rt.Rig(cams, opts)
-    pipe = Pipeline(par, depth=depth, lanes=lanes, group=group)
+    pipe = rt.Pipe.for_rig(par, depth=depth, lanes=lanes, group=group)
     T = 11
     frames_t = [synth.rig_frames(spec, t, drift=True) for t in range(T)]
     dev = [seq.upload(f) for f in frames_t]
@@ -371,14 +369,13 @@ def test_pipeline_caller_stream_changes():
     (3 lanes, 6 slots, 8 frame-sets): a stream change issues the pending
     applies on their own stream first, and the outputs and final state equal
     consecutive rt_frameset calls bit for bit."""
-    from paper_1910_03517_amd.pipeline import Pipeline
     say("case: pipeline 3 lanes, depth 6, group 3, caller stream alternating, 4x 480x200 rgb8, 8 frame-sets")
     spec = synth.RigSpec("pipe streams 4x480x200", 12, [synth.CamSpec(480, 200, 3, 8, 0, p) for p in range(4)])
     cams = rt_cams(spec.cams)
     opts = rt.Options(n_blocks=8, band_width=16, smoothing=True)
     seq = rt.Rig(cams, opts)
     par = rt.Rig(cams, opts)
-    pipe = Pipeline(par, depth=6, lanes=3, group=3)
+    pipe = rt.Pipe.for_rig(par, depth=6, lanes=3, group=3)
     T = 8
     dev = [seq.upload(synth.rig_frames(spec, t, drift=True)) for t in range(T)]
     outs_p = [par.alloc_frames() for _ in range(T)]
@@ -408,7 +405,6 @@ def test_pipeline_mixed_rings_matches_sequential():
     smoothing; every output and the final state equal consecutive rt_frameset
     calls, and the last frame-sets' whole-frame statistics and tables equal
     theirs."""
-    from paper_1910_03517_amd.pipeline import Pipeline
     say("case: pipeline mixed rings, 3 lanes, depth 6, group 3, 7 frame-sets")
     cams_spec = ([synth.CamSpec(200, 90, 3, 8, 0, p) for p in (1, 0, 2)]
                  + [synth.CamSpec(120, 64, 1, 16, 4, p) for p in (1, 0)]
@@ -418,7 +414,7 @@ def test_pipeline_mixed_rings_matches_sequential():
     seq = rt.Rig(cams, opts)
     par = rt.Rig(cams, opts)
     depth = 6
-    pipe = Pipeline(par, depth=depth, lanes=3, group=3)
+    pipe = rt.Pipe.for_rig(par, depth=depth, lanes=3, group=3)
     rng = np.random.default_rng(21)
     T = 7
     frames_t = [[synth.tiny_frame(c.height, c.width, c.channels, c.bit_depth, rng) for c in cams_spec]
@@ -453,14 +449,13 @@ def test_pipeline_waits_for_ready_event():
     """Frames written on a side stream right before each submit, ordered
     only by the ready event the submit passes: the results equal consecutive
     rt_frameset calls on the same frames."""
-    from paper_1910_03517_amd.pipeline import Pipeline
     say("case: pipeline ready_event, 3 lanes, 4x 480x200 rgb8, 7 frame-sets")
     spec = synth.RigSpec("pipe 4x480x200", 13, [synth.CamSpec(480, 200, 3, 8, 0, p) for p in range(4)])
     cams = rt_cams(spec.cams)
     opts = rt.Options(n_blocks=8, band_width=16, smoothing=True)
     seq = rt.Rig(cams, opts)
     par = rt.Rig(cams, opts)
-    pipe = Pipeline(par, depth=6, lanes=3, group=3)
+    pipe = rt.Pipe.for_rig(par, depth=6, lanes=3, group=3)
     T = 7
     frames_t = [synth.rig_frames(spec, t, drift=True) for t in range(T)]
     src = [seq.upload(f) for f in frames_t]          # device copies, written once
@@ -490,13 +485,12 @@ def test_pipeline_waits_for_ready_event():
 
 
 def test_pipeline_rejects_bad_lanes_and_groups():
-    from paper_1910_03517_amd.pipeline import LutSet, WholeSet
     spec = synth.RigSpec("pipe 2x64x32", 12, [synth.CamSpec(64, 32, 3, 8, 0, p) for p in range(2)])
     rig = rt.Rig(rt_cams(spec.cams), rt.Options(n_blocks=2, band_width=8))
     for depth, lanes, group, needle in [(2, 0, 1, "lanes"), (4, 5, 1, "lanes"), (2, 3, 1, "below"),
                                         (2, 1, 0, "group"), (2, 1, 3, "group")]:
-        luts = [LutSet(rig.sizes) for _ in range(depth)]
-        wholes = [WholeSet(rig.sizes) for _ in range(depth)]
+        luts = [rt.LutSet(rig.sizes) for _ in range(depth)]
+        wholes = [rt.WholeSet(rig.sizes) for _ in range(depth)]
         with pytest.raises(rt.RtError, match=needle):
             rt.Pipe(rig.ctx, rig.bufs, luts, wholes, lanes=lanes, group=group)
     rig.close()
@@ -521,7 +515,6 @@ def test_graph_replays_match_eager(pipelined):
     """Captured frame-set graphs, replayed over a cycle of 4 input buffers for 8
     steps with eager torch work and synchronizations between replays: every
     replay equals the eager rt_frameset result of the same step."""
-    from paper_1910_03517_amd.pipeline import LutSet, WholeSet
     say(f"case: graph replay pipelined={pipelined}, 3x352x144 rgb8 + 2x96x64 u12")
     spec = synth.RigSpec("graph", 12, [synth.CamSpec(352, 144, 3, 8, 0, p) for p in range(3)]
                          + [synth.CamSpec(96, 64, 1, 12, 1, p) for p in range(2)])
@@ -533,8 +526,8 @@ def test_graph_replays_match_eager(pipelined):
     torch.cuda.synchronize()
     order = [t % 4 for t in range(8)]
     eager = _eager_sequence(cams, opts, dev, order)
-    luts = [LutSet(rig.sizes) for _ in range(2)]
-    whole = WholeSet(rig.sizes)
+    luts = [rt.LutSet(rig.sizes) for _ in range(2)]
+    whole = rt.WholeSet(rig.sizes)
     out = rig.alloc_frames()
     b = rig.bufs
     if pipelined:

@@ -51,7 +51,12 @@ def host_out(cams, outs):
     return res
 
 
-def serve(surrogate=None, lanes=1):
+def serve(surrogate=None, lanes=1, producer=False):
+    """Every frame-set of every rig through the server.  producer: the input
+    frames start out zero and are written by a separate producer stream (a
+    stand-in for a decoder) behind some delaying work; each request carries
+    the event recorded after its write, and the server's device work must
+    wait for it."""
     backend = GpuBackend(RIGS, OPTS, surrogate=surrogate, lanes=lanes)
     results = {}
 
@@ -63,14 +68,32 @@ def serve(surrogate=None, lanes=1):
                  max_batches_in_flight=2, on_done=on_done)
     inputs = {}
     order = [(r, t) for t in range(max(N_PER_RIG)) for r in range(3) if t < N_PER_RIG[r]]
+    staged = {}
     for r, t in order:
         cams = [backend.cams[i] for i in backend.idx[r]]
         inputs[(r, t)] = to_device(cams, rig_frames(r, t))
+        if producer:
+            staged[(r, t)] = inputs[(r, t)]
+            inputs[(r, t)] = [torch.zeros_like(d) for d in staged[(r, t)]]
     torch.cuda.synchronize()                     # the backend's streams do not wait for this one
+    ready = {}
+    if producer:
+        ps = torch.cuda.Stream()
+        busy = torch.rand((2048, 2048), device="cuda")
+        with torch.cuda.stream(ps):
+            for r, t in order:
+                for _ in range(4):
+                    busy = busy @ busy
+                    busy = busy / busy.abs().amax()
+                for d, src in zip(inputs[(r, t)], staged[(r, t)]):
+                    d.copy_(src)
+                ev = torch.cuda.Event()
+                ev.record(ps)
+                ready[(r, t)] = ev
     # Everything arrives before the first scheduling pass, so launches carry
     # one frame-set of every rig that still has one (batches of 3, 3, 3, 2, 1).
     for r, t in order:
-        req = srv.submit(r, inputs[(r, t)])
+        req = srv.submit(r, inputs[(r, t)], ready=ready.get((r, t)))
         assert req.seq == t
     srv.drain(timeout=60)
     rep = srv.report()
@@ -81,12 +104,14 @@ def serve(surrogate=None, lanes=1):
     return results
 
 
-@pytest.mark.parametrize("lanes", [1, 2])
-def test_serving_mix_matches_oracle_and_alone(lanes):
+@pytest.mark.parametrize("lanes,producer", [(1, False), (2, False), (1, True), (2, True)])
+def test_serving_mix_matches_oracle_and_alone(lanes, producer):
     """lanes 1: one rt_frameset_batch per batch on one stream; lanes 2: the
-    batches through the frame-set pipeline, consecutive ones overlapping."""
-    say(f"case: serving plain, 3 rigs, {lanes} lanes")
-    results = serve(lanes=lanes)
+    batches through the frame-set pipeline, consecutive ones overlapping.
+    producer: the frames are written by another stream, ordered by the
+    requests' ready events."""
+    say(f"case: serving plain, 3 rigs, {lanes} lanes, producer stream {producer}")
+    results = serve(lanes=lanes, producer=producer)
     for r in range(3):
         cams = rt_cams(RIGS[r])
         co, oo = oracle_cams(cams), oracle_opts(OPTS)

@@ -402,3 +402,31 @@ def test_fused_frameset_validation():
         rt.rt_surrogate_frameset(rig.ctx, w, 0.1, dev, out, rig.bufs, rig.bufs.whole_hist, bad)
     rig.check()
     rig.close()
+
+
+def test_training_resumes_bit_exact_from_checkpoint(tmp_path):
+    """Two epochs, a checkpoint, one more epoch; a fresh trainer loaded from
+    the checkpoint runs the third epoch to the same weights, moments, step
+    and loss, bit for bit."""
+    say("case: checkpoint resume, 3 epochs of 4 batches")
+    rng = np.random.default_rng(12)
+    n = 4 * 64 + 9
+    X = torch.as_tensor(rng.uniform(0, 2, (n, 576)).astype(np.float32), device="cuda")
+    T = torch.as_tensor(rng.normal(1, 0.3, (n, 6)).astype(np.float32), device="cuda")
+    data = su.Dataset(X, T)
+    a = su.Trainer(synth.mlp_init(3), lr=3e-3, batch=64, seed=8)
+    a.epoch(data)
+    a.epoch(data)
+    path = str(tmp_path / "ckpt.npz")
+    a.save(path)
+    la = a.epoch(data)
+    b = su.Trainer(synth.mlp_init(4), lr=1e-2, batch=64, seed=99)
+    b.load(path)
+    lb = b.epoch(data)
+    torch.cuda.synchronize()
+    assert a.step == b.step == 12
+    assert la == lb
+    for x, y in ((a.w, b.w), (a.m, b.m), (a.v, b.v)):
+        hx, hy = x.host(), y.host()
+        for k in rt.MlpTensors.NAMES:
+            assert np.array_equal(hx[k], hy[k]), k

@@ -60,6 +60,7 @@ class FakeBackend(Backend):
         if self.device_error:
             raise RuntimeError("device lost")
         self.launches.append([(r.rig, r.seq) for r in batch])
+        self.ready_seen = getattr(self, "ready_seen", []) + [r.ready for r in batch]
         start = max(self.clock(), self.stream_free_at)
         self.stream_free_at = start + self.duration
         self.outstanding += 1
@@ -258,3 +259,14 @@ def test_threaded_run_with_arrival_thread():
     for r in range(3):
         assert launched_order(fake, r) == list(range(20))
     assert srv.mem_peak <= 1000
+
+
+def test_ready_events_reach_the_backend():
+    """A producer's ready event travels with its request to the launch."""
+    clock = Clock()
+    fake = FakeBackend(2, clock)
+    srv = Server(fake, mem_budget=10_000, clock=clock)
+    srv.submit(0, ["a"], ready="ev-a")
+    srv.submit(1, ["b"])
+    run_until_idle(srv, clock)
+    assert sorted(fake.ready_seen, key=str) == [None, "ev-a"]
