@@ -44,6 +44,13 @@ R-weight  h = floor(W / 2); left column col < h has Q8 weight
           odd width has weight 0.
 R-apply   y = ((256 - w) x + w f(x) + 128) >> 8, i.e. the exact convex
           combination rounded half up.
+R-seam    seam gradient cost (section 4.2): box means of factor x factor
+          blocks, the two box columns on each side of the seam aligned with
+          it, Euclidean norm over the channels in sample units; the interior
+          reference is the same cost at a virtual seam at column floor(W/2).
+R-seam-rows  the rows of a seam are the boxes of the shorter image from the
+          top; with no row, or an image narrower than two boxes, the cost is
+          undefined (NaN).
 
 Every floating-point step is one IEEE binary64 operation on Python floats
 (no fused multiply-add), so the result is reproducible to the last bit.
@@ -540,23 +547,67 @@ def box_downsample(img: np.ndarray, factor: int, from_right: bool) -> np.ndarray
     return sub.reshape(r, factor, cc, factor, img.shape[2]).mean(axis=(1, 3))
 
 
-def seam_cost(left: np.ndarray, right: np.ndarray, factor: int = 8) -> float:
-    """Mean over rows of (d+ + d-)/2 for the seam between `left` and `right`.
+def seam_row_costs(left: np.ndarray, right: np.ndarray, factor: int = 8) -> np.ndarray:
+    """(d+ + d-)/2 for every downsampled row of the seam between `left` and `right`.
 
     d+ = |(I+_1 - I+_0) - (I+_0 - I-_0)|, d- = |(I-_-1 - I-_0) - (I-_0 - I+_0)|,
     with |.| the Euclidean norm over the colour channels, after box
-    downsampling by `factor` in both directions.
+    downsampling by `factor` in both directions (R-seam).  The rows are the
+    boxes of the shorter image from the top (R-seam-rows); empty when either
+    image is narrower than two boxes or shorter than one.
     """
-    lft = box_downsample(left[:, left.shape[1] - 2 * factor:], factor, True)
-    rgt = box_downsample(right[:, :2 * factor], factor, False)
+    n = min(left.shape[0], right.shape[0]) // factor
+    if n == 0 or left.shape[1] < 2 * factor or right.shape[1] < 2 * factor:
+        return np.zeros(0, np.float64)
+    lft = box_downsample(left[:n * factor, left.shape[1] - 2 * factor:], factor, True)
+    rgt = box_downsample(right[:n * factor, :2 * factor], factor, False)
     im1, im0 = lft[:, 0, :], lft[:, 1, :]
     ip0, ip1 = rgt[:, 0, :], rgt[:, 1, :]
     d_plus = np.sqrt((((ip1 - ip0) - (ip0 - im0)) ** 2).sum(axis=1))
     d_minus = np.sqrt((((im1 - im0) - (im0 - ip0)) ** 2).sum(axis=1))
-    return float(((d_plus + d_minus) / 2.0).mean())
+    return (d_plus + d_minus) / 2.0
+
+
+def seam_cost(left: np.ndarray, right: np.ndarray, factor: int = 8) -> float:
+    """The gradient cost of section 4.2: the mean over rows of (d+ + d-)/2
+    (seam_row_costs); NaN when no row is defined."""
+    r = seam_row_costs(left, right, factor)
+    return float(r.mean()) if r.size else math.nan
+
+
+def interior_rows(img: np.ndarray, factor: int = 8) -> np.ndarray:
+    """Row costs at a virtual seam in the middle of one image: columns
+    [0, W/2) on the left, [W/2, W) on the right (section 4.2's reference)."""
+    m = img.shape[1] // 2
+    return seam_row_costs(img[:, :m], img[:, m:], factor)
 
 
 def interior_cost(img: np.ndarray, factor: int = 8) -> float:
     """The same cost at a virtual seam in the middle of one image (section 4.2)."""
-    m = img.shape[1] // 2
-    return seam_cost(img[:, :m], img[:, m:], factor)
+    r = interior_rows(img, factor)
+    return float(r.mean()) if r.size else math.nan
+
+
+def seam_costs(cams: list[Camera], opts: Options, frames: list[np.ndarray], factor: int = 8) -> dict:
+    """The cost of every seam of the rig and the interior reference of every camera.
+
+    seam[k]: the seam between camera k (left image) and the camera its right
+    side faces (R-ring), NaN without one; interior[k]: the virtual seam in
+    the middle of camera k.  seam_rows[k] / interior_rows[k] hold the row
+    values behind each mean.
+    """
+    K = len(cams)
+    seam = np.full(K, math.nan)
+    interior = np.full(K, math.nan)
+    s_rows, i_rows = [], []
+    for k in range(K):
+        fc = facing(cams, opts, k, RIGHT)
+        r = seam_row_costs(frames[k], frames[fc[0]], factor) if fc is not None else np.zeros(0)
+        s_rows.append(r)
+        if r.size:
+            seam[k] = float(r.mean())
+        ri = interior_rows(frames[k], factor)
+        i_rows.append(ri)
+        if ri.size:
+            interior[k] = float(ri.mean())
+    return dict(seam=seam, interior=interior, seam_rows=s_rows, interior_rows=i_rows)
