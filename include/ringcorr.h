@@ -319,6 +319,38 @@ rt_status rt_frameset_removal(rt_ctx* ctx, const void* const* frames, const void
                               uint64_t* kept_sums, const rt_params_buf* state, const rt_lut_buf* lut,
                               uint8_t* method, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Seam gradient cost (section 4.2, the gradient-cost equation) as a monitor
+ * over any frame-set of the context (input or corrected frames).
+ *
+ * Frames are box-downsampled by `factor` in both directions (8 in the
+ * paper; 1..64): each box value is the mean of factor x factor samples.  For
+ * a seam between a left image I- and a right image I+, with I-_{-1}, I-_0
+ * the last two box columns of I- and I+_0, I+_1 the first two of I+, row i
+ * of the downsampled seam has
+ *   d+_i = |(I+_1 - I+_0) - (I+_0 - I-_0)|,  d-_i = |(I-_{-1} - I-_0) - (I-_0 - I+_0)|,
+ * with |.| the Euclidean norm over the camera's channels in sample units,
+ * and the cost is the mean over rows of (d+_i + d-_i) / 2.
+ *   seam[k]      the seam between camera k (left image) and the camera its
+ *                right side faces (ring order); NaN without one (open
+ *                chain end).  A one-camera closed ring faces itself.
+ *   interior[k]  the same cost at a virtual seam at column floor(W/2) of
+ *                camera k (the reference value of section 4.2's table).
+ * The rows of a seam are the boxes of the shorter of its two images from the
+ * top; with no row, or an image (or image half) narrower than two boxes, the
+ * cost is NaN.  Row values are evaluated in binary64 in the order written
+ * above (box means as sum / factor^2, squares summed over the channels in
+ * channel order, one square root per norm); the mean sums the rows in a
+ * fixed order (deterministic).
+ * seam, interior: float64 [K] (8-byte aligned).  rows (may be NULL):
+ * float64 [K][2][row_stride], the row values of the seam (index 0) and of
+ * the interior (index 1) of each camera; entries past a seam's row count
+ * are not written; row_stride >= floor(max height / factor) when rows is
+ * given.  Only cameras of the active set are read and written.
+ * ------------------------------------------------------------------------ */
+rt_status rt_seam_cost(rt_ctx* ctx, const void* const* frames, int32_t factor, double* seam, double* interior,
+                       double* rows, int32_t row_stride, void* stream);
+
 /* A frame-set captured once into a HIP graph for fixed buffers and replayed
  * with one launch per frame-set.
  *

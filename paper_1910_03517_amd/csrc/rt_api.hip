@@ -1213,6 +1213,27 @@ rt_status rt_ctx_apply_times(rt_ctx* ctx, float* ms, int32_t max_n, int32_t* n_o
   return RT_OK;
 }
 
+rt_status rt_seam_cost(rt_ctx* ctx, const void* const* frames, int32_t factor, double* seam, double* interior,
+                       double* rows, int32_t row_stride, void* stream) {
+  if (!ctx) return fail(RT_EINVAL, "ctx is NULL");
+  if (factor < 1 || factor > 64) return fail(RT_EINVAL, "factor %d outside 1..64", factor);
+  rt_status r = check_frames(ctx, frames, "frames");
+  if (r == RT_OK) r = check_ptr(seam, 8, "seam");
+  if (r == RT_OK) r = check_ptr(interior, 8, "interior");
+  if (r != RT_OK) return r;
+  if (rows) {
+    if (!aligned(rows, 8)) return fail(RT_EINVAL, "rows is not 8-byte aligned");
+    int h_max = 0;
+    for (const rt_camera_desc& c : ctx->cams) h_max = std::max(h_max, c.height);
+    if (row_stride < h_max / factor)
+      return fail(RT_EINVAL, "row_stride %d < %d rows (max height / factor)", row_stride, h_max / factor);
+  }
+  const FramePtrs fp = make_ptrs(ctx, frames, nullptr);
+  hipError_t e = launch_seam_cost(ctx->geo, fp, seam, interior, rows, rows ? row_stride : 0, factor,
+                                  (hipStream_t)stream);
+  return e == hipSuccess ? RT_OK : hip_fail(e, "seam cost");
+}
+
 rt_status rt_stream_copy(void* dst, const void* src, int64_t bytes, int32_t vec_bytes, void* stream) {
   if (!dst || !src) return fail(RT_EINVAL, "dst or src is NULL");
   if (bytes < 0) return fail(RT_EINVAL, "bytes < 0");

@@ -151,5 +151,7 @@ hipError_t launch_motion_stats(const Geo& g, const FramePtrs& fp, const PrevPtrs
                                const Removal& rm, hipStream_t st);
 hipError_t launch_estimate_removal(const Geo& g, const Bufs& b, const Removal& rm, hipStream_t st);
 hipError_t launch_stream_copy(void* dst, const void* src, int64_t bytes, int vec_bytes, hipStream_t st);
+hipError_t launch_seam_cost(const Geo& g, const FramePtrs& fp, double* seam, double* interior, double* rows,
+                            int row_stride, int factor, hipStream_t st);
 
 }  // namespace rc

@@ -32,7 +32,7 @@ EXPORTED = ["rt_ctx_create", "rt_ctx_destroy", "rt_ctx_sizes", "rt_stats", "rt_e
             "rt_surrogate_features", "rt_estimate_new", "rt_surrogate_targets", "rt_surrogate_select",
             "rt_surrogate_frameset",
             "rt_mlp_forward", "rt_mlp_backward", "rt_mlp_adam", "rt_mlp_mse", "rt_gather_rows", "rt_mlp_train",
-            "rt_motion_stats", "rt_estimate_removal", "rt_frameset_removal",
+            "rt_motion_stats", "rt_estimate_removal", "rt_frameset_removal", "rt_seam_cost",
             "rt_status_str", "rt_last_error"]
 RT_METHOD_NONE, RT_METHOD_REMOVAL, RT_METHOD_SMOOTHING = 0, 1, 2
 MLP_IN, MLP_HID, MLP_OUT = 576, 256, 6
@@ -159,6 +159,7 @@ def load(path: str = LIB_PATH) -> ct.CDLL:
     lib.rt_frameset_removal.argtypes = [P, ct.POINTER(P), ct.POINTER(P), ct.POINTER(P), R, ct.POINTER(rt_stats_buf),
                                         P, ct.POINTER(rt_params_buf), ct.POINTER(rt_lut_buf), P, P]
     lib.rt_graph_destroy.argtypes = [P]
+    lib.rt_seam_cost.argtypes = [P, ct.POINTER(P), ct.c_int32, P, P, P, ct.c_int32, P]
     lib.rt_ctx_apply_times.argtypes = [P, ct.POINTER(ct.c_float), ct.c_int32, ct.POINTER(ct.c_int32)]
     for name in EXPORTED:
         getattr(lib, name).restype = ct.c_int32
@@ -527,6 +528,13 @@ def _removal(tau: int, min_kept: float) -> rt_removal_opts:
     return rt_removal_opts(int(tau), 0, float(min_kept))
 
 
+def rt_seam_cost(ctx, frames, factor, seam, interior, rows=None, row_stride: int = 0, stream=None) -> None:
+    """Seam gradient cost of every seam and interior reference (float64 [K]
+    tensors seam, interior; rows float64 [K][2][row_stride] or None)."""
+    _check(load().rt_seam_cost(ctx, _ptr_array(frames), factor, _p(seam), _p(interior), _p(rows), row_stride,
+                               _stream_handle(stream)))
+
+
 def rt_motion_stats(ctx, frames, prev_frames, tau, min_kept, band_hist, band_sums, kept_sums, stream=None) -> None:
     ro = _removal(tau, min_kept)
     sb = rt_stats_buf(_p(band_hist), _p(band_sums), None, None)
@@ -708,6 +716,22 @@ class Rig:
         uint8 [K][2][NB] (may be None)."""
         rt_frameset_removal(self.ctx, frames, prev_frames, out_frames, tau, min_kept, self.bufs, kept_sums, method,
                             stream)
+
+    def seam_cost(self, frames, factor: int = 8, rows: bool = False, stream=None):
+        """Seam gradient cost of every seam and the interior reference of every
+        camera of `frames` (device tensors); returns (seam, interior[, rows])
+        as float64 device tensors, [K] and [K][2][floor(max H / factor)]."""
+        import torch
+        K = self.sizes.n_cams
+        dev = frames[0].device
+        seam = torch.empty(K, dtype=torch.float64, device=dev)
+        interior = torch.empty(K, dtype=torch.float64, device=dev)
+        rbuf, stride = None, 0
+        if rows:
+            stride = max(1, max(c.height for c in self.cams) // factor)
+            rbuf = torch.full((K, 2, stride), float("nan"), dtype=torch.float64, device=dev)
+        rt_seam_cost(self.ctx, frames, factor, seam, interior, rbuf, stride, stream)
+        return (seam, interior, rbuf) if rows else (seam, interior)
 
     def frameset_batch(self, active: int, frames, out_frames, stream=None) -> None:
         """Frame-set of the cameras in bitmask `active` (whole rings); the
