@@ -11,6 +11,9 @@ Modules
   ringcorr   -- the correction method of section 3.1 ("White balance and
                 exposure correction") and the seam gradient cost of
                 section 4.2 (the gradient-cost equation).
+  attention  -- the difference approach of section 3.3's attention
+                mechanisms: thresholded frame difference, on-pixel counts per
+                cell and per sliding window, windows over a threshold.
   surrogate  -- the learned estimator: feature vector, MLP forward/backward,
                 MSE loss, Adam and the fallback rule.  The paper has no such
                 network; it is specified by the project and pinned by finite
