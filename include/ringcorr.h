@@ -495,6 +495,24 @@ rt_status rt_surrogate_frameset(rt_ctx* ctx, const rt_mlp* w, float tol, const v
                                 const rt_params_buf* state, const rt_lut_buf* lut, const rt_surrogate_work* work,
                                 void* stream);
 
+/* rt_surrogate_frameset for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, hosts that forbid
+ * allocation after start-up): the same launches and results, with the
+ * workspace in a static device array of the library instead of the caller's
+ * rt_surrogate_work.  The array holds the workspace of RT_STATIC_UNITS units
+ * (K * 2 * NB <= RT_STATIC_UNITS, else RT_EUNSUPPORTED), about 9 MB; each GPU
+ * the library runs on holds its own copy until the process ends, set up when
+ * the first context on that device is created.  The call allocates nothing.
+ * Every call on one GPU shares that GPU's array and its contents of the last
+ * call: calls that overlap on one GPU (other streams, other threads) race
+ * and must be ordered by the caller.  The context's device must be the
+ * current device (RT_EINVAL otherwise). */
+#define RT_STATIC_UNITS 2048
+rt_status rt_surrogate_frameset_static(rt_ctx* ctx, const rt_mlp* w, float tol, const void* const* frames,
+                                       void* const* out_frames, const rt_stats_buf* stats,
+                                       const uint32_t* whole_hist_prev, const rt_params_buf* state,
+                                       const rt_lut_buf* lut, void* stream);
+
 /* Forward pass over n rows: H1, H2 float32 [n][256] (post-ReLU), Y [n][6]. */
 rt_status rt_mlp_forward(const rt_mlp* w, const float* X, int32_t n, float* H1, float* H2, float* Y, void* stream);
 

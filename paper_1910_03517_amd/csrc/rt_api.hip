@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <functional>
 #include <new>
 #include <string>
@@ -279,6 +280,8 @@ const char* rt_status_str(rt_status s) {
 
 const char* rt_last_error(void) { return g_last_error.c_str(); }
 
+static hipError_t static_scratch(int device, void** out);
+
 rt_status rt_ctx_create(const rt_camera_desc* cams, int32_t n_cams, const rt_opts* opts, rt_ctx** out) {
   if (!out) return fail(RT_EINVAL, "out is NULL");
   *out = nullptr;
@@ -327,6 +330,12 @@ rt_status rt_ctx_create(const rt_camera_desc* cams, int32_t n_cams, const rt_opt
   rt_ctx* ctx = new (std::nothrow) rt_ctx();
   if (!ctx) return fail(RT_ENOMEM, "host allocation failed");
   (void)hipGetDevice(&ctx->device);
+  {
+    // Set-up of the static workspace on this device (rt_surrogate_frameset_static);
+    // a failure is kept and reported by that entry point only.
+    void* unused = nullptr;
+    (void)static_scratch(ctx->device, &unused);
+  }
   ctx->n_cams = n_cams;
   ctx->opts = o;
   ctx->cams.assign(cams, cams + n_cams);
@@ -1017,32 +1026,16 @@ static void mlp_ptrs(const rt_mlp* m, float** out) {
   out[0] = m->w1; out[1] = m->b1; out[2] = m->w2; out[3] = m->b2; out[4] = m->w3; out[5] = m->b3;
 }
 
-rt_status rt_surrogate_frameset(rt_ctx* ctx, const rt_mlp* w, float tol, const void* const* frames,
-                                void* const* out_frames, const rt_stats_buf* stats, const uint32_t* whole_hist_prev,
-                                const rt_params_buf* state, const rt_lut_buf* lut, const rt_surrogate_work* work,
-                                void* stream) {
-  if (!ctx) return fail(RT_EINVAL, "ctx is NULL");
-  const uint64_t active = ctx->geo.active;
-  rt_status r = check_mlp(w, "weights");
-  if (r == RT_OK) r = check_frames_masked(ctx, active, frames, "frames");
-  if (r == RT_OK) r = check_frames_masked(ctx, active, (const void* const*)out_frames, "out_frames");
-  if (r == RT_OK) r = check_stats(stats, true, true);
-  if (r == RT_OK) r = check_ptr(whole_hist_prev, 4, "whole_hist_prev");
-  if (r == RT_OK) r = check_params(state);
-  if (r == RT_OK) r = check_lut(lut);
-  if (r != RT_OK) return r;
-  if (!work) return fail(RT_EINVAL, "work struct is NULL");
-  const void* fw[4] = {work->X, work->H1, work->H2, work->Y};
-  for (int i = 0; i < 4; ++i)
-    if ((r = check_ptr(fw[i], 4, "work activation")) != RT_OK) return r;
-  if ((r = check_ptr(work->p_new, 8, "work p_new")) != RT_OK) return r;
-  if ((r = check_ptr(work->status, 4, "work status")) != RT_OK) return r;
-  if ((r = check_ptr(work->used, 1, "work used")) != RT_OK) return r;
-  if ((r = check_ptr(work->residual, 4, "work residual")) != RT_OK) return r;
-  if (!(tol >= 0.0f)) return fail(RT_EINVAL, "tol must be >= 0");
+// Launches of rt_surrogate_frameset once its arguments are validated; the
+// workspace regions are device pointers of the caller's or of the static
+// workspace below.
+static rt_status surrogate_frameset_run(rt_ctx* ctx, const rt_mlp* w, float tol, const void* const* frames,
+                                        void* const* out_frames, const rt_stats_buf* stats,
+                                        const uint32_t* whole_hist_prev, const rt_params_buf* state,
+                                        const rt_lut_buf* lut, const rt_surrogate_work* work, void* stream) {
   hipStream_t st = (hipStream_t)stream;
   const Geo& g = ctx->geo;
-  const FramePtrs fp = make_ptrs_masked(ctx, frames, out_frames, active);
+  const FramePtrs fp = make_ptrs_masked(ctx, frames, out_frames, g.active);
   const Bufs b = make_bufs(stats, state, lut);
   hipError_t e = launch_band_stats(g, fp, b, st);
   if (e != hipSuccess) return hip_fail(e, "band statistics");
@@ -1056,6 +1049,118 @@ rt_status rt_surrogate_frameset(rt_ctx* ctx, const rt_mlp* w, float tol, const v
                         work->residual, st);
   if (e != hipSuccess) return hip_fail(e, "surrogate choice and tables");
   return whole_pass(ctx, g, fp, b, true, false, st);
+}
+
+// Arguments of rt_surrogate_frameset other than the workspace.
+static rt_status check_surrogate_frameset(rt_ctx* ctx, const rt_mlp* w, float tol, const void* const* frames,
+                                          void* const* out_frames, const rt_stats_buf* stats,
+                                          const uint32_t* whole_hist_prev, const rt_params_buf* state,
+                                          const rt_lut_buf* lut) {
+  if (!ctx) return fail(RT_EINVAL, "ctx is NULL");
+  const uint64_t active = ctx->geo.active;
+  rt_status r = check_mlp(w, "weights");
+  if (r == RT_OK) r = check_frames_masked(ctx, active, frames, "frames");
+  if (r == RT_OK) r = check_frames_masked(ctx, active, (const void* const*)out_frames, "out_frames");
+  if (r == RT_OK) r = check_stats(stats, true, true);
+  if (r == RT_OK) r = check_ptr(whole_hist_prev, 4, "whole_hist_prev");
+  if (r == RT_OK) r = check_params(state);
+  if (r == RT_OK) r = check_lut(lut);
+  if (r != RT_OK) return r;
+  if (!(tol >= 0.0f)) return fail(RT_EINVAL, "tol must be >= 0");
+  return RT_OK;
+}
+
+rt_status rt_surrogate_frameset(rt_ctx* ctx, const rt_mlp* w, float tol, const void* const* frames,
+                                void* const* out_frames, const rt_stats_buf* stats, const uint32_t* whole_hist_prev,
+                                const rt_params_buf* state, const rt_lut_buf* lut, const rt_surrogate_work* work,
+                                void* stream) {
+  rt_status r = check_surrogate_frameset(ctx, w, tol, frames, out_frames, stats, whole_hist_prev, state, lut);
+  if (r != RT_OK) return r;
+  if (!work) return fail(RT_EINVAL, "work struct is NULL");
+  const void* fw[4] = {work->X, work->H1, work->H2, work->Y};
+  for (int i = 0; i < 4; ++i)
+    if ((r = check_ptr(fw[i], 4, "work activation")) != RT_OK) return r;
+  if ((r = check_ptr(work->p_new, 8, "work p_new")) != RT_OK) return r;
+  if ((r = check_ptr(work->status, 4, "work status")) != RT_OK) return r;
+  if ((r = check_ptr(work->used, 1, "work used")) != RT_OK) return r;
+  if ((r = check_ptr(work->residual, 4, "work residual")) != RT_OK) return r;
+  return surrogate_frameset_run(ctx, w, tol, frames, out_frames, stats, whole_hist_prev, state, lut, work, stream);
+}
+
+// ---------------------------------------------------------------------------
+// The workspace of rt_surrogate_frameset_static: a file-scope device array
+// (every GPU the library runs on holds its own copy until the process ends),
+// found through hipGetSymbolAddress once per device when the first context on
+// that device is created.  Host code uses only the device address kept here,
+// never the array's name.  Regions for kStaticUnits units, each 256-byte
+// aligned: X f32 [U][576], H1 and H2 f32 [U][256], Y f32 [U][6], p_new f64
+// [U][3][2], status i32 [U][3], used u8 [U], residual f32 [U].
+namespace {
+constexpr size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
+constexpr size_t kStOffX = 0;
+constexpr size_t kStOffH1 = kStOffX + align256((size_t)RT_STATIC_UNITS * kMlpIn * 4);
+constexpr size_t kStOffH2 = kStOffH1 + align256((size_t)RT_STATIC_UNITS * kMlpHid * 4);
+constexpr size_t kStOffY = kStOffH2 + align256((size_t)RT_STATIC_UNITS * kMlpHid * 4);
+constexpr size_t kStOffP = kStOffY + align256((size_t)RT_STATIC_UNITS * kMlpOut * 4);
+constexpr size_t kStOffS = kStOffP + align256((size_t)RT_STATIC_UNITS * 6 * 8);
+constexpr size_t kStOffU = kStOffS + align256((size_t)RT_STATIC_UNITS * 3 * 4);
+constexpr size_t kStOffR = kStOffU + align256((size_t)RT_STATIC_UNITS);
+constexpr size_t kStaticBytes = kStOffR + align256((size_t)RT_STATIC_UNITS * 4);
+constexpr int kMaxDevices = 64;
+
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};        // device address of `scratch` on each device
+hipError_t g_scratch_err[kMaxDevices] = {};   // result of the lookup (hipSuccess once found)
+bool g_scratch_done[kMaxDevices] = {};
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kStaticBytes];
+
+// Looks the array up on `device` (the current device) once; later calls
+// return the kept result.
+static hipError_t static_scratch(int device, void** out) {
+  *out = nullptr;
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_done[device]) {
+    void* p = nullptr;
+    g_scratch_err[device] = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    g_scratch_ptr[device] = g_scratch_err[device] == hipSuccess ? p : nullptr;
+    g_scratch_done[device] = true;
+  }
+  *out = g_scratch_ptr[device];
+  return g_scratch_err[device];
+}
+
+rt_status rt_surrogate_frameset_static(rt_ctx* ctx, const rt_mlp* w, float tol, const void* const* frames,
+                                       void* const* out_frames, const rt_stats_buf* stats,
+                                       const uint32_t* whole_hist_prev, const rt_params_buf* state,
+                                       const rt_lut_buf* lut, void* stream) {
+  rt_status r = check_surrogate_frameset(ctx, w, tol, frames, out_frames, stats, whole_hist_prev, state, lut);
+  if (r != RT_OK) return r;
+  const int64_t units = (int64_t)ctx->n_cams * 2 * ctx->opts.n_blocks;
+  if (units > RT_STATIC_UNITS)
+    return fail(RT_EUNSUPPORTED, "%lld units (cameras x 2 x n_blocks) exceed the static workspace of %d units",
+                (long long)units, RT_STATIC_UNITS);
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "current device");
+  if (dev != ctx->device) return fail(RT_EINVAL, "the context lives on device %d, the current device is %d",
+                                      ctx->device, dev);
+  void* base = nullptr;
+  e = static_scratch(dev, &base);
+  if (e != hipSuccess || !base) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "static workspace");
+  unsigned char* p = static_cast<unsigned char*>(base);
+  rt_surrogate_work work;
+  work.X = reinterpret_cast<float*>(p + kStOffX);
+  work.H1 = reinterpret_cast<float*>(p + kStOffH1);
+  work.H2 = reinterpret_cast<float*>(p + kStOffH2);
+  work.Y = reinterpret_cast<float*>(p + kStOffY);
+  work.p_new = reinterpret_cast<double*>(p + kStOffP);
+  work.status = reinterpret_cast<int32_t*>(p + kStOffS);
+  work.used = p + kStOffU;
+  work.residual = reinterpret_cast<float*>(p + kStOffR);
+  return surrogate_frameset_run(ctx, w, tol, frames, out_frames, stats, whole_hist_prev, state, lut, &work, stream);
 }
 
 rt_status rt_mlp_forward(const rt_mlp* w, const float* X, int32_t n, float* H1, float* H2, float* Y, void* stream) {

@@ -33,6 +33,7 @@ EXPORTED = ["rt_ctx_create", "rt_ctx_destroy", "rt_ctx_sizes", "rt_stats", "rt_e
             "rt_surrogate_frameset",
             "rt_mlp_forward", "rt_mlp_backward", "rt_mlp_adam", "rt_mlp_mse", "rt_gather_rows", "rt_mlp_train",
             "rt_motion_stats", "rt_estimate_removal", "rt_frameset_removal", "rt_seam_cost",
+            "rt_surrogate_frameset_static",
             "rt_status_str", "rt_last_error"]
 RT_METHOD_NONE, RT_METHOD_REMOVAL, RT_METHOD_SMOOTHING = 0, 1, 2
 MLP_IN, MLP_HID, MLP_OUT = 576, 256, 6
@@ -145,6 +146,9 @@ def load(path: str = LIB_PATH) -> ct.CDLL:
     lib.rt_surrogate_frameset.argtypes = [P, M, ct.c_float, ct.POINTER(P), ct.POINTER(P), ct.POINTER(rt_stats_buf),
                                           P, ct.POINTER(rt_params_buf), ct.POINTER(rt_lut_buf),
                                           ct.POINTER(rt_surrogate_work), P]
+    lib.rt_surrogate_frameset_static.argtypes = [P, M, ct.c_float, ct.POINTER(P), ct.POINTER(P),
+                                                 ct.POINTER(rt_stats_buf), P, ct.POINTER(rt_params_buf),
+                                                 ct.POINTER(rt_lut_buf), P]
     lib.rt_mlp_forward.argtypes = [M, P, ct.c_int32, P, P, P, P]
     lib.rt_mlp_backward.argtypes = [M, P, P, P, P, P, ct.c_int32, M, P, P, P, P]
     lib.rt_mlp_adam.argtypes = [M, M, M, M, ct.c_int32, ct.c_float, ct.c_float, ct.c_float, ct.c_float, P]
@@ -391,6 +395,17 @@ def rt_surrogate_frameset(ctx, w: MlpTensors, tol, frames, out_frames, bufs: "Bu
     _check(load().rt_surrogate_frameset(ctx, ct.byref(w.c()), float(tol), _ptr_array(frames), _ptr_array(out_frames),
                                         ct.byref(sb), _p(whole_hist_prev), ct.byref(pb), ct.byref(lb), ct.byref(wk),
                                         _stream_handle(stream)))
+
+
+def rt_surrogate_frameset_static(ctx, w: MlpTensors, tol, frames, out_frames, bufs: "Buffers", whole_hist_prev,
+                                 stream=None) -> None:
+    """rt_surrogate_frameset with the library's static workspace (allocates nothing)."""
+    sb = rt_stats_buf(_p(bufs.band_hist), _p(bufs.band_sums), _p(bufs.whole_hist), _p(bufs.whole_sums))
+    pb = rt_params_buf(_p(bufs.params), _p(bufs.valid))
+    lb = rt_lut_buf(_p(bufs.lut8), _p(bufs.q16), _p(bufs.weights))
+    _check(load().rt_surrogate_frameset_static(ctx, ct.byref(w.c()), float(tol), _ptr_array(frames),
+                                               _ptr_array(out_frames), ct.byref(sb), _p(whole_hist_prev),
+                                               ct.byref(pb), ct.byref(lb), _stream_handle(stream)))
 
 
 def rt_mlp_forward(w: MlpTensors, X, n, H1, H2, Y, stream=None) -> None:
