@@ -13,10 +13,17 @@ rotate so that the 256 MB Infinity Cache cannot serve repeats.
 
     python bench.py [--gpus 1] [--steps 300] [--warmup 20] [--config rig14]
 
-Prints ONE JSON line.  After the timed region, two further legs add their
-own objects to it: "surrogate" (the network trained on the device from the
-plain estimator, then its inference path against the plain one) and
-"serving" (three rigs behind the server, paced at 30 fps and saturated).
+Prints ONE JSON line.  In the pipe mode the launch knobs (apply lanes, group
+size, segment height, apply grid) come from the autotuner, timed in that
+mode on the benchmark rig before the timed region unless cached or given on
+the command line ("tuned" says which).  After the timed region, further
+legs add their own objects to the line: "removal" (object removal with the
+smoothing fallback, eager, and the seam-cost monitor), "surrogate" (the
+network trained on the device from the plain estimator, then its inference
+path against the plain one), "serving" (three rigs behind the server,
+paced at 30 fps and saturated), "uneven" (the three-ring rig of mixed
+sizes in the same launch mode) and "moving_object" (the methods compared
+around a vehicle that crosses a seam, 16 and 64 blocks).
 The roofline figure is for the dominant kernel (the apply pass with fused
 statistics), timed by HIP events the library attaches to its dispatches in
 the timed region (every n-th), next to the streaming-copy ceiling of the
@@ -326,6 +333,7 @@ def serving_leg(args, base, surrogate_w=None) -> dict:
     n_rigs, pool = 3, 4
     out = {"rigs": n_rigs, "rig": spec.name, "fps": 30, "jitter_ms": 2.0, "mem_budget_framesets": 4,
            "plain_apply_lanes": args.serve_lanes}
+    tuned_plain = None
     for path in ("plain", "surrogate"):
         if path == "surrogate" and surrogate_w is None:
             continue
@@ -343,6 +351,13 @@ def serving_leg(args, base, surrogate_w=None) -> dict:
                 per.append(dev)
             frames.append(per)
         torch.cuda.synchronize()
+        if path == "plain":
+            if be.tuned is None:
+                be.autotune([frames[r][0] for r in range(n_rigs)])
+            out["tuned"] = {"source": be.tuned_source, "tile_rows": be.tuned.tile_rows, "grid": be.tuned.grid,
+                            "us_per_batch_of_3_when_tuned": round(be.tuned.us_per_frameset, 2)}
+        elif tuned_plain is not None:
+            be.rig.tune(tuned_plain.tile_rows, tuned_plain.grid)
         fs_bytes = be.frameset_bytes(0)
         res = {}
         # Paced: arrivals of each rig at phase + i/30 s + Exp(2 ms), seeded.
@@ -376,8 +391,123 @@ def serving_leg(args, base, surrogate_w=None) -> dict:
             rep = srv.report()
             res[mode] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in rep.items()}
         res["offered_GPix_s"] = round(n_rigs * 30 * be.rig_pixels(0) / 1e9, 3)
+        if path == "plain":
+            tuned_plain = be.tuned
         be.close()
         out[path] = res
+    return out
+
+
+def removal_leg(rig, ins, outs) -> dict:
+    """Object removal with the smoothing fallback (section 3.1) on the
+    benchmark rig: one rt_frameset_removal per frame-set (the previous
+    frame-set's input as the reference for the frame difference), eager on
+    one stream, next to eager rt_frameset on the same buffers; and the seam
+    gradient cost monitor (section 4.2) per call on the corrected frames."""
+    import torch
+    from paper_1910_03517_amd import rt
+    K, NB = rig.sizes.n_cams, rig.sizes.n_blocks
+    kept = torch.zeros((K, 2, NB, 3, 3), dtype=torch.int64, device="cuda")
+    method = torch.zeros((K, 2, NB), dtype=torch.uint8, device="cuda")
+    seam = torch.zeros(K, dtype=torch.float64, device="cuda")
+    inter = torch.zeros(K, dtype=torch.float64, device="cuda")
+    nb = len(ins)
+    px = sum(c.width * c.height for c in rig.cams)
+
+    def timed(fn, k=60):
+        for i in range(5):
+            fn(i)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for i in range(k):
+            fn(5 + i)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / k * 1e3
+
+    rm_us = timed(lambda i: rig.frameset_removal(ins[i % nb], ins[(i - 1) % nb], outs[i % nb], kept, method))
+    m = method.cpu().numpy()
+    plain_us = timed(lambda i: rig.frameset(ins[i % nb], outs[i % nb]))
+    seam_us = timed(lambda i: rt.rt_seam_cost(rig.ctx, outs[i % nb], 8, seam, inter))
+    s_out = seam.cpu().numpy()
+    rt.rt_seam_cost(rig.ctx, ins[0], 8, seam, inter)
+    s_in = seam.cpu().numpy()
+    rig.check()
+    return {"removal_us_per_frameset": round(rm_us, 2), "removal_GPix_s": round(px / rm_us / 1e3, 2),
+            "plain_us_per_frameset": round(plain_us, 2), "plain_GPix_s": round(px / plain_us / 1e3, 2),
+            "units_removal": int((m == 1).sum()), "units_smoothing": int((m == 2).sum()),
+            "seam_monitor_us": round(seam_us, 2),
+            "seam_cost_input_mean": round(float(s_in.mean()), 3), "seam_cost_corrected_mean": round(float(s_out.mean()), 3),
+            "interior_cost_corrected_mean": round(float(inter.cpu().numpy().mean()), 3),
+            "what": "eager, one stream; removal: rt_frameset_removal with the previous frame-set as reference "
+                    "(tau 20, min_kept 0.25); seam monitor: rt_seam_cost (factor 8) of every seam and image centre"}
+
+
+def moving_object_leg() -> dict:
+    """Section 4.1's comparison on the device: a striped vehicle crosses the
+    seam between the first two cameras of a 4 x 1920x1080 ring in 16 frames;
+    each method (standard, removal alone, removal with the smoothing
+    fallback, smoothing) with 16 and 64 blocks corrects the scene with and
+    without the vehicle; reported: the discolouration of the seam-side
+    correction domains in the blocks the vehicle overlaps (mean absolute
+    difference of the two corrected results over background samples, grey
+    levels; per frame, its maximum and mean over the sequence) and the seam
+    gradient cost of the corrected frames at that seam."""
+    import numpy as np
+    import torch
+    from paper_1910_03517_amd import evaluate, rt, synth
+    W, H, K, T = 1920, 1080, 4, 16
+    spec = synth.RigSpec("moving-object 4x1920x1080 rgb8", 41, [synth.CamSpec(W, H, 3, 8, 0, p) for p in range(K)])
+    # 40 px per frame: the stripes of the vehicle (period 16 px) move by half a
+    # period between frames, so its inside changes too (at a multiple of the
+    # period it would look still to the frame difference).
+    ob = synth.seam_crossing(spec, 0, speed=40.0, frames=T, rows=(0.62, 0.657), width_frac=0.08)
+    cams = [rt.Camera(W, H, 3, 8, 0, p).with_pitch() for p in range(K)]
+    host = {tag: [synth.rig_frames(spec, t, objects=objs) for t in range(T)]
+            for tag, objs in (("obj", (ob,)), ("ref", ()))}
+    up = rt.Rig(cams, rt.Options())
+    dev = {tag: [up.upload(f) for f in fr] for tag, fr in host.items()}
+    up.close()
+    out = {"workload": spec.name, "frames": T, "object_rows": [ob.y0, ob.y0 + ob.h], "object_width": ob.w,
+           "speed_px_per_frame": ob.speed}
+    for nb in (16, 64):
+        rows = evaluate.affected_rows(H, nb, ob.y0, ob.h)
+        ml, mr = evaluate.seam_halves_mask(H, W, W, rows)
+        aff = [j for j in range(nb) if rows[j * H // nb]]
+        for mode in ("standard", "removal", "auto", "smoothing"):
+            res, seams, units = {}, {}, [0, 0]
+            for tag in ("obj", "ref"):
+                rig = rt.Rig(cams, rt.Options(n_blocks=nb, smoothing=(mode == "smoothing")))
+                kept = torch.zeros((K, 2, nb, 3, 3), dtype=torch.int64, device="cuda")
+                method = torch.zeros((K, 2, nb), dtype=torch.uint8, device="cuda")
+                o = rig.alloc_frames()
+                seq, sc = [], []
+                for t in range(T):
+                    if mode in ("removal", "auto"):
+                        rig.frameset_removal(dev[tag][t], dev[tag][t - 1] if t else None, o, kept, method,
+                                             min_kept=0.0 if mode == "removal" else 0.25)
+                        if tag == "obj":
+                            m = method.cpu().numpy()
+                            for k, s in ((0, 1), (1, 0)):
+                                units[0] += int((m[k, s, aff] == 1).sum())
+                                units[1] += int((m[k, s, aff] == 2).sum())
+                    else:
+                        rig.frameset(dev[tag][t], o)
+                    sc.append(float(rig.seam_cost(o)[0][0]))
+                    seq.append([o[k][:, :W * 3].reshape(H, W, 3).cpu().numpy() for k in (0, 1)])
+                rig.check()
+                rig.close()
+                res[tag], seams[tag] = seq, sc
+            d = [evaluate.discolouration([(host["obj"][t][0], host["ref"][t][0], res["obj"][t][0], res["ref"][t][0], ml),
+                                          (host["obj"][t][1], host["ref"][t][1], res["obj"][t][1], res["ref"][t][1], mr)])
+                 for t in range(T)]
+            entry = {"discolouration_max": round(max(d), 3), "discolouration_mean": round(float(np.mean(d)), 3),
+                     "seam_cost_mean": round(float(np.mean(seams["obj"])), 3),
+                     "seam_cost_without_object_mean": round(float(np.mean(seams["ref"])), 3)}
+            if mode in ("removal", "auto"):
+                entry["affected_units_removal"], entry["affected_units_smoothing"] = units
+            out[f"{mode}@{nb}"] = entry
     return out
 
 
@@ -414,7 +544,6 @@ def plain_leg(args, rig_spec, steps: int, warmup: int, timing_every: int):
     rig = rt.Rig(cams, opts)
     if args.tile_rows or args.grid is not None:
         rig.tune(args.tile_rows or rig.tuning()[0], rig.tuning()[1] if args.grid is None else args.grid)
-    tile_rows, grid, n_tiles = rig.tuning()
     alg_bytes = algorithmic_bytes(cams, opts.band_width)
 
     # Distinct frame-sets rotated through NBUF buffer pairs (distinct addresses).
@@ -423,15 +552,41 @@ def plain_leg(args, rig_spec, steps: int, warmup: int, timing_every: int):
     outs = [rig.alloc_frames() for _ in range(args.nbuf)]
     torch.cuda.synchronize()
 
+    # Launch knobs of the pipe mode: given on the command line, else the
+    # autotuner's (cached for this rig and device, or timed now in the pipe
+    # mode itself; the knobs never change results).
+    lanes, group = args.lanes or 3, args.group or 3
+    tuned = {"source": "command line" if (args.lanes or args.group or args.tile_rows or args.grid is not None)
+             else "default"}
+    if args.mode == "pipe" and tuned["source"] == "default" and not args.no_autotune:
+        from paper_1910_03517_amd import autotune
+        t_tune = time.perf_counter()
+        choice = autotune.cached_pipe(rig)
+        src = "cache"
+        if choice is None:
+            log(f"{rig_spec.name}: autotuning the pipe (lanes, group, tile rows, grid)")
+            choice = autotune.tune_pipe(rig, ins, outs, depth=args.depth)
+            src = "tuned"
+        lanes, group = choice.lanes, choice.group
+        tuned = {"source": src, "lanes": lanes, "group": group, "tile_rows": choice.tile_rows,
+                 "grid": choice.grid, "us_per_frameset_when_tuned": round(choice.us_per_frameset, 2),
+                 "seconds": round(time.perf_counter() - t_tune, 2)}
+        # The tuning advanced the estimator state: back to the initial one.
+        rig.bufs.params.zero_()
+        rig.bufs.params[..., 0] = 1.0
+        rig.bufs.valid.zero_()
+        torch.cuda.synchronize()
+    tile_rows, grid, n_tiles = rig.tuning()
+
     stream = torch.cuda.current_stream()
     pipe, graphs = None, None
     b = rig.bufs
     if args.mode == "pipe":
         # A frame-set's buffers are reused `nbuf` steps later: with nbuf a
         # multiple of depth that apply starts only after the earlier one ended.
-        assert max(args.lanes, args.group) <= args.depth and args.nbuf % args.depth == 0, \
+        assert max(lanes, group) <= args.depth and args.nbuf % args.depth == 0, \
             "need lanes, group <= depth and depth | nbuf"
-        pipe = rt.Pipe.for_rig(rig, depth=args.depth, lanes=args.lanes, group=args.group)
+        pipe = rt.Pipe.for_rig(rig, depth=args.depth, lanes=lanes, group=group)
         in_ptrs = [rt.ptr_array(x) for x in ins]
         out_ptrs = [rt.ptr_array(x) for x in outs]
     elif args.mode == "graph":
@@ -549,7 +704,8 @@ def plain_leg(args, rig_spec, steps: int, warmup: int, timing_every: int):
         "hbm_frac": round(alg_bytes * steps / (ms_total / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
         "algorithmic_bytes_per_frameset": alg_bytes, "pixels_per_frameset": px,
         "n_blocks": opts.n_blocks, "band_width": opts.band_width,
-        "tile_rows": tile_rows, "apply_grid": grid, "n_tiles": n_tiles,
+        "tile_rows": tile_rows, "apply_grid": grid, "n_tiles": n_tiles, "lanes": lanes, "group": group,
+        "tuned": tuned,
         "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 4),
                        "p99": round(float(np.percentile(lat_ms, 99)), 4),
                        "what": "start to end of each step's GPU work, steps back to back, measured after the timed "
@@ -572,8 +728,12 @@ def main() -> int:
                     help="pipe: rt_pipe_submit per step (statistics and estimates on their own stream, applies "
                          "round-robin over --lanes streams); graph-pipelined: one two-branch graph launch per step; "
                          "graph: one captured rt_frameset per step; eager: one rt_frameset call per step")
-    ap.add_argument("--lanes", type=int, default=3, help="apply streams of the pipe mode")
-    ap.add_argument("--group", type=int, default=3, help="frame-sets whose applies the pipe mode issues together")
+    ap.add_argument("--lanes", type=int, default=0,
+                    help="apply streams of the pipe mode (default: the autotuner's choice, else 3)")
+    ap.add_argument("--group", type=int, default=0,
+                    help="frame-sets whose applies the pipe mode issues together (default: the autotuner's, else 3)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="pipe mode: skip the autotuner (3 lanes in groups of 3 and the context's work split)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--grid", type=int, default=None,
@@ -587,6 +747,9 @@ def main() -> int:
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-vga", action="store_true", help="skip the 1x640x480 per-call leg")
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven three-ring rig leg")
+    ap.add_argument("--no-removal", action="store_true", help="skip the object-removal / seam-monitor leg")
+    ap.add_argument("--no-moving-object", action="store_true",
+                    help="skip the moving-object comparison of the methods (section 4.1)")
     ap.add_argument("--uneven-steps", type=int, default=0, help="steps of the uneven leg (default: --steps)")
     ap.add_argument("--sur-bases", type=int, default=4)
     ap.add_argument("--sur-draws", type=int, default=112, help="gain draws per base scene (448 units each)")
@@ -628,7 +791,7 @@ def main() -> int:
         "warmup": args.warmup, "ms_per_step": rep["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u8", "data": "synthetic",
         "config": {"workload": workload, "path": "plain", "mode": "smoothing" if args.smoothing else "standard",
-                   "launch_mode": args.mode + (f", {args.lanes} apply lanes, depth {args.depth}, group {args.group}"
+                   "launch_mode": args.mode + (f", {rep['lanes']} apply lanes, depth {args.depth}, group {rep['group']}"
                                                if args.mode == "pipe" else ""),
                    "n_blocks": rep["n_blocks"], "band_width": rep["band_width"],
                    "pixels_per_frameset": rep["pixels_per_frameset"], "rotating_buffers": args.nbuf,
@@ -640,10 +803,14 @@ def main() -> int:
         "host_issue_us_per_step": rep["host_issue_us_per_step"],
         "roofline": roof,
         "kernel_hash": khash,
+        "tuned": rep["tuned"],
     }
     if args.config == "rig14" and not args.no_vga:
         log("vga calls")
         out["vga"] = vga_leg()
+    if args.config == "rig14" and not args.no_removal:
+        log("object removal and seam monitor")
+        out["removal"] = removal_leg(rig, ins, outs)
     sur_w = None
     if not args.no_surrogate and args.config == "rig14":
         sur_w, out["surrogate"] = surrogate_leg(args, rig, ins, outs)
@@ -662,6 +829,11 @@ def main() -> int:
         uroof = urep.pop("roofline")
         out["uneven"] = {**urep, "steps": us, "roofline": {k: uroof[k] for k in (
             "achieved", "frac", "launch_us", "launches_timed", "copy_ceiling_GBs", "alone", "per_step")}}
+    if args.config == "rig14" and not args.no_moving_object:
+        log("moving object: standard, removal, removal with fallback, smoothing at 16 and 64 blocks")
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        out["moving_object"] = moving_object_leg()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(rig_spec, args.smoothing, args.cpu_budget)

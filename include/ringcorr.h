@@ -346,10 +346,38 @@ rt_status rt_frameset_removal(rt_ctx* ctx, const void* const* frames, const void
  * float64 [K][2][row_stride], the row values of the seam (index 0) and of
  * the interior (index 1) of each camera; entries past a seam's row count
  * are not written; row_stride >= floor(max height / factor) when rows is
- * given.  Only cameras of the active set are read and written.
+ * given; with rows NULL the context keeps the row values in a device buffer
+ * of its own (allocated, or grown, by the first call that needs it).  Only
+ * cameras of the active set are read and written.
  * ------------------------------------------------------------------------ */
 rt_status rt_seam_cost(rt_ctx* ctx, const void* const* frames, int32_t factor, double* seam, double* interior,
                        double* rows, int32_t row_stride, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Difference approach of the attention mechanisms (section 3.3): where to
+ * run a detector, from the change between two consecutive frames.
+ *
+ * A pixel is on when the absolute difference of one of its samples to the
+ * same sample of prev_frames exceeds tau << (bit_depth - 8) (tau in 8-bit
+ * units, the thresholded difference of section 3.1's object removal).
+ * cells u32 [K][hc][wc]: on-pixels per cell of `cell` x `cell` pixels aligned
+ * to the frame's top left corner (cut by the border in the last row and
+ * column), hc = ceil(max height / cell), wc = ceil(max width / cell) over the
+ * context's cameras; entries beyond a camera's own cells are 0.
+ * windows u32 and selected u8 [K][hc - m + 1][wc - m + 1] (either may be
+ * NULL; both skipped when hc < m or wc < m): the on-pixels of the window of
+ * m x m cells starting at each cell, and whether that count exceeds theta;
+ * windows that leave a camera's own cell grid are 0 and not selected.
+ * cell: a multiple of 4 in 4..256; m in 1..64; tau >= 0; theta >= 0.  Only
+ * cameras of the active set are read and written.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  int32_t tau, cell, m, theta;
+} rt_attention_opts;
+
+rt_status rt_attention(rt_ctx* ctx, const void* const* frames, const void* const* prev_frames,
+                       const rt_attention_opts* ao, uint32_t* cells, uint32_t* windows, uint8_t* selected,
+                       void* stream);
 
 /* A frame-set captured once into a HIP graph for fixed buffers and replayed
  * with one launch per frame-set.

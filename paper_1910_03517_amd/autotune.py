@@ -1,13 +1,20 @@
-"""Autotuner for the apply pass's work split.
+"""Autotuner for the launch configuration of the correction path.
 
-Searches the runtime knobs of a context (segment height in rows and apply
-grid; see rt_ctx_tune) by timing the full frame-set on the device, and
-caches the winner per (GPU architecture, rig signature, options) in a JSON
+Two searches, each timed on the device in the launch mode that will use it
+and cached per (GPU architecture, rig signature, options, mode) in a JSON
 file.  The knobs never change results, only speed.
 
+* eager (one rt_frameset per frame-set on one stream, as the serving
+  backend issues its batches): the apply pass's work split, segment height
+  in rows and apply grid (rt_ctx_tune);
+* pipe (rt_pipe: statistics and estimates in order on one stream, applies
+  round-robin over several streams): apply lanes and group size together
+  with the work split.
+
     from paper_1910_03517_amd import autotune
-    best = autotune.tune(rig, frames_dev, out_dev)          # applies and caches
-    autotune.apply_cached(rig)                               # later runs
+    best = autotune.tune(rig, frames_dev, out_dev)               # eager; applies and caches
+    autotune.apply_cached(rig)                                    # later runs
+    pc = autotune.tune_pipe(rig, frames_dev, out_dev)            # pipe; tunes the rig, returns lanes/group
 """
 from __future__ import annotations
 
@@ -19,6 +26,11 @@ from dataclasses import asdict, dataclass
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "ringcorr", "autotune.json")
 TILE_ROWS = (8, 16, 32, 64)
 GRIDS = (0, 512, 768, 1024)
+# Pipe mode: (lanes, group) pairs and work splits worth timing.  More lanes
+# than 4 or groups larger than the lane count were slower in every
+# measurement; one lane is the plain stream order.
+PIPE_LANES = ((2, 2), (3, 1), (3, 3), (4, 4))
+PIPE_SPLITS = ((32, 0), (48, 0), (64, 0), (32, 512))
 
 
 @dataclass(frozen=True)
@@ -28,9 +40,12 @@ class Choice:
     us_per_frameset: float
 
 
-def signature(cams, opts, arch: str) -> str:
-    """Stable key of a rig: architecture, every camera's geometry, and the options."""
+def signature(cams, opts, arch: str, mode: str = "eager") -> str:
+    """Stable key of a rig: architecture, every camera's geometry, the options
+    and the launch mode the knobs were timed in."""
     parts = [arch, f"nb={opts.n_blocks}", f"bw={opts.band_width}", f"closed={int(opts.closed_ring)}"]
+    if mode != "eager":
+        parts.append(f"mode={mode}")
     for c in cams:
         parts.append(f"{c.width}x{c.height}x{c.channels}b{c.bit_depth}r{c.ring}p{c.pos}s{c.pitch_bytes}")
     return hashlib.sha256("|".join(parts).encode()).hexdigest()[:24]
@@ -113,5 +128,90 @@ def apply_cached(rig, cache_path: str = DEFAULT_CACHE) -> Choice | None:
     if not entry:
         return None
     choice = Choice(int(entry["tile_rows"]), int(entry["grid"]), float(entry["us_per_frameset"]))
+    rig.tune(choice.tile_rows, choice.grid)
+    return choice
+
+
+@dataclass(frozen=True)
+class PipeChoice:
+    lanes: int
+    group: int
+    tile_rows: int
+    grid: int
+    us_per_frameset: float
+
+
+def pipe_candidates(cams, n_blocks: int) -> list[tuple[int, int, int, int]]:
+    """(lanes, group, tile_rows, grid) tuples for the pipe mode; tile heights
+    above the tallest block are dropped."""
+    tallest = max(-(-c.height // n_blocks) for c in cams)
+    splits = [(r, g) for r, g in PIPE_SPLITS if r <= max(tallest, PIPE_SPLITS[0][0])]
+    return [(l, gr, r, g) for l, gr in PIPE_LANES for r, g in splits]
+
+
+def time_pipe(rig, frames, outs, lanes: int, group: int, depth: int = 8, steps: int = 24, warmup: int = 8) -> float:
+    """Mean microseconds per frame-set through an rt_pipe of `lanes` apply
+    streams issued in groups of `group`, rotating over the given buffers
+    (their count must be a multiple of depth)."""
+    import torch
+    from . import rt
+    n = len(frames)
+    stream = torch.cuda.current_stream()
+    pipe = rt.Pipe.for_rig(rig, depth=depth, lanes=lanes, group=group)
+    ip = [rt.ptr_array(x) for x in frames]
+    op = [rt.ptr_array(x) for x in outs]
+    try:
+        for i in range(warmup):
+            pipe.submit(frames[i % n], outs[i % n], stream, ip[i % n], op[i % n])
+        pipe.join(stream)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for i in range(steps):
+            j = (warmup + i) % n
+            pipe.submit(frames[j], outs[j], stream, ip[j], op[j])
+        pipe.join(stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps * 1e3
+    finally:
+        pipe.close()
+
+
+def tune_pipe(rig, frames, outs, cache_path: str | None = DEFAULT_CACHE, rounds: int = 2, depth: int = 8,
+              cands: list[tuple[int, int, int, int]] | None = None) -> PipeChoice:
+    """Time every pipe candidate `rounds` times (interleaved, best time per
+    candidate), tune the rig to the fastest work split, cache the choice and
+    return it (the caller builds its pipe with choice.lanes / choice.group)."""
+    arch = device_arch()
+    key = signature(rig.cams, rig.opts, arch, "pipe")
+    cands = cands or pipe_candidates(rig.cams, rig.opts.n_blocks)
+    best_us = {c: float("inf") for c in cands}
+    for _ in range(rounds):
+        for c in cands:
+            lanes, group, tile_rows, grid = c
+            rig.tune(tile_rows, grid)
+            best_us[c] = min(best_us[c], time_pipe(rig, frames, outs, lanes, group, depth))
+    c = min(cands, key=lambda k: best_us[k])
+    choice = PipeChoice(c[0], c[1], c[2], c[3], best_us[c])
+    rig.tune(choice.tile_rows, choice.grid)
+    if cache_path:
+        cache = load_cache(cache_path)
+        cache[key] = asdict(choice)
+        save_cache(cache, cache_path)
+    return choice
+
+
+def cached_pipe(rig, cache_path: str = DEFAULT_CACHE) -> PipeChoice | None:
+    """The cached pipe choice for this rig, with the rig tuned to its work
+    split; None if there is none."""
+    entry = load_cache(cache_path).get(signature(rig.cams, rig.opts, device_arch(), "pipe"))
+    if not entry:
+        return None
+    try:
+        choice = PipeChoice(int(entry["lanes"]), int(entry["group"]), int(entry["tile_rows"]), int(entry["grid"]),
+                            float(entry["us_per_frameset"]))
+    except (KeyError, TypeError, ValueError):
+        return None
     rig.tune(choice.tile_rows, choice.grid)
     return choice

@@ -31,6 +31,8 @@ struct rt_ctx {
   DevCam* dcams = nullptr;
   Tile* dtiles = nullptr;
   int32_t* dwg = nullptr;   // [n_wg + 1] first segment of each apply workgroup
+  double* seam_rows = nullptr;   // row values of rt_seam_cost when the caller passes none
+  size_t seam_rows_n = 0;
 
   // Optional timing of the apply kernel: events recorded right before and
   // after each apply launch, in a ring of n_timing slots.
@@ -395,6 +397,7 @@ rt_status rt_ctx_destroy(rt_ctx* ctx) {
   if (ctx->dcams) (void)hipFree(ctx->dcams);
   if (ctx->dtiles) (void)hipFree(ctx->dtiles);
   if (ctx->dwg) (void)hipFree(ctx->dwg);
+  if (ctx->seam_rows) (void)hipFree(ctx->seam_rows);
   delete ctx;
   return RT_OK;
 }
@@ -1326,17 +1329,55 @@ rt_status rt_seam_cost(rt_ctx* ctx, const void* const* frames, int32_t factor, d
   if (r == RT_OK) r = check_ptr(seam, 8, "seam");
   if (r == RT_OK) r = check_ptr(interior, 8, "interior");
   if (r != RT_OK) return r;
+  int h_max = 0;
+  for (const rt_camera_desc& c : ctx->cams) h_max = std::max(h_max, c.height);
+  const int max_rows = h_max / factor;
   if (rows) {
     if (!aligned(rows, 8)) return fail(RT_EINVAL, "rows is not 8-byte aligned");
-    int h_max = 0;
-    for (const rt_camera_desc& c : ctx->cams) h_max = std::max(h_max, c.height);
-    if (row_stride < h_max / factor)
-      return fail(RT_EINVAL, "row_stride %d < %d rows (max height / factor)", row_stride, h_max / factor);
+    if (row_stride < max_rows)
+      return fail(RT_EINVAL, "row_stride %d < %d rows (max height / factor)", row_stride, max_rows);
+  } else {
+    // The context's own row buffer, grown when a call needs more rows.
+    row_stride = std::max(max_rows, 1);
+    const size_t need = (size_t)ctx->n_cams * 2 * row_stride;
+    if (need > ctx->seam_rows_n) {
+      if (ctx->seam_rows) (void)hipFree(ctx->seam_rows);
+      ctx->seam_rows = nullptr;
+      ctx->seam_rows_n = 0;
+      hipError_t e = hipMalloc((void**)&ctx->seam_rows, need * sizeof(double));
+      if (e != hipSuccess) return fail(RT_ENOMEM, "seam cost row buffer: %s", hipGetErrorString(e));
+      ctx->seam_rows_n = need;
+    }
+    rows = ctx->seam_rows;
   }
   const FramePtrs fp = make_ptrs(ctx, frames, nullptr);
-  hipError_t e = launch_seam_cost(ctx->geo, fp, seam, interior, rows, rows ? row_stride : 0, factor,
+  hipError_t e = launch_seam_cost(ctx->geo, fp, seam, interior, rows, row_stride, factor, max_rows,
                                   (hipStream_t)stream);
   return e == hipSuccess ? RT_OK : hip_fail(e, "seam cost");
+}
+
+rt_status rt_attention(rt_ctx* ctx, const void* const* frames, const void* const* prev_frames,
+                       const rt_attention_opts* ao, uint32_t* cells, uint32_t* windows, uint8_t* selected,
+                       void* stream) {
+  if (!ctx) return fail(RT_EINVAL, "ctx is NULL");
+  if (!ao) return fail(RT_EINVAL, "attention options are NULL");
+  if (ao->cell < 4 || ao->cell > 256 || ao->cell % 4 != 0)
+    return fail(RT_EINVAL, "cell %d must be a multiple of 4 in 4..256", ao->cell);
+  if (ao->m < 1 || ao->m > 64) return fail(RT_EINVAL, "m %d outside 1..64", ao->m);
+  if (ao->tau < 0 || ao->theta < 0) return fail(RT_EINVAL, "tau and theta must be >= 0");
+  rt_status r = check_frames(ctx, frames, "frames");
+  if (r == RT_OK) r = check_frames(ctx, prev_frames, "prev_frames");
+  if (r == RT_OK) r = check_ptr(cells, 4, "cells");
+  if (r != RT_OK) return r;
+  if (windows && !aligned(windows, 4)) return fail(RT_EINVAL, "windows is not 4-byte aligned");
+  int h_max = 0;
+  for (const rt_camera_desc& c : ctx->cams) h_max = std::max(h_max, c.height);
+  const int hc = (h_max + ao->cell - 1) / ao->cell, wc = (ctx->w_max + ao->cell - 1) / ao->cell;
+  const FramePtrs fp = make_ptrs(ctx, frames, nullptr);
+  const FramePtrs pp = make_ptrs(ctx, prev_frames, nullptr);
+  hipError_t e = launch_attention(ctx->geo, fp, pp.in, cells, windows, selected, hc, wc, ao->cell, ao->m,
+                                  (uint32_t)ao->tau, (uint32_t)ao->theta, (hipStream_t)stream);
+  return e == hipSuccess ? RT_OK : hip_fail(e, "attention map");
 }
 
 rt_status rt_stream_copy(void* dst, const void* src, int64_t bytes, int32_t vec_bytes, void* stream) {

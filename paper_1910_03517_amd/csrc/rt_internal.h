@@ -151,7 +151,10 @@ hipError_t launch_motion_stats(const Geo& g, const FramePtrs& fp, const PrevPtrs
                                const Removal& rm, hipStream_t st);
 hipError_t launch_estimate_removal(const Geo& g, const Bufs& b, const Removal& rm, hipStream_t st);
 hipError_t launch_stream_copy(void* dst, const void* src, int64_t bytes, int vec_bytes, hipStream_t st);
+hipError_t launch_attention(const Geo& g, const FramePtrs& fp, const uint8_t* const* prev, uint32_t* cells,
+                            uint32_t* windows, uint8_t* selected, int hc, int wc, int cell, int m, uint32_t tau,
+                            uint32_t theta, hipStream_t st);
 hipError_t launch_seam_cost(const Geo& g, const FramePtrs& fp, double* seam, double* interior, double* rows,
-                            int row_stride, int factor, hipStream_t st);
+                            int row_stride, int factor, int max_rows, hipStream_t st);
 
 }  // namespace rc

@@ -33,7 +33,7 @@ EXPORTED = ["rt_ctx_create", "rt_ctx_destroy", "rt_ctx_sizes", "rt_stats", "rt_e
             "rt_surrogate_frameset",
             "rt_mlp_forward", "rt_mlp_backward", "rt_mlp_adam", "rt_mlp_mse", "rt_gather_rows", "rt_mlp_train",
             "rt_motion_stats", "rt_estimate_removal", "rt_frameset_removal", "rt_seam_cost",
-            "rt_surrogate_frameset_static",
+            "rt_surrogate_frameset_static", "rt_attention",
             "rt_status_str", "rt_last_error"]
 RT_METHOD_NONE, RT_METHOD_REMOVAL, RT_METHOD_SMOOTHING = 0, 1, 2
 MLP_IN, MLP_HID, MLP_OUT = 576, 256, 6
@@ -86,6 +86,10 @@ class rt_surrogate_work(ct.Structure):
 
 class rt_removal_opts(ct.Structure):
     _fields_ = [("tau", ct.c_int32), ("reserved", ct.c_int32), ("min_kept", ct.c_double)]
+
+
+class rt_attention_opts(ct.Structure):
+    _fields_ = [("tau", ct.c_int32), ("cell", ct.c_int32), ("m", ct.c_int32), ("theta", ct.c_int32)]
 
 
 class RtError(RuntimeError):
@@ -164,6 +168,7 @@ def load(path: str = LIB_PATH) -> ct.CDLL:
                                         P, ct.POINTER(rt_params_buf), ct.POINTER(rt_lut_buf), P, P]
     lib.rt_graph_destroy.argtypes = [P]
     lib.rt_seam_cost.argtypes = [P, ct.POINTER(P), ct.c_int32, P, P, P, ct.c_int32, P]
+    lib.rt_attention.argtypes = [P, ct.POINTER(P), ct.POINTER(P), ct.POINTER(rt_attention_opts), P, P, P, P]
     lib.rt_ctx_apply_times.argtypes = [P, ct.POINTER(ct.c_float), ct.c_int32, ct.POINTER(ct.c_int32)]
     for name in EXPORTED:
         getattr(lib, name).restype = ct.c_int32
@@ -550,6 +555,15 @@ def rt_seam_cost(ctx, frames, factor, seam, interior, rows=None, row_stride: int
                                _stream_handle(stream)))
 
 
+def rt_attention(ctx, frames, prev_frames, tau, cell, m, theta, cells, windows=None, selected=None,
+                 stream=None) -> None:
+    """Difference approach of the attention mechanisms (cells u32 [K][hc][wc];
+    windows u32 / selected u8 [K][hc-m+1][wc-m+1] or None)."""
+    ao = rt_attention_opts(int(tau), int(cell), int(m), int(theta))
+    _check(load().rt_attention(ctx, _ptr_array(frames), _ptr_array(prev_frames), ct.byref(ao), _p(cells),
+                               _p(windows), _p(selected), _stream_handle(stream)))
+
+
 def rt_motion_stats(ctx, frames, prev_frames, tau, min_kept, band_hist, band_sums, kept_sums, stream=None) -> None:
     ro = _removal(tau, min_kept)
     sb = rt_stats_buf(_p(band_hist), _p(band_sums), None, None)
@@ -747,6 +761,22 @@ class Rig:
             rbuf = torch.full((K, 2, stride), float("nan"), dtype=torch.float64, device=dev)
         rt_seam_cost(self.ctx, frames, factor, seam, interior, rbuf, stride, stream)
         return (seam, interior, rbuf) if rows else (seam, interior)
+
+    def attention(self, frames, prev_frames, tau: int = 20, cell: int = 16, m: int = 8, theta: int = 256,
+                  stream=None):
+        """Attention map of the difference approach: (cells, windows, selected)
+        device tensors laid out over the largest camera's cell grid."""
+        import torch
+        K = self.sizes.n_cams
+        hc = -(-max(c.height for c in self.cams) // cell)
+        wc = -(-max(c.width for c in self.cams) // cell)
+        dev = frames[0].device
+        cells = torch.empty((K, hc, wc), dtype=torch.int32, device=dev)
+        shape = (K, max(hc - m + 1, 0), max(wc - m + 1, 0))
+        win = torch.empty(shape, dtype=torch.int32, device=dev)
+        sel = torch.empty(shape, dtype=torch.uint8, device=dev)
+        rt_attention(self.ctx, frames, prev_frames, tau, cell, m, theta, cells, win, sel, stream)
+        return cells, win, sel
 
     def frameset_batch(self, active: int, frames, out_frames, stream=None) -> None:
         """Frame-set of the cameras in bitmask `active` (whole rings); the

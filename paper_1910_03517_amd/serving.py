@@ -382,6 +382,28 @@ class GpuBackend(Backend):
         self.pipe = None
         if lanes > 1 and surrogate is None:
             self.pipe = rt.Pipe.for_rig(self.rig, depth=depth, lanes=lanes, group=1)
+        # The apply work split timed for this context (autotune.tune, eager
+        # launches as the batches issue them), if one is cached.
+        from . import autotune
+        self.tuned = autotune.apply_cached(self.rig)
+        self.tuned_source = "cache" if self.tuned is not None else "default"
+
+    def autotune(self, frames_per_rig, cache_path=None):
+        """Time the apply work splits on this context with one frame-set of
+        every rig (device frame lists), keep and cache the fastest."""
+        from . import autotune
+        frames = [f for r in range(self.n_rigs) for f in frames_per_rig[r]]
+        outs = self.rig.alloc_frames()
+        kw = {} if cache_path is None else {"cache_path": cache_path}
+        self.tuned = autotune.tune(self.rig, [frames], [outs], **kw)
+        self.tuned_source = "tuned"
+        # Timing advanced every rig's estimator state: back to the initial one.
+        b = self.rig.bufs
+        b.params.zero_()
+        b.params[..., 0] = 1.0
+        b.valid.zero_()
+        self.torch.cuda.synchronize()
+        return self.tuned
 
     def frameset_bytes(self, rig: int) -> int:
         return self._bytes[rig]

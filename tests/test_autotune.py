@@ -70,3 +70,15 @@ def test_autotune_on_device_keeps_results(tmp_path):
     assert got is not None and again.tuning()[:2] == (best.tile_rows, best.grid)
     for r in (ref, tuned, again):
         r.close()
+
+
+def test_pipe_candidates_and_mode_in_signature():
+    cams = [rt.Camera(1920, 1080, 3, 8, 0, p).with_pitch() for p in range(14)]
+    c = autotune.pipe_candidates(cams, 16)
+    assert len(c) == len(autotune.PIPE_LANES) * len(autotune.PIPE_SPLITS)
+    assert all(group <= lanes for lanes, group, _, _ in c)
+    small = autotune.pipe_candidates([rt.Camera(320, 120, 3, 8, 0, 0).with_pitch()], 16)   # blocks of 8 rows
+    assert {r for _, _, r, _ in small} == {32}                 # taller splits dropped, the smallest kept
+    o = rt.Options()
+    assert autotune.signature(cams, o, "gfx950") != autotune.signature(cams, o, "gfx950", "pipe")
+    assert autotune.signature(cams, o, "gfx950") == autotune.signature(cams, o, "gfx950", "eager")
