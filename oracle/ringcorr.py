@@ -44,6 +44,15 @@ R-weight  h = floor(W / 2); left column col < h has Q8 weight
           odd width has weight 0.
 R-apply   y = ((256 - w) x + w f(x) + 128) >> 8, i.e. the exact convex
           combination rounded half up.
+R-vblend  optional (section 5: convex combinations of the maps of adjacent
+          blocks): with doubled block centres C_j = r0_j + r1_j - 1, row r of
+          block j blends block j with its neighbour on r's side of the centre,
+          j - 1 if 2r < C_j, else j + 1 (alone at the first and last centre):
+          between the blocks a < b, v = round_half_up(256 (2r - C_a) /
+          (C_b - C_a)) and each Q16 parameter of the row is floor(((256 - v)
+          P_a + v P_b + 128) / 256) (A and Bq alike, per side and channel); the
+          row's map is then evaluated and blended with the identity as in
+          R-apply.  Needs blocks of at least one row (H >= NB).
 R-seam    seam gradient cost (section 4.2): box means of factor x factor
           blocks, the two box columns on each side of the seam aligned with
           it, Euclidean norm over the channels in sample units; the interior
@@ -87,6 +96,7 @@ class Options:
     ema_alpha: float = 0.05     # alpha of the blending equation of section 3.1
     a_min: float = 0.125
     a_max: float = 8.0
+    vblend: bool = False        # blend the maps of adjacent blocks row by row (R-vblend)
 
 
 # --------------------------------------------------------------------------
@@ -464,9 +474,57 @@ def blend(x: np.ndarray, fx: np.ndarray, w: np.ndarray) -> np.ndarray:
     return ((256 - w) * x + w * fx + 128) >> 8
 
 
+def row_blend(height: int, n_blocks: int, row: int) -> tuple[int, int, int]:
+    """(block a, block b, Q8 weight v of b) of one row under R-vblend; a == b
+    with v = 0 where the row takes one block's map."""
+    bounds = block_bounds(height, n_blocks)
+    j = block_of_row(row, height, n_blocks)
+    cj = bounds[j][0] + bounds[j][1] - 1
+    if 2 * row < cj:
+        a, b = j - 1, j
+    else:
+        a, b = j, j + 1
+    if a < 0 or b >= n_blocks:
+        return j, j, 0
+    ca = bounds[a][0] + bounds[a][1] - 1
+    cb = bounds[b][0] + bounds[b][1] - 1
+    v = ((2 * row - ca) * 512 + (cb - ca)) // (2 * (cb - ca))
+    return a, b, v
+
+
+def blend_q16(pa: int, pb: int, v: int) -> int:
+    """floor(((256 - v) pa + v pb + 128) / 256) in exact integers (R-vblend)."""
+    return ((256 - v) * pa + v * pb + 128) >> 8
+
+
+def apply_camera_vblend(frame: np.ndarray, cam: Camera, opts: Options, q16_cam: np.ndarray) -> np.ndarray:
+    """Corrected copy of one frame with the maps of adjacent blocks blended row
+    by row (R-vblend).  q16_cam [2][NB][CSLOTS][2]."""
+    if cam.height < opts.n_blocks:
+        raise ValueError("blending adjacent blocks needs blocks of at least one row")
+    out = frame.copy()
+    w, side = column_weights(cam.width)
+    maxv = (1 << cam.bit_depth) - 1
+    for r in range(cam.height):
+        a, b, v = row_blend(cam.height, opts.n_blocks, r)
+        for s in (LEFT, RIGHT):
+            cols = np.nonzero(side == s)[0]
+            if cols.size == 0:
+                continue
+            for c in range(cam.channels):
+                A = blend_q16(int(q16_cam[s, a, c, 0]), int(q16_cam[s, b, c, 0]), v)
+                Bq = blend_q16(int(q16_cam[s, a, c, 1]), int(q16_cam[s, b, c, 1]), v)
+                x = frame[r, cols, c].astype(np.int64)
+                fx = np.clip((A * x + Bq + 32768) >> 16, 0, maxv)
+                out[r, cols, c] = blend(x, fx, w[cols]).astype(frame.dtype)
+    return out
+
+
 def apply_camera(frame: np.ndarray, cam: Camera, opts: Options,
                  lut8_cam: np.ndarray, q16_cam: np.ndarray) -> np.ndarray:
     """Corrected copy of one frame.  lut8_cam [2][NB][CSLOTS][256], q16_cam [2][NB][CSLOTS][2]."""
+    if opts.vblend:
+        return apply_camera_vblend(frame, cam, opts, q16_cam)
     out = frame.copy()
     w, side = column_weights(cam.width)
     maxv = (1 << cam.bit_depth) - 1
