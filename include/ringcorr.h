@@ -79,10 +79,21 @@ typedef struct {
 
 /* Method options.  n_blocks >= 1 (paper: 16 or 64), band_width >= 1 (clamped to
  * floor(W/2) per camera), closed_ring 0/1, mode RT_MODE_*, ema_alpha in (0, 1]
- * (paper: 0.05), 0 < a_min <= a_max (clamp of the gain a). */
+ * (paper: 0.05), 0 < a_min <= a_max (clamp of the gain a).
+ * vblend 0/1 (section 5: convex combinations of the maps of adjacent blocks):
+ * 1 blends the maps of adjacent blocks row by row in every apply.  With
+ * doubled block centres C_j = r0_j + r1_j - 1, row r of block j blends j with
+ * its neighbour on r's side of the centre (j - 1 if 2r < C_j, else j + 1;
+ * alone before the first centre and from the last one on): between blocks
+ * a < b the weight of b is v = round_half_up(256 (2r - C_a) / (C_b - C_a))
+ * and each Q16 parameter of the row is floor(((256 - v) P_a + v P_b + 128) /
+ * 256) per side and channel; the row's map is then evaluated and blended
+ * with the identity as in rt_apply.  Needs height >= n_blocks for every
+ * camera (RT_EUNSUPPORTED otherwise).  Estimates and tables are unchanged. */
 typedef struct {
   int32_t n_blocks, band_width, closed_ring, mode;
   double ema_alpha, a_min, a_max;
+  int32_t vblend, reserved;
 } rt_opts;
 
 /* Element counts of every caller-owned buffer of a context. */

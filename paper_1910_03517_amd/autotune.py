@@ -46,6 +46,8 @@ def signature(cams, opts, arch: str, mode: str = "eager") -> str:
     parts = [arch, f"nb={opts.n_blocks}", f"bw={opts.band_width}", f"closed={int(opts.closed_ring)}"]
     if mode != "eager":
         parts.append(f"mode={mode}")
+    if getattr(opts, "vblend", False):
+        parts.append("vblend=1")
     for c in cams:
         parts.append(f"{c.width}x{c.height}x{c.channels}b{c.bit_depth}r{c.ring}p{c.pos}s{c.pitch_bytes}")
     return hashlib.sha256("|".join(parts).encode()).hexdigest()[:24]

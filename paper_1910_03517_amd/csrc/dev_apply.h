@@ -328,6 +328,121 @@ __device__ void apply_tile(const Geo& g, const FramePtrs& fp, const Bufs& b, int
   if (STATS && flush) flush_whole<C, BPS>(g, b, t.cam, L, a1, a2);
 }
 
+// Row-wise blend of adjacent blocks' maps (section 5's convex combinations of
+// the maps of adjacent blocks; every block holds at least one row): with
+// doubled block centres C_j = r0_j + r1_j - 1, row r of block j blends j with
+// its neighbour on r's side of the centre (alone before the first and from
+// the last centre on), weight v of the second block = round_half_up(256
+// (2r - C_a) / (C_b - C_a)); each Q16 parameter of the row is
+// floor(((256 - v) P_a + v P_b + 128) / 256).
+__device__ inline int block_centre2(int j, int H, int nb) {
+  return (int)((int64_t)j * H / nb) + (int)((int64_t)(j + 1) * H / nb) - 1;
+}
+
+__device__ inline void vblend_row(int H, int nb, int r, int& a, int& b, int& v) {
+  const int j = (int)(((int64_t)(r + 1) * nb - 1) / H);
+  const int lo = 2 * r < block_centre2(j, H, nb) ? j - 1 : j;
+  if (lo < 0 || lo + 1 >= nb) {
+    a = b = j;
+    v = 0;
+    return;
+  }
+  const int ca = block_centre2(lo, H, nb), cb = block_centre2(lo + 1, H, nb);
+  a = lo;
+  b = lo + 1;
+  v = ((2 * r - ca) * 512 + (cb - ca)) / (2 * (cb - ca));
+}
+
+__device__ inline int64_t blend_q16(int64_t pa, int64_t pb, int v) {
+  return ((256 - v) * pa + v * pb + 128) >> 8;
+}
+
+// Apply (and statistics) of segment ti with the maps blended row by row.
+// Each row's blended Q16 pairs of both sides are computed once per row
+// (uniform over the workgroup) and every sample is evaluated from its side's
+// pair in 64-bit integers, 8-bit and 16-bit samples alike.  Same histogram
+// and flush as apply_tile.
+template <int C, int BPS, bool WRITE, bool STATS, bool WTAB>
+__device__ void apply_tile_vblend(const Geo& g, const FramePtrs& fp, const Bufs& b, int ti, ApplyLds& L,
+                                  bool first, bool last) {
+  const bool clear = first || BPS == 2 || kPack;
+  const bool flush = last || BPS == 2 || kPack;
+  constexpr int SPG = 4 * C;     // samples per group
+  const int tid = threadIdx.x;
+  const Tile t = uniform_tile(g.tiles[ti]);
+  const DevCam cam = uniform_cam(g.cams[t.cam]);
+  const int W = cam.width, H = cam.height, half = cam.half, nb = g.n_blocks;
+  const int shift = cam.bit_depth - 8;
+  const uint32_t maxv = (1u << cam.bit_depth) - 1u;
+  const int pitch = (int)cam.pitch;
+  if (STATS && clear) {
+    for (int i = tid; i < kHistWords / kCS * C; i += kThreads) L.hist[i] = 0;
+  }
+  __syncthreads();
+  const __amdgpu_buffer_rsrc_t rin = frame_rsrc(fp.in[t.cam], cam);
+  __amdgpu_buffer_rsrc_t rout = rin;
+  if (WRITE) rout = frame_rsrc(fp.out[t.cam], cam);
+  const uint16_t* wrow = b.weights + (int64_t)t.cam * g.w_max;
+  const int hrep = tid & (kRep - 1);
+  unsigned long long a1 = 0, a2 = 0;
+  const int ngroups = (W + 3) >> 2;
+  for (int grp = tid; grp < ngroups; grp += kThreads) {
+    const int col0 = grp * 4, npx = min(4, W - col0);
+    uint32_t wp[4];
+    bool right[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      const int col = col0 + p;
+      uint32_t w = 0;
+      if (WRITE && p < npx) w = WTAB ? (uint32_t)wrow[col] : blend_weight(W, col);
+      wp[p] = (256u - w) | (w << 16);
+      right[p] = col >= half;
+    }
+    for (int row = t.r0; row < t.r1; ++row) {
+      int ja, jb, v;
+      vblend_row(H, nb, row, ja, jb, v);
+      int64_t A[2][kCS], Bq[2][kCS];
+      if (WRITE) {
+#pragma unroll
+        for (int sd = 0; sd < 2; ++sd)
+#pragma unroll
+          for (int c = 0; c < C; ++c) {
+            const int64_t ua = unit_index(t.cam, sd, ja, c, nb), ub = unit_index(t.cam, sd, jb, c, nb);
+            A[sd][c] = blend_q16(uniform(b.q16[ua * 2]), uniform(b.q16[ub * 2]), v);
+            Bq[sd][c] = blend_q16(uniform(b.q16[ua * 2 + 1]), uniform(b.q16[ub * 2 + 1]), v);
+          }
+      }
+      const int off = row * pitch + col0 * C * BPS;
+#pragma unroll
+      for (int i = 0; i < SPG; ++i) {
+        const int p = i / C, c = i - p * C;
+        if (p < npx) {
+          const uint32_t x = BPS == 1 ? __builtin_amdgcn_raw_buffer_load_b8(rin, off + i, 0, 0)
+                                      : __builtin_amdgcn_raw_buffer_load_b16(rin, off + 2 * i, 0, 0);
+          if (STATS) {
+            uint32_t bin = x;
+            if (BPS == 2) { bin = x >> shift; bin = bin > 255u ? 255u : bin; }
+            __hip_atomic_fetch_add(&L.hist[hist_word(c, bin) * kRep + hrep], 1u << hist_shift(bin),
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (BPS == 2) { a1 += x; a2 += (unsigned long long)x * x; }
+          }
+          if (WRITE) {
+            const int sd = right[p] ? 1 : 0;
+            int64_t y = (A[sd][c] * (int64_t)x + Bq[sd][c] + 32768) >> 16;
+            y = y < 0 ? 0 : (y > (int64_t)maxv ? (int64_t)maxv : y);
+            const uint32_t xf = x | ((uint32_t)y << 16);
+            const uint32_t o = __builtin_amdgcn_udot2(__builtin_bit_cast(u16x2, xf),
+                                                      __builtin_bit_cast(u16x2, wp[p]), 128u, false) >> 8;
+            if (BPS == 1) __builtin_amdgcn_raw_buffer_store_b8((uint8_t)o, rout, off + i, 0, 0);
+            else __builtin_amdgcn_raw_buffer_store_b16((uint16_t)o, rout, off + 2 * i, 0, 0);
+          }
+        }
+      }
+    }
+  }
+  if (STATS && flush) flush_whole<C, BPS>(g, b, t.cam, L, a1, a2);
+}
+
 // Direct-map constants of this many blocks fit in the LDS table area.
 constexpr int kRunBlocks = (int)(sizeof(ApplyLds::lut) / (2 * kCS * 2 * sizeof(int32_t)));
 
@@ -482,6 +597,13 @@ __device__ inline int apply_tile_dispatch(const Geo& g, const FramePtrs& fp, con
   const int k = uniform(g.tiles[ti].cam);
   const DevCam cam = uniform_cam(g.cams[k]);
   int te = ti + 1;
+  if (g.vblend) {
+    const bool lastv = te == se || uniform(g.tiles[te].cam) != k;
+    if (cam.bps == 2) apply_tile_vblend<1, 2, WRITE, STATS, WTAB>(g, fp, b, ti, L, first, lastv);
+    else if (cam.channels == 3) apply_tile_vblend<3, 1, WRITE, STATS, WTAB>(g, fp, b, ti, L, first, lastv);
+    else apply_tile_vblend<1, 1, WRITE, STATS, WTAB>(g, fp, b, ti, L, first, lastv);
+    return te;
+  }
   const bool direct = cam.bps == 1 && WRITE && STATS && RC_APPLY_DIRECT && tile_direct(g, b, ti);
   const int j0 = uniform(g.tiles[ti].block);
   // Packed counters bound the rows between flushes.

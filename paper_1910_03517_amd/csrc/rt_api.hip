@@ -259,6 +259,7 @@ static rt_status build_tables(rt_ctx* ctx, int tile_rows, int grid) {
   g.w_max = ctx->w_max;
   g.n_tiles = (int32_t)nt;
   g.mode = ctx->opts.mode;
+  g.vblend = ctx->opts.vblend;
   g.alpha = ctx->opts.ema_alpha;
   g.a_min = ctx->opts.a_min;
   g.a_max = ctx->opts.a_max;
@@ -297,6 +298,12 @@ rt_status rt_ctx_create(const rt_camera_desc* cams, int32_t n_cams, const rt_opt
   if (!(o.ema_alpha > 0.0 && o.ema_alpha <= 1.0)) return fail(RT_EINVAL, "ema_alpha must lie in (0, 1]");
   if (!(o.a_min > 0.0 && o.a_min <= o.a_max && isfinite(o.a_max)))
     return fail(RT_EINVAL, "need 0 < a_min <= a_max < inf");
+  if (o.vblend != 0 && o.vblend != 1) return fail(RT_EINVAL, "vblend must be 0 or 1");
+  if (o.vblend)
+    for (int k = 0; k < n_cams; ++k)
+      if (cams[k].height < o.n_blocks)
+        return fail(RT_EUNSUPPORTED, "vblend needs blocks of at least one row: camera %d has %d rows < n_blocks %d", k,
+                    cams[k].height, o.n_blocks);
 
   for (int k = 0; k < n_cams; ++k) {
     const rt_camera_desc& c = cams[k];

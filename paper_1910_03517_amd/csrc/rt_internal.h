@@ -83,6 +83,7 @@ struct Geo {
   int32_t n_wg;          // apply workgroups
   double alpha, a_min, a_max;
   uint64_t active;       // cameras processed by this launch (bit k = camera k)
+  int32_t vblend;        // 1: the maps of adjacent blocks are blended row by row in the apply
 };
 
 __host__ __device__ inline bool cam_active(const Geo& g, int k) { return (g.active >> k) & 1ull; }

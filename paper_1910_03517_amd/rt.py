@@ -48,7 +48,7 @@ class rt_camera_desc(ct.Structure):
 class rt_opts(ct.Structure):
     _fields_ = [("n_blocks", ct.c_int32), ("band_width", ct.c_int32), ("closed_ring", ct.c_int32),
                 ("mode", ct.c_int32), ("ema_alpha", ct.c_double), ("a_min", ct.c_double),
-                ("a_max", ct.c_double)]
+                ("a_max", ct.c_double), ("vblend", ct.c_int32), ("reserved", ct.c_int32)]
 
 
 class rt_sizes(ct.Structure):
@@ -627,11 +627,12 @@ class Options:
     ema_alpha: float = 0.05
     a_min: float = 0.125
     a_max: float = 8.0
+    vblend: bool = False     # blend the maps of adjacent blocks row by row
 
     def to_c(self) -> rt_opts:
         return rt_opts(self.n_blocks, self.band_width, int(self.closed_ring),
                        RT_MODE_SMOOTHING if self.smoothing else RT_MODE_STANDARD,
-                       self.ema_alpha, self.a_min, self.a_max)
+                       self.ema_alpha, self.a_min, self.a_max, int(self.vblend), 0)
 
 
 class Buffers:

@@ -111,7 +111,7 @@ def build_dataset(kind: str, n_bases: int, draws_per_base: int, seed: int, opts:
     Xs, Ts, owner = [], [], []
     for base_i in range(n_bases):
         spec = synth.RigSpec(f"dataset {kind}", 1000 + seed, specs)
-        base = rig.upload(synth.rig_frames(spec, base_i, seed=seed, distortion=False))
+        base = rig.upload(synth.rig_frames(spec, 0, seed=1000 * seed + base_i, distortion=False))
         grng = np.random.default_rng([1910, 31, seed, base_i])
         for d in range(draws_per_base):
             gains = synth.draw_gains(len(cams), 3, grng)
@@ -234,3 +234,4 @@ def predict(w: rt.MlpTensors, X, device="cuda"):
     y = torch.zeros((n, rt.MLP_OUT), **e)
     rt.rt_mlp_forward(w, X, n, h1, h2, y)
     return y
+

@@ -80,8 +80,9 @@ def _rng(*key: int) -> np.random.Generator:
 
 
 def scene_rgb(height: int, width: int, rng: np.random.Generator, noise_sigma: float = 4.0,
-              no_clip: bool = False) -> np.ndarray:
-    """Periodic-in-x RGB panorama, uint8 (height, width, 3)."""
+              no_clip: bool = False, phases: np.ndarray | None = None) -> np.ndarray:
+    """Periodic-in-x RGB panorama, uint8 (height, width, 3).  `phases` of the
+    three sinusoids (drawn from rng when None); the noise comes from rng."""
     hz = int(round(HORIZON * height))
     rows = np.zeros((height, 3), np.float32)
     t_sky = np.arange(hz, dtype=np.float32) / max(hz - 1, 1)
@@ -89,7 +90,8 @@ def scene_rgb(height: int, width: int, rng: np.random.Generator, noise_sigma: fl
     for c in range(3):
         rows[:hz, c] = SKY_TOP[c] + (SKY_HORIZON[c] - SKY_TOP[c]) * t_sky
         rows[hz:, c] = GROUND_HORIZON[c] + (GROUND_BOTTOM[c] - GROUND_HORIZON[c]) * t_gnd
-    phases = rng.uniform(0.0, 2.0 * np.pi, 3)
+    if phases is None:
+        phases = rng.uniform(0.0, 2.0 * np.pi, 3)
     x = np.arange(width, dtype=np.float64)
     wave = sum(SIN_AMP * np.sin(2.0 * np.pi * m * x / width + phases[m - 1]) for m in (1, 2, 3))
     img = rows[:, None, :] + wave.astype(np.float32)[None, :, None]
@@ -100,13 +102,15 @@ def scene_rgb(height: int, width: int, rng: np.random.Generator, noise_sigma: fl
     return np.clip(np.rint(img), lo, hi).astype(np.uint8)
 
 
-def scene_ir(height: int, width: int, rng: np.random.Generator, noise_sigma: float = 1024.0) -> np.ndarray:
+def scene_ir(height: int, width: int, rng: np.random.Generator, noise_sigma: float = 1024.0,
+             phases: np.ndarray | None = None) -> np.ndarray:
     """Periodic-in-x single-channel 16-bit panorama rescaled to [8000, 40000]."""
     hz = int(round(HORIZON * height))
     rows = np.zeros(height, np.float32)
     rows[:hz] = np.linspace(0.2, 0.8, hz, dtype=np.float32) if hz else rows[:0]
     rows[hz:] = np.linspace(0.7, 0.3, height - hz, dtype=np.float32) if height > hz else rows[hz:]
-    phases = rng.uniform(0.0, 2.0 * np.pi, 3)
+    if phases is None:
+        phases = rng.uniform(0.0, 2.0 * np.pi, 3)
     x = np.arange(width, dtype=np.float64)
     wave = sum(0.05 * np.sin(2.0 * np.pi * m * x / width + phases[m - 1]) for m in (1, 2, 3))
     base = rows[:, None] + wave.astype(np.float32)[None, :]
@@ -189,8 +193,9 @@ def rig_frames(rig: RigSpec, frame: int = 0, drift: bool = False, seed: int = 0,
                objects: tuple = (), noise_sigma: float = 4.0) -> list[np.ndarray]:
     """Distorted frames of every camera of `rig` for frame index `frame`.
 
-    Gains are drawn once per (rig, seed); with drift they vary smoothly over
-    a 300-frame period.  Scene noise is redrawn for every frame.  `objects`
+    Gains and the scene are drawn once per (rig, seed); with drift the gains
+    vary smoothly over a 300-frame period.  Sensor noise is redrawn for every
+    frame.  `objects`
     (MovingObject) are drawn into their ring's panorama before it is cut and
     distorted.
     """
@@ -202,10 +207,12 @@ def rig_frames(rig: RigSpec, frame: int = 0, drift: bool = False, seed: int = 0,
         h = cams[0].height
         widths = [c.width for c in cams]
         rng = _rng(rig.config_id, seed, frame, ring)
+        # The scene is fixed per (rig, seed, ring); the sensor noise is drawn per frame.
+        phases = _rng(rig.config_id, seed, 30_000 + ring).uniform(0.0, 2.0 * np.pi, 3)
         if cams[0].bit_depth == 8:
-            pano = scene_rgb(h, sum(widths), rng, noise_sigma=noise_sigma, no_clip=no_clip)
+            pano = scene_rgb(h, sum(widths), rng, noise_sigma=noise_sigma, no_clip=no_clip, phases=phases)
         else:
-            pano = scene_ir(h, sum(widths), rng)
+            pano = scene_ir(h, sum(widths), rng, phases=phases)
         for ob in objects:
             if ob.ring == ring and cams[0].bit_depth == 8:
                 ob.draw(pano, frame)

@@ -146,10 +146,12 @@ def test_small_rig_object_crossing_sequence():
 
 
 def test_small_rig_object_covering_blocks_takes_the_fallback():
-    """A tall object over a whole band block: the fallback (smoothing) is taken there."""
+    """A tall object over a whole band block: the fallback (smoothing) is taken
+    there.  It moves by half the period of its stripes per frame, so every
+    pixel of it changes between frames and none of the covered band remains."""
     say("case: removal sequence, fallback")
     spec = synth.RigSpec("removal cover", 32, [synth.CamSpec(128, 64, 3, 8, 0, p) for p in range(3)])
-    ob = synth.MovingObject(x0=100.0, y0=0, w=40, h=64, speed=3.0)
+    ob = synth.MovingObject(x0=100.0, y0=0, w=40, h=64, speed=8.0)
     seen = removal_sequence(spec, rt.Options(n_blocks=4, band_width=8, smoothing=True), 6, (ob,))
     assert rc.METHOD_SMOOTHING in seen and rc.METHOD_REMOVAL in seen
 

@@ -7,6 +7,8 @@ integer decision is made on the same numbers); forward, backward and Adam
 against the binary64 oracle element by element: |gpu - ref| <= 1e-4 |ref|
 plus the float32 rounding bound of the products involved (tests/mlp_bounds.py
 states it), for every activation, workspace value and gradient."""
+import math
+
 import numpy as np
 import pytest
 
@@ -283,8 +285,11 @@ def test_training_gain_over_untrained_and_no_correction():
     assert train.X.shape[0] > 10000
     tr = su.Trainer(synth.mlp_init(7), lr=1e-3, batch=256, seed=0)
     untrained = rt.MlpTensors(synth.mlp_init(7))
-    losses = [tr.epoch(train) for _ in range(12)]
-    assert losses[-1] < 0.2 * losses[0], losses
+    losses = []
+    for e in range(100):            # cosine decay of the step size, 1e-3 -> 1e-5
+        tr.lr = 1e-5 + 0.5 * (1e-3 - 1e-5) * (1 + math.cos(math.pi * e / 100))
+        losses.append(tr.epoch(train))
+    assert losses[-1] < 0.05 * losses[0], losses
     Th = held.T.cpu().numpy().astype(np.float64)
 
     def err(Y):
@@ -330,7 +335,11 @@ def test_training_gain_over_untrained_and_no_correction():
     c_unc, c_sur, c_plain = ring_cost(frames), ring_cost(got), ring_cost(plain)
     say(f"seam cost: uncorrected {c_unc:.2f} surrogate path {c_sur:.2f} (network used on {used:.1%} of units) "
         f"plain {c_plain:.2f}")
-    assert c_sur < 0.5 * c_unc
+    # The network is used, and the path with it still removes most of the
+    # seam cost (at this tolerance the accepted outputs differ from the plain
+    # estimate by up to 0.05 in a gain, so its cost lies above the plain path's).
+    assert used > 0.0
+    assert c_sur < 0.1 * c_unc
     rig.close()
 
 
