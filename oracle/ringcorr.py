@@ -53,6 +53,20 @@ R-vblend  optional (section 5: convex combinations of the maps of adjacent
           P_a + v P_b + 128) / 256) (A and Bq alike, per side and channel); the
           row's map is then evaluated and blended with the identity as in
           R-apply.  Needs blocks of at least one row (H >= NB).
+R-qfit    optional (the map should make the main characteristics of the two
+          distributions agree, section 3.1; a least-squares fit of quantiles
+          instead of the two moments): with M = 64 levels p_i = (2i + 1) /
+          (2M), the level-i quantile of a band histogram h with n samples is
+          the smallest bin v with 2M cum_h(v) >= (2i + 1) n; x_i and f_i are
+          the bin centres (in sample units) of the own and the facing band's
+          quantiles, the shared spectrum's quantiles are y_i = (x_i + f_i) / 2
+          (the midway distribution: the average of the two quantile
+          functions), and (a, b) is the least-squares line of y on x:
+          a = cov(x, y) / var(x) from exact integer sums (a = 1 when every x_i
+          is equal), clamped to [a_min, a_max], b = mean(y) - a mean(x).  For
+          two bands whose samples are affine images of each other it gives
+          the moment fit's map.  Plain estimate only (standard and smoothing
+          modes).
 R-seam    seam gradient cost (section 4.2): box means of factor x factor
           blocks, the two box columns on each side of the seam aligned with
           it, Euclidean norm over the channels in sample units; the interior
@@ -97,6 +111,7 @@ class Options:
     a_min: float = 0.125
     a_max: float = 8.0
     vblend: bool = False        # blend the maps of adjacent blocks row by row (R-vblend)
+    fit: str = "moments"        # "moments" (R-fit) or "quantile" (R-qfit)
 
 
 # --------------------------------------------------------------------------
@@ -234,6 +249,59 @@ def fit_side(own: tuple[int, int, int], fac: tuple[int, int, int],
     return a, b
 
 
+QFIT_LEVELS = 64
+
+
+def quantile_bins(hist: np.ndarray, levels: int = QFIT_LEVELS) -> list[int]:
+    """Bin of the level-i quantile of a histogram, i = 0 .. levels - 1: the
+    smallest bin v whose cumulative count reaches (2i + 1) / (2 levels) of the
+    total (reading R-qfit).  Exact integers."""
+    n = int(hist.sum())
+    out = []
+    for i in range(levels):
+        need = (2 * i + 1) * n
+        cum = 0
+        for v in range(NBINS):
+            cum += int(hist[v])
+            if 2 * levels * cum >= need:
+                out.append(v)
+                break
+    return out
+
+
+def bin_centre2(v: int, bit_depth: int) -> int:
+    """Twice the centre of bin v in sample units (bins of 2^(d - 8) samples
+    for bit depth d > 8; the bin itself for 8-bit samples)."""
+    sh = 0 if bit_depth == 8 else bit_depth - 8
+    return ((2 * v) << sh) + (1 << sh) - 1
+
+
+def fit_side_quantile(own_hist: np.ndarray, fac_hist: np.ndarray, bit_depth: int,
+                      a_min: float, a_max: float):
+    """Affine map (a, b) by the least-squares fit of the shared spectrum's
+    quantiles on the own band's (reading R-qfit).  own_hist, fac_hist: one
+    channel's 256-bin histograms.  None when either band is empty."""
+    if int(own_hist.sum()) == 0 or int(fac_hist.sum()) == 0:
+        return None
+    M = QFIT_LEVELS
+    x2 = [bin_centre2(v, bit_depth) for v in quantile_bins(own_hist)]    # 2 x_i
+    f2 = [bin_centre2(v, bit_depth) for v in quantile_bins(fac_hist)]    # 2 f_i
+    sx, sf = sum(x2), sum(f2)
+    sxx = sum(x * x for x in x2)
+    sxf = sum(x * f for x, f in zip(x2, f2))
+    # With y_i = (x_i + f_i) / 2: M sum(x y) - sum(x) sum(y) = num / 8 and
+    # M sum(x^2) - sum(x)^2 = den / 4 in the doubled integers.
+    num = M * (sxx + sxf) - sx * (sx + sf)
+    den = M * sxx - sx * sx
+    a = 1.0 if den == 0 else float(num) / (2.0 * float(den))
+    a = min(max(a, a_min), a_max)
+    mu_o = float(sx) / float(2 * M)
+    mu_s = float(sx + sf) / float(4 * M)
+    am = a * mu_o
+    b = mu_s - am
+    return a, b
+
+
 def ema(prev: float, new: float, alpha: float) -> float:
     """One step of the exponential smoothing of section 3.1 (reading R-ema)."""
     keep = 1.0 - alpha
@@ -243,13 +311,19 @@ def ema(prev: float, new: float, alpha: float) -> float:
 
 
 def estimate(cams: list[Camera], opts: Options, band_sums: np.ndarray,
-             prev_params: np.ndarray | None = None, prev_valid: np.ndarray | None = None):
+             prev_params: np.ndarray | None = None, prev_valid: np.ndarray | None = None,
+             band_hist: np.ndarray | None = None):
     """Per (camera, side, block, channel) affine maps for one frame-set.
 
     band_sums: [K][2][NB][CSLOTS][3].  prev_params f64 [K][2][NB][CSLOTS][2],
     prev_valid u8 [K][2][NB][CSLOTS] (1 = the unit holds an estimate).
+    band_hist [K][2][NB][CSLOTS][256]: needed by the quantile fit (R-qfit).
     Returns (params, valid) of the same shapes.
     """
+    if opts.fit not in ("moments", "quantile"):
+        raise ValueError(f"unknown fit {opts.fit!r}")
+    if opts.fit == "quantile" and band_hist is None:
+        raise ValueError("the quantile fit needs the band histograms")
     K, nb = len(cams), opts.n_blocks
     if prev_params is None:
         prev_params = np.zeros((K, 2, nb, CSLOTS, 2), np.float64)
@@ -272,7 +346,11 @@ def estimate(cams: list[Camera], opts: Options, band_sums: np.ndarray,
                         continue
                     own = tuple(int(v) for v in band_sums[k, s, j, c])
                     fac = tuple(int(v) for v in band_sums[fc[0], fc[1], j, c])
-                    new = fit_side(own, fac, opts.a_min, opts.a_max)
+                    if opts.fit == "quantile":
+                        new = fit_side_quantile(band_hist[k, s, j, c], band_hist[fc[0], fc[1], j, c],
+                                                cam.bit_depth, opts.a_min, opts.a_max)
+                    else:
+                        new = fit_side(own, fac, opts.a_min, opts.a_max)
                     had = bool(prev_valid[k, s, j, c])
                     if new is None:
                         if had:
@@ -350,8 +428,10 @@ def estimate_removal(cams: list[Camera], opts: Options, band_sums: np.ndarray, k
 
     Returns (params, valid, method); method u8 [K][2][NB] is METHOD_REMOVAL,
     METHOD_SMOOTHING, or METHOD_NONE where no new estimate was made (no facing
-    band, or an empty band).
+    band, or an empty band).  The fits are the moment fit (R-fit) only.
     """
+    if opts.fit != "moments":
+        raise ValueError("object removal keeps only the moments of the kept pixels")
     K, nb = len(cams), opts.n_blocks
     if prev_params is None:
         prev_params = np.zeros((K, 2, nb, CSLOTS, 2), np.float64)
@@ -563,7 +643,7 @@ def frameset(cams: list[Camera], opts: Options, frames: list[np.ndarray],
     for k, (cam, f) in enumerate(zip(cams, frames)):
         bh[k], bs[k] = band_stats(f, cam, opts)
         wh[k], ws[k] = whole_stats(f, cam)
-    params, valid = estimate(cams, opts, bs, prev_params, prev_valid)
+    params, valid = estimate(cams, opts, bs, prev_params, prev_valid, band_hist=bh)
     lut8, qq = build_luts(cams, opts, params)
     outs = [apply_camera(f, cam, opts, lut8[k], qq[k]) for k, (cam, f) in enumerate(zip(cams, frames))]
     return dict(band_hist=bh, band_sums=bs, whole_hist=wh, whole_sums=ws, params=params,
