@@ -11,6 +11,9 @@ Modules
   ringcorr   -- the correction method of section 3.1 ("White balance and
                 exposure correction") and the seam gradient cost of
                 section 4.2 (the gradient-cost equation).
+  crossmap   -- the cross-channel 3x3 linear maps that section 5 proposes:
+                cross sums of the bands, Cholesky-factor midway fit, Q16
+                matrix maps and their blend with the identity.
   attention  -- the difference approach of section 3.3's attention
                 mechanisms: thresholded frame difference, on-pixel counts per
                 cell and per sliding window, windows over a threshold.
