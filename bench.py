@@ -484,6 +484,19 @@ def removal_leg(rig, ins, outs) -> dict:
     vblend_us = timed(lambda i: vb.frameset(ins[i % nb], outs[i % nb]))
     vb.check()
     vb.close()
+    qf = rt.Rig(rig.cams, rt.Options(fit="quantile"))
+    quantile_us = timed(lambda i: qf.frameset(ins[i % nb], outs[i % nb]))
+    qf.check()
+    qf.close()
+    xr = rt.Rig(rig.cams, rt.Options())
+    xs = rt.CrossSet(xr.sizes)
+    cross_us = timed(lambda i: rt.rt_frameset_cross(xr.ctx, ins[i % nb], outs[i % nb], xr.bufs, xs))
+    cross_apply_us = timed(lambda i: rt.rt_apply_cross(xr.ctx, ins[i % nb], outs[i % nb], xs, xr.bufs.whole_hist,
+                                                       xr.bufs.whole_sums))
+    p3 = xs.params3.cpu().numpy()
+    units_3x3 = int((abs(p3[..., [1, 2, 3, 5, 6, 7]]).max(axis=-1) > 0).sum())
+    xr.check()
+    xr.close()
     att = rig.attention(ins[0], ins[1])            # buffers of the leg, then the timed calls
     att_us = timed(lambda i: rt.rt_attention(rig.ctx, ins[i % nb], ins[(i - 1) % nb], 20, 16, 8, 256, *att))
     att_bytes = 2 * sum(c.width * c.height * c.channels * c.bps for c in rig.cams)
@@ -496,13 +509,22 @@ def removal_leg(rig, ins, outs) -> dict:
             "units_removal": int((m == 1).sum()), "units_smoothing": int((m == 2).sum()),
             "seam_monitor_us": round(seam_us, 2),
             "vblend_us_per_frameset": round(vblend_us, 2), "vblend_GPix_s": round(px / vblend_us / 1e3, 2),
+            "quantile_fit_us_per_frameset": round(quantile_us, 2),
+            "quantile_fit_GPix_s": round(px / quantile_us / 1e3, 2),
+            "cross3x3_us_per_frameset": round(cross_us, 2), "cross3x3_GPix_s": round(px / cross_us / 1e3, 2),
+            "cross3x3_apply_us": round(cross_apply_us, 2),
+            "cross3x3_apply_hbm_frac": round(6 * px / cross_apply_us / 1e3 / HBM_PEAK_GBS, 4),
+            "cross3x3_units_3x3": units_3x3, "cross3x3_units": int(p3.shape[0] * p3.shape[1] * p3.shape[2]),
             "attention_us": round(att_us, 2), "attention_GB_s": round(att_bytes / att_us / 1e3, 1),
             "attention_hbm_frac": round(att_bytes / att_us / 1e3 / HBM_PEAK_GBS, 4),
             "seam_cost_input_mean": round(float(s_in.mean()), 3), "seam_cost_corrected_mean": round(float(s_out.mean()), 3),
             "interior_cost_corrected_mean": round(float(inter.cpu().numpy().mean()), 3),
             "what": "eager, one stream; removal: rt_frameset_removal with the previous frame-set as reference "
                     "(tau 20, min_kept 0.25); seam monitor: rt_seam_cost (factor 8) of every seam and image centre; "
-                    "vblend: rt_frameset with the maps of adjacent blocks blended row by row; attention: "
+                    "vblend: rt_frameset with the maps of adjacent blocks blended row by row; quantile fit: "
+                    "rt_frameset with fit = quantile; cross3x3: rt_frameset_cross (band and cross sums, 3x3 fit, "
+                    "maps, apply with whole-frame statistics) and rt_apply_cross alone (units_3x3: units whose map "
+                    "has off-diagonal terms, the rest took the per-channel fallback); attention: "
                     "rt_attention (tau 20, 16-pixel cells, 8x8-cell windows) on two consecutive frame-sets, "
                     "both frames read once"}
 

@@ -89,11 +89,28 @@ typedef struct {
  * and each Q16 parameter of the row is floor(((256 - v) P_a + v P_b + 128) /
  * 256) per side and channel; the row's map is then evaluated and blended
  * with the identity as in rt_apply.  Needs height >= n_blocks for every
- * camera (RT_EUNSUPPORTED otherwise).  Estimates and tables are unchanged. */
+ * camera (RT_EUNSUPPORTED otherwise).  Estimates and tables are unchanged.
+ * fit RT_FIT_* (section 3.1: the affine map makes the main characteristics of
+ * the two band distributions agree): RT_FIT_MOMENTS matches the means and
+ * standard deviations (see rt_estimate); RT_FIT_QUANTILE fits the line by
+ * least squares on M = 64 quantiles: the level-i quantile (i = 0..M-1) of a
+ * band histogram h with n samples is the smallest bin v with
+ * 2M cum_h(v) >= (2i + 1) n; x_i and f_i are the centres of the own and the
+ * facing band's quantile bins in sample units (bin v covers
+ * [v 2^s, (v + 1) 2^s) for s = bit_depth - 8, centre v 2^s + (2^s - 1)/2); the
+ * shared spectrum's quantiles are y_i = (x_i + f_i)/2 (the midway distribution);
+ * a = cov(x, y)/var(x), from exact integer sums and one binary64 division
+ * (1 when every x_i is equal), clamped to [a_min, a_max]; b = mean(y) -
+ * a mean(x).  Bands that are affine images of each other get the moment
+ * fit's map.  The quantile fit is taken by rt_estimate (which then reads
+ * stats->band_hist), rt_frameset, rt_frameset_batch, the pipeline and graphs;
+ * the object-removal and surrogate entry points return RT_EUNSUPPORTED. */
+enum { RT_FIT_MOMENTS = 0, RT_FIT_QUANTILE = 1 };
+
 typedef struct {
   int32_t n_blocks, band_width, closed_ring, mode;
   double ema_alpha, a_min, a_max;
-  int32_t vblend, reserved;
+  int32_t vblend, fit;
 } rt_opts;
 
 /* Element counts of every caller-owned buffer of a context. */
@@ -167,7 +184,9 @@ rt_status rt_stats(rt_ctx* ctx, const void* const* frames, const rt_stats_buf* o
  * when either band is empty: the unit keeps its state (identity if invalid).
  * Sides without a facing band (open chain) get the identity.  In smoothing
  * mode a valid unit becomes (1 - alpha) prev + alpha new, element-wise.
- * state is read and overwritten in place (params and valid). */
+ * state is read and overwritten in place (params and valid).  With the
+ * context's fit RT_FIT_QUANTILE, (a, b) is the quantile least-squares fit
+ * (see rt_opts) of the band histograms stats->band_hist instead. */
 rt_status rt_estimate(rt_ctx* ctx, const rt_stats_buf* stats, const rt_params_buf* state, void* stream);
 
 /* Section 3.1, the affine maps as fixed-point tables plus the convex-blend
@@ -329,6 +348,65 @@ rt_status rt_frameset_removal(rt_ctx* ctx, const void* const* frames, const void
                               void* const* out_frames, const rt_removal_opts* ro, const rt_stats_buf* stats,
                               uint64_t* kept_sums, const rt_params_buf* state, const rt_lut_buf* lut,
                               uint8_t* method, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Cross-channel 3x3 maps (section 5: linear maps across the colour channels
+ * instead of one affine map per channel), for contexts whose cameras are all
+ * 8-bit RGB (RT_EUNSUPPORTED otherwise, and with vblend or RT_FIT_QUANTILE).
+ * Per (camera, side, block) the map is y = M x + t on the pixel's (R, G, B):
+ *   the cross sums S_RG, S_RB, S_GB of each band (exact) and its (n, S1, S2)
+ *   per channel give the mean mu = S1/n and the covariance C_cd = S_cd/n -
+ *   mu_c mu_d (binary64; the diagonal, S2/n - mu^2, clamped at 0); L_own and
+ *   L_fac are the lower Cholesky factors of the own and the facing band's C;
+ *   the shared spectrum has L* = (L_own + L_fac)/2 and mu* = (mu_own +
+ *   mu_fac)/2; M = L* L_own^-1 (solved from M L_own = L*, row by row from the
+ *   last column) and t = mu* - M mu_own, so that a band with the own mean and
+ *   covariance is sent to one with mean mu* and covariance L* L*^T.  Every
+ *   step is one binary64 operation in a fixed order.  When either covariance
+ *   has a pivot <= 0, or M has a diagonal entry outside [a_min, a_max] or an
+ *   off-diagonal entry beyond a_max in magnitude, M and t are rt_estimate's
+ *   per-channel maps (a diagonal M).  An empty band keeps the unit's state
+ *   (identity if invalid); a side without a facing band gets the identity.
+ *   Smoothing mode blends the twelve parameters as rt_estimate does.
+ *   q3 = round_half_even(params3 * 65536); f_r(x) = clamp((A_r0 x_0 + A_r1 x_1
+ *   + A_r2 x_2 + B_r + 32768) >> 16, 0, 255); y_r = ((256 - w) x_r + w f_r(x)
+ *   + 128) >> 8 with rt_build_lut's column weights.
+ * Caller-owned device buffers (element counts): cross uint64 [K][2][NB][3]
+ * = (S_RG, S_RB, S_GB); params3 double [K][2][NB][12] = (M row-major, t);
+ * valid3 uint8 [K][2][NB]; q3 int64 [K][2][NB][12]; weights uint16
+ * [K][w_max].  8-byte alignment (weights 2, valid3 1).
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  uint64_t* cross;
+  double* params3;
+  uint8_t* valid3;
+  int64_t* q3;
+  uint16_t* weights;
+} rt_cross_buf;
+
+/* Cross sums of every band (x->cross is written). */
+rt_status rt_cross_stats(rt_ctx* ctx, const void* const* frames, const rt_cross_buf* x, void* stream);
+
+/* The 3x3 fit from stats->band_sums and x->cross; x->params3 and x->valid3
+ * are read and updated in place. */
+rt_status rt_estimate_cross(rt_ctx* ctx, const rt_stats_buf* stats, const rt_cross_buf* x, void* stream);
+
+/* x->q3 and x->weights from x->params3. */
+rt_status rt_build_cross(rt_ctx* ctx, const rt_cross_buf* x, void* stream);
+
+/* The apply pass with the 3x3 maps of x->q3 and the weights of x->weights;
+ * whole_out (may be NULL) receives the whole-frame statistics of the input
+ * as in rt_apply. */
+rt_status rt_apply_cross(rt_ctx* ctx, const void* const* frames, void* const* out_frames, const rt_cross_buf* x,
+                         const rt_stats_buf* whole_out, void* stream);
+
+/* One frame-set with the 3x3 maps: band statistics (stats->band_hist,
+ * band_sums), cross sums, fit, maps, then the apply with the whole-frame
+ * statistics (stats->whole_hist, whole_sums); the same results as rt_stats,
+ * rt_cross_stats, rt_estimate_cross, rt_build_cross and rt_apply_cross in
+ * that order. */
+rt_status rt_frameset_cross(rt_ctx* ctx, const void* const* frames, void* const* out_frames,
+                            const rt_stats_buf* stats, const rt_cross_buf* x, void* stream);
 
 /* ------------------------------------------------------------------------
  * Seam gradient cost (section 4.2, the gradient-cost equation) as a monitor

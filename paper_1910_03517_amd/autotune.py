@@ -151,7 +151,7 @@ def pipe_candidates(cams, n_blocks: int) -> list[tuple[int, int, int, int]]:
     return [(l, gr, r, g) for l, gr in PIPE_LANES for r, g in splits]
 
 
-def time_pipe(rig, frames, outs, lanes: int, group: int, depth: int = 8, steps: int = 24, warmup: int = 8) -> float:
+def time_pipe(rig, frames, outs, lanes: int, group: int, depth: int = 8, steps: int = 64, warmup: int = 16) -> float:
     """Mean microseconds per frame-set through an rt_pipe of `lanes` apply
     streams issued in groups of `group`, rotating over the given buffers
     (their count must be a multiple of depth)."""
@@ -180,22 +180,27 @@ def time_pipe(rig, frames, outs, lanes: int, group: int, depth: int = 8, steps: 
         pipe.close()
 
 
-def tune_pipe(rig, frames, outs, cache_path: str | None = DEFAULT_CACHE, rounds: int = 2, depth: int = 8,
+def tune_pipe(rig, frames, outs, cache_path: str | None = DEFAULT_CACHE, rounds: int = 3, depth: int = 8,
               cands: list[tuple[int, int, int, int]] | None = None) -> PipeChoice:
-    """Time every pipe candidate `rounds` times (interleaved, best time per
-    candidate), tune the rig to the fastest work split, cache the choice and
-    return it (the caller builds its pipe with choice.lanes / choice.group)."""
+    """Time every pipe candidate `rounds` times (interleaved, after an
+    untimed run that brings the device to its working clocks; the median of
+    each candidate's times), tune the rig to the fastest work split, cache the
+    choice and return it (the caller builds its pipe with choice.lanes /
+    choice.group)."""
     arch = device_arch()
     key = signature(rig.cams, rig.opts, arch, "pipe")
     cands = cands or pipe_candidates(rig.cams, rig.opts.n_blocks)
-    best_us = {c: float("inf") for c in cands}
+    rig.tune(cands[0][2], cands[0][3])
+    time_pipe(rig, frames, outs, cands[0][0], cands[0][1], depth, steps=256)
+    times = {c: [] for c in cands}
     for _ in range(rounds):
         for c in cands:
             lanes, group, tile_rows, grid = c
             rig.tune(tile_rows, grid)
-            best_us[c] = min(best_us[c], time_pipe(rig, frames, outs, lanes, group, depth))
-    c = min(cands, key=lambda k: best_us[k])
-    choice = PipeChoice(c[0], c[1], c[2], c[3], best_us[c])
+            times[c].append(time_pipe(rig, frames, outs, lanes, group, depth))
+    med = {c: sorted(t)[len(t) // 2] for c, t in times.items()}
+    c = min(cands, key=lambda k: med[k])
+    choice = PipeChoice(c[0], c[1], c[2], c[3], med[c])
     rig.tune(choice.tile_rows, choice.grid)
     if cache_path:
         cache = load_cache(cache_path)

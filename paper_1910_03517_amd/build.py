@@ -21,7 +21,7 @@ LIB = os.path.join(HERE, "libringcorr.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["rt_api.hip", "k_stats.hip", "k_estimate.hip", "k_apply.hip", "k_util.hip", "k_mlp.hip", "k_surrogate.hip", "k_seam.hip", "k_attention.hip"]
+SOURCES = ["rt_api.hip", "k_stats.hip", "k_estimate.hip", "k_apply.hip", "k_util.hip", "k_mlp.hip", "k_surrogate.hip", "k_seam.hip", "k_attention.hip", "k_cross.hip"]
 
 CFLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

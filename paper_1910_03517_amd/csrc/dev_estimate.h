@@ -57,6 +57,100 @@ __device__ inline int fit_sums(const Geo& g, int channels, int c, const uint64_t
   return kStNew;
 }
 
+// Quantile least-squares fit (RT_FIT_QUANTILE): the line through the pairs
+// (x_i, (x_i + f_i) / 2) of the own and facing band's level-i quantiles,
+// i = 0..63, with the bin centres doubled so that every sum is an exact
+// integer.  One wave takes a facing pair's channel, lane i the level i.
+constexpr int kQLevels = kWave;
+
+struct QSums {
+  int64_t sx, sf, sxx, sff, sxf;   // sums of 2x, 2f, (2x)^2, (2f)^2, (2x)(2f)
+};
+
+// Inclusive prefix sums of a 256-bin histogram (global memory) into cum (LDS),
+// lane l taking bins 4l .. 4l + 3.
+__device__ inline void wave_cum(const uint32_t* h, uint32_t* cum, int lane) {
+  const uint32_t c0 = h[4 * lane], c1 = c0 + h[4 * lane + 1], c2 = c1 + h[4 * lane + 2], c3 = c2 + h[4 * lane + 3];
+  uint32_t incl = c3;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const uint32_t t = __shfl_up(incl, d, kWave);
+    if (lane >= d) incl += t;
+  }
+  const uint32_t base = incl - c3;
+  cum[4 * lane] = base + c0;
+  cum[4 * lane + 1] = base + c1;
+  cum[4 * lane + 2] = base + c2;
+  cum[4 * lane + 3] = base + c3;
+}
+
+// Smallest bin v with 2 M cum(v) >= (2 level + 1) n (binary search).
+__device__ inline int quantile_bin(const uint32_t* cum, int level) {
+  const uint64_t n = cum[kNB - 1];
+  const uint64_t need = (uint64_t)(2 * level + 1) * n;
+  int lo = 0, hi = kNB - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if ((uint64_t)(2 * kQLevels) * cum[mid] >= need) hi = mid;
+    else lo = mid + 1;
+  }
+  return lo;
+}
+
+// Twice the centre of bin v in sample units: bins of 2^shift samples.
+__device__ inline int64_t bin_centre2(int v, int shift) {
+  return ((int64_t)(2 * v) << shift) + (1 << shift) - 1;
+}
+
+// The quantile sums of one channel of a facing pair (own histogram ho, facing
+// hf, 256 bins each in global memory) by one whole wave; cum is 2 x 256 words
+// of LDS owned by the wave.  Every lane returns the totals.
+__device__ inline QSums wave_quantile_sums(const uint32_t* ho, const uint32_t* hf, int shift, uint32_t* cum,
+                                           int lane) {
+  wave_cum(ho, cum, lane);
+  wave_cum(hf, cum + kNB, lane);
+  // Lanes read what other lanes of the wave wrote.
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const int64_t x = bin_centre2(quantile_bin(cum, lane), shift);
+  const int64_t f = bin_centre2(quantile_bin(cum + kNB, lane), shift);
+  QSums q;
+  q.sx = (int64_t)wave_sum_u64((unsigned long long)x);
+  q.sf = (int64_t)wave_sum_u64((unsigned long long)f);
+  q.sxx = (int64_t)wave_sum_u64((unsigned long long)(x * x));
+  q.sff = (int64_t)wave_sum_u64((unsigned long long)(f * f));
+  q.sxf = (int64_t)wave_sum_u64((unsigned long long)(x * f));
+  __builtin_amdgcn_wave_barrier();
+  return q;
+}
+
+// The quantile fit of channel c of a unit, own band = x of the sums when
+// own_x, else f; n_own / n_fac are the bands' sample counts; has_fac false:
+// no facing band.  Statuses as fit_sums.
+__device__ inline int fit_quantile(const Geo& g, int channels, int c, bool has_fac, uint64_t n_own, uint64_t n_fac,
+                                   const QSums& q, bool own_x, double& a, double& bb) {
+  a = 1.0;
+  bb = 0.0;
+  if (c >= channels) return kStUnused;
+  if (!has_fac) return kStIdentity;
+  if (n_own == 0 || n_fac == 0) return kStNone;
+  const int64_t M = kQLevels;
+  const int64_t sx = own_x ? q.sx : q.sf, sf = own_x ? q.sf : q.sx;
+  const int64_t sxx = own_x ? q.sxx : q.sff;
+  const int64_t num = M * (sxx + q.sxf) - sx * (sx + sf);
+  const int64_t den = M * sxx - sx * sx;
+  double aa = den == 0 ? 1.0 : (double)num / (2.0 * (double)den);
+  aa = aa < g.a_min ? g.a_min : aa;
+  aa = aa > g.a_max ? g.a_max : aa;
+  const double mu_o = (double)sx / (double)(2 * M);
+  const double mu_s = (double)(sx + sf) / (double)(4 * M);
+  const double am = aa * mu_o;
+  a = aa;
+  bb = mu_s - am;
+  return kStNew;
+}
+
 // fit_sums of unit u = ((k * 2 + s) * NB + j) * 3 + c from the band sums in
 // the caller layout.
 __device__ inline int fit_new(const Geo& g, const uint64_t* band_sums, int u, double& a, double& bb) {

@@ -12,6 +12,34 @@ __global__ __launch_bounds__(kThreads) void k_estimate(Geo g, Bufs b) {
   if (u < g.n_cams * 2 * g.n_blocks * kCS && cam_active(g, u / (2 * g.n_blocks * kCS))) estimate_unit(g, b, u);
 }
 
+// The quantile fit of every unit (RT_FIT_QUANTILE), one wave per (camera,
+// side, block, channel) unit: the wave gathers the quantiles of the unit's
+// band and of the band it faces from the band histograms, its first lane fits
+// and updates the state.
+__global__ __launch_bounds__(kThreads) void k_estimate_quantile(Geo g, Bufs b) {
+  __shared__ uint32_t cum[kThreads / kWave][2 * kNB];
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int u = uniform((int32_t)(blockIdx.x * (kThreads / kWave) + wave));
+  const int nb = g.n_blocks;
+  if (u >= g.n_cams * 2 * nb * kCS) return;    // the whole wave
+  const int c = u % kCS, j = (u / kCS) % nb, s = (u / (kCS * nb)) & 1, k = u / (kCS * nb * 2);
+  if (!cam_active(g, k)) return;
+  const DevCam cam = uniform_cam(g.cams[k]);
+  const int fc = cam.face_cam[s];
+  const int64_t uf = fc < 0 ? -1 : unit_index(fc, cam.face_side[s], j, c, nb);
+  const uint64_t n_own = b.band_sums[(int64_t)u * 3];
+  const uint64_t n_fac = uf < 0 ? 0 : b.band_sums[uf * 3];
+  QSums q = {0, 0, 0, 0, 0};
+  if (c < cam.channels && uf >= 0 && n_own != 0 && n_fac != 0)
+    q = wave_quantile_sums(b.band_hist + (int64_t)u * kNB, b.band_hist + uf * kNB, cam.bit_depth - 8 > 0 ? cam.bit_depth - 8 : 0,
+                           cum[wave], lane);
+  if (lane == 0) {
+    double a, bb;
+    const int st = fit_quantile(g, cam.channels, c, uf >= 0, n_own, n_fac, q, true, a, bb);
+    temporal_update(g, b.params, b.valid, u, st, a, bb);
+  }
+}
+
 __global__ __launch_bounds__(kThreads) void k_build_lut(Geo g, Bufs b) {
   if (!cam_active(g, blockIdx.x / (2 * g.n_blocks))) return;
   lut_entry(g, b, blockIdx.x, threadIdx.x);
@@ -42,10 +70,11 @@ __global__ __launch_bounds__(kThreads) void k_weights(Geo g, Bufs b) {
 // also sum the pixels that do not move against the previous frames, and
 // each unit takes the object-removal fit or the smoothing fallback
 // (removal_step), as k_motion_stats and k_estimate_removal would.
-template <bool WIDE, bool REMOVAL, typename Lds>
+template <bool WIDE, bool REMOVAL, bool QFIT, typename Lds>
 __device__ __attribute__((always_inline)) void band_estimate_body(const Geo& g, const FramePtrs& fp,
                                                                   const PrevPtrs& pp, const Bufs& b,
                                                                   const Removal& rm, Lds* L) {
+  static_assert(!(REMOVAL && QFIT), "object removal keeps only the moments of the kept pixels");
   constexpr int NT = WIDE ? 2 * kThreads : kThreads;
   // This kernel's chain of dependent steps is what the next apply waits
   // for; its waves take issue priority over the apply waves they share
@@ -55,6 +84,10 @@ __device__ __attribute__((always_inline)) void band_estimate_body(const Geo& g, 
   __shared__ uint64_t sums[3][9];            // (n, S1, S2) per channel of the units taken
   __shared__ uint64_t kept[REMOVAL ? 3 : 1][9];   // the same over their kept pixels
   __shared__ double ab[3][kCS][2];           // their maps after the fit
+  // QFIT: the quantile sums of the facing pair (u0, u1) per channel, wave c
+  // taking channel c.
+  __shared__ uint32_t qcum[QFIT ? kCS : 1][QFIT ? 2 * kNB : 1];
+  __shared__ QSums qs[QFIT ? kCS : 1];
   const int nb = g.n_blocks;
   const int k = blockIdx.x / nb, j = blockIdx.x - (blockIdx.x / nb) * nb;
   const int tid = threadIdx.x;
@@ -114,6 +147,18 @@ __device__ __attribute__((always_inline)) void band_estimate_body(const Geo& g, 
     for (int col = tid; col < g.w_max; col += NT)
       b.weights[(int64_t)k * g.w_max + col] = (uint16_t)blend_weight(cam.width, col);
   __syncthreads();
+  if constexpr (QFIT) {
+    // Only u0 and u1 face each other; the band histograms were written by
+    // this workgroup's band passes.
+    const int wv = uniform((int32_t)(tid / kWave));
+    if (uf >= 0 && wv < uniform(cam.channels)) {
+      const int shift = cam.bit_depth > 8 ? cam.bit_depth - 8 : 0;
+      const QSums q = wave_quantile_sums(b.band_hist + ((int64_t)u0 * kCS + wv) * kNB,
+                                         b.band_hist + ((int64_t)uf * kCS + wv) * kNB, shift, qcum[wv], tid % kWave);
+      if (tid % kWave == 0) qs[wv] = q;
+    }
+    __syncthreads();
+  }
   if (fitter) {
     const int other = (uf >= 0 && t < 2) ? 1 - t : -1;
     const uint64_t* fac = other >= 0 ? &sums[other][c * 3] : nullptr;
@@ -126,7 +171,12 @@ __device__ __attribute__((always_inline)) void band_estimate_body(const Geo& g, 
       if (c == 0 && rm.method) rm.method[unit_at(t)] = (uint8_t)m;
     } else {
       double a, bb;
-      const int st = fit_sums(g, channels, c, &sums[t][c * 3], fac, a, bb);
+      int st;
+      if (QFIT && fac)
+        st = fit_quantile(g, channels, c, true, sums[t][c * 3], sums[other][c * 3], qs[QFIT ? c : 0], t == 0, a,
+                          bb);
+      else
+        st = fit_sums(g, channels, c, &sums[t][c * 3], fac, a, bb);
       temporal_step(g, st, a, bb, p0, p1, v);
     }
     b.params[u * 2] = p0;
@@ -139,12 +189,12 @@ __device__ __attribute__((always_inline)) void band_estimate_body(const Geo& g, 
   for (int w = half; w < n; w += (WIDE ? 2 : 1)) lut_entry_ab(g, b, unit_at(w), ltid, ab[w]);
 }
 
-template <bool WIDE>
+template <bool WIDE, bool QFIT>
 __global__ __launch_bounds__(WIDE ? 2 * kThreads : kThreads) void k_band_estimate(Geo g, FramePtrs fp, Bufs b) {
   __shared__ StatsLds L[WIDE ? 2 : 1];
   PrevPtrs pp;
   Removal rm;
-  band_estimate_body<WIDE, false>(g, fp, pp, b, rm, L);
+  band_estimate_body<WIDE, false, QFIT>(g, fp, pp, b, rm, L);
 }
 
 template <bool WIDE>
@@ -152,7 +202,7 @@ __global__ __launch_bounds__(WIDE ? 2 * kThreads : kThreads) void k_band_estimat
                                                                                           PrevPtrs pp, Bufs b,
                                                                                           Removal rm) {
   __shared__ MotionLds L[WIDE ? 2 : 1];
-  band_estimate_body<WIDE, true>(g, fp, pp, b, rm, L);
+  band_estimate_body<WIDE, true, false>(g, fp, pp, b, rm, L);
 }
 
 // Band statistics with the kept sums, one workgroup per (camera, side, block).
@@ -194,10 +244,12 @@ constexpr int kWideSeamBlocks = 64;
 
 hipError_t launch_band_estimate(const Geo& g, const FramePtrs& fp, const Bufs& b, hipStream_t st) {
   const int blocks = g.n_cams * g.n_blocks;
-  if (blocks <= kWideSeamBlocks)
-    hipLaunchKernelGGL(k_band_estimate<true>, dim3(blocks), dim3(2 * kThreads), 0, st, g, fp, b);
-  else
-    hipLaunchKernelGGL(k_band_estimate<false>, dim3(blocks), dim3(kThreads), 0, st, g, fp, b);
+  const bool wide = blocks <= kWideSeamBlocks, q = g.fit == RT_FIT_QUANTILE;
+  const dim3 grid(blocks), block(wide ? 2 * kThreads : kThreads);
+  if (wide && q) hipLaunchKernelGGL((k_band_estimate<true, true>), grid, block, 0, st, g, fp, b);
+  else if (wide) hipLaunchKernelGGL((k_band_estimate<true, false>), grid, block, 0, st, g, fp, b);
+  else if (q) hipLaunchKernelGGL((k_band_estimate<false, true>), grid, block, 0, st, g, fp, b);
+  else hipLaunchKernelGGL((k_band_estimate<false, false>), grid, block, 0, st, g, fp, b);
   return hipGetLastError();
 }
 
@@ -225,7 +277,18 @@ hipError_t launch_estimate_removal(const Geo& g, const Bufs& b, const Removal& r
 
 hipError_t launch_estimate(const Geo& g, const Bufs& b, hipStream_t st) {
   const int total = g.n_cams * 2 * g.n_blocks * kCS;
+  if (g.fit == RT_FIT_QUANTILE) {
+    constexpr int per = kThreads / kWave;
+    hipLaunchKernelGGL(k_estimate_quantile, dim3((total + per - 1) / per), dim3(kThreads), 0, st, g, b);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_estimate, dim3((total + kThreads - 1) / kThreads), dim3(kThreads), 0, st, g, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_weights(const Geo& g, const Bufs& b, hipStream_t st) {
+  const int64_t n = (int64_t)g.n_cams * g.w_max;
+  hipLaunchKernelGGL(k_weights, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0, st, g, b);
   return hipGetLastError();
 }
 

@@ -260,6 +260,7 @@ static rt_status build_tables(rt_ctx* ctx, int tile_rows, int grid) {
   g.n_tiles = (int32_t)nt;
   g.mode = ctx->opts.mode;
   g.vblend = ctx->opts.vblend;
+  g.fit = ctx->opts.fit;
   g.alpha = ctx->opts.ema_alpha;
   g.a_min = ctx->opts.a_min;
   g.a_max = ctx->opts.a_max;
@@ -299,6 +300,7 @@ rt_status rt_ctx_create(const rt_camera_desc* cams, int32_t n_cams, const rt_opt
   if (!(o.a_min > 0.0 && o.a_min <= o.a_max && isfinite(o.a_max)))
     return fail(RT_EINVAL, "need 0 < a_min <= a_max < inf");
   if (o.vblend != 0 && o.vblend != 1) return fail(RT_EINVAL, "vblend must be 0 or 1");
+  if (o.fit != RT_FIT_MOMENTS && o.fit != RT_FIT_QUANTILE) return fail(RT_EINVAL, "fit %d unknown", o.fit);
   if (o.vblend)
     for (int k = 0; k < n_cams; ++k)
       if (cams[k].height < o.n_blocks)
@@ -646,6 +648,7 @@ rt_status rt_motion_stats(rt_ctx* ctx, const void* const* frames, const void* co
 rt_status rt_estimate_removal(rt_ctx* ctx, const rt_stats_buf* stats, const uint64_t* kept_sums,
                               const rt_removal_opts* ro, const rt_params_buf* state, uint8_t* method, void* stream) {
   if (!ctx) return fail(RT_EINVAL, "ctx is NULL");
+  if (ctx->opts.fit != RT_FIT_MOMENTS) return fail(RT_EUNSUPPORTED, "object removal fits the moments only");
   rt_status r = check_stats(stats, true, false);
   if (r == RT_OK) r = check_removal(ro);
   if (r == RT_OK) r = check_ptr(kept_sums, 8, "kept_sums");
@@ -661,6 +664,7 @@ rt_status rt_frameset_removal(rt_ctx* ctx, const void* const* frames, const void
                               uint64_t* kept_sums, const rt_params_buf* state, const rt_lut_buf* lut,
                               uint8_t* method, void* stream) {
   if (!ctx) return fail(RT_EINVAL, "ctx is NULL");
+  if (ctx->opts.fit != RT_FIT_MOMENTS) return fail(RT_EUNSUPPORTED, "object removal fits the moments only");
   const uint64_t active = ctx->geo.active;
   rt_status r = check_frames_masked(ctx, active, frames, "frames");
   if (r == RT_OK && prev_frames) r = check_frames_masked(ctx, active, prev_frames, "prev_frames");
@@ -995,6 +999,7 @@ rt_status rt_surrogate_features(rt_ctx* ctx, const rt_stats_buf* stats, float* X
 
 rt_status rt_estimate_new(rt_ctx* ctx, const rt_stats_buf* stats, double* p_new, int32_t* status, void* stream) {
   if (!ctx) return fail(RT_EINVAL, "ctx is NULL");
+  if (ctx->opts.fit != RT_FIT_MOMENTS) return fail(RT_EUNSUPPORTED, "the surrogate's plain estimate fits the moments only");
   if (!stats) return fail(RT_EINVAL, "stats buffer struct is NULL");
   rt_status r = check_ptr(stats->band_sums, 8, "band_sums");
   if (r == RT_OK) r = check_ptr(p_new, 8, "p_new");
@@ -1067,6 +1072,7 @@ static rt_status check_surrogate_frameset(rt_ctx* ctx, const rt_mlp* w, float to
                                           const uint32_t* whole_hist_prev, const rt_params_buf* state,
                                           const rt_lut_buf* lut) {
   if (!ctx) return fail(RT_EINVAL, "ctx is NULL");
+  if (ctx->opts.fit != RT_FIT_MOMENTS) return fail(RT_EUNSUPPORTED, "the surrogate's plain estimate fits the moments only");
   const uint64_t active = ctx->geo.active;
   rt_status r = check_mlp(w, "weights");
   if (r == RT_OK) r = check_frames_masked(ctx, active, frames, "frames");
@@ -1326,6 +1332,100 @@ rt_status rt_ctx_apply_times(rt_ctx* ctx, float* ms, int32_t max_n, int32_t* n_o
   }
   *n_out = n;
   return RT_OK;
+}
+
+// ---------------------------------------------------------------- cross-channel 3x3 maps
+
+static rt_status check_cross_ctx(const rt_ctx* ctx) {
+  if (!ctx) return fail(RT_EINVAL, "ctx is NULL");
+  for (int k = 0; k < ctx->n_cams; ++k)
+    if (ctx->cams[k].channels != 3 || ctx->cams[k].bit_depth != 8)
+      return fail(RT_EUNSUPPORTED, "cross-channel maps need 8-bit RGB cameras (camera %d)", k);
+  if (ctx->opts.vblend) return fail(RT_EUNSUPPORTED, "cross-channel maps are not blended between blocks");
+  if (ctx->opts.fit != RT_FIT_MOMENTS) return fail(RT_EUNSUPPORTED, "cross-channel maps fit the moments only");
+  return RT_OK;
+}
+
+static rt_status check_cross(const rt_cross_buf* x, bool cross, bool state, bool q3, bool weights) {
+  if (!x) return fail(RT_EINVAL, "cross buffer struct is NULL");
+  rt_status r = RT_OK;
+  if (cross && (r = check_ptr(x->cross, 8, "cross")) != RT_OK) return r;
+  if (state && (r = check_ptr(x->params3, 8, "params3")) != RT_OK) return r;
+  if (state && (r = check_ptr(x->valid3, 1, "valid3")) != RT_OK) return r;
+  if (q3 && (r = check_ptr(x->q3, 8, "q3")) != RT_OK) return r;
+  if (weights && (r = check_ptr(x->weights, 2, "weights")) != RT_OK) return r;
+  return RT_OK;
+}
+
+static CrossBufs make_cross(const rt_cross_buf* x) {
+  return CrossBufs{x->cross, x->params3, x->valid3, x->q3, x->weights};
+}
+
+rt_status rt_cross_stats(rt_ctx* ctx, const void* const* frames, const rt_cross_buf* x, void* stream) {
+  rt_status r = check_cross_ctx(ctx);
+  if (r == RT_OK) r = check_frames(ctx, frames, "frames");
+  if (r == RT_OK) r = check_cross(x, true, false, false, false);
+  if (r != RT_OK) return r;
+  const hipError_t e = launch_cross_stats(ctx->geo, make_ptrs(ctx, frames, nullptr), make_cross(x), (hipStream_t)stream);
+  return e == hipSuccess ? RT_OK : hip_fail(e, "cross statistics");
+}
+
+rt_status rt_estimate_cross(rt_ctx* ctx, const rt_stats_buf* stats, const rt_cross_buf* x, void* stream) {
+  rt_status r = check_cross_ctx(ctx);
+  if (r == RT_OK && !stats) r = fail(RT_EINVAL, "stats buffer struct is NULL");
+  if (r == RT_OK) r = check_ptr(stats->band_sums, 8, "band_sums");
+  if (r == RT_OK) r = check_cross(x, true, true, false, false);
+  if (r != RT_OK) return r;
+  const hipError_t e = launch_estimate_cross(ctx->geo, make_bufs(stats, nullptr, nullptr), make_cross(x),
+                                             (hipStream_t)stream);
+  return e == hipSuccess ? RT_OK : hip_fail(e, "cross-channel estimate");
+}
+
+rt_status rt_build_cross(rt_ctx* ctx, const rt_cross_buf* x, void* stream) {
+  rt_status r = check_cross_ctx(ctx);
+  if (r == RT_OK) r = check_cross(x, false, true, true, true);
+  if (r != RT_OK) return r;
+  const hipError_t e = launch_build_cross(ctx->geo, make_cross(x), (hipStream_t)stream);
+  return e == hipSuccess ? RT_OK : hip_fail(e, "cross-channel maps");
+}
+
+rt_status rt_apply_cross(rt_ctx* ctx, const void* const* frames, void* const* out_frames, const rt_cross_buf* x,
+                         const rt_stats_buf* whole_out, void* stream) {
+  rt_status r = check_cross_ctx(ctx);
+  if (r == RT_OK) r = check_frames(ctx, frames, "frames");
+  if (r == RT_OK) r = check_frames(ctx, (const void* const*)out_frames, "out_frames");
+  if (r == RT_OK) r = check_cross(x, false, false, true, true);
+  if (r == RT_OK && whole_out) r = check_stats(whole_out, false, true);
+  if (r != RT_OK) return r;
+  hipStream_t st = (hipStream_t)stream;
+  const Bufs b = make_bufs(whole_out, nullptr, nullptr);
+  hipError_t e = hipSuccess;
+  if (whole_out) e = launch_zero_whole(ctx->geo, b, st);
+  if (e == hipSuccess)
+    e = launch_apply_cross(ctx->geo, make_ptrs(ctx, frames, out_frames), b, make_cross(x), whole_out != nullptr, st);
+  return e == hipSuccess ? RT_OK : hip_fail(e, "cross-channel apply");
+}
+
+rt_status rt_frameset_cross(rt_ctx* ctx, const void* const* frames, void* const* out_frames,
+                            const rt_stats_buf* stats, const rt_cross_buf* x, void* stream) {
+  rt_status r = check_cross_ctx(ctx);
+  if (r == RT_OK) r = check_frames(ctx, frames, "frames");
+  if (r == RT_OK) r = check_frames(ctx, (const void* const*)out_frames, "out_frames");
+  if (r == RT_OK) r = check_stats(stats, true, true);
+  if (r == RT_OK) r = check_cross(x, true, true, true, true);
+  if (r != RT_OK) return r;
+  hipStream_t st = (hipStream_t)stream;
+  const Geo& g = ctx->geo;
+  const FramePtrs fp = make_ptrs(ctx, frames, out_frames);
+  const Bufs b = make_bufs(stats, nullptr, nullptr);
+  const CrossBufs xb = make_cross(x);
+  hipError_t e = launch_band_stats(g, fp, b, st);
+  if (e == hipSuccess) e = launch_cross_stats(g, fp, xb, st);
+  if (e == hipSuccess) e = launch_estimate_cross(g, b, xb, st);
+  if (e == hipSuccess) e = launch_build_cross(g, xb, st);
+  if (e == hipSuccess) e = launch_zero_whole(g, b, st);
+  if (e == hipSuccess) e = launch_apply_cross(g, fp, b, xb, true, st);
+  return e == hipSuccess ? RT_OK : hip_fail(e, "cross-channel frame-set");
 }
 
 rt_status rt_seam_cost(rt_ctx* ctx, const void* const* frames, int32_t factor, double* seam, double* interior,

@@ -73,6 +73,15 @@ struct Bufs {
   uint16_t* weights;
 };
 
+// Caller buffers of the cross-channel 3x3 maps (device pointers).
+struct CrossBufs {
+  uint64_t* cross;    // [K][2][NB][3] = (S_RG, S_RB, S_GB)
+  double* params3;    // [K][2][NB][12] = M row-major, then t
+  uint8_t* valid3;    // [K][2][NB]
+  int64_t* q3;        // [K][2][NB][12]
+  uint16_t* weights;  // [K][w_max]
+};
+
 // Context-wide constants passed to every kernel.
 struct Geo {
   const DevCam* cams;    // device array [K]
@@ -84,6 +93,7 @@ struct Geo {
   double alpha, a_min, a_max;
   uint64_t active;       // cameras processed by this launch (bit k = camera k)
   int32_t vblend;        // 1: the maps of adjacent blocks are blended row by row in the apply
+  int32_t fit;           // RT_FIT_MOMENTS or RT_FIT_QUANTILE
 };
 
 __host__ __device__ inline bool cam_active(const Geo& g, int k) { return (g.active >> k) & 1ull; }
@@ -144,6 +154,12 @@ hipError_t launch_build_lut(const Geo& g, const Bufs& b, hipStream_t st);
 hipError_t launch_apply(const Geo& g, const FramePtrs& fp, const Bufs& b, bool write, bool stats, hipStream_t st,
                         hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
 hipError_t launch_zero_whole(const Geo& g, const Bufs& b, hipStream_t st);
+hipError_t launch_weights(const Geo& g, const Bufs& b, hipStream_t st);
+hipError_t launch_cross_stats(const Geo& g, const FramePtrs& fp, const CrossBufs& x, hipStream_t st);
+hipError_t launch_estimate_cross(const Geo& g, const Bufs& b, const CrossBufs& x, hipStream_t st);
+hipError_t launch_build_cross(const Geo& g, const CrossBufs& x, hipStream_t st);
+hipError_t launch_apply_cross(const Geo& g, const FramePtrs& fp, const Bufs& b, const CrossBufs& x, bool stats,
+                              hipStream_t st);
 struct PrevPtrs;
 struct Removal;
 hipError_t launch_band_estimate_removal(const Geo& g, const FramePtrs& fp, const PrevPtrs& pp, const Bufs& b,

@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(HERE, "libringcorr.so")
 
 RT_OK, RT_EINVAL, RT_ENOMEM, RT_EDEVICE, RT_EUNSUPPORTED, RT_ESTATE = 0, -1, -2, -3, -4, -5
 RT_MODE_STANDARD, RT_MODE_SMOOTHING = 0, 1
+RT_FIT_MOMENTS, RT_FIT_QUANTILE = 0, 1
 RT_MAX_CAMS = 64
 CSLOTS, NBINS = 3, 256
 
@@ -34,6 +35,7 @@ EXPORTED = ["rt_ctx_create", "rt_ctx_destroy", "rt_ctx_sizes", "rt_stats", "rt_e
             "rt_mlp_forward", "rt_mlp_backward", "rt_mlp_adam", "rt_mlp_mse", "rt_gather_rows", "rt_mlp_train",
             "rt_motion_stats", "rt_estimate_removal", "rt_frameset_removal", "rt_seam_cost",
             "rt_surrogate_frameset_static", "rt_attention",
+            "rt_cross_stats", "rt_estimate_cross", "rt_build_cross", "rt_apply_cross", "rt_frameset_cross",
             "rt_status_str", "rt_last_error"]
 RT_METHOD_NONE, RT_METHOD_REMOVAL, RT_METHOD_SMOOTHING = 0, 1, 2
 MLP_IN, MLP_HID, MLP_OUT = 576, 256, 6
@@ -48,7 +50,7 @@ class rt_camera_desc(ct.Structure):
 class rt_opts(ct.Structure):
     _fields_ = [("n_blocks", ct.c_int32), ("band_width", ct.c_int32), ("closed_ring", ct.c_int32),
                 ("mode", ct.c_int32), ("ema_alpha", ct.c_double), ("a_min", ct.c_double),
-                ("a_max", ct.c_double), ("vblend", ct.c_int32), ("reserved", ct.c_int32)]
+                ("a_max", ct.c_double), ("vblend", ct.c_int32), ("fit", ct.c_int32)]
 
 
 class rt_sizes(ct.Structure):
@@ -86,6 +88,11 @@ class rt_surrogate_work(ct.Structure):
 
 class rt_removal_opts(ct.Structure):
     _fields_ = [("tau", ct.c_int32), ("reserved", ct.c_int32), ("min_kept", ct.c_double)]
+
+
+class rt_cross_buf(ct.Structure):
+    _fields_ = [("cross", ct.c_void_p), ("params3", ct.c_void_p), ("valid3", ct.c_void_p), ("q3", ct.c_void_p),
+                ("weights", ct.c_void_p)]
 
 
 class rt_attention_opts(ct.Structure):
@@ -170,6 +177,13 @@ def load(path: str = LIB_PATH) -> ct.CDLL:
     lib.rt_seam_cost.argtypes = [P, ct.POINTER(P), ct.c_int32, P, P, P, ct.c_int32, P]
     lib.rt_attention.argtypes = [P, ct.POINTER(P), ct.POINTER(P), ct.POINTER(rt_attention_opts), P, P, P, P]
     lib.rt_ctx_apply_times.argtypes = [P, ct.POINTER(ct.c_float), ct.c_int32, ct.POINTER(ct.c_int32)]
+    X = ct.POINTER(rt_cross_buf)
+    S = ct.POINTER(rt_stats_buf)
+    lib.rt_cross_stats.argtypes = [P, ct.POINTER(P), X, P]
+    lib.rt_estimate_cross.argtypes = [P, S, X, P]
+    lib.rt_build_cross.argtypes = [P, X, P]
+    lib.rt_apply_cross.argtypes = [P, ct.POINTER(P), ct.POINTER(P), X, S, P]
+    lib.rt_frameset_cross.argtypes = [P, ct.POINTER(P), ct.POINTER(P), S, X, P]
     for name in EXPORTED:
         getattr(lib, name).restype = ct.c_int32
     lib.rt_status_str.argtypes = [ct.c_int32]
@@ -555,6 +569,60 @@ def rt_seam_cost(ctx, frames, factor, seam, interior, rows=None, row_stride: int
                                _stream_handle(stream)))
 
 
+class CrossSet:
+    """Device buffers of the cross-channel 3x3 maps of one context (shapes as
+    the C-ABI documents); the state starts as the identity, not yet valid."""
+
+    def __init__(self, sizes: "rt_sizes", device="cuda"):
+        import torch
+        K, NB = sizes.n_cams, sizes.n_blocks
+        e = dict(device=device)
+        self.cross = torch.zeros((K, 2, NB, 3), dtype=torch.int64, **e)
+        self.params3 = torch.zeros((K, 2, NB, 12), dtype=torch.float64, **e)
+        self.params3[..., 0] = 1.0
+        self.params3[..., 4] = 1.0
+        self.params3[..., 8] = 1.0
+        self.valid3 = torch.zeros((K, 2, NB), dtype=torch.uint8, **e)
+        self.q3 = torch.zeros((K, 2, NB, 12), dtype=torch.int64, **e)
+        self.weights = torch.zeros((K, sizes.w_max), dtype=torch.int16, **e)
+
+    def c(self) -> rt_cross_buf:
+        return rt_cross_buf(_p(self.cross), _p(self.params3), _p(self.valid3), _p(self.q3), _p(self.weights))
+
+    def host(self) -> dict:
+        return {k: getattr(self, k).cpu().numpy() for k in ("cross", "params3", "valid3", "q3", "weights")}
+
+
+def rt_cross_stats(ctx, frames, x: CrossSet, stream=None) -> None:
+    xb = x.c()
+    _check(load().rt_cross_stats(ctx, _ptr_array(frames), ct.byref(xb), _stream_handle(stream)))
+
+
+def rt_estimate_cross(ctx, band_sums, x: CrossSet, stream=None) -> None:
+    sb = rt_stats_buf(None, _p(band_sums), None, None)
+    xb = x.c()
+    _check(load().rt_estimate_cross(ctx, ct.byref(sb), ct.byref(xb), _stream_handle(stream)))
+
+
+def rt_build_cross(ctx, x: CrossSet, stream=None) -> None:
+    xb = x.c()
+    _check(load().rt_build_cross(ctx, ct.byref(xb), _stream_handle(stream)))
+
+
+def rt_apply_cross(ctx, frames, out_frames, x: CrossSet, whole_hist=None, whole_sums=None, stream=None) -> None:
+    xb = x.c()
+    wb = rt_stats_buf(None, None, _p(whole_hist), _p(whole_sums)) if whole_hist is not None else None
+    _check(load().rt_apply_cross(ctx, _ptr_array(frames), _ptr_array(out_frames), ct.byref(xb),
+                                 ct.byref(wb) if wb is not None else None, _stream_handle(stream)))
+
+
+def rt_frameset_cross(ctx, frames, out_frames, bufs, x: CrossSet, stream=None) -> None:
+    sb = rt_stats_buf(_p(bufs.band_hist), _p(bufs.band_sums), _p(bufs.whole_hist), _p(bufs.whole_sums))
+    xb = x.c()
+    _check(load().rt_frameset_cross(ctx, _ptr_array(frames), _ptr_array(out_frames), ct.byref(sb), ct.byref(xb),
+                                    _stream_handle(stream)))
+
+
 def rt_attention(ctx, frames, prev_frames, tau, cell, m, theta, cells, windows=None, selected=None,
                  stream=None) -> None:
     """Difference approach of the attention mechanisms (cells u32 [K][hc][wc];
@@ -628,11 +696,15 @@ class Options:
     a_min: float = 0.125
     a_max: float = 8.0
     vblend: bool = False     # blend the maps of adjacent blocks row by row
+    fit: str = "moments"     # "moments" or "quantile" (least squares on 64 quantiles)
 
     def to_c(self) -> rt_opts:
+        fits = {"moments": RT_FIT_MOMENTS, "quantile": RT_FIT_QUANTILE}
+        if self.fit not in fits:
+            raise ValueError(f"unknown fit {self.fit!r}")
         return rt_opts(self.n_blocks, self.band_width, int(self.closed_ring),
                        RT_MODE_SMOOTHING if self.smoothing else RT_MODE_STANDARD,
-                       self.ema_alpha, self.a_min, self.a_max, int(self.vblend), 0)
+                       self.ema_alpha, self.a_min, self.a_max, int(self.vblend), fits[self.fit])
 
 
 class Buffers:

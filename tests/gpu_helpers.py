@@ -25,7 +25,7 @@ def oracle_cams(cams):
 def oracle_opts(o: rt.Options) -> rc.Options:
     return rc.Options(n_blocks=o.n_blocks, band_width=o.band_width, closed_ring=o.closed_ring,
                       smoothing=o.smoothing, ema_alpha=o.ema_alpha, a_min=o.a_min, a_max=o.a_max,
-                      vblend=o.vblend)
+                      vblend=o.vblend, fit=o.fit)
 
 
 def rt_cams(spec_cams, pad: int = 0):
