@@ -775,7 +775,7 @@ def plain_leg(args, rig_spec, steps: int, warmup: int, timing_every: int):
     step_gbs = ab / (ms_step * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": "k_apply<true,true> (apply + fused whole-frame statistics)", "bytes_per_launch": ab,
+            "kernel": "k_apply<true,true,false> (apply + fused whole-frame statistics)", "bytes_per_launch": ab,
             "launch_us": round(launch_us, 2), "launch_timing": apply_where, "launches_timed": int(apply_ms.size),
             "copy_ceiling_GBs": round(copy_gbs, 1), "frac_of_copy_ceiling": round(achieved / copy_gbs, 4),
             "alone": {"launch_us": round(alone_us, 2), "achieved": round(alone_gbs, 1),
@@ -827,7 +827,7 @@ def main() -> int:
     ap.add_argument("--copy-only", action="store_true", help="time the streaming copy of the frame bytes only")
     ap.add_argument("--timing-every", type=int, default=0,
                     help="time every n-th apply launch of the timed region with HIP events "
-                         "(default: steps // 10, at least 1, so that about ten launches are timed)")
+                         "(default: steps // 5, at least 1, so that about five launches are timed)")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate training/inference leg")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-vga", action="store_true", help="skip the 1x640x480 per-call leg")
@@ -860,7 +860,7 @@ def main() -> int:
 
     torch.cuda.set_device(0)
     rig_spec = config(args.config)
-    timing_every = args.timing_every or max(1, args.steps // 10)
+    timing_every = args.timing_every or max(1, args.steps // 5)
     if args.copy_only:
         cams = [rt.Camera(c.width, c.height, c.channels, c.bit_depth, c.ring, c.pos).with_pitch()
                 for c in rig_spec.cams]
@@ -912,7 +912,7 @@ def main() -> int:
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
         us = args.uneven_steps or args.steps
-        urig, urep, _, _, _ = plain_leg(args, config("uneven"), us, args.warmup, args.timing_every or max(1, us // 10))
+        urig, urep, _, _, _ = plain_leg(args, config("uneven"), us, args.warmup, args.timing_every or max(1, us // 5))
         urig.close()
         uroof = urep.pop("roofline")
         out["uneven"] = {**urep, "steps": us, "roofline": {k: uroof[k] for k in (

@@ -572,6 +572,138 @@ __device__ void apply_run_direct(const Geo& g, const FramePtrs& fp, const Bufs& 
   if (last || kPack) flush_whole<C, 1>(g, b, t0.cam, L, 0ull, 0ull);
 }
 
+// Whether every row map blended from blocks [js, je] of camera k can be
+// evaluated directly (uniform): a blended pair lies between its two blocks'
+// pairs (floor of a convex combination plus one half), so |A| < 2^23 and
+// 255 max|A| + max|Bq + 2^15| < 2^31 over the blocks bound every row's
+// A x + Bq + 2^15 inside int32.
+__device__ inline bool vblend_direct_ok(const Geo& g, const Bufs& b, int k, int js, int je) {
+  int64_t ma = 0, mc = 0;
+  for (int j = js; j <= je; ++j)
+#pragma unroll
+    for (int sd = 0; sd < 2; ++sd)
+#pragma unroll
+      for (int c = 0; c < kCS; ++c) {
+        const int64_t u = unit_index(k, sd, j, c, g.n_blocks);
+        const int64_t A = uniform(b.q16[u * 2]), C = uniform(b.q16[u * 2 + 1]) + 32768;
+        ma = max(ma, A < 0 ? -A : A);
+        mc = max(mc, C < 0 ? -C : C);
+      }
+  return ma < (1 << 23) && 255 * ma + mc <= (int64_t)INT32_MAX;
+}
+
+// Rows whose blended direct constants fit the LDS table area.
+constexpr int kVblendRows = (int)(sizeof(ApplyLds::lut) / (2 * kCS * 2 * sizeof(int32_t)));
+
+// Apply of segments [ti, te) of one 8-bit camera with the maps blended row
+// by row (apply_tile_vblend's results), kVblendRows rows at a time: one
+// thread per row blends the row's two blocks' Q16 pairs of both sides into
+// direct constants in LDS, then every thread takes its pixels' constants of
+// each row from there and the samples follow the direct path of
+// apply_run_direct.
+template <int C, bool STATS, bool WTAB>
+__device__ void apply_run_vblend(const Geo& g, const FramePtrs& fp, const Bufs& b, int ti, int te, ApplyLds& L,
+                                 bool first, bool last) {
+  constexpr int NW = C;
+  const int tid = threadIdx.x;
+  const Tile t0 = uniform_tile(g.tiles[ti]);
+  const int R0 = t0.r0, R1 = uniform(g.tiles[te - 1].r1);
+  const DevCam cam = uniform_cam(g.cams[t0.cam]);
+  const int W = cam.width, half = cam.half, H = cam.height, nb = g.n_blocks;
+  const int pitch = (int)cam.pitch;
+  int32_t* rc = reinterpret_cast<int32_t*>(L.lut);   // [row - chunk start][side][channel][A, Bq + 2^15]
+  if (STATS && (first || kPack))
+    for (int i = tid; i < kHistWords / kCS * C; i += kThreads) L.hist[i] = 0;
+  const __amdgpu_buffer_rsrc_t rin = frame_rsrc(fp.in[t0.cam], cam);
+  const __amdgpu_buffer_rsrc_t rout = frame_rsrc(fp.out[t0.cam], cam);
+  const uint16_t* wrow = b.weights + (int64_t)t0.cam * g.w_max;
+  const int hrep = tid & (kRep - 1);
+  const int ngroups = (W + 3) >> 2;
+  unsigned long long a1 = 0, a2 = 0;
+
+  for (int c0 = R0; c0 < R1; c0 += kVblendRows) {
+    const int c1 = min(c0 + kVblendRows, R1);
+    __syncthreads();   // the previous chunk's rows are done with the table
+    if (tid < c1 - c0) {
+      int ja, jb, v;
+      vblend_row(H, nb, c0 + tid, ja, jb, v);
+#pragma unroll
+      for (int sd = 0; sd < 2; ++sd)
+#pragma unroll
+        for (int c = 0; c < kCS; ++c) {
+          const int64_t ua = unit_index(t0.cam, sd, ja, c, nb), ub = unit_index(t0.cam, sd, jb, c, nb);
+          const int i = ((tid * 2 + sd) * kCS + c) * 2;
+          rc[i] = (int32_t)blend_q16(b.q16[ua * 2], b.q16[ub * 2], v);
+          rc[i + 1] = (int32_t)(blend_q16(b.q16[ua * 2 + 1], b.q16[ub * 2 + 1], v) + 32768);
+        }
+    }
+    __syncthreads();
+    for (int grp = tid; grp < ngroups; grp += kThreads) {
+      const int col0 = grp * 4;
+      const int npx = min(4, W - col0);
+      PixConst pc;
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        const uint32_t w = p < npx ? (WTAB ? (uint32_t)wrow[col0 + p] : blend_weight(W, col0 + p)) : 0u;
+        pc.wp[p] = (256u - w) | (w << 16);
+      }
+      auto select_row = [&](int r) {
+        const int base = (r - c0) * 2 * kCS * 2;
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+          const int sb = base + (col0 + p >= half ? kCS * 2 : 0);
+#pragma unroll
+          for (int c = 0; c < kCS; ++c) {
+            pc.da[p][c] = rc[sb + c * 2];
+            pc.dc[p][c] = rc[sb + c * 2 + 1];
+          }
+        }
+      };
+      const int cbyte = col0 * C;
+      if (npx == 4) {
+        for (int row = c0; row < c1; row += kUnroll) {
+          uint32_t d[kUnroll][NW];
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u)
+            if (row + u < c1) load_group<NW>(rin, (row + u) * pitch + cbyte, d[u]);
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u) {
+            if (row + u < c1) {
+              select_row(row + u);
+              uint32_t r[4 * C], o[NW];
+#pragma unroll
+              for (int i = 0; i < 4 * C; ++i) {
+                const int p = i / C, c = i - (i / C) * C;
+                const uint32_t x = (d[u][i >> 2] >> (8 * (i & 3))) & 0xffu;
+                r[i] = one_sample<1, true, STATS, true, true>(x, c, p, pc, L, hrep, 0, 255u, a1, a2);
+              }
+#pragma unroll
+              for (int q = 0; q < NW; ++q) o[q] = pack_raw4(r[4 * q], r[4 * q + 1], r[4 * q + 2], r[4 * q + 3]);
+              store_group<NW>(rout, (row + u) * pitch + cbyte, o);
+            }
+          }
+        }
+      } else {
+        // Ragged end of the row: sample by sample, touching only the row's bytes.
+        for (int row = c0; row < c1; ++row) {
+          select_row(row);
+          const int off = row * pitch + cbyte;
+#pragma unroll
+          for (int i = 0; i < 4 * C; ++i) {
+            const int p = i / C, c = i - (i / C) * C;
+            if (p < npx) {
+              const uint32_t x = __builtin_amdgcn_raw_buffer_load_b8(rin, off + i, 0, 0);
+              const uint32_t y = one_sample<1, true, STATS, true>(x, c, p, pc, L, hrep, 0, 255u, a1, a2);
+              __builtin_amdgcn_raw_buffer_store_b8((uint8_t)y, rout, off + i, 0, 0);
+            }
+          }
+        }
+      }
+    }
+  }
+  if (STATS && (last || kPack)) flush_whole<C, 1>(g, b, t0.cam, L, 0ull, 0ull);
+}
+
 // Whether the six 8-bit maps of segment ti can be evaluated directly (uniform).
 __device__ inline bool tile_direct(const Geo& g, const Bufs& b, int ti) {
   const Tile t = uniform_tile(g.tiles[ti]);
@@ -591,13 +723,29 @@ __device__ inline bool tile_direct(const Geo& g, const Bufs& b, int ti) {
 // the camera's consecutive segments (apply_run_direct); otherwise one
 // (apply_tile).  Returns the end of the segments taken; `last` is set when
 // they end the camera's run in this workgroup.
-template <bool WRITE, bool STATS, bool WTAB>
+template <bool WRITE, bool STATS, bool WTAB, bool VBLEND = false>
 __device__ inline int apply_tile_dispatch(const Geo& g, const FramePtrs& fp, const Bufs& b, int ti, int se,
                                           ApplyLds& L, bool first) {
   const int k = uniform(g.tiles[ti].cam);
   const DevCam cam = uniform_cam(g.cams[k]);
   int te = ti + 1;
-  if (g.vblend) {
+  if constexpr (VBLEND) {
+    const int j0 = uniform(g.tiles[ti].block);
+    if (cam.bps == 1 && WRITE && RC_APPLY_DIRECT &&
+        vblend_direct_ok(g, b, k, j0 > 0 ? j0 - 1 : 0, min(j0 + 1, g.n_blocks - 1))) {
+      // A camera's consecutive segments whose blocks and neighbours fit the
+      // staging area and evaluate directly.
+      const int cap = max_tile_rows(cam.width), r0 = uniform(g.tiles[ti].r0);
+      while (te < se && uniform(g.tiles[te].cam) == k && uniform(g.tiles[te].r1) - r0 <= cap) {
+        const int jt = uniform(g.tiles[te].block);
+        if (!vblend_direct_ok(g, b, k, jt, min(jt + 1, g.n_blocks - 1))) break;
+        ++te;
+      }
+      const bool lastr = te == se || uniform(g.tiles[te].cam) != k;
+      if (cam.channels == 3) apply_run_vblend<3, STATS, WTAB>(g, fp, b, ti, te, L, first, lastr);
+      else apply_run_vblend<1, STATS, WTAB>(g, fp, b, ti, te, L, first, lastr);
+      return te;
+    }
     const bool lastv = te == se || uniform(g.tiles[te].cam) != k;
     if (cam.bps == 2) apply_tile_vblend<1, 2, WRITE, STATS, WTAB>(g, fp, b, ti, L, first, lastv);
     else if (cam.channels == 3) apply_tile_vblend<3, 1, WRITE, STATS, WTAB>(g, fp, b, ti, L, first, lastv);

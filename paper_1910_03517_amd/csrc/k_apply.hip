@@ -14,7 +14,9 @@ namespace rc {
 #ifndef RC_APPLY_WAVES
 #define RC_APPLY_WAVES 1
 #endif
-template <bool WRITE, bool STATS>
+// VBLEND: the maps of adjacent blocks blended row by row (a kernel of its own,
+// so that its registers do not weigh on the plain pass).
+template <bool WRITE, bool STATS, bool VBLEND>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(RC_APPLY_WAVES)))
 void k_apply(Geo g, FramePtrs fp, Bufs b) {
   __shared__ ApplyLds L;
@@ -26,7 +28,7 @@ void k_apply(Geo g, FramePtrs fp, Bufs b) {
       ++s;
       continue;
     }
-    s = apply_tile_dispatch<WRITE, STATS, true>(g, fp, b, s, s1, L, cam != prev);
+    s = apply_tile_dispatch<WRITE, STATS, true, VBLEND>(g, fp, b, s, s1, L, cam != prev);
     __syncthreads();
     prev = cam;
   }
@@ -37,9 +39,16 @@ void k_apply(Geo g, FramePtrs fp, Bufs b) {
 hipError_t launch_apply(const Geo& g, const FramePtrs& fp, const Bufs& b, bool write, bool stats, hipStream_t st,
                         hipEvent_t start, hipEvent_t stop) {
   const dim3 grid(g.n_wg), block(kThreads);
-  if (write && stats) hipExtLaunchKernelGGL((k_apply<true, true>), grid, block, 0, st, start, stop, 0u, g, fp, b);
-  else if (write) hipExtLaunchKernelGGL((k_apply<true, false>), grid, block, 0, st, start, stop, 0u, g, fp, b);
-  else if (stats) hipExtLaunchKernelGGL((k_apply<false, true>), grid, block, 0, st, start, stop, 0u, g, fp, b);
+  if (g.vblend && write && stats)
+    hipExtLaunchKernelGGL((k_apply<true, true, true>), grid, block, 0, st, start, stop, 0u, g, fp, b);
+  else if (g.vblend && write)
+    hipExtLaunchKernelGGL((k_apply<true, false, true>), grid, block, 0, st, start, stop, 0u, g, fp, b);
+  else if (write && stats)
+    hipExtLaunchKernelGGL((k_apply<true, true, false>), grid, block, 0, st, start, stop, 0u, g, fp, b);
+  else if (write)
+    hipExtLaunchKernelGGL((k_apply<true, false, false>), grid, block, 0, st, start, stop, 0u, g, fp, b);
+  else if (stats)
+    hipExtLaunchKernelGGL((k_apply<false, true, false>), grid, block, 0, st, start, stop, 0u, g, fp, b);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }

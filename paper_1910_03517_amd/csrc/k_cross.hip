@@ -19,6 +19,7 @@
 namespace rc {
 
 constexpr int kX3 = 12;   // parameters of one map
+constexpr int kXU = 4;    // rows in flight per thread in the apply
 
 // ----------------------------------------------------------------- statistics
 
@@ -207,37 +208,66 @@ __device__ inline bool cross_small(const int64_t (&q)[2][kX3]) {
 
 // The blended sample of channel r: f = clamp((A_r . x + B_r + 2^15) >> 16,
 // 0, 255), y = ((256 - w) x_r + w f + 128) >> 8.
-// SMALL: a32 holds the pixel's map in 32-bit form (B + 2^15 last); else a64
-// points at its side's Q16 map in LDS.
-template <bool SMALL>
-__device__ inline uint32_t cross_sample(const int32_t* a32, const int64_t* a64, uint32_t x0, uint32_t x1, uint32_t x2,
-                                        uint32_t xr, int r, uint32_t wp) {
-  uint32_t f;
-  if (SMALL) {
-    int32_t v = a32[r * 3] * (int32_t)x0 + a32[r * 3 + 1] * (int32_t)x1 + a32[r * 3 + 2] * (int32_t)x2 + a32[9 + r];
-    v >>= 16;
-    f = (uint32_t)(v < 0 ? 0 : (v > 255 ? 255 : v));
-  } else {
-    int64_t v = a64[r * 3] * (int64_t)x0 + a64[r * 3 + 1] * (int64_t)x1 + a64[r * 3 + 2] * (int64_t)x2 + a64[9 + r] +
-                32768;
-    v >>= 16;
-    f = (uint32_t)(v < 0 ? 0 : (v > 255 ? 255 : v));
+// f_r(x) = clamp((A_r . x + B_r + 2^15) >> 16, 0, 255) of one pixel, the map
+// in 32-bit form a[12] (A sign-extended from 24 bits, then B + 2^15: see
+// cross_small) or, WIDE, in 64-bit form.
+template <typename T>
+__device__ inline uint32_t cross_map(const T* a, uint32_t x0, uint32_t x1, uint32_t x2, int r) {
+  T v = a[r * 3] * (T)x0 + a[r * 3 + 1] * (T)x1 + a[r * 3 + 2] * (T)x2 + a[9 + r];
+  v >>= 16;
+  return (uint32_t)(v < 0 ? 0 : (v > 255 ? 255 : v));
+}
+
+// y = ((256 - w) x + w f + 128) >> 8 as one dot product of (x, f) with (256 - w, w).
+__device__ inline uint32_t cross_blend(uint32_t x, uint32_t f, uint32_t wp) {
+  return __builtin_amdgcn_udot2(__builtin_bit_cast(u16x2, x | (f << 16)), __builtin_bit_cast(u16x2, wp), 128u,
+                                false) >> 8;
+}
+
+// One row of a 4-pixel group: the histogram of its samples (STATS), then
+// their corrected values, the map of pixel p given by map(p, x0, x1, x2, r).
+template <bool STATS, typename Map>
+__device__ inline void cross_group(const uint32_t (&d)[3], uint32_t (&o)[3], int npx, const uint32_t (&wp)[4],
+                                   ApplyLds& L, int hrep, Map map) {
+  o[0] = o[1] = o[2] = 0u;
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    if (p < npx) {
+      uint32_t xs[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const int i = p * 3 + c;
+        xs[c] = (d[i >> 2] >> (8 * (i & 3))) & 0xffu;
+        if (STATS)
+          __hip_atomic_fetch_add(&L.hist[hist_word(c, xs[c]) * kRep + hrep], 1u << hist_shift(xs[c]),
+                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const int i = p * 3 + c;
+        o[i >> 2] |= cross_blend(xs[c], map(p, xs[0], xs[1], xs[2], c), wp[p]) << (8 * (i & 3));
+      }
+    }
   }
-  const uint32_t xf = xr | (f << 16);
-  return __builtin_amdgcn_udot2(__builtin_bit_cast(u16x2, xf), __builtin_bit_cast(u16x2, wp), 128u, false) >> 8;
 }
 
 // Segment ti with the cross-channel maps of its block; optional whole-frame
-// statistics as in the plain apply (first clears, last flushes).
+// statistics as in the plain apply (first clears, last flushes).  SMALL (the
+// maps fit 32-bit arithmetic, cross_small): the groups of four pixels that
+// lie on one side take that side's map, the same for every lane (so it stays
+// in scalar registers), with kXU rows of loads in flight.  The group holding
+// the image centre, and every group when the maps need 64-bit arithmetic, go
+// sample by sample with the map read from LDS.
 template <bool STATS, bool SMALL>
-__device__ __attribute__((always_inline)) void cross_tile(const Geo& g, const FramePtrs& fp, const Bufs& b, const CrossBufs& x, int ti,
-                           ApplyLds& L, bool first, bool last, const int64_t (&q)[2][kX3]) {
+__device__ __attribute__((always_inline)) void cross_tile(const Geo& g, const FramePtrs& fp, const Bufs& b,
+                                                          const CrossBufs& x, int ti, ApplyLds& L, bool first,
+                                                          bool last, const int64_t (&q)[2][kX3]) {
   const int tid = threadIdx.x;
   const Tile t = uniform_tile(g.tiles[ti]);
   const DevCam cam = uniform_cam(g.cams[t.cam]);
   const int W = cam.width, half = cam.half, pitch = (int)cam.pitch;
-  int64_t* qs = reinterpret_cast<int64_t*>(L.lut);   // [side][12] for the 64-bit path
-  if (!SMALL && tid < 2 * kX3) qs[tid] = x.q3[(((int64_t)t.cam * 2 + tid / kX3) * g.n_blocks + t.block) * kX3 + tid % kX3];
+  int64_t* qs = reinterpret_cast<int64_t*>(L.lut);   // [side][12]
+  if (tid < 2 * kX3) qs[tid] = x.q3[(((int64_t)t.cam * 2 + tid / kX3) * g.n_blocks + t.block) * kX3 + tid % kX3];
   if (STATS && first)
     for (int i = tid; i < kHistWords; i += kThreads) L.hist[i] = 0;
   __syncthreads();
@@ -246,64 +276,108 @@ __device__ __attribute__((always_inline)) void cross_tile(const Geo& g, const Fr
   const uint16_t* wrow = x.weights + (int64_t)t.cam * g.w_max;
   const int hrep = tid & (kRep - 1);
   const int ngroups = (W + 3) >> 2;
-  for (int grp = tid; grp < ngroups; grp += kThreads) {
+  // Both sides' maps in 32-bit form (uniform).
+  int32_t aL[kX3], aR[kX3];
+#pragma unroll
+  for (int i = 0; i < kX3; ++i) {
+    aL[i] = i >= 9 ? (int32_t)(q[0][i] + 32768) : (int32_t)((uint32_t)q[0][i] << 8) >> 8;
+    aR[i] = i >= 9 ? (int32_t)(q[1][i] + 32768) : (int32_t)((uint32_t)q[1][i] << 8) >> 8;
+  }
+  // Group grp (four pixels) of every row of the segment: mode 0 / 1 all on
+  // the left / right side with that side's map, 2 sample by sample.
+  auto do_group = [&](int grp, int mode) {
     const int col0 = grp * 4, npx = min(4, W - col0);
     uint32_t wp[4];
-    int32_t a32[4][SMALL ? kX3 : 1];
-    int sdp[4];
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
       const uint32_t w = p < npx ? (uint32_t)wrow[col0 + p] : 0u;
       wp[p] = (256u - w) | (w << 16);
-      sdp[p] = col0 + p >= half ? 1 : 0;
-      if (SMALL) {
-#pragma unroll
-        for (int i = 0; i < kX3; ++i) {
-          const int64_t v = sdp[p] ? q[1][i] : q[0][i];
-          // Sign-extended from 24 bits (cross_small): the products are 24-bit multiplies.
-          a32[p][i] = i >= 9 ? (int32_t)(v + 32768) : (int32_t)((uint32_t)v << 8) >> 8;
-        }
-      }
     }
-    for (int row = t.r0; row < t.r1; ++row) {
-      const int off = row * pitch + col0 * 3;
-      uint32_t d[3] = {0u, 0u, 0u};
-      if (npx == 4) {
-        load_group<3>(rin, off, d);
-      } else {
+    auto rows_one_side = [&](const int32_t (&a)[kX3]) {
+      auto map = [&](int, uint32_t x0, uint32_t x1, uint32_t x2, int r) {
+        return cross_map<int32_t>(a, x0, x1, x2, r);
+      };
+      for (int row = t.r0; row < t.r1; row += kXU) {
+        uint32_t d[kXU][3];
 #pragma unroll
-        for (int i = 0; i < 12; ++i)
-          if (i < 3 * npx) d[i >> 2] |= (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(rin, off + i, 0, 0) << (8 * (i & 3));
-      }
-      uint32_t o[3] = {0u, 0u, 0u};
+        for (int u = 0; u < kXU; ++u) {
+          const int off = (row + u) * pitch + col0 * 3;
+          if (row + u < t.r1) {
+            if (npx == 4) {
+              load_group<3>(rin, off, d[u]);
+            } else {
+              d[u][0] = d[u][1] = d[u][2] = 0u;
 #pragma unroll
-      for (int p = 0; p < 4; ++p) {
-        if (p < npx) {
-          uint32_t xs[3];
-#pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            const int i = p * 3 + c;
-            xs[c] = (d[i >> 2] >> (8 * (i & 3))) & 0xffu;
-            if (STATS)
-              __hip_atomic_fetch_add(&L.hist[hist_word(c, xs[c]) * kRep + hrep], 1u << hist_shift(xs[c]),
-                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+              for (int i = 0; i < 12; ++i)
+                if (i < 3 * npx)
+                  d[u][i >> 2] |= (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(rin, off + i, 0, 0) << (8 * (i & 3));
+            }
           }
+        }
 #pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            const int i = p * 3 + c;
-            const uint32_t y = cross_sample<SMALL>(a32[p], qs + sdp[p] * kX3, xs[0], xs[1], xs[2], xs[c], c, wp[p]);
-            o[i >> 2] |= y << (8 * (i & 3));
+        for (int u = 0; u < kXU; ++u) {
+          if (row + u < t.r1) {
+            const int off = (row + u) * pitch + col0 * 3;
+            uint32_t o[3];
+            cross_group<STATS>(d[u], o, npx, wp, L, hrep, map);
+            if (npx == 4) {
+              store_group<3>(rout, off, o);
+            } else {
+#pragma unroll
+              for (int i = 0; i < 12; ++i)
+                if (i < 3 * npx)
+                  __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(o[i >> 2] >> (8 * (i & 3))), rout, off + i, 0, 0);
+            }
           }
         }
       }
-      if (npx == 4) {
-        store_group<3>(rout, off, o);
-      } else {
-#pragma unroll
-        for (int i = 0; i < 12; ++i)
-          if (i < 3 * npx) __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(o[i >> 2] >> (8 * (i & 3))), rout, off + i, 0, 0);
+    };
+    if (SMALL && mode == 0) {
+      rows_one_side(aL);
+    } else if (SMALL && mode == 1) {
+      rows_one_side(aR);
+    } else {
+      // Sample by sample in 64-bit integers (exact for every map).
+      for (int row = t.r0; row < t.r1; ++row) {
+        const int off = row * pitch + col0 * 3;
+#pragma unroll 1
+        for (int p = 0; p < npx; ++p) {
+          const uint32_t x0 = __builtin_amdgcn_raw_buffer_load_b8(rin, off + 3 * p, 0, 0);
+          const uint32_t x1 = __builtin_amdgcn_raw_buffer_load_b8(rin, off + 3 * p + 1, 0, 0);
+          const uint32_t x2 = __builtin_amdgcn_raw_buffer_load_b8(rin, off + 3 * p + 2, 0, 0);
+          if (STATS) {
+            __hip_atomic_fetch_add(&L.hist[hist_word(0, x0) * kRep + hrep], 1u << hist_shift(x0), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_fetch_add(&L.hist[hist_word(1, x1) * kRep + hrep], 1u << hist_shift(x1), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_fetch_add(&L.hist[hist_word(2, x2) * kRep + hrep], 1u << hist_shift(x2), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+          }
+          const int base = col0 + p >= half ? kX3 : 0;
+          const uint32_t w = (uint32_t)wrow[col0 + p], wpp = (256u - w) | (w << 16);
+#pragma unroll 1
+          for (int c = 0; c < 3; ++c) {
+            int64_t v = qs[base + c * 3] * (int64_t)x0 + qs[base + c * 3 + 1] * (int64_t)x1 +
+                        qs[base + c * 3 + 2] * (int64_t)x2 + qs[base + 9 + c] + 32768;
+            v >>= 16;
+            const uint32_t f = (uint32_t)(v < 0 ? 0 : (v > 255 ? 255 : v));
+            const uint32_t xc = c == 0 ? x0 : (c == 1 ? x1 : x2);
+            __builtin_amdgcn_raw_buffer_store_b8((uint8_t)cross_blend(xc, f, wpp), rout, off + 3 * p + c, 0, 0);
+          }
+        }
       }
     }
+  };
+  if (SMALL) {
+    // Threads take the all-left groups, then the all-right ones, so that
+    // every wave but the last of each run follows one side's path; the group
+    // holding the image centre (when half % 4 != 0) goes sample by sample.
+    const int gL = half >> 2, gR = (half + 3) >> 2;
+    for (int i = tid; i < gL; i += kThreads) do_group(i, 0);
+    for (int i = tid; i < ngroups - gR; i += kThreads) do_group(gR + i, 1);
+    if (gR > gL && tid == 0) do_group(gL, 2);
+  } else {
+    for (int grp = tid; grp < ngroups; grp += kThreads) do_group(grp, 2);
   }
   if (STATS && (last || kPack)) flush_whole<3, 1>(g, b, t.cam, L, 0ull, 0ull);
 }

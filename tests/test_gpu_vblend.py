@@ -2,7 +2,9 @@
 convex combinations of adjacent maps, option vblend) against the oracle:
 corrected frames bit for bit (with and without the fused whole-frame
 statistics, which stay bit-exact), over small ragged rigs of every sample
-type, random per-block maps, and whole frame-sets up to the 14x1920x1080 rig."""
+type, random per-block maps (the row-blended direct path of 8-bit maps and
+the per-sample path of maps beyond 24 bits and of 16-bit samples), and whole
+frame-sets up to the 14x1920x1080 rig."""
 import numpy as np
 import pytest
 
@@ -64,6 +66,39 @@ def test_vblend_apply_random_maps(case):
                 wh, ws = rc.whole_stats(frames[k], co[k])
                 assert_ints_equal(h["whole_hist"][k], wh, f"cam {k} whole_hist")
                 assert_ints_equal(h["whole_sums"][k], ws, f"cam {k} whole_sums")
+    rig.close()
+
+
+def test_vblend_apply_maps_beyond_24_bits():
+    """8-bit maps with gains of a few hundred (|A| >= 2^23) cannot be
+    evaluated in 32-bit integers: those segments take the per-sample 64-bit
+    path, the others the row-blended direct one, in the same launch."""
+    rng = np.random.default_rng(63)
+    W, H, K, NB = 96, 48, 2, 6
+    spec = [synth.CamSpec(W, H, 3, 8, 0, p) for p in range(K)]
+    cams = rt_cams(spec, pad=1)
+    opts = rt.Options(n_blocks=NB, band_width=8, vblend=True)
+    rig = rt.Rig(cams, opts)
+    co, oo = oracle_cams(cams), oracle_opts(opts)
+    frames = [synth.tiny_frame(H, W, 3, 8, rng) for _ in range(K)]
+    dev, out = rig.upload(frames), rig.alloc_frames()
+    params = np.zeros(tuple(rig.bufs.params.shape))
+    params[..., 0] = rng.uniform(0.5, 2.0, params.shape[:-1])
+    params[..., 1] = rng.uniform(-40, 40, params.shape[:-1])
+    params[1, :, 3:, :, 0] = rng.uniform(150, 300, params[1, :, 3:, :, 0].shape)    # camera 1, lower blocks
+    rig.bufs.params.copy_(torch.as_tensor(params, device="cuda"))
+    rig.bufs.valid.fill_(1)
+    rig.build_lut()
+    assert np.abs(rig.bufs.host()["q16"][1, :, 3:, :, 0]).min() >= 1 << 23
+    for whole in (True, False):
+        rig.apply(dev, out, whole=whole)
+        torch.cuda.synchronize()
+        h = rig.bufs.host()
+        for k, g in enumerate(rig.download(out)):
+            assert_ints_equal(g, rc.apply_camera(frames[k], co[k], oo, h["lut8"][k], h["q16"][k]), f"cam {k} whole={whole}")
+        if whole:
+            for k in range(K):
+                assert_ints_equal(h["whole_hist"][k], rc.whole_stats(frames[k], co[k])[0], f"cam {k} whole_hist")
     rig.close()
 
 
