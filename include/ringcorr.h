@@ -254,7 +254,9 @@ rt_status rt_ctx_set_active(rt_ctx* ctx, uint64_t active);
  * lanes may run concurrently.  Applies are issued `group` frame-sets at a
  * time (when the group is full, or at rt_pipe_join): one cross-stream
  * dependency per lane and group instead of one per frame-set, which is what
- * bounds the host's submission rate.  Consecutive frame-sets rotate over
+ * bounds the host's submission rate; the first `lanes` frame-sets after the
+ * pipeline's creation or an rt_pipe_join are issued one at a time, so that
+ * an idle pipeline fills at once.  Consecutive frame-sets rotate over
  * `depth` table and whole-frame-statistics slots (luts[depth], wholes[depth],
  * all distinct); the statistics of frame-set t wait for the apply of
  * frame-set t - depth (depth >= 2 * group lets stream E run a group ahead of

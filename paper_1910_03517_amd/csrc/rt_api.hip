@@ -811,6 +811,7 @@ struct rt_pipe {
   std::vector<Pending> pending;                  // estimated, apply not yet issued
   hipStream_t caller = nullptr;                  // lane 0 of the pending applies
   int64_t submitted = 0, groups = 0;
+  int warm = 0;                                  // frame-sets since creation or the last join (capped)
 };
 
 // Issues the pending applies as one group (see above).
@@ -927,7 +928,10 @@ static rt_status pipe_submit(rt_pipe* p, uint64_t active, const void* const* fra
   if (e == hipSuccess) e = launch_band_estimate(g, fp, be, p->s_est);
   if (e == hipSuccess) {
     p->pending.push_back({fp, active, (hipEvent_t)done_event, slot, (int)(p->submitted % p->lanes)});
-    if ((int)p->pending.size() == p->group) e = pipe_flush(p);
+    // An idle pipeline issues its first `lanes` applies one at a time, so
+    // that they do not wait for a full group of estimates.
+    if ((int)p->pending.size() == p->group || p->warm < p->lanes) e = pipe_flush(p);
+    if (p->warm < p->lanes) ++p->warm;
   }
   if (e != hipSuccess) return hip_fail(e, "pipeline submit");
   if (slot_out) *slot_out = slot;
@@ -952,6 +956,7 @@ rt_status rt_pipe_submit_batch(rt_pipe* p, uint64_t active, const void* const* f
 rt_status rt_pipe_join(rt_pipe* p, void* stream) {
   if (!p) return fail(RT_EINVAL, "pipe is NULL");
   hipError_t e = pipe_flush(p);
+  p->warm = 0;
   for (int l = 0; e == hipSuccess && l < p->lanes; ++l)
     if (p->last_group[l] >= 0) e = hipStreamWaitEvent((hipStream_t)stream, p->ev_lane[p->last_group[l]][l], 0);
   return e == hipSuccess ? RT_OK : hip_fail(e, "pipeline join");
