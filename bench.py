@@ -696,6 +696,30 @@ def plain_leg(args, rig_spec, steps: int, warmup: int, timing_every: int):
         else:
             rig.frameset(ins[i % args.nbuf], outs[i % args.nbuf])
 
+    # The pipe takes the timed frame-sets a group at a time in one library
+    # call each (rt_pipe_submit_n, pointer arrays built beforehand).
+    chunks = {}
+    if pipe is not None:
+        for j in range(args.nbuf):
+            idx = [(j + u) % args.nbuf for u in range(group)]
+            chunks[j] = (rt.ptr_array_n([ins[x] for x in idx]), rt.ptr_array_n([outs[x] for x in idx]), group)
+
+    def steps_from(i0, n):
+        if pipe is None:
+            for i in range(n):
+                step(i0 + i)
+            return
+        i = 0
+        while i < n:
+            c = min(group, n - i)
+            j = (i0 + i) % args.nbuf
+            if c == group:
+                pipe.submit_n(None, None, stream, ptrs=chunks[j])
+            else:
+                for u in range(c):
+                    step(i0 + i + u)
+            i += c
+
     log(f"{rig_spec.name}: timing {steps} steps ({args.mode})")
     for i in range(warmup):
         step(i)
@@ -713,8 +737,7 @@ def plain_leg(args, rig_spec, steps: int, warmup: int, timing_every: int):
     torch.cuda.synchronize()
     w0 = time.perf_counter()
     ev0.record(stream)
-    for i in range(steps):
-        step(first + i)
+    steps_from(first, steps)
     if pipe is not None:
         pipe.join(stream)
     ev1.record(stream)

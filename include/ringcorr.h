@@ -286,6 +286,16 @@ rt_status rt_pipe_submit(rt_pipe* p, const void* const* frames, void* const* out
 rt_status rt_pipe_join(rt_pipe* p, void* stream);
 rt_status rt_pipe_destroy(rt_pipe* p);
 
+/* n consecutive rt_pipe_submit calls (no ready event) in one: frame-set i
+ * reads frames[i * K + k] and writes out_frames[i * K + k] for camera k of
+ * the context's K cameras.  slots_out (may be NULL) receives the n slots.  A
+ * frame-set that fails validation stops the call with its error; the ones
+ * before it stay submitted and *n_done (may be NULL) says how many were.
+ * For hosts that hold several frame-sets at once (recorded video, a
+ * benchmark), it saves one call into the library per frame-set. */
+rt_status rt_pipe_submit_n(rt_pipe* p, int32_t n, const void* const* frames, void* const* out_frames, void* stream,
+                           int32_t* slots_out, int32_t* n_done);
+
 /* rt_pipe_submit for the cameras in bitmask `active` only (whole rings, as
  * for rt_frameset_batch; the frames and out_frames entries of the other
  * cameras may be NULL), for serving several rigs from one context: the

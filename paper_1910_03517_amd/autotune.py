@@ -160,22 +160,23 @@ def time_pipe(rig, frames, outs, lanes: int, group: int, depth: int = 8, steps: 
     n = len(frames)
     stream = torch.cuda.current_stream()
     pipe = rt.Pipe.for_rig(rig, depth=depth, lanes=lanes, group=group)
-    ip = [rt.ptr_array(x) for x in frames]
-    op = [rt.ptr_array(x) for x in outs]
+    # A group of frame-sets per library call, as the bench submits them.
+    chunks = [(rt.ptr_array_n([frames[(j + u) % n] for u in range(group)]),
+               rt.ptr_array_n([outs[(j + u) % n] for u in range(group)]), group) for j in range(n)]
     try:
-        for i in range(warmup):
-            pipe.submit(frames[i % n], outs[i % n], stream, ip[i % n], op[i % n])
+        for i in range(0, warmup - warmup % group, group):
+            pipe.submit_n(None, None, stream, ptrs=chunks[i % n])
         pipe.join(stream)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        timed = steps - steps % group
         e0.record(stream)
-        for i in range(steps):
-            j = (warmup + i) % n
-            pipe.submit(frames[j], outs[j], stream, ip[j], op[j])
+        for i in range(0, timed, group):
+            pipe.submit_n(None, None, stream, ptrs=chunks[(warmup + i) % n])
         pipe.join(stream)
         e1.record(stream)
         torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / steps * 1e3
+        return e0.elapsed_time(e1) / timed * 1e3
     finally:
         pipe.close()
 

@@ -953,6 +953,24 @@ rt_status rt_pipe_submit_batch(rt_pipe* p, uint64_t active, const void* const* f
   return pipe_submit(p, active, frames, out_frames, stream, ready_event, done_event, slot_out);
 }
 
+rt_status rt_pipe_submit_n(rt_pipe* p, int32_t n, const void* const* frames, void* const* out_frames, void* stream,
+                           int32_t* slots_out, int32_t* n_done) {
+  if (n_done) *n_done = 0;
+  if (!p) return fail(RT_EINVAL, "pipe is NULL");
+  if (n < 0) return fail(RT_EINVAL, "n %d < 0", n);
+  if (n > 0 && (!frames || !out_frames)) return fail(RT_EINVAL, "frames or out_frames is NULL");
+  const int K = p->ctx->n_cams;
+  for (int i = 0; i < n; ++i) {
+    int32_t slot = 0;
+    const rt_status r = pipe_submit(p, p->ctx->geo.active, frames + (int64_t)i * K, out_frames + (int64_t)i * K,
+                                    stream, nullptr, nullptr, &slot);
+    if (r != RT_OK) return r;
+    if (slots_out) slots_out[i] = slot;
+    if (n_done) *n_done = i + 1;
+  }
+  return RT_OK;
+}
+
 rt_status rt_pipe_join(rt_pipe* p, void* stream) {
   if (!p) return fail(RT_EINVAL, "pipe is NULL");
   hipError_t e = pipe_flush(p);

@@ -29,7 +29,7 @@ EXPORTED = ["rt_ctx_create", "rt_ctx_destroy", "rt_ctx_sizes", "rt_stats", "rt_e
             "rt_build_lut", "rt_apply", "rt_frameset", "rt_frameset_batch", "rt_ctx_set_active", "rt_ctx_check", "rt_ctx_tune", "rt_ctx_tuning",
             "rt_stream_copy", "rt_ctx_timing", "rt_ctx_apply_times", "rt_graph_create", "rt_graph_launch",
             "rt_graph_destroy", "rt_pipe_create", "rt_pipe_submit", "rt_pipe_destroy",
-            "rt_pipe_create_lanes", "rt_pipe_join", "rt_pipe_submit_batch",
+            "rt_pipe_create_lanes", "rt_pipe_join", "rt_pipe_submit_batch", "rt_pipe_submit_n",
             "rt_surrogate_features", "rt_estimate_new", "rt_surrogate_targets", "rt_surrogate_select",
             "rt_surrogate_frameset",
             "rt_mlp_forward", "rt_mlp_backward", "rt_mlp_adam", "rt_mlp_mse", "rt_gather_rows", "rt_mlp_train",
@@ -142,6 +142,8 @@ def load(path: str = LIB_PATH) -> ct.CDLL:
     lib.rt_pipe_create.argtypes = [P, ct.c_int32, ct.POINTER(rt_stats_buf), ct.POINTER(rt_params_buf),
                                    ct.POINTER(rt_lut_buf), ct.POINTER(rt_stats_buf), ct.POINTER(P)]
     lib.rt_pipe_submit.argtypes = [P, ct.POINTER(P), ct.POINTER(P), P, P, ct.POINTER(ct.c_int32)]
+    lib.rt_pipe_submit_n.argtypes = [P, ct.c_int32, ct.POINTER(P), ct.POINTER(P), P, ct.POINTER(ct.c_int32),
+                                     ct.POINTER(ct.c_int32)]
     lib.rt_pipe_destroy.argtypes = [P]
     lib.rt_pipe_create_lanes.argtypes = [P, ct.c_int32, ct.c_int32, ct.c_int32, ct.POINTER(rt_stats_buf),
                                          ct.POINTER(rt_params_buf), ct.POINTER(rt_lut_buf), ct.POINTER(rt_stats_buf),
@@ -204,6 +206,12 @@ def _stream_handle(stream) -> ct.c_void_p:
         import torch
         stream = torch.cuda.current_stream()
     return ct.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def ptr_array_n(frame_sets) -> ct.Array:
+    """Device pointers of several frame-sets back to back (rt_pipe_submit_n's layout)."""
+    flat = [t for fs in frame_sets for t in fs]
+    return _ptr_array(flat)
 
 
 def _ptr_array(tensors) -> ct.Array:
@@ -328,6 +336,19 @@ class Pipe:
         ev = ct.c_void_p(ready_event.cuda_event) if ready_event is not None else None
         _check(load().rt_pipe_submit(self.handle, fa, oa, _stream_handle(stream), ev, ct.byref(self._slot)))
         return self._slot.value
+
+    def submit_n(self, frames_list, outs_list, stream=None, ptrs=None) -> list:
+        """Several frame-sets in one library call (rt_pipe_submit_n); ptrs may
+        pass prebuilt (frames, outs, n) from ptr_array_n (frames_list and
+        outs_list are then ignored).  Returns the slots."""
+        if ptrs is not None:
+            fa, oa, n = ptrs
+        else:
+            fa, oa, n = ptr_array_n(frames_list), ptr_array_n(outs_list), len(frames_list)
+        slots = (ct.c_int32 * n)()
+        done = ct.c_int32()
+        _check(load().rt_pipe_submit_n(self.handle, n, fa, oa, _stream_handle(stream), slots, ct.byref(done)))
+        return list(slots)
 
     def submit_batch(self, active: int, frames, out_frames, stream=None, ready_event=None, done_event=None) -> int:
         """submit() for the cameras in bitmask `active` (whole rings); entries of

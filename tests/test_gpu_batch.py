@@ -2,6 +2,7 @@
 context.  Every step is compared with the oracle (bit-exact statistics,
 tables, pixels; parameters bitwise), each ring's results in the mix equal
 those of the ring served alone, and nothing of an inactive camera changes."""
+import ctypes as ct
 import numpy as np
 import pytest
 
@@ -217,3 +218,54 @@ def test_pipe_submit_batch_validation():
     rig.check()
     rig.close()
 
+
+
+def test_pipe_submit_n_matches_single_submits():
+    """rt_pipe_submit_n over 7 frame-sets (groups of 3, the last partial)
+    gives the outputs, whole-frame statistics and state of seven single
+    submits; a frame-set with a missing frame stops the call after the ones
+    before it, which stay submitted."""
+    spec = synth.RigSpec("submit_n 3x96x64", 77, [synth.CamSpec(96, 64, 3, 8, 0, p) for p in range(3)])
+    cams = rt_cams(spec.cams)
+    frames = [synth.rig_frames(spec, t, drift=True) for t in range(7)]
+    results = {}
+    for how in ("single", "n"):
+        rig = rt.Rig(cams, rt.Options(n_blocks=4, smoothing=True))
+        pipe = rt.Pipe.for_rig(rig, depth=8, lanes=3, group=3)
+        dev = [rig.upload(f) for f in frames]
+        outs = [rig.alloc_frames() for _ in frames]
+        torch.cuda.synchronize()
+        if how == "single":
+            slots = [pipe.submit(dev[t], outs[t]) for t in range(7)]
+        else:
+            slots = pipe.submit_n(dev[:4], outs[:4]) + pipe.submit_n(dev[4:], outs[4:])
+        pipe.join()
+        torch.cuda.synchronize()
+        rig.check()
+        results[how] = ([rig.download(o) for o in outs], rig.bufs.host()["params"],
+                        pipe.whole[slots[-1]].whole_hist.cpu().numpy(), slots)
+        pipe.close()
+        rig.close()
+    a, b = results["single"], results["n"]
+    assert a[3] == b[3]
+    for t in range(7):
+        for k in range(3):
+            assert np.array_equal(a[0][t][k], b[0][t][k]), (t, k)
+    assert np.array_equal(a[1].view(np.uint64), b[1].view(np.uint64))
+    assert np.array_equal(a[2], b[2])
+    rig = rt.Rig(cams, rt.Options(n_blocks=4))
+    pipe = rt.Pipe.for_rig(rig, depth=4, lanes=2, group=2)
+    dev = [rig.upload(f) for f in frames[:3]]
+    outs = [rig.alloc_frames() for _ in range(3)]
+    fa = rt.ptr_array_n(dev)
+    fa[4] = None                                   # camera 1 of frame-set 1
+    oa = rt.ptr_array_n(outs)
+    slots = (ct.c_int32 * 3)()
+    done = ct.c_int32()
+    st = rt.load().rt_pipe_submit_n(pipe.handle, 3, fa, oa, None, slots, ct.byref(done))
+    assert st == rt.RT_EINVAL and done.value == 1
+    pipe.join()
+    torch.cuda.synchronize()
+    rig.check()
+    pipe.close()
+    rig.close()
