@@ -101,6 +101,15 @@ int main(void) {
   { rt_opts b = o; b.ema_alpha = 0.0 / 0.0; refuse(&good, 1, &b, RT_EINVAL, "alpha NaN"); }
   { rt_opts b = o; b.a_min = 2.0; b.a_max = 1.0; refuse(&good, 1, &b, RT_EINVAL, "a_min > a_max"); }
   { rt_opts b = o; b.a_max = 1.0 / 0.0; refuse(&good, 1, &b, RT_EINVAL, "a_max inf"); }
+  { rt_opts b = o; b.vblend = 2; refuse(&good, 1, &b, RT_EINVAL, "vblend 2"); }
+  { rt_opts b = o; b.fit = 7; refuse(&good, 1, &b, RT_EINVAL, "fit 7"); }
+  { rt_opts b = o; b.fit = -1; refuse(&good, 1, &b, RT_EINVAL, "fit -1"); }
+  {
+    rt_camera_desc c = cam(32, 8, 3, 8, 0, 0, 96);
+    rt_opts b = o;
+    b.vblend = 1;
+    refuse(&c, 1, &b, RT_EUNSUPPORTED, "vblend with fewer rows than blocks");
+  }
 
   /* Cameras. */
   { rt_camera_desc c = cam(0, 32, 3, 8, 0, 0, 192); refuse(&c, 1, &o, RT_EINVAL, "width 0"); }
@@ -153,6 +162,17 @@ int main(void) {
   EXPECT(rt_mlp_forward(NULL, NULL, 1, NULL, NULL, NULL, NULL) == RT_EINVAL, "mlp_forward NULL");
   EXPECT(rt_mlp_mse(NULL, NULL, 1, NULL, NULL) == RT_EINVAL, "mlp_mse NULL");
   EXPECT(rt_gather_rows(NULL, 1, NULL, 1, NULL, NULL) == RT_EINVAL, "gather NULL");
+  {
+    int32_t done = 5;
+    EXPECT(rt_pipe_submit_n(NULL, 2, NULL, NULL, NULL, NULL, &done) == RT_EINVAL && done == 0, "pipe_submit_n NULL");
+  }
+  EXPECT(rt_cross_stats(NULL, NULL, NULL, NULL) == RT_EINVAL, "cross_stats NULL");
+  EXPECT(rt_estimate_cross(NULL, NULL, NULL, NULL) == RT_EINVAL, "estimate_cross NULL");
+  EXPECT(rt_build_cross(NULL, NULL, NULL) == RT_EINVAL, "build_cross NULL");
+  EXPECT(rt_apply_cross(NULL, NULL, NULL, NULL, NULL, NULL) == RT_EINVAL, "apply_cross NULL");
+  EXPECT(rt_frameset_cross(NULL, NULL, NULL, NULL, NULL, NULL) == RT_EINVAL, "frameset_cross NULL");
+  EXPECT(rt_seam_cost(NULL, NULL, 8, NULL, NULL, NULL, 0, NULL) == RT_EINVAL, "seam_cost NULL");
+  EXPECT(rt_attention(NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL) == RT_EINVAL, "attention NULL");
 
   /* A message longer than the formatting buffer is truncated, not overrun. */
   {
