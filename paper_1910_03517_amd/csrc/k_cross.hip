@@ -208,47 +208,44 @@ __device__ inline bool cross_small(const int64_t (&q)[2][kX3]) {
 
 // The blended sample of channel r: f = clamp((A_r . x + B_r + 2^15) >> 16,
 // 0, 255), y = ((256 - w) x_r + w f + 128) >> 8.
-// f_r(x) = clamp((A_r . x + B_r + 2^15) >> 16, 0, 255) of one pixel, the map
-// in 32-bit form a[12] (A sign-extended from 24 bits, then B + 2^15: see
-// cross_small) or, WIDE, in 64-bit form.
-template <typename T>
-__device__ inline uint32_t cross_map(const T* a, uint32_t x0, uint32_t x1, uint32_t x2, int r) {
-  T v = a[r * 3] * (T)x0 + a[r * 3 + 1] * (T)x1 + a[r * 3 + 2] * (T)x2 + a[9 + r];
-  v >>= 16;
-  return (uint32_t)(v < 0 ? 0 : (v > 255 ? 255 : v));
-}
-
 // y = ((256 - w) x + w f + 128) >> 8 as one dot product of (x, f) with (256 - w, w).
 __device__ inline uint32_t cross_blend(uint32_t x, uint32_t f, uint32_t wp) {
   return __builtin_amdgcn_udot2(__builtin_bit_cast(u16x2, x | (f << 16)), __builtin_bit_cast(u16x2, wp), 128u,
                                 false) >> 8;
 }
 
-// One row of a 4-pixel group: the histogram of its samples (STATS), then
-// their corrected values, the map of pixel p given by map(p, x0, x1, x2, r).
-template <bool STATS, typename Map>
-__device__ inline void cross_group(const uint32_t (&d)[3], uint32_t (&o)[3], int npx, const uint32_t (&wp)[4],
-                                   ApplyLds& L, int hrep, Map map) {
-  o[0] = o[1] = o[2] = 0u;
+// One row of a 4-pixel group with a 32-bit map a (B + 2^15 last) shared by
+// its four pixels: the histogram of its samples (STATS), then per sample the
+// map clamped in place, clamp(v, 0, 2^24 - 1) & 0xffff0000 = f << 16 for the
+// arithmetic v >> 16 (so f lands in the high half next to x), the blend as
+// one dot product, and the four results of a dword gathered by byte permutes.
+template <bool STATS>
+__device__ inline void cross_group_fast(const uint32_t (&d)[3], uint32_t (&o)[3], int npx, const uint32_t (&wp)[4],
+                                        ApplyLds& L, int hrep, const int32_t (&a)[kX3]) {
+  uint32_t raw[12];
 #pragma unroll
   for (int p = 0; p < 4; ++p) {
-    if (p < npx) {
-      uint32_t xs[3];
+    uint32_t xs[3];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const int i = p * 3 + c;
-        xs[c] = (d[i >> 2] >> (8 * (i & 3))) & 0xffu;
-        if (STATS)
-          __hip_atomic_fetch_add(&L.hist[hist_word(c, xs[c]) * kRep + hrep], 1u << hist_shift(xs[c]),
-                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-      }
+    for (int c = 0; c < 3; ++c) {
+      const int i = p * 3 + c;
+      xs[c] = (d[i >> 2] >> (8 * (i & 3))) & 0xffu;
+      if (STATS && p < npx)
+        __hip_atomic_fetch_add(&L.hist[hist_word(c, xs[c]) * kRep + hrep], 1u << hist_shift(xs[c]), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const int i = p * 3 + c;
-        o[i >> 2] |= cross_blend(xs[c], map(p, xs[0], xs[1], xs[2], c), wp[p]) << (8 * (i & 3));
-      }
+    for (int r = 0; r < 3; ++r) {
+      int32_t v = a[r * 3] * (int32_t)xs[0] + a[r * 3 + 1] * (int32_t)xs[1] + a[r * 3 + 2] * (int32_t)xs[2] + a[9 + r];
+      v = v < 0 ? 0 : (v > 0xffffff ? 0xffffff : v);
+      const uint32_t xf = ((uint32_t)v & 0xffff0000u) | xs[r];
+      raw[p * 3 + r] = p < npx ? __builtin_amdgcn_udot2(__builtin_bit_cast(u16x2, xf),
+                                                        __builtin_bit_cast(u16x2, wp[p]), 128u, false)
+                               : 0u;
     }
   }
+#pragma unroll
+  for (int q = 0; q < 3; ++q) o[q] = pack_raw4(raw[4 * q], raw[4 * q + 1], raw[4 * q + 2], raw[4 * q + 3]);
 }
 
 // Segment ti with the cross-channel maps of its block; optional whole-frame
@@ -294,9 +291,6 @@ __device__ __attribute__((always_inline)) void cross_tile(const Geo& g, const Fr
       wp[p] = (256u - w) | (w << 16);
     }
     auto rows_one_side = [&](const int32_t (&a)[kX3]) {
-      auto map = [&](int, uint32_t x0, uint32_t x1, uint32_t x2, int r) {
-        return cross_map<int32_t>(a, x0, x1, x2, r);
-      };
       for (int row = t.r0; row < t.r1; row += kXU) {
         uint32_t d[kXU][3];
 #pragma unroll
@@ -319,7 +313,7 @@ __device__ __attribute__((always_inline)) void cross_tile(const Geo& g, const Fr
           if (row + u < t.r1) {
             const int off = (row + u) * pitch + col0 * 3;
             uint32_t o[3];
-            cross_group<STATS>(d[u], o, npx, wp, L, hrep, map);
+            cross_group_fast<STATS>(d[u], o, npx, wp, L, hrep, a);
             if (npx == 4) {
               store_group<3>(rout, off, o);
             } else {
