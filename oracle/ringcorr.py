@@ -256,17 +256,12 @@ def quantile_bins(hist: np.ndarray, levels: int = QFIT_LEVELS) -> list[int]:
     """Bin of the level-i quantile of a histogram, i = 0 .. levels - 1: the
     smallest bin v whose cumulative count reaches (2i + 1) / (2 levels) of the
     total (reading R-qfit).  Exact integers."""
-    n = int(hist.sum())
-    out = []
-    for i in range(levels):
-        need = (2 * i + 1) * n
-        cum = 0
-        for v in range(NBINS):
-            cum += int(hist[v])
-            if 2 * levels * cum >= need:
-                out.append(v)
-                break
-    return out
+    h = np.asarray(hist, np.int64)
+    n = int(h.sum())
+    cum2m = 2 * levels * np.cumsum(h)                       # 2M cum(v), exact int64
+    need = (2 * np.arange(levels, dtype=np.int64) + 1) * n  # (2i + 1) n
+    # smallest v with 2M cum(v) >= need: the left insertion point in the sorted cum2m
+    return [int(v) for v in np.searchsorted(cum2m, need, side="left")]
 
 
 def bin_centre2(v: int, bit_depth: int) -> int:
