@@ -370,8 +370,10 @@ def vga_leg(reps: int = 200) -> dict:
 
 def serving_leg(args, base, surrogate_w=None) -> dict:
     """Three rigs of the benchmark camera ring in one context behind the
-    server: paced (30 fps per rig, exponential jitter of mean 2 ms) and
-    saturated (every frame-set submitted at once)."""
+    server: paced (30 fps per rig, exponential jitter of mean 2 ms), the same
+    arrival process replayed `serve_speedup` times faster (a load near the
+    server's capacity, where batches across rigs form), and saturated
+    (every frame-set submitted at once)."""
     import threading
 
     import torch
@@ -382,6 +384,7 @@ def serving_leg(args, base, surrogate_w=None) -> dict:
     spec = synth.rig14_1080p()
     n_rigs, pool = 3, 4
     out = {"rigs": n_rigs, "rig": spec.name, "fps": 30, "jitter_ms": 2.0, "mem_budget_framesets": 4,
+           "accelerated_speedup": args.serve_speedup, "accelerated_seconds": args.serve_accel_seconds,
            "plain_apply_lanes": args.serve_lanes}
     tuned_plain = None
     for path in ("plain", "surrogate"):
@@ -415,7 +418,11 @@ def serving_leg(args, base, surrogate_w=None) -> dict:
         n_each = int(args.serve_seconds * 30)
         arrivals = sorted((float(rng.uniform(0, 1 / 30)) + i / 30 + float(rng.exponential(2e-3)), r, i)
                           for r in range(n_rigs) for i in range(n_each))
-        for mode in ("paced", "saturated"):
+        S = args.serve_speedup
+        n_acc = int(args.serve_accel_seconds * 30 * S)
+        arrivals_acc = sorted((float(rng.uniform(0, 1 / (30 * S))) + i / (30 * S) + float(rng.exponential(2e-3 / S)),
+                               r, i) for r in range(n_rigs) for i in range(n_acc))
+        for mode in ("paced", "accelerated", "saturated"):
             log(f"serving: {path} {mode}")
             srv = Server(be, mem_budget=4 * fs_bytes, max_batches_in_flight=3, queue_limit=1 << 20)
             # warm-up outside the measurement
@@ -425,12 +432,14 @@ def serving_leg(args, base, surrogate_w=None) -> dict:
             srv.finished.clear()
             srv.batch_sizes.clear()
             srv.start()
-            if mode == "paced":
+            if mode in ("paced", "accelerated"):
                 t_start = time.perf_counter()
-                for t, r, i in arrivals:
+                for t, r, i in (arrivals if mode == "paced" else arrivals_acc):
                     dt = t_start + t - time.perf_counter()
-                    if dt > 0:
-                        time.sleep(dt)
+                    if dt > 2e-4:
+                        time.sleep(dt - 1e-4)
+                    while t_start + t > time.perf_counter():
+                        pass
                     srv.submit(r, frames[r][i % pool])
             else:
                 n_sat = args.serve_saturated
@@ -441,6 +450,7 @@ def serving_leg(args, base, surrogate_w=None) -> dict:
             rep = srv.report()
             res[mode] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in rep.items()}
         res["offered_GPix_s"] = round(n_rigs * 30 * be.rig_pixels(0) / 1e9, 3)
+        res["accelerated_offered_GPix_s"] = round(n_rigs * 30 * S * be.rig_pixels(0) / 1e9, 3)
         if path == "plain":
             tuned_plain = be.tuned
         be.close()
@@ -871,6 +881,10 @@ def main() -> int:
     ap.add_argument("--serve-lanes", type=int, default=1,
                     help="apply lanes of the serving backend's frame-set pipeline (plain path; 1 = one stream)")
     ap.add_argument("--serve-saturated", type=int, default=40, help="frame-sets per rig in the saturated run")
+    ap.add_argument("--serve-speedup", type=float, default=50.0,
+                    help="replay factor of the accelerated serving run (30 fps per rig times this)")
+    ap.add_argument("--serve-accel-seconds", type=float, default=0.5,
+                    help="wall-clock seconds of the accelerated serving run")
     ap.add_argument("--cpu-budget", type=float, default=10.0, help="seconds of oracle work per CPU-baseline leg")
     args = ap.parse_args()
     if args.gpus != 1:
