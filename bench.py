@@ -650,20 +650,20 @@ def plain_leg(args, rig_spec, steps: int, warmup: int, timing_every: int):
     # Launch knobs of the pipe mode: given on the command line, else the
     # autotuner's (cached for this rig and device, or timed now in the pipe
     # mode itself; the knobs never change results).
-    lanes, group = args.lanes or 3, args.group or 3
-    tuned = {"source": "command line" if (args.lanes or args.group or args.tile_rows or args.grid is not None)
-             else "default"}
+    lanes, group, fuse = args.lanes or 3, args.group or 3, max(args.fuse, 0)
+    tuned = {"source": "command line" if (args.lanes or args.group or args.tile_rows or args.grid is not None
+                                          or args.fuse >= 0) else "default"}
     if args.mode == "pipe" and tuned["source"] == "default" and not args.no_autotune:
         from paper_1910_03517_amd import autotune
         t_tune = time.perf_counter()
         choice = autotune.cached_pipe(rig)
         src = "cache"
         if choice is None:
-            log(f"{rig_spec.name}: autotuning the pipe (lanes, group, tile rows, grid)")
+            log(f"{rig_spec.name}: autotuning the pipe (lanes, group, fused or not, tile rows, grid)")
             choice = autotune.tune_pipe(rig, ins, outs, depth=args.depth)
             src = "tuned"
-        lanes, group = choice.lanes, choice.group
-        tuned = {"source": src, "lanes": lanes, "group": group, "tile_rows": choice.tile_rows,
+        lanes, group, fuse = choice.lanes, choice.group, choice.fuse
+        tuned = {"source": src, "lanes": lanes, "group": group, "fuse": fuse, "tile_rows": choice.tile_rows,
                  "grid": choice.grid, "us_per_frameset_when_tuned": round(choice.us_per_frameset, 2),
                  "seconds": round(time.perf_counter() - t_tune, 2)}
         # The tuning advanced the estimator state: back to the initial one.
@@ -681,7 +681,7 @@ def plain_leg(args, rig_spec, steps: int, warmup: int, timing_every: int):
         # multiple of depth that apply starts only after the earlier one ended.
         assert max(lanes, group) <= args.depth and args.nbuf % args.depth == 0, \
             "need lanes, group <= depth and depth | nbuf"
-        pipe = rt.Pipe.for_rig(rig, depth=args.depth, lanes=lanes, group=group)
+        pipe = rt.Pipe.for_rig(rig, depth=args.depth, lanes=lanes, group=group, fuse=bool(fuse))
         in_ptrs = [rt.ptr_array(x) for x in ins]
         out_ptrs = [rt.ptr_array(x) for x in outs]
     elif args.mode == "graph":
@@ -757,6 +757,7 @@ def plain_leg(args, rig_spec, steps: int, warmup: int, timing_every: int):
     rig.check()
     ms_total = ev0.elapsed_time(ev1)
     apply_ms = np.array(rt.rt_ctx_apply_times(rig.ctx, steps))
+    apply_sets = np.array(rt.rt_ctx_apply_sets(rig.ctx, steps), dtype=np.float64)
     rt.rt_ctx_timing(rig.ctx, 0)
     first += steps
     apply_where = f"inside the timed region, every {timing_every}th apply launch"
@@ -769,6 +770,7 @@ def plain_leg(args, rig_spec, steps: int, warmup: int, timing_every: int):
                         b.whole_hist, b.whole_sums, stream=stream)
         torch.cuda.synchronize()
         apply_ms = np.array(rt.rt_ctx_apply_times(rig.ctx, steps))
+        apply_sets = np.ones(apply_ms.size)
         rt.rt_ctx_timing(rig.ctx, 0)
 
     # The same kernel with no other work beside it (one stream, launches back to back).
@@ -802,19 +804,25 @@ def plain_leg(args, rig_spec, steps: int, warmup: int, timing_every: int):
 
     ab = apply_bytes(cams)
     launch_us = float(apply_ms.mean() * 1e3)
-    achieved = ab / (launch_us * 1e-6) / 1e9
+    sets_per_launch = float(apply_sets.mean())
+    achieved = ab * sets_per_launch / (launch_us * 1e-6) / 1e9
     alone_us = float(alone_ms.mean() * 1e3)
     alone_gbs = ab / (alone_us * 1e-6) / 1e9
     step_gbs = ab / (ms_step * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": "k_apply<true,true,false> (apply + fused whole-frame statistics)", "bytes_per_launch": ab,
+            "kernel": ("k_apply_sets<false> (apply + fused whole-frame statistics, up to 4 frame-sets per launch)"
+                       if pipe is not None and pipe.fuse else
+                       "k_apply<true,true,false> (apply + fused whole-frame statistics)"),
+            "bytes_per_launch": round(ab * sets_per_launch), "bytes_per_frameset": ab,
+            "frame_sets_per_launch": round(sets_per_launch, 3),
             "launch_us": round(launch_us, 2), "launch_timing": apply_where, "launches_timed": int(apply_ms.size),
             "copy_ceiling_GBs": round(copy_gbs, 1), "frac_of_copy_ceiling": round(achieved / copy_gbs, 4),
             "alone": {"launch_us": round(alone_us, 2), "achieved": round(alone_gbs, 1),
                       "frac": round(alone_gbs / HBM_PEAK_GBS, 4), "frac_of_copy_ceiling": round(alone_gbs / copy_gbs, 4),
                       "launches_timed": int(alone_ms.size),
-                      "what": "the same launches back to back on one stream after the timed region"},
+                      "what": "the single-frame-set apply launches back to back on one stream after the timed "
+                              "region"},
             "per_step": {"achieved": round(step_gbs, 1), "frac": round(step_gbs / HBM_PEAK_GBS, 4),
                          "what": "apply bytes per frame-set / time per frame-set (launches may overlap)"}}
     rep = {
@@ -823,6 +831,7 @@ def plain_leg(args, rig_spec, steps: int, warmup: int, timing_every: int):
         "algorithmic_bytes_per_frameset": alg_bytes, "pixels_per_frameset": px,
         "n_blocks": opts.n_blocks, "band_width": opts.band_width,
         "tile_rows": tile_rows, "apply_grid": grid, "n_tiles": n_tiles, "lanes": lanes, "group": group,
+        "fuse": int(bool(pipe is not None and pipe.fuse)),
         "tuned": tuned,
         "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 4),
                        "p99": round(float(np.percentile(lat_ms, 99)), 4),
@@ -850,6 +859,9 @@ def main() -> int:
                     help="apply streams of the pipe mode (default: the autotuner's choice, else 3)")
     ap.add_argument("--group", type=int, default=0,
                     help="frame-sets whose applies the pipe mode issues together (default: the autotuner's, else 3)")
+    ap.add_argument("--fuse", type=int, default=-1, choices=[-1, 0, 1],
+                    help="pipe mode: 1 issues each group's applies as one launch of up to 4 frame-sets, groups over "
+                         "the lanes in turn; 0 one launch per frame-set (default -1: the autotuner's choice, else 0)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="pipe mode: skip the autotuner (3 lanes in groups of 3 and the context's work split)")
     ap.add_argument("--no-cpu-baseline", action="store_true")

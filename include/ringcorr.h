@@ -308,6 +308,17 @@ rt_status rt_pipe_submit_n(rt_pipe* p, int32_t n, const void* const* frames, voi
 rt_status rt_pipe_submit_batch(rt_pipe* p, uint64_t active, const void* const* frames, void* const* out_frames,
                                void* stream, void* ready_event, void* done_event, int32_t* slot_out);
 
+/* Fused applies (fuse = 1; 0, the default, restores the form above): the
+ * applies of a group go to one lane, groups taking the lanes in turn, as
+ * one kernel launch per run of up to 4 consecutive frame-sets with the same
+ * active cameras (the grid holds each frame-set's workgroups in turn, so
+ * the launch has no drain between them).  A group then costs the host one
+ * cross-stream wait and one record instead of one per lane, and the lanes
+ * overlap the end of one group with the start of the next.  Results are
+ * those of the unfused pipeline.  Issues the pending applies first.
+ * RT_EUNSUPPORTED for a context of more than 16 cameras. */
+rt_status rt_pipe_set_fuse(rt_pipe* p, int32_t fuse);
+
 /* ------------------------------------------------------------------------
  * Object removal with the smoothing fallback (section 3.1: the two
  * supplemental methods for objects that move across a seam; section 4.1
@@ -528,7 +539,8 @@ rt_status rt_ctx_tuning(const rt_ctx* ctx, int32_t* tile_rows, int32_t* grid, in
 
 /* Instrumentation: with slots > 0, every `every`-th later apply kernel launch
  * of this context (rt_apply, rt_stats with whole-frame statistics,
- * rt_frameset, rt_pipe_submit; the first one included) takes two HIP events
+ * rt_frameset, rt_pipe_submit, fused pipeline applies; the first one
+ * included) takes two HIP events
  * attached to its dispatch (the kernel's own start and end, no marker packets
  * around it), kept in a ring of `slots` entries; slots = 0 turns it off.
  * every >= 1.  Synchronizes the device. */
@@ -538,6 +550,11 @@ rt_status rt_ctx_timing(rt_ctx* ctx, int32_t slots, int32_t every);
  * kernel launches, oldest first, into ms[]; *n_out receives the count.  Waits
  * for those launches to finish. */
 rt_status rt_ctx_apply_times(rt_ctx* ctx, float* ms, int32_t max_n, int32_t* n_out);
+
+/* For the same launches as rt_ctx_apply_times, the number of frame-sets
+ * each covered (1, or up to 4 for fused pipeline applies); *n_out receives
+ * the count. */
+rt_status rt_ctx_apply_sets(const rt_ctx* ctx, int32_t* sets, int32_t max_n, int32_t* n_out);
 
 /* Measurement utility, not part of the method: copy `bytes` bytes from src to
  * dst (device pointers, 16-byte aligned, non-overlapping, bytes < 2 GiB) with

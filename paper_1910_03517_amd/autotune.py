@@ -26,10 +26,13 @@ from dataclasses import asdict, dataclass
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "ringcorr", "autotune.json")
 TILE_ROWS = (8, 16, 32, 64)
 GRIDS = (0, 512, 768, 1024)
-# Pipe mode: (lanes, group) pairs and work splits worth timing.  More lanes
-# than 4 or groups larger than the lane count were slower in every
-# measurement; one lane is the plain stream order.
-PIPE_LANES = ((2, 2), (3, 1), (3, 3), (4, 4))
+# Pipe mode: (lanes, group, fuse) forms and work splits worth timing.  Unfused,
+# more lanes than 4 or groups larger than the lane count were slower in
+# every measurement; one lane is the plain stream order.  Fused, a group is
+# one launch of up to 4 frame-sets and the lanes take whole groups in turn
+# (rigs of at most 16 cameras).
+PIPE_LANES = ((2, 2, 0), (3, 1, 0), (3, 3, 0), (4, 4, 0), (1, 3, 1), (2, 3, 1), (2, 4, 1), (3, 4, 1))
+FUSE_MAX_CAMS = 16
 PIPE_SPLITS = ((32, 0), (48, 0), (64, 0), (32, 512))
 
 
@@ -141,25 +144,29 @@ class PipeChoice:
     tile_rows: int
     grid: int
     us_per_frameset: float
+    fuse: int = 0
 
 
-def pipe_candidates(cams, n_blocks: int) -> list[tuple[int, int, int, int]]:
-    """(lanes, group, tile_rows, grid) tuples for the pipe mode; tile heights
-    above the tallest block are dropped."""
+def pipe_candidates(cams, n_blocks: int) -> list[tuple[int, int, int, int, int]]:
+    """(lanes, group, tile_rows, grid, fuse) tuples for the pipe mode; tile
+    heights above the tallest block are dropped, and the fused forms for rigs
+    of more than FUSE_MAX_CAMS cameras."""
     tallest = max(-(-c.height // n_blocks) for c in cams)
     splits = [(r, g) for r, g in PIPE_SPLITS if r <= max(tallest, PIPE_SPLITS[0][0])]
-    return [(l, gr, r, g) for l, gr in PIPE_LANES for r, g in splits]
+    forms = [f for f in PIPE_LANES if not f[2] or len(cams) <= FUSE_MAX_CAMS]
+    return [(l, gr, r, g, fu) for l, gr, fu in forms for r, g in splits]
 
 
-def time_pipe(rig, frames, outs, lanes: int, group: int, depth: int = 8, steps: int = 64, warmup: int = 16) -> float:
+def time_pipe(rig, frames, outs, lanes: int, group: int, depth: int = 8, steps: int = 64, warmup: int = 16,
+              fuse: int = 0) -> float:
     """Mean microseconds per frame-set through an rt_pipe of `lanes` apply
-    streams issued in groups of `group`, rotating over the given buffers
-    (their count must be a multiple of depth)."""
+    streams issued in groups of `group` (fused or not), rotating over the
+    given buffers (their count must be a multiple of depth)."""
     import torch
     from . import rt
     n = len(frames)
     stream = torch.cuda.current_stream()
-    pipe = rt.Pipe.for_rig(rig, depth=depth, lanes=lanes, group=group)
+    pipe = rt.Pipe.for_rig(rig, depth=depth, lanes=lanes, group=group, fuse=bool(fuse))
     # A group of frame-sets per library call, as the bench submits them.
     chunks = [(rt.ptr_array_n([frames[(j + u) % n] for u in range(group)]),
                rt.ptr_array_n([outs[(j + u) % n] for u in range(group)]), group) for j in range(n)]
@@ -182,26 +189,26 @@ def time_pipe(rig, frames, outs, lanes: int, group: int, depth: int = 8, steps: 
 
 
 def tune_pipe(rig, frames, outs, cache_path: str | None = DEFAULT_CACHE, rounds: int = 3, depth: int = 8,
-              cands: list[tuple[int, int, int, int]] | None = None) -> PipeChoice:
+              cands: list[tuple[int, int, int, int, int]] | None = None) -> PipeChoice:
     """Time every pipe candidate `rounds` times (interleaved, after an
     untimed run that brings the device to its working clocks; the median of
     each candidate's times), tune the rig to the fastest work split, cache the
     choice and return it (the caller builds its pipe with choice.lanes /
-    choice.group)."""
+    choice.group / choice.fuse)."""
     arch = device_arch()
     key = signature(rig.cams, rig.opts, arch, "pipe")
     cands = cands or pipe_candidates(rig.cams, rig.opts.n_blocks)
     rig.tune(cands[0][2], cands[0][3])
-    time_pipe(rig, frames, outs, cands[0][0], cands[0][1], depth, steps=256)
+    time_pipe(rig, frames, outs, cands[0][0], cands[0][1], depth, steps=256, fuse=cands[0][4])
     times = {c: [] for c in cands}
     for _ in range(rounds):
         for c in cands:
-            lanes, group, tile_rows, grid = c
+            lanes, group, tile_rows, grid, fuse = c
             rig.tune(tile_rows, grid)
-            times[c].append(time_pipe(rig, frames, outs, lanes, group, depth))
+            times[c].append(time_pipe(rig, frames, outs, lanes, group, depth, fuse=fuse))
     med = {c: sorted(t)[len(t) // 2] for c, t in times.items()}
     c = min(cands, key=lambda k: med[k])
-    choice = PipeChoice(c[0], c[1], c[2], c[3], med[c])
+    choice = PipeChoice(c[0], c[1], c[2], c[3], med[c], c[4])
     rig.tune(choice.tile_rows, choice.grid)
     if cache_path:
         cache = load_cache(cache_path)
@@ -218,7 +225,7 @@ def cached_pipe(rig, cache_path: str = DEFAULT_CACHE) -> PipeChoice | None:
         return None
     try:
         choice = PipeChoice(int(entry["lanes"]), int(entry["group"]), int(entry["tile_rows"]), int(entry["grid"]),
-                            float(entry["us_per_frameset"]))
+                            float(entry["us_per_frameset"]), int(entry.get("fuse", 0)))
     except (KeyError, TypeError, ValueError):
         return None
     rig.tune(choice.tile_rows, choice.grid)

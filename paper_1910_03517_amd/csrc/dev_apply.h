@@ -211,8 +211,8 @@ __device__ inline void flush_whole(const Geo& g, const Bufs& b, int cam, ApplyLd
 // whole-frame statistics (the camera's last segment in the run); 16-bit
 // samples, whose sums are kept in registers, and the packed histogram, whose
 // counters are bounded per segment, do both on every segment.
-template <int C, int BPS, bool WRITE, bool STATS, bool WTAB>
-__device__ void apply_tile(const Geo& g, const FramePtrs& fp, const Bufs& b, int ti, ApplyLds& L, bool first,
+template <int C, int BPS, bool WRITE, bool STATS, bool WTAB, class FP>
+__device__ void apply_tile(const Geo& g, const FP& fp, const Bufs& b, int ti, ApplyLds& L, bool first,
                            bool last) {
   const bool clear = first || BPS == 2 || kPack;
   const bool flush = last || BPS == 2 || kPack;
@@ -362,8 +362,8 @@ __device__ inline int64_t blend_q16(int64_t pa, int64_t pb, int v) {
 // (uniform over the workgroup) and every sample is evaluated from its side's
 // pair in 64-bit integers, 8-bit and 16-bit samples alike.  Same histogram
 // and flush as apply_tile.
-template <int C, int BPS, bool WRITE, bool STATS, bool WTAB>
-__device__ void apply_tile_vblend(const Geo& g, const FramePtrs& fp, const Bufs& b, int ti, ApplyLds& L,
+template <int C, int BPS, bool WRITE, bool STATS, bool WTAB, class FP>
+__device__ void apply_tile_vblend(const Geo& g, const FP& fp, const Bufs& b, int ti, ApplyLds& L,
                                   bool first, bool last) {
   const bool clear = first || BPS == 2 || kPack;
   const bool flush = last || BPS == 2 || kPack;
@@ -453,8 +453,8 @@ constexpr int kRunBlocks = (int)(sizeof(ApplyLds::lut) / (2 * kCS * 2 * sizeof(i
 // re-selects its pixels' constants (by side) from them, so a block boundary
 // costs no memory latency and no partly filled unroll step.  Same results as
 // apply_tile.
-template <int C, bool WTAB>
-__device__ void apply_run_direct(const Geo& g, const FramePtrs& fp, const Bufs& b, int ti, int te, ApplyLds& L,
+template <int C, bool WTAB, class FP>
+__device__ void apply_run_direct(const Geo& g, const FP& fp, const Bufs& b, int ti, int te, ApplyLds& L,
                                  bool first, bool last) {
   constexpr int NW = C;          // dwords per 4-pixel group
   const int tid = threadIdx.x;
@@ -601,8 +601,8 @@ constexpr int kVblendRows = (int)(sizeof(ApplyLds::lut) / (2 * kCS * 2 * sizeof(
 // direct constants in LDS, then every thread takes its pixels' constants of
 // each row from there and the samples follow the direct path of
 // apply_run_direct.
-template <int C, bool STATS, bool WTAB>
-__device__ void apply_run_vblend(const Geo& g, const FramePtrs& fp, const Bufs& b, int ti, int te, ApplyLds& L,
+template <int C, bool STATS, bool WTAB, class FP>
+__device__ void apply_run_vblend(const Geo& g, const FP& fp, const Bufs& b, int ti, int te, ApplyLds& L,
                                  bool first, bool last) {
   constexpr int NW = C;
   const int tid = threadIdx.x;
@@ -723,8 +723,8 @@ __device__ inline bool tile_direct(const Geo& g, const Bufs& b, int ti) {
 // the camera's consecutive segments (apply_run_direct); otherwise one
 // (apply_tile).  Returns the end of the segments taken; `last` is set when
 // they end the camera's run in this workgroup.
-template <bool WRITE, bool STATS, bool WTAB, bool VBLEND = false>
-__device__ inline int apply_tile_dispatch(const Geo& g, const FramePtrs& fp, const Bufs& b, int ti, int se,
+template <bool WRITE, bool STATS, bool WTAB, bool VBLEND = false, class FP = FramePtrs>
+__device__ inline int apply_tile_dispatch(const Geo& g, const FP& fp, const Bufs& b, int ti, int se,
                                           ApplyLds& L, bool first) {
   const int k = uniform(g.tiles[ti].cam);
   const DevCam cam = uniform_cam(g.cams[k]);

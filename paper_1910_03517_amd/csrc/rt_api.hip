@@ -41,6 +41,7 @@ struct rt_ctx {
   int64_t n_timed = 0;
   int64_t n_applies = 0;
   std::vector<hipEvent_t> ev_begin, ev_end;
+  std::vector<int32_t> timed_sets;   // frame-sets each timed launch covered
   bool capturing = false;   // no timing events inside a captured graph
   int64_t generation = 0;   // bumped whenever device tables are rebuilt
   Geo geo{};
@@ -395,6 +396,7 @@ static void free_timing(rt_ctx* ctx) {
   for (hipEvent_t ev : ctx->ev_end) (void)hipEventDestroy(ev);
   ctx->ev_begin.clear();
   ctx->ev_end.clear();
+  ctx->timed_sets.clear();
   ctx->n_timing = 0;
   ctx->n_timed = 0;
 }
@@ -472,7 +474,17 @@ static hipError_t timed_apply(rt_ctx* ctx, const Geo& g, const FramePtrs& fp, co
   if (ctx->n_applies++ % ctx->timing_every != 0) return launch_apply(g, fp, b, write, stats, st);
   const int slot = (int)(ctx->n_timed % ctx->n_timing);
   const hipError_t e = launch_apply(g, fp, b, write, stats, st, ctx->ev_begin[slot], ctx->ev_end[slot]);
-  if (e == hipSuccess) ++ctx->n_timed;
+  if (e == hipSuccess) ctx->timed_sets[slot] = 1, ++ctx->n_timed;
+  return e;
+}
+
+// The same for an apply launch over several frame-sets.
+static hipError_t timed_apply_sets(rt_ctx* ctx, const Geo& g, const SetPtrs& sp, hipStream_t st) {
+  if (ctx->n_timing <= 0 || ctx->capturing) return launch_apply_sets(g, sp, st);
+  if (ctx->n_applies++ % ctx->timing_every != 0) return launch_apply_sets(g, sp, st);
+  const int slot = (int)(ctx->n_timed % ctx->n_timing);
+  const hipError_t e = launch_apply_sets(g, sp, st, ctx->ev_begin[slot], ctx->ev_end[slot]);
+  if (e == hipSuccess) ctx->timed_sets[slot] = sp.n_sets, ++ctx->n_timed;
   return e;
 }
 
@@ -812,11 +824,56 @@ struct rt_pipe {
   hipStream_t caller = nullptr;                  // lane 0 of the pending applies
   int64_t submitted = 0, groups = 0;
   int warm = 0;                                  // frame-sets since creation or the last join (capped)
+  int fuse = 0;                                  // 1: a group's applies in one launch, groups over the lanes
 };
+
+// Fused form: the group's applies go to one lane (groups take the lanes in
+// turn) as launches of up to kSetsMax frame-sets with one camera mask, so
+// the host pays one wait and one record per group.
+static hipError_t pipe_flush_fused(rt_pipe* p) {
+  rt_ctx* ctx = p->ctx;
+  const int g = (int)(p->groups % kGroupRing), l = (int)(p->groups % p->lanes);
+  hipStream_t sl = l ? p->s_lane[l - 1] : p->caller;
+  hipError_t e = hipEventRecord(p->ev_est[g], p->s_est);
+  if (e == hipSuccess) e = hipStreamWaitEvent(sl, p->ev_est[g], 0);
+  const size_t np = p->pending.size();
+  for (size_t i = 0; e == hipSuccess && i < np;) {
+    size_t n = 1;
+    while (i + n < np && n < (size_t)kSetsMax && p->pending[i + n].active == p->pending[i].active) ++n;
+    SetPtrs sp;
+    memset(&sp, 0, sizeof sp);
+    sp.n_sets = (int32_t)n;
+    for (size_t m = 0; m < n; ++m) {
+      const auto& q = p->pending[i + m];
+      for (int k = 0; k < ctx->n_cams; ++k) {
+        sp.f[m].in[k] = q.fp.in[k];
+        sp.f[m].out[k] = q.fp.out[k];
+      }
+      sp.b[m] = SetBufs{p->wholes[q.slot].whole_hist, p->wholes[q.slot].whole_sums, p->luts[q.slot].lut8,
+                        p->luts[q.slot].q16, p->luts[q.slot].weights};
+    }
+    Geo gg = ctx->geo;
+    gg.active = p->pending[i].active;
+    e = timed_apply_sets(ctx, gg, sp, sl);
+    for (size_t m = 0; m < n; ++m) {
+      const auto& q = p->pending[i + m];
+      if (e == hipSuccess && q.done) e = hipEventRecord(q.done, sl);
+      p->slot_group[q.slot] = p->groups;
+      p->slot_lane[q.slot] = l;
+    }
+    i += n;
+  }
+  if (e == hipSuccess) e = hipEventRecord(p->ev_lane[g][l], sl);
+  p->last_group[l] = g;
+  p->pending.clear();
+  ++p->groups;
+  return e;
+}
 
 // Issues the pending applies as one group (see above).
 static hipError_t pipe_flush(rt_pipe* p) {
   if (p->pending.empty()) return hipSuccess;
+  if (p->fuse) return pipe_flush_fused(p);
   rt_ctx* ctx = p->ctx;
   const int g = (int)(p->groups % kGroupRing);
   hipError_t e = hipEventRecord(p->ev_est[g], p->s_est);
@@ -885,6 +942,18 @@ rt_status rt_pipe_create_lanes(rt_ctx* ctx, int32_t depth, int32_t lanes, int32_
     return hip_fail(e, "creating the pipeline streams and events");
   }
   *out = p;
+  return RT_OK;
+}
+
+rt_status rt_pipe_set_fuse(rt_pipe* p, int32_t fuse) {
+  if (!p) return fail(RT_EINVAL, "pipe is NULL");
+  if (fuse != 0 && fuse != 1) return fail(RT_EINVAL, "fuse %d is not 0 or 1", fuse);
+  if (fuse && p->ctx->n_cams > kSetCams)
+    return fail(RT_EUNSUPPORTED, "fused applies take rigs of at most %d cameras (this one has %d)", kSetCams,
+                p->ctx->n_cams);
+  const hipError_t e = pipe_flush(p);
+  if (e != hipSuccess) return hip_fail(e, "pipeline flush");
+  p->fuse = fuse;
   return RT_OK;
 }
 
@@ -1337,6 +1406,7 @@ rt_status rt_ctx_timing(rt_ctx* ctx, int32_t slots, int32_t every) {
     ctx->ev_begin.push_back(a);
     ctx->ev_end.push_back(b);
   }
+  ctx->timed_sets.assign(slots, 0);
   ctx->n_timing = slots;
   return RT_OK;
 }
@@ -1353,6 +1423,17 @@ rt_status rt_ctx_apply_times(rt_ctx* ctx, float* ms, int32_t max_n, int32_t* n_o
     if (e == hipSuccess) e = hipEventElapsedTime(&ms[i], ctx->ev_begin[slot], ctx->ev_end[slot]);
     if (e != hipSuccess) return hip_fail(e, "reading timing events");
   }
+  *n_out = n;
+  return RT_OK;
+}
+
+rt_status rt_ctx_apply_sets(const rt_ctx* ctx, int32_t* sets, int32_t max_n, int32_t* n_out) {
+  if (!ctx || !sets || !n_out || max_n < 0) return fail(RT_EINVAL, "ctx, sets or n_out is NULL, or max_n < 0");
+  *n_out = 0;
+  if (ctx->n_timing <= 0) return RT_OK;
+  const int64_t avail = std::min<int64_t>(ctx->n_timed, ctx->n_timing);
+  const int n = (int)std::min<int64_t>(avail, max_n);
+  for (int i = 0; i < n; ++i) sets[i] = ctx->timed_sets[(size_t)((ctx->n_timed - n + i) % ctx->n_timing)];
   *n_out = n;
   return RT_OK;
 }

@@ -60,6 +60,29 @@ struct FramePtrs {
   uint8_t* out[RT_MAX_CAMS];
 };
 
+// Several frame-sets of one rig in one apply launch: set f takes workgroups
+// [f * n_wg, (f + 1) * n_wg), its frames at index [f][k] and its own tables,
+// weights and whole-frame buffers (the pipeline's slots).
+// Sized so that the kernel argument stays near the single-set one.
+constexpr int kSetsMax = 4;    // frame-sets per launch
+constexpr int kSetCams = 16;   // cameras per frame-set
+struct SetFrames {
+  const uint8_t* in[kSetCams];
+  uint8_t* out[kSetCams];
+};
+struct SetBufs {
+  uint32_t* whole_hist;
+  uint64_t* whole_sums;
+  uint8_t* lut8;
+  int64_t* q16;
+  uint16_t* weights;
+};
+struct SetPtrs {
+  SetFrames f[kSetsMax];
+  SetBufs b[kSetsMax];
+  int32_t n_sets;
+};
+
 // Caller buffers (device pointers) of one launch.
 struct Bufs {
   uint32_t* band_hist;
@@ -153,6 +176,11 @@ hipError_t launch_band_estimate(const Geo& g, const FramePtrs& fp, const Bufs& b
 hipError_t launch_build_lut(const Geo& g, const Bufs& b, hipStream_t st);
 hipError_t launch_apply(const Geo& g, const FramePtrs& fp, const Bufs& b, bool write, bool stats, hipStream_t st,
                         hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
+// Apply with whole-frame statistics of sp.n_sets (1..kSetsMax) frame-sets of
+// the rig in one launch (every camera at most kSetCams; g.active the same
+// for all sets).
+hipError_t launch_apply_sets(const Geo& g, const SetPtrs& sp, hipStream_t st, hipEvent_t start = nullptr,
+                             hipEvent_t stop = nullptr);
 hipError_t launch_zero_whole(const Geo& g, const Bufs& b, hipStream_t st);
 hipError_t launch_weights(const Geo& g, const Bufs& b, hipStream_t st);
 hipError_t launch_cross_stats(const Geo& g, const FramePtrs& fp, const CrossBufs& x, hipStream_t st);

@@ -30,6 +30,7 @@ EXPORTED = ["rt_ctx_create", "rt_ctx_destroy", "rt_ctx_sizes", "rt_stats", "rt_e
             "rt_stream_copy", "rt_ctx_timing", "rt_ctx_apply_times", "rt_graph_create", "rt_graph_launch",
             "rt_graph_destroy", "rt_pipe_create", "rt_pipe_submit", "rt_pipe_destroy",
             "rt_pipe_create_lanes", "rt_pipe_join", "rt_pipe_submit_batch", "rt_pipe_submit_n",
+            "rt_pipe_set_fuse", "rt_ctx_apply_sets",
             "rt_surrogate_features", "rt_estimate_new", "rt_surrogate_targets", "rt_surrogate_select",
             "rt_surrogate_frameset",
             "rt_mlp_forward", "rt_mlp_backward", "rt_mlp_adam", "rt_mlp_mse", "rt_gather_rows", "rt_mlp_train",
@@ -145,6 +146,8 @@ def load(path: str = LIB_PATH) -> ct.CDLL:
     lib.rt_pipe_submit_n.argtypes = [P, ct.c_int32, ct.POINTER(P), ct.POINTER(P), P, ct.POINTER(ct.c_int32),
                                      ct.POINTER(ct.c_int32)]
     lib.rt_pipe_destroy.argtypes = [P]
+    lib.rt_pipe_set_fuse.argtypes = [P, ct.c_int32]
+    lib.rt_ctx_apply_sets.argtypes = [P, ct.POINTER(ct.c_int32), ct.c_int32, ct.POINTER(ct.c_int32)]
     lib.rt_pipe_create_lanes.argtypes = [P, ct.c_int32, ct.c_int32, ct.c_int32, ct.POINTER(rt_stats_buf),
                                          ct.POINTER(rt_params_buf), ct.POINTER(rt_lut_buf), ct.POINTER(rt_stats_buf),
                                          ct.POINTER(P)]
@@ -302,14 +305,14 @@ class Pipe:
     params, valid.  Pipe.for_rig allocates the slots of a Rig."""
 
     @classmethod
-    def for_rig(cls, rig: "Rig", depth: int = 2, lanes: int = 1, group: int = 1) -> "Pipe":
+    def for_rig(cls, rig: "Rig", depth: int = 2, lanes: int = 1, group: int = 1, fuse: bool = False) -> "Pipe":
         luts = [LutSet(rig.sizes, rig.device) for _ in range(depth)]
         wholes = [WholeSet(rig.sizes, rig.device) for _ in range(depth)]
-        p = cls(rig.ctx, rig.bufs, luts, wholes, lanes=lanes, group=group)
+        p = cls(rig.ctx, rig.bufs, luts, wholes, lanes=lanes, group=group, fuse=fuse)
         p.luts, p.whole = luts, wholes
         return p
 
-    def __init__(self, ctx, bufs, luts, wholes, lanes: int = 1, group: int = 1):
+    def __init__(self, ctx, bufs, luts, wholes, lanes: int = 1, group: int = 1, fuse: bool = False):
         depth = len(luts)
         assert len(wholes) == depth
         la = (rt_lut_buf * depth)(*[rt_lut_buf(_p(l.lut8), _p(l.q16), _p(l.weights)) for l in luts])
@@ -323,8 +326,17 @@ class Pipe:
         self.depth = depth
         self.lanes = lanes
         self.group = group
+        self.fuse = False
         self._keep = (bufs, luts, wholes)
         self._slot = ct.c_int32()
+        if fuse:
+            self.set_fuse(True)
+
+    def set_fuse(self, fuse: bool) -> None:
+        """rt_pipe_set_fuse: a group's applies as launches of up to 4
+        frame-sets on one lane, groups taking the lanes in turn."""
+        _check(load().rt_pipe_set_fuse(self.handle, int(bool(fuse))))
+        self.fuse = bool(fuse)
 
     def submit(self, frames, out_frames, stream=None, frame_ptrs=None, out_ptrs=None, ready_event=None) -> int:
         """Enqueue one frame-set; returns its slot.  frame_ptrs / out_ptrs may
@@ -525,6 +537,14 @@ def rt_ctx_apply_times(ctx, max_n: int) -> list[float]:
     buf = (ct.c_float * max(max_n, 1))()
     n = ct.c_int32()
     _check(load().rt_ctx_apply_times(ctx, buf, max_n, ct.byref(n)))
+    return [buf[i] for i in range(n.value)]
+
+
+def rt_ctx_apply_sets(ctx, max_n: int) -> list[int]:
+    """Frame-sets covered by each launch that rt_ctx_apply_times reports."""
+    buf = (ct.c_int32 * max(max_n, 1))()
+    n = ct.c_int32()
+    _check(load().rt_ctx_apply_sets(ctx, buf, max_n, ct.byref(n)))
     return [buf[i] for i in range(n.value)]
 
 

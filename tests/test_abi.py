@@ -117,3 +117,5 @@ def test_null_arguments_are_rejected():
     assert lib.rt_mlp_mse(None, None, 1, None, None) == rt.RT_EINVAL
     assert lib.rt_gather_rows(None, 1, None, 1, None, None) == rt.RT_EINVAL
     assert lib.rt_ctx_apply_times(None, None, 0, None) == rt.RT_EINVAL
+    assert lib.rt_ctx_apply_sets(None, None, 0, None) == rt.RT_EINVAL
+    assert lib.rt_pipe_set_fuse(None, 1) == rt.RT_EINVAL

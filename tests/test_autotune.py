@@ -76,9 +76,12 @@ def test_pipe_candidates_and_mode_in_signature():
     cams = [rt.Camera(1920, 1080, 3, 8, 0, p).with_pitch() for p in range(14)]
     c = autotune.pipe_candidates(cams, 16)
     assert len(c) == len(autotune.PIPE_LANES) * len(autotune.PIPE_SPLITS)
-    assert all(group <= lanes for lanes, group, _, _ in c)
+    assert all(group <= lanes for lanes, group, _, _, fuse in c if not fuse)
+    assert all(group <= 4 for _, group, _, _, fuse in c if fuse)
     small = autotune.pipe_candidates([rt.Camera(320, 120, 3, 8, 0, 0).with_pitch()], 16)   # blocks of 8 rows
-    assert {r for _, _, r, _ in small} == {32}                 # taller splits dropped, the smallest kept
+    assert {r for _, _, r, _, _ in small} == {32}              # taller splits dropped, the smallest kept
+    many = autotune.pipe_candidates([rt.Camera(320, 120, 3, 8, 0, p).with_pitch() for p in range(17)], 16)
+    assert many and not any(fuse for *_, fuse in many)         # fused launches take at most 16 cameras
     o = rt.Options()
     assert autotune.signature(cams, o, "gfx950") != autotune.signature(cams, o, "gfx950", "pipe")
     assert autotune.signature(cams, o, "gfx950") == autotune.signature(cams, o, "gfx950", "eager")
