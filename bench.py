@@ -4,8 +4,9 @@ One step = one frame-set through every step of the path: band statistics,
 estimate, tables, apply with fused whole-frame statistics.  By default steps
 go through rt_pipe with several apply lanes (the statistics and estimates of
 consecutive frame-sets run in order on one stream, ahead of the applies,
-which go round-robin over LANES streams, so that consecutive applies
-overlap); --lanes 1 keeps every apply on the caller's stream, --mode eager
+which go over LANES streams, so that consecutive applies overlap; with
+--fuse 1 a group's applies are one launch and groups take the lanes in
+turn); --lanes 1 keeps every apply on the caller's stream, --mode eager
 issues one rt_frameset per step on one stream, --mode graph /
 graph-pipelined replay captured HIP graphs.  Inputs are seeded synthetic
 rigs already resident in HBM; NBUF distinct input/output frame-set buffers
@@ -14,7 +15,7 @@ rotate so that the 256 MB Infinity Cache cannot serve repeats.
     python bench.py [--gpus 1] [--steps 300] [--warmup 20] [--config rig14]
 
 Prints ONE JSON line.  In the pipe mode the launch knobs (apply lanes, group
-size, segment height, apply grid) come from the autotuner, timed in that
+size, fused or not, segment height, apply grid) come from the autotuner, timed in that
 mode on the benchmark rig before the timed region unless cached or given on
 the command line ("tuned" says which).  After the timed region, further
 legs add their own objects to the line: "removal" (object removal with the
@@ -51,7 +52,9 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 METRIC = "corrected GPix/s and % HBM roofline; p50/p99 frame-set latency, plain vs surrogate"
 KERNEL_SOURCES = ["dev_common.h", "dev_apply.h", "dev_estimate.h", "k_apply.hip", "rt_internal.h"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_apply_rig14_traffic.txt")
+# Counter-derived HBM traffic of each form of the dominant kernel.
+TRAFFIC_FILES = {"k_apply_sets<false>": os.path.join(ROOT, "profiles", "k_apply_sets_rig14_traffic.txt"),
+                 "k_apply<true,true,false>": os.path.join(ROOT, "profiles", "k_apply_rig14_traffic.txt")}
 
 
 def log(msg: str) -> None:
@@ -96,19 +99,22 @@ def algorithmic_bytes(cams, band_width: int) -> int:
     return total
 
 
-def traffic_from_profile(khash: str, workload: str):
-    """Counter-derived HBM bytes per apply launch from the committed rocprofv3
-    summary, if it was taken on this exact kernel source and workload; else None."""
+def traffic_from_profile(khash: str, workload: str, kernel: str):
+    """Counter-derived HBM bytes per frame-set of the apply kernel from the
+    committed rocprofv3 summary, if it was taken on this exact kernel source,
+    kernel form and workload; else None."""
+    if kernel not in TRAFFIC_FILES:
+        return None
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(TRAFFIC_FILES[kernel]) as f:
             kv = dict(line.split(":", 1) for line in f if ":" in line and not line.startswith("#"))
     except OSError:
         return None
     kv = {k.strip(): v.strip() for k, v in kv.items()}
-    if kv.get("kernel_hash") != khash or kv.get("workload") != workload:
+    if kv.get("kernel_hash") != khash or kv.get("workload") != workload or kv.get("kernel") != kernel:
         return None
     try:
-        return int(float(kv["hbm_bytes_per_launch"]))
+        return float(kv["hbm_bytes_per_frameset"])
     except (KeyError, ValueError):
         return None
 
@@ -622,11 +628,12 @@ def copy_ceiling(rt, torch, frame_bytes: int, nbuf: int, steps: int, warmup: int
     return 2 * frame_bytes * steps / (c0.elapsed_time(c1) / 1e3) / 1e9
 
 
-def plain_leg(args, rig_spec, steps: int, warmup: int, timing_every: int):
+def plain_leg(args, rig_spec, steps: int, warmup: int, timing_every: int = 0):
     """The timed region of the plain path on one rig: `steps` frame-sets back
     to back in the chosen launch mode, the apply launches timed by the
-    library's events, then the same launches alone and the frame-set latency.
-    Returns (rig, report, ins, outs, base)."""
+    library's events (every timing_every-th; 0: about five launches of the
+    region), then the single-frame-set launches alone and the frame-set
+    latency.  Returns (rig, report, ins, outs, base)."""
     import torch
     from paper_1910_03517_amd import rt, synth
 
@@ -742,6 +749,12 @@ def plain_leg(args, rig_spec, steps: int, warmup: int, timing_every: int):
     # Timed region: exactly `steps` frame-sets back to back, bracketed by a
     # start and an end event.  The library attaches its own events to every
     # n-th apply dispatch in the region (the dominant kernel's durations).
+    if timing_every <= 0:
+        # Apply launches in the region: one per frame-set, or, fused, the
+        # first `lanes` alone and then one per group.
+        launches = steps if not (pipe is not None and pipe.fuse) else \
+            min(steps, lanes) + -(-max(0, steps - lanes) // group)
+        timing_every = max(1, launches // 5)
     rt.rt_ctx_timing(rig.ctx, steps, timing_every)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -806,6 +819,7 @@ def plain_leg(args, rig_spec, steps: int, warmup: int, timing_every: int):
     launch_us = float(apply_ms.mean() * 1e3)
     sets_per_launch = float(apply_sets.mean())
     achieved = ab * sets_per_launch / (launch_us * 1e-6) / 1e9
+    by_sets = {str(int(n)): round(float(apply_ms[apply_sets == n].mean() * 1e3), 2) for n in np.unique(apply_sets)}
     alone_us = float(alone_ms.mean() * 1e3)
     alone_gbs = ab / (alone_us * 1e-6) / 1e9
     step_gbs = ab / (ms_step * 1e-3) / 1e9
@@ -815,7 +829,7 @@ def plain_leg(args, rig_spec, steps: int, warmup: int, timing_every: int):
                        if pipe is not None and pipe.fuse else
                        "k_apply<true,true,false> (apply + fused whole-frame statistics)"),
             "bytes_per_launch": round(ab * sets_per_launch), "bytes_per_frameset": ab,
-            "frame_sets_per_launch": round(sets_per_launch, 3),
+            "frame_sets_per_launch": round(sets_per_launch, 3), "launch_us_by_frame_sets": by_sets,
             "launch_us": round(launch_us, 2), "launch_timing": apply_where, "launches_timed": int(apply_ms.size),
             "copy_ceiling_GBs": round(copy_gbs, 1), "frac_of_copy_ceiling": round(achieved / copy_gbs, 4),
             "alone": {"launch_us": round(alone_us, 2), "achieved": round(alone_gbs, 1),
@@ -872,7 +886,7 @@ def main() -> int:
     ap.add_argument("--copy-only", action="store_true", help="time the streaming copy of the frame bytes only")
     ap.add_argument("--timing-every", type=int, default=0,
                     help="time every n-th apply launch of the timed region with HIP events "
-                         "(default: steps // 5, at least 1, so that about five launches are timed)")
+                         "(default: about five launches of the region are timed)")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate training/inference leg")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-vga", action="store_true", help="skip the 1x640x480 per-call leg")
@@ -909,7 +923,7 @@ def main() -> int:
 
     torch.cuda.set_device(0)
     rig_spec = config(args.config)
-    timing_every = args.timing_every or max(1, args.steps // 5)
+    timing_every = args.timing_every
     if args.copy_only:
         cams = [rt.Camera(c.width, c.height, c.channels, c.bit_depth, c.ring, c.pos).with_pitch()
                 for c in rig_spec.cams]
@@ -922,13 +936,15 @@ def main() -> int:
     khash = kernel_hash()
     workload = rig_spec.name
     roof = rep.pop("roofline")
-    roof["traffic"] = traffic_from_profile(khash, workload)
+    per_set = traffic_from_profile(khash, workload, roof["kernel"].split()[0])
+    roof["traffic"] = round(per_set * roof["frame_sets_per_launch"]) if per_set else None
     out = {
         "metric": METRIC, "value": rep["GPix_s"], "unit": "GPix/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": rep["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u8", "data": "synthetic",
         "config": {"workload": workload, "path": "plain", "mode": "smoothing" if args.smoothing else "standard",
                    "launch_mode": args.mode + (f", {rep['lanes']} apply lanes, depth {args.depth}, group {rep['group']}"
+                                               + (", fused applies" if rep["fuse"] else "")
                                                if args.mode == "pipe" else ""),
                    "n_blocks": rep["n_blocks"], "band_width": rep["band_width"],
                    "pixels_per_frameset": rep["pixels_per_frameset"], "rotating_buffers": args.nbuf,
@@ -961,7 +977,7 @@ def main() -> int:
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
         us = args.uneven_steps or args.steps
-        urig, urep, _, _, _ = plain_leg(args, config("uneven"), us, args.warmup, args.timing_every or max(1, us // 5))
+        urig, urep, _, _, _ = plain_leg(args, config("uneven"), us, args.warmup, args.timing_every)
         urig.close()
         uroof = urep.pop("roofline")
         out["uneven"] = {**urep, "steps": us, "roofline": {k: uroof[k] for k in (
