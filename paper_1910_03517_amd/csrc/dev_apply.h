@@ -647,8 +647,26 @@ __device__ void apply_run_vblend(const Geo& g, const FP& fp, const Bufs& b, int 
         const uint32_t w = p < npx ? (WTAB ? (uint32_t)wrow[col0 + p] : blend_weight(W, col0 + p)) : 0u;
         pc.wp[p] = (256u - w) | (w << 16);
       }
+      // A group on one side of the centre takes one side's constants (three
+      // 8-byte LDS reads per row); only the group across the centre, if
+      // any, selects per pixel.
+      const bool one_side = (col0 >= half) == (col0 + 3 >= half);
+      const int side0 = col0 >= half ? kCS * 2 : 0;
       auto select_row = [&](int r) {
         const int base = (r - c0) * 2 * kCS * 2;
+        if (one_side) {
+          const int2* q = reinterpret_cast<const int2*>(rc + base + side0);
+#pragma unroll
+          for (int c = 0; c < kCS; ++c) {
+            const int2 v = q[c];
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+              pc.da[p][c] = v.x;
+              pc.dc[p][c] = v.y;
+            }
+          }
+          return;
+        }
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
           const int sb = base + (col0 + p >= half ? kCS * 2 : 0);

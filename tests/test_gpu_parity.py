@@ -173,21 +173,22 @@ def test_rig14_frameset_smoothing():
     frameset_sequence(synth.rig14_1080p(), rt.Options(smoothing=True), 3)
 
 
-def pipeline_vs_oracle(spec, n, label):
+def pipeline_vs_oracle(spec, n, label, lanes=3, fuse=False):
     """n frame-sets of `spec` (drifting gains, smoothing) through the
-    pipeline in the bench's launch configuration (3 apply lanes, 8 slots,
-    applies issued 3 frame-sets at a time, the last group partial): every
-    output against the oracle's frame-set sequence, the last two frame-sets'
-    whole-frame statistics and the final state bitwise."""
+    pipeline in one of the bench's launch configurations (8 slots, applies
+    issued 3 frame-sets at a time, the last group partial; 3 lanes, or fused:
+    a group per launch, 2 lanes): every output against the oracle's
+    frame-set sequence, the last two frame-sets' whole-frame statistics and
+    the final state bitwise."""
     cams = rt_cams(spec.cams)
     opts = rt.Options(smoothing=True)
     rig = rt.Rig(cams, opts)
-    pipe = rt.Pipe.for_rig(rig, depth=8, lanes=3, group=3)
+    pipe = rt.Pipe.for_rig(rig, depth=8, lanes=lanes, group=3, fuse=fuse)
     frames = [synth.rig_frames(spec, t, drift=True) for t in range(n)]
     dev = [rig.upload(f) for f in frames]
     outs = [rig.alloc_frames() for _ in range(n)]
     torch.cuda.synchronize()
-    say(f"case: {label} pipeline, 3 lanes, depth 8, group 3, {n} frame-sets")
+    say(f"case: {label} pipeline, {lanes} lanes, depth 8, group 3, fuse {fuse}, {n} frame-sets")
     slots = [pipe.submit(dev[t], outs[t]) for t in range(n)]
     pipe.join()
     torch.cuda.synchronize()
@@ -213,6 +214,18 @@ def test_rig14_lanes_pipeline_matches_oracle():
     """Ten 14x1920x1080 RGB8 frame-sets (two slots reused) through the
     pipeline against the oracle."""
     pipeline_vs_oracle(synth.rig14_1080p(), 10, "rig14")
+
+
+def test_rig14_fused_pipeline_matches_oracle():
+    """The bench's fused form (2 lanes, groups of 3 in one apply launch) on
+    ten 14x1920x1080 RGB8 frame-sets against the oracle."""
+    pipeline_vs_oracle(synth.rig14_1080p(), 10, "rig14", lanes=2, fuse=True)
+
+
+def test_uneven_rig_fused_pipeline_matches_oracle():
+    """The fused form on five frame-sets of the uneven three-ring rig (16
+    cameras, the most a fused launch takes)."""
+    pipeline_vs_oracle(synth.uneven_rig(), 5, "uneven rig", lanes=2, fuse=True)
 
 
 def test_uneven_rig_lanes_pipeline_matches_oracle():
