@@ -8,9 +8,11 @@ which go over LANES streams, so that consecutive applies overlap; with
 --fuse 1 a group's applies are one launch and groups take the lanes in
 turn); --lanes 1 keeps every apply on the caller's stream, --mode eager
 issues one rt_frameset per step on one stream, --mode graph /
-graph-pipelined replay captured HIP graphs.  Inputs are seeded synthetic
-rigs already resident in HBM; NBUF distinct input/output frame-set buffers
-rotate so that the 256 MB Infinity Cache cannot serve repeats.
+graph-pipelined replay captured HIP graphs (the frames rebound before each
+launch, so one graph, or two for alternating tables, serves every buffer).
+Inputs are seeded synthetic rigs already resident in HBM; NBUF distinct
+input/output frame-set buffers rotate so that the 256 MB Infinity Cache
+cannot serve repeats.
 
     python bench.py [--gpus 1] [--steps 300] [--warmup 20] [--config rig14]
 
@@ -692,21 +694,33 @@ def plain_leg(args, rig_spec, steps: int, warmup: int, timing_every: int = 0):
         in_ptrs = [rt.ptr_array(x) for x in ins]
         out_ptrs = [rt.ptr_array(x) for x in outs]
     elif args.mode == "graph":
+        # One captured frame-set; each step rebinds its frames (rt_graph_set_frames) and launches it.
         whole = rt.WholeSet(rig.sizes)
-        graphs = [rt.Graph(rig.ctx, ins[i], outs[i], rt.LutSet(rig.sizes), whole, b) for i in range(args.nbuf)]
+        graphs = [rt.Graph(rig.ctx, ins[0], outs[0], rt.LutSet(rig.sizes), whole, b)]
+        in_ptrs = [rt.ptr_array(x) for x in ins]
+        out_ptrs = [rt.ptr_array(x) for x in outs]
     elif args.mode == "graph-pipelined":
+        # Two two-branch graphs (the table buffers alternate), frames rebound every step.
         assert args.nbuf % 2 == 0
         luts = [rt.LutSet(rig.sizes) for _ in range(2)]
         wholes = [rt.WholeSet(rig.sizes) for _ in range(2)]
         rt.rt_stats(rig.ctx, ins[0], b.band_hist, b.band_sums)
         rt.rt_estimate(rig.ctx, b.band_hist, b.band_sums, b.params, b.valid)
         rt.rt_build_lut(rig.ctx, b.params, b.valid, luts[0].lut8, luts[0].q16, luts[0].weights)
-        graphs = [rt.Graph(rig.ctx, ins[i], outs[i], luts[i % 2], wholes[i % 2], b,
-                           ins[(i + 1) % args.nbuf], luts[(i + 1) % 2]) for i in range(args.nbuf)]
+        graphs = [rt.Graph(rig.ctx, ins[p], outs[p], luts[p], wholes[p], b, ins[p + 1], luts[1 - p]) for p in range(2)]
+        in_ptrs = [rt.ptr_array(x) for x in ins]
+        out_ptrs = [rt.ptr_array(x) for x in outs]
 
     def step(i, ready=None):
         if graphs is not None:
-            graphs[i % args.nbuf].launch(stream)
+            j = i % args.nbuf
+            g = graphs[i % len(graphs)]
+            if args.mode == "graph":
+                g.set_frames(None, None, frame_ptrs=in_ptrs[j], out_ptrs=out_ptrs[j])
+            else:
+                g.set_frames(None, None, frame_ptrs=in_ptrs[j], out_ptrs=out_ptrs[j],
+                             next_ptrs=in_ptrs[(j + 1) % args.nbuf])
+            g.launch(stream)
         elif pipe is not None:
             j = i % args.nbuf
             pipe.submit(ins[j], outs[j], stream, in_ptrs[j], out_ptrs[j], ready_event=ready)
@@ -868,7 +882,8 @@ def main() -> int:
     ap.add_argument("--mode", default="pipe", choices=["pipe", "graph-pipelined", "graph", "eager"],
                     help="pipe: rt_pipe_submit per step (statistics and estimates on their own stream, applies "
                          "round-robin over --lanes streams); graph-pipelined: one two-branch graph launch per step; "
-                         "graph: one captured rt_frameset per step; eager: one rt_frameset call per step")
+                         "graph: one captured rt_frameset per step (frames rebound each step); eager: one "
+                         "rt_frameset call per step")
     ap.add_argument("--lanes", type=int, default=0,
                     help="apply streams of the pipe mode (default: the autotuner's choice, else 3)")
     ap.add_argument("--group", type=int, default=0,

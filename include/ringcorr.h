@@ -518,6 +518,19 @@ rt_status rt_graph_create(rt_ctx* ctx, const void* const* frames, void* const* o
 rt_status rt_graph_launch(rt_graph* g, void* stream);
 rt_status rt_graph_destroy(rt_graph* g);
 
+/* Rebinds the frames of a captured graph for its later launches: frames ->
+ * out_frames (validated like rt_frameset's), and for a two-branch graph
+ * next_frames (required there, NULL otherwise; RT_EINVAL on a mismatch).
+ * Tables, statistics and state buffers stay those of the capture.  One
+ * graph then serves any frame buffers: a frame-set costs one rebind (host
+ * only: the kernel nodes' frame-pointer arguments are replaced in the
+ * instantiated graph) and one launch.  Call it between launches, ordered on
+ * the host like them; launches already enqueued keep their frames.
+ * RT_EUNSUPPORTED if the capture's frame-pointer arguments could not be
+ * identified among the graph's nodes. */
+rt_status rt_graph_set_frames(rt_graph* g, const void* const* frames, void* const* out_frames,
+                              const void* const* next_frames);
+
 /* Synchronize the device and report RT_EDEVICE if a HIP error is pending. */
 rt_status rt_ctx_check(rt_ctx* ctx);
 

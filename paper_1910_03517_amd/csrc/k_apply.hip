@@ -82,6 +82,15 @@ hipError_t launch_apply(const Geo& g, const FramePtrs& fp, const Bufs& b, bool w
   return hipGetLastError();
 }
 
+const void* apply_kernel(const Geo& g, bool write, bool stats) {
+  if (g.vblend && write && stats) return reinterpret_cast<const void*>(&k_apply<true, true, true>);
+  if (g.vblend && write) return reinterpret_cast<const void*>(&k_apply<true, false, true>);
+  if (write && stats) return reinterpret_cast<const void*>(&k_apply<true, true, false>);
+  if (write) return reinterpret_cast<const void*>(&k_apply<true, false, false>);
+  if (stats) return reinterpret_cast<const void*>(&k_apply<false, true, false>);
+  return nullptr;
+}
+
 hipError_t launch_apply_sets(const Geo& g, const SetPtrs& sp, hipStream_t st, hipEvent_t start, hipEvent_t stop) {
   if (sp.n_sets < 1 || sp.n_sets > kSetsMax || g.n_cams > kSetCams) return hipErrorInvalidValue;
   const dim3 grid(g.n_wg * sp.n_sets), block(kThreads);

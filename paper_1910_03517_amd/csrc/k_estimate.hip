@@ -253,6 +253,14 @@ hipError_t launch_band_estimate(const Geo& g, const FramePtrs& fp, const Bufs& b
   return hipGetLastError();
 }
 
+const void* band_estimate_kernel(const Geo& g) {
+  const bool wide = g.n_cams * g.n_blocks <= kWideSeamBlocks, q = g.fit == RT_FIT_QUANTILE;
+  if (wide && q) return reinterpret_cast<const void*>(&k_band_estimate<true, true>);
+  if (wide) return reinterpret_cast<const void*>(&k_band_estimate<true, false>);
+  if (q) return reinterpret_cast<const void*>(&k_band_estimate<false, true>);
+  return reinterpret_cast<const void*>(&k_band_estimate<false, false>);
+}
+
 hipError_t launch_band_estimate_removal(const Geo& g, const FramePtrs& fp, const PrevPtrs& pp, const Bufs& b,
                                         const Removal& rm, hipStream_t st) {
   const int blocks = g.n_cams * g.n_blocks;

@@ -52,6 +52,14 @@ struct rt_graph {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int64_t generation = 0;
+  bool pipelined = false;
+  // Kernel nodes whose second argument is a FramePtrs: next = false for
+  // the frame-set's own frames (frames -> out_frames), true for next_frames.
+  struct FrameNode {
+    hipGraphNode_t node;
+    bool next;
+  };
+  std::vector<FrameNode> frame_nodes;
 };
 
 
@@ -761,6 +769,34 @@ rt_status rt_graph_create(rt_ctx* ctx, const void* const* frames, void* const* o
     g->graph = graph;
   }
   if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+  g->pipelined = pipelined;
+  if (e == hipSuccess) {
+    // The nodes that rt_graph_set_frames rebinds: the band-statistics
+    // kernel and the apply, each accepted only if its second argument holds
+    // exactly the frame pointers it was captured with.
+    const FramePtrs fp = make_ptrs(ctx, frames, out_frames);
+    const FramePtrs fn = pipelined ? make_ptrs(ctx, next_frames, nullptr) : fp;
+    const void* k_est = band_estimate_kernel(ctx->geo);
+    const void* k_app = apply_kernel(ctx->geo, true, true);
+    size_t n = 0;
+    if (hipGraphGetNodes(g->graph, nullptr, &n) == hipSuccess && n > 0) {
+      std::vector<hipGraphNode_t> nodes(n);
+      if (hipGraphGetNodes(g->graph, nodes.data(), &n) == hipSuccess) {
+        for (size_t i = 0; i < n; ++i) {
+          hipGraphNodeType t;
+          hipKernelNodeParams kp;
+          if (hipGraphNodeGetType(nodes[i], &t) != hipSuccess || t != hipGraphNodeTypeKernel) continue;
+          if (hipGraphKernelNodeGetParams(nodes[i], &kp) != hipSuccess || !kp.kernelParams) continue;
+          const bool est = kp.func == k_est, app = kp.func == k_app;
+          if (!est && !app) continue;
+          const FramePtrs& want = est && pipelined ? fn : fp;
+          if (!kp.kernelParams[1] || memcmp(kp.kernelParams[1], &want, sizeof(FramePtrs)) != 0) continue;
+          g->frame_nodes.push_back({nodes[i], est && pipelined});
+        }
+      }
+    }
+    if (g->frame_nodes.size() != 2) g->frame_nodes.clear();
+  }
   if (ev_fork) (void)hipEventDestroy(ev_fork);
   if (ev_join) (void)hipEventDestroy(ev_join);
   if (s1) (void)hipStreamDestroy(s1);
@@ -771,6 +807,35 @@ rt_status rt_graph_create(rt_ctx* ctx, const void* const* frames, void* const* o
     return hip_fail(e, "capturing the frame-set graph");
   }
   *out = g;
+  return RT_OK;
+}
+
+rt_status rt_graph_set_frames(rt_graph* g, const void* const* frames, void* const* out_frames,
+                              const void* const* next_frames) {
+  if (!g || !g->exec) return fail(RT_EINVAL, "graph is NULL");
+  rt_ctx* ctx = g->ctx;
+  if (g->generation != ctx->generation)
+    return fail(RT_ESTATE, "the context's tables were rebuilt after this graph was captured; capture it again");
+  if (g->pipelined != (next_frames != nullptr))
+    return fail(RT_EINVAL, g->pipelined ? "a two-branch graph needs next_frames" : "next_frames given for a one-branch graph");
+  rt_status r = check_frames(ctx, frames, "frames");
+  if (r == RT_OK) r = check_frames(ctx, (const void* const*)out_frames, "out_frames");
+  if (r == RT_OK && next_frames) r = check_frames(ctx, next_frames, "next_frames");
+  if (r != RT_OK) return r;
+  if (g->frame_nodes.empty())
+    return fail(RT_EUNSUPPORTED, "the graph's frame-pointer arguments were not found among its nodes");
+  FramePtrs fp = make_ptrs(ctx, frames, out_frames);
+  FramePtrs fn = next_frames ? make_ptrs(ctx, next_frames, nullptr) : fp;
+  for (const auto& f : g->frame_nodes) {
+    hipKernelNodeParams kp;
+    hipError_t e = hipGraphKernelNodeGetParams(f.node, &kp);
+    if (e != hipSuccess) return hip_fail(e, "reading a graph node");
+    void* args[3] = {kp.kernelParams[0], f.next ? (void*)&fn : (void*)&fp, kp.kernelParams[2]};
+    kp.kernelParams = args;
+    kp.extra = nullptr;
+    e = hipGraphExecKernelNodeSetParams(g->exec, f.node, &kp);
+    if (e != hipSuccess) return hip_fail(e, "rebinding the graph's frames");
+  }
   return RT_OK;
 }
 

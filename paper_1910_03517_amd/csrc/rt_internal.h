@@ -176,6 +176,12 @@ hipError_t launch_band_estimate(const Geo& g, const FramePtrs& fp, const Bufs& b
 hipError_t launch_build_lut(const Geo& g, const Bufs& b, hipStream_t st);
 hipError_t launch_apply(const Geo& g, const FramePtrs& fp, const Bufs& b, bool write, bool stats, hipStream_t st,
                         hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
+// Host addresses of the kernels that launch_band_estimate and launch_apply
+// launch for g (the latter with write and stats as given); both take
+// (Geo, FramePtrs, Bufs).  Used to find them among a captured graph's nodes.
+const void* band_estimate_kernel(const Geo& g);
+const void* apply_kernel(const Geo& g, bool write, bool stats);
+
 // Apply with whole-frame statistics of sp.n_sets (1..kSetsMax) frame-sets of
 // the rig in one launch (every camera at most kSetCams; g.active the same
 // for all sets).

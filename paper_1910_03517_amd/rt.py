@@ -30,7 +30,7 @@ EXPORTED = ["rt_ctx_create", "rt_ctx_destroy", "rt_ctx_sizes", "rt_stats", "rt_e
             "rt_stream_copy", "rt_ctx_timing", "rt_ctx_apply_times", "rt_graph_create", "rt_graph_launch",
             "rt_graph_destroy", "rt_pipe_create", "rt_pipe_submit", "rt_pipe_destroy",
             "rt_pipe_create_lanes", "rt_pipe_join", "rt_pipe_submit_batch", "rt_pipe_submit_n",
-            "rt_pipe_set_fuse", "rt_ctx_apply_sets",
+            "rt_pipe_set_fuse", "rt_ctx_apply_sets", "rt_graph_set_frames",
             "rt_surrogate_features", "rt_estimate_new", "rt_surrogate_targets", "rt_surrogate_select",
             "rt_surrogate_frameset",
             "rt_mlp_forward", "rt_mlp_backward", "rt_mlp_adam", "rt_mlp_mse", "rt_gather_rows", "rt_mlp_train",
@@ -140,6 +140,7 @@ def load(path: str = LIB_PATH) -> ct.CDLL:
                                     ct.POINTER(P), ct.POINTER(rt_lut_buf), ct.POINTER(rt_stats_buf),
                                     ct.POINTER(rt_params_buf), ct.POINTER(P)]
     lib.rt_graph_launch.argtypes = [P, P]
+    lib.rt_graph_set_frames.argtypes = [P, ct.POINTER(P), ct.POINTER(P), ct.POINTER(P)]
     lib.rt_pipe_create.argtypes = [P, ct.c_int32, ct.POINTER(rt_stats_buf), ct.POINTER(rt_params_buf),
                                    ct.POINTER(rt_lut_buf), ct.POINTER(rt_stats_buf), ct.POINTER(P)]
     lib.rt_pipe_submit.argtypes = [P, ct.POINTER(P), ct.POINTER(P), P, P, ct.POINTER(ct.c_int32)]
@@ -516,6 +517,17 @@ class Graph:
 
     def launch(self, stream=None) -> None:
         _check(load().rt_graph_launch(self.handle, _stream_handle(stream)))
+
+    def set_frames(self, frames, out_frames, next_frames=None, frame_ptrs=None, out_ptrs=None,
+                   next_ptrs=None) -> None:
+        """rt_graph_set_frames: later launches read `frames`, write
+        `out_frames` (and, two-branch, gather the statistics of
+        `next_frames`); prebuilt pointer arrays (ptr_array) may be passed
+        instead.  The caller keeps the tensors alive while launches use them."""
+        fa = frame_ptrs if frame_ptrs is not None else _ptr_array(frames)
+        oa = out_ptrs if out_ptrs is not None else _ptr_array(out_frames)
+        na = next_ptrs if next_ptrs is not None else (_ptr_array(next_frames) if next_frames is not None else None)
+        _check(load().rt_graph_set_frames(self.handle, fa, oa, na))
 
     def close(self) -> None:
         if self.handle is not None:

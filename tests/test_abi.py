@@ -98,6 +98,7 @@ def test_null_arguments_are_rejected():
     assert lib.rt_graph_create(None, None, None, None, None, None, None, None, None, None) == rt.RT_EINVAL
     assert lib.rt_graph_launch(None, None) == rt.RT_EINVAL
     assert lib.rt_graph_destroy(None) == rt.RT_OK
+    assert lib.rt_graph_set_frames(None, None, None, None) == rt.RT_EINVAL
     assert lib.rt_pipe_create(None, 2, None, None, None, None, None) == rt.RT_EINVAL
     assert lib.rt_pipe_submit(None, None, None, None, None, None) == rt.RT_EINVAL
     assert lib.rt_pipe_destroy(None) == rt.RT_OK

@@ -570,6 +570,65 @@ def test_graph_replays_match_eager(pipelined):
     rig.close()
 
 
+@pytest.mark.parametrize("pipelined", [False, True])
+def test_graph_rebound_frames_match_eager(pipelined):
+    """One captured graph (two for the two-branch form, which alternate the
+    table buffers) serves every input and output buffer: rt_graph_set_frames
+    before each launch, over a cycle of 4 inputs and 2 outputs for 9 steps
+    with eager torch work between the launches; every launch equals the
+    eager rt_frameset result of the same step.  A mismatched next_frames is
+    refused."""
+    say(f"case: graph set_frames pipelined={pipelined}, 3x352x144 rgb8 + 2x96x64 u12")
+    spec = synth.RigSpec("graph rebind", 14, [synth.CamSpec(352, 144, 3, 8, 0, p) for p in range(3)]
+                         + [synth.CamSpec(96, 64, 1, 12, 1, p) for p in range(2)])
+    cams = rt_cams(spec.cams)
+    opts = rt.Options(n_blocks=6, band_width=12, smoothing=True)
+    rig = rt.Rig(cams, opts)
+    frames = [synth.rig_frames(spec, t, drift=True) for t in range(4)]
+    dev = [rig.upload(f) for f in frames]
+    torch.cuda.synchronize()
+    order = [(3 * t) % 4 for t in range(9)]
+    eager = _eager_sequence(cams, opts, dev, order)
+    luts = [rt.LutSet(rig.sizes) for _ in range(2)]
+    whole = rt.WholeSet(rig.sizes)
+    outs = [rig.alloc_frames() for _ in range(2)]
+    b = rig.bufs
+    if pipelined:
+        rt.rt_stats(rig.ctx, dev[order[0]], b.band_hist, b.band_sums)
+        rt.rt_estimate(rig.ctx, b.band_hist, b.band_sums, b.params, b.valid)
+        rt.rt_build_lut(rig.ctx, b.params, b.valid, luts[0].lut8, luts[0].q16, luts[0].weights)
+        # captured on buffers of no step, so that every launch is rebound
+        graphs = [rt.Graph(rig.ctx, dev[1], outs[1], luts[p], whole, b, dev[2], luts[1 - p]) for p in range(2)]
+        with pytest.raises(rt.RtError, match="next_frames"):
+            graphs[0].set_frames(dev[0], outs[0])
+    else:
+        graphs = [rt.Graph(rig.ctx, dev[1], outs[1], luts[0], whole, b)]
+        with pytest.raises(rt.RtError, match="next_frames"):
+            graphs[0].set_frames(dev[0], outs[0], dev[1])
+    scratch = torch.zeros(1 << 20, device="cuda")
+    for t, i in enumerate(order):
+        g = graphs[t % len(graphs)]
+        out = outs[t % 2]
+        if pipelined:
+            g.set_frames(dev[i], out, dev[order[(t + 1) % len(order)]])
+        else:
+            g.set_frames(dev[i], out)
+        g.launch()
+        torch.cuda.synchronize()
+        scratch.add_(1.0)                       # eager work between launches
+        torch.cuda.synchronize()
+        got = rig.download(out)
+        for k, (a, e) in enumerate(zip(got, eager[t]["out"])):
+            assert np.array_equal(a, e), f"step {t} camera {k}"
+        assert np.array_equal(whole.whole_hist.cpu().numpy(), eager[t]["wh"]), f"step {t} whole_hist"
+        if not pipelined:
+            assert np.array_equal(b.params.cpu().numpy(), eager[t]["params"]), f"step {t} params"
+    rig.check()
+    for g in graphs:
+        g.close()
+    rig.close()
+
+
 @pytest.mark.parametrize("channels,bit_depth", [(3, 8), (1, 16)])
 def test_whole_histogram_counters_do_not_overflow(channels, bit_depth):
     """A flat 8192-wide frame puts every sample of a tile into one bin; with
