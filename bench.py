@@ -466,12 +466,13 @@ def serving_leg(args, base, surrogate_w=None) -> dict:
     return out
 
 
-def removal_leg(rig, ins, outs) -> dict:
+def removal_leg(rig, ins, outs, lanes: int = 2, group: int = 3, fuse: bool = True) -> dict:
     """Object removal with the smoothing fallback (section 3.1) on the
     benchmark rig: one rt_frameset_removal per frame-set (the previous
     frame-set's input as the reference for the frame difference), eager on
-    one stream, next to eager rt_frameset on the same buffers; and the seam
-    gradient cost monitor (section 4.2) per call on the corrected frames."""
+    one stream, next to eager rt_frameset on the same buffers, then both
+    through the frame-set pipeline in the given form; and the seam gradient
+    cost monitor (section 4.2) per call on the corrected frames."""
     import torch
     from paper_1910_03517_amd import rt
     K, NB = rig.sizes.n_cams, rig.sizes.n_blocks
@@ -497,6 +498,30 @@ def removal_leg(rig, ins, outs) -> dict:
     rm_us = timed(lambda i: rig.frameset_removal(ins[i % nb], ins[(i - 1) % nb], outs[i % nb], kept, method))
     m = method.cpu().numpy()
     plain_us = timed(lambda i: rig.frameset(ins[i % nb], outs[i % nb]))
+
+    def pipe_us(removal: bool, k: int = 60) -> float:
+        pipe = rt.Pipe.for_rig(rig, depth=8, lanes=lanes, group=group, fuse=fuse)
+        if removal:
+            pipe.set_removal(kept, method)
+        try:
+            for i in range(6):
+                pipe.submit(ins[i % nb], outs[i % nb])
+            pipe.join()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for i in range(k):
+                pipe.submit(ins[(6 + i) % nb], outs[(6 + i) % nb])
+            pipe.join()
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / k * 1e3
+        finally:
+            pipe.close()
+
+    rm_pipe_us = pipe_us(True)
+    m_pipe = method.cpu().numpy()
+    plain_pipe_us = pipe_us(False)
     seam_us = timed(lambda i: rt.rt_seam_cost(rig.ctx, outs[i % nb], 8, seam, inter))
     vb = rt.Rig(rig.cams, rt.Options(vblend=True))
     vblend_us = timed(lambda i: vb.frameset(ins[i % nb], outs[i % nb]))
@@ -524,6 +549,11 @@ def removal_leg(rig, ins, outs) -> dict:
     rig.check()
     return {"removal_us_per_frameset": round(rm_us, 2), "removal_GPix_s": round(px / rm_us / 1e3, 2),
             "plain_us_per_frameset": round(plain_us, 2), "plain_GPix_s": round(px / plain_us / 1e3, 2),
+            "removal_pipe_us_per_frameset": round(rm_pipe_us, 2), "removal_pipe_GPix_s": round(px / rm_pipe_us / 1e3, 2),
+            "plain_pipe_us_per_frameset": round(plain_pipe_us, 2),
+            "plain_pipe_GPix_s": round(px / plain_pipe_us / 1e3, 2),
+            "pipe_form": {"lanes": lanes, "group": group, "fuse": int(bool(fuse)), "frame_sets": 60},
+            "units_removal_pipe": int((m_pipe == 1).sum()),
             "units_removal": int((m == 1).sum()), "units_smoothing": int((m == 2).sum()),
             "seam_monitor_us": round(seam_us, 2),
             "vblend_us_per_frameset": round(vblend_us, 2), "vblend_GPix_s": round(px / vblend_us / 1e3, 2),
@@ -537,8 +567,9 @@ def removal_leg(rig, ins, outs) -> dict:
             "attention_hbm_frac": round(att_bytes / att_us / 1e3 / HBM_PEAK_GBS, 4),
             "seam_cost_input_mean": round(float(s_in.mean()), 3), "seam_cost_corrected_mean": round(float(s_out.mean()), 3),
             "interior_cost_corrected_mean": round(float(inter.cpu().numpy().mean()), 3),
-            "what": "eager, one stream; removal: rt_frameset_removal with the previous frame-set as reference "
-                    "(tau 20, min_kept 0.25); seam monitor: rt_seam_cost (factor 8) of every seam and image centre; "
+            "what": "eager, one stream, unless named pipe; removal: rt_frameset_removal with the previous "
+                    "frame-set as reference (tau 20, min_kept 0.25); removal_pipe / plain_pipe: the same through "
+                    "rt_pipe (rt_pipe_set_removal) in pipe_form, submits back to back and one join; seam monitor: rt_seam_cost (factor 8) of every seam and image centre; "
                     "vblend: rt_frameset with the maps of adjacent blocks blended row by row; quantile fit: "
                     "rt_frameset with fit = quantile; cross3x3: rt_frameset_cross (band and cross sums, 3x3 fit, "
                     "maps, apply with whole-frame statistics) and rt_apply_cross alone (units_3x3: units whose map "
@@ -978,7 +1009,7 @@ def main() -> int:
         out["vga"] = vga_leg()
     if args.config == "rig14" and not args.no_removal:
         log("object removal and seam monitor")
-        out["removal"] = removal_leg(rig, ins, outs)
+        out["removal"] = removal_leg(rig, ins, outs, rep["lanes"], rep["group"], bool(rep["fuse"]))
     sur_w = None
     if not args.no_surrogate and args.config == "rig14":
         sur_w, out["surrogate"] = surrogate_leg(args, rig, ins, outs)

@@ -372,6 +372,21 @@ rt_status rt_frameset_removal(rt_ctx* ctx, const void* const* frames, const void
                               uint64_t* kept_sums, const rt_params_buf* state, const rt_lut_buf* lut,
                               uint8_t* method, void* stream);
 
+/* Object removal in the frame-set pipeline: with ro (not NULL) every later
+ * rt_pipe_submit* estimates as rt_frameset_removal does, each active camera
+ * compared with its frame of its last submit (nothing moves in a frame-set
+ * in which an active camera has none yet: the first submit after this
+ * call, or a camera's first).  kept_sums (uint64 [K][2][NB][3][3]) and
+ * method (uint8 [K][2][NB], may be NULL) are single buffers written on the
+ * pipeline's stream E in submit order, like the band statistics: after
+ * rt_pipe_join they hold the last frame-set's.  The results are exactly
+ * those of consecutive rt_frameset_removal calls with prev_frames = the
+ * previous frame-set's frames.  A frame-set's input frames are then read
+ * again by the next submit's statistics: keep them unchanged until the
+ * apply of that next frame-set has finished.  ro NULL turns removal off.
+ * RT_EUNSUPPORTED unless the context fits the moments. */
+rt_status rt_pipe_set_removal(rt_pipe* p, const rt_removal_opts* ro, uint64_t* kept_sums, uint8_t* method);
+
 /* ------------------------------------------------------------------------
  * Cross-channel 3x3 maps (section 5: linear maps across the colour channels
  * instead of one affine map per channel), for contexts whose cameras are all

@@ -890,6 +890,11 @@ struct rt_pipe {
   int64_t submitted = 0, groups = 0;
   int warm = 0;                                  // frame-sets since creation or the last join (capped)
   int fuse = 0;                                  // 1: a group's applies in one launch, groups over the lanes
+  // Object removal (rt_pipe_set_removal): the options and buffers, and each
+  // camera's frame of its last submit, which the next one is compared with.
+  bool removal = false;
+  Removal rm{};
+  const uint8_t* prev_in[RT_MAX_CAMS] = {};
 };
 
 // Fused form: the group's applies go to one lane (groups take the lanes in
@@ -1022,6 +1027,22 @@ rt_status rt_pipe_set_fuse(rt_pipe* p, int32_t fuse) {
   return RT_OK;
 }
 
+rt_status rt_pipe_set_removal(rt_pipe* p, const rt_removal_opts* ro, uint64_t* kept_sums, uint8_t* method) {
+  if (!p) return fail(RT_EINVAL, "pipe is NULL");
+  if (!ro) {
+    p->removal = false;
+    return RT_OK;
+  }
+  if (p->ctx->opts.fit != RT_FIT_MOMENTS) return fail(RT_EUNSUPPORTED, "object removal fits the moments only");
+  rt_status r = check_removal(ro);
+  if (r == RT_OK) r = check_ptr(kept_sums, 8, "kept_sums");
+  if (r != RT_OK) return r;
+  p->rm = make_removal(ro, kept_sums, method, false);
+  memset(p->prev_in, 0, sizeof p->prev_in);
+  p->removal = true;
+  return RT_OK;
+}
+
 rt_status rt_pipe_create(rt_ctx* ctx, int32_t depth, const rt_stats_buf* bands, const rt_params_buf* state,
                          const rt_lut_buf* luts, const rt_stats_buf* wholes, rt_pipe** out) {
   return rt_pipe_create_lanes(ctx, depth, 1, 1, bands, state, luts, wholes, out);
@@ -1059,7 +1080,27 @@ static rt_status pipe_submit(rt_pipe* p, uint64_t active, const void* const* fra
     if (q == hipErrorNotReady) e = hipStreamWaitEvent(p->s_est, prev, 0);
     else if (q != hipSuccess) e = q;
   }
-  if (e == hipSuccess) e = launch_band_estimate(g, fp, be, p->s_est);
+  if (e == hipSuccess && p->removal) {
+    // Against each active camera's frame of its last submit; if one has
+    // none yet, nothing moves in this frame-set.
+    PrevPtrs pp;
+    memset(&pp, 0, sizeof pp);
+    bool has_prev = true;
+    for (int k = 0; k < ctx->n_cams; ++k)
+      if ((active >> k) & 1ull) {
+        pp.in[k] = p->prev_in[k];
+        has_prev = has_prev && p->prev_in[k] != nullptr;
+      }
+    if (!has_prev) memset(&pp, 0, sizeof pp);
+    Removal rm = p->rm;
+    rm.has_prev = has_prev ? 1 : 0;
+    e = launch_band_estimate_removal(g, fp, pp, be, rm, p->s_est);
+    if (e == hipSuccess)
+      for (int k = 0; k < ctx->n_cams; ++k)
+        if ((active >> k) & 1ull) p->prev_in[k] = fp.in[k];
+  } else if (e == hipSuccess) {
+    e = launch_band_estimate(g, fp, be, p->s_est);
+  }
   if (e == hipSuccess) {
     p->pending.push_back({fp, active, (hipEvent_t)done_event, slot, (int)(p->submitted % p->lanes)});
     // An idle pipeline issues its first `lanes` applies one at a time, so

@@ -30,7 +30,7 @@ EXPORTED = ["rt_ctx_create", "rt_ctx_destroy", "rt_ctx_sizes", "rt_stats", "rt_e
             "rt_stream_copy", "rt_ctx_timing", "rt_ctx_apply_times", "rt_graph_create", "rt_graph_launch",
             "rt_graph_destroy", "rt_pipe_create", "rt_pipe_submit", "rt_pipe_destroy",
             "rt_pipe_create_lanes", "rt_pipe_join", "rt_pipe_submit_batch", "rt_pipe_submit_n",
-            "rt_pipe_set_fuse", "rt_ctx_apply_sets", "rt_graph_set_frames",
+            "rt_pipe_set_fuse", "rt_ctx_apply_sets", "rt_graph_set_frames", "rt_pipe_set_removal",
             "rt_surrogate_features", "rt_estimate_new", "rt_surrogate_targets", "rt_surrogate_select",
             "rt_surrogate_frameset",
             "rt_mlp_forward", "rt_mlp_backward", "rt_mlp_adam", "rt_mlp_mse", "rt_gather_rows", "rt_mlp_train",
@@ -148,6 +148,7 @@ def load(path: str = LIB_PATH) -> ct.CDLL:
                                      ct.POINTER(ct.c_int32)]
     lib.rt_pipe_destroy.argtypes = [P]
     lib.rt_pipe_set_fuse.argtypes = [P, ct.c_int32]
+    lib.rt_pipe_set_removal.argtypes = [P, ct.POINTER(rt_removal_opts), P, P]
     lib.rt_ctx_apply_sets.argtypes = [P, ct.POINTER(ct.c_int32), ct.c_int32, ct.POINTER(ct.c_int32)]
     lib.rt_pipe_create_lanes.argtypes = [P, ct.c_int32, ct.c_int32, ct.c_int32, ct.POINTER(rt_stats_buf),
                                          ct.POINTER(rt_params_buf), ct.POINTER(rt_lut_buf), ct.POINTER(rt_stats_buf),
@@ -332,6 +333,21 @@ class Pipe:
         self._slot = ct.c_int32()
         if fuse:
             self.set_fuse(True)
+
+    def set_removal(self, kept_sums, method=None, tau: int = 20, min_kept: float = 0.25, on: bool = True) -> None:
+        """rt_pipe_set_removal: later submits estimate with object removal
+        against each camera's previously submitted frame (kept_sums int64
+        [K][2][NB][3][3], method uint8 [K][2][NB] or None); on=False turns it
+        off.  A submitted frame-set's inputs must stay unchanged until the
+        next frame-set's apply has finished."""
+        if not on:
+            _check(load().rt_pipe_set_removal(self.handle, None, None, None))
+            self._removal = None
+            return
+        ro = rt_removal_opts(tau, 0, min_kept)
+        _check(load().rt_pipe_set_removal(self.handle, ct.byref(ro), _p(kept_sums),
+                                          _p(method) if method is not None else None))
+        self._removal = (kept_sums, method)
 
     def set_fuse(self, fuse: bool) -> None:
         """rt_pipe_set_fuse: a group's applies as launches of up to 4

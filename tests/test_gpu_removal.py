@@ -3,7 +3,9 @@ supplemental methods for moving objects, chosen per seam unit) against the
 oracle: band and kept sums bit for bit, the method of every unit exactly,
 parameters bitwise equal (within 1e-4 at worst), tables and pixels bit for
 bit - from tiny ragged geometries to the full 14x1920x1080 rig with an object
-crossing a seam."""
+crossing a seam - and the same method through the frame-set pipeline."""
+import ctypes as ct
+
 import numpy as np
 import pytest
 
@@ -209,4 +211,102 @@ def test_removal_validation():
     with pytest.raises(rt.RtError, match="prev_frames"):
         rig.frameset_removal(dev, [dev[0], None], out, kept, method)
     rig.check()
+    rig.close()
+
+
+@pytest.mark.parametrize("lanes,group,fuse", [(1, 1, False), (3, 3, False), (2, 3, True)])
+def test_pipeline_removal_matches_eager_and_oracle(lanes, group, fuse):
+    """Object removal through the frame-set pipeline (each frame-set compared
+    with the one submitted before it) over 9 frame-sets with an object
+    crossing a seam: every output, the final state, kept sums and methods
+    equal consecutive rt_frameset_removal calls, and the outputs the oracle's
+    removal sequence; turning removal off gives the plain pipeline again."""
+    say(f"case: pipeline removal lanes {lanes} group {group} fuse {fuse}, 4x320x180 rgb8, 9 frame-sets")
+    spec = synth.RigSpec("pipe removal", 41, [synth.CamSpec(320, 180, 3, 8, 0, p) for p in range(4)])
+    ob = synth.MovingObject(x0=250.0, y0=100, w=60, h=40, speed=12.0)
+    cams = rt_cams(spec.cams)
+    opts = rt.Options(n_blocks=8, band_width=16, smoothing=True)
+    T = 9
+    frames = [synth.rig_frames(spec, t, drift=True, objects=(ob,)) for t in range(T)]
+    # eager sequence
+    seq = rt.Rig(cams, opts)
+    kept_s, method_s = kept_buf(seq)
+    dev = [seq.upload(f) for f in frames]
+    out_s = seq.alloc_frames()
+    eager = []
+    for t in range(T):
+        seq.frameset_removal(dev[t], dev[t - 1] if t else None, out_s, kept_s, method_s)
+        torch.cuda.synchronize()
+        eager.append(seq.download(out_s))
+    hs = seq.bufs.host()
+    # pipeline
+    par = rt.Rig(cams, opts)
+    kept_p, method_p = kept_buf(par)
+    outs = [par.alloc_frames() for _ in range(T)]
+    pipe = rt.Pipe.for_rig(par, depth=8, lanes=lanes, group=group, fuse=fuse)
+    pipe.set_removal(kept_p, method_p)
+    for t in range(T):
+        pipe.submit(dev[t], outs[t])
+    pipe.join()
+    torch.cuda.synchronize()
+    par.check()
+    for t in range(T):
+        for k, (a, b) in enumerate(zip(par.download(outs[t]), eager[t])):
+            assert np.array_equal(a, b), f"frame-set {t} camera {k}"
+    hp = par.bufs.host()
+    assert np.array_equal(hp["params"].view(np.uint64), hs["params"].view(np.uint64))
+    assert np.array_equal(hp["valid"], hs["valid"])
+    assert np.array_equal(kept_p.cpu().numpy(), kept_s.cpu().numpy())
+    assert np.array_equal(method_p.cpu().numpy(), method_s.cpu().numpy())
+    # the oracle's removal sequence on the same frames
+    co, oo = oracle_cams(cams), oracle_opts(opts)
+    pp = pv = None
+    seen = set()
+    for t in range(T):
+        ref = rc.frameset_removal(co, oo, frames[t], frames[t - 1] if t else None, pp, pv)
+        pp, pv = ref["params"], ref["valid"]
+        seen |= set(np.unique(ref["method"]).tolist())
+        for k, (a, b) in enumerate(zip(par.download(outs[t]), ref["out"])):
+            assert_ints_equal(a, b, f"oracle t {t} camera {k}")
+    assert rc.METHOD_REMOVAL in seen
+    # removal off: the next frame-sets follow the plain pipeline
+    pipe.set_removal(None, on=False)
+    extra = [synth.rig_frames(spec, T + t, drift=True) for t in range(2)]
+    dx = [par.upload(f) for f in extra]
+    ox = [par.alloc_frames() for _ in range(2)]
+    for t in range(2):
+        pipe.submit(dx[t], ox[t])
+    pipe.join()
+    torch.cuda.synchronize()
+    for t in range(2):
+        seq.frameset(dx[t], out_s)
+        torch.cuda.synchronize()
+        for k, (a, b) in enumerate(zip(par.download(ox[t]), seq.download(out_s))):
+            assert np.array_equal(a, b), f"after removal off: frame-set {t} camera {k}"
+    pipe.close()
+    seq.close()
+    par.close()
+
+
+def test_pipeline_removal_validation():
+    say("case: pipeline removal validation")
+    spec = synth.RigSpec("pipe removal val", 42, [synth.CamSpec(64, 32, 3, 8, 0, p) for p in range(2)])
+    cams = rt_cams(spec.cams)
+    lib = rt.load()
+    q = rt.Rig(cams, rt.Options(n_blocks=2, band_width=8, fit="quantile"))
+    kq, _ = kept_buf(q)
+    pq = rt.Pipe.for_rig(q, depth=2)
+    ro = rt.rt_removal_opts(20, 0, 0.25)
+    assert lib.rt_pipe_set_removal(pq.handle, ct.byref(ro), rt._p(kq), None) == rt.RT_EUNSUPPORTED
+    pq.close()
+    q.close()
+    rig = rt.Rig(cams, rt.Options(n_blocks=2, band_width=8))
+    kept, _ = kept_buf(rig)
+    pipe = rt.Pipe.for_rig(rig, depth=2)
+    for tau, mk in [(-1, 0.25), (256, 0.25), (20, -0.1), (20, 1.5), (20, float("nan"))]:
+        bad = rt.rt_removal_opts(tau, 0, mk)
+        assert lib.rt_pipe_set_removal(pipe.handle, ct.byref(bad), rt._p(kept), None) == rt.RT_EINVAL, (tau, mk)
+    assert lib.rt_pipe_set_removal(pipe.handle, ct.byref(ro), None, None) == rt.RT_EINVAL
+    assert lib.rt_pipe_set_removal(pipe.handle, None, None, None) == rt.RT_OK
+    pipe.close()
     rig.close()
