@@ -623,6 +623,22 @@ def test_graph_rebound_frames_match_eager(pipelined):
         assert np.array_equal(whole.whole_hist.cpu().numpy(), eager[t]["wh"]), f"step {t} whole_hist"
         if not pipelined:
             assert np.array_equal(b.params.cpu().numpy(), eager[t]["params"]), f"step {t} params"
+    if not pipelined:
+        # Rebinds between launches that are still queued or running: each
+        # launch keeps the frames it was launched with.
+        more = [(3 * t + 1) % 4 for t in range(6)]
+        eager2 = _eager_sequence(cams, opts, dev, order + more)[len(order):]
+        outs2 = [rig.alloc_frames() for _ in more]
+        torch.cuda.synchronize()
+        g = graphs[0]
+        for t, i in enumerate(more):
+            g.set_frames(dev[i], outs2[t])
+            g.launch()
+        torch.cuda.synchronize()
+        for t in range(len(more)):
+            for k, (a, e) in enumerate(zip(rig.download(outs2[t]), eager2[t]["out"])):
+                assert np.array_equal(a, e), f"queued step {t} camera {k}"
+        assert np.array_equal(b.params.cpu().numpy(), eager2[-1]["params"])
     rig.check()
     for g in graphs:
         g.close()
