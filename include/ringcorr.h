@@ -383,7 +383,9 @@ rt_status rt_frameset_removal(rt_ctx* ctx, const void* const* frames, const void
  * those of consecutive rt_frameset_removal calls with prev_frames = the
  * previous frame-set's frames.  A frame-set's input frames are then read
  * again by the next submit's statistics: keep them unchanged until the
- * apply of that next frame-set has finished.  ro NULL turns removal off.
+ * apply of that next frame-set has finished; an in-place submit (an active
+ * camera with out_frames[k] == frames[k]) is refused with RT_EINVAL while
+ * removal is on.  ro NULL turns removal off.
  * RT_EUNSUPPORTED unless the context fits the moments. */
 rt_status rt_pipe_set_removal(rt_pipe* p, const rt_removal_opts* ro, uint64_t* kept_sums, uint8_t* method);
 

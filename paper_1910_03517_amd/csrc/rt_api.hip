@@ -1055,6 +1055,12 @@ static rt_status pipe_submit(rt_pipe* p, uint64_t active, const void* const* fra
   if (r == RT_OK) r = check_frames_masked(ctx, active, (const void* const*)out_frames, "out_frames");
   if (r != RT_OK) return r;
   if (done_event && p->group != 1) return fail(RT_EINVAL, "done_event needs a pipeline with group 1");
+  // With object removal the next submit's statistics read this frame-set's
+  // inputs, unordered with respect to this apply: it must not overwrite them.
+  if (p->removal)
+    for (int k = 0; k < ctx->n_cams; ++k)
+      if (((active >> k) & 1ull) && frames[k] == out_frames[k])
+        return fail(RT_EINVAL, "camera %d: an in-place frame-set cannot be pipelined with object removal", k);
   const int slot = (int)(p->submitted % p->depth);
   hipError_t e = hipSuccess;
   // The slot's previous apply may still be pending: issue it first.

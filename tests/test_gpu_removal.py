@@ -307,6 +307,15 @@ def test_pipeline_removal_validation():
         bad = rt.rt_removal_opts(tau, 0, mk)
         assert lib.rt_pipe_set_removal(pipe.handle, ct.byref(bad), rt._p(kept), None) == rt.RT_EINVAL, (tau, mk)
     assert lib.rt_pipe_set_removal(pipe.handle, ct.byref(ro), None, None) == rt.RT_EINVAL
+    # in place: refused while removal is on, accepted once it is off
+    pipe.set_removal(kept)
+    dev = rig.upload(synth.rig_frames(spec, 0))
+    with pytest.raises(rt.RtError, match="in-place"):
+        pipe.submit(dev, dev)
     assert lib.rt_pipe_set_removal(pipe.handle, None, None, None) == rt.RT_OK
+    pipe.submit(dev, dev)
+    pipe.join()
+    torch.cuda.synchronize()
+    rig.check()
     pipe.close()
     rig.close()
