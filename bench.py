@@ -831,14 +831,32 @@ def plain_leg(args, rig_spec, steps: int, warmup: int, timing_every: int = 0):
         apply_sets = np.ones(apply_ms.size)
         rt.rt_ctx_timing(rig.ctx, 0)
 
-    # The same kernel with no other work beside it (one stream, launches back to back).
+    # The single-frame-set apply with no other work beside it (one stream,
+    # launches back to back).
     rt.rt_ctx_timing(rig.ctx, steps)
     for i in range(steps):
         rt.rt_apply(rig.ctx, ins[i % args.nbuf], outs[i % args.nbuf], b.lut8, b.q16, b.weights,
                     b.whole_hist, b.whole_sums, stream=stream)
     torch.cuda.synchronize()
-    alone_ms = np.array(rt.rt_ctx_apply_times(rig.ctx, steps))
+    single_ms = np.array(rt.rt_ctx_apply_times(rig.ctx, steps))
     rt.rt_ctx_timing(rig.ctx, 0)
+    # The timed region's kernel form alone: fused, rt_apply_sets with the
+    # group's frame-sets per launch (the pipeline's slot tables); else the
+    # single-frame-set launches above.
+    alone_ms, alone_sets = single_ms, np.ones(single_ms.size)
+    if pipe is not None and pipe.fuse:
+        n = min(group, 4)
+        fused = [(rt.ptr_array_n([ins[(i * n + u) % args.nbuf] for u in range(n)]),
+                  rt.ptr_array_n([outs[(i * n + u) % args.nbuf] for u in range(n)])) for i in range(args.nbuf)]
+        launches = max(4, steps // n)
+        rt.rt_ctx_timing(rig.ctx, launches)
+        for i in range(launches):
+            rt.rt_apply_sets(rig.ctx, None, None, pipe.luts[:n], pipe.whole[:n], stream=stream,
+                             ptrs=fused[i % args.nbuf])
+        torch.cuda.synchronize()
+        alone_ms = np.array(rt.rt_ctx_apply_times(rig.ctx, launches))
+        alone_sets = np.array(rt.rt_ctx_apply_sets(rig.ctx, launches), dtype=np.float64)
+        rt.rt_ctx_timing(rig.ctx, 0)
 
     # Frame-set latency, outside the timed region: per-step start and end events.
     n_lat = min(steps, 100)
@@ -866,7 +884,9 @@ def plain_leg(args, rig_spec, steps: int, warmup: int, timing_every: int = 0):
     achieved = ab * sets_per_launch / (launch_us * 1e-6) / 1e9
     by_sets = {str(int(n)): round(float(apply_ms[apply_sets == n].mean() * 1e3), 2) for n in np.unique(apply_sets)}
     alone_us = float(alone_ms.mean() * 1e3)
-    alone_gbs = ab / (alone_us * 1e-6) / 1e9
+    alone_gbs = ab * float(alone_sets.mean()) / (alone_us * 1e-6) / 1e9
+    single_us = float(single_ms.mean() * 1e3)
+    single_gbs = ab / (single_us * 1e-6) / 1e9
     step_gbs = ab / (ms_step * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
@@ -879,9 +899,12 @@ def plain_leg(args, rig_spec, steps: int, warmup: int, timing_every: int = 0):
             "copy_ceiling_GBs": round(copy_gbs, 1), "frac_of_copy_ceiling": round(achieved / copy_gbs, 4),
             "alone": {"launch_us": round(alone_us, 2), "achieved": round(alone_gbs, 1),
                       "frac": round(alone_gbs / HBM_PEAK_GBS, 4), "frac_of_copy_ceiling": round(alone_gbs / copy_gbs, 4),
-                      "launches_timed": int(alone_ms.size),
-                      "what": "the single-frame-set apply launches back to back on one stream after the timed "
-                              "region"},
+                      "launches_timed": int(alone_ms.size), "frame_sets_per_launch": round(float(alone_sets.mean()), 3),
+                      "what": "the timed region's kernel form back to back on one stream after it (fused: "
+                              "rt_apply_sets with the group's frame-sets per launch)"},
+            "alone_single": {"launch_us": round(single_us, 2), "achieved": round(single_gbs, 1),
+                             "frac": round(single_gbs / HBM_PEAK_GBS, 4), "launches_timed": int(single_ms.size),
+                             "what": "k_apply<true,true,false>, one frame-set per launch, back to back on one stream"},
             "per_step": {"achieved": round(step_gbs, 1), "frac": round(step_gbs / HBM_PEAK_GBS, 4),
                          "what": "apply bytes per frame-set / time per frame-set (launches may overlap)"}}
     rep = {

@@ -207,6 +207,19 @@ rt_status rt_build_lut(rt_ctx* ctx, const rt_params_buf* params, const rt_lut_bu
 rt_status rt_apply(rt_ctx* ctx, const void* const* frames, void* const* out_frames, const rt_lut_buf* lut,
                    const rt_stats_buf* whole_out, void* stream);
 
+/* rt_apply with whole-frame statistics for n (1..4) frame-sets in one kernel
+ * launch (the launch the fused pipeline issues): frame-set i reads
+ * frames[i * K + k] and writes out_frames[i * K + k] for camera k of the
+ * context's K cameras, with the tables luts[i]; wholes[i] (whole_hist and
+ * whole_sums; band fields ignored) is cleared and receives the statistics of
+ * its input.  The same results as n rt_apply calls with whole_out =
+ * &wholes[i]; the luts and wholes of different frame-sets must not overlap,
+ * and no frame-set may write another's input.  RT_EINVAL for n outside 1..4,
+ * RT_EUNSUPPORTED for a context of more than 16 cameras.  For hosts that
+ * hold several frame-sets whose tables are built (recorded video). */
+rt_status rt_apply_sets(rt_ctx* ctx, int32_t n, const void* const* frames, void* const* out_frames,
+                        const rt_lut_buf* luts, const rt_stats_buf* wholes, void* stream);
+
 /* One whole frame-set: band statistics of frame t -> estimate (updating
  * `state`) -> tables and weights, clearing stats' whole-frame fields -> apply
  * to frame t with the whole-frame statistics of the input accumulated in the

@@ -559,6 +559,41 @@ rt_status rt_apply(rt_ctx* ctx, const void* const* frames, void* const* out_fram
   return e == hipSuccess ? RT_OK : hip_fail(e, "apply");
 }
 
+rt_status rt_apply_sets(rt_ctx* ctx, int32_t n, const void* const* frames, void* const* out_frames,
+                        const rt_lut_buf* luts, const rt_stats_buf* wholes, void* stream) {
+  if (!ctx) return fail(RT_EINVAL, "ctx is NULL");
+  if (n < 1 || n > kSetsMax) return fail(RT_EINVAL, "n %d outside 1..%d", n, kSetsMax);
+  if (ctx->n_cams > kSetCams)
+    return fail(RT_EUNSUPPORTED, "applies of several frame-sets take rigs of at most %d cameras (this one has %d)",
+                kSetCams, ctx->n_cams);
+  if (!frames || !out_frames || !luts || !wholes) return fail(RT_EINVAL, "frames, out_frames, luts or wholes is NULL");
+  const int K = ctx->n_cams;
+  rt_status r = RT_OK;
+  for (int i = 0; r == RT_OK && i < n; ++i) {
+    r = check_frames(ctx, frames + (int64_t)i * K, "frames");
+    if (r == RT_OK) r = check_frames(ctx, (const void* const*)(out_frames + (int64_t)i * K), "out_frames");
+    if (r == RT_OK) r = check_lut(&luts[i]);
+    if (r == RT_OK) r = check_stats(&wholes[i], false, true);
+  }
+  if (r != RT_OK) return r;
+  hipStream_t st = (hipStream_t)stream;
+  SetPtrs sp;
+  memset(&sp, 0, sizeof sp);
+  sp.n_sets = n;
+  hipError_t e = hipSuccess;
+  for (int i = 0; e == hipSuccess && i < n; ++i) {
+    const FramePtrs fp = make_ptrs(ctx, frames + (int64_t)i * K, out_frames + (int64_t)i * K);
+    for (int k = 0; k < K; ++k) {
+      sp.f[i].in[k] = fp.in[k];
+      sp.f[i].out[k] = fp.out[k];
+    }
+    sp.b[i] = SetBufs{wholes[i].whole_hist, wholes[i].whole_sums, luts[i].lut8, luts[i].q16, luts[i].weights};
+    e = launch_zero_whole(ctx->geo, make_bufs(&wholes[i], nullptr, nullptr), st);
+  }
+  if (e == hipSuccess) e = timed_apply_sets(ctx, ctx->geo, sp, st);
+  return e == hipSuccess ? RT_OK : hip_fail(e, "apply of several frame-sets");
+}
+
 // The frame-set sequence over the cameras in `active`: band statistics,
 // estimate + tables + clearing of the whole-frame statistics, apply.
 static rt_status frameset_masked(rt_ctx* ctx, uint64_t active, const void* const* frames, void* const* out_frames,

@@ -30,7 +30,7 @@ EXPORTED = ["rt_ctx_create", "rt_ctx_destroy", "rt_ctx_sizes", "rt_stats", "rt_e
             "rt_stream_copy", "rt_ctx_timing", "rt_ctx_apply_times", "rt_graph_create", "rt_graph_launch",
             "rt_graph_destroy", "rt_pipe_create", "rt_pipe_submit", "rt_pipe_destroy",
             "rt_pipe_create_lanes", "rt_pipe_join", "rt_pipe_submit_batch", "rt_pipe_submit_n",
-            "rt_pipe_set_fuse", "rt_ctx_apply_sets", "rt_graph_set_frames", "rt_pipe_set_removal",
+            "rt_pipe_set_fuse", "rt_ctx_apply_sets", "rt_graph_set_frames", "rt_pipe_set_removal", "rt_apply_sets",
             "rt_surrogate_features", "rt_estimate_new", "rt_surrogate_targets", "rt_surrogate_select",
             "rt_surrogate_frameset",
             "rt_mlp_forward", "rt_mlp_backward", "rt_mlp_adam", "rt_mlp_mse", "rt_gather_rows", "rt_mlp_train",
@@ -125,6 +125,8 @@ def load(path: str = LIB_PATH) -> ct.CDLL:
     lib.rt_estimate.argtypes = [P, ct.POINTER(rt_stats_buf), ct.POINTER(rt_params_buf), P]
     lib.rt_build_lut.argtypes = [P, ct.POINTER(rt_params_buf), ct.POINTER(rt_lut_buf), P]
     lib.rt_apply.argtypes = [P, ct.POINTER(P), ct.POINTER(P), ct.POINTER(rt_lut_buf), ct.POINTER(rt_stats_buf), P]
+    lib.rt_apply_sets.argtypes = [P, ct.c_int32, ct.POINTER(P), ct.POINTER(P), ct.POINTER(rt_lut_buf),
+                                  ct.POINTER(rt_stats_buf), P]
     lib.rt_frameset.argtypes = [P, ct.POINTER(P), ct.POINTER(P), ct.POINTER(rt_stats_buf),
                                 ct.POINTER(rt_params_buf), ct.POINTER(rt_lut_buf), P]
     lib.rt_frameset_batch.argtypes = [P, ct.c_uint64, ct.POINTER(P), ct.POINTER(P), ct.POINTER(rt_stats_buf),
@@ -596,6 +598,17 @@ def rt_build_lut(ctx, params, valid, lut8, q16, weights, stream=None) -> None:
     pb = rt_params_buf(_p(params), _p(valid))
     lb = rt_lut_buf(_p(lut8), _p(q16), _p(weights))
     _check(load().rt_build_lut(ctx, ct.byref(pb), ct.byref(lb), _stream_handle(stream)))
+
+
+def rt_apply_sets(ctx, frames_list, outs_list, luts, wholes, stream=None, ptrs=None) -> None:
+    """rt_apply_sets: the applies (with whole-frame statistics) of len(luts)
+    frame-sets in one launch; luts / wholes are LutSet / WholeSet objects,
+    ptrs may pass prebuilt (frames, outs) arrays from ptr_array_n."""
+    n = len(luts)
+    fa, oa = ptrs if ptrs is not None else (ptr_array_n(frames_list), ptr_array_n(outs_list))
+    la = (rt_lut_buf * n)(*[rt_lut_buf(_p(l.lut8), _p(l.q16), _p(l.weights)) for l in luts])
+    wa = (rt_stats_buf * n)(*[rt_stats_buf(None, None, _p(w.whole_hist), _p(w.whole_sums)) for w in wholes])
+    _check(load().rt_apply_sets(ctx, n, fa, oa, la, wa, _stream_handle(stream)))
 
 
 def rt_apply(ctx, frames, out_frames, lut8, q16, weights, whole_hist=None, whole_sums=None, stream=None) -> None:

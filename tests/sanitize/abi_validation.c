@@ -152,6 +152,7 @@ int main(void) {
   EXPECT(rt_ctx_apply_sets(NULL, NULL, 0, NULL) == RT_EINVAL, "apply_sets NULL");
   EXPECT(rt_pipe_set_fuse(NULL, 1) == RT_EINVAL, "set_fuse NULL");
   EXPECT(rt_pipe_set_removal(NULL, NULL, NULL, NULL) == RT_EINVAL, "set_removal NULL");
+  EXPECT(rt_apply_sets(NULL, 1, NULL, NULL, NULL, NULL, NULL) == RT_EINVAL, "apply_sets NULL");
   EXPECT(rt_graph_set_frames(NULL, NULL, NULL, NULL) == RT_EINVAL, "graph_set_frames NULL");
   EXPECT(rt_stream_copy(NULL, NULL, 16, 16, NULL) == RT_EINVAL, "stream_copy NULL");
   EXPECT(rt_graph_launch(NULL, NULL) == RT_EINVAL, "graph_launch NULL");

@@ -121,3 +121,4 @@ def test_null_arguments_are_rejected():
     assert lib.rt_ctx_apply_sets(None, None, 0, None) == rt.RT_EINVAL
     assert lib.rt_pipe_set_fuse(None, 1) == rt.RT_EINVAL
     assert lib.rt_pipe_set_removal(None, None, None, None) == rt.RT_EINVAL
+    assert lib.rt_apply_sets(None, 1, None, None, None, None, None) == rt.RT_EINVAL

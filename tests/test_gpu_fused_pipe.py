@@ -198,3 +198,61 @@ def test_set_fuse_validation():
     assert lib.rt_ctx_apply_sets(None, ct.byref(st), 1, ct.byref(st)) == rt.RT_EINVAL
     pipe.close()
     par.close()
+
+
+@pytest.mark.parametrize("vblend", [False, True])
+def test_apply_sets_equals_single_applies(vblend):
+    """rt_apply_sets over 1..4 frame-sets (each with its own tables, built
+    from a different frame-set) equals rt_apply with whole-frame statistics
+    per frame-set, outputs and statistics bit for bit; refusals for n outside
+    1..4 and for more than 16 cameras."""
+    say(f"case: rt_apply_sets vblend={vblend}, 3 rgb8 + 2 gray16 cameras")
+    spec = ([synth.CamSpec(200, 90, 3, 8, 0, p) for p in (1, 0, 2)]
+            + [synth.CamSpec(120, 64, 1, 16, 4, p) for p in (1, 0)])
+    cams = rt_cams(spec, 1)
+    opts = rt.Options(n_blocks=5, band_width=12, closed_ring=False, vblend=vblend)
+    rig = rt.Rig(cams, opts)
+    rng = np.random.default_rng(51)
+    frames = [[synth.tiny_frame(c.height, c.width, c.channels, c.bit_depth, rng) for c in spec] for _ in range(4)]
+    dev = [rig.upload(f) for f in frames]
+    luts = [rt.LutSet(rig.sizes) for _ in range(4)]
+    b = rig.bufs
+    for t in range(4):
+        rt.rt_stats(rig.ctx, dev[t], b.band_hist, b.band_sums)
+        rt.rt_estimate(rig.ctx, b.band_hist, b.band_sums, b.params, b.valid)
+        rt.rt_build_lut(rig.ctx, b.params, b.valid, luts[t].lut8, luts[t].q16, luts[t].weights)
+    torch.cuda.synchronize()
+    ref_out, ref_w = [], []
+    for t in range(4):
+        out = rig.alloc_frames()
+        w = rt.WholeSet(rig.sizes)
+        rt.rt_apply(rig.ctx, dev[t], out, luts[t].lut8, luts[t].q16, luts[t].weights, w.whole_hist, w.whole_sums)
+        torch.cuda.synchronize()
+        ref_out.append(rig.download(out))
+        ref_w.append((w.whole_hist.cpu().numpy(), w.whole_sums.cpu().numpy()))
+    for n in (1, 3, 4):
+        outs = [rig.alloc_frames() for _ in range(n)]
+        wholes = [rt.WholeSet(rig.sizes) for _ in range(n)]
+        for w in wholes:                      # stale values: the call clears them
+            w.whole_hist.fill_(7)
+            w.whole_sums.fill_(9)
+        rt.rt_apply_sets(rig.ctx, dev[:n], outs, luts[:n], wholes)
+        torch.cuda.synchronize()
+        for t in range(n):
+            for k, (a, e) in enumerate(zip(rig.download(outs[t]), ref_out[t])):
+                assert np.array_equal(a, e), f"n {n} frame-set {t} camera {k}"
+            assert np.array_equal(wholes[t].whole_hist.cpu().numpy(), ref_w[t][0]), f"n {n} t {t} whole_hist"
+            assert np.array_equal(wholes[t].whole_sums.cpu().numpy(), ref_w[t][1]), f"n {n} t {t} whole_sums"
+    rig.check()
+    lib = rt.load()
+    fa, oa = rt.ptr_array_n(dev[:1]), rt.ptr_array_n([rig.alloc_frames()])
+    la = (rt.rt_lut_buf * 1)(rt.rt_lut_buf(rt._p(luts[0].lut8), rt._p(luts[0].q16), rt._p(luts[0].weights)))
+    w0 = rt.WholeSet(rig.sizes)
+    wa = (rt.rt_stats_buf * 1)(rt.rt_stats_buf(None, None, rt._p(w0.whole_hist), rt._p(w0.whole_sums)))
+    for n in (0, 5, -1):
+        assert lib.rt_apply_sets(rig.ctx, n, fa, oa, la, wa, None) == rt.RT_EINVAL, n
+    rig.close()
+    big = rt.Rig(rt_cams([synth.CamSpec(64, 32, 3, 8, 0, p) for p in range(17)]),
+                 rt.Options(n_blocks=2, band_width=8))
+    assert lib.rt_apply_sets(big.ctx, 1, None, None, None, None, None) == rt.RT_EUNSUPPORTED
+    big.close()
