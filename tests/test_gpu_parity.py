@@ -570,19 +570,19 @@ def test_graph_replays_match_eager(pipelined):
     rig.close()
 
 
-@pytest.mark.parametrize("pipelined", [False, True])
-def test_graph_rebound_frames_match_eager(pipelined):
+@pytest.mark.parametrize("pipelined,extra", [(False, {}), (True, {}), (False, {"vblend": True, "fit": "quantile"})])
+def test_graph_rebound_frames_match_eager(pipelined, extra):
     """One captured graph (two for the two-branch form, which alternate the
     table buffers) serves every input and output buffer: rt_graph_set_frames
     before each launch, over a cycle of 4 inputs and 2 outputs for 9 steps
     with eager torch work between the launches; every launch equals the
     eager rt_frameset result of the same step.  A mismatched next_frames is
     refused."""
-    say(f"case: graph set_frames pipelined={pipelined}, 3x352x144 rgb8 + 2x96x64 u12")
+    say(f"case: graph set_frames pipelined={pipelined} {extra}, 3x352x144 rgb8 + 2x96x64 u12")
     spec = synth.RigSpec("graph rebind", 14, [synth.CamSpec(352, 144, 3, 8, 0, p) for p in range(3)]
                          + [synth.CamSpec(96, 64, 1, 12, 1, p) for p in range(2)])
     cams = rt_cams(spec.cams)
-    opts = rt.Options(n_blocks=6, band_width=12, smoothing=True)
+    opts = rt.Options(n_blocks=6, band_width=12, smoothing=True, **extra)
     rig = rt.Rig(cams, opts)
     frames = [synth.rig_frames(spec, t, drift=True) for t in range(4)]
     dev = [rig.upload(f) for f in frames]
