@@ -381,12 +381,13 @@ def serving_leg(args, base, surrogate_w=None) -> dict:
     server: paced (30 fps per rig, exponential jitter of mean 2 ms), the same
     arrival process replayed `serve_speedup` times faster (a load near the
     server's capacity, where batches across rigs form), and saturated
-    (every frame-set submitted at once)."""
+    (every frame-set submitted at once); then more rigs than one context
+    takes, spread over contexts (ShardedBackend), saturated."""
     import threading
 
     import torch
     from paper_1910_03517_amd import synth
-    from paper_1910_03517_amd.serving import GpuBackend, Server
+    from paper_1910_03517_amd.serving import GpuBackend, Server, ShardedBackend
     from paper_1910_03517_amd.surrogate import Surrogate
 
     spec = synth.rig14_1080p()
@@ -463,6 +464,39 @@ def serving_leg(args, base, surrogate_w=None) -> dict:
             tuned_plain = be.tuned
         be.close()
         out[path] = res
+    if args.serve_sharded_rigs > 0:
+        n6 = args.serve_sharded_rigs
+        log(f"serving: {n6} rigs over several contexts, saturated")
+        be = ShardedBackend([spec.cams] * n6, lanes=args.serve_lanes)
+        frames = []
+        for r in range(n6):
+            cams = be.rig_cams(r)
+            per = []
+            for i in range(2):
+                dev = [torch.zeros((c.height, c.pitch_bytes), dtype=torch.uint8, device="cuda") for c in cams]
+                for d, c, f in zip(dev, cams, base[(r + i) % len(base)]):
+                    raw = np.ascontiguousarray(f).view(np.uint8).reshape(c.height, c.row_bytes)
+                    d[:, :c.row_bytes].copy_(torch.from_numpy(raw))
+                per.append(dev)
+            frames.append(per)
+        torch.cuda.synchronize()
+        srv = Server(be, mem_budget=2 * n6 * be.frameset_bytes(0), max_batches_in_flight=3, queue_limit=1 << 20)
+        for r in range(n6):
+            srv.submit(r, frames[r][0])
+        srv.drain()
+        srv.finished.clear()
+        srv.batch_sizes.clear()
+        srv.start()
+        for i in range(args.serve_saturated):
+            for r in range(n6):
+                srv.submit(r, frames[r][i % 2])
+        srv.stop(drain=True)
+        rep = srv.report()
+        out["sharded"] = {"rigs": n6, "cameras": n6 * len(spec.cams), "contexts": len(be.shards),
+                          "saturated": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in rep.items()},
+                          "what": "rigs filled into contexts of at most 64 cameras, one launch per context and "
+                                  "batch on the context's own stream; every frame-set submitted at once"}
+        be.close()
     return out
 
 
@@ -948,6 +982,8 @@ def main() -> int:
     ap.add_argument("--no-autotune", action="store_true",
                     help="pipe mode: skip the autotuner (3 lanes in groups of 3 and the context's work split)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-sharded-rigs", type=int, default=6,
+                    help="serving leg: rigs of the benchmark ring spread over contexts (0: skip)")
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--grid", type=int, default=None,
                     help="apply workgroups (rt_ctx_tune; 0 = one per tile; default: the context's own choice)")

@@ -421,21 +421,25 @@ class GpuBackend(Backend):
     def free_out(self, rig: int, out) -> None:
         self._pool[rig].append(out)
 
-    def _check(self, req: Request) -> str:
+    def rig_cams(self, rig: int) -> list:
+        return [self.cams[i] for i in self.idx[rig]]
+
+    def check(self, req: Request) -> str:
+        """Why req's frames cannot be launched ("" if they can)."""
         ids = self.idx[req.rig]
         if req.frames is None or len(req.frames) != len(ids):
-            return f"rig {req.rig}: expected {len(ids)} frames"
-        for f, i in zip(req.frames, ids):
+            return f"expected {len(ids)} frames"
+        for n, (f, i) in enumerate(zip(req.frames, ids)):
             c = self.cams[i]
             if not (hasattr(f, "data_ptr") and f.is_cuda and f.dtype == self.torch.uint8
                     and tuple(f.shape) == (c.height, c.pitch_bytes) and f.is_contiguous()
                     and f.data_ptr() % 16 == 0):
-                return f"rig {req.rig}: camera frame {i} must be a contiguous uint8 device tensor of shape " \
+                return f"camera frame {n} must be a contiguous uint8 device tensor of shape " \
                        f"({c.height}, {c.pitch_bytes}), 16-byte aligned"
         return ""
 
     def launch(self, batch: list[Request]):
-        bad = {req.rig: msg for req in batch if (msg := self._check(req))}
+        bad = {req.rig: f"rig {req.rig}: {msg}" for req in batch if (msg := self.check(req))}
         if bad:
             raise BackendError(list(bad), "; ".join(bad.values()))
         K = len(self.cams)
@@ -481,3 +485,92 @@ class GpuBackend(Backend):
             self.pipe.close()
         self.stream.synchronize()
         self.rig.close()
+
+
+class ShardedBackend(Backend):
+    """Rigs spread over several contexts, for more cameras than one context
+    takes (RT_MAX_CAMS): rigs fill the contexts in order, each context a
+    GpuBackend with its own device stream (and pipeline), so the contexts'
+    work runs concurrently.  A batch is split by context: every context with
+    a frame-set in it gets one launch, and the batch completes when all
+    have.  A refused frame-set is refused before any context launches.
+    shard_cls (default GpuBackend) builds a context's backend from its rigs,
+    the options and the remaining keyword arguments."""
+
+    def __init__(self, rigs, opts=None, max_cams: int | None = None, shard_cls=None, **kw):
+        import copy
+        self._copy = copy.copy
+        if max_cams is None:
+            from . import rt
+            max_cams = rt.RT_MAX_CAMS
+        shard_cls = shard_cls or GpuBackend
+        groups, cur, n = [], [], 0
+        for r, rig_cams in enumerate(rigs):
+            if len(rig_cams) > max_cams:
+                raise ValueError(f"rig {r} has {len(rig_cams)} cameras, more than a context takes ({max_cams})")
+            if cur and n + len(rig_cams) > max_cams:
+                groups.append(cur)
+                cur, n = [], 0
+            cur.append(r)
+            n += len(rig_cams)
+        if cur:
+            groups.append(cur)
+        self.shards = []
+        try:
+            for g in groups:
+                self.shards.append(shard_cls([rigs[r] for r in g], opts, **kw))
+        except Exception:
+            self.close()
+            raise
+        self.where = {r: (s, l) for s, g in enumerate(groups) for l, r in enumerate(g)}
+        self.n_rigs = len(rigs)
+
+    def _at(self, rig: int):
+        s, l = self.where[rig]
+        return self.shards[s], l
+
+    def rig_cams(self, rig: int) -> list:
+        b, l = self._at(rig)
+        return b.rig_cams(l)
+
+    def frameset_bytes(self, rig: int) -> int:
+        b, l = self._at(rig)
+        return b.frameset_bytes(l)
+
+    def rig_pixels(self, rig: int) -> int:
+        b, l = self._at(rig)
+        return b.rig_pixels(l)
+
+    def alloc_out(self, rig: int):
+        b, l = self._at(rig)
+        return b.alloc_out(l)
+
+    def free_out(self, rig: int, out) -> None:
+        b, l = self._at(rig)
+        b.free_out(l, out)
+
+    def launch(self, batch: list[Request]):
+        parts, bad = {}, {}
+        for req in batch:
+            s, l = self.where[req.rig]
+            local = self._copy(req)
+            local.rig = l
+            msg = self.shards[s].check(local)
+            if msg:
+                bad[req.rig] = f"rig {req.rig}: {msg}"
+            parts.setdefault(s, []).append(local)
+        if bad:
+            raise BackendError(list(bad), "; ".join(bad.values()))
+        return [self.shards[s].launch(part) for s, part in sorted(parts.items())]
+
+    def ready(self, token) -> bool:
+        return all(ev.query() for ev in token)
+
+    def wait(self, token) -> None:
+        for ev in token:
+            ev.synchronize()
+
+    def close(self) -> None:
+        for b in self.shards:
+            b.close()
+        self.shards = []

@@ -12,7 +12,7 @@ pytestmark = pytest.mark.gpu
 
 from oracle import ringcorr as rc  # noqa: E402
 from paper_1910_03517_amd import rt, synth  # noqa: E402
-from paper_1910_03517_amd.serving import GpuBackend, Server  # noqa: E402
+from paper_1910_03517_amd.serving import GpuBackend, Server, ShardedBackend  # noqa: E402
 from paper_1910_03517_amd.surrogate import Surrogate, Workspace  # noqa: E402
 
 
@@ -51,17 +51,20 @@ def host_out(cams, outs):
     return res
 
 
-def serve(surrogate=None, lanes=1, producer=False):
+def serve(surrogate=None, lanes=1, producer=False, max_cams=None):
     """Every frame-set of every rig through the server.  producer: the input
     frames start out zero and are written by a separate producer stream (a
     stand-in for a decoder) behind some delaying work; each request carries
     the event recorded after its write, and the server's device work must
     wait for it."""
-    backend = GpuBackend(RIGS, OPTS, surrogate=surrogate, lanes=lanes)
+    if max_cams is None:
+        backend = GpuBackend(RIGS, OPTS, surrogate=surrogate, lanes=lanes)
+    else:
+        backend = ShardedBackend(RIGS, OPTS, max_cams=max_cams, surrogate=surrogate, lanes=lanes)
     results = {}
 
     def on_done(req):
-        cams = [backend.cams[i] for i in backend.idx[req.rig]]
+        cams = backend.rig_cams(req.rig)
         results[(req.rig, req.seq)] = host_out(cams, req.out)
 
     srv = Server(backend, mem_budget=max(N_PER_RIG) * sum(backend.frameset_bytes(r) for r in range(3)),
@@ -70,7 +73,7 @@ def serve(surrogate=None, lanes=1, producer=False):
     order = [(r, t) for t in range(max(N_PER_RIG)) for r in range(3) if t < N_PER_RIG[r]]
     staged = {}
     for r, t in order:
-        cams = [backend.cams[i] for i in backend.idx[r]]
+        cams = backend.rig_cams(r)
         inputs[(r, t)] = to_device(cams, rig_frames(r, t))
         if producer:
             staged[(r, t)] = inputs[(r, t)]
@@ -104,14 +107,17 @@ def serve(surrogate=None, lanes=1, producer=False):
     return results
 
 
-@pytest.mark.parametrize("lanes,producer", [(1, False), (2, False), (1, True), (2, True)])
-def test_serving_mix_matches_oracle_and_alone(lanes, producer):
+@pytest.mark.parametrize("lanes,producer,max_cams", [(1, False, None), (2, False, None), (1, True, None),
+                                                     (2, True, None), (1, False, 5), (2, True, 4)])
+def test_serving_mix_matches_oracle_and_alone(lanes, producer, max_cams):
     """lanes 1: one rt_frameset_batch per batch on one stream; lanes 2: the
     batches through the frame-set pipeline, consecutive ones overlapping.
     producer: the frames are written by another stream, ordered by the
-    requests' ready events."""
-    say(f"case: serving plain, 3 rigs, {lanes} lanes, producer stream {producer}")
-    results = serve(lanes=lanes, producer=producer)
+    requests' ready events.  max_cams: the rigs spread over several contexts
+    (ShardedBackend; 5 cameras: two contexts, 4: three), each batch split
+    into one launch per context."""
+    say(f"case: serving plain, 3 rigs, {lanes} lanes, producer stream {producer}, max_cams {max_cams}")
+    results = serve(lanes=lanes, producer=producer, max_cams=max_cams)
     for r in range(3):
         cams = rt_cams(RIGS[r])
         co, oo = oracle_cams(cams), oracle_opts(OPTS)

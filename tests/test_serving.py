@@ -270,3 +270,103 @@ def test_ready_events_reach_the_backend():
     srv.submit(1, ["b"])
     run_until_idle(srv, clock)
     assert sorted(fake.ready_seen, key=str) == [None, "ev-a"]
+
+
+class Token:
+    """A launch event of FakeShard: completes when the test says so."""
+
+    def __init__(self):
+        self.done = False
+
+    def query(self):
+        return self.done
+
+    def synchronize(self):
+        self.done = True
+
+
+class FakeShard:
+    """One context's backend for ShardedBackend (a rig: its list of cameras)."""
+
+    made = []
+
+    def __init__(self, rigs, opts=None, refuse=(), **kw):
+        self.rigs = [len(r) for r in rigs]
+        self.refuse = set(refuse)
+        self.kw = kw
+        self.launches = []
+        FakeShard.made.append(self)
+
+    def rig_cams(self, rig):
+        return ["cam"] * self.rigs[rig]
+
+    def frameset_bytes(self, rig):
+        return 10 * self.rigs[rig]
+
+    def rig_pixels(self, rig):
+        return 100 * self.rigs[rig]
+
+    def alloc_out(self, rig):
+        return ("out", id(self), rig)
+
+    def free_out(self, rig, out):
+        assert out == ("out", id(self), rig)
+
+    def check(self, req):
+        return "bad frames" if self.rigs[req.rig] in self.refuse else ""
+
+    def launch(self, batch):
+        tok = Token()
+        self.launches.append(([r.rig for r in batch], tok))
+        return tok
+
+    def close(self):
+        self.closed = True
+
+
+def test_sharded_backend_splits_rigs_and_batches():
+    """Rigs fill contexts in order up to max_cams cameras; a batch becomes one
+    launch per context with the rigs' local indices; it is ready when every
+    context's launch is; a refused frame-set refuses before any launch,
+    with the global rig index; and the server runs over it unchanged."""
+    from paper_1910_03517_amd.serving import ShardedBackend
+    FakeShard.made = []
+    cams = [3, 2, 4, 1, 5]                     # rigs' camera counts
+    rigs = [["cam"] * n for n in cams]
+    sb = ShardedBackend(rigs, None, max_cams=5, shard_cls=FakeShard, refuse=(), lanes=2)
+    shards = FakeShard.made
+    assert [s.rigs for s in shards] == [[3, 2], [4, 1], [5]]
+    assert all(s.kw == {"lanes": 2} and s.refuse == set() for s in shards)
+    assert [len(sb.rig_cams(r)) for r in range(5)] == cams
+    assert [sb.frameset_bytes(r) for r in range(5)] == [30, 20, 40, 10, 50]
+    assert sb.alloc_out(3) == ("out", id(shards[1]), 1)
+    clock = Clock()
+    srv = Server(sb, mem_budget=10_000, clock=clock)
+    reqs = [srv.submit(r, ["f"] * cams[r]) for r in (4, 0, 3, 1)]
+    srv.poll()
+    assert shards[0].launches[0][0] == [0, 1]
+    assert shards[1].launches[0][0] == [1]
+    assert shards[2].launches[0][0] == [0]
+    assert srv.pending() == 4
+    shards[0].launches[0][1].done = True
+    shards[1].launches[0][1].done = True
+    srv.poll()
+    assert srv.pending() == 4                  # the third context has not finished
+    shards[2].launches[0][1].done = True
+    srv.poll()
+    assert srv.pending() == 0 and all(r.status == "done" for r in reqs)
+    # a refused frame-set: rig 2 (the 4-camera rig, context 1, local 0)
+    FakeShard.made = []
+    sb = ShardedBackend(rigs, None, max_cams=5, shard_cls=FakeShard, refuse=(4,))
+    srv = Server(sb, mem_budget=10_000, clock=clock)
+    bad = srv.submit(2, ["f"] * 4)
+    good = srv.submit(0, ["f"] * 3)
+    srv.poll()
+    assert bad.status == "failed" and "rig 2: bad frames" in bad.error
+    assert [len(s.launches) for s in FakeShard.made] == [1, 0, 0]
+    FakeShard.made[0].launches[0][1].done = True
+    srv.poll()
+    assert good.status == "done"
+    with pytest.raises(ValueError, match="more than a context takes"):
+        ShardedBackend([["cam"] * 3, ["cam"] * 9], None, max_cams=8, shard_cls=FakeShard)
+    sb.close()
