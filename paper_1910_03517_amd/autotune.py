@@ -33,7 +33,7 @@ GRIDS = (0, 512, 768, 1024)
 # (rigs of at most 16 cameras).
 PIPE_LANES = ((2, 2, 0), (3, 1, 0), (3, 3, 0), (4, 4, 0), (1, 3, 1), (2, 3, 1), (2, 4, 1), (3, 4, 1))
 FUSE_MAX_CAMS = 16
-FUSE_TIE = 0.02
+FUSE_TIE = 0.03
 PIPE_SPLITS = ((32, 0), (48, 0), (64, 0), (32, 512))
 
 
@@ -210,7 +210,9 @@ def tune_pipe(rig, frames, outs, cache_path: str | None = DEFAULT_CACHE, rounds:
     med = {c: sorted(t)[len(t) // 2] for c, t in times.items()}
     c = min(cands, key=lambda k: med[k])
     # A fused form within FUSE_TIE of the fastest is taken instead: it costs
-    # the host one wait and one record per group rather than per lane.
+    # the host one wait and one record per group rather than per lane, and
+    # short runs (a burst of frame-sets after an idle pipeline) favour it,
+    # while over 64 frame-sets the forms measured within 1.5 % of each other.
     fused = [k for k in cands if k[4]]
     if fused and not c[4]:
         f = min(fused, key=lambda k: med[k])
