@@ -280,6 +280,25 @@ def surrogate_leg(args, rig, ins, outs):
     torch.cuda.synchronize()
     train_s = e0.elapsed_time(e1) / 1e3
     samples = (tr.step - steps0) * tr.batch
+    # The same training kernels at larger mini-batches (throughput only, a
+    # fresh network each, not the trained model): how much of the gap to the
+    # FP32 peak is the 1024-sample batch's small products.
+    scaling = {}
+    for bs in (4096, 16384):
+        tb = sg.Trainer(synth.mlp_init(1), lr=args.sur_lr, batch=bs)
+        tb.epoch(data)
+        s0 = tb.step
+        a, z = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(3):
+            tb.epoch(data)
+        z.record()
+        torch.cuda.synchronize()
+        sec = a.elapsed_time(z) / 1e3
+        ns = (tb.step - s0) * bs
+        scaling[str(bs)] = {"samples_per_s": round(ns / sec, 1),
+                            "TFLOP_s": round(ns * MLP_FLOP_PER_SAMPLE_STEP / sec / 1e12, 3)}
+        del tb
     # Held-out residuals (max over the unit's six outputs, normalised units).
     y = sg.predict(tr.w, held.X)
     res = (y - held.T).abs().amax(dim=1).cpu().numpy()
@@ -327,7 +346,9 @@ def surrogate_leg(args, rig, ins, outs):
                      "loss_first_epoch": round(losses[0], 7), "loss_last_epoch": round(losses[-1], 7),
                      "samples_per_s": round(samples / train_s, 1),
                      "TFLOP_s": round(samples * MLP_FLOP_PER_SAMPLE_STEP / train_s / 1e12, 3),
-                     "fp32_peak_TFLOP_s": 157.3},
+                     "fp32_peak_TFLOP_s": 157.3,
+                     "larger_batches": {**scaling, "what": "the same kernels at larger mini-batches, three epochs "
+                                                           "of a fresh network each (throughput only)"}},
         "held_out_residual": {**residuals(res), "units": int(res.size)},
         "held_out_floor": {**residuals(floor),
                            "what": "moment estimate from the same 64-bin features (bin centres, Sheppard's "

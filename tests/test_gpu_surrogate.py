@@ -156,7 +156,7 @@ def test_forward_backward_adam_against_fp64():
         mb.check(f"adam {k}", wh[k], Pa[k], 2 * (4 * mb.U32 * np.abs(Pa[k]) + 256 * mb.U32 * 1e-3))
 
 
-@pytest.mark.parametrize("n", [1, 5, 33, 96, 448, 2048, 2049])
+@pytest.mark.parametrize("n", [1, 5, 33, 96, 448, 2048, 2049, 16384])
 def test_forward_sizes_against_fp64(n):
     """Forward at row counts around the tile sizes and across the switch from
     the k-split 32 x 32 tiles (<= 2048 rows) to the 64 x 64 tiles."""
@@ -248,17 +248,19 @@ def test_corrupted_weights_fall_back_to_plain():
     plain.close()
 
 
-def test_library_training_loop_equals_stepwise_calls():
+@pytest.mark.parametrize("batch", [64, 4096])
+def test_library_training_loop_equals_stepwise_calls(batch):
     """rt_mlp_train (all steps enqueued by the library) gives bit for bit the
-    weights, moments and losses of the per-step calls."""
-    say("case: rt_mlp_train vs per-step calls, 3 epochs of 4 batches")
+    weights, moments and losses of the per-step calls (mini-batches of 64,
+    and of 4096 as the bench's throughput probe uses)."""
+    say(f"case: rt_mlp_train vs per-step calls, 3 epochs of 4 batches of {batch}")
     rng = np.random.default_rng(11)
-    n = 4 * 64 + 17                          # a ragged tail that no batch covers
+    n = 4 * batch + 17                       # a ragged tail that no batch covers
     X = torch.as_tensor(rng.uniform(0, 2, (n, 576)).astype(np.float32), device="cuda")
     T = torch.as_tensor(rng.normal(1, 0.3, (n, 6)).astype(np.float32), device="cuda")
     data = su.Dataset(X, T)
-    a = su.Trainer(synth.mlp_init(2), lr=3e-3, batch=64, seed=5)
-    b = su.Trainer(synth.mlp_init(2), lr=3e-3, batch=64, seed=5)
+    a = su.Trainer(synth.mlp_init(2), lr=3e-3, batch=batch, seed=5)
+    b = su.Trainer(synth.mlp_init(2), lr=3e-3, batch=batch, seed=5)
     for _ in range(3):
         la = a.epoch(data)
         lb = b.epoch_stepwise(data)
