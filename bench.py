@@ -1041,7 +1041,8 @@ def main() -> int:
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported (the correction of one rig "
-              f"runs on one device; see the sharding notes of the design document)", file=sys.stderr)
+              f"runs on one device; across GPUs the path would shard by camera, one arc of the ring per GPU, "
+              f"exchanging only the facing band statistics of the seams between arcs)", file=sys.stderr)
         return 2
 
     import torch
