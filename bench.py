@@ -9,7 +9,9 @@ which go over LANES streams, so that consecutive applies overlap; with
 turn); --lanes 1 keeps every apply on the caller's stream, --mode eager
 issues one rt_frameset per step on one stream, --mode graph /
 graph-pipelined replay captured HIP graphs (the frames rebound before each
-launch, so one graph, or two for alternating tables, serves every buffer).
+launch, so one graph, or two for alternating tables, serves every buffer),
+--mode ahead issues one rt_frameset_ahead launch per step (the apply of a
+frame-set beside the estimate of the next).
 Inputs are seeded synthetic rigs already resident in HBM; NBUF distinct
 input/output frame-set buffers rotate so that the 256 MB Infinity Cache
 cannot serve repeats.
@@ -796,6 +798,15 @@ def plain_leg(args, rig_spec, steps: int, warmup: int, timing_every: int = 0):
         graphs = [rt.Graph(rig.ctx, ins[p], outs[p], luts[p], wholes[p], b, ins[p + 1], luts[1 - p]) for p in range(2)]
         in_ptrs = [rt.ptr_array(x) for x in ins]
         out_ptrs = [rt.ptr_array(x) for x in outs]
+    elif args.mode == "ahead":
+        # One rt_frameset_ahead launch per step: the apply of frame-set i with
+        # the tables the previous launch built, beside the estimate of i + 1;
+        # two table and two whole-statistics buffers taken in turn.
+        ahead = ([rt.LutSet(rig.sizes) for _ in range(2)], [rt.WholeSet(rig.sizes) for _ in range(2)])
+        in_ptrs = [rt.ptr_array(x) for x in ins]
+        out_ptrs = [rt.ptr_array(x) for x in outs]
+        rt.rt_frameset_ahead(rig.ctx, None, None, None, None, ins[0], ahead[0][0], ahead[1][0], b, stream,
+                             ptrs=(None, None, in_ptrs[0]))
 
     def step(i, ready=None):
         if graphs is not None:
@@ -810,6 +821,11 @@ def plain_leg(args, rig_spec, steps: int, warmup: int, timing_every: int = 0):
         elif pipe is not None:
             j = i % args.nbuf
             pipe.submit(ins[j], outs[j], stream, in_ptrs[j], out_ptrs[j], ready_event=ready)
+        elif args.mode == "ahead":
+            j, p = i % args.nbuf, i % 2
+            luts, wholes = ahead
+            rt.rt_frameset_ahead(rig.ctx, None, None, luts[p], wholes[p], None, luts[1 - p], wholes[1 - p], b, stream,
+                                 ptrs=(in_ptrs[j], out_ptrs[j], in_ptrs[(j + 1) % args.nbuf]))
         else:
             rig.frameset(ins[i % args.nbuf], outs[i % args.nbuf])
 
@@ -875,8 +891,10 @@ def plain_leg(args, rig_spec, steps: int, warmup: int, timing_every: int = 0):
     first += steps
     apply_where = f"inside the timed region, every {timing_every}th apply launch"
     if apply_ms.size == 0:
-        # Captured graphs carry no timing events: time the apply launches on their own.
-        apply_where = "separate loop (graph modes record no events inside the graph)"
+        # Captured graphs and the look-ahead launches carry no apply timing
+        # events: time the apply launches on their own.
+        apply_where = ("separate loop (graph modes record no events inside the graph)" if args.mode != "ahead" else
+                       "separate loop (the look-ahead launch is timed as the step)")
         rt.rt_ctx_timing(rig.ctx, steps)
         for i in range(steps):
             rt.rt_apply(rig.ctx, ins[i % args.nbuf], outs[i % args.nbuf], b.lut8, b.q16, b.weights,
@@ -973,7 +991,7 @@ def plain_leg(args, rig_spec, steps: int, warmup: int, timing_every: int = 0):
         "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 4),
                        "p99": round(float(np.percentile(lat_ms, 99)), 4),
                        "what": "start to end of each step's GPU work, steps back to back, measured after the timed "
-                               "region (in graph-pipelined mode a frame-set's estimate ran one step earlier)"},
+                               "region (in graph-pipelined and ahead modes a frame-set's estimate ran one step earlier)"},
         "wall_s": round(wall, 4), "host_issue_us_per_step": round(host_issue / steps * 1e6, 2),
         "roofline": roof,
     }
@@ -988,7 +1006,7 @@ def main() -> int:
     ap.add_argument("--config", default="rig14", choices=["rig14", "uneven", "vga"])
     ap.add_argument("--nbuf", type=int, default=8)
     ap.add_argument("--smoothing", action="store_true")
-    ap.add_argument("--mode", default="pipe", choices=["pipe", "graph-pipelined", "graph", "eager"],
+    ap.add_argument("--mode", default="pipe", choices=["pipe", "graph-pipelined", "graph", "ahead", "eager"],
                     help="pipe: rt_pipe_submit per step (statistics and estimates on their own stream, applies "
                          "round-robin over --lanes streams); graph-pipelined: one two-branch graph launch per step; "
                          "graph: one captured rt_frameset per step (frames rebound each step); eager: one "

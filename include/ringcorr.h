@@ -247,6 +247,33 @@ rt_status rt_frameset_batch(rt_ctx* ctx, uint64_t active, const void* const* fra
                             const rt_stats_buf* stats, const rt_params_buf* state, const rt_lut_buf* lut,
                             void* stream);
 
+/* The frame-set loop with one kernel launch per frame-set (the estimate of
+ * frame-set t+1 alongside the apply of frame-set t, as the two-branch graph
+ * below, without a graph or a second stream).  In one launch, concurrently:
+ *   apply part (frames non-NULL): frames -> out_frames of frame-set t with
+ *     the tables in `lut`, built by an earlier call; the statistics of the
+ *     input are accumulated into whole's whole_hist / whole_sums, which that
+ *     earlier call cleared (band fields ignored);
+ *   estimate part (next_frames non-NULL): band statistics of frame-set t+1
+ *     into `bands` (band fields; whole fields ignored), the estimate into
+ *     `state` (which holds the previous frame-set's estimate for the
+ *     temporal smoothing of section 3.1), the
+ *     tables and weights into `next_lut`, and next_whole's whole fields
+ *     cleared for the call that applies frame-set t+1.
+ * At least one part must be requested.  With both, next_lut and next_whole
+ * must not share memory with lut and whole (RT_EINVAL when their pointers
+ * are equal), since both parts run at once.  Calls on one stream for
+ * t = 0, 1, ..., T with frames = frame-set t-1 (NULL at t = 0) and
+ * next_frames = frame-set t (NULL at t = T), alternating two table and two
+ * whole-statistics buffers, give exactly the results of T consecutive
+ * rt_frameset calls.  Honours the context's active set; the seam and apply
+ * parts of the context's configuration (fit, blend) are those of
+ * rt_frameset.  All buffers stay owned by the caller. */
+rt_status rt_frameset_ahead(rt_ctx* ctx, const void* const* frames, void* const* out_frames, const rt_lut_buf* lut,
+                            const rt_stats_buf* whole, const void* const* next_frames, const rt_lut_buf* next_lut,
+                            const rt_stats_buf* next_whole, const rt_stats_buf* bands, const rt_params_buf* state,
+                            void* stream);
+
 /* Restricts every later call on ctx that takes frames or runs per-camera
  * kernels (all entry points above and below except rt_frameset_batch) to the
  * cameras in `active`, with the semantics rt_frameset_batch documents: the

@@ -1,9 +1,13 @@
 // Estimate and table kernels of section 3.1: one thread per (camera, side,
 // block, channel) for the affine fit, one workgroup per (camera, side, block)
-// for the tables, one thread per column for the blend weights.
+// for the tables, one thread per column for the blend weights; the
+// look-ahead frame-set kernel (the apply of one frame-set in the same launch
+// as the seam estimate of the next).
+#include "dev_apply.h"
 #include "dev_estimate.h"
 #include "dev_motion.h"
 #include "dev_stats.h"
+#include "rt_ahead_internal.h"
 
 namespace rc {
 
@@ -73,7 +77,7 @@ __global__ __launch_bounds__(kThreads) void k_weights(Geo g, Bufs b) {
 template <bool WIDE, bool REMOVAL, bool QFIT, typename Lds>
 __device__ __attribute__((always_inline)) void band_estimate_body(const Geo& g, const FramePtrs& fp,
                                                                   const PrevPtrs& pp, const Bufs& b,
-                                                                  const Removal& rm, Lds* L) {
+                                                                  const Removal& rm, Lds* L, int bid, int nblk) {
   static_assert(!(REMOVAL && QFIT), "object removal keeps only the moments of the kept pixels");
   constexpr int NT = WIDE ? 2 * kThreads : kThreads;
   // This kernel's chain of dependent steps is what the next apply waits
@@ -89,12 +93,12 @@ __device__ __attribute__((always_inline)) void band_estimate_body(const Geo& g, 
   __shared__ uint32_t qcum[QFIT ? kCS : 1][QFIT ? 2 * kNB : 1];
   __shared__ QSums qs[QFIT ? kCS : 1];
   const int nb = g.n_blocks;
-  const int k = blockIdx.x / nb, j = blockIdx.x - (blockIdx.x / nb) * nb;
+  const int k = bid / nb, j = bid - (bid / nb) * nb;
   const int tid = threadIdx.x;
   // WIDE: each half is whole waves, so its unit (camera, frame pointer) is
   // uniform per wave and stays in scalar registers.
   const int half = WIDE ? uniform((int32_t)(tid / kThreads)) : 0, ltid = tid - half * kThreads;
-  if (b.whole_hist) zero_whole(g, b, blockIdx.x * NT + tid, gridDim.x * NT);
+  if (b.whole_hist) zero_whole(g, b, bid * NT + tid, nblk * NT);
   if (!cam_active(g, k)) return;
   const DevCam& cam = g.cams[k];
   // Units taken, n of them: u0 the right band of camera k; u1 the band it
@@ -194,7 +198,7 @@ __global__ __launch_bounds__(WIDE ? 2 * kThreads : kThreads) void k_band_estimat
   __shared__ StatsLds L[WIDE ? 2 : 1];
   PrevPtrs pp;
   Removal rm;
-  band_estimate_body<WIDE, false, QFIT>(g, fp, pp, b, rm, L);
+  band_estimate_body<WIDE, false, QFIT>(g, fp, pp, b, rm, L, (int)blockIdx.x, (int)gridDim.x);
 }
 
 template <bool WIDE>
@@ -202,7 +206,7 @@ __global__ __launch_bounds__(WIDE ? 2 * kThreads : kThreads) void k_band_estimat
                                                                                           PrevPtrs pp, Bufs b,
                                                                                           Removal rm) {
   __shared__ MotionLds L[WIDE ? 2 : 1];
-  band_estimate_body<WIDE, true, false>(g, fp, pp, b, rm, L);
+  band_estimate_body<WIDE, true, false>(g, fp, pp, b, rm, L, (int)blockIdx.x, (int)gridDim.x);
 }
 
 // Band statistics with the kept sums, one workgroup per (camera, side, block).
@@ -237,6 +241,59 @@ __global__ __launch_bounds__(kThreads) void k_estimate_removal(Geo g, Bufs b, Re
   b.params[(int64_t)u * 2 + 1] = p1;
   b.valid[u] = v;
   if (c == 0 && rm.method) rm.method[u / kCS] = (uint8_t)m;
+}
+
+// A frame-set of the look-ahead loop in one launch: workgroups [0, n_est)
+// take the seam blocks of frame-set t + 1 (fe, be: its band statistics,
+// estimate and tables, and the clearing of its whole-frame statistics, as
+// k_band_estimate), the others apply frame-set t (fa, ba: with the tables an
+// earlier launch built, as k_apply with statistics).  The two parts share no
+// buffer and neither waits for the other; consecutive launches on a stream
+// chain the estimates in order.
+union AheadLds {
+  ApplyLds a;
+  StatsLds s;
+};
+template <bool VBLEND, bool QFIT>
+__global__ __launch_bounds__(kThreads) void k_frameset_ahead(Geo g, FramePtrs fa, Bufs ba, FramePtrs fe, Bufs be,
+                                                             int n_est) {
+  __shared__ AheadLds U;
+  const int bid = (int)blockIdx.x;
+  if (bid < n_est) {
+    PrevPtrs pp;
+    Removal rm;
+    band_estimate_body<false, false, QFIT>(g, fe, pp, be, rm, &U.s, bid, n_est);
+    return;
+  }
+  const int w = bid - n_est;
+  const int s0 = uniform(g.wg_seg[w]), s1 = uniform(g.wg_seg[w + 1]);
+  int prev = -1;
+  for (int s = s0; s < s1;) {
+    const int cam = uniform(g.tiles[s].cam);
+    if (!cam_active(g, cam)) {
+      ++s;
+      continue;
+    }
+    s = apply_tile_dispatch<true, true, true, VBLEND>(g, fa, ba, s, s1, U.a, cam != prev);
+    __syncthreads();
+    prev = cam;
+  }
+}
+
+hipError_t launch_frameset_ahead(const Geo& g, const FramePtrs* fa, const Bufs& ba, const FramePtrs* fe,
+                                 const Bufs& be, hipStream_t st) {
+  const int n_est = fe ? g.n_cams * g.n_blocks : 0, n_app = fa ? g.n_wg : 0;
+  if (n_est + n_app == 0) return hipSuccess;
+  const FramePtrs none = {};
+  const FramePtrs& a = fa ? *fa : none;
+  const FramePtrs& e = fe ? *fe : none;
+  const dim3 grid(n_est + n_app), block(kThreads);
+  const bool q = g.fit == RT_FIT_QUANTILE;
+  if (g.vblend && q) hipLaunchKernelGGL((k_frameset_ahead<true, true>), grid, block, 0, st, g, a, ba, e, be, n_est);
+  else if (g.vblend) hipLaunchKernelGGL((k_frameset_ahead<true, false>), grid, block, 0, st, g, a, ba, e, be, n_est);
+  else if (q) hipLaunchKernelGGL((k_frameset_ahead<false, true>), grid, block, 0, st, g, a, ba, e, be, n_est);
+  else hipLaunchKernelGGL((k_frameset_ahead<false, false>), grid, block, 0, st, g, a, ba, e, be, n_est);
+  return hipGetLastError();
 }
 
 // Seam blocks up to which the wide form is launched.

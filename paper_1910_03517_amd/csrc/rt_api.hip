@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "dev_motion.h"
+#include "rt_ahead_internal.h"
 #include "rt_internal.h"
 #include "rt_surrogate_internal.h"
 
@@ -628,6 +629,52 @@ rt_status rt_frameset_batch(rt_ctx* ctx, uint64_t active, const void* const* fra
   rt_status r = check_active(ctx, active);
   if (r != RT_OK) return r;
   return frameset_masked(ctx, active, frames, out_frames, stats, state, lut, stream);
+}
+
+rt_status rt_frameset_ahead(rt_ctx* ctx, const void* const* frames, void* const* out_frames, const rt_lut_buf* lut,
+                            const rt_stats_buf* whole, const void* const* next_frames, const rt_lut_buf* next_lut,
+                            const rt_stats_buf* next_whole, const rt_stats_buf* bands, const rt_params_buf* state,
+                            void* stream) {
+  if (!ctx) return fail(RT_EINVAL, "ctx is NULL");
+  const bool apply = frames != nullptr, est = next_frames != nullptr;
+  if (!apply && !est) return fail(RT_EINVAL, "frames and next_frames are both NULL");
+  rt_status r = RT_OK;
+  if (apply) {
+    r = check_frames(ctx, frames, "frames");
+    if (r == RT_OK) r = check_frames(ctx, (const void* const*)out_frames, "out_frames");
+    if (r == RT_OK) r = check_lut(lut);
+    if (r == RT_OK) r = check_stats(whole, false, true);
+  }
+  if (est && r == RT_OK) {
+    r = check_frames(ctx, next_frames, "next_frames");
+    if (r == RT_OK) r = check_lut(next_lut);
+    if (r == RT_OK) r = check_stats(next_whole, false, true);
+    if (r == RT_OK) r = check_stats(bands, true, false);
+    if (r == RT_OK) r = check_params(state);
+  }
+  if (r != RT_OK) return r;
+  if (apply && est) {
+    if (next_lut->lut8 == lut->lut8 || next_lut->q16 == lut->q16)
+      return fail(RT_EINVAL, "next_lut must be distinct from lut");
+    if (next_whole->whole_hist == whole->whole_hist || next_whole->whole_sums == whole->whole_sums)
+      return fail(RT_EINVAL, "next_whole must be distinct from whole");
+  }
+  FramePtrs fa, fe;
+  Bufs ba, be;
+  if (apply) {
+    fa = make_ptrs(ctx, frames, out_frames);
+    ba = make_bufs(whole, nullptr, lut);
+  }
+  if (est) {
+    fe = make_ptrs(ctx, next_frames, nullptr);
+    be = make_bufs(next_whole, state, next_lut);
+    be.band_hist = bands->band_hist;
+    be.band_sums = bands->band_sums;
+  }
+  const hipError_t e = launch_frameset_ahead(ctx->geo, apply ? &fa : nullptr, apply ? ba : be, est ? &fe : nullptr,
+                                             est ? be : ba, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "look-ahead frame-set");
+  return RT_OK;
 }
 
 rt_status rt_ctx_set_active(rt_ctx* ctx, uint64_t active) {

@@ -26,7 +26,7 @@ RT_MAX_CAMS = 64
 CSLOTS, NBINS = 3, 256
 
 EXPORTED = ["rt_ctx_create", "rt_ctx_destroy", "rt_ctx_sizes", "rt_stats", "rt_estimate",
-            "rt_build_lut", "rt_apply", "rt_frameset", "rt_frameset_batch", "rt_ctx_set_active", "rt_ctx_check", "rt_ctx_tune", "rt_ctx_tuning",
+            "rt_build_lut", "rt_apply", "rt_frameset", "rt_frameset_batch", "rt_frameset_ahead", "rt_ctx_set_active", "rt_ctx_check", "rt_ctx_tune", "rt_ctx_tuning",
             "rt_stream_copy", "rt_ctx_timing", "rt_ctx_apply_times", "rt_graph_create", "rt_graph_launch",
             "rt_graph_destroy", "rt_pipe_create", "rt_pipe_submit", "rt_pipe_destroy",
             "rt_pipe_create_lanes", "rt_pipe_join", "rt_pipe_submit_batch", "rt_pipe_submit_n",
@@ -131,6 +131,9 @@ def load(path: str = LIB_PATH) -> ct.CDLL:
                                 ct.POINTER(rt_params_buf), ct.POINTER(rt_lut_buf), P]
     lib.rt_frameset_batch.argtypes = [P, ct.c_uint64, ct.POINTER(P), ct.POINTER(P), ct.POINTER(rt_stats_buf),
                                       ct.POINTER(rt_params_buf), ct.POINTER(rt_lut_buf), P]
+    lib.rt_frameset_ahead.argtypes = [P, ct.POINTER(P), ct.POINTER(P), ct.POINTER(rt_lut_buf),
+                                      ct.POINTER(rt_stats_buf), ct.POINTER(P), ct.POINTER(rt_lut_buf),
+                                      ct.POINTER(rt_stats_buf), ct.POINTER(rt_stats_buf), ct.POINTER(rt_params_buf), P]
     lib.rt_ctx_set_active.argtypes = [P, ct.c_uint64]
     lib.rt_ctx_check.argtypes = [P]
     lib.rt_ctx_tune.argtypes = [P, ct.c_int32, ct.c_int32]
@@ -634,6 +637,33 @@ def rt_frameset_batch(ctx, active: int, frames, out_frames, bufs: "Buffers", str
     lb = rt_lut_buf(_p(bufs.lut8), _p(bufs.q16), _p(bufs.weights))
     _check(load().rt_frameset_batch(ctx, ct.c_uint64(active), _ptr_array(frames), _ptr_array(out_frames),
                                     ct.byref(sb), ct.byref(pb), ct.byref(lb), _stream_handle(stream)))
+
+
+def rt_frameset_ahead(ctx, frames, out_frames, lut, whole, next_frames, next_lut, next_whole,
+                      bufs: "Buffers", stream=None, ptrs=None) -> None:
+    """rt_frameset_ahead: the apply of frame-set t (frames -> out_frames with
+    LutSet `lut`, statistics into WholeSet `whole`; frames None: none) and,
+    in the same launch, the estimate of frame-set t + 1 (next_frames into
+    bufs' band statistics and estimator state, tables into `next_lut`,
+    `next_whole` cleared; next_frames None: none).  ptrs may pass prebuilt
+    (frames, out_frames, next_frames) arrays from ptr_array, None for a part
+    not requested."""
+    def lut_ref(l):
+        return ct.byref(rt_lut_buf(_p(l.lut8), _p(l.q16), _p(l.weights))) if l is not None else None
+
+    def whole_ref(w):
+        return ct.byref(rt_stats_buf(None, None, _p(w.whole_hist), _p(w.whole_sums))) if w is not None else None
+
+    bb = rt_stats_buf(_p(bufs.band_hist), _p(bufs.band_sums), None, None)
+    pb = rt_params_buf(_p(bufs.params), _p(bufs.valid))
+    if ptrs is not None:
+        fa, oa, na = ptrs
+    else:
+        fa = _ptr_array(frames) if frames is not None else None
+        oa = _ptr_array(out_frames) if frames is not None else None
+        na = _ptr_array(next_frames) if next_frames is not None else None
+    _check(load().rt_frameset_ahead(ctx, fa, oa, lut_ref(lut), whole_ref(whole), na, lut_ref(next_lut),
+                                    whole_ref(next_whole), ct.byref(bb), ct.byref(pb), _stream_handle(stream)))
 
 
 def rt_ctx_set_active(ctx, active: int) -> None:

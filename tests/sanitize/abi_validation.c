@@ -141,6 +141,8 @@ int main(void) {
   EXPECT(rt_apply(NULL, NULL, NULL, NULL, NULL, NULL) == RT_EINVAL, "rt_apply NULL");
   EXPECT(rt_frameset(NULL, NULL, NULL, NULL, NULL, NULL, NULL) == RT_EINVAL, "rt_frameset NULL");
   EXPECT(rt_frameset_batch(NULL, 1, NULL, NULL, NULL, NULL, NULL, NULL) == RT_EINVAL, "batch NULL");
+  EXPECT(rt_frameset_ahead(NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL) == RT_EINVAL,
+         "ahead NULL");
   EXPECT(rt_ctx_set_active(NULL, 1) == RT_EINVAL, "set_active NULL");
   EXPECT(rt_ctx_sizes(NULL, NULL) == RT_EINVAL, "sizes NULL");
   EXPECT(rt_ctx_destroy(NULL) == RT_OK, "destroy NULL");

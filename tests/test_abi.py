@@ -87,6 +87,7 @@ def test_null_arguments_are_rejected():
     assert lib.rt_apply(None, None, None, None, None, None) == rt.RT_EINVAL
     assert lib.rt_frameset(None, None, None, None, None, None, None) == rt.RT_EINVAL
     assert lib.rt_frameset_batch(None, 1, None, None, None, None, None, None) == rt.RT_EINVAL
+    assert lib.rt_frameset_ahead(None, None, None, None, None, None, None, None, None, None, None) == rt.RT_EINVAL
     assert lib.rt_ctx_set_active(None, 1) == rt.RT_EINVAL
     assert lib.rt_ctx_sizes(None, None) == rt.RT_EINVAL
     assert lib.rt_ctx_destroy(None) == rt.RT_OK
