@@ -261,8 +261,8 @@ rt_status rt_frameset_batch(rt_ctx* ctx, uint64_t active, const void* const* fra
  *     tables and weights into `next_lut`, and next_whole's whole fields
  *     cleared for the call that applies frame-set t+1.
  * At least one part must be requested.  With both, next_lut and next_whole
- * must not share memory with lut and whole (RT_EINVAL when their pointers
- * are equal), since both parts run at once.  Calls on one stream for
+ * must not share memory with lut and whole (RT_EINVAL when any of their
+ * pointers, weights included, are equal), since both parts run at once.  Calls on one stream for
  * t = 0, 1, ..., T with frames = frame-set t-1 (NULL at t = 0) and
  * next_frames = frame-set t (NULL at t = T), alternating two table and two
  * whole-statistics buffers, give exactly the results of T consecutive

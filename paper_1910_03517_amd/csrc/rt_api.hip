@@ -654,7 +654,7 @@ rt_status rt_frameset_ahead(rt_ctx* ctx, const void* const* frames, void* const*
   }
   if (r != RT_OK) return r;
   if (apply && est) {
-    if (next_lut->lut8 == lut->lut8 || next_lut->q16 == lut->q16)
+    if (next_lut->lut8 == lut->lut8 || next_lut->q16 == lut->q16 || next_lut->weights == lut->weights)
       return fail(RT_EINVAL, "next_lut must be distinct from lut");
     if (next_whole->whole_hist == whole->whole_hist || next_whole->whole_sums == whole->whole_sums)
       return fail(RT_EINVAL, "next_whole must be distinct from whole");

@@ -153,6 +153,10 @@ def test_ahead_refusals():
         rt.rt_frameset_ahead(rig.ctx, dev, out, L, W, dev, L, W2, rig.bufs)
     with pytest.raises(rt.RtError):
         rt.rt_frameset_ahead(rig.ctx, dev, out, L, W, dev, L2, W, rig.bufs)
+    L3 = rt.LutSet(rig.sizes)
+    L3.weights = L.weights                       # tables distinct, weights shared
+    with pytest.raises(rt.RtError):
+        rt.rt_frameset_ahead(rig.ctx, dev, out, L, W, dev, L3, W2, rig.bufs)
     with pytest.raises(rt.RtError):
         rt.rt_frameset_ahead(rig.ctx, dev, out, None, W, None, None, None, rig.bufs)
     with pytest.raises(rt.RtError):
