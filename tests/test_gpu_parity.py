@@ -235,6 +235,43 @@ def test_uneven_rig_lanes_pipeline_matches_oracle():
     pipeline_vs_oracle(synth.uneven_rig(), 5, "uneven rig")
 
 
+def test_rig14_ahead_loop_matches_oracle():
+    """Six drifting 14x1080p frame-sets (smoothing) through rt_frameset_ahead,
+    one launch per frame-set: every output, every frame-set's whole-frame
+    histogram and the final state against the oracle's sequence, bitwise."""
+    spec = synth.rig14_1080p()
+    cams = rt_cams(spec.cams)
+    opts = rt.Options(smoothing=True)
+    rig = rt.Rig(cams, opts)
+    n = 6
+    frames = [synth.rig_frames(spec, t, drift=True) for t in range(n)]
+    dev = [rig.upload(f) for f in frames]
+    outs = [rig.alloc_frames() for _ in range(n)]
+    luts = [rt.LutSet(rig.sizes) for _ in range(2)]
+    wholes = [rt.WholeSet(rig.sizes) for _ in range(2)]
+    torch.cuda.synchronize()
+    say(f"case: rig14 look-ahead loop, {n} frame-sets")
+    co, oo = oracle_cams(cams), oracle_opts(opts)
+    prev_p = prev_v = None
+    rt.rt_frameset_ahead(rig.ctx, None, None, None, None, dev[0], luts[0], wholes[0], rig.bufs)
+    for t in range(n):
+        a, e = t % 2, (t + 1) % 2
+        nxt = t + 1 < n
+        rt.rt_frameset_ahead(rig.ctx, dev[t], outs[t], luts[a], wholes[a], dev[t + 1] if nxt else None,
+                             luts[e] if nxt else None, wholes[e] if nxt else None, rig.bufs)
+        torch.cuda.synchronize()
+        ref = rc.frameset(co, oo, frames[t], prev_p, prev_v)
+        prev_p, prev_v = ref["params"], ref["valid"]
+        for k, (x, y) in enumerate(zip(rig.download(outs[t]), ref["out"])):
+            assert np.array_equal(x, y), f"frame-set {t} camera {k}"
+        assert np.array_equal(wholes[a].whole_hist.cpu().numpy().astype(np.int64), ref["whole_hist"]), f"t {t}"
+    rig.check()
+    h = rig.bufs.host()
+    assert np.array_equal(h["params"].view(np.uint64), prev_p.view(np.uint64))
+    assert np.array_equal(h["valid"], prev_v)
+    rig.close()
+
+
 def test_uneven_rig_frameset():
     frameset_sequence(synth.uneven_rig(), rt.Options(), 1)
 
